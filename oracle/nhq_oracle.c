@@ -1,0 +1,530 @@
+/*
+ * CPU oracle for native hybrid queries (NHQ) -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, obviously correct C in FP64.  Only the test suite, the smoke
+ * check and the CPU-baseline leg of the benchmark may load this library; the
+ * product path never does.  It shares no code, header or table with the GPU
+ * path.
+ *
+ * What it computes (paper sections cited per function):
+ *   chi     attribute distance, Eq. (4)-(5), restricted to the constrained
+ *           attributes of a query (wildcards contribute nothing);
+ *   delta2  squared Euclidean distance, Eq. (1), FP64 direct form;
+ *   gamma   fusion distance, Eq. (6), with the default weights of Sec. 3.2
+ *           ("optimal weight configuration"): w_v = 1, w_l = delta / m;
+ *   bruteforce   exact hybrid top-k (Def. 4 with Def. 2): exact attribute
+ *           filter, then exact vector top-k ordered by (delta, id);
+ *   build   composite index (Alg. 1 in degree-bounded form): exact l nearest
+ *           candidates under Gamma, then the landing-zone edge selection of
+ *           Sec. 4.1 steps (1)-(3) (Def. 7), optional reverse-edge pass;
+ *   search  joint pruning (Alg. 2) in beam form: a pool of the L best
+ *           vertices by Gamma, each expanded once, until no unexpanded entry
+ *           remains; output filtered to exact attribute matches (Def. 4).
+ *
+ * Ordering keys.  Gamma = delta * (m_q + chi) / m_q is ordered through the
+ * monotone key (m_q * Gamma)^2 = delta^2 * (m_q + chi)^2 (key = delta^2 when
+ * m_q = 0).  KEY64 evaluates it in FP64 (exact on integer-valued vectors).
+ * KEY32 rounds delta^2 to float and takes one float multiply, which is the
+ * precision a float32 kernel takes the same ordering decision in; on
+ * integer-valued vectors (delta^2 < 2^24) it is reproducible bit for bit.
+ * Ties are broken by the smaller id everywhere.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_WILDCARD 0xFF
+#define OR_KEY64 0
+#define OR_KEY32 1
+
+/* ---------------------------------------------------------------- Eq. 1 */
+double or_delta2(const float *x, const float *y, int d)
+{
+    double s = 0.0;
+    for (int i = 0; i < d; ++i) {
+        double t = (double)x[i] - (double)y[i];
+        s += t * t;
+    }
+    return s;
+}
+
+/* ------------------------------------------------------------ Eq. 4, 5 */
+/* phi = 1 where codes differ; summed over the attributes the query
+ * constrains (code != wildcard).  For two objects every attribute counts. */
+int or_chi(const uint8_t *qa, const uint8_t *ea, int m)
+{
+    int c = 0;
+    for (int i = 0; i < m; ++i)
+        if (qa[i] != OR_WILDCARD && qa[i] != ea[i])
+            c += 1;
+    return c;
+}
+
+int or_arity(const uint8_t *qa, int m)
+{
+    int c = 0;
+    for (int i = 0; i < m; ++i)
+        if (qa[i] != OR_WILDCARD)
+            c += 1;
+    return c;
+}
+
+/* ---------------------------------------------------------------- Eq. 6 */
+double or_gamma(double delta, int chi, int mq)
+{
+    if (mq == 0)
+        return delta;
+    double w_v = 1.0;
+    double w_l = delta / (double)mq;
+    return w_v * delta + w_l * (double)chi;
+}
+
+double or_order_key(double d2, int chi, int mq, int mode)
+{
+    double mult = (mq == 0) ? 1.0 : (double)((mq + chi) * (mq + chi));
+    if (mode == OR_KEY32) {
+        volatile float f = (float)d2;
+        volatile float g = (float)mult;
+        volatile float kk = f * g;
+        return (double)kk;
+    }
+    return d2 * mult;
+}
+
+/* (key, id) lexicographic comparison */
+static int lt(double ka, int64_t ia, double kb, int64_t ib)
+{
+    return ka < kb || (ka == kb && ia < ib);
+}
+
+/* ------------------------------------------------ Def. 4 exact top-k */
+/* For each query: P = objects whose attributes equal the query's on every
+ * constrained attribute; the answer is the k members of P with the smallest
+ * (delta, id).  ids padded with -1, dist with +inf.  by_gamma != 0 instead
+ * ranks every object by (Gamma, id) (an unfiltered ranking). */
+void or_bruteforce(const float *x, const uint8_t *attrs, int64_t n, int d, int m,
+                   const float *q, const uint8_t *qa, int64_t nq, int k, int by_gamma,
+                   int32_t *out_ids, double *out_dist, int64_t *out_nmatch, int nthreads)
+{
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+#endif
+    for (int64_t iq = 0; iq < nq; ++iq) {
+        const float *qv = q + iq * (int64_t)d;
+        const uint8_t *qav = qa + iq * (int64_t)m;
+        int mq = or_arity(qav, m);
+        double *bk = (double *)malloc(sizeof(double) * (size_t)(k > 0 ? k : 1));
+        int64_t *bi = (int64_t *)malloc(sizeof(int64_t) * (size_t)(k > 0 ? k : 1));
+        int cnt = 0;
+        int64_t nmatch = 0;
+        for (int64_t e = 0; e < n; ++e) {
+            int c = or_chi(qav, attrs + e * (int64_t)m, m);
+            if (c == 0)
+                nmatch += 1;
+            if (!by_gamma && c != 0)
+                continue;
+            double d2 = or_delta2(qv, x + e * (int64_t)d, d);
+            double key = by_gamma ? or_order_key(d2, c, mq, OR_KEY64) : d2;
+            if (k == 0)
+                continue;
+            if (cnt == k && !lt(key, e, bk[k - 1], bi[k - 1]))
+                continue;
+            /* insertion into the sorted top-k list */
+            int pos = (cnt < k) ? cnt : k - 1;
+            while (pos > 0 && lt(key, e, bk[pos - 1], bi[pos - 1])) {
+                bk[pos] = bk[pos - 1];
+                bi[pos] = bi[pos - 1];
+                pos -= 1;
+            }
+            bk[pos] = key;
+            bi[pos] = e;
+            if (cnt < k)
+                cnt += 1;
+        }
+        for (int j = 0; j < k; ++j) {
+            if (j < cnt) {
+                int64_t e = bi[j];
+                out_ids[iq * k + j] = (int32_t)e;
+                double d2 = or_delta2(qv, x + e * (int64_t)d, d);
+                int c = or_chi(qav, attrs + e * (int64_t)m, m);
+                out_dist[iq * k + j] = or_gamma(sqrt(d2), c, mq);
+            } else {
+                out_ids[iq * k + j] = -1;
+                out_dist[iq * k + j] = INFINITY;
+            }
+        }
+        if (out_nmatch)
+            out_nmatch[iq] = nmatch;
+        free(bk);
+        free(bi);
+    }
+}
+
+/* ---------------------------------------------- candidate lists (Sec. 4.1 (1)) */
+/* Object-object fusion key: every one of the m attributes counts. */
+static double obj_key(const float *x, const uint8_t *attrs, int d, int m, int64_t a, int64_t b)
+{
+    double d2 = or_delta2(x + a * (int64_t)d, x + b * (int64_t)d, d);
+    int c = or_chi(attrs + a * (int64_t)m, attrs + b * (int64_t)m, m);
+    return or_order_key(d2, c, m, OR_KEY64);
+}
+
+/* exact l nearest of vertex i among V \ {i}, by (key, id); returns count */
+static int nearest_l(const float *x, const uint8_t *attrs, int64_t n, int d, int m, int use_attrs,
+                     int64_t i, int l, double *ck, int64_t *ci)
+{
+    int cnt = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == i)
+            continue;
+        double key = use_attrs ? obj_key(x, attrs, d, m, i, j)
+                               : or_delta2(x + i * (int64_t)d, x + j * (int64_t)d, d);
+        if (cnt == l && !lt(key, j, ck[l - 1], ci[l - 1]))
+            continue;
+        int pos = (cnt < l) ? cnt : l - 1;
+        while (pos > 0 && lt(key, j, ck[pos - 1], ci[pos - 1])) {
+            ck[pos] = ck[pos - 1];
+            ci[pos] = ci[pos - 1];
+            pos -= 1;
+        }
+        ck[pos] = key;
+        ci[pos] = j;
+        if (cnt < l)
+            cnt += 1;
+    }
+    return cnt;
+}
+
+/* ------------------------------------- landing-zone selection (Sec. 4.1 (2)-(3)) */
+/* Candidates arrive sorted by (key to i, id).  A candidate p joins N(i) iff
+ * it lies in the intersection of the landing zones L(i, j) of every j
+ * already in N(i): p must be strictly closer to i than to j (half-space
+ * H(i, j), Def. 7); the ball B(i, Gamma(i, j)) is excluded because every
+ * later candidate is at least as far from i as j is.  At most R neighbours. */
+static int landing_zone_select(const float *x, const uint8_t *attrs, int d, int m, int64_t i,
+                               const double *ck, const int64_t *ci, int nc, int R, int32_t *out)
+{
+    int nsel = 0;
+    for (int t = 0; t < nc && nsel < R; ++t) {
+        int64_t p = ci[t];
+        double k_pi = ck[t];
+        int ok = 1;
+        for (int s = 0; s < nsel; ++s) {
+            double k_pj = obj_key(x, attrs, d, m, p, out[s]);
+            if (!(k_pi < k_pj)) {
+                ok = 0;
+                break;
+            }
+        }
+        if (ok)
+            out[nsel++] = (int32_t)p;
+    }
+    (void)i;
+    return nsel;
+}
+
+/* Build adjacency rows.  rows == NULL: every vertex (then the optional
+ * reverse pass runs); otherwise only the listed vertices, forward pass only.
+ * adj_out: [nrows][R], -1 padded.  cand_out (nullable): [nrows][l]. */
+void or_build(const float *x, const uint8_t *attrs, int64_t n, int d, int m, int l, int R,
+              int reverse, const int64_t *rows, int64_t nrows, int32_t *adj_out,
+              int32_t *cand_out, int nthreads)
+{
+    int64_t nr = rows ? nrows : n;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
+#endif
+    for (int64_t r = 0; r < nr; ++r) {
+        int64_t i = rows ? rows[r] : r;
+        double *ck = (double *)malloc(sizeof(double) * (size_t)l);
+        int64_t *ci = (int64_t *)malloc(sizeof(int64_t) * (size_t)l);
+        int nc = nearest_l(x, attrs, n, d, m, 1, i, l, ck, ci);
+        if (cand_out)
+            for (int t = 0; t < l; ++t)
+                cand_out[r * l + t] = (t < nc) ? (int32_t)ci[t] : -1;
+        int32_t *row = adj_out + r * (int64_t)R;
+        int ns = landing_zone_select(x, attrs, d, m, i, ck, ci, nc, R, row);
+        for (int t = ns; t < R; ++t)
+            row[t] = -1;
+        free(ck);
+        free(ci);
+    }
+    if (rows || !reverse)
+        return;
+
+    /* Reverse pass: every j re-selects from N(j) united with the vertices that
+     * chose j, ordered by (key to j, id), under the same landing-zone rule. */
+    int64_t *offer_cnt = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i)
+        for (int t = 0; t < R; ++t) {
+            int32_t j = adj_out[i * R + t];
+            if (j >= 0)
+                offer_cnt[j + 1] += 1;
+        }
+    for (int64_t j = 0; j < n; ++j)
+        offer_cnt[j + 1] += offer_cnt[j];
+    int32_t *offers = (int32_t *)malloc(sizeof(int32_t) * (size_t)(offer_cnt[n] + 1));
+    int64_t *fill = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i)
+        for (int t = 0; t < R; ++t) {
+            int32_t j = adj_out[i * R + t];
+            if (j >= 0)
+                offers[offer_cnt[j] + fill[j]++] = (int32_t)i;
+        }
+    int32_t *fwd = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * R);
+    memcpy(fwd, adj_out, sizeof(int32_t) * (size_t)n * R);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+#endif
+    for (int64_t j = 0; j < n; ++j) {
+        int64_t no = offer_cnt[j + 1] - offer_cnt[j];
+        int cap = R + (int)no;
+        double *ck = (double *)malloc(sizeof(double) * (size_t)cap);
+        int64_t *ci = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+        int cnt = 0;
+        for (int t = 0; t < cap; ++t) {
+            int64_t v = (t < R) ? fwd[j * R + t] : offers[offer_cnt[j] + (t - R)];
+            if (v < 0)
+                continue;
+            int dup = 0;
+            for (int s = 0; s < cnt; ++s)
+                if (ci[s] == v) {
+                    dup = 1;
+                    break;
+                }
+            if (dup)
+                continue;
+            double key = obj_key(x, attrs, d, m, j, v);
+            int pos = cnt;
+            while (pos > 0 && lt(key, v, ck[pos - 1], ci[pos - 1])) {
+                ck[pos] = ck[pos - 1];
+                ci[pos] = ci[pos - 1];
+                pos -= 1;
+            }
+            ck[pos] = key;
+            ci[pos] = v;
+            cnt += 1;
+        }
+        int32_t *row = adj_out + j * (int64_t)R;
+        int ns = landing_zone_select(x, attrs, d, m, j, ck, ci, cnt, R, row);
+        for (int t = ns; t < R; ++t)
+            row[t] = -1;
+        free(ck);
+        free(ci);
+    }
+    free(fwd);
+    free(offers);
+    free(fill);
+    free(offer_cnt);
+}
+
+/* exact k nearest of listed rows (graph quality, Eq. 7): use_attrs selects
+ * the fusion key (composite index) or plain delta (vector-only graph). */
+void or_knn_rows(const float *x, const uint8_t *attrs, int64_t n, int d, int m, int use_attrs,
+                 const int64_t *rows, int64_t nrows, int k, int32_t *out, int nthreads)
+{
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
+#endif
+    for (int64_t r = 0; r < nrows; ++r) {
+        double *ck = (double *)malloc(sizeof(double) * (size_t)k);
+        int64_t *ci = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
+        int nc = nearest_l(x, attrs, n, d, m, use_attrs, rows[r], k, ck, ci);
+        for (int t = 0; t < k; ++t)
+            out[r * k + t] = (t < nc) ? (int32_t)ci[t] : -1;
+        free(ck);
+        free(ci);
+    }
+}
+
+/* ------------------------------------------------ Alg. 2, beam form */
+typedef struct {
+    double key;
+    double d2;
+    int64_t id;
+    int chi;
+    int expanded;
+} pentry;
+
+/* One pass of joint pruning per query.
+ *   xs       vectors the loop scores with (the stored form: float32, or the
+ *            decoded bf16 / fp8 values);
+ *   xr       float32 vectors for the final re-score (nullable);
+ *   seeds    the entry sample (nseeds ids); the initial pool (the seed set
+ *            B of Alg. 2) is its ninit best members by (key, id);
+ *   key_mode OR_KEY64 or OR_KEY32 (ordering precision, see the header);
+ *   out_mode 0: exact attribute matches only (Def. 4), in pool order;
+ *            1: the first k pool entries, unfiltered;
+ *   rerank_n >0 with xr: re-score the first rerank_n output candidates from
+ *            xr in FP64, re-sort by (key, id), then cut to k;
+ *   max_hops expansion cap (flag set when reached).
+ * Outputs ids (-1 padded), Gamma (+inf padded), NDC (neighbour distance
+ * evaluations; the entry sample is not counted) and H (expansions). */
+void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
+               const uint8_t *attrs, int64_t n, int d, int m, const float *q,
+               const uint8_t *qa, int64_t nq, int k, int L, const int32_t *seeds,
+               int nseeds, int ninit, int key_mode, int out_mode, int rerank_n, int64_t max_hops,
+               int32_t *out_ids, double *out_gamma, int64_t *out_ndc, int64_t *out_hops,
+               int32_t *out_flag, int nthreads)
+{
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nthreads)
+#endif
+    {
+        int64_t *stamp = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+        for (int64_t v = 0; v < n; ++v)
+            stamp[v] = -1;
+        pentry *pool = (pentry *)malloc(sizeof(pentry) * (size_t)(L + 1));
+        int ocap = (rerank_n > k ? rerank_n : k) + 1;
+        pentry *outl = (pentry *)malloc(sizeof(pentry) * (size_t)ocap);
+        pentry *best = (pentry *)malloc(sizeof(pentry) * (size_t)(ninit > 0 ? ninit : 1));
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+        for (int64_t iq = 0; iq < nq; ++iq) {
+            const float *qv = q + iq * (int64_t)d;
+            const uint8_t *qav = qa + iq * (int64_t)m;
+            int mq = or_arity(qav, m);
+            int size = 0;
+            int64_t ndc = 0, hops = 0;
+            int flag = 0;
+
+            /* score v and offer it to the pool (insertion keeps (key, id) order) */
+#define OFFER(vv)                                                                        \
+    do {                                                                                 \
+        int64_t v_ = (vv);                                                               \
+        double d2_ = or_delta2(qv, xs + v_ * (int64_t)d, d);                            \
+        int c_ = or_chi(qav, attrs + v_ * (int64_t)m, m);                               \
+        double k_ = or_order_key(d2_, c_, mq, key_mode);                                \
+        ndc += 1;                                                                        \
+        if (size == L && !lt(k_, v_, pool[L - 1].key, pool[L - 1].id))                  \
+            break;                                                                       \
+        int pos_ = (size < L) ? size : L - 1;                                            \
+        while (pos_ > 0 && lt(k_, v_, pool[pos_ - 1].key, pool[pos_ - 1].id)) {         \
+            pool[pos_] = pool[pos_ - 1];                                                 \
+            pos_ -= 1;                                                                   \
+        }                                                                                \
+        pool[pos_].key = k_;                                                             \
+        pool[pos_].d2 = d2_;                                                             \
+        pool[pos_].id = v_;                                                              \
+        pool[pos_].chi = c_;                                                             \
+        pool[pos_].expanded = 0;                                                         \
+        if (size < L)                                                                    \
+            size += 1;                                                                   \
+    } while (0)
+
+            /* Alg. 2 initialisation: C <- B, R <- B.  B is the n_init best
+             * (by key, id) of the entry sample; they enter the pool and the
+             * visited set.  Their scoring is not counted in NDC. */
+            {
+                int nb = 0;
+                for (int s = 0; s < nseeds; ++s) {
+                    int64_t v = seeds[s];
+                    if (v < 0 || v >= n)
+                        continue;
+                    double d2 = or_delta2(qv, xs + v * (int64_t)d, d);
+                    int c = or_chi(qav, attrs + v * (int64_t)m, m);
+                    double key = or_order_key(d2, c, mq, key_mode);
+                    int dup = 0;
+                    for (int t = 0; t < nb; ++t)
+                        if (best[t].id == v)
+                            dup = 1;
+                    if (dup)
+                        continue;
+                    if (nb == ninit && !lt(key, v, best[ninit - 1].key, best[ninit - 1].id))
+                        continue;
+                    int pos = (nb < ninit) ? nb : ninit - 1;
+                    while (pos > 0 && lt(key, v, best[pos - 1].key, best[pos - 1].id)) {
+                        best[pos] = best[pos - 1];
+                        pos -= 1;
+                    }
+                    best[pos].key = key;
+                    best[pos].d2 = d2;
+                    best[pos].id = v;
+                    best[pos].chi = c;
+                    best[pos].expanded = 0;
+                    if (nb < ninit)
+                        nb += 1;
+                }
+                for (int t = 0; t < nb && t < L; ++t) {
+                    pool[t] = best[t];
+                    stamp[best[t].id] = iq;
+                }
+                size = nb < L ? nb : L;
+            }
+            /* expansion loop: take the best unexpanded vertex, score its
+             * unvisited neighbours, keep the L best (joint pruning) */
+            for (;;) {
+                int cur = -1;
+                for (int t = 0; t < size; ++t)
+                    if (!pool[t].expanded) {
+                        cur = t;
+                        break;
+                    }
+                if (cur < 0)
+                    break;
+                if (hops >= max_hops) {
+                    flag = 1;
+                    break;
+                }
+                pool[cur].expanded = 1;
+                hops += 1;
+                int64_t u = pool[cur].id;
+                for (int t = 0; t < R; ++t) {
+                    int64_t v = adj[u * (int64_t)R + t];
+                    if (v < 0 || v >= n)
+                        continue;
+                    if (stamp[v] == iq)
+                        continue;
+                    stamp[v] = iq;
+                    OFFER(v);
+                }
+            }
+#undef OFFER
+            /* output: Def. 4 filter (mode 0) or raw pool order (mode 1) */
+            int want = (rerank_n > 0 && xr) ? rerank_n : k;
+            int no = 0;
+            for (int t = 0; t < size && no < want; ++t)
+                if (out_mode == 1 || pool[t].chi == 0)
+                    outl[no++] = pool[t];
+            if (rerank_n > 0 && xr) {
+                for (int t = 0; t < no; ++t) {
+                    outl[t].d2 = or_delta2(qv, xr + outl[t].id * (int64_t)d, d);
+                    outl[t].key = or_order_key(outl[t].d2, outl[t].chi, mq, OR_KEY64);
+                }
+                for (int t = 1; t < no; ++t) { /* insertion sort by (key, id) */
+                    pentry e = outl[t];
+                    int p = t;
+                    while (p > 0 && lt(e.key, e.id, outl[p - 1].key, outl[p - 1].id)) {
+                        outl[p] = outl[p - 1];
+                        p -= 1;
+                    }
+                    outl[p] = e;
+                }
+            }
+            for (int j = 0; j < k; ++j) {
+                if (j < no) {
+                    out_ids[iq * k + j] = (int32_t)outl[j].id;
+                    out_gamma[iq * k + j] = or_gamma(sqrt(outl[j].d2), outl[j].chi, mq);
+                } else {
+                    out_ids[iq * k + j] = -1;
+                    out_gamma[iq * k + j] = INFINITY;
+                }
+            }
+            if (out_ndc)
+                out_ndc[iq] = ndc;
+            if (out_hops)
+                out_hops[iq] = hops;
+            if (out_flag)
+                out_flag[iq] = flag;
+        }
+        free(stamp);
+        free(pool);
+        free(outl);
+        free(best);
+    }
+}
