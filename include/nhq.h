@@ -1,0 +1,168 @@
+/*
+ * libnhq -- native hybrid queries (NHQ, Wang et al., arXiv 2203.13601) on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * A hybrid query (Def. 4) asks for the k objects nearest to a query vector
+ * among the objects whose structured attributes equal the query's.  NHQ
+ * answers it with one proximity graph, the composite index (Alg. 1, Sec. 5.1),
+ * whose edges are chosen under the fusion distance Gamma (Eq. 6) with the
+ * landing-zone edge selection (Sec. 4.1, Def. 7), and one best-first search
+ * that prunes on vectors and attributes at once (joint pruning, Alg. 2).
+ *
+ * Conventions for every entry point:
+ *  - Array arguments are DEVICE pointers owned by the caller unless marked
+ *    "host".  Vectors are row-major float32 [rows][d]; attribute codes are
+ *    row-major uint8 [rows][m] with m <= 4 and object codes < 255; in query
+ *    codes 255 (0xFF) marks an unconstrained attribute (wildcard).
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
+ *    is asynchronous unless stated otherwise: outputs are valid once the
+ *    stream has been synchronised.
+ *  - Return value: NHQ_OK (0) or a negative NHQ_E* code; nhq_strerror() turns
+ *    it into text and nhq_last_error() gives the calling thread's last
+ *    detailed message.  No C++ exception crosses this boundary.
+ *  - An index owns every device copy it makes; it never aliases caller memory
+ *    after a call returns.  Calls that use one index must be ordered on one
+ *    stream (they share the index's workspace).
+ *  - Fusion distance: Gamma(q, e) = delta * (1 + chi / m_q) where delta is the
+ *    Euclidean distance (Eq. 1), chi the number of constrained attributes on
+ *    which the codes differ (Eq. 4-5) and m_q the number of constrained
+ *    attributes (Gamma = delta when m_q = 0).  These are the weights
+ *    w_v = 1, w_l = delta / m of Sec. 3.2.  Between two objects m_q = m.
+ *  - Results: ids int32 [nq][k] padded with -1, distances float32 [nq][k]
+ *    (Gamma) padded with +inf.
+ */
+#ifndef NHQ_H
+#define NHQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NHQ_OK 0
+#define NHQ_EINVAL (-1)   /* bad argument: shape, size, mode, null pointer   */
+#define NHQ_ENOMEM (-2)   /* device or host allocation failed                 */
+#define NHQ_EHIP (-3)     /* a HIP runtime call or kernel launch failed       */
+#define NHQ_EDEVICE (-4)  /* a kernel raised its error word (see below)       */
+#define NHQ_ENOTSUP (-5)  /* valid request this build does not support        */
+#define NHQ_EIO (-6)      /* file error in save / load                        */
+#define NHQ_EBUSY (-7)    /* serving: no free slot or ring entry              */
+
+#define NHQ_STORAGE_FP32 0
+#define NHQ_STORAGE_BF16 1
+#define NHQ_STORAGE_FP8 2 /* OCP e4m3 with one float32 scale per vector */
+
+#define NHQ_MAX_DEGREE 64
+#define NHQ_MAX_BEAM 1024
+#define NHQ_MAX_ATTRS 4
+
+typedef struct nhq_index nhq_index;
+
+/* Build parameters (Alg. 1 / Sec. 4.1 / Sec. 4.3).  Zero fields take the
+ * defaults given in brackets. */
+typedef struct {
+    int32_t degree;        /* R: out-degree bound of the graph            [32] */
+    int32_t cand;          /* l: candidate-list size of edge selection    [64] */
+    int32_t reverse_edges; /* 1: re-select each row from its forward edges
+                              united with the vertices that chose it       [0] */
+    int32_t storage;       /* NHQ_STORAGE_*: form the search scores with   [0] */
+    int32_t n_entry;       /* size of the random entry sample from which each
+                              query's seed set is taken                  [1024] */
+    int32_t reserved0;
+    uint64_t seed;         /* splitmix64 seed of the entry sample          [0] */
+} nhq_build_params;
+
+/* Search parameters (Alg. 2).  Pass NULL for all defaults. */
+typedef struct {
+    int32_t n_init;      /* seed set size: the best n_init members of the
+                            entry sample start the pool                   [32] */
+    int32_t rerank;      /* r > 0: re-score the first r*k eligible pool entries
+                            from the float32 copy and re-sort (precision form;
+                            r*k <= beam); 0: off                           [0] */
+    int32_t output_mode; /* 0: exact attribute matches only (Def. 4);
+                            1: the first k pool entries by Gamma           [0] */
+    int32_t max_hops;    /* expansion cap; reaching it sets the error word
+                            bit NHQ_DEVERR_HOPCAP                      [100000] */
+    int32_t visited_log2;/* log2 slots of the per-query visited hash (10..13);
+                            0 = automatic                                  [0] */
+    int32_t learned;     /* 1: in-loop stop/beam network (needs nhq_mlp_load) */
+    float stop_threshold;/* stop when sigmoid(stop logit) exceeds it    [0.5] */
+    int32_t check_every; /* network evaluated every this many hops        [4] */
+    uint32_t *counters;  /* nullable DEVICE uint32 [nq][2]: NDC (neighbour
+                            distance evaluations) and H (expansions)          */
+} nhq_search_params;
+
+/* Device error word bits (accumulated per index; nhq_index_device_error). */
+#define NHQ_DEVERR_HOPCAP 0x1u
+#define NHQ_DEVERR_BADID 0x2u
+
+/* ------------------------------------------------------------------ index */
+
+/* Ingest an object set (Def. 1): copies the vectors (padded to the kernel
+ * width), packs the attribute codes, derives the storage form, the row norms
+ * and the entry sample.  The graph is empty until nhq_index_build_graph or
+ * nhq_index_set_graph.  vecs: device float32 [n][d]; attrs: device uint8
+ * [n][m]; n in [1, 2^28); d in [1, 1024]; m in [0, 4].  Synchronises the
+ * stream before returning (ingest statistics are read back). */
+int nhq_index_create(const float *vecs, const uint8_t *attrs, int64_t n, int32_t d, int32_t m,
+                     const nhq_build_params *params, void *stream, nhq_index **out);
+
+/* Composite-index build on the GPU (Alg. 1 in degree-bounded form with the
+ * fusion distance of Sec. 5.1): exact l nearest candidates under Gamma from
+ * dense tiles, the landing-zone selection of Sec. 4.1 steps (1)-(3), and the
+ * optional reverse-edge pass. */
+int nhq_index_build_graph(nhq_index *ix, void *stream);
+
+/* nhq_index_create followed by nhq_index_build_graph. */
+int nhq_build_index(const float *vecs, const uint8_t *attrs, int64_t n, int32_t d, int32_t m,
+                    const nhq_build_params *params, void *stream, nhq_index **out);
+
+/* Install a graph built elsewhere: adj device int32 [n][degree], -1 padded,
+ * ids in [0, n).  degree in [1, 64].  The index keeps its own copy. */
+int nhq_index_set_graph(nhq_index *ix, const int32_t *adj, int32_t degree, void *stream);
+
+/* Copy the graph (device int32 [n][degree]) / the entry sample (device int32
+ * [n_entry]) out of the index. */
+int nhq_index_get_graph(const nhq_index *ix, int32_t *adj_out, void *stream);
+int nhq_index_get_entry(const nhq_index *ix, int32_t *entry_out, void *stream);
+
+/* Shape queries (host outputs, any may be NULL). */
+int nhq_index_info(const nhq_index *ix, int64_t *n, int32_t *d, int32_t *m, int32_t *degree,
+                   int32_t *storage, int32_t *n_entry);
+
+/* Read and clear the index's device error word (synchronises the stream). */
+int nhq_index_device_error(nhq_index *ix, void *stream, uint32_t *bits_out);
+
+void nhq_index_free(nhq_index *ix);
+
+/* ----------------------------------------------------------------- search */
+
+/* Hybrid query (Def. 4) answered by joint pruning (Alg. 2) in beam form: one
+ * wavefront per query keeps the `beam` best vertices by Gamma in LDS, expands
+ * the best unexpanded one (gathers its adjacency row, the attribute words and
+ * vectors of its unvisited neighbours), offers each neighbour to the pool,
+ * and stops when every pool entry is expanded.  Output per output_mode.
+ * queries: device float32 [nq][d]; qattrs: device uint8 [nq][m];
+ * 1 <= k <= beam <= 1024; ids: device int32 [nq][k]; dists: device float32
+ * [nq][k].  nq = 0 is a no-op. */
+int nhq_hybrid_search(const nhq_index *ix, const float *queries, const uint8_t *qattrs,
+                      int64_t nq, int32_t k, int32_t beam, const nhq_search_params *sp,
+                      int32_t *ids, float *dists, void *stream);
+
+/* Exact hybrid k-NN (Def. 4 with Def. 2): exact attribute filter, then the k
+ * nearest matches by (delta, id).  Same argument layout as the search; k in
+ * [1, 1024].  dists are delta (= Gamma for matches). */
+int nhq_bruteforce_hybrid_knn(const nhq_index *ix, const float *queries, const uint8_t *qattrs,
+                              int64_t nq, int32_t k, int32_t *ids, float *dists, void *stream);
+
+/* ------------------------------------------------------------------ misc */
+const char *nhq_strerror(int code);
+const char *nhq_last_error(void);
+int nhq_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NHQ_H */

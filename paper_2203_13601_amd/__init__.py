@@ -1,0 +1,12 @@
+"""MI355X-native native hybrid queries (NHQ, arXiv 2203.13601).
+
+The product is ``libnhq.so`` (HIP kernels for gfx950 behind the C ABI of
+``include/nhq.h``); this package is its thin Python binding.  Importing it
+does not load the library; the first call does, and raises if the library
+has not been built.
+"""
+from ._binding import (BuildParams, Index, NHQError, SearchParams, lib,  # noqa: F401
+                       nhq_bruteforce_hybrid_knn, nhq_build_index, nhq_hybrid_search,
+                       nhq_index_build_graph, nhq_index_create, nhq_index_device_error,
+                       nhq_index_get_entry, nhq_index_get_graph, nhq_index_info,
+                       nhq_index_set_graph, DEVERR_BADID, DEVERR_HOPCAP, STORAGE)

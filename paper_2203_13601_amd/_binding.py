@@ -1,0 +1,242 @@
+"""ctypes binding of libnhq: argument marshalling only.
+
+Every function here has the name of the C entry point it calls and does no
+arithmetic of the method: it checks shapes and dtypes, passes device
+pointers and the current HIP stream of torch, and turns error codes into
+``NHQError``.  Tensors must live on the GPU the index was created on.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnhq.so")
+
+STORAGE = {"fp32": 0, "bf16": 1, "fp8": 2}
+DEVERR_HOPCAP = 0x1
+DEVERR_BADID = 0x2
+
+
+class NHQError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__("%s failed (%d): %s" % (where, code, msg))
+        self.code = code
+
+
+class BuildParams(ctypes.Structure):
+    _fields_ = [("degree", ctypes.c_int32), ("cand", ctypes.c_int32),
+                ("reverse_edges", ctypes.c_int32), ("storage", ctypes.c_int32),
+                ("n_entry", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+class SearchParams(ctypes.Structure):
+    _fields_ = [("n_init", ctypes.c_int32), ("rerank", ctypes.c_int32),
+                ("output_mode", ctypes.c_int32), ("max_hops", ctypes.c_int32),
+                ("visited_log2", ctypes.c_int32), ("learned", ctypes.c_int32),
+                ("stop_threshold", ctypes.c_float), ("check_every", ctypes.c_int32),
+                ("counters", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libnhq.so (after torch, so both use torch's HIP runtime).  Fails
+    loudly when the library has not been built: there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libnhq.so is not built (run __graft_entry__.build() or "
+                          "python -m paper_2203_13601_amd.build_lib)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    sig = {
+        "nhq_index_create": ([P, P, i64, i32, i32, P, P, P], i32),
+        "nhq_index_build_graph": ([P, P], i32),
+        "nhq_build_index": ([P, P, i64, i32, i32, P, P, P], i32),
+        "nhq_index_set_graph": ([P, P, i32, P], i32),
+        "nhq_index_get_graph": ([P, P, P], i32),
+        "nhq_index_get_entry": ([P, P, P], i32),
+        "nhq_index_info": ([P, P, P, P, P, P, P], i32),
+        "nhq_index_device_error": ([P, P, P], i32),
+        "nhq_index_free": ([P], None),
+        "nhq_hybrid_search": ([P, P, P, i64, i32, i32, P, P, P, P], i32),
+        "nhq_bruteforce_hybrid_knn": ([P, P, P, i64, i32, P, P, P], i32),
+        "nhq_strerror": ([i32], ctypes.c_char_p),
+        "nhq_last_error": ([], ctypes.c_char_p),
+        "nhq_version": ([], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != 0:
+        L = lib()
+        raise NHQError(rc, where, L.nhq_last_error().decode() or L.nhq_strerror(rc).decode())
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, name: str, ndim: int) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if t.dim() != ndim:
+        raise ValueError("%s must have %d dimensions" % (name, ndim))
+    return t.contiguous()
+
+
+class Index:
+    """Owning handle of an nhq_index."""
+
+    def __init__(self, handle: ctypes.c_void_p, keep=()):
+        self._h = handle
+        self._keep = keep
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if not self._h:
+            raise ValueError("index was freed")
+        return self._h
+
+    def free(self) -> None:
+        if self._h:
+            lib().nhq_index_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _params(degree=32, cand=64, reverse_edges=False, storage="fp32", n_entry=1024, seed=0):
+    return BuildParams(int(degree), int(cand), int(bool(reverse_edges)),
+                       STORAGE[storage] if isinstance(storage, str) else int(storage),
+                       int(n_entry), 0, int(seed))
+
+
+def nhq_index_create(vecs: torch.Tensor, attrs: torch.Tensor, stream=None, **params) -> Index:
+    vecs = _dev(vecs, torch.float32, "vecs", 2)
+    attrs = _dev(attrs, torch.uint8, "attrs", 2)
+    if attrs.shape[0] != vecs.shape[0]:
+        raise ValueError("vecs and attrs differ in rows")
+    p = _params(**params)
+    h = ctypes.c_void_p()
+    _check(lib().nhq_index_create(vecs.data_ptr(), attrs.data_ptr(), vecs.shape[0], vecs.shape[1],
+                                  attrs.shape[1], ctypes.byref(p), _stream(stream), ctypes.byref(h)),
+           "nhq_index_create")
+    return Index(h)
+
+
+def nhq_index_build_graph(ix: Index, stream=None) -> None:
+    _check(lib().nhq_index_build_graph(ix.handle, _stream(stream)), "nhq_index_build_graph")
+
+
+def nhq_build_index(vecs: torch.Tensor, attrs: torch.Tensor, stream=None, **params) -> Index:
+    vecs = _dev(vecs, torch.float32, "vecs", 2)
+    attrs = _dev(attrs, torch.uint8, "attrs", 2)
+    if attrs.shape[0] != vecs.shape[0]:
+        raise ValueError("vecs and attrs differ in rows")
+    p = _params(**params)
+    h = ctypes.c_void_p()
+    _check(lib().nhq_build_index(vecs.data_ptr(), attrs.data_ptr(), vecs.shape[0], vecs.shape[1],
+                                 attrs.shape[1], ctypes.byref(p), _stream(stream), ctypes.byref(h)),
+           "nhq_build_index")
+    return Index(h)
+
+
+def nhq_index_set_graph(ix: Index, adj: torch.Tensor, stream=None) -> None:
+    adj = _dev(adj, torch.int32, "adj", 2)
+    n = nhq_index_info(ix)["n"]
+    if adj.shape[0] != n:
+        raise ValueError("adj must have n rows")
+    _check(lib().nhq_index_set_graph(ix.handle, adj.data_ptr(), adj.shape[1], _stream(stream)),
+           "nhq_index_set_graph")
+
+
+def nhq_index_info(ix: Index) -> dict:
+    n = ctypes.c_int64()
+    d, m, deg, st, ne = (ctypes.c_int32() for _ in range(5))
+    _check(lib().nhq_index_info(ix.handle, ctypes.byref(n), ctypes.byref(d), ctypes.byref(m),
+                                ctypes.byref(deg), ctypes.byref(st), ctypes.byref(ne)),
+           "nhq_index_info")
+    return {"n": n.value, "d": d.value, "m": m.value, "degree": deg.value,
+            "storage": st.value, "n_entry": ne.value}
+
+
+def nhq_index_get_graph(ix: Index, stream=None) -> torch.Tensor:
+    info = nhq_index_info(ix)
+    out = torch.empty((info["n"], info["degree"]), dtype=torch.int32, device="cuda")
+    _check(lib().nhq_index_get_graph(ix.handle, out.data_ptr(), _stream(stream)), "nhq_index_get_graph")
+    return out
+
+
+def nhq_index_get_entry(ix: Index, stream=None) -> torch.Tensor:
+    info = nhq_index_info(ix)
+    out = torch.empty((info["n_entry"],), dtype=torch.int32, device="cuda")
+    _check(lib().nhq_index_get_entry(ix.handle, out.data_ptr(), _stream(stream)), "nhq_index_get_entry")
+    return out
+
+
+def nhq_index_device_error(ix: Index, stream=None) -> int:
+    bits = ctypes.c_uint32()
+    _check(lib().nhq_index_device_error(ix.handle, _stream(stream), ctypes.byref(bits)),
+           "nhq_index_device_error")
+    return bits.value
+
+
+def nhq_hybrid_search(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, k: int, beam: int,
+                      n_init: int = 32, rerank: int = 0, output_mode: int = 0, max_hops: int = 0,
+                      visited_log2: int = 0, learned: bool = False, stop_threshold: float = 0.0,
+                      check_every: int = 0, counters: bool = False, stream=None,
+                      out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None):
+    """Returns (ids int32 [nq,k], dists float32 [nq,k]) and, with
+    counters=True, a uint32-valued int32 tensor [nq,2] of (NDC, H)."""
+    queries = _dev(queries, torch.float32, "queries", 2)
+    qattrs = _dev(qattrs, torch.uint8, "qattrs", 2)
+    nq = queries.shape[0]
+    if qattrs.shape[0] != nq:
+        raise ValueError("queries and qattrs differ in rows")
+    if out is None:
+        ids = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
+        dists = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
+    else:
+        ids, dists = out
+    cnt = torch.zeros((nq, 2), dtype=torch.int32, device=queries.device) if counters else None
+    sp = SearchParams(int(n_init), int(rerank), int(output_mode), int(max_hops), int(visited_log2),
+                      int(bool(learned)), float(stop_threshold), int(check_every),
+                      cnt.data_ptr() if cnt is not None else None)
+    _check(lib().nhq_hybrid_search(ix.handle, queries.data_ptr(), qattrs.data_ptr(), nq, int(k),
+                                   int(beam), ctypes.byref(sp), ids.data_ptr(), dists.data_ptr(),
+                                   _stream(stream)), "nhq_hybrid_search")
+    return (ids, dists, cnt) if counters else (ids, dists)
+
+
+def nhq_bruteforce_hybrid_knn(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, k: int,
+                              stream=None):
+    queries = _dev(queries, torch.float32, "queries", 2)
+    qattrs = _dev(qattrs, torch.uint8, "qattrs", 2)
+    nq = queries.shape[0]
+    ids = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
+    dists = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
+    _check(lib().nhq_bruteforce_hybrid_knn(ix.handle, queries.data_ptr(), qattrs.data_ptr(), nq,
+                                           int(k), ids.data_ptr(), dists.data_ptr(), _stream(stream)),
+           "nhq_bruteforce_hybrid_knn")
+    return ids, dists

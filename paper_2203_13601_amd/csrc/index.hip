@@ -1,0 +1,494 @@
+// Index object, ingest kernels (attribute packing, storage conversion, row
+// norms) and the C entry points of libnhq that are not kernels themselves.
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <unordered_set>
+#include <vector>
+
+#include "nhq_internal.h"
+
+namespace nhq {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+int padded_dim(int d)
+{
+    static const int widths[] = {32, 64, 96, 128, 256, 512, 960, 1024};
+    for (int w : widths)
+        if (d <= w)
+            return w;
+    return -1;
+}
+
+int ensure_workspace(Index *ix, size_t bytes)
+{
+    if (ix->ws_bytes >= bytes)
+        return NHQ_OK;
+    if (ix->ws) {
+        NHQ_HIP(hipDeviceSynchronize());
+        NHQ_HIP(hipFree(ix->ws));
+        ix->ws = nullptr;
+        ix->ws_bytes = 0;
+    }
+    if (hipMalloc(&ix->ws, bytes) != hipSuccess)
+        return fail(NHQ_ENOMEM, "workspace allocation failed");
+    ix->ws_bytes = bytes;
+    return NHQ_OK;
+}
+
+namespace {
+
+// ---------------------------------------------------------------- kernels
+__global__ void k_pad_copy(const float *__restrict__ src, float *__restrict__ dst, int64_t n,
+                           int d, int dp)
+{
+    const int64_t total = n * dp;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = t / dp;
+        const int c = (int)(t - r * dp);
+        dst[t] = c < d ? src[r * d + c] : 0.0f;
+    }
+}
+
+// attribute codes (one byte each) packed little-endian into one word
+__global__ void k_pack_attr(const uint8_t *__restrict__ a, uint32_t *__restrict__ out, int64_t n,
+                            int m, uint32_t *__restrict__ bad)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t w = 0;
+        for (int j = 0; j < m; ++j) {
+            const uint32_t c = a[i * m + j];
+            if (c == 0xFFu)
+                atomicOr(bad, 1u);
+            w |= c << (8 * j);
+        }
+        out[i] = w;
+    }
+}
+
+__global__ void k_row_norm(const float *__restrict__ v, float *__restrict__ norm, int64_t n, int dp)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float *r = v + i * dp;
+        float s = 0.0f;
+        for (int c = 0; c < dp; ++c)
+            s = fmaf(r[c], r[c], s);
+        norm[i] = s;
+    }
+}
+
+// float32 -> bfloat16, round to nearest even (finite inputs)
+__global__ void k_to_bf16(const float *__restrict__ v, uint16_t *__restrict__ out, int64_t total)
+{
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t u = __float_as_uint(v[t]);
+        out[t] = (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+    }
+}
+
+// OCP e4m3 ("FN": bias 7, no infinities, largest finite 448) of a double,
+// nearest value with ties to the even code, saturating at +-448.
+__device__ uint8_t e4m3_from_double(double x)
+{
+    const uint32_t sign = signbit(x) ? 0x80u : 0u;
+    const double a = fabs(x);
+    uint32_t code;
+    if (a >= 448.0) {
+        code = 0x7Eu;
+    } else if (a < 0.015625) {  // below 2^-6: multiples of 2^-9
+        code = (uint32_t)rint(a * 512.0);  // 8 lands on 2^-6, code 0x08
+    } else {
+        int ex;
+        const double f = frexp(a, &ex);  // a = f 2^ex, f in [0.5, 1)
+        const int e = ex - 1;             // a in [2^e, 2^(e+1))
+        uint32_t mant = (uint32_t)rint((2.0 * f - 1.0) * 8.0);
+        int be = e + 7;
+        if (mant == 8u) {
+            mant = 0;
+            be += 1;
+        }
+        code = ((uint32_t)be << 3) | mant;
+        if (code > 0x7Eu)
+            code = 0x7Eu;
+    }
+    return (uint8_t)(code | sign);
+}
+
+// one wave per row: scale s = max|x| / 448 (1 for a zero row), codes e4m3(x/s)
+__global__ __launch_bounds__(64) void k_to_fp8(const float *__restrict__ v, uint8_t *__restrict__ out,
+                                               float *__restrict__ scale, int64_t n, int dp)
+{
+    const int lane = threadIdx.x;
+    for (int64_t r = blockIdx.x; r < n; r += gridDim.x) {
+        const float *row = v + r * dp;
+        float mx = 0.0f;
+        for (int c = lane; c < dp; c += 64)
+            mx = fmaxf(mx, fabsf(row[c]));
+        for (int o = 32; o > 0; o >>= 1)
+            mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+        const float s = mx > 0.0f ? mx / 448.0f : 1.0f;
+        for (int c = lane; c < dp; c += 64)
+            out[r * dp + c] = e4m3_from_double((double)row[c] / (double)s);
+        if (lane == 0)
+            scale[r] = s;
+    }
+}
+
+int grid_for(int64_t work, int block)
+{
+    int64_t g = (work + block - 1) / block;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
+}
+
+void free_index(Index *ix)
+{
+    if (!ix)
+        return;
+    if (ix->vecs && ix->vecs != ix->vec32)
+        (void)hipFree(ix->vecs);
+    void *ptrs[] = {ix->vec32, ix->scale, ix->attr, ix->norm, ix->adj, ix->entry, ix->err, ix->ws, ix->mlp};
+    for (void *p : ptrs)
+        if (p)
+            (void)hipFree(p);
+}
+
+}  // namespace
+}  // namespace nhq
+
+using namespace nhq;
+
+extern "C" {
+
+int nhq_version(void) { return 1; }
+
+const char *nhq_strerror(int code)
+{
+    switch (code) {
+    case NHQ_OK:
+        return "ok";
+    case NHQ_EINVAL:
+        return "invalid argument";
+    case NHQ_ENOMEM:
+        return "out of memory";
+    case NHQ_EHIP:
+        return "HIP runtime error";
+    case NHQ_EDEVICE:
+        return "device error word set";
+    case NHQ_ENOTSUP:
+        return "not supported";
+    case NHQ_EIO:
+        return "i/o error";
+    case NHQ_EBUSY:
+        return "busy";
+    }
+    return "unknown error";
+}
+
+const char *nhq_last_error(void) { return g_last_error.c_str(); }
+
+int nhq_index_create(const float *vecs, const uint8_t *attrs, int64_t n, int32_t d, int32_t m,
+                     const nhq_build_params *params, void *stream, nhq_index **out)
+{
+    if (!out)
+        return fail(NHQ_EINVAL, "out is null");
+    *out = nullptr;
+    if (!vecs || (m > 0 && !attrs))
+        return fail(NHQ_EINVAL, "vecs/attrs is null");
+    if (n < 1 || n >= kMaxN)
+        return fail(NHQ_EINVAL, "n must be in [1, 2^28)");
+    if (d < 1 || d > 1024)
+        return fail(NHQ_EINVAL, "d must be in [1, 1024]");
+    if (m < 0 || m > NHQ_MAX_ATTRS)
+        return fail(NHQ_EINVAL, "m must be in [0, 4]");
+    nhq_build_params p{};
+    if (params)
+        p = *params;
+    if (p.degree == 0)
+        p.degree = 32;
+    if (p.cand == 0)
+        p.cand = 64;
+    if (p.n_entry == 0)
+        p.n_entry = 1024;
+    if (p.degree < 1 || p.degree > NHQ_MAX_DEGREE)
+        return fail(NHQ_EINVAL, "degree must be in [1, 64]");
+    if (p.cand < p.degree || p.cand > 256)
+        return fail(NHQ_EINVAL, "cand must be in [degree, 256]");
+    if (p.storage < 0 || p.storage > 2)
+        return fail(NHQ_EINVAL, "storage must be 0, 1 or 2");
+    if (p.n_entry < 1 || p.n_entry > 65536)
+        return fail(NHQ_EINVAL, "n_entry must be in [1, 65536]");
+
+    hipStream_t st = (hipStream_t)stream;
+    nhq_index *h = new (std::nothrow) nhq_index();
+    if (!h)
+        return fail(NHQ_ENOMEM, "host allocation failed");
+    Index *ix = &h->impl;
+    int rc = NHQ_OK;
+    do {
+        if (hipGetDevice(&ix->device) != hipSuccess) {
+            rc = fail(NHQ_EHIP, "hipGetDevice failed");
+            break;
+        }
+        ix->n = n;
+        ix->d = d;
+        ix->dp = padded_dim(d);
+        ix->m = m;
+        ix->storage = p.storage;
+        ix->cand = p.cand;
+        ix->reverse_edges = p.reverse_edges ? 1 : 0;
+        ix->seed = p.seed;
+        ix->degree = 0;
+        const int want_degree = p.degree;
+        const size_t rows = (size_t)n * ix->dp;
+        if (hipMalloc(&ix->vec32, rows * sizeof(float)) != hipSuccess ||
+            hipMalloc(&ix->attr, (size_t)n * sizeof(uint32_t)) != hipSuccess ||
+            hipMalloc(&ix->norm, (size_t)n * sizeof(float)) != hipSuccess ||
+            hipMalloc(&ix->err, 2 * sizeof(uint32_t)) != hipSuccess) {
+            rc = fail(NHQ_ENOMEM, "index allocation failed");
+            break;
+        }
+        ix->degree = want_degree;  // graph allocated now, filled by build/set
+        if (hipMalloc(&ix->adj, (size_t)n * want_degree * sizeof(int32_t)) != hipSuccess) {
+            rc = fail(NHQ_ENOMEM, "graph allocation failed");
+            break;
+        }
+        if (hipMemsetAsync(ix->adj, 0xFF, (size_t)n * want_degree * sizeof(int32_t), st) != hipSuccess ||
+            hipMemsetAsync(ix->err, 0, 2 * sizeof(uint32_t), st) != hipSuccess) {
+            rc = fail(NHQ_EHIP, "memset failed");
+            break;
+        }
+        hipLaunchKernelGGL(k_pad_copy, dim3(grid_for((int64_t)rows, 256)), dim3(256), 0, st, vecs,
+                           ix->vec32, n, d, ix->dp);
+        if (m > 0) {
+            hipLaunchKernelGGL(k_pack_attr, dim3(grid_for(n, 256)), dim3(256), 0, st, attrs,
+                               ix->attr, n, m, ix->err + 1);
+        } else {
+            (void)hipMemsetAsync(ix->attr, 0, (size_t)n * sizeof(uint32_t), st);
+        }
+        hipLaunchKernelGGL(k_row_norm, dim3(grid_for(n, 256)), dim3(256), 0, st, ix->vec32, ix->norm,
+                           n, ix->dp);
+        if (ix->storage == NHQ_STORAGE_FP32) {
+            ix->vecs = ix->vec32;
+        } else if (ix->storage == NHQ_STORAGE_BF16) {
+            if (hipMalloc(&ix->vecs, rows * sizeof(uint16_t)) != hipSuccess) {
+                rc = fail(NHQ_ENOMEM, "bf16 storage allocation failed");
+                break;
+            }
+            hipLaunchKernelGGL(k_to_bf16, dim3(grid_for((int64_t)rows, 256)), dim3(256), 0, st,
+                               ix->vec32, (uint16_t *)ix->vecs, (int64_t)rows);
+        } else {
+            if (hipMalloc(&ix->vecs, rows) != hipSuccess ||
+                hipMalloc(&ix->scale, (size_t)n * sizeof(float)) != hipSuccess) {
+                rc = fail(NHQ_ENOMEM, "fp8 storage allocation failed");
+                break;
+            }
+            hipLaunchKernelGGL(k_to_fp8, dim3(grid_for(n, 1)), dim3(64), 0, st, ix->vec32,
+                               (uint8_t *)ix->vecs, ix->scale, n, ix->dp);
+        }
+        if (hipGetLastError() != hipSuccess) {
+            rc = fail(NHQ_EHIP, "ingest kernel launch failed");
+            break;
+        }
+        // entry sample: first n_entry distinct splitmix64 values mod n
+        const int64_t ne = std::min<int64_t>(p.n_entry, n);
+        std::vector<int32_t> ent;
+        ent.reserve((size_t)ne);
+        std::unordered_set<int64_t> seen;
+        uint64_t state = p.seed;
+        while ((int64_t)ent.size() < ne) {
+            const int64_t v = (int64_t)(splitmix64_next(state) % (uint64_t)n);
+            if (seen.insert(v).second)
+                ent.push_back((int32_t)v);
+        }
+        ix->n_entry = (int)ne;
+        if (hipMalloc(&ix->entry, (size_t)ne * sizeof(int32_t)) != hipSuccess) {
+            rc = fail(NHQ_ENOMEM, "entry allocation failed");
+            break;
+        }
+        if (hipMemcpyAsync(ix->entry, ent.data(), (size_t)ne * sizeof(int32_t), hipMemcpyHostToDevice,
+                           st) != hipSuccess) {
+            rc = fail(NHQ_EHIP, "entry upload failed");
+            break;
+        }
+        uint32_t bad = 0;
+        if (hipMemcpyAsync(&bad, ix->err + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            rc = fail(NHQ_EHIP, "ingest synchronisation failed");
+            break;
+        }
+        if (bad) {
+            rc = fail(NHQ_EINVAL, "object attribute code 255 is reserved for query wildcards");
+            break;
+        }
+    } while (0);
+    if (rc != NHQ_OK) {
+        free_index(ix);
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return NHQ_OK;
+}
+
+int nhq_index_set_graph(nhq_index *h, const int32_t *adj, int32_t degree, void *stream)
+{
+    if (!h || !adj)
+        return fail(NHQ_EINVAL, "null argument");
+    Index *ix = &h->impl;
+    if (degree < 1 || degree > NHQ_MAX_DEGREE)
+        return fail(NHQ_EINVAL, "degree must be in [1, 64]");
+    hipStream_t st = (hipStream_t)stream;
+    if (degree != ix->degree) {
+        NHQ_HIP(hipStreamSynchronize(st));
+        if (ix->adj)
+            NHQ_HIP(hipFree(ix->adj));
+        ix->adj = nullptr;
+        if (hipMalloc(&ix->adj, (size_t)ix->n * degree * sizeof(int32_t)) != hipSuccess)
+            return fail(NHQ_ENOMEM, "graph allocation failed");
+        ix->degree = degree;
+    }
+    NHQ_HIP(hipMemcpyAsync(ix->adj, adj, (size_t)ix->n * degree * sizeof(int32_t),
+                           hipMemcpyDeviceToDevice, st));
+    return NHQ_OK;
+}
+
+int nhq_index_get_graph(const nhq_index *h, int32_t *adj_out, void *stream)
+{
+    if (!h || !adj_out)
+        return fail(NHQ_EINVAL, "null argument");
+    const Index *ix = &h->impl;
+    NHQ_HIP(hipMemcpyAsync(adj_out, ix->adj, (size_t)ix->n * ix->degree * sizeof(int32_t),
+                           hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return NHQ_OK;
+}
+
+int nhq_index_get_entry(const nhq_index *h, int32_t *entry_out, void *stream)
+{
+    if (!h || !entry_out)
+        return fail(NHQ_EINVAL, "null argument");
+    const Index *ix = &h->impl;
+    NHQ_HIP(hipMemcpyAsync(entry_out, ix->entry, (size_t)ix->n_entry * sizeof(int32_t),
+                           hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return NHQ_OK;
+}
+
+int nhq_index_info(const nhq_index *h, int64_t *n, int32_t *d, int32_t *m, int32_t *degree,
+                   int32_t *storage, int32_t *n_entry)
+{
+    if (!h)
+        return fail(NHQ_EINVAL, "null index");
+    const Index *ix = &h->impl;
+    if (n)
+        *n = ix->n;
+    if (d)
+        *d = ix->d;
+    if (m)
+        *m = ix->m;
+    if (degree)
+        *degree = ix->degree;
+    if (storage)
+        *storage = ix->storage;
+    if (n_entry)
+        *n_entry = ix->n_entry;
+    return NHQ_OK;
+}
+
+int nhq_index_device_error(nhq_index *h, void *stream, uint32_t *bits_out)
+{
+    if (!h || !bits_out)
+        return fail(NHQ_EINVAL, "null argument");
+    Index *ix = &h->impl;
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t bits = 0;
+    NHQ_HIP(hipMemcpyAsync(&bits, ix->err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    NHQ_HIP(hipStreamSynchronize(st));
+    NHQ_HIP(hipMemsetAsync(ix->err, 0, sizeof(uint32_t), st));
+    *bits_out = bits;
+    return NHQ_OK;
+}
+
+void nhq_index_free(nhq_index *h)
+{
+    if (!h)
+        return;
+    (void)hipDeviceSynchronize();
+    free_index(&h->impl);
+    delete h;
+}
+
+int nhq_hybrid_search(const nhq_index *h, const float *queries, const uint8_t *qattrs, int64_t nq,
+                      int32_t k, int32_t beam, const nhq_search_params *sp, int32_t *ids,
+                      float *dists, void *stream)
+{
+    if (!h)
+        return fail(NHQ_EINVAL, "null index");
+    const Index *ix = &h->impl;
+    if (nq < 0)
+        return fail(NHQ_EINVAL, "nq < 0");
+    if (nq == 0)
+        return NHQ_OK;
+    if (!queries || !ids || !dists || (ix->m > 0 && !qattrs))
+        return fail(NHQ_EINVAL, "null array argument");
+    if (k < 1 || beam < k || beam > NHQ_MAX_BEAM)
+        return fail(NHQ_EINVAL, "need 1 <= k <= beam <= 1024");
+    nhq_search_params p{};
+    if (sp)
+        p = *sp;
+    if (p.n_init == 0)
+        p.n_init = 32;
+    if (p.max_hops == 0)
+        p.max_hops = 100000;
+    if (p.stop_threshold == 0.0f)
+        p.stop_threshold = 0.5f;
+    if (p.check_every == 0)
+        p.check_every = 4;
+    if (p.n_init < 1 || p.max_hops < 1)
+        return fail(NHQ_EINVAL, "n_init and max_hops must be positive");
+    if (p.output_mode != 0 && p.output_mode != 1)
+        return fail(NHQ_EINVAL, "output_mode must be 0 or 1");
+    if (p.rerank < 0 || (int64_t)p.rerank * k > beam)
+        return fail(NHQ_EINVAL, "rerank * k must not exceed beam");
+    if (p.visited_log2 != 0 && (p.visited_log2 < 10 || p.visited_log2 > 13))
+        return fail(NHQ_EINVAL, "visited_log2 must be 0 or in [10, 13]");
+    if (p.learned && !ix->mlp)
+        return fail(NHQ_EINVAL, "learned stop requested but no network is loaded");
+    SearchLaunch s{};
+    s.ix = ix;
+    s.q = queries;
+    s.qa = qattrs;
+    s.nq = nq;
+    s.k = k;
+    s.L = beam;
+    s.n_init = p.n_init;
+    s.out_mode = p.output_mode;
+    s.rerank_n = p.rerank * k;
+    s.max_hops = p.max_hops;
+    s.hash_log2 = p.visited_log2;
+    s.learned = p.learned;
+    s.check_every = p.check_every;
+    s.stop_threshold = p.stop_threshold;
+    s.ids = ids;
+    s.dists = dists;
+    s.counters = p.counters;
+    s.stream = (hipStream_t)stream;
+    return launch_search(s);
+}
+
+}  // extern "C"

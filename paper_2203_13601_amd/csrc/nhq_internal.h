@@ -1,0 +1,96 @@
+// Internal declarations shared by the libnhq translation units: the index
+// object, error plumbing and the device helpers every kernel uses.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <string>
+
+#include "nhq.h"
+
+// ------------------------------------------------------------------ errors
+namespace nhq {
+
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+#define NHQ_HIP(call)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return ::nhq::fail(NHQ_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// --------------------------------------------------------------- packing
+// Pool / candidate id word: vertex id in the low 28 bits, chi (0..4) in bits
+// 28..30, the "expanded" flag in bit 31.  Order comparisons use the id bits.
+constexpr uint32_t kIdMask = 0x0FFFFFFFu;
+constexpr uint32_t kExpBit = 0x80000000u;
+constexpr int kChiShift = 28;
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+constexpr int64_t kMaxN = int64_t(1) << 28;
+
+// Padded widths the kernels are instantiated for (the stored rows are padded
+// with zeros to the next one; zeros change no distance).
+int padded_dim(int d);
+
+struct Index {
+    int device = 0;
+    int64_t n = 0;
+    int d = 0, dp = 0, m = 0;
+    int degree = 0;  // 0 until a graph exists
+    int storage = NHQ_STORAGE_FP32;
+    int cand = 64;
+    int reverse_edges = 0;
+    int n_entry = 0;
+    uint64_t seed = 0;
+    float *vec32 = nullptr;     // [n][dp] float32 copy (rerank / fp32 storage)
+    void *vecs = nullptr;       // storage form [n][dp] (== vec32 for fp32)
+    float *scale = nullptr;     // fp8: per-row scale [n]
+    uint32_t *attr = nullptr;   // [n] packed codes, byte i = attribute i
+    float *norm = nullptr;      // [n] squared norms of the float32 rows
+    int32_t *adj = nullptr;     // [n][degree]
+    int32_t *entry = nullptr;   // [n_entry]
+    uint32_t *err = nullptr;    // device error word
+    // per-index workspace (grown on demand)
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    std::mutex mu;
+    // learned stop network (fp16 weights, device), null when not loaded
+    void *mlp = nullptr;
+};
+
+int ensure_workspace(Index *ix, size_t bytes);
+
+// splitmix64 (Steele, Lea and Flood, 2014)
+inline uint64_t splitmix64_next(uint64_t &state)
+{
+    state += 0x9E3779B97F4A7C15ull;
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// ------------------------------------------------------------ launchers
+struct SearchLaunch {
+    const Index *ix;
+    const float *q;
+    const uint8_t *qa;
+    int64_t nq;
+    int k, L, n_init, out_mode, rerank_n, max_hops, hash_log2, learned, check_every;
+    float stop_threshold;
+    int32_t *ids;
+    float *dists;
+    uint32_t *counters;
+    hipStream_t stream;
+};
+int launch_search(const SearchLaunch &s);
+
+}  // namespace nhq
+
+struct nhq_index {
+    nhq::Index impl;
+};

@@ -1,0 +1,603 @@
+// Joint pruning (Alg. 2) in beam form on gfx950: one wavefront per query.
+//
+// Per wave, in LDS: the pool (the `beam` best vertices by fusion distance,
+// sorted by (key, id), each with its chi and an "expanded" flag), a staging
+// list for the current batch of candidates, and the visited set (a bitset
+// when the object set is small, else an open-addressing hash).  Per lane, in
+// registers: this lane's slice of the query vector.
+//
+// Scoring a candidate row uses G lanes (G = 8 for rows up to 512 elements,
+// 16 above): lane g of a group holds 4-element chunks g, g+G, g+2G, ... so a
+// group's loads for one row are contiguous 16-, 8- or 4-byte pieces (fp32,
+// bf16, fp8 storage) and 64/G rows are scored per round.  Partial sums are
+// reduced inside the group with xor-shuffles.
+//
+// Ordering key: Gamma = delta * (m_q + chi) / m_q is ordered through
+// key = delta^2 * (m_q + chi)^2 (delta^2 when m_q = 0), one float multiply of
+// the float32 delta^2.  Ties are broken by the smaller id.
+#include "nhq_internal.h"
+
+namespace nhq {
+namespace {
+
+struct SearchArgs {
+    const void *vecs;
+    const float *vec32;
+    const float *scale;
+    const uint32_t *attr;
+    const int32_t *adj;
+    const int32_t *entry;
+    const float *q;
+    const uint8_t *qa;
+    int32_t *out_ids;
+    float *out_dist;
+    uint32_t *counters;
+    uint32_t *err;
+    int64_t n;
+    int64_t nq;
+    int d, m, R, n_entry;
+    int k, L, n_init, out_mode, rerank_n, max_hops;
+    int scap;       // staging capacity (entries)
+    int vis_words;  // visited-set words
+    int use_bitset;
+    int hash_log2;
+};
+
+template <int DP>
+struct Shape {
+    static constexpr int G = DP <= 512 ? 8 : 16;           // lanes per row
+    static constexpr int NG = 64 / G;                      // rows per round
+    static constexpr int NCH = DP / (4 * G);               // 4-element chunks per lane
+    static constexpr int RB = NCH <= 4 ? 4 : (NCH <= 8 ? 2 : 1);  // rounds in flight
+    static_assert(DP % (4 * G) == 0, "padded width must split into lane chunks");
+};
+
+template <int ST>
+struct Chunk;
+template <>
+struct Chunk<NHQ_STORAGE_FP32> {
+    using T = float4;
+};
+template <>
+struct Chunk<NHQ_STORAGE_BF16> {
+    using T = uint2;
+};
+template <>
+struct Chunk<NHQ_STORAGE_FP8> {
+    using T = uint32_t;
+};
+
+__device__ __forceinline__ void wsync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ int rdl_i(int v, int i) { return __builtin_amdgcn_readlane(v, i); }
+__device__ __forceinline__ uint32_t rdl_u(uint32_t v, int i)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, i);
+}
+__device__ __forceinline__ float rdl_f(float v, int i)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
+}
+__device__ __forceinline__ int lanes_below(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// number of constrained attribute bytes that differ (Eq. 4-5)
+__device__ __forceinline__ int chi_of(uint32_t a, uint32_t qword, uint32_t qmask)
+{
+    uint32_t x = (a ^ qword) & qmask;
+    uint32_t y = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;
+    return __popc(y & 0x80808080u);
+}
+
+__device__ __forceinline__ float key_mult(int chi, int mq)
+{
+    return mq == 0 ? 1.0f : (float)((mq + chi) * (mq + chi));
+}
+
+__device__ __forceinline__ bool lt_key(float ka, uint32_t ia, float kb, uint32_t ib)
+{
+    return ka < kb || (ka == kb && ia < ib);
+}
+
+template <int ST>
+__device__ __forceinline__ float4 decode(typename Chunk<ST>::T c, float s);
+
+template <>
+__device__ __forceinline__ float4 decode<NHQ_STORAGE_FP32>(float4 c, float)
+{
+    return c;
+}
+template <>
+__device__ __forceinline__ float4 decode<NHQ_STORAGE_BF16>(uint2 c, float)
+{
+    return make_float4(__uint_as_float(c.x << 16), __uint_as_float(c.x & 0xFFFF0000u),
+                       __uint_as_float(c.y << 16), __uint_as_float(c.y & 0xFFFF0000u));
+}
+template <>
+__device__ __forceinline__ float4 decode<NHQ_STORAGE_FP8>(uint32_t c, float s)
+{
+    // OCP e4m3 (gfx950 hardware conversion), then the per-vector scale
+    auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)c, false);
+    auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)c, true);
+    return make_float4(lo[0] * s, lo[1] * s, hi[0] * s, hi[1] * s);
+}
+
+template <int G>
+__device__ __forceinline__ float group_sum(float v)
+{
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Score staged candidates sid[0..nf): for each, delta^2 of the query and the
+// row (storage ST), written to out[j] as the ordering key (want_key) or as
+// delta^2.
+template <int DP, int ST>
+__device__ __forceinline__ void score_batch(const void *vbase, const float *scale,
+                                            const float4 (&qv)[Shape<DP>::NCH],
+                                            const uint32_t *sid, float *out, int nf, int mq,
+                                            bool want_key)
+{
+    using S = Shape<DP>;
+    using T = typename Chunk<ST>::T;
+    const int lane = threadIdx.x;
+    const int g = lane % S::G, gi = lane / S::G;
+    const int rounds = (nf + S::NG - 1) / S::NG;
+    for (int r0 = 0; r0 < rounds; r0 += S::RB) {
+        T buf[S::RB][S::NCH];
+        float sc[S::RB];
+        uint32_t w[S::RB];
+#pragma unroll
+        for (int rr = 0; rr < S::RB; ++rr) {
+            const int j = (r0 + rr) * S::NG + gi;
+            w[rr] = 0;
+            sc[rr] = 1.0f;
+            if (j < nf) {
+                w[rr] = sid[j];
+                const int64_t id = w[rr] & kIdMask;
+                const T *row = reinterpret_cast<const T *>(vbase) + id * (DP / 4);
+#pragma unroll
+                for (int c = 0; c < S::NCH; ++c)
+                    buf[rr][c] = row[g + S::G * c];
+                if (ST == NHQ_STORAGE_FP8)
+                    sc[rr] = scale[id];
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < S::RB; ++rr) {
+            const int j = (r0 + rr) * S::NG + gi;
+            float a0 = 0.0f, a1 = 0.0f;
+            if (j < nf) {
+#pragma unroll
+                for (int c = 0; c < S::NCH; ++c) {
+                    const float4 x = decode<ST>(buf[rr][c], sc[rr]);
+                    const float t0 = qv[c].x - x.x, t1 = qv[c].y - x.y;
+                    const float t2 = qv[c].z - x.z, t3 = qv[c].w - x.w;
+                    a0 = fmaf(t0, t0, a0);
+                    a1 = fmaf(t1, t1, a1);
+                    a0 = fmaf(t2, t2, a0);
+                    a1 = fmaf(t3, t3, a1);
+                }
+            }
+            float d2 = group_sum<S::G>(a0 + a1);
+            if (j < nf && g == 0) {
+                const int c = (int)((w[rr] >> kChiShift) & 7u);
+                out[j] = want_key ? d2 * key_mult(c, mq) : d2;
+            }
+        }
+    }
+}
+
+// Merge one batch of candidates (lane j holds candidate j when `valid`) into
+// the sorted pool of capacity `cap`: the pool becomes the cap best of
+// pool + batch by (key, id).  Candidates already pooled are dropped.  `lo`
+// (first position that may hold an unexpanded entry) is lowered to the
+// first insertion point.  Returns the new size.
+__device__ int pool_merge(float *pkey, uint32_t *pid, int size, int cap, float ck, uint32_t cw,
+                          bool valid, int &lo)
+{
+    const int lane = threadIdx.x;
+    const uint32_t cm = cw & kIdMask;
+    if (valid && size >= cap) {
+        const float wk = pkey[cap - 1];
+        const uint32_t wm = pid[cap - 1] & kIdMask;
+        valid = lt_key(ck, cm, wk, wm);
+    }
+    int p = 0;
+    if (valid) {
+        int a0 = 0, a1 = size;
+        while (a0 < a1) {
+            const int mid = (a0 + a1) >> 1;
+            if (lt_key(pkey[mid], pid[mid] & kIdMask, ck, cm))
+                a0 = mid + 1;
+            else
+                a1 = mid;
+        }
+        p = a0;
+        if (p < size && pkey[p] == ck && (pid[p] & kIdMask) == cm)
+            valid = false;
+    }
+    const uint64_t bal = __ballot(valid);
+    if (bal == 0)
+        return size;
+    int rank = 0, pmin = size;
+    for (uint64_t b = bal; b; b &= b - 1) {
+        const int i = __ffsll((unsigned long long)b) - 1;
+        const float ki = rdl_f(ck, i);
+        const uint32_t mi = rdl_u(cm, i);
+        const int pi = rdl_i(p, i);
+        rank += lt_key(ki, mi, ck, cm) ? 1 : 0;
+        pmin = min(pmin, pi);
+    }
+    const int nv = __popcll(bal);
+    const int nsize = min(cap, size + nv);
+    if (pmin < size) {
+        for (int base = pmin + ((size - 1 - pmin) & ~63); base >= pmin; base -= 64) {
+            const int e = base + lane;
+            const bool act = e < size;
+            float ek = 0.0f;
+            uint32_t ew = 0;
+            if (act) {
+                ek = pkey[e];
+                ew = pid[e];
+            }
+            int sh = 0;
+            for (uint64_t b = bal; b; b &= b - 1) {
+                const int i = __ffsll((unsigned long long)b) - 1;
+                sh += (rdl_i(p, i) <= e) ? 1 : 0;
+            }
+            wsync();
+            if (act && e + sh < cap) {
+                pkey[e + sh] = ek;
+                pid[e + sh] = ew;
+            }
+            wsync();
+        }
+    }
+    if (valid && p + rank < cap) {
+        pkey[p + rank] = ck;
+        pid[p + rank] = cw;
+    }
+    wsync();
+    lo = min(lo, pmin);
+    return nsize;
+}
+
+// visited test-and-set; returns true when v was not yet visited.  `unrec`
+// reports a fresh vertex the hash could not record (table region full).
+__device__ __forceinline__ bool visit(uint32_t *vis, bool bitset, int hash_log2, uint32_t v,
+                                      bool &unrec)
+{
+    unrec = false;
+    if (bitset) {
+        const uint32_t bit = 1u << (v & 31u);
+        const uint32_t old = atomicOr(&vis[v >> 5], bit);
+        return (old & bit) == 0;
+    }
+    const uint32_t slots_mask = (1u << hash_log2) - 1u;
+    uint32_t h = (v * 0x9E3779B1u) >> (32 - hash_log2);
+#pragma unroll 1
+    for (int probe = 0; probe < 16; ++probe) {
+        const uint32_t s = (h + (uint32_t)probe) & slots_mask;
+        const uint32_t old = atomicCAS(&vis[s], kEmpty, v);
+        if (old == kEmpty)
+            return true;
+        if (old == v)
+            return false;
+    }
+    unrec = true;
+    return true;
+}
+
+template <int DP, int ST>
+__global__ __launch_bounds__(64) void k_search(const SearchArgs a)
+{
+    using S = Shape<DP>;
+    extern __shared__ __align__(16) uint32_t smem[];
+    const int lane = threadIdx.x;
+    const int64_t qi = blockIdx.x;
+    if (qi >= a.nq)
+        return;
+    const int L = a.L;
+    float *pkey = reinterpret_cast<float *>(smem);
+    uint32_t *pid = smem + L;
+    float *skey = reinterpret_cast<float *>(smem + 2 * L);
+    uint32_t *sid = smem + 2 * L + a.scap;
+    uint32_t *vis = smem + 2 * L + 2 * a.scap;
+    const bool bitset = a.use_bitset != 0;
+    const int g = lane % S::G;
+
+    // query slice in registers, query attributes packed like the objects'
+    float4 qv[S::NCH];
+    const float *qp = a.q + qi * (int64_t)a.d;
+#pragma unroll
+    for (int c = 0; c < S::NCH; ++c) {
+        const int e = 4 * (g + S::G * c);
+        qv[c].x = e + 0 < a.d ? qp[e + 0] : 0.0f;
+        qv[c].y = e + 1 < a.d ? qp[e + 1] : 0.0f;
+        qv[c].z = e + 2 < a.d ? qp[e + 2] : 0.0f;
+        qv[c].w = e + 3 < a.d ? qp[e + 3] : 0.0f;
+    }
+    uint32_t qword = 0, qmask = 0;
+    int mq = 0;
+    for (int i = 0; i < a.m; ++i) {
+        const uint32_t c = a.qa[qi * a.m + i];
+        if (c != 0xFFu) {
+            qword |= c << (8 * i);
+            qmask |= 0xFFu << (8 * i);
+            mq += 1;
+        }
+    }
+    for (int i = lane; i < a.vis_words; i += 64)
+        vis[i] = bitset ? 0u : kEmpty;
+    wsync();
+
+    // ---- seed set: the n_init best members of the entry sample
+    int size = 0, lo = 0;
+    const int cap0 = min(a.n_init, L);
+    for (int e0 = 0; e0 < a.n_entry; e0 += 64) {
+        const int ne = min(64, a.n_entry - e0);
+        uint32_t cw = 0;
+        if (lane < ne) {
+            const uint32_t id = (uint32_t)a.entry[e0 + lane];
+            cw = id | ((uint32_t)chi_of(a.attr[id], qword, qmask) << kChiShift);
+            sid[lane] = cw;
+        }
+        wsync();
+        score_batch<DP, ST>(a.vecs, a.scale, qv, sid, skey, ne, mq, true);
+        wsync();
+        const float ck = lane < ne ? skey[lane] : 0.0f;
+        size = pool_merge(pkey, pid, size, cap0, ck, cw, lane < ne, lo);
+    }
+    for (int e = lane; e < size; e += 64) {
+        bool unrec;
+        visit(vis, bitset, a.hash_log2, pid[e] & kIdMask, unrec);
+    }
+    wsync();
+    lo = 0;
+
+    // ---- expansion loop
+    uint32_t ndc = 0, hops = 0;
+    bool capped = false, badid = false;
+    for (;;) {
+        int cur = -1;
+        for (int base = lo; base < size; base += 64) {
+            const int e = base + lane;
+            const bool un = e < size && (pid[e] & kExpBit) == 0;
+            const uint64_t bb = __ballot(un);
+            if (bb) {
+                cur = base + __ffsll((unsigned long long)bb) - 1;
+                break;
+            }
+        }
+        if (cur < 0)
+            break;
+        if ((int)hops >= a.max_hops) {
+            capped = true;
+            break;
+        }
+        hops += 1;
+        const uint32_t uw = pid[cur];
+        wsync();
+        if (lane == 0)
+            pid[cur] = uw | kExpBit;
+        lo = cur + 1;
+        const int64_t u = uw & kIdMask;
+        int nb = -1;
+        if (lane < a.R)
+            nb = a.adj[u * a.R + lane];
+        if (nb >= a.n || nb < -1) {
+            badid = true;
+            nb = -1;
+        }
+        bool fresh = false, unrec = false;
+        if (nb >= 0)
+            fresh = visit(vis, bitset, a.hash_log2, (uint32_t)nb, unrec);
+        // a vertex the hash could not record may repeat inside this batch
+        uint64_t ub = __ballot(unrec);
+        while (ub) {
+            const int i = __ffsll((unsigned long long)ub) - 1;
+            ub &= ub - 1;
+            if (unrec && lane > i && nb == rdl_i(nb, i))
+                fresh = false;
+        }
+        const uint64_t fb = __ballot(fresh);
+        const int nf = __popcll(fb);
+        if (nf == 0)
+            continue;
+        if (fresh) {
+            const int c = chi_of(a.attr[nb], qword, qmask);
+            sid[lanes_below(fb)] = (uint32_t)nb | ((uint32_t)c << kChiShift);
+        }
+        wsync();
+        ndc += nf;
+        score_batch<DP, ST>(a.vecs, a.scale, qv, sid, skey, nf, mq, true);
+        wsync();
+        const float ck = lane < nf ? skey[lane] : 0.0f;
+        const uint32_t cw = lane < nf ? sid[lane] : 0u;
+        size = pool_merge(pkey, pid, size, L, ck, cw, lane < nf, lo);
+    }
+
+    // ---- output: eligible entries in pool order (Def. 4 filter or raw)
+    const int want = a.rerank_n > 0 ? a.rerank_n : a.k;
+    int got = 0;
+    for (int base = 0; base < size && got < want; base += 64) {
+        const int e = base + lane;
+        const uint32_t w = e < size ? pid[e] : 0u;
+        const bool el = e < size && (a.out_mode == 1 || ((w >> kChiShift) & 7u) == 0);
+        const uint64_t bb = __ballot(el);
+        const int pos = got + lanes_below(bb);
+        if (el && pos < want)
+            sid[pos] = w & ~kExpBit;
+        got += __popcll(bb);
+    }
+    got = min(got, want);
+    wsync();
+    // delta^2 from the float32 copy (identical to the loop's for fp32 storage)
+    score_batch<DP, NHQ_STORAGE_FP32>(a.vec32, nullptr, qv, sid, skey, got, mq, false);
+    wsync();
+    // final order into LDS (the pool is no longer needed), then one store
+    // per output slot
+    for (int j0 = 0; j0 < got; j0 += 64) {
+        const int j = j0 + lane;
+        if (j < got) {
+            const uint32_t w = sid[j];
+            const int c = (int)((w >> kChiShift) & 7u);
+            const float d2 = skey[j];
+            int slot = j;
+            if (a.rerank_n > 0) {
+                // rank by exact (key, id) among the re-scored entries
+                const float kj = d2 * key_mult(c, mq);
+                const uint32_t ij = w & kIdMask;
+                slot = 0;
+                for (int i = 0; i < got; ++i) {
+                    const uint32_t wi = sid[i];
+                    const float ki = skey[i] * key_mult((int)((wi >> kChiShift) & 7u), mq);
+                    slot += lt_key(ki, wi & kIdMask, kj, ij) ? 1 : 0;
+                }
+            }
+            if (slot < a.k) {
+                const float dl = sqrtf(d2);
+                pid[slot] = w & kIdMask;
+                pkey[slot] = mq == 0 ? dl : dl * ((float)(mq + c) / (float)mq);
+            }
+        }
+    }
+    wsync();
+    const int nout = min(got, a.k);
+    int32_t *oid = a.out_ids + qi * a.k;
+    float *od = a.out_dist + qi * a.k;
+    for (int j0 = 0; j0 < a.k; j0 += 64) {
+        const int j = j0 + lane;
+        if (j < a.k) {
+            oid[j] = j < nout ? (int32_t)pid[j] : -1;
+            od[j] = j < nout ? pkey[j] : __int_as_float(0x7F800000);
+        }
+    }
+    if (lane == 0) {
+        if (a.counters) {
+            a.counters[2 * qi + 0] = ndc;
+            a.counters[2 * qi + 1] = hops;
+        }
+        if (capped)
+            atomicOr(a.err, NHQ_DEVERR_HOPCAP);
+    }
+    if (badid && a.err)
+        atomicOr(a.err, NHQ_DEVERR_BADID);
+}
+
+template <int DP, int ST>
+int launch_one(const SearchArgs &a, size_t lds, hipStream_t st)
+{
+    auto kern = k_search<DP, ST>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess)
+            return fail(NHQ_EHIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)a.nq), dim3(64), lds, st, a);
+    NHQ_HIP(hipGetLastError());
+    return NHQ_OK;
+}
+
+template <int DP>
+int launch_dp(const SearchArgs &a, int storage, size_t lds, hipStream_t st)
+{
+    switch (storage) {
+    case NHQ_STORAGE_FP32:
+        return launch_one<DP, NHQ_STORAGE_FP32>(a, lds, st);
+    case NHQ_STORAGE_BF16:
+        return launch_one<DP, NHQ_STORAGE_BF16>(a, lds, st);
+    case NHQ_STORAGE_FP8:
+        return launch_one<DP, NHQ_STORAGE_FP8>(a, lds, st);
+    }
+    return fail(NHQ_EINVAL, "unknown storage form");
+}
+
+}  // namespace
+
+int launch_search(const SearchLaunch &s)
+{
+    const Index *ix = s.ix;
+    SearchArgs a{};
+    a.vecs = ix->vecs;
+    a.vec32 = ix->vec32;
+    a.scale = ix->scale;
+    a.attr = ix->attr;
+    a.adj = ix->adj;
+    a.entry = ix->entry;
+    a.q = s.q;
+    a.qa = s.qa;
+    a.out_ids = s.ids;
+    a.out_dist = s.dists;
+    a.counters = s.counters;
+    a.err = ix->err;
+    a.n = ix->n;
+    a.nq = s.nq;
+    a.d = ix->d;
+    a.m = ix->m;
+    a.R = ix->degree;
+    a.n_entry = ix->n_entry;
+    a.k = s.k;
+    a.L = s.L;
+    a.n_init = s.n_init;
+    a.out_mode = s.out_mode;
+    a.rerank_n = s.rerank_n;
+    a.max_hops = s.max_hops;
+    const int want = s.rerank_n > 0 ? s.rerank_n : s.k;
+    a.scap = want > 64 ? ((want + 63) & ~63) : 64;
+    // visited set: bitset when it is no larger than the hash would be
+    int hb = s.hash_log2;
+    if (hb <= 0) {
+        int slots = 1024;
+        while (slots < 8 * s.L && slots < 4096)
+            slots <<= 1;
+        hb = 0;
+        while ((1 << hb) < slots)
+            ++hb;
+    }
+    const int64_t bit_words = (ix->n + 31) / 32;
+    if (bit_words <= (int64_t(1) << hb)) {
+        a.use_bitset = 1;
+        a.vis_words = (int)bit_words;
+        a.hash_log2 = 0;
+    } else {
+        a.use_bitset = 0;
+        a.vis_words = 1 << hb;
+        a.hash_log2 = hb;
+    }
+    const size_t lds = sizeof(uint32_t) * ((size_t)2 * a.L + (size_t)2 * a.scap + (size_t)a.vis_words);
+    if (s.nq > 0x7FFFFFFF)
+        return fail(NHQ_EINVAL, "too many queries in one call");
+    switch (ix->dp) {
+    case 32:
+        return launch_dp<32>(a, ix->storage, lds, s.stream);
+    case 64:
+        return launch_dp<64>(a, ix->storage, lds, s.stream);
+    case 96:
+        return launch_dp<96>(a, ix->storage, lds, s.stream);
+    case 128:
+        return launch_dp<128>(a, ix->storage, lds, s.stream);
+    case 256:
+        return launch_dp<256>(a, ix->storage, lds, s.stream);
+    case 512:
+        return launch_dp<512>(a, ix->storage, lds, s.stream);
+    case 960:
+        return launch_dp<960>(a, ix->storage, lds, s.stream);
+    case 1024:
+        return launch_dp<1024>(a, ix->storage, lds, s.stream);
+    }
+    return fail(NHQ_EINVAL, "unsupported padded dimension");
+}
+
+}  // namespace nhq

@@ -1,0 +1,200 @@
+"""GPU parity of the joint-pruning search (Alg. 2, beam form) against the CPU
+oracle, through the C ABI.
+
+Graphs come from the oracle's build or from the seeded random-graph
+generator, never from the GPU.  On integer-valued vectors every distance is
+exact in float32, so the kernel must agree with the oracle in its float32
+key mode id for id, and (with an exact visited set) NDC for NDC and hop for
+hop.  On float vectors the orders can differ only at near-ties: the result
+sets must overlap and every returned distance must equal the FP64 distance
+of the returned object to 1e-4 relative."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+nhq = pytest.importorskip("paper_2203_13601_amd")
+
+GAMMA_RTOL = 1e-4
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _index(w, adj, storage="fp32", n_entry=256, seed=None):
+    ix = nhq.nhq_index_create(_dev(w.x), _dev(w.attrs), storage=storage, n_entry=n_entry,
+                              seed=w.build_seed if seed is None else seed, degree=adj.shape[1])
+    nhq.nhq_index_set_graph(ix, _dev(adj))
+    return ix
+
+
+def _gpu(ix, w, k, L, **kw):
+    ids, d, cnt = nhq.nhq_hybrid_search(ix, _dev(w.q), _dev(w.qattrs), k, L, counters=True, **kw)
+    torch.cuda.synchronize()
+    return ids.cpu().numpy(), d.cpu().numpy(), cnt.cpu().numpy()
+
+
+def _check_gamma(w, ids, dist, mode=0):
+    """every returned distance is Gamma of the returned object, FP64 oracle"""
+    for i in range(ids.shape[0]):
+        mq = oracle.arity(w.qattrs[i])
+        for v, g in zip(ids[i], dist[i]):
+            if v < 0:
+                assert np.isinf(g)
+                continue
+            c = oracle.chi(w.qattrs[i], w.attrs[v])
+            if mode == 0:
+                assert c == 0
+            want = oracle.gamma(oracle.delta(w.q[i], w.x[v]), c, mq)
+            assert abs(g - want) <= GAMMA_RTOL * max(want, 1e-30), (i, v, g, want)
+
+
+@pytest.fixture(scope="module")
+def int_set():
+    w = synth.small(8000, 128, 96, seed=51, integer=True, n_centres=8)
+    adj = oracle.build_graph(w.x, w.attrs, l=48, R=32)
+    return w, adj
+
+
+@pytest.fixture(scope="module")
+def float_set():
+    w = synth.config1(n=6000, nq=96)
+    adj = oracle.build_graph(w.x, w.attrs, l=48, R=32)
+    return w, adj
+
+
+def test_entry_sample_matches_oracle(int_set):
+    w, adj = int_set
+    for ne, seed in ((256, 5), (1, 0), (8000, 77), (9000, 3)):
+        ix = _index(w, adj, n_entry=ne, seed=seed)
+        got = nhq.nhq_index_get_entry(ix).cpu().numpy()
+        assert np.array_equal(got, oracle.entry_points(seed, w.n, ne))
+        ix.free()
+
+
+@pytest.mark.parametrize("k,L,n_init", [(10, 64, 32), (1, 16, 8), (10, 100, 32), (32, 32, 32),
+                                        (10, 256, 64), (5, 513, 1)])
+def test_integer_data_id_ndc_hop_exact(int_set, k, L, n_init):
+    w, adj = int_set
+    ix = _index(w, adj, n_entry=256)
+    entry = oracle.entry_points(w.build_seed, w.n, 256)
+    ids, dist, cnt = _gpu(ix, w, k, L, n_init=n_init)
+    oi, og, ondc, ohops, _ = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, k, L, entry,
+                                           n_init=n_init, key_mode=oracle.KEY32)
+    assert np.array_equal(ids, oi)
+    assert np.array_equal(cnt[:, 0], ondc)
+    assert np.array_equal(cnt[:, 1], ohops)
+    fin = np.isfinite(og)
+    assert np.array_equal(np.isfinite(dist), fin)
+    assert np.allclose(dist[fin], og[fin], rtol=GAMMA_RTOL)
+    assert nhq.nhq_index_device_error(ix) == 0
+
+
+def test_hash_visited_set_same_answers(int_set):
+    # n = 40000 with a 1024-slot hash: the visited set is the LDS hash; the
+    # answers and (while the hash records everything) NDC equal the oracle's
+    w0, _ = int_set
+    w = synth.small(40000, 32, 64, seed=52, integer=True, n_centres=4)
+    adj = synth.random_graph(w.n, 16, seed=9, pad_frac=0.25)
+    ix = _index(w, adj, n_entry=128)
+    entry = oracle.entry_points(w.build_seed, w.n, 128)
+    for L, hb in ((48, 10), (200, 10), (200, 12)):
+        ids, dist, cnt = _gpu(ix, w, 10, L, visited_log2=hb)
+        oi, og, ondc, ohops, _ = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, L, entry,
+                                               key_mode=oracle.KEY32)
+        assert np.array_equal(ids, oi)
+        # a lossy hash only adds re-evaluations; it never changes the pool
+        assert (cnt[:, 0] >= ondc).all()
+        assert np.array_equal(cnt[:, 1], ohops)
+        if hb == 12:
+            assert np.array_equal(cnt[:, 0], ondc)
+
+
+def test_float_data_matches_fp64_oracle(float_set):
+    w, adj = float_set
+    ix = _index(w, adj, n_entry=512)
+    entry = oracle.entry_points(w.build_seed, w.n, 512)
+    for L in (32, 64, 160):
+        ids, dist, cnt = _gpu(ix, w, 10, L)
+        oi, og, ondc, _, _ = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, L, entry)
+        overlap = np.mean([len(set(a[a >= 0]) & set(b[b >= 0])) / max(1, (b >= 0).sum())
+                           for a, b in zip(ids, oi)])
+        assert overlap >= 0.99, overlap
+        _check_gamma(w, ids, dist)
+        assert abs(cnt[:, 0].mean() - ondc.mean()) <= 0.02 * ondc.mean()
+
+
+def test_wildcards_raw_mode_rerank_and_padding():
+    # d = 37 (padded), partial constraints, -1 padded rows, degree 20
+    w = synth.small(3000, 37, 64, seed=53, integer=True, wildcard_arity=True)
+    adj = synth.random_graph(w.n, 20, seed=10, pad_frac=0.4)
+    ix = _index(w, adj, n_entry=64)
+    entry = oracle.entry_points(w.build_seed, w.n, 64)
+    for mode in (0, 1):
+        ids, dist, _ = _gpu(ix, w, 12, 60, output_mode=mode)
+        oi, og, _, _, _ = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 12, 60, entry,
+                                        key_mode=oracle.KEY32, out_mode=mode)
+        assert np.array_equal(ids, oi)
+        _check_gamma(w, ids, dist, mode)
+    # re-score of the first 4k from the float32 copy (identical vectors here)
+    ids, dist, _ = _gpu(ix, w, 10, 64, rerank=4)
+    oi, og, _, _, _ = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, 64, entry,
+                                    key_mode=oracle.KEY32, rerank_n=40, xr=w.x)
+    assert np.array_equal(ids, oi)
+
+
+def test_no_attributes_is_plain_vector_search():
+    w = synth.small(2500, 64, 40, seed=54, integer=True)
+    attrs = np.zeros((w.n, 0), np.uint8)
+    qa = np.zeros((w.nq, 0), np.uint8)
+    adj = oracle.build_graph(w.x, np.zeros((w.n, 1), np.uint8), l=32, R=16)
+    ix = nhq.nhq_index_create(_dev(w.x), _dev(attrs), n_entry=64, seed=3, degree=16)
+    nhq.nhq_index_set_graph(ix, _dev(adj))
+    ids, dist = nhq.nhq_hybrid_search(ix, _dev(w.q), _dev(qa), 10, 64)
+    entry = oracle.entry_points(3, w.n, 64)
+    oi, og, _, _, _ = oracle.search(adj, w.x, np.zeros((w.n, 0), np.uint8), w.q, qa, 10, 64, entry,
+                                    key_mode=oracle.KEY32)
+    assert np.array_equal(ids.cpu().numpy(), oi)
+
+
+def test_degenerate_inputs(int_set):
+    w, adj = int_set
+    ix = _index(w, adj, n_entry=32)
+    # nq = 0 is a no-op
+    e = torch.empty((0, w.d), dtype=torch.float32, device="cuda")
+    ea = torch.empty((0, w.m), dtype=torch.uint8, device="cuda")
+    ids, dist = nhq.nhq_hybrid_search(ix, e, ea, 10, 32)
+    assert ids.shape == (0, 10)
+    # a constraint no object satisfies: all padding
+    qa = np.full((4, w.m), 0, np.uint8)
+    attrs = w.attrs.copy()
+    attrs[(attrs == 0).all(1)] = 1
+    ix2 = nhq.nhq_index_create(_dev(w.x), _dev(attrs), n_entry=32, seed=1, degree=adj.shape[1])
+    nhq.nhq_index_set_graph(ix2, _dev(adj))
+    ids, dist = nhq.nhq_hybrid_search(ix2, _dev(w.q[:4]), _dev(qa), 10, 64)
+    assert (ids.cpu().numpy() == -1).all() and torch.isinf(dist).all()
+    # hop cap raises the device error word
+    ids, dist = nhq.nhq_hybrid_search(ix, _dev(w.q), _dev(w.qattrs), 10, 64, max_hops=2)
+    torch.cuda.synchronize()
+    assert nhq.nhq_index_device_error(ix) & nhq.DEVERR_HOPCAP
+    assert nhq.nhq_index_device_error(ix) == 0
+
+
+def test_argument_errors(int_set):
+    w, adj = int_set
+    ix = _index(w, adj, n_entry=32)
+    q, qa = _dev(w.q[:2]), _dev(w.qattrs[:2])
+    for kw in (dict(k=11, beam=10), dict(k=1, beam=1025), dict(k=0, beam=8),
+               dict(k=10, beam=30, rerank=4), dict(k=10, beam=64, visited_log2=14)):
+        k = kw.pop("k")
+        beam = kw.pop("beam")
+        with pytest.raises(nhq.NHQError):
+            nhq.nhq_hybrid_search(ix, q, qa, k, beam, **kw)
+    with pytest.raises(nhq.NHQError):
+        bad = adj.copy()
+        nhq.nhq_index_create(_dev(w.x), _dev(np.full_like(w.attrs, 255)), n_entry=8)
