@@ -153,7 +153,9 @@ int nhq_hybrid_search(const nhq_index *ix, const float *queries, const uint8_t *
 
 /* Exact hybrid k-NN (Def. 4 with Def. 2): exact attribute filter, then the k
  * nearest matches by (delta, id).  Same argument layout as the search; k in
- * [1, 1024].  dists are delta (= Gamma for matches). */
+ * [1, 128].  dists are delta (= Gamma for matches), rounded to float32 from a
+ * float64 direct-form re-score of the dense tiles' k + 16 best.  Uses
+ * stream-ordered temporary allocations. */
 int nhq_bruteforce_hybrid_knn(const nhq_index *ix, const float *queries, const uint8_t *qattrs,
                               int64_t nq, int32_t k, int32_t *ids, float *dists, void *stream);
 

@@ -1,6 +1,56 @@
-// Composite-index build on the GPU and exact hybrid k-NN (placeholders until
-// the dense kernels land).
+// Composite-index build on the GPU (Alg. 1 in degree-bounded form, Sec. 4.1
+// edge selection, fusion distance in the build per Sec. 5.1) and exact hybrid
+// k-NN (Def. 4): orchestration of the dense top-K tiles, the exact re-score,
+// the landing-zone selection and the reverse pass.
+#include <algorithm>
+
 #include "nhq_internal.h"
+
+namespace nhq {
+
+int launch_dense_topk(const float *A, const float *A_norm, const uint32_t *A_attr,
+                      const uint32_t *A_mask, int64_t na, const Index *ix, int mode, int K,
+                      int32_t *out_ids, float *out_keys, hipStream_t st);
+int launch_select(const Index *ix, const int32_t *cand, int K, int l, int32_t *adj, hipStream_t st);
+int launch_reverse(const Index *ix, const int32_t *fwd, int32_t *adj, hipStream_t st);
+int launch_refine(const Index *ix, const float *qpad, const int32_t *cand, int64_t nq, int K, int k,
+                  int32_t *ids, float *dists, hipStream_t st);
+
+// extra candidates the dense tiles keep beyond l (they rank by a GEMM-form
+// key; the exact re-score then keeps the l best)
+constexpr int kMargin = 16;
+
+namespace {
+
+__global__ void k_pad_queries(const float *__restrict__ q, const uint8_t *__restrict__ qa,
+                              int64_t nq, int d, int dp, int m, float *__restrict__ qpad,
+                              float *__restrict__ qnorm, uint32_t *__restrict__ qword,
+                              uint32_t *__restrict__ qmask)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nq;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        for (int c = 0; c < dp; ++c) {
+            const float v = c < d ? q[i * d + c] : 0.0f;
+            qpad[i * dp + c] = v;
+            s = fmaf(v, v, s);
+        }
+        qnorm[i] = s;
+        uint32_t w = 0, mk = 0;
+        for (int j = 0; j < m; ++j) {
+            const uint32_t c = qa[i * m + j];
+            if (c != 0xFFu) {
+                w |= c << (8 * j);
+                mk |= 0xFFu << (8 * j);
+            }
+        }
+        qword[i] = w;
+        qmask[i] = mk;
+    }
+}
+
+}  // namespace
+}  // namespace nhq
 
 using namespace nhq;
 
@@ -8,9 +58,34 @@ extern "C" {
 
 int nhq_index_build_graph(nhq_index *h, void *stream)
 {
-    (void)h;
-    (void)stream;
-    return fail(NHQ_ENOTSUP, "GPU graph build not available in this build");
+    if (!h)
+        return fail(NHQ_EINVAL, "null index");
+    Index *ix = &h->impl;
+    hipStream_t st = (hipStream_t)stream;
+    if (ix->n < 2)
+        return fail(NHQ_EINVAL, "a graph needs at least two objects");
+    const int l = (int)std::min<int64_t>(ix->cand, ix->n - 1);
+    const int K = (int)std::min<int64_t>(std::min(l + kMargin, 160), ix->n - 1);
+    int32_t *cand = nullptr, *fwd = nullptr;
+    NHQ_HIP(hipMallocAsync((void **)&cand, sizeof(int32_t) * (size_t)ix->n * K, st));
+    int rc = launch_dense_topk(ix->vec32, ix->norm, ix->attr, nullptr, ix->n, ix, 0, K, cand,
+                               nullptr, st);
+    if (rc == NHQ_OK) {
+        if (ix->reverse_edges) {
+            if (hipMallocAsync((void **)&fwd, sizeof(int32_t) * (size_t)ix->n * ix->degree, st) != hipSuccess)
+                rc = fail(NHQ_ENOMEM, "forward graph allocation failed");
+            if (rc == NHQ_OK)
+                rc = launch_select(ix, cand, K, l, fwd, st);
+            if (rc == NHQ_OK)
+                rc = launch_reverse(ix, fwd, ix->adj, st);
+        } else {
+            rc = launch_select(ix, cand, K, l, ix->adj, st);
+        }
+    }
+    (void)hipFreeAsync(cand, st);
+    if (fwd)
+        (void)hipFreeAsync(fwd, st);
+    return rc;
 }
 
 int nhq_build_index(const float *vecs, const uint8_t *attrs, int64_t n, int32_t d, int32_t m,
@@ -30,8 +105,35 @@ int nhq_build_index(const float *vecs, const uint8_t *attrs, int64_t n, int32_t 
 int nhq_bruteforce_hybrid_knn(const nhq_index *h, const float *queries, const uint8_t *qattrs,
                               int64_t nq, int32_t k, int32_t *ids, float *dists, void *stream)
 {
-    (void)h; (void)queries; (void)qattrs; (void)nq; (void)k; (void)ids; (void)dists; (void)stream;
-    return fail(NHQ_ENOTSUP, "exact k-NN not available in this build");
+    if (!h)
+        return fail(NHQ_EINVAL, "null index");
+    const Index *ix = &h->impl;
+    if (nq < 0 || k < 1 || k > 128)
+        return fail(NHQ_EINVAL, "need nq >= 0 and 1 <= k <= 128");
+    if (nq == 0)
+        return NHQ_OK;
+    if (!queries || !ids || !dists || (ix->m > 0 && !qattrs))
+        return fail(NHQ_EINVAL, "null array argument");
+    hipStream_t st = (hipStream_t)stream;
+    const int K = (int)std::min<int64_t>(k + kMargin, std::max<int64_t>(1, ix->n));
+    float *qpad = nullptr, *qnorm = nullptr;
+    uint32_t *qw = nullptr, *qm = nullptr;
+    int32_t *cand = nullptr;
+    NHQ_HIP(hipMallocAsync((void **)&qpad, sizeof(float) * (size_t)nq * ix->dp, st));
+    NHQ_HIP(hipMallocAsync((void **)&qnorm, sizeof(float) * (size_t)nq, st));
+    NHQ_HIP(hipMallocAsync((void **)&qw, sizeof(uint32_t) * (size_t)nq, st));
+    NHQ_HIP(hipMallocAsync((void **)&qm, sizeof(uint32_t) * (size_t)nq, st));
+    NHQ_HIP(hipMallocAsync((void **)&cand, sizeof(int32_t) * (size_t)nq * K, st));
+    const int grid = (int)std::min<int64_t>(65536, (nq + 255) / 256);
+    hipLaunchKernelGGL(k_pad_queries, dim3(grid), dim3(256), 0, st, queries, qattrs, nq, ix->d,
+                       ix->dp, ix->m, qpad, qnorm, qw, qm);
+    int rc = launch_dense_topk(qpad, qnorm, qw, qm, nq, ix, 1, K, cand, nullptr, st);
+    if (rc == NHQ_OK)
+        rc = launch_refine(ix, qpad, cand, nq, K, k, ids, dists, st);
+    void *bufs[] = {qpad, qnorm, qw, qm, cand};
+    for (void *b : bufs)
+        (void)hipFreeAsync(b, st);
+    return rc;
 }
 
 }  // extern "C"
