@@ -151,6 +151,27 @@ int nhq_hybrid_search(const nhq_index *ix, const float *queries, const uint8_t *
                       int64_t nq, int32_t k, int32_t beam, const nhq_search_params *sp,
                       int32_t *ids, float *dists, void *stream);
 
+/* The two stages of nhq_hybrid_search, for callers that time or overlap them.
+ *
+ * nhq_seed_rank: the seed set B of Alg. 2 is taken from the index's random
+ * entry sample (Sec. 3.2: seeds are usually drawn at random); this ranks the
+ * whole sample for every query by Gamma on the matrix cores and writes the
+ * positions (in the entry sample) of the n_cand best, -1 padded, to cand:
+ * device int32 [nq][n_cand], 1 <= n_cand <= 144.  Uses stream-ordered
+ * temporary allocations.
+ *
+ * nhq_search_seeded: the joint-pruning search given those candidates: it
+ * re-scores them exactly, starts the pool with the best n_init of them and
+ * runs the expansion loop.  nhq_hybrid_search passes n_cand = min(n_entry,
+ * n_init + 16); the result then equals a search started from the best n_init
+ * members of the whole entry sample unless the dense ranking (float32 GEMM
+ * form of delta^2) misplaces one past the 16-entry margin. */
+int nhq_seed_rank(const nhq_index *ix, const float *queries, const uint8_t *qattrs, int64_t nq,
+                  int32_t n_cand, int32_t *cand, void *stream);
+int nhq_search_seeded(const nhq_index *ix, const float *queries, const uint8_t *qattrs, int64_t nq,
+                      const int32_t *cand, int32_t n_cand, int32_t k, int32_t beam,
+                      const nhq_search_params *sp, int32_t *ids, float *dists, void *stream);
+
 /* Exact hybrid k-NN (Def. 4 with Def. 2): exact attribute filter, then the k
  * nearest matches by (delta, id).  Same argument layout as the search; k in
  * [1, 128].  dists are delta (= Gamma for matches), rounded to float32 from a

@@ -68,6 +68,8 @@ def lib() -> ctypes.CDLL:
         "nhq_index_free": ([P], None),
         "nhq_hybrid_search": ([P, P, P, i64, i32, i32, P, P, P, P], i32),
         "nhq_bruteforce_hybrid_knn": ([P, P, P, i64, i32, P, P, P], i32),
+        "nhq_seed_rank": ([P, P, P, i64, i32, P, P], i32),
+        "nhq_search_seeded": ([P, P, P, i64, P, i32, i32, i32, P, P, P, P], i32),
         "nhq_strerror": ([i32], ctypes.c_char_p),
         "nhq_last_error": ([], ctypes.c_char_p),
         "nhq_version": ([], i32),
@@ -226,6 +228,42 @@ def nhq_hybrid_search(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, k:
     _check(lib().nhq_hybrid_search(ix.handle, queries.data_ptr(), qattrs.data_ptr(), nq, int(k),
                                    int(beam), ctypes.byref(sp), ids.data_ptr(), dists.data_ptr(),
                                    _stream(stream)), "nhq_hybrid_search")
+    return (ids, dists, cnt) if counters else (ids, dists)
+
+
+def nhq_seed_rank(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, n_cand: int,
+                  stream=None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    queries = _dev(queries, torch.float32, "queries", 2)
+    qattrs = _dev(qattrs, torch.uint8, "qattrs", 2)
+    nq = queries.shape[0]
+    cand = out if out is not None else torch.empty((nq, n_cand), dtype=torch.int32, device=queries.device)
+    _check(lib().nhq_seed_rank(ix.handle, queries.data_ptr(), qattrs.data_ptr(), nq, int(n_cand),
+                               cand.data_ptr(), _stream(stream)), "nhq_seed_rank")
+    return cand
+
+
+def nhq_search_seeded(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, cand: torch.Tensor,
+                      k: int, beam: int, n_init: int = 32, rerank: int = 0, output_mode: int = 0,
+                      max_hops: int = 0, visited_log2: int = 0, learned: bool = False,
+                      stop_threshold: float = 0.0, check_every: int = 0, counters: bool = False,
+                      stream=None, out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None):
+    queries = _dev(queries, torch.float32, "queries", 2)
+    qattrs = _dev(qattrs, torch.uint8, "qattrs", 2)
+    cand = _dev(cand, torch.int32, "cand", 2)
+    nq = queries.shape[0]
+    if out is None:
+        ids = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
+        dists = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
+    else:
+        ids, dists = out
+    cnt = torch.zeros((nq, 2), dtype=torch.int32, device=queries.device) if counters else None
+    sp = SearchParams(int(n_init), int(rerank), int(output_mode), int(max_hops), int(visited_log2),
+                      int(bool(learned)), float(stop_threshold), int(check_every),
+                      cnt.data_ptr() if cnt is not None else None)
+    _check(lib().nhq_search_seeded(ix.handle, queries.data_ptr(), qattrs.data_ptr(), nq,
+                                   cand.data_ptr(), cand.shape[1], int(k), int(beam), ctypes.byref(sp),
+                                   ids.data_ptr(), dists.data_ptr(), _stream(stream)),
+           "nhq_search_seeded")
     return (ids, dists, cnt) if counters else (ids, dists)
 
 

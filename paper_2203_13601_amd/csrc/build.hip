@@ -8,9 +8,6 @@
 
 namespace nhq {
 
-int launch_dense_topk(const float *A, const float *A_norm, const uint32_t *A_attr,
-                      const uint32_t *A_mask, int64_t na, const Index *ix, int mode, int K,
-                      int32_t *out_ids, float *out_keys, hipStream_t st);
 int launch_select(const Index *ix, const int32_t *cand, int K, int l, int32_t *adj, hipStream_t st);
 int launch_reverse(const Index *ix, const int32_t *fwd, int32_t *adj, hipStream_t st);
 int launch_refine(const Index *ix, const float *qpad, const int32_t *cand, int64_t nq, int K, int k,
@@ -20,36 +17,6 @@ int launch_refine(const Index *ix, const float *qpad, const int32_t *cand, int64
 // key; the exact re-score then keeps the l best)
 constexpr int kMargin = 16;
 
-namespace {
-
-__global__ void k_pad_queries(const float *__restrict__ q, const uint8_t *__restrict__ qa,
-                              int64_t nq, int d, int dp, int m, float *__restrict__ qpad,
-                              float *__restrict__ qnorm, uint32_t *__restrict__ qword,
-                              uint32_t *__restrict__ qmask)
-{
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nq;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        float s = 0.0f;
-        for (int c = 0; c < dp; ++c) {
-            const float v = c < d ? q[i * d + c] : 0.0f;
-            qpad[i * dp + c] = v;
-            s = fmaf(v, v, s);
-        }
-        qnorm[i] = s;
-        uint32_t w = 0, mk = 0;
-        for (int j = 0; j < m; ++j) {
-            const uint32_t c = qa[i * m + j];
-            if (c != 0xFFu) {
-                w |= c << (8 * j);
-                mk |= 0xFFu << (8 * j);
-            }
-        }
-        qword[i] = w;
-        qmask[i] = mk;
-    }
-}
-
-}  // namespace
 }  // namespace nhq
 
 using namespace nhq;
@@ -68,8 +35,8 @@ int nhq_index_build_graph(nhq_index *h, void *stream)
     const int K = (int)std::min<int64_t>(std::min(l + kMargin, 160), ix->n - 1);
     int32_t *cand = nullptr, *fwd = nullptr;
     NHQ_HIP(hipMallocAsync((void **)&cand, sizeof(int32_t) * (size_t)ix->n * K, st));
-    int rc = launch_dense_topk(ix->vec32, ix->norm, ix->attr, nullptr, ix->n, ix, 0, K, cand,
-                               nullptr, st);
+    int rc = launch_dense_topk(ix->vec32, ix->norm, ix->attr, nullptr, ix->n, ix->vec32, ix->norm,
+                               ix->attr, ix->n, ix->dp, ix->m, 0, 1, K, cand, nullptr, st);
     if (rc == NHQ_OK) {
         if (ix->reverse_edges) {
             if (hipMallocAsync((void **)&fwd, sizeof(int32_t) * (size_t)ix->n * ix->degree, st) != hipSuccess)
@@ -124,10 +91,10 @@ int nhq_bruteforce_hybrid_knn(const nhq_index *h, const float *queries, const ui
     NHQ_HIP(hipMallocAsync((void **)&qw, sizeof(uint32_t) * (size_t)nq, st));
     NHQ_HIP(hipMallocAsync((void **)&qm, sizeof(uint32_t) * (size_t)nq, st));
     NHQ_HIP(hipMallocAsync((void **)&cand, sizeof(int32_t) * (size_t)nq * K, st));
-    const int grid = (int)std::min<int64_t>(65536, (nq + 255) / 256);
-    hipLaunchKernelGGL(k_pad_queries, dim3(grid), dim3(256), 0, st, queries, qattrs, nq, ix->d,
-                       ix->dp, ix->m, qpad, qnorm, qw, qm);
-    int rc = launch_dense_topk(qpad, qnorm, qw, qm, nq, ix, 1, K, cand, nullptr, st);
+    int rc = launch_pad_queries(queries, qattrs, nq, ix->d, ix->dp, ix->m, qpad, qnorm, qw, qm, st);
+    if (rc == NHQ_OK)
+        rc = launch_dense_topk(qpad, qnorm, qw, qm, nq, ix->vec32, ix->norm, ix->attr, ix->n, ix->dp,
+                               ix->m, 1, 0, K, cand, nullptr, st);
     if (rc == NHQ_OK)
         rc = launch_refine(ix, qpad, cand, nq, K, k, ids, dists, st);
     void *bufs[] = {qpad, qnorm, qw, qm, cand};

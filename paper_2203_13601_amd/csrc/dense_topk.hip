@@ -2,11 +2,13 @@
 //
 // For every row a of A it finds the K best columns b of B by (key, id), where
 //   delta^2 = |a|^2 + |b|^2 - 2 a.b           (a.b from v_mfma_f32_16x16x4f32)
-//   build mode:    key = delta^2 (m + chi)^2,  b != a   (chi over all m codes)
+//   fusion mode:   key = delta^2 (m_a + chi)^2 (delta^2 when m_a = 0), chi and
+//                  m_a over a's constrained codes (all m codes for an object)
 //   filter mode:   key = delta^2, only b with chi(a's constraint, b) = 0
-// Build mode gives the candidate lists of the composite index (Sec. 4.1 step
-// (1) under the fusion distance of Sec. 5.1); filter mode gives the exact
-// hybrid k-NN of Def. 4.  The GEMM form of delta^2 is exact on integer-valued
+// Fusion mode gives the candidate lists of the composite index (Sec. 4.1 step
+// (1) under the fusion distance of Sec. 5.1; b != a) and ranks the entry
+// sample for each query's seed set; filter mode gives the exact hybrid k-NN
+// of Def. 4.  The GEMM form of delta^2 is exact on integer-valued
 // vectors; elsewhere the caller keeps a margin of extra candidates and
 // re-scores them exactly.
 //
@@ -34,7 +36,8 @@ struct TopkArgs {
     const float *B_norm;  // [nb]
     const uint32_t *B_attr;  // [nb]
     int64_t na, nb;
-    int m, K, cap, mode;  // mode 0 build, 1 filter
+    int m, K, cap, mode;  // mode 0 fusion key, 1 exact-match filter
+    int self_exclude;     // skip column == row (A and B are the same set)
     int32_t *out_ids;     // [na][K]
     float *out_keys;      // [na][K]
 };
@@ -152,7 +155,7 @@ __global__ __launch_bounds__(256) void k_dense_topk(const TopkArgs a)
     const uint32_t full = a.m >= 4 ? 0xFFFFFFFFu : ((1u << (8 * a.m)) - 1u);
     const uint32_t rmask = a.A_mask ? a.A_mask[rowc] : full;
     const int mq = __popc(rmask) / 8;
-    const float mult_base = (float)(a.mode == 0 ? a.m : mq);
+    const float mult_base = (float)mq;
 
     for (int64_t c0 = 0; c0 < a.nb; c0 += 64) {
         f32x4 acc[4];
@@ -187,7 +190,7 @@ __global__ __launch_bounds__(256) void k_dense_topk(const TopkArgs a)
                 const int64_t col = c0 + 16 * s + 4 * lq + r;
                 if (!row_ok || col >= a.nb)
                     continue;
-                if (a.mode == 0 && col == row)
+                if (a.self_exclude && col == row)
                     continue;
                 const int c = chi_of(a.B_attr[col], rattr, rmask);
                 if (a.mode == 1 && c != 0)
@@ -246,8 +249,9 @@ int launch_dp(const TopkArgs &a, hipStream_t st)
 }  // namespace
 
 int launch_dense_topk(const float *A, const float *A_norm, const uint32_t *A_attr,
-                      const uint32_t *A_mask, int64_t na, const Index *ix, int mode, int K,
-                      int32_t *out_ids, float *out_keys, hipStream_t st)
+                      const uint32_t *A_mask, int64_t na, const float *B, const float *B_norm,
+                      const uint32_t *B_attr, int64_t nb, int dp, int m, int mode,
+                      int self_exclude, int K, int32_t *out_ids, float *out_keys, hipStream_t st)
 {
     if (K < 1 || K > 160)
         return fail(NHQ_EINVAL, "dense top-K supports 1 <= K <= 160");
@@ -256,20 +260,21 @@ int launch_dense_topk(const float *A, const float *A_norm, const uint32_t *A_att
     a.A_norm = A_norm;
     a.A_attr = A_attr;
     a.A_mask = A_mask;
-    a.B = ix->vec32;
-    a.B_norm = ix->norm;
-    a.B_attr = ix->attr;
+    a.B = B;
+    a.B_norm = B_norm;
+    a.B_attr = B_attr;
     a.na = na;
-    a.nb = ix->n;
-    a.m = ix->m;
+    a.nb = nb;
+    a.m = m;
     a.K = K;
     a.cap = ((K + 64 + 15) / 16) * 16;
     a.mode = mode;
+    a.self_exclude = self_exclude;
     a.out_ids = out_ids;
     a.out_keys = out_keys;
     if (na == 0)
         return NHQ_OK;
-    switch (ix->dp) {
+    switch (dp) {
     case 32:
         return launch_dp<32>(a, st);
     case 64:

@@ -151,6 +151,52 @@ __global__ __launch_bounds__(64) void k_to_fp8(const float *__restrict__ v, uint
     }
 }
 
+__global__ void k_pad_queries(const float *__restrict__ q, const uint8_t *__restrict__ qa,
+                              int64_t nq, int d, int dp, int m, float *__restrict__ qpad,
+                              float *__restrict__ qnorm, uint32_t *__restrict__ qword,
+                              uint32_t *__restrict__ qmask)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nq;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        for (int c = 0; c < dp; ++c) {
+            const float v = c < d ? q[i * d + c] : 0.0f;
+            qpad[i * dp + c] = v;
+            s = fmaf(v, v, s);
+        }
+        qnorm[i] = s;
+        uint32_t w = 0, mk = 0;
+        for (int j = 0; j < m; ++j) {
+            const uint32_t c = qa[i * m + j];
+            if (c != 0xFFu) {
+                w |= c << (8 * j);
+                mk |= 0xFFu << (8 * j);
+            }
+        }
+        qword[i] = w;
+        qmask[i] = mk;
+    }
+}
+
+// dense copy of the entry sample's rows, norms and codes
+__global__ void k_gather_entry(const int32_t *__restrict__ entry, int ne, const float *__restrict__ vec32,
+                               const float *__restrict__ norm, const uint32_t *__restrict__ attr,
+                               int dp, float *__restrict__ ev, float *__restrict__ en,
+                               uint32_t *__restrict__ ea)
+{
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < (int64_t)ne * dp;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = t / dp;
+        const int c = (int)(t - r * dp);
+        const int64_t id = entry[r];
+        ev[t] = vec32[id * dp + c];
+        if (c == 0) {
+            en[r] = norm[id];
+            ea[r] = attr[id];
+        }
+    }
+}
+
 int grid_for(int64_t work, int block)
 {
     int64_t g = (work + block - 1) / block;
@@ -163,13 +209,26 @@ void free_index(Index *ix)
         return;
     if (ix->vecs && ix->vecs != ix->vec32)
         (void)hipFree(ix->vecs);
-    void *ptrs[] = {ix->vec32, ix->scale, ix->attr, ix->norm, ix->adj, ix->entry, ix->err, ix->ws, ix->mlp};
+    void *ptrs[] = {ix->vec32, ix->scale, ix->attr, ix->norm, ix->adj, ix->entry, ix->entry_vec,
+                    ix->entry_norm, ix->entry_attr, ix->err, ix->ws, ix->mlp};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
 }
 
 }  // namespace
+
+int launch_pad_queries(const float *q, const uint8_t *qa, int64_t nq, int d, int dp, int m,
+                       float *qpad, float *qnorm, uint32_t *qword, uint32_t *qmask, hipStream_t st)
+{
+    if (nq == 0)
+        return NHQ_OK;
+    hipLaunchKernelGGL(k_pad_queries, dim3(grid_for(nq, 64)), dim3(64), 0, st, q, qa, nq, d, dp, m,
+                       qpad, qnorm, qword, qmask);
+    NHQ_HIP(hipGetLastError());
+    return NHQ_OK;
+}
+
 }  // namespace nhq
 
 using namespace nhq;
@@ -327,6 +386,15 @@ int nhq_index_create(const float *vecs, const uint8_t *attrs, int64_t n, int32_t
             rc = fail(NHQ_EHIP, "entry upload failed");
             break;
         }
+        if (hipMalloc(&ix->entry_vec, (size_t)ne * ix->dp * sizeof(float)) != hipSuccess ||
+            hipMalloc(&ix->entry_norm, (size_t)ne * sizeof(float)) != hipSuccess ||
+            hipMalloc(&ix->entry_attr, (size_t)ne * sizeof(uint32_t)) != hipSuccess) {
+            rc = fail(NHQ_ENOMEM, "entry sample allocation failed");
+            break;
+        }
+        hipLaunchKernelGGL(k_gather_entry, dim3(grid_for(ne * ix->dp, 256)), dim3(256), 0, st, ix->entry,
+                           (int)ne, ix->vec32, ix->norm, ix->attr, ix->dp, ix->entry_vec,
+                           ix->entry_norm, ix->entry_attr);
         uint32_t bad = 0;
         if (hipMemcpyAsync(&bad, ix->err + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess) {
@@ -433,9 +501,38 @@ void nhq_index_free(nhq_index *h)
     delete h;
 }
 
-int nhq_hybrid_search(const nhq_index *h, const float *queries, const uint8_t *qattrs, int64_t nq,
-                      int32_t k, int32_t beam, const nhq_search_params *sp, int32_t *ids,
-                      float *dists, void *stream)
+int nhq_seed_rank(const nhq_index *h, const float *queries, const uint8_t *qattrs, int64_t nq,
+                  int32_t n_cand, int32_t *cand, void *stream)
+{
+    if (!h)
+        return fail(NHQ_EINVAL, "null index");
+    const Index *ix = &h->impl;
+    if (nq < 0 || n_cand < 1 || n_cand > 144)
+        return fail(NHQ_EINVAL, "need nq >= 0 and 1 <= n_cand <= 144");
+    if (nq == 0)
+        return NHQ_OK;
+    if (!queries || !cand || (ix->m > 0 && !qattrs))
+        return fail(NHQ_EINVAL, "null array argument");
+    hipStream_t st = (hipStream_t)stream;
+    float *qpad = nullptr, *qnorm = nullptr;
+    uint32_t *qw = nullptr, *qm = nullptr;
+    NHQ_HIP(hipMallocAsync((void **)&qpad, sizeof(float) * (size_t)nq * ix->dp, st));
+    NHQ_HIP(hipMallocAsync((void **)&qnorm, sizeof(float) * (size_t)nq, st));
+    NHQ_HIP(hipMallocAsync((void **)&qw, sizeof(uint32_t) * (size_t)nq, st));
+    NHQ_HIP(hipMallocAsync((void **)&qm, sizeof(uint32_t) * (size_t)nq, st));
+    int rc = launch_pad_queries(queries, qattrs, nq, ix->d, ix->dp, ix->m, qpad, qnorm, qw, qm, st);
+    if (rc == NHQ_OK)
+        rc = launch_dense_topk(qpad, qnorm, qw, qm, nq, ix->entry_vec, ix->entry_norm, ix->entry_attr,
+                               ix->n_entry, ix->dp, ix->m, 0, 0, n_cand, cand, nullptr, st);
+    void *bufs[] = {qpad, qnorm, qw, qm};
+    for (void *b : bufs)
+        (void)hipFreeAsync(b, st);
+    return rc;
+}
+
+int nhq_search_seeded(const nhq_index *h, const float *queries, const uint8_t *qattrs, int64_t nq,
+                      const int32_t *cand, int32_t n_cand, int32_t k, int32_t beam,
+                      const nhq_search_params *sp, int32_t *ids, float *dists, void *stream)
 {
     if (!h)
         return fail(NHQ_EINVAL, "null index");
@@ -444,8 +541,10 @@ int nhq_hybrid_search(const nhq_index *h, const float *queries, const uint8_t *q
         return fail(NHQ_EINVAL, "nq < 0");
     if (nq == 0)
         return NHQ_OK;
-    if (!queries || !ids || !dists || (ix->m > 0 && !qattrs))
+    if (!queries || !ids || !dists || !cand || (ix->m > 0 && !qattrs))
         return fail(NHQ_EINVAL, "null array argument");
+    if (n_cand < 1 || n_cand > 1024)
+        return fail(NHQ_EINVAL, "need 1 <= n_cand <= 1024");
     if (k < 1 || beam < k || beam > NHQ_MAX_BEAM)
         return fail(NHQ_EINVAL, "need 1 <= k <= beam <= 1024");
     nhq_search_params p{};
@@ -459,8 +558,8 @@ int nhq_hybrid_search(const nhq_index *h, const float *queries, const uint8_t *q
         p.stop_threshold = 0.5f;
     if (p.check_every == 0)
         p.check_every = 4;
-    if (p.n_init < 1 || p.max_hops < 1)
-        return fail(NHQ_EINVAL, "n_init and max_hops must be positive");
+    if (p.n_init < 1 || p.n_init > 128 || p.max_hops < 1)
+        return fail(NHQ_EINVAL, "need 1 <= n_init <= 128 and max_hops >= 1");
     if (p.output_mode != 0 && p.output_mode != 1)
         return fail(NHQ_EINVAL, "output_mode must be 0 or 1");
     if (p.rerank < 0 || (int64_t)p.rerank * k > beam)
@@ -471,6 +570,8 @@ int nhq_hybrid_search(const nhq_index *h, const float *queries, const uint8_t *q
         return fail(NHQ_EINVAL, "learned stop requested but no network is loaded");
     SearchLaunch s{};
     s.ix = ix;
+    s.seed_cand = cand;
+    s.n_seed_cand = n_cand;
     s.q = queries;
     s.qa = qattrs;
     s.nq = nq;
@@ -489,6 +590,31 @@ int nhq_hybrid_search(const nhq_index *h, const float *queries, const uint8_t *q
     s.counters = p.counters;
     s.stream = (hipStream_t)stream;
     return launch_search(s);
+}
+
+int nhq_hybrid_search(const nhq_index *h, const float *queries, const uint8_t *qattrs, int64_t nq,
+                      int32_t k, int32_t beam, const nhq_search_params *sp, int32_t *ids,
+                      float *dists, void *stream)
+{
+    if (!h)
+        return fail(NHQ_EINVAL, "null index");
+    const Index *ix = &h->impl;
+    if (nq < 0)
+        return fail(NHQ_EINVAL, "nq < 0");
+    if (nq == 0)
+        return NHQ_OK;
+    const int n_init = (sp && sp->n_init > 0) ? sp->n_init : 32;
+    if (n_init > 128)
+        return fail(NHQ_EINVAL, "need 1 <= n_init <= 128");
+    const int ks = std::min(ix->n_entry, n_init + 16);
+    hipStream_t st = (hipStream_t)stream;
+    int32_t *cand = nullptr;
+    NHQ_HIP(hipMallocAsync((void **)&cand, sizeof(int32_t) * (size_t)nq * ks, st));
+    int rc = nhq_seed_rank(h, queries, qattrs, nq, ks, cand, stream);
+    if (rc == NHQ_OK)
+        rc = nhq_search_seeded(h, queries, qattrs, nq, cand, ks, k, beam, sp, ids, dists, stream);
+    (void)hipFreeAsync(cand, st);
+    return rc;
 }
 
 }  // extern "C"

@@ -53,6 +53,9 @@ struct Index {
     float *norm = nullptr;      // [n] squared norms of the float32 rows
     int32_t *adj = nullptr;     // [n][degree]
     int32_t *entry = nullptr;   // [n_entry]
+    float *entry_vec = nullptr;     // [n_entry][dp] float32 rows of the entry sample
+    float *entry_norm = nullptr;    // [n_entry]
+    uint32_t *entry_attr = nullptr; // [n_entry]
     uint32_t *err = nullptr;    // device error word
     // per-index workspace (grown on demand)
     void *ws = nullptr;
@@ -79,6 +82,8 @@ struct SearchLaunch {
     const Index *ix;
     const float *q;
     const uint8_t *qa;
+    const int32_t *seed_cand;  // [nq][n_seed_cand] entry-sample candidates per query
+    int n_seed_cand;
     int64_t nq;
     int k, L, n_init, out_mode, rerank_n, max_hops, hash_log2, learned, check_every;
     float stop_threshold;
@@ -88,6 +93,16 @@ struct SearchLaunch {
     hipStream_t stream;
 };
 int launch_search(const SearchLaunch &s);
+
+// dense tiles with a streaming top-K (see dense_topk.hip)
+int launch_dense_topk(const float *A, const float *A_norm, const uint32_t *A_attr,
+                      const uint32_t *A_mask, int64_t na, const float *B, const float *B_norm,
+                      const uint32_t *B_attr, int64_t nb, int dp, int m, int mode,
+                      int self_exclude, int K, int32_t *out_ids, float *out_keys, hipStream_t st);
+
+// queries -> zero-padded float32 rows, squared norms, packed codes and masks
+int launch_pad_queries(const float *q, const uint8_t *qa, int64_t nq, int d, int dp, int m,
+                       float *qpad, float *qnorm, uint32_t *qword, uint32_t *qmask, hipStream_t st);
 
 }  // namespace nhq
 

@@ -26,7 +26,8 @@ struct SearchArgs {
     const float *scale;
     const uint32_t *attr;
     const int32_t *adj;
-    const int32_t *entry;
+    const int32_t *seed_cand;  // [nq][n_seed] positions in the entry sample (-1 padded)
+    const int32_t *entry;      // entry sample: position -> vertex id
     const float *q;
     const uint8_t *qa;
     int32_t *out_ids;
@@ -35,7 +36,7 @@ struct SearchArgs {
     uint32_t *err;
     int64_t n;
     int64_t nq;
-    int d, m, R, n_entry;
+    int d, m, R, n_seed;
     int k, L, n_init, out_mode, rerank_n, max_hops;
     int scap;       // staging capacity (entries)
     int vis_words;  // visited-set words
@@ -341,21 +342,24 @@ __global__ __launch_bounds__(64) void k_search(const SearchArgs a)
         vis[i] = bitset ? 0u : kEmpty;
     wsync();
 
-    // ---- seed set: the n_init best members of the entry sample
+    // ---- seed set: the n_init best members of the entry sample, re-scored
+    // exactly from the candidates the dense ranking kept
     int size = 0, lo = 0;
     const int cap0 = min(a.n_init, L);
-    for (int e0 = 0; e0 < a.n_entry; e0 += 64) {
-        const int ne = min(64, a.n_entry - e0);
-        uint32_t cw = 0;
-        if (lane < ne) {
-            const uint32_t id = (uint32_t)a.entry[e0 + lane];
-            cw = id | ((uint32_t)chi_of(a.attr[id], qword, qmask) << kChiShift);
-            sid[lane] = cw;
-        }
+    for (int e0 = 0; e0 < a.n_seed; e0 += 64) {
+        const int e = e0 + lane;
+        const int32_t pos = e < a.n_seed ? a.seed_cand[qi * a.n_seed + e] : -1;
+        const int32_t v = pos >= 0 ? a.entry[pos] : -1;
+        const bool ok = v >= 0 && v < a.n;
+        const uint64_t vb = __ballot(ok);
+        const int ne = __popcll(vb);
+        if (ok)
+            sid[lanes_below(vb)] = (uint32_t)v | ((uint32_t)chi_of(a.attr[v], qword, qmask) << kChiShift);
         wsync();
         score_batch<DP, ST>(a.vecs, a.scale, qv, sid, skey, ne, mq, true);
         wsync();
         const float ck = lane < ne ? skey[lane] : 0.0f;
+        const uint32_t cw = lane < ne ? sid[lane] : 0u;
         size = pool_merge(pkey, pid, size, cap0, ck, cw, lane < ne, lo);
     }
     for (int e = lane; e < size; e += 64) {
@@ -535,6 +539,7 @@ int launch_search(const SearchLaunch &s)
     a.scale = ix->scale;
     a.attr = ix->attr;
     a.adj = ix->adj;
+    a.seed_cand = s.seed_cand;
     a.entry = ix->entry;
     a.q = s.q;
     a.qa = s.qa;
@@ -547,7 +552,7 @@ int launch_search(const SearchLaunch &s)
     a.d = ix->d;
     a.m = ix->m;
     a.R = ix->degree;
-    a.n_entry = ix->n_entry;
+    a.n_seed = s.n_seed_cand;
     a.k = s.k;
     a.L = s.L;
     a.n_init = s.n_init;
