@@ -12,8 +12,10 @@
 // vectors; elsewhere the caller keeps a margin of extra candidates and
 // re-scores them exactly.
 //
-// Work split: a workgroup of 4 waves owns 64 rows (16 per wave) and streams
-// every column of B in tiles of 64 (4 MFMA sub-tiles of 16).  MFMA operand A
+// Work split: a workgroup of 2 waves owns 32 rows (16 per wave) and streams
+// one range of columns of B (the grid's y dimension splits the columns when
+// there are too few row blocks to fill the chip; a merge kernel then joins
+// the per-range lists) in tiles of 64 (4 MFMA sub-tiles of 16).  MFMA operand A
 // holds 16 columns and operand B the wave's 16 rows, so in the 16x16 result
 // lane l holds row l % 16 against columns 4 (l / 16) + r, r = 0..3.  Each lane
 // supplies point (l % 16) at dims 16 t + 4 (l / 16) + j for k-step 4 t + j:
@@ -38,8 +40,10 @@ struct TopkArgs {
     int64_t na, nb;
     int m, K, cap, mode;  // mode 0 fusion key, 1 exact-match filter
     int self_exclude;     // skip column == row (A and B are the same set)
-    int32_t *out_ids;     // [na][K]
-    float *out_keys;      // [na][K]
+    int64_t col_span;     // columns per split (multiple of 64)
+    int splits;           // gridDim.y
+    int32_t *out_ids;     // [na][splits][K] (splits == 1: the final lists)
+    float *out_keys;      // [na][splits][K]
 };
 
 __device__ __forceinline__ void wsync()
@@ -60,7 +64,7 @@ __device__ __forceinline__ bool lt_key(float ka, uint32_t ia, float kb, uint32_t
     return ka < kb || (ka == kb && ia < ib);
 }
 
-constexpr int kWaves = 4;
+constexpr int kWaves = 2;
 constexpr int kRowsPerWave = 16;
 
 // Re-rank row r's buffer: keep its `keep` best entries, sorted, in place;
@@ -72,7 +76,7 @@ __device__ void compact_row(float *bk, uint32_t *bi, int *cnt, float *thk, uint3
     const int n = cnt[r];
     float *rk = bk + r * cap;
     uint32_t *ri = bi + r * cap;
-    constexpr int MAXT = 4;  // cap <= 256
+    constexpr int MAXT = 5;  // cap <= 320
     float ke[MAXT];
     uint32_t ie[MAXT];
     int rank[MAXT];
@@ -87,12 +91,21 @@ __device__ void compact_row(float *bk, uint32_t *bi, int *cnt, float *thk, uint3
             ie[t] = ri[e];
         }
     }
-    for (int i = 0; i < n; ++i) {
-        const float ki = rk[i];
-        const uint32_t ii = ri[i];
+    // every lane compares its entries with all n entries; the buffer is read
+    // 4 entries per LDS access (rows are 16-byte aligned, padding compares
+    // as +inf) so the reads pipeline instead of chaining
+    for (int i = 0; i < n; i += 4) {
+        const float4 k4 = *reinterpret_cast<const float4 *>(rk + i);
+        const uint4 i4 = *reinterpret_cast<const uint4 *>(ri + i);
+        const float kk[4] = {k4.x, i + 1 < n ? k4.y : __int_as_float(0x7F800000),
+                             i + 2 < n ? k4.z : __int_as_float(0x7F800000),
+                             i + 3 < n ? k4.w : __int_as_float(0x7F800000)};
+        const uint32_t ii[4] = {i4.x, i4.y, i4.z, i4.w};
 #pragma unroll
-        for (int t = 0; t < MAXT; ++t)
-            rank[t] += lt_key(ki, ii, ke[t], ie[t]) ? 1 : 0;
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int t = 0; t < MAXT; ++t)
+                rank[t] += lt_key(kk[u], ii[u], ke[t], ie[t]) ? 1 : 0;
     }
     wsync();
 #pragma unroll
@@ -114,7 +127,7 @@ __device__ void compact_row(float *bk, uint32_t *bi, int *cnt, float *thk, uint3
 }
 
 template <int DP>
-__global__ __launch_bounds__(256) void k_dense_topk(const TopkArgs a)
+__global__ __launch_bounds__(128) void k_dense_topk(const TopkArgs a)
 {
     constexpr int NT = DP / 16;             // float4 chunks per lane per point
     constexpr bool ROWS_IN_REGS = NT <= 16;  // rows stay in registers up to 256 dims
@@ -157,45 +170,79 @@ __global__ __launch_bounds__(256) void k_dense_topk(const TopkArgs a)
     const int mq = __popc(rmask) / 8;
     const float mult_base = (float)mq;
 
-    for (int64_t c0 = 0; c0 < a.nb; c0 += 64) {
+    const int64_t cbeg = (int64_t)blockIdx.y * a.col_span;
+    const int64_t cend = min(a.nb, cbeg + a.col_span);
+    for (int64_t c0 = cbeg; c0 < cend; c0 += 64) {
         f32x4 acc[4];
+        const float4 *bcol[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             acc[s] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
             int64_t col = c0 + 16 * s + rl;
-            if (col >= a.nb)
-                col = a.nb - 1;
-            const float4 *bcol = reinterpret_cast<const float4 *>(a.B + col * DP);
+            if (col >= cend)
+                col = cend - 1;
+            bcol[s] = reinterpret_cast<const float4 *>(a.B + col * DP);
+        }
+        // norms and codes of this lane's 16 columns, fetched ahead of the MFMAs
+        float4 nrm[4];
+        uint4 atr[4];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const float4 cb = bcol[4 * t + lq];
-                float4 rv;
-                if constexpr (ROWS_IN_REGS)
-                    rv = ra[t];
-                else
-                    rv = arow[4 * t + lq];
-                acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb.x, rv.x, acc[s], 0, 0, 0);
-                acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb.y, rv.y, acc[s], 0, 0, 0);
-                acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb.z, rv.z, acc[s], 0, 0, 0);
-                acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb.w, rv.w, acc[s], 0, 0, 0);
+        for (int s = 0; s < 4; ++s) {
+            const int64_t cb0 = c0 + 16 * s + 4 * lq;
+            if (cb0 + 3 < cend) {
+                nrm[s] = *reinterpret_cast<const float4 *>(a.B_norm + cb0);
+                atr[s] = *reinterpret_cast<const uint4 *>(a.B_attr + cb0);
+            } else {
+                const int64_t c1 = min(cb0 + 1, cend - 1), c2 = min(cb0 + 2, cend - 1);
+                const int64_t c3 = min(cb0 + 3, cend - 1), cz = min(cb0, cend - 1);
+                nrm[s] = make_float4(a.B_norm[cz], a.B_norm[c1], a.B_norm[c2], a.B_norm[c3]);
+                atr[s] = make_uint4(a.B_attr[cz], a.B_attr[c1], a.B_attr[c2], a.B_attr[c3]);
             }
+        }
+        // four independent accumulation chains, interleaved per k-step
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            float4 cb[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                cb[s] = bcol[s][4 * t + lq];
+            float4 rv;
+            if constexpr (ROWS_IN_REGS)
+                rv = ra[t];
+            else
+                rv = arow[4 * t + lq];
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[s].x, rv.x, acc[s], 0, 0, 0);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[s].y, rv.y, acc[s], 0, 0, 0);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[s].z, rv.z, acc[s], 0, 0, 0);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[s].w, rv.w, acc[s], 0, 0, 0);
         }
         // epilogue: keys of this lane's 16 columns for its row
         const float tk = thk[rl];
         const uint32_t ti = thi[rl];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
+            const int64_t cb0 = c0 + 16 * s + 4 * lq;  // this lane's 4 columns
+            const float nb4[4] = {nrm[s].x, nrm[s].y, nrm[s].z, nrm[s].w};
+            const uint32_t at4[4] = {atr[s].x, atr[s].y, atr[s].z, atr[s].w};
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t col = c0 + 16 * s + 4 * lq + r;
-                if (!row_ok || col >= a.nb)
+                const int64_t col = cb0 + r;
+                if (!row_ok || col >= cend)
                     continue;
                 if (a.self_exclude && col == row)
                     continue;
-                const int c = chi_of(a.B_attr[col], rattr, rmask);
+                const int c = chi_of(at4[r], rattr, rmask);
                 if (a.mode == 1 && c != 0)
                     continue;
-                float d2 = rn + a.B_norm[col] - 2.0f * acc[s][r];
+                float d2 = rn + nb4[r] - 2.0f * acc[s][r];
                 d2 = fmaxf(d2, 0.0f);
                 const float mult = mult_base == 0.0f ? 1.0f : (mult_base + c) * (mult_base + c);
                 const float key = a.mode == 0 ? d2 * mult : d2;
@@ -224,10 +271,54 @@ __global__ __launch_bounds__(256) void k_dense_topk(const TopkArgs a)
         if (orow >= a.na)
             break;
         const int n = cnt[r];
+        const int64_t base = (orow * a.splits + blockIdx.y) * a.K;
         for (int e = lane; e < a.K; e += 64) {
-            a.out_ids[orow * a.K + e] = e < n ? (int32_t)bi[r * cap + e] : -1;
+            a.out_ids[base + e] = e < n ? (int32_t)bi[r * cap + e] : -1;
             if (a.out_keys)
-                a.out_keys[orow * a.K + e] = e < n ? bk[r * cap + e] : __int_as_float(0x7F800000);
+                a.out_keys[base + e] = e < n ? bk[r * cap + e] : __int_as_float(0x7F800000);
+        }
+    }
+}
+
+// join the per-range sorted lists of one row: K steps of a k-way merge, the
+// head of list s held by lane s (splits <= 64)
+__global__ __launch_bounds__(64) void k_merge_lists(const int32_t *__restrict__ pid,
+                                                    const float *__restrict__ pkey, int64_t na,
+                                                    int splits, int K, int32_t *__restrict__ out_ids,
+                                                    float *__restrict__ out_keys)
+{
+    const int lane = threadIdx.x;
+    const int64_t r = blockIdx.x;
+    if (r >= na)
+        return;
+    const int64_t base = r * splits * K;
+    int head = 0;
+    for (int e = 0; e < K; ++e) {
+        float hk = __int_as_float(0x7F800000);
+        uint32_t hi = 0xFFFFFFFFu;
+        if (lane < splits && head < K) {
+            const int32_t v = pid[base + lane * K + head];
+            if (v >= 0) {
+                hk = pkey[base + lane * K + head];
+                hi = (uint32_t)v;
+            }
+        }
+        float bk = hk;
+        uint32_t bi = hi;
+        for (int o = 32; o > 0; o >>= 1) {
+            const float ok = __shfl_xor(bk, o, 64);
+            const uint32_t oi = (uint32_t)__shfl_xor((int)bi, o, 64);
+            if (lt_key(ok, oi, bk, bi)) {
+                bk = ok;
+                bi = oi;
+            }
+        }
+        if (lane < splits && hi == bi && hi != 0xFFFFFFFFu)
+            head += 1;
+        if (lane == 0) {
+            out_ids[r * K + e] = bi == 0xFFFFFFFFu ? -1 : (int32_t)bi;
+            if (out_keys)
+                out_keys[r * K + e] = bk;
         }
     }
 }
@@ -241,7 +332,7 @@ int launch_dp(const TopkArgs &a, hipStream_t st)
         NHQ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const int64_t blocks = (a.na + kWaves * kRowsPerWave - 1) / (kWaves * kRowsPerWave);
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * kWaves), lds, st, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks, (unsigned)a.splits), dim3(64 * kWaves), lds, st, a);
     NHQ_HIP(hipGetLastError());
     return NHQ_OK;
 }
@@ -267,32 +358,52 @@ int launch_dense_topk(const float *A, const float *A_norm, const uint32_t *A_att
     a.nb = nb;
     a.m = m;
     a.K = K;
-    a.cap = ((K + 64 + 15) / 16) * 16;
+    // a full tile (64 appends per row) of slack above the kept K, so a row is
+    // re-ranked only after at least 64 new survivors
+    a.cap = ((K + 128 + 15) / 16) * 16;
     a.mode = mode;
     a.self_exclude = self_exclude;
-    a.out_ids = out_ids;
-    a.out_keys = out_keys;
-    if (na == 0)
+    if (na == 0 || nb == 0)
         return NHQ_OK;
-    switch (dp) {
-    case 32:
-        return launch_dp<32>(a, st);
-    case 64:
-        return launch_dp<64>(a, st);
-    case 96:
-        return launch_dp<96>(a, st);
-    case 128:
-        return launch_dp<128>(a, st);
-    case 256:
-        return launch_dp<256>(a, st);
-    case 512:
-        return launch_dp<512>(a, st);
-    case 960:
-        return launch_dp<960>(a, st);
-    case 1024:
-        return launch_dp<1024>(a, st);
+    // split the columns until about 2048 workgroups are in flight, keeping
+    // at least 512 columns per split
+    const int64_t row_blocks = (na + kWaves * kRowsPerWave - 1) / (kWaves * kRowsPerWave);
+    int splits = 1;
+    while (splits < 64 && row_blocks * splits < 2048 && nb / (2 * splits) >= 512)
+        splits *= 2;
+    a.splits = splits;
+    a.col_span = ((nb + splits - 1) / splits + 63) / 64 * 64;
+    int32_t *pid = out_ids;
+    float *pkey = out_keys;
+    if (splits > 1) {
+        NHQ_HIP(hipMallocAsync((void **)&pid, sizeof(int32_t) * (size_t)na * splits * K, st));
+        NHQ_HIP(hipMallocAsync((void **)&pkey, sizeof(float) * (size_t)na * splits * K, st));
     }
-    return fail(NHQ_EINVAL, "unsupported padded dimension");
+    a.out_ids = pid;
+    a.out_keys = pkey;
+    int rc = NHQ_OK;
+    switch (dp) {
+    case 32: rc = launch_dp<32>(a, st); break;
+    case 64: rc = launch_dp<64>(a, st); break;
+    case 96: rc = launch_dp<96>(a, st); break;
+    case 128: rc = launch_dp<128>(a, st); break;
+    case 256: rc = launch_dp<256>(a, st); break;
+    case 512: rc = launch_dp<512>(a, st); break;
+    case 960: rc = launch_dp<960>(a, st); break;
+    case 1024: rc = launch_dp<1024>(a, st); break;
+    default: rc = fail(NHQ_EINVAL, "unsupported padded dimension");
+    }
+    if (splits > 1) {
+        if (rc == NHQ_OK) {
+            hipLaunchKernelGGL(k_merge_lists, dim3((unsigned)na), dim3(64), 0, st, pid, pkey, na, splits,
+                               K, out_ids, out_keys);
+            if (hipGetLastError() != hipSuccess)
+                rc = fail(NHQ_EHIP, "merge launch failed");
+        }
+        (void)hipFreeAsync(pid, st);
+        (void)hipFreeAsync(pkey, st);
+    }
+    return rc;
 }
 
 }  // namespace nhq

@@ -521,9 +521,14 @@ int nhq_seed_rank(const nhq_index *h, const float *queries, const uint8_t *qattr
     NHQ_HIP(hipMallocAsync((void **)&qw, sizeof(uint32_t) * (size_t)nq, st));
     NHQ_HIP(hipMallocAsync((void **)&qm, sizeof(uint32_t) * (size_t)nq, st));
     int rc = launch_pad_queries(queries, qattrs, nq, ix->d, ix->dp, ix->m, qpad, qnorm, qw, qm, st);
-    if (rc == NHQ_OK)
-        rc = launch_dense_topk(qpad, qnorm, qw, qm, nq, ix->entry_vec, ix->entry_norm, ix->entry_attr,
-                               ix->n_entry, ix->dp, ix->m, 0, 0, n_cand, cand, nullptr, st);
+    if (rc == NHQ_OK) {
+        if (ix->n_entry <= 8192)
+            rc = launch_seed_rank(ix, qpad, qnorm, qw, qm, nq, n_cand, cand, st);
+        else
+            rc = launch_dense_topk(qpad, qnorm, qw, qm, nq, ix->entry_vec, ix->entry_norm,
+                                   ix->entry_attr, ix->n_entry, ix->dp, ix->m, 0, 0, n_cand, cand,
+                                   nullptr, st);
+    }
     void *bufs[] = {qpad, qnorm, qw, qm};
     for (void *b : bufs)
         (void)hipFreeAsync(b, st);

@@ -100,6 +100,10 @@ int launch_dense_topk(const float *A, const float *A_norm, const uint32_t *A_att
                       const uint32_t *B_attr, int64_t nb, int dp, int m, int mode,
                       int self_exclude, int K, int32_t *out_ids, float *out_keys, hipStream_t st);
 
+// seed ranking of the entry sample (see seed.hip): positions of the K best
+int launch_seed_rank(const Index *ix, const float *qpad, const float *qnorm, const uint32_t *qword,
+                     const uint32_t *qmask, int64_t nq, int K, int32_t *cand, hipStream_t st);
+
 // queries -> zero-padded float32 rows, squared norms, packed codes and masks
 int launch_pad_queries(const float *q, const uint8_t *qa, int64_t nq, int d, int dp, int m,
                        float *qpad, float *qnorm, uint32_t *qword, uint32_t *qmask, hipStream_t st);

@@ -36,7 +36,7 @@ struct SearchArgs {
     uint32_t *err;
     int64_t n;
     int64_t nq;
-    int d, m, R, n_seed;
+    int d, m, R, n_seed, n_entry;
     int k, L, n_init, out_mode, rerank_n, max_hops;
     int scap;       // staging capacity (entries)
     int vis_words;  // visited-set words
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(64) void k_search(const SearchArgs a)
     for (int e0 = 0; e0 < a.n_seed; e0 += 64) {
         const int e = e0 + lane;
         const int32_t pos = e < a.n_seed ? a.seed_cand[qi * a.n_seed + e] : -1;
-        const int32_t v = pos >= 0 ? a.entry[pos] : -1;
+        const int32_t v = (pos >= 0 && pos < a.n_entry) ? a.entry[pos] : -1;
         const bool ok = v >= 0 && v < a.n;
         const uint64_t vb = __ballot(ok);
         const int ne = __popcll(vb);
@@ -553,6 +553,7 @@ int launch_search(const SearchLaunch &s)
     a.m = ix->m;
     a.R = ix->degree;
     a.n_seed = s.n_seed_cand;
+    a.n_entry = ix->n_entry;
     a.k = s.k;
     a.L = s.L;
     a.n_init = s.n_init;

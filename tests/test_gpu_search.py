@@ -198,3 +198,24 @@ def test_argument_errors(int_set):
     with pytest.raises(nhq.NHQError):
         bad = adj.copy()
         nhq.nhq_index_create(_dev(w.x), _dev(np.full_like(w.attrs, 255)), n_entry=8)
+
+
+@pytest.mark.parametrize("n_entry,n_cand", [(4096, 48), (300, 20), (64, 100), (5000, 1)])
+def test_seed_rank_is_the_exact_best_of_the_entry_sample(n_entry, n_cand):
+    # integer data: the dense ranking is exact, so the positions it returns
+    # are exactly the n_cand best entries by (key, position).  The oracle
+    # gives them as the pool of a search over the entry sample alone (ids =
+    # positions) with no edges, seeded by the whole sample.
+    w = synth.small(20000, 64, 200, seed=55, integer=True, n_centres=8, wildcard_arity=True)
+    ix = nhq.nhq_index_create(_dev(w.x), _dev(w.attrs), n_entry=n_entry, seed=9)
+    cand = nhq.nhq_seed_rank(ix, _dev(w.q), _dev(w.qattrs), n_cand).cpu().numpy()
+    entry = oracle.entry_points(9, w.n, n_entry)
+    ne = len(entry)
+    noedge = np.full((ne, 1), -1, np.int32)
+    want, _, _, _, _ = oracle.search(noedge, w.x[entry], w.attrs[entry], w.q, w.qattrs, n_cand,
+                                     n_cand, np.arange(ne, dtype=np.int32), n_init=n_cand,
+                                     key_mode=oracle.KEY32, out_mode=1)
+    for i in range(w.nq):
+        got = cand[i]
+        assert sorted(got[got >= 0].tolist()) == sorted(want[i][want[i] >= 0].tolist())
+        assert (got >= 0).sum() == min(n_cand, ne)
