@@ -29,7 +29,7 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def _profiled_traffic(kernel: str, source: str):
+def _profiled_traffic(kernel: str, source: str, tag: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when no
     summary exists or the kernel source changed since it was taken."""
@@ -40,7 +40,7 @@ def _profiled_traffic(kernel: str, source: str):
         h = hashlib.sha256(open(os.path.join(root, source), "rb").read()).hexdigest()[:16]
     except OSError:
         return None
-    for fn in sorted(glob.glob(os.path.join(root, "profiles", "%s_*.md" % kernel))):
+    for fn in sorted(glob.glob(os.path.join(root, "profiles", "%s_*%s.md" % (kernel, tag)))):
         txt = open(fn).read()
         if "source_sha256_16[%s]: %s" % (source, h) not in txt:
             continue
@@ -174,7 +174,10 @@ def main():
                                 ndc=op["ndc"], hops=op["hops"], d=w.d, m=w.m,
                                 scale_bytes=4 if args.storage == "fp8" else 0)
     search_avg_s = float(np.mean(search_ms)) / 1000.0
-    traffic = _profiled_traffic("k_search", "paper_2203_13601_amd/csrc/search.hip")
+    traffic = None
+    if args.n == 1_000_000 and args.nq == 10_000 and args.storage == "fp32":
+        traffic = _profiled_traffic("k_search", "paper_2203_13601_amd/csrc/search.hip",
+                                    "_beam%d" % beam)
     achieved = bq * nq / search_avg_s / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": 8000.0, "unit": "GB/s",
             "frac": round(achieved / 8000.0, 5), "traffic": traffic,
