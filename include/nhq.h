@@ -128,6 +128,13 @@ int nhq_index_set_graph(nhq_index *ix, const int32_t *adj, int32_t degree, void 
 int nhq_index_get_graph(const nhq_index *ix, int32_t *adj_out, void *stream);
 int nhq_index_get_entry(const nhq_index *ix, int32_t *entry_out, void *stream);
 
+/* Copy the storage form the search scores with: rows padded to the kernel
+ * width dp (returned in *dp_out): float32 [n][dp], bf16 bit patterns uint16
+ * [n][dp] or OCP e4m3 codes uint8 [n][dp]; scales (fp8 only, else untouched)
+ * float32 [n].  Device outputs; scales may be NULL. */
+int nhq_index_get_storage(const nhq_index *ix, void *rows_out, float *scales_out, int32_t *dp_out,
+                          void *stream);
+
 /* Shape queries (host outputs, any may be NULL). */
 int nhq_index_info(const nhq_index *ix, int64_t *n, int32_t *d, int32_t *m, int32_t *degree,
                    int32_t *storage, int32_t *n_entry);

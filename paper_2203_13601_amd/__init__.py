@@ -8,5 +8,5 @@ has not been built.
 from ._binding import (BuildParams, Index, NHQError, SearchParams, lib,  # noqa: F401
                        nhq_bruteforce_hybrid_knn, nhq_build_index, nhq_hybrid_search,
                        nhq_index_build_graph, nhq_index_create, nhq_index_device_error,
-                       nhq_index_get_entry, nhq_index_get_graph, nhq_index_info,
+                       nhq_index_get_entry, nhq_index_get_graph, nhq_index_get_storage, nhq_index_info,
                        nhq_index_set_graph, nhq_search_seeded, nhq_seed_rank, DEVERR_BADID, DEVERR_HOPCAP, STORAGE)

@@ -64,6 +64,7 @@ def lib() -> ctypes.CDLL:
         "nhq_index_get_graph": ([P, P, P], i32),
         "nhq_index_get_entry": ([P, P, P], i32),
         "nhq_index_info": ([P, P, P, P, P, P, P], i32),
+        "nhq_index_get_storage": ([P, P, P, P, P], i32),
         "nhq_index_device_error": ([P, P, P], i32),
         "nhq_index_free": ([P], None),
         "nhq_hybrid_search": ([P, P, P, i64, i32, i32, P, P, P, P], i32),
@@ -195,6 +196,31 @@ def nhq_index_get_entry(ix: Index, stream=None) -> torch.Tensor:
     out = torch.empty((info["n_entry"],), dtype=torch.int32, device="cuda")
     _check(lib().nhq_index_get_entry(ix.handle, out.data_ptr(), _stream(stream)), "nhq_index_get_entry")
     return out
+
+
+def nhq_index_get_storage(ix: Index, stream=None):
+    """(rows [n, dp] as float32 / int16 bf16 bit patterns / uint8 e4m3 codes,
+    scales float32 [n] or None)"""
+    info = nhq_index_info(ix)
+    st = info["storage"]
+    dp = ctypes.c_int32()
+    _d = _padded_dim(info["d"])
+    dt = {0: torch.float32, 1: torch.int16, 2: torch.uint8}[st]
+    rows = torch.empty((info["n"], _d), dtype=dt, device="cuda")
+    scales = torch.empty((info["n"],), dtype=torch.float32, device="cuda") if st == 2 else None
+    _check(lib().nhq_index_get_storage(ix.handle, rows.data_ptr(),
+                                       scales.data_ptr() if scales is not None else None,
+                                       ctypes.byref(dp), _stream(stream)), "nhq_index_get_storage")
+    if dp.value != _d:
+        raise RuntimeError("padded width mismatch")
+    return rows, scales
+
+
+def _padded_dim(d: int) -> int:
+    for w in (32, 64, 96, 128, 256, 512, 960, 1024):
+        if d <= w:
+            return w
+    raise ValueError("d > 1024")
 
 
 def nhq_index_device_error(ix: Index, stream=None) -> int:

@@ -457,6 +457,22 @@ int nhq_index_get_entry(const nhq_index *h, int32_t *entry_out, void *stream)
     return NHQ_OK;
 }
 
+int nhq_index_get_storage(const nhq_index *h, void *rows_out, float *scales_out, int32_t *dp_out,
+                          void *stream)
+{
+    if (!h || !rows_out)
+        return fail(NHQ_EINVAL, "null argument");
+    const Index *ix = &h->impl;
+    const size_t elem = ix->storage == NHQ_STORAGE_FP32 ? 4 : (ix->storage == NHQ_STORAGE_BF16 ? 2 : 1);
+    hipStream_t st = (hipStream_t)stream;
+    NHQ_HIP(hipMemcpyAsync(rows_out, ix->vecs, (size_t)ix->n * ix->dp * elem, hipMemcpyDeviceToDevice, st));
+    if (scales_out && ix->storage == NHQ_STORAGE_FP8)
+        NHQ_HIP(hipMemcpyAsync(scales_out, ix->scale, (size_t)ix->n * sizeof(float), hipMemcpyDeviceToDevice, st));
+    if (dp_out)
+        *dp_out = ix->dp;
+    return NHQ_OK;
+}
+
 int nhq_index_info(const nhq_index *h, int64_t *n, int32_t *d, int32_t *m, int32_t *degree,
                    int32_t *storage, int32_t *n_entry)
 {
