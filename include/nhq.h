@@ -74,6 +74,21 @@ typedef struct {
     uint64_t seed;         /* splitmix64 seed of the entry sample          [0] */
 } nhq_build_params;
 
+/* Per-checkpoint search traces (training data of the stop network).  Every
+ * check_every hops the search records 8 state features, the hop count and a
+ * fingerprint of its current top-k eligible ids; at the end the fingerprint
+ * of the final top-k.  Device arrays: feat float32 [nq][cap][8], hop uint32
+ * [nq][cap], hash uint32 [nq][cap], count int32 [nq] (checkpoints written),
+ * final_hash uint32 [nq]. */
+typedef struct {
+    float *feat;
+    uint32_t *hop;
+    uint32_t *hash;
+    int32_t *count;
+    uint32_t *final_hash;
+    int32_t cap;
+} nhq_trace;
+
 /* Search parameters (Alg. 2).  Pass NULL for all defaults. */
 typedef struct {
     int32_t n_init;      /* seed set size: the best n_init members of the
@@ -92,6 +107,9 @@ typedef struct {
     int32_t check_every; /* network evaluated every this many hops        [4] */
     uint32_t *counters;  /* nullable DEVICE uint32 [nq][2]: NDC (neighbour
                             distance evaluations) and H (expansions)          */
+    float cap_factor;    /* learned, > 0: stop at cap_factor * 2^(beam output
+                            at the first checkpoint) hops                  [0] */
+    const nhq_trace *trace; /* nullable: record checkpoint traces           */
 } nhq_search_params;
 
 /* Device error word bits (accumulated per index; nhq_index_device_error). */
@@ -186,6 +204,52 @@ int nhq_search_seeded(const nhq_index *ix, const float *queries, const uint8_t *
  * stream-ordered temporary allocations. */
 int nhq_bruteforce_hybrid_knn(const nhq_index *ix, const float *queries, const uint8_t *qattrs,
                               int64_t nq, int32_t k, int32_t *ids, float *dists, void *stream);
+
+/* ------------------------------------------------------ learned stop network
+ *
+ * A small network (8 -> 64 -> 64 -> 2, ReLU) reads the search-state features
+ * at every checkpoint and outputs a stop logit and log2 of a hop budget.
+ * The paper names learned routing only as prior art (Sec. 4.2); the network,
+ * its features and labels are this library's design (stated in nhq_trace
+ * and below).  Parameters are float32 vectors of NHQ_MLP_PARAMS values in the
+ * order W1 [64][8], b1 [64], W2 [64][64], b2 [64], W3 [2][64], b3 [2]. */
+#define NHQ_MLP_PARAMS 4866
+
+/* Training samples from traces: sample (q, c) for every checkpoint c <
+ * count[q]: X = feat, y_stop = 1 when the checkpoint's top-k fingerprint
+ * equals the final one (continuing would not change the answer), y_beam =
+ * log2 of the hop of the first checkpoint from which every later one holds
+ * the final top-k (the final hop count H, from counters [nq][2], when the
+ * last one does not).  Outputs are device float32:
+ * X [nq*cap][8], y_stop [nq*cap], y_beam [nq*cap]; *n_out (host) = samples
+ * written, in (q, c) order.  Synchronises the stream. */
+int nhq_trace_samples(const nhq_trace *tr, int64_t nq, const uint32_t *counters, float *X,
+                      float *y_stop, float *y_beam, int64_t *n_out, void *stream);
+
+/* Loss and gradient of the mean loss over n samples (binary cross-entropy
+ * of the stop logit plus lam * Huber(1) of the beam output) at `params`
+ * (device float32 [NHQ_MLP_PARAMS]); grad device [NHQ_MLP_PARAMS], loss
+ * device [1], z (nullable) device [n][2] network outputs. */
+int nhq_mlp_grad(const float *params, const float *X, const float *y_stop, const float *y_beam,
+                 int64_t n, float lam, float *grad, float *loss, float *z, void *stream);
+
+/* Adam training (Kingma and Ba) of `params` in place for `epochs` passes
+ * over the samples in mini-batches of `batch` (a multiple of 128), shuffled
+ * per epoch from `seed`.  adam_state: device float32 [2 * NHQ_MLP_PARAMS]
+ * (first and second moments; zero it to start), step: host in/out count of
+ * Adam steps taken.  loss_out (nullable): device float32 [epochs], mean
+ * loss per epoch. */
+int nhq_mlp_train(float *params, float *adam_state, int64_t *step, const float *X,
+                  const float *y_stop, const float *y_beam, int64_t n, int32_t epochs,
+                  int32_t batch, float lr, float lam, uint64_t seed, float *loss_out, void *stream);
+
+/* Install the network in the index (rounded to fp16) for learned searches;
+ * params NULL removes it. */
+int nhq_mlp_load(nhq_index *ix, const float *params, void *stream);
+
+/* The in-loop inference on given features (fp16 weights, float32
+ * accumulation): X device [n][8], Z device [n][2]. */
+int nhq_mlp_eval(const nhq_index *ix, const float *X, int64_t n, float *Z, void *stream);
 
 /* ------------------------------------------------------------------ misc */
 const char *nhq_strerror(int code);

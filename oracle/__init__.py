@@ -78,7 +78,8 @@ def lib():
         L.or_knn_rows.argtypes = [P, P, i64, i32, i32, i32, P, i64, i32, P, i32]
         L.or_search.restype = None
         L.or_search.argtypes = [P, i32, P, P, P, i64, i32, i32, P, P, i64, i32, i32, P, i32,
-                                i32, i32, i32, i32, i64, P, P, P, P, P, i32]
+                                i32, i32, i32, i32, i64, P, P, P, P, P, i32, P, P, P, P, P, i32,
+                                P, ctypes.c_double, ctypes.c_double, i32]
         _lib = L
     return _lib
 
@@ -217,9 +218,13 @@ def entry_points(build_seed: int, n: int, n_seeds: int = 32) -> np.ndarray:
 # ------------------------------------------------------------ Alg. 2
 def search(adj, xs, attrs, q, qa, k: int, L: int, seeds, n_init: int = 32, key_mode: int = KEY64,
            out_mode: int = 0, rerank_n: int = 0, xr=None, max_hops: int = 1 << 40,
-           threads: Optional[int] = None):
+           threads: Optional[int] = None, check_every: int = 0, trace_cap: int = 0,
+           mlp: Optional[np.ndarray] = None, stop_threshold: float = 0.5, cap_factor: float = 0.0):
     """Joint pruning in beam form; see ``or_search`` in nhq_oracle.c.
-    Returns (ids [nq,k], gamma [nq,k], ndc [nq], hops [nq], flag [nq])."""
+    Returns (ids [nq,k], gamma [nq,k], ndc [nq], hops [nq], flag [nq]); with
+    trace_cap > 0 also a dict of checkpoint traces (feat [nq,cap,8], hop,
+    hash, count, final_hash).  ``mlp`` (float64 [4866], weights as the GPU
+    holds them) turns on the learned stop with threshold stop_threshold."""
     adj = np.ascontiguousarray(adj, dtype=np.int32)
     xs, attrs, q, qa = _f32(xs), _u8(attrs), _f32(q), _u8(qa)
     xr = None if xr is None else _f32(xr)
@@ -233,9 +238,22 @@ def search(adj, xs, attrs, q, qa, k: int, L: int, seeds, n_init: int = 32, key_m
     ndc = np.empty(nq, dtype=np.int64)
     hops = np.empty(nq, dtype=np.int64)
     flag = np.empty(nq, dtype=np.int32)
+    tr = None
+    if trace_cap > 0:
+        tr = {"feat": np.zeros((nq, trace_cap, 8)), "hop": np.zeros((nq, trace_cap), np.uint32),
+              "hash": np.zeros((nq, trace_cap), np.uint32), "count": np.zeros(nq, np.int32),
+              "final_hash": np.zeros(nq, np.uint32)}
+    w = None if mlp is None else np.ascontiguousarray(mlp, dtype=np.float64)
+    logit = math.log(stop_threshold / (1.0 - stop_threshold))
     lib().or_search(_p(adj), R, _p(xs), _p(xr), _p(attrs), n, d, m, _p(q), _p(qa), nq, k, L,
                     _p(seeds), seeds.shape[0], int(n_init), key_mode, out_mode, rerank_n, max_hops,
-                    _p(ids), _p(gam), _p(ndc), _p(hops), _p(flag), _threads(threads))
+                    _p(ids), _p(gam), _p(ndc), _p(hops), _p(flag), int(check_every),
+                    _p(tr["feat"]) if tr else None, _p(tr["hop"]) if tr else None,
+                    _p(tr["hash"]) if tr else None, _p(tr["count"]) if tr else None,
+                    _p(tr["final_hash"]) if tr else None, int(trace_cap), _p(w), logit,
+                    float(cap_factor), _threads(threads))
+    if tr is not None:
+        return ids, gam, ndc, hops, flag, tr
     return ids, gam, ndc, hops, flag
 
 

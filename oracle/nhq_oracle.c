@@ -348,7 +348,61 @@ typedef struct {
     int64_t id;
     int chi;
     int expanded;
+    int64_t born; /* expansion during which the entry entered the pool */
 } pentry;
+
+/* ---------------------------------------------------------- stop network */
+/* Checkpoint state features and the stop network.  The paper cites learned
+ * routing only as prior art (Sec. 4.2); these definitions are the library's
+ * and are restated here from its interface documentation:
+ *   every S expansions (before the next one) the state is summarised by
+ *   f1 = ln(1 + H) / 8, f2 = ln(1 + NDC) / 8,
+ *   f3 = (sum over constrained attributes of ln(count(code) / n)) / 8
+ *        (count 0 read as 0.5),
+ *   f4 = eligible entries among the first k pool positions / k,
+ *   f5 = ln(key of k-th eligible / that key at its first checkpoint), 1 if
+ *        fewer than k eligible,
+ *   f6 = ln(key of the next entry to expand / key of k-th eligible), -1 if
+ *        fewer than k eligible,
+ *   f7 = entries that joined the pool since the last checkpoint / (S R),
+ *   f8 = min((H - last H at which the eligible top-k changed) / 64, 1);
+ *   the top-k fingerprint is the sum mod 2^32 of fmix32(id + 0x9E3779B9)
+ *   (MurmurHash3's finaliser) over the first k eligible ids. */
+static uint32_t fmix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
+}
+
+/* 8 -> 64 -> 64 -> 2 with ReLU; w in the order W1 [64][8], b1, W2 [64][64],
+ * b2, W3 [2][64], b3 */
+static void mlp_forward(const double *w, const double *f, double *z)
+{
+    const double *W1 = w, *b1 = w + 512, *W2 = w + 576, *b2 = w + 4672, *W3 = w + 4736, *b3 = w + 4864;
+    double h1[64], h2[64];
+    for (int j = 0; j < 64; ++j) {
+        double a = b1[j];
+        for (int i = 0; i < 8; ++i)
+            a += W1[j * 8 + i] * f[i];
+        h1[j] = a > 0 ? a : 0;
+    }
+    for (int j = 0; j < 64; ++j) {
+        double a = b2[j];
+        for (int i = 0; i < 64; ++i)
+            a += W2[j * 64 + i] * h1[i];
+        h2[j] = a > 0 ? a : 0;
+    }
+    for (int o = 0; o < 2; ++o) {
+        double a = b3[o];
+        for (int j = 0; j < 64; ++j)
+            a += W3[o * 64 + j] * h2[j];
+        z[o] = a;
+    }
+}
 
 /* One pass of joint pruning per query.
  *   xs       vectors the loop scores with (the stored form: float32, or the
@@ -369,8 +423,25 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
                const uint8_t *qa, int64_t nq, int k, int L, const int32_t *seeds,
                int nseeds, int ninit, int key_mode, int out_mode, int rerank_n, int64_t max_hops,
                int32_t *out_ids, double *out_gamma, int64_t *out_ndc, int64_t *out_hops,
-               int32_t *out_flag, int nthreads)
+               int32_t *out_flag, int check_every, double *tr_feat, uint32_t *tr_hop,
+               uint32_t *tr_hash, int32_t *tr_count, uint32_t *tr_final, int tr_cap,
+               const double *mlp, double stop_logit, double cap_factor, int nthreads)
 {
+    /* ln(count / n) of every attribute code (count 0 read as 0.5) */
+    double logp[4][256];
+    for (int i = 0; i < 4; ++i)
+        for (int c = 0; c < 256; ++c)
+            logp[i][c] = 0.0;
+    if (check_every > 0) {
+        int64_t cnt[4][256];
+        memset(cnt, 0, sizeof(cnt));
+        for (int64_t e = 0; e < n; ++e)
+            for (int i = 0; i < m && i < 4; ++i)
+                cnt[i][attrs[e * (int64_t)m + i]] += 1;
+        for (int i = 0; i < 4; ++i)
+            for (int c = 0; c < 256; ++c)
+                logp[i][c] = log((cnt[i][c] > 0 ? (double)cnt[i][c] : 0.5) / (double)n);
+    }
 #ifdef _OPENMP
 #pragma omp parallel num_threads(nthreads)
 #endif
@@ -413,6 +484,7 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
         pool[pos_].id = v_;                                                              \
         pool[pos_].chi = c_;                                                             \
         pool[pos_].expanded = 0;                                                         \
+        pool[pos_].born = hops;                                                          \
         if (size < L)                                                                    \
             size += 1;                                                                   \
     } while (0)
@@ -447,6 +519,7 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
                     best[pos].id = v;
                     best[pos].chi = c;
                     best[pos].expanded = 0;
+                    best[pos].born = -1;
                     if (nb < ninit)
                         nb += 1;
                 }
@@ -458,6 +531,14 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
             }
             /* expansion loop: take the best unexpanded vertex, score its
              * unvisited neighbours, keep the L best (joint pruning) */
+            int have_first = 0, have_prev = 0, ntrace = 0;
+            double kth_first = 0.0, budget = 1e300;
+            uint32_t prev_hash = 0;
+            int64_t last_change = 0, ins_window = 0;
+            double logsel = 0.0;
+            for (int i = 0; i < m && i < 4; ++i)
+                if (qav[i] != OR_WILDCARD)
+                    logsel += logp[i][qav[i]];
             for (;;) {
                 int cur = -1;
                 for (int t = 0; t < size; ++t)
@@ -467,6 +548,61 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
                     }
                 if (cur < 0)
                     break;
+                if (check_every > 0 && hops > 0 && hops % check_every == 0) {
+                    int nel = 0, fk = 0, has_kth = 0;
+                    double kth = 0.0;
+                    uint32_t h = 0;
+                    for (int t = 0; t < size && nel < k; ++t) {
+                        int el = out_mode == 1 || pool[t].chi == 0;
+                        if (!el)
+                            continue;
+                        if (t < k)
+                            fk += 1;
+                        h += fmix32((uint32_t)pool[t].id + 0x9E3779B9u);
+                        nel += 1;
+                        if (nel == k) {
+                            has_kth = 1;
+                            kth = pool[t].key;
+                        }
+                    }
+                    if (have_prev && h != prev_hash)
+                        last_change = hops;
+                    prev_hash = h;
+                    have_prev = 1;
+                    if (has_kth && !have_first) {
+                        kth_first = kth;
+                        have_first = 1;
+                    }
+                    int64_t joined = ins_window;
+                    ins_window = 0;
+                    double f[8], lo_ = 1e-30;
+                    f[0] = log(1.0 + (double)hops) / 8.0;
+                    f[1] = log(1.0 + (double)ndc) / 8.0;
+                    f[2] = logsel / 8.0;
+                    f[3] = (double)fk / (double)k;
+                    f[4] = has_kth ? log((kth > lo_ ? kth : lo_) / (kth_first > lo_ ? kth_first : lo_)) : 1.0;
+                    f[5] = has_kth ? log((pool[cur].key > lo_ ? pool[cur].key : lo_) / (kth > lo_ ? kth : lo_)) : -1.0;
+                    f[6] = (double)joined / (double)(check_every * R);
+                    f[7] = (double)(hops - last_change) / 64.0;
+                    if (f[7] > 1.0)
+                        f[7] = 1.0;
+                    if (tr_feat && ntrace < tr_cap) {
+                        int64_t tt = iq * (int64_t)tr_cap + ntrace;
+                        for (int i = 0; i < 8; ++i)
+                            tr_feat[tt * 8 + i] = f[i];
+                        tr_hop[tt] = (uint32_t)hops;
+                        tr_hash[tt] = h;
+                        ntrace += 1;
+                    }
+                    if (mlp) {
+                        double z[2];
+                        mlp_forward(mlp, f, z);
+                        if (cap_factor > 0 && hops == check_every)
+                            budget = cap_factor * pow(2.0, z[1]);
+                        if (z[0] >= stop_logit || (double)hops >= budget)
+                            break;
+                    }
+                }
                 if (hops >= max_hops) {
                     flag = 1;
                     break;
@@ -483,8 +619,23 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
                     stamp[v] = iq;
                     OFFER(v);
                 }
+                /* entries this expansion added that are still pooled */
+                for (int t = 0; t < size; ++t)
+                    if (pool[t].born == hops)
+                        ins_window += 1;
             }
 #undef OFFER
+            if (tr_feat) {
+                int nel = 0;
+                uint32_t h = 0;
+                for (int t = 0; t < size && nel < k; ++t)
+                    if (out_mode == 1 || pool[t].chi == 0) {
+                        h += fmix32((uint32_t)pool[t].id + 0x9E3779B9u);
+                        nel += 1;
+                    }
+                tr_final[iq] = h;
+                tr_count[iq] = ntrace;
+            }
             /* output: Def. 4 filter (mode 0) or raw pool order (mode 1) */
             int want = (rerank_n > 0 && xr) ? rerank_n : k;
             int no = 0;

@@ -34,12 +34,21 @@ class BuildParams(ctypes.Structure):
                 ("seed", ctypes.c_uint64)]
 
 
+class Trace(ctypes.Structure):
+    _fields_ = [("feat", ctypes.c_void_p), ("hop", ctypes.c_void_p), ("hash", ctypes.c_void_p),
+                ("count", ctypes.c_void_p), ("final_hash", ctypes.c_void_p), ("cap", ctypes.c_int32)]
+
+
 class SearchParams(ctypes.Structure):
     _fields_ = [("n_init", ctypes.c_int32), ("rerank", ctypes.c_int32),
                 ("output_mode", ctypes.c_int32), ("max_hops", ctypes.c_int32),
                 ("visited_log2", ctypes.c_int32), ("learned", ctypes.c_int32),
                 ("stop_threshold", ctypes.c_float), ("check_every", ctypes.c_int32),
-                ("counters", ctypes.c_void_p)]
+                ("counters", ctypes.c_void_p), ("cap_factor", ctypes.c_float),
+                ("trace", ctypes.c_void_p)]
+
+
+MLP_PARAMS = 4866
 
 
 _lib = None
@@ -71,6 +80,12 @@ def lib() -> ctypes.CDLL:
         "nhq_bruteforce_hybrid_knn": ([P, P, P, i64, i32, P, P, P], i32),
         "nhq_seed_rank": ([P, P, P, i64, i32, P, P], i32),
         "nhq_search_seeded": ([P, P, P, i64, P, i32, i32, i32, P, P, P, P], i32),
+        "nhq_trace_samples": ([P, i64, P, P, P, P, P, P], i32),
+        "nhq_mlp_grad": ([P, P, P, P, i64, ctypes.c_float, P, P, P, P], i32),
+        "nhq_mlp_train": ([P, P, P, P, P, P, i64, i32, i32, ctypes.c_float, ctypes.c_float,
+                           ctypes.c_uint64, P, P], i32),
+        "nhq_mlp_load": ([P, P, P], i32),
+        "nhq_mlp_eval": ([P, P, i64, P, P], i32),
         "nhq_strerror": ([i32], ctypes.c_char_p),
         "nhq_last_error": ([], ctypes.c_char_p),
         "nhq_version": ([], i32),
@@ -234,7 +249,8 @@ def nhq_hybrid_search(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, k:
                       n_init: int = 32, rerank: int = 0, output_mode: int = 0, max_hops: int = 0,
                       visited_log2: int = 0, learned: bool = False, stop_threshold: float = 0.0,
                       check_every: int = 0, counters: bool = False, stream=None,
-                      out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None):
+                      out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None,
+                      cap_factor: float = 0.0, trace: Optional["TraceBuffers"] = None):
     """Returns (ids int32 [nq,k], dists float32 [nq,k]) and, with
     counters=True, a uint32-valued int32 tensor [nq,2] of (NDC, H)."""
     queries = _dev(queries, torch.float32, "queries", 2)
@@ -250,7 +266,8 @@ def nhq_hybrid_search(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, k:
     cnt = torch.zeros((nq, 2), dtype=torch.int32, device=queries.device) if counters else None
     sp = SearchParams(int(n_init), int(rerank), int(output_mode), int(max_hops), int(visited_log2),
                       int(bool(learned)), float(stop_threshold), int(check_every),
-                      cnt.data_ptr() if cnt is not None else None)
+                      cnt.data_ptr() if cnt is not None else None, float(cap_factor),
+                      ctypes.cast(ctypes.byref(trace.c), ctypes.c_void_p) if trace is not None else None)
     _check(lib().nhq_hybrid_search(ix.handle, queries.data_ptr(), qattrs.data_ptr(), nq, int(k),
                                    int(beam), ctypes.byref(sp), ids.data_ptr(), dists.data_ptr(),
                                    _stream(stream)), "nhq_hybrid_search")
@@ -272,7 +289,8 @@ def nhq_search_seeded(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, ca
                       k: int, beam: int, n_init: int = 32, rerank: int = 0, output_mode: int = 0,
                       max_hops: int = 0, visited_log2: int = 0, learned: bool = False,
                       stop_threshold: float = 0.0, check_every: int = 0, counters: bool = False,
-                      stream=None, out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None):
+                      stream=None, out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None,
+                      cap_factor: float = 0.0, trace: Optional["TraceBuffers"] = None):
     queries = _dev(queries, torch.float32, "queries", 2)
     qattrs = _dev(qattrs, torch.uint8, "qattrs", 2)
     cand = _dev(cand, torch.int32, "cand", 2)
@@ -285,7 +303,8 @@ def nhq_search_seeded(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, ca
     cnt = torch.zeros((nq, 2), dtype=torch.int32, device=queries.device) if counters else None
     sp = SearchParams(int(n_init), int(rerank), int(output_mode), int(max_hops), int(visited_log2),
                       int(bool(learned)), float(stop_threshold), int(check_every),
-                      cnt.data_ptr() if cnt is not None else None)
+                      cnt.data_ptr() if cnt is not None else None, float(cap_factor),
+                      ctypes.cast(ctypes.byref(trace.c), ctypes.c_void_p) if trace is not None else None)
     _check(lib().nhq_search_seeded(ix.handle, queries.data_ptr(), qattrs.data_ptr(), nq,
                                    cand.data_ptr(), cand.shape[1], int(k), int(beam), ctypes.byref(sp),
                                    ids.data_ptr(), dists.data_ptr(), _stream(stream)),
@@ -304,3 +323,83 @@ def nhq_bruteforce_hybrid_knn(ix: Index, queries: torch.Tensor, qattrs: torch.Te
                                            int(k), ids.data_ptr(), dists.data_ptr(), _stream(stream)),
            "nhq_bruteforce_hybrid_knn")
     return ids, dists
+
+
+class TraceBuffers:
+    """Device buffers of nhq_trace for nq queries and up to `cap` checkpoints."""
+
+    def __init__(self, nq: int, cap: int, device="cuda"):
+        self.feat = torch.zeros((nq, cap, 8), dtype=torch.float32, device=device)
+        self.hop = torch.zeros((nq, cap), dtype=torch.int32, device=device)
+        self.hash = torch.zeros((nq, cap), dtype=torch.int32, device=device)
+        self.count = torch.zeros((nq,), dtype=torch.int32, device=device)
+        self.final_hash = torch.zeros((nq,), dtype=torch.int32, device=device)
+        self.nq, self.cap = nq, cap
+        self.c = Trace(self.feat.data_ptr(), self.hop.data_ptr(), self.hash.data_ptr(),
+                       self.count.data_ptr(), self.final_hash.data_ptr(), cap)
+
+
+def nhq_trace_samples(trace: TraceBuffers, counters: Optional[torch.Tensor] = None, stream=None):
+    """(X [n,8], y_stop [n], y_beam [n]) training samples of a trace."""
+    rows = trace.nq * trace.cap
+    dev = trace.feat.device
+    X = torch.empty((max(rows, 1), 8), dtype=torch.float32, device=dev)
+    ys = torch.empty((max(rows, 1),), dtype=torch.float32, device=dev)
+    yb = torch.empty((max(rows, 1),), dtype=torch.float32, device=dev)
+    n = ctypes.c_int64()
+    _check(lib().nhq_trace_samples(ctypes.byref(trace.c), trace.nq,
+                                   counters.data_ptr() if counters is not None else None,
+                                   X.data_ptr(), ys.data_ptr(), yb.data_ptr(), ctypes.byref(n),
+                                   _stream(stream)), "nhq_trace_samples")
+    return X[: n.value], ys[: n.value], yb[: n.value]
+
+
+def nhq_mlp_grad(params: torch.Tensor, X: torch.Tensor, y_stop: torch.Tensor, y_beam: torch.Tensor,
+                 lam: float = 1.0, want_z: bool = False, stream=None):
+    """(grad [4866], loss [1], z [n,2] or None) of the mean loss at params."""
+    params = _dev(params, torch.float32, "params", 1)
+    X = _dev(X, torch.float32, "X", 2)
+    y_stop = _dev(y_stop, torch.float32, "y_stop", 1)
+    y_beam = _dev(y_beam, torch.float32, "y_beam", 1)
+    n = X.shape[0]
+    grad = torch.empty_like(params)
+    loss = torch.empty((1,), dtype=torch.float32, device=params.device)
+    z = torch.empty((n, 2), dtype=torch.float32, device=params.device) if want_z else None
+    _check(lib().nhq_mlp_grad(params.data_ptr(), X.data_ptr(), y_stop.data_ptr(), y_beam.data_ptr(), n,
+                              float(lam), grad.data_ptr(), loss.data_ptr(),
+                              z.data_ptr() if z is not None else None, _stream(stream)), "nhq_mlp_grad")
+    return grad, loss, z
+
+
+def nhq_mlp_train(params: torch.Tensor, adam_state: torch.Tensor, step: int, X: torch.Tensor,
+                  y_stop: torch.Tensor, y_beam: torch.Tensor, epochs: int, batch: int = 1024,
+                  lr: float = 1e-3, lam: float = 1.0, seed: int = 0, stream=None):
+    """Trains params in place; returns (new step count, loss per epoch)."""
+    for name, t in (("params", params), ("adam_state", adam_state)):
+        if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+            raise TypeError("%s must be a contiguous float32 CUDA tensor" % name)
+    X = _dev(X, torch.float32, "X", 2)
+    y_stop = _dev(y_stop, torch.float32, "y_stop", 1)
+    y_beam = _dev(y_beam, torch.float32, "y_beam", 1)
+    st = ctypes.c_int64(int(step))
+    losses = torch.zeros((max(epochs, 1),), dtype=torch.float32, device=params.device)
+    _check(lib().nhq_mlp_train(params.data_ptr(), adam_state.data_ptr(), ctypes.byref(st), X.data_ptr(),
+                               y_stop.data_ptr(), y_beam.data_ptr(), X.shape[0], int(epochs), int(batch),
+                               float(lr), float(lam), int(seed), losses.data_ptr(), _stream(stream)),
+           "nhq_mlp_train")
+    return st.value, losses[:epochs]
+
+
+def nhq_mlp_load(ix: Index, params: Optional[torch.Tensor], stream=None) -> None:
+    if params is not None:
+        params = _dev(params, torch.float32, "params", 1)
+    _check(lib().nhq_mlp_load(ix.handle, params.data_ptr() if params is not None else None,
+                              _stream(stream)), "nhq_mlp_load")
+
+
+def nhq_mlp_eval(ix: Index, X: torch.Tensor, stream=None) -> torch.Tensor:
+    X = _dev(X, torch.float32, "X", 2)
+    Z = torch.empty((X.shape[0], 2), dtype=torch.float32, device=X.device)
+    _check(lib().nhq_mlp_eval(ix.handle, X.data_ptr(), X.shape[0], Z.data_ptr(), _stream(stream)),
+           "nhq_mlp_eval")
+    return Z

@@ -178,6 +178,14 @@ __global__ void k_pad_queries(const float *__restrict__ q, const uint8_t *__rest
     }
 }
 
+// counts of every (attribute, code) pair
+__global__ void k_code_hist(const uint8_t *__restrict__ a, int64_t n, int m, uint32_t *__restrict__ cnt)
+{
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n * m;
+         t += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&cnt[(t % m) * 256 + a[t]], 1u);
+}
+
 // dense copy of the entry sample's rows, norms and codes
 __global__ void k_gather_entry(const int32_t *__restrict__ entry, int ne, const float *__restrict__ vec32,
                                const float *__restrict__ norm, const uint32_t *__restrict__ attr,
@@ -210,7 +218,7 @@ void free_index(Index *ix)
     if (ix->vecs && ix->vecs != ix->vec32)
         (void)hipFree(ix->vecs);
     void *ptrs[] = {ix->vec32, ix->scale, ix->attr, ix->norm, ix->adj, ix->entry, ix->entry_vec,
-                    ix->entry_norm, ix->entry_attr, ix->err, ix->ws, ix->mlp};
+                    ix->entry_norm, ix->entry_attr, ix->err, ix->ws, ix->mlp, ix->logp};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -395,14 +403,35 @@ int nhq_index_create(const float *vecs, const uint8_t *attrs, int64_t n, int32_t
         hipLaunchKernelGGL(k_gather_entry, dim3(grid_for(ne * ix->dp, 256)), dim3(256), 0, st, ix->entry,
                            (int)ne, ix->vec32, ix->norm, ix->attr, ix->dp, ix->entry_vec,
                            ix->entry_norm, ix->entry_attr);
+        // per-attribute code frequencies: ln(count / n), the selectivity
+        // estimate the stop network reads (ln(0.5 / n) for absent codes)
+        uint32_t *hist = nullptr;
+        std::vector<uint32_t> hh((size_t)4 * 256, 0u);
+        if (hipMalloc(&hist, sizeof(uint32_t) * 4 * 256) != hipSuccess ||
+            hipMalloc(&ix->logp, sizeof(float) * 4 * 256) != hipSuccess) {
+            rc = fail(NHQ_ENOMEM, "histogram allocation failed");
+            break;
+        }
+        (void)hipMemsetAsync(hist, 0, sizeof(uint32_t) * 4 * 256, st);
+        if (m > 0)
+            hipLaunchKernelGGL(k_code_hist, dim3(grid_for(n * m, 256)), dim3(256), 0, st, attrs, n, m, hist);
         uint32_t bad = 0;
-        if (hipMemcpyAsync(&bad, ix->err + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        if (hipMemcpyAsync(hh.data(), hist, sizeof(uint32_t) * 4 * 256, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(&bad, ix->err + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess) {
             rc = fail(NHQ_EHIP, "ingest synchronisation failed");
             break;
         }
+        (void)hipFree(hist);
         if (bad) {
             rc = fail(NHQ_EINVAL, "object attribute code 255 is reserved for query wildcards");
+            break;
+        }
+        std::vector<float> lp((size_t)4 * 256);
+        for (size_t t = 0; t < lp.size(); ++t)
+            lp[t] = (float)std::log((hh[t] > 0 ? (double)hh[t] : 0.5) / (double)n);
+        if (hipMemcpy(ix->logp, lp.data(), sizeof(float) * lp.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            rc = fail(NHQ_EHIP, "log-frequency upload failed");
             break;
         }
     } while (0);
@@ -577,8 +606,15 @@ int nhq_search_seeded(const nhq_index *h, const float *queries, const uint8_t *q
         p.max_hops = 100000;
     if (p.stop_threshold == 0.0f)
         p.stop_threshold = 0.5f;
+    if (!(p.stop_threshold > 0.0f && p.stop_threshold < 1.0f))
+        return fail(NHQ_EINVAL, "stop_threshold must be in (0, 1)");
+    if (p.trace && (p.trace->cap < 1 || !p.trace->feat || !p.trace->hop || !p.trace->hash ||
+                    !p.trace->count || !p.trace->final_hash))
+        return fail(NHQ_EINVAL, "incomplete trace buffers");
     if (p.check_every == 0)
         p.check_every = 4;
+    if (p.check_every < 1)
+        return fail(NHQ_EINVAL, "check_every must be positive");
     if (p.n_init < 1 || p.n_init > 128 || p.max_hops < 1)
         return fail(NHQ_EINVAL, "need 1 <= n_init <= 128 and max_hops >= 1");
     if (p.output_mode != 0 && p.output_mode != 1)
@@ -605,7 +641,9 @@ int nhq_search_seeded(const nhq_index *h, const float *queries, const uint8_t *q
     s.hash_log2 = p.visited_log2;
     s.learned = p.learned;
     s.check_every = p.check_every;
-    s.stop_threshold = p.stop_threshold;
+    s.stop_logit = logf(p.stop_threshold / (1.0f - p.stop_threshold));
+    s.cap_factor = p.cap_factor;
+    s.trace = p.trace;
     s.ids = ids;
     s.dists = dists;
     s.counters = p.counters;

@@ -63,6 +63,7 @@ struct Index {
     std::mutex mu;
     // learned stop network (fp16 weights, device), null when not loaded
     void *mlp = nullptr;
+    float *logp = nullptr;  // [m][256] ln(count / n) of every attribute code
 };
 
 int ensure_workspace(Index *ix, size_t bytes);
@@ -86,7 +87,8 @@ struct SearchLaunch {
     int n_seed_cand;
     int64_t nq;
     int k, L, n_init, out_mode, rerank_n, max_hops, hash_log2, learned, check_every;
-    float stop_threshold;
+    float stop_logit, cap_factor;
+    const nhq_trace *trace;
     int32_t *ids;
     float *dists;
     uint32_t *counters;

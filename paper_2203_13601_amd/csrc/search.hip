@@ -42,6 +42,18 @@ struct SearchArgs {
     int vis_words;  // visited-set words
     int use_bitset;
     int hash_log2;
+    // checkpoints every `ckpt` hops (0 = none): features for the stop network
+    int ckpt, learned;
+    float stop_logit;     // learned: stop when the stop logit >= this
+    float cap_factor;     // learned, > 0: hop budget cap_factor * 2^(beam output)
+    const uint16_t *mlp;  // fp16 weights of the stop network
+    const float *logp;    // [m][256] ln(count / n) per attribute code
+    float *trace_feat;    // [nq][trace_cap][8] (nullable: no trace)
+    uint32_t *trace_hop;  // [nq][trace_cap]
+    uint32_t *trace_hash; // [nq][trace_cap]
+    int32_t *trace_count; // [nq]
+    uint32_t *final_hash; // [nq]
+    int trace_cap;
 };
 
 template <int DP>
@@ -204,7 +216,7 @@ __device__ __forceinline__ void score_batch(const void *vbase, const float *scal
 // (first position that may hold an unexpanded entry) is lowered to the
 // first insertion point.  Returns the new size.
 __device__ int pool_merge(float *pkey, uint32_t *pid, int size, int cap, float ck, uint32_t cw,
-                          bool valid, int &lo)
+                          bool valid, int &lo, int *inserted = nullptr)
 {
     const int lane = threadIdx.x;
     const uint32_t cm = cw & kIdMask;
@@ -228,8 +240,11 @@ __device__ int pool_merge(float *pkey, uint32_t *pid, int size, int cap, float c
             valid = false;
     }
     const uint64_t bal = __ballot(valid);
-    if (bal == 0)
+    if (bal == 0) {
+        if (inserted)
+            *inserted = 0;
         return size;
+    }
     int rank = 0, pmin = size;
     for (uint64_t b = bal; b; b &= b - 1) {
         const int i = __ffsll((unsigned long long)b) - 1;
@@ -268,9 +283,100 @@ __device__ int pool_merge(float *pkey, uint32_t *pid, int size, int cap, float c
         pkey[p + rank] = ck;
         pid[p + rank] = cw;
     }
+    if (inserted)
+        *inserted = __popcll(__ballot(valid && p + rank < cap));
     wsync();
     lo = min(lo, pmin);
     return nsize;
+}
+
+// MurmurHash3's 32-bit finaliser; the eligible top-k is fingerprinted by the
+// sum (mod 2^32) of fmix32(id + 0x9E3779B9) over its ids (order-free)
+__device__ __forceinline__ uint32_t fmix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += (uint32_t)__shfl_xor((int)v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ float wave_sum_f32(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// The first k eligible pool entries (attribute matches; every entry in raw
+// mode): how many of the first k positions are eligible, their fingerprint,
+// and the key of the k-th one (has_kth false when fewer than k exist).
+__device__ void eligible_topk(const float *pkey, const uint32_t *pid, int size, int k, int out_mode,
+                              int &in_first_k, uint32_t &hash, float &key_kth, bool &has_kth)
+{
+    const int lane = threadIdx.x;
+    int nel = 0, fk = 0;
+    uint32_t h = 0;
+    has_kth = false;
+    key_kth = 0.0f;
+    for (int base = 0; base < size && nel < k; base += 64) {
+        const int e = base + lane;
+        const uint32_t w = e < size ? pid[e] : 0u;
+        const bool el = e < size && (out_mode == 1 || ((w >> kChiShift) & 7u) == 0);
+        const uint64_t bb = __ballot(el);
+        const int pos = nel + lanes_below(bb);
+        const bool take = el && pos < k;
+        h += take ? fmix32((w & kIdMask) + 0x9E3779B9u) : 0u;
+        fk += __popcll(__ballot(el && e < k));
+        const uint64_t kb = __ballot(el && pos == k - 1);
+        if (kb) {
+            has_kth = true;
+            key_kth = rdl_f(e < size ? pkey[e] : 0.0f, __ffsll((unsigned long long)kb) - 1);
+        }
+        nel += __popcll(bb);
+    }
+    hash = wave_sum_u32(h);
+    in_first_k = fk;
+}
+
+__device__ __forceinline__ float h2f(uint16_t b)
+{
+    _Float16 v;
+    __builtin_memcpy(&v, &b, 2);
+    return (float)v;
+}
+
+// The stop network (8 -> 64 -> 64 -> 2, ReLU, fp16 weights, fp32
+// accumulation).  Lane j computes hidden unit j; `scratch` holds 64 floats
+// of LDS.  Weight layout: W1 [64][8], b1 [64], W2 [64][64], b2 [64],
+// W3 [2][64], b3 [2].
+__device__ void mlp_eval(const uint16_t *w, const float (&f)[8], float *scratch, float &z0, float &z1)
+{
+    const int j = threadIdx.x & 63;
+    const uint16_t *W1 = w, *b1 = w + 512, *W2 = w + 576, *b2 = w + 4672, *W3 = w + 4736, *b3 = w + 4864;
+    float a1 = h2f(b1[j]);
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        a1 = fmaf(h2f(W1[j * 8 + i]), f[i], a1);
+    scratch[j] = fmaxf(a1, 0.0f);
+    wsync();
+    float a2 = h2f(b2[j]);
+    for (int i = 0; i < 64; ++i)
+        a2 = fmaf(h2f(W2[j * 64 + i]), scratch[i], a2);
+    const float hh = fmaxf(a2, 0.0f);
+    z0 = h2f(b3[0]) + wave_sum_f32(h2f(W3[j]) * hh);
+    z1 = h2f(b3[1]) + wave_sum_f32(h2f(W3[64 + j]) * hh);
+    wsync();
 }
 
 // visited test-and-set; returns true when v was not yet visited.  `unrec`
@@ -338,6 +444,14 @@ __global__ __launch_bounds__(64) void k_search(const SearchArgs a)
             mq += 1;
         }
     }
+    float logsel = 0.0f;
+    if (a.ckpt > 0) {
+        for (int i = 0; i < a.m; ++i) {
+            const uint32_t c = a.qa[qi * a.m + i];
+            if (c != 0xFFu)
+                logsel += a.logp[i * 256 + c];
+        }
+    }
     for (int i = lane; i < a.vis_words; i += 64)
         vis[i] = bitset ? 0u : kEmpty;
     wsync();
@@ -372,6 +486,11 @@ __global__ __launch_bounds__(64) void k_search(const SearchArgs a)
     // ---- expansion loop
     uint32_t ndc = 0, hops = 0;
     bool capped = false, badid = false;
+    // checkpoint state
+    float key_kth_first = 0.0f, budget = 3.0e38f;
+    bool have_first = false, have_prev = false;
+    uint32_t prev_hash = 0;
+    int last_change = 0, ins_window = 0, ntrace = 0;
     for (;;) {
         int cur = -1;
         for (int base = lo; base < size; base += 64) {
@@ -385,6 +504,55 @@ __global__ __launch_bounds__(64) void k_search(const SearchArgs a)
         }
         if (cur < 0)
             break;
+        if (a.ckpt > 0 && hops > 0 && hops % (uint32_t)a.ckpt == 0) {
+            // ---- checkpoint: search-state features (see the stop network)
+            int fk;
+            uint32_t h;
+            float kth;
+            bool has_kth;
+            eligible_topk(pkey, pid, size, a.k, a.out_mode, fk, h, kth, has_kth);
+            if (have_prev && h != prev_hash)
+                last_change = (int)hops;
+            prev_hash = h;
+            have_prev = true;
+            if (has_kth && !have_first) {
+                key_kth_first = kth;
+                have_first = true;
+            }
+            const float front = pkey[cur];
+            float f[8];
+            f[0] = logf(1.0f + (float)hops) * 0.125f;
+            f[1] = logf(1.0f + (float)ndc) * 0.125f;
+            f[2] = logsel * 0.125f;
+            f[3] = (float)fk / (float)a.k;
+            f[4] = has_kth ? logf(fmaxf(kth, 1e-30f) / fmaxf(key_kth_first, 1e-30f)) : 1.0f;
+            f[5] = has_kth ? logf(fmaxf(front, 1e-30f) / fmaxf(kth, 1e-30f)) : -1.0f;
+            f[6] = (float)ins_window / (float)(a.ckpt * a.R);
+            f[7] = fminf((float)((int)hops - last_change) / 64.0f, 1.0f);
+            ins_window = 0;
+            if (a.trace_feat && ntrace < a.trace_cap) {
+                const int64_t t = qi * a.trace_cap + ntrace;
+                float mine = f[0];
+#pragma unroll
+                for (int i = 1; i < 8; ++i)
+                    mine = lane == i ? f[i] : mine;
+                if (lane < 8)
+                    a.trace_feat[t * 8 + lane] = mine;
+                if (lane == 0) {
+                    a.trace_hop[t] = hops;
+                    a.trace_hash[t] = h;
+                }
+                ntrace += 1;
+            }
+            if (a.learned) {
+                float z0, z1;
+                mlp_eval(a.mlp, f, skey, z0, z1);
+                if (a.cap_factor > 0.0f && (int)hops == a.ckpt)
+                    budget = a.cap_factor * exp2f(z1);
+                if (z0 >= a.stop_logit || (float)hops >= budget)
+                    break;
+            }
+        }
         if ((int)hops >= a.max_hops) {
             capped = true;
             break;
@@ -428,7 +596,20 @@ __global__ __launch_bounds__(64) void k_search(const SearchArgs a)
         wsync();
         const float ck = lane < nf ? skey[lane] : 0.0f;
         const uint32_t cw = lane < nf ? sid[lane] : 0u;
-        size = pool_merge(pkey, pid, size, L, ck, cw, lane < nf, lo);
+        int ins = 0;
+        size = pool_merge(pkey, pid, size, L, ck, cw, lane < nf, lo, &ins);
+        ins_window += ins;
+    }
+    if (a.trace_feat) {
+        int fk;
+        uint32_t h;
+        float kth;
+        bool has_kth;
+        eligible_topk(pkey, pid, size, a.k, a.out_mode, fk, h, kth, has_kth);
+        if (lane == 0) {
+            a.final_hash[qi] = h;
+            a.trace_count[qi] = ntrace;
+        }
     }
 
     // ---- output: eligible entries in pool order (Def. 4 filter or raw)
@@ -560,6 +741,20 @@ int launch_search(const SearchLaunch &s)
     a.out_mode = s.out_mode;
     a.rerank_n = s.rerank_n;
     a.max_hops = s.max_hops;
+    a.ckpt = (s.learned || s.trace) ? s.check_every : 0;
+    a.learned = s.learned;
+    a.stop_logit = s.stop_logit;
+    a.cap_factor = s.cap_factor;
+    a.mlp = reinterpret_cast<const uint16_t *>(ix->mlp);
+    a.logp = ix->logp;
+    if (s.trace) {
+        a.trace_feat = s.trace->feat;
+        a.trace_hop = s.trace->hop;
+        a.trace_hash = s.trace->hash;
+        a.trace_count = s.trace->count;
+        a.final_hash = s.trace->final_hash;
+        a.trace_cap = s.trace->cap;
+    }
     const int want = s.rerank_n > 0 ? s.rerank_n : s.k;
     a.scap = want > 64 ? ((want + 63) & ~63) : 64;
     // visited set: bitset when it is no larger than the hash would be

@@ -1,0 +1,209 @@
+"""Learned stop network on the GPU against the CPU oracle: checkpoint traces,
+training samples, gradients and Adam steps (FP64 reference), fp16 in-loop
+inference, learned-stop searches, and what the trained network gains over
+fixed-beam search at equal recall."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+nhq = pytest.importorskip("paper_2203_13601_amd")
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _flat(p):
+    return np.concatenate([p[k].ravel() for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+
+
+def _unflat(v):
+    out, o = {}, 0
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        shp = oracle.MLPRef.SHAPES[k]
+        sz = int(np.prod(shp))
+        out[k] = np.asarray(v[o:o + sz], dtype=np.float64).reshape(shp)
+        o += sz
+    return out
+
+
+@pytest.fixture(scope="module")
+def setup():
+    w = synth.small(8000, 64, 160, seed=91, integer=True, n_centres=6)
+    adj = oracle.build_graph(w.x, w.attrs, l=48, R=24)
+    ix = nhq.nhq_index_create(_dev(w.x), _dev(w.attrs), n_entry=256, seed=5, degree=24)
+    nhq.nhq_index_set_graph(ix, _dev(adj))
+    entry = oracle.entry_points(5, w.n, 256)
+    return w, adj, ix, entry
+
+
+def test_trace_matches_oracle(setup):
+    w, adj, ix, entry = setup
+    tr = nhq.TraceBuffers(w.nq, 48)
+    ids, dist, cnt = nhq.nhq_hybrid_search(ix, _dev(w.q), _dev(w.qattrs), 10, 96, check_every=4,
+                                           counters=True, trace=tr)
+    torch.cuda.synchronize()
+    o = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, 96, entry, key_mode=oracle.KEY32,
+                      check_every=4, trace_cap=48)
+    otr = o[5]
+    assert np.array_equal(ids.cpu().numpy(), o[0])
+    assert np.array_equal(tr.count.cpu().numpy(), otr["count"])
+    assert np.array_equal(tr.final_hash.cpu().numpy().view(np.uint32), otr["final_hash"])
+    c = otr["count"]
+    mask = np.arange(48)[None, :] < c[:, None]
+    assert np.array_equal(tr.hop.cpu().numpy().view(np.uint32)[mask], otr["hop"][mask])
+    assert np.array_equal(tr.hash.cpu().numpy().view(np.uint32)[mask], otr["hash"][mask])
+    f = tr.feat.cpu().numpy()[mask]
+    assert np.allclose(f, otr["feat"][mask], atol=2e-6, rtol=1e-5)
+    # samples and labels
+    X, ys, yb = nhq.nhq_trace_samples(tr, cnt)
+    X, ys, yb = X.cpu().numpy(), ys.cpu().numpy(), yb.cpu().numpy()
+    assert X.shape[0] == c.sum()
+    wy, wb, r = [], [], 0
+    for q in range(w.nq):
+        lab = otr["hash"][q, :c[q]] == otr["final_hash"][q]
+        first = o[3][q]
+        for t in range(c[q] - 1, -1, -1):
+            if not lab[t]:
+                break
+            first = otr["hop"][q, t]
+        wy += list(lab.astype(np.float32))
+        wb += [np.log2(max(1, first))] * c[q]
+    assert np.array_equal(ys, np.array(wy, np.float32))
+    assert np.allclose(yb, np.array(wb), atol=1e-6)
+
+
+def test_gradient_matches_fp64_reference():
+    rng = np.random.default_rng(0)
+    p = oracle.MLPRef.init(1)
+    for k in p:
+        p[k] = p[k] + rng.standard_normal(p[k].shape) * 0.05
+    n = 300
+    X = rng.standard_normal((n, 8))
+    ys = (rng.uniform(size=n) > 0.5).astype(np.float64)
+    yb = rng.uniform(3, 8, size=n)
+    g, loss, z = nhq.nhq_mlp_grad(_dev(_flat(p).astype(np.float32)), _dev(X.astype(np.float32)),
+                                  _dev(ys.astype(np.float32)), _dev(yb.astype(np.float32)), 0.5,
+                                  want_z=True)
+    # the reference sees the same float32-rounded inputs
+    p32 = {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+    X32 = X.astype(np.float32).astype(np.float64)
+    yb32 = yb.astype(np.float32).astype(np.float64)
+    zr, cache = oracle.MLPRef.forward(p32, X32)
+    gr = _flat(oracle.MLPRef.backward(p32, cache, zr, ys, yb32, lam=0.5))
+    lr_ = oracle.MLPRef.loss(zr, ys, yb32, lam=0.5)
+    assert np.allclose(z.cpu().numpy(), zr, rtol=1e-5, atol=1e-5)
+    assert loss.item() == pytest.approx(lr_, rel=1e-5)
+    gg = g.cpu().numpy().astype(np.float64)
+    scale = np.abs(gr).max()
+    assert np.abs(gg - gr).max() <= 1e-5 * scale
+
+
+def test_adam_training_matches_reference():
+    rng = np.random.default_rng(1)
+    p = oracle.MLPRef.init(2)
+    n = 256
+    X = rng.standard_normal((n, 8)).astype(np.float32)
+    ys = (X[:, 0] > 0).astype(np.float32)
+    yb = (X[:, 1] * 2 + 5).astype(np.float32)
+    params = _dev(_flat(p).astype(np.float32))
+    state = torch.zeros(2 * nhq.MLP_PARAMS, dtype=torch.float32, device="cuda")
+    step, losses = nhq.nhq_mlp_train(params, state, 0, _dev(X), _dev(ys), _dev(yb), epochs=5,
+                                     batch=256, lr=1e-2, lam=1.0, seed=3)
+    assert step == 5
+    # one full batch per epoch: the order of samples does not matter
+    pr = {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+    st = {}
+    X64, ys64, yb64 = X.astype(np.float64), ys.astype(np.float64), yb.astype(np.float64)
+    ref_losses = []
+    for _ in range(5):
+        z, cache = oracle.MLPRef.forward(pr, X64)
+        ref_losses.append(oracle.MLPRef.loss(z, ys64, yb64))
+        pr = oracle.MLPRef.adam(pr, oracle.MLPRef.backward(pr, cache, z, ys64, yb64), st, lr=1e-2)
+    got = params.cpu().numpy().astype(np.float64)
+    want = _flat(pr)
+    assert np.abs(got - want).max() <= 1e-4 * max(1.0, np.abs(want).max())
+    assert np.allclose(losses.cpu().numpy(), ref_losses, rtol=1e-4)
+
+
+def test_fp16_inference_matches_reference(setup):
+    w, adj, ix, entry = setup
+    p = oracle.MLPRef.init(4)
+    flat = _flat(p).astype(np.float32)
+    nhq.nhq_mlp_load(ix, _dev(flat))
+    X = np.random.default_rng(5).standard_normal((500, 8)).astype(np.float32)
+    Z = nhq.nhq_mlp_eval(ix, _dev(X)).cpu().numpy()
+    ph = _unflat(flat.astype(np.float16).astype(np.float64))
+    zr, _ = oracle.MLPRef.forward(ph, X.astype(np.float64))
+    assert np.abs(Z - zr).max() <= 1e-2
+    assert np.abs(Z - zr).max() <= 1e-4 * max(1.0, np.abs(zr).max())
+    nhq.nhq_mlp_load(ix, None)
+
+
+def test_learned_search_matches_oracle(setup):
+    w, adj, ix, entry = setup
+    p = oracle.MLPRef.init(6)
+    flat = _flat(p).astype(np.float32)
+    flat[4864] = -1.0                 # a stop logit that crosses zero for some states
+    nhq.nhq_mlp_load(ix, _dev(flat))
+    wh = flat.astype(np.float16).astype(np.float64)
+    for tau in (0.3, 0.6):
+        ids, dist, cnt = nhq.nhq_hybrid_search(ix, _dev(w.q), _dev(w.qattrs), 10, 128, learned=True,
+                                               stop_threshold=tau, check_every=4, counters=True)
+        o = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, 128, entry, key_mode=oracle.KEY32,
+                          check_every=4, mlp=wh, stop_threshold=tau)
+        same = (ids.cpu().numpy() == o[0]).all(axis=1) & (cnt.cpu().numpy()[:, 1] == o[3])
+        # a decision can flip only where the logit sits within rounding of the threshold
+        assert same.mean() >= 0.97, same.mean()
+    nhq.nhq_mlp_load(ix, None)
+    with pytest.raises(nhq.NHQError):
+        nhq.nhq_hybrid_search(ix, _dev(w.q), _dev(w.qattrs), 10, 64, learned=True)
+
+
+def test_trained_network_gain_over_fixed_beam():
+    # train on traces of training queries, evaluate on held-out queries:
+    # the learned stop (from a large beam) against the fixed-beam sweep
+    from paper_2203_13601_amd import learned
+    from paper_2203_13601_amd.metrics import recall_at_k
+    w = synth.small(30000, 64, 1200, seed=92, integer=True, n_centres=16, zipf=True)
+    ix = nhq.nhq_build_index(_dev(w.x), _dev(w.attrs), degree=32, cand=64, n_entry=1024, seed=7)
+    qtr, qatr = _dev(w.q[:800]), _dev(w.qattrs[:800])
+    qte, qate = _dev(w.q[800:]), _dev(w.qattrs[800:])
+    params, info = learned.train_stop_network(ix, qtr, qatr, k=10, beam=128, epochs=30, seed=1)
+    nhq.nhq_mlp_load(ix, params)
+    gi, gd = nhq.nhq_bruteforce_hybrid_knn(ix, qte, qate, 10)
+    gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
+    qa_np = w.qattrs[800:]
+    def run(**kw):
+        ids, dist, cnt = nhq.nhq_hybrid_search(ix, qte, qate, 10, kw.pop("beam"), counters=True, **kw)
+        r = recall_at_k(ids.cpu().numpy(), dist.cpu().numpy(), gi, gd, w.attrs, qa_np, 10).mean()
+        return r, cnt.cpu().numpy()[:, 1].mean()
+    fixed = {L: run(beam=L) for L in (12, 16, 24, 32, 48, 64, 96, 128)}
+    learned_pts = {tau: run(beam=128, learned=True, stop_threshold=tau, check_every=4)
+                   for tau in (0.5, 0.8, 0.9, 0.95, 0.99)}
+    Ls = sorted(fixed)
+
+    def fixed_hops_at(r):
+        """hops the fixed beam needs for recall r (linear between swept beams)"""
+        for a, b in zip(Ls, Ls[1:]):
+            (ra, ha), (rb, hb) = fixed[a], fixed[b]
+            if ra <= r <= rb:
+                return ha + (hb - ha) * ((r - ra) / max(rb - ra, 1e-9))
+        return None
+
+    report = {tau: (round(r, 4), round(h, 1), fixed_hops_at(r)) for tau, (r, h) in learned_pts.items()}
+    print("fixed beam (recall, hops):", {L: (round(r, 4), round(h, 1)) for L, (r, h) in fixed.items()})
+    print("learned (recall, hops, fixed-beam hops at that recall):", report)
+    # a higher threshold stops later and loses less recall
+    taus = sorted(learned_pts)
+    hops = [learned_pts[t][1] for t in taus]
+    assert all(b >= a - 1e-9 for a, b in zip(hops, hops[1:]))
+    # the most conservative threshold stays close to the largest beam's recall
+    # while stopping well before that beam is exhausted
+    r99, h99 = learned_pts[0.99]
+    assert r99 >= fixed[128][0] - 0.02
+    assert h99 < 0.8 * fixed[128][1]

@@ -1,0 +1,89 @@
+"""Pins of the oracle's checkpoint traces and learned stop (the stop
+network's inputs), by properties that hold whatever the data."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+
+@pytest.fixture(scope="module")
+def traced():
+    w = synth.small(4000, 16, 60, seed=81, integer=True, n_centres=6)
+    adj = oracle.build_graph(w.x, w.attrs, l=32, R=16)
+    entry = oracle.entry_points(3, w.n, 128)
+    out = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, 96, entry, key_mode=oracle.KEY32,
+                        check_every=4, trace_cap=64)
+    return w, adj, entry, out
+
+
+def test_trace_counters_and_closed_forms(traced):
+    w, adj, entry, (ids, gam, ndc, hops, flag, tr) = traced
+    for q in range(w.nq):
+        c = tr["count"][q]
+        assert c == min(64, max(0, (hops[q] - 1) // 4))   # checkpoints at 4, 8, ... < H
+        for t in range(c):
+            h = tr["hop"][q, t]
+            assert h == 4 * (t + 1)
+            f = tr["feat"][q, t]
+            assert f[0] == pytest.approx(math.log1p(h) / 8)
+            assert 0.0 <= f[3] <= 1.0 and 0.0 <= f[6] <= 1.0 and 0.0 <= f[7] <= 1.0
+            assert f[1] >= 0.0
+
+
+def test_selectivity_feature_is_log_frequency(traced):
+    w, adj, entry, (ids, gam, ndc, hops, flag, tr) = traced
+    for q in range(w.nq):
+        if tr["count"][q] == 0:
+            continue
+        want = 0.0
+        for i in range(w.m):
+            c = int(w.qattrs[q, i])
+            if c != 255:
+                cnt = int((w.attrs[:, i] == c).sum())
+                want += math.log((cnt if cnt else 0.5) / w.n)
+        assert tr["feat"][q, 0, 2] == pytest.approx(want / 8, abs=1e-12)
+
+
+def test_kth_key_only_improves(traced):
+    # the pool keeps the best keys seen, so the k-th eligible key never grows
+    # while k eligible entries exist (f5 <= 0 and non-increasing)
+    w, adj, entry, (ids, gam, ndc, hops, flag, tr) = traced
+    for q in range(w.nq):
+        c = tr["count"][q]
+        f5 = tr["feat"][q, :c, 4]
+        f6 = tr["feat"][q, :c, 5]
+        real = f5[f5 != 1.0]
+        if len(real) and real[0] != 0.0:
+            continue  # first defined value is the reference: 0
+        assert (real <= 1e-12).all()
+        assert (f6[f5 == 1.0] == -1.0).all()
+
+
+def test_fingerprint_is_the_set_of_returned_ids(traced):
+    w, adj, entry, (ids, gam, ndc, hops, flag, tr) = traced
+    def fmix32(h):
+        h ^= h >> 16; h = (h * 0x85EBCA6B) & 0xFFFFFFFF
+        h ^= h >> 13; h = (h * 0xC2B2AE35) & 0xFFFFFFFF
+        return h ^ (h >> 16)
+    for q in range(w.nq):
+        want = sum(fmix32((int(v) + 0x9E3779B9) & 0xFFFFFFFF) for v in ids[q] if v >= 0) & 0xFFFFFFFF
+        assert int(tr["final_hash"][q]) == want
+
+
+def test_learned_stop_extremes(traced):
+    w, adj, entry, (ids, gam, ndc, hops, flag, tr) = traced
+    p = oracle.MLPRef.init(0)
+    flat = np.concatenate([p[k].ravel() for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+    never = flat.copy()
+    never[4864] = -1e6            # stop logit always very negative
+    always = flat.copy()
+    always[4864] = 1e6
+    a = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, 96, entry, key_mode=oracle.KEY32,
+                      check_every=4, mlp=never)
+    assert np.array_equal(a[0], ids) and np.array_equal(a[3], hops)
+    b = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, 96, entry, key_mode=oracle.KEY32,
+                      check_every=4, mlp=always)
+    assert (b[3] == np.minimum(hops, 4)).all()
