@@ -62,6 +62,7 @@ def main():
     ap.add_argument("--storage", default="fp32", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--n-entry", type=int, default=4096)
     ap.add_argument("--n-init", type=int, default=32)
+    ap.add_argument("--expand", type=int, default=1, help="vertices expanded per step")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -117,7 +118,7 @@ def main():
         if ev is not None:
             ev[1].record()
         r = nhq.nhq_search_seeded(ix, q, qa, cand, k, beam, n_init=args.n_init, counters=counters,
-                                  out=(ids, dists))
+                                  out=(ids, dists), expand=args.expand)
         if ev is not None:
             ev[2].record()
         return r
@@ -232,6 +233,7 @@ def main():
         "config": {"workload": w.name, "n": w.n, "d": w.d, "m": w.m, "cards": list(w.cards),
                    "queries_per_step": nq, "k": k, "beam": beam, "degree": w.degree,
                    "cand": w.cand, "n_entry": args.n_entry, "n_init": args.n_init,
+                   "expand": args.expand,
                    "storage": args.storage, "recall_at_beam": round(op["recall"], 5),
                    "qps_at_target_interp": None if q_at is None else round(q_at, 1),
                    "build_s": round(build_s, 3), "exact_knn_s": round(gt_s, 3),

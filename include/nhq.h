@@ -110,6 +110,9 @@ typedef struct {
     float cap_factor;    /* learned, > 0: stop at cap_factor * 2^(beam output
                             at the first checkpoint) hops                  [0] */
     const nhq_trace *trace; /* nullable: record checkpoint traces           */
+    int32_t expand;      /* vertices expanded per step: the `expand` best
+                            unexpanded pool entries are expanded together and
+                            their neighbours merged as one batch (1..8)    [1] */
 } nhq_search_params;
 
 /* Device error word bits (accumulated per index; nhq_index_device_error). */

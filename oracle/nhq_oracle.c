@@ -425,8 +425,12 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
                int32_t *out_ids, double *out_gamma, int64_t *out_ndc, int64_t *out_hops,
                int32_t *out_flag, int check_every, double *tr_feat, uint32_t *tr_hop,
                uint32_t *tr_hash, int32_t *tr_count, uint32_t *tr_final, int tr_cap,
-               const double *mlp, double stop_logit, double cap_factor, int nthreads)
+               const double *mlp, double stop_logit, double cap_factor, int expand, int nthreads)
 {
+    if (expand < 1)
+        expand = 1;
+    if (expand > 64)
+        expand = 64;
     /* ln(count / n) of every attribute code (count 0 read as 0.5) */
     double logp[4][256];
     for (int i = 0; i < 4; ++i)
@@ -453,6 +457,8 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
         int ocap = (rerank_n > k ? rerank_n : k) + 1;
         pentry *outl = (pentry *)malloc(sizeof(pentry) * (size_t)ocap);
         pentry *best = (pentry *)malloc(sizeof(pentry) * (size_t)(ninit > 0 ? ninit : 1));
+        int64_t *fresh = (int64_t *)malloc(sizeof(int64_t) * (size_t)expand * (size_t)R + 1);
+        int *selpos = (int *)malloc(sizeof(int) * (size_t)expand);
 #ifdef _OPENMP
 #pragma omp for schedule(dynamic, 1)
 #endif
@@ -461,7 +467,7 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
             const uint8_t *qav = qa + iq * (int64_t)m;
             int mq = or_arity(qav, m);
             int size = 0;
-            int64_t ndc = 0, hops = 0;
+            int64_t ndc = 0, hops = 0, chunk_stamp = 0;
             int flag = 0;
 
             /* score v and offer it to the pool (insertion keeps (key, id) order) */
@@ -484,7 +490,7 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
         pool[pos_].id = v_;                                                              \
         pool[pos_].chi = c_;                                                             \
         pool[pos_].expanded = 0;                                                         \
-        pool[pos_].born = hops;                                                          \
+        pool[pos_].born = chunk_stamp;                                                   \
         if (size < L)                                                                    \
             size += 1;                                                                   \
     } while (0)
@@ -519,7 +525,7 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
                     best[pos].id = v;
                     best[pos].chi = c;
                     best[pos].expanded = 0;
-                    best[pos].born = -1;
+                    best[pos].born = 0;
                     if (nb < ninit)
                         nb += 1;
                 }
@@ -539,16 +545,20 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
             for (int i = 0; i < m && i < 4; ++i)
                 if (qav[i] != OR_WILDCARD)
                     logsel += logp[i][qav[i]];
+            int64_t next_ckpt = check_every;
+            int first_ckpt = 1;
             for (;;) {
-                int cur = -1;
-                for (int t = 0; t < size; ++t)
-                    if (!pool[t].expanded) {
-                        cur = t;
-                        break;
-                    }
-                if (cur < 0)
+                /* the E best unexpanded entries (E = expand), in pool order */
+                int nsel = 0;
+                for (int t = 0; t < size && nsel < expand; ++t)
+                    if (!pool[t].expanded)
+                        selpos[nsel++] = t;
+                if (nsel == 0)
                     break;
-                if (check_every > 0 && hops > 0 && hops % check_every == 0) {
+                int cur = selpos[0];
+                if (check_every > 0 && hops >= next_ckpt) {
+                    while (next_ckpt <= hops)
+                        next_ckpt += check_every;
                     int nel = 0, fk = 0, has_kth = 0;
                     double kth = 0.0;
                     uint32_t h = 0;
@@ -597,32 +607,49 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
                     if (mlp) {
                         double z[2];
                         mlp_forward(mlp, f, z);
-                        if (cap_factor > 0 && hops == check_every)
+                        if (cap_factor > 0 && first_ckpt)
                             budget = cap_factor * pow(2.0, z[1]);
+                        first_ckpt = 0;
                         if (z[0] >= stop_logit || (double)hops >= budget)
                             break;
                     }
+                    first_ckpt = 0;
                 }
                 if (hops >= max_hops) {
                     flag = 1;
                     break;
                 }
-                pool[cur].expanded = 1;
-                hops += 1;
-                int64_t u = pool[cur].id;
-                for (int t = 0; t < R; ++t) {
-                    int64_t v = adj[u * (int64_t)R + t];
-                    if (v < 0 || v >= n)
-                        continue;
-                    if (stamp[v] == iq)
-                        continue;
-                    stamp[v] = iq;
-                    OFFER(v);
+                if (nsel > max_hops - hops)
+                    nsel = (int)(max_hops - hops);
+                int64_t us[64];
+                for (int e = 0; e < nsel; ++e) {
+                    pool[selpos[e]].expanded = 1;
+                    us[e] = pool[selpos[e]].id;
                 }
-                /* entries this expansion added that are still pooled */
-                for (int t = 0; t < size; ++t)
-                    if (pool[t].born == hops)
-                        ins_window += 1;
+                hops += nsel;
+                /* unvisited neighbours of the selected vertices, in (vertex,
+                 * slot) order; each is scored once */
+                int nf = 0;
+                for (int e = 0; e < nsel; ++e)
+                    for (int t = 0; t < R; ++t) {
+                        int64_t v = adj[us[e] * (int64_t)R + t];
+                        if (v < 0 || v >= n)
+                            continue;
+                        if (stamp[v] == iq)
+                            continue;
+                        stamp[v] = iq;
+                        fresh[nf++] = v;
+                    }
+                /* offered to the pool in batches of 64; entries of a batch
+                 * still pooled after it count as joined */
+                for (int c0 = 0; c0 < nf; c0 += 64) {
+                    chunk_stamp += 1;
+                    for (int c = c0; c < nf && c < c0 + 64; ++c)
+                        OFFER(fresh[c]);
+                    for (int t = 0; t < size; ++t)
+                        if (pool[t].born == chunk_stamp)
+                            ins_window += 1;
+                }
             }
 #undef OFFER
             if (tr_feat) {
@@ -677,5 +704,7 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
         free(pool);
         free(outl);
         free(best);
+        free(fresh);
+        free(selpos);
     }
 }

@@ -613,6 +613,10 @@ int nhq_search_seeded(const nhq_index *h, const float *queries, const uint8_t *q
         return fail(NHQ_EINVAL, "incomplete trace buffers");
     if (p.check_every == 0)
         p.check_every = 4;
+    if (p.expand == 0)
+        p.expand = 1;
+    if (p.expand < 1 || p.expand > 8)
+        return fail(NHQ_EINVAL, "expand must be in [1, 8]");
     if (p.check_every < 1)
         return fail(NHQ_EINVAL, "check_every must be positive");
     if (p.n_init < 1 || p.n_init > 128 || p.max_hops < 1)
@@ -643,6 +647,7 @@ int nhq_search_seeded(const nhq_index *h, const float *queries, const uint8_t *q
     s.check_every = p.check_every;
     s.stop_logit = logf(p.stop_threshold / (1.0f - p.stop_threshold));
     s.cap_factor = p.cap_factor;
+    s.expand = p.expand;
     s.trace = p.trace;
     s.ids = ids;
     s.dists = dists;

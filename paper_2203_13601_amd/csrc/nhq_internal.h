@@ -88,6 +88,7 @@ struct SearchLaunch {
     int64_t nq;
     int k, L, n_init, out_mode, rerank_n, max_hops, hash_log2, learned, check_every;
     float stop_logit, cap_factor;
+    int expand;
     const nhq_trace *trace;
     int32_t *ids;
     float *dists;

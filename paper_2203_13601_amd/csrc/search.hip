@@ -15,6 +15,8 @@
 // Ordering key: Gamma = delta * (m_q + chi) / m_q is ordered through
 // key = delta^2 * (m_q + chi)^2 (delta^2 when m_q = 0), one float multiply of
 // the float32 delta^2.  Ties are broken by the smaller id.
+#include <algorithm>
+
 #include "nhq_internal.h"
 
 namespace nhq {
@@ -44,6 +46,7 @@ struct SearchArgs {
     int hash_log2;
     // checkpoints every `ckpt` hops (0 = none): features for the stop network
     int ckpt, learned;
+    int expand;           // vertices expanded per step (1 = Alg. 2 as printed)
     float stop_logit;     // learned: stop when the stop logit >= this
     float cap_factor;     // learned, > 0: hop budget cap_factor * 2^(beam output)
     const uint16_t *mlp;  // fp16 weights of the stop network
@@ -61,7 +64,7 @@ struct Shape {
     static constexpr int G = DP <= 512 ? 8 : 16;           // lanes per row
     static constexpr int NG = 64 / G;                      // rows per round
     static constexpr int NCH = DP / (4 * G);               // 4-element chunks per lane
-    static constexpr int RB = NCH <= 4 ? 4 : (NCH <= 8 ? 2 : 1);  // rounds in flight
+    static constexpr int RB = NCH <= 4 ? 2 : 1;  // rounds in flight
     static_assert(DP % (4 * G) == 0, "padded width must split into lane chunks");
 };
 
@@ -152,13 +155,16 @@ __device__ __forceinline__ float group_sum(float v)
 }
 
 // Score staged candidates sid[0..nf): for each, delta^2 of the query and the
-// row (storage ST), written to out[j] as the ordering key (want_key) or as
-// delta^2.
+// row (storage ST), written to out[j] as the ordering key or as delta^2.
+// mode 0: key, chi taken from the staged word; mode 1: key, chi computed
+// from the attribute word (fetched together with the row) and written into
+// the staged word; mode 2: delta^2.
 template <int DP, int ST>
 __device__ __forceinline__ void score_batch(const void *vbase, const float *scale,
                                             const float4 (&qv)[Shape<DP>::NCH],
-                                            const uint32_t *sid, float *out, int nf, int mq,
-                                            bool want_key)
+                                            uint32_t *sid, float *out, int nf, int mq,
+                                            int mode, const uint32_t *attr = nullptr,
+                                            uint32_t qword = 0, uint32_t qmask = 0)
 {
     using S = Shape<DP>;
     using T = typename Chunk<ST>::T;
@@ -168,11 +174,12 @@ __device__ __forceinline__ void score_batch(const void *vbase, const float *scal
     for (int r0 = 0; r0 < rounds; r0 += S::RB) {
         T buf[S::RB][S::NCH];
         float sc[S::RB];
-        uint32_t w[S::RB];
+        uint32_t w[S::RB], aw[S::RB];
 #pragma unroll
         for (int rr = 0; rr < S::RB; ++rr) {
             const int j = (r0 + rr) * S::NG + gi;
             w[rr] = 0;
+            aw[rr] = 0;
             sc[rr] = 1.0f;
             if (j < nf) {
                 w[rr] = sid[j];
@@ -183,6 +190,8 @@ __device__ __forceinline__ void score_batch(const void *vbase, const float *scal
                     buf[rr][c] = row[g + S::G * c];
                 if (ST == NHQ_STORAGE_FP8)
                     sc[rr] = scale[id];
+                if (mode == 1 && g == 0)
+                    aw[rr] = attr[id];
             }
         }
 #pragma unroll
@@ -203,8 +212,12 @@ __device__ __forceinline__ void score_batch(const void *vbase, const float *scal
             }
             float d2 = group_sum<S::G>(a0 + a1);
             if (j < nf && g == 0) {
-                const int c = (int)((w[rr] >> kChiShift) & 7u);
-                out[j] = want_key ? d2 * key_mult(c, mq) : d2;
+                int c = (int)((w[rr] >> kChiShift) & 7u);
+                if (mode == 1) {
+                    c = chi_of(aw[rr], qword, qmask);
+                    sid[j] = w[rr] | ((uint32_t)c << kChiShift);
+                }
+                out[j] = mode == 2 ? d2 : d2 * key_mult(c, mq);
             }
         }
     }
@@ -405,7 +418,7 @@ __device__ __forceinline__ bool visit(uint32_t *vis, bool bitset, int hash_log2,
     return true;
 }
 
-template <int DP, int ST>
+template <int DP, int ST, bool CK>
 __global__ __launch_bounds__(64) void k_search(const SearchArgs a)
 {
     using S = Shape<DP>;
@@ -445,7 +458,7 @@ __global__ __launch_bounds__(64) void k_search(const SearchArgs a)
         }
     }
     float logsel = 0.0f;
-    if (a.ckpt > 0) {
+    if (CK && a.ckpt > 0) {
         for (int i = 0; i < a.m; ++i) {
             const uint32_t c = a.qa[qi * a.m + i];
             if (c != 0xFFu)
@@ -468,9 +481,9 @@ __global__ __launch_bounds__(64) void k_search(const SearchArgs a)
         const uint64_t vb = __ballot(ok);
         const int ne = __popcll(vb);
         if (ok)
-            sid[lanes_below(vb)] = (uint32_t)v | ((uint32_t)chi_of(a.attr[v], qword, qmask) << kChiShift);
+            sid[lanes_below(vb)] = (uint32_t)v;
         wsync();
-        score_batch<DP, ST>(a.vecs, a.scale, qv, sid, skey, ne, mq, true);
+        score_batch<DP, ST>(a.vecs, a.scale, qv, sid, skey, ne, mq, 1, a.attr, qword, qmask);
         wsync();
         const float ck = lane < ne ? skey[lane] : 0.0f;
         const uint32_t cw = lane < ne ? sid[lane] : 0u;
@@ -491,20 +504,35 @@ __global__ __launch_bounds__(64) void k_search(const SearchArgs a)
     bool have_first = false, have_prev = false;
     uint32_t prev_hash = 0;
     int last_change = 0, ins_window = 0, ntrace = 0;
+    // E = 1: the adjacency row of the runner-up is fetched one hop ahead (it
+    // is the next vertex to expand unless this hop inserts a better one)
+    const int E = a.expand;
+    int64_t pf_id = -1;
+    int pf_nb = -1;
+    uint32_t next_ckpt = (uint32_t)a.ckpt;
+    bool first_ckpt = true;
     for (;;) {
-        int cur = -1;
-        for (int base = lo; base < size; base += 64) {
+        // ---- the E best unexpanded entries (one more, unexpanded, when E = 1)
+        const int want_sel = E == 1 ? 2 : E;
+        int nsel = 0, mysel = -1;
+        for (int base = lo; base < size && nsel < want_sel; base += 64) {
             const int e = base + lane;
             const bool un = e < size && (pid[e] & kExpBit) == 0;
-            const uint64_t bb = __ballot(un);
-            if (bb) {
-                cur = base + __ffsll((unsigned long long)bb) - 1;
-                break;
+            uint64_t bb = __ballot(un);
+            while (bb && nsel < want_sel) {
+                const int pos = base + __ffsll((unsigned long long)bb) - 1;
+                bb &= bb - 1;
+                if (lane == nsel)
+                    mysel = pos;
+                nsel += 1;
             }
         }
-        if (cur < 0)
+        if (nsel == 0)
             break;
-        if (a.ckpt > 0 && hops > 0 && hops % (uint32_t)a.ckpt == 0) {
+        const int cur = rdl_i(mysel, 0);
+        if (CK && a.ckpt > 0 && hops >= next_ckpt) {
+            while (next_ckpt <= hops)
+                next_ckpt += (uint32_t)a.ckpt;
             // ---- checkpoint: search-state features (see the stop network)
             int fk;
             uint32_t h;
@@ -547,60 +575,91 @@ __global__ __launch_bounds__(64) void k_search(const SearchArgs a)
             if (a.learned) {
                 float z0, z1;
                 mlp_eval(a.mlp, f, skey, z0, z1);
-                if (a.cap_factor > 0.0f && (int)hops == a.ckpt)
+                if (a.cap_factor > 0.0f && first_ckpt)
                     budget = a.cap_factor * exp2f(z1);
+                first_ckpt = false;
                 if (z0 >= a.stop_logit || (float)hops >= budget)
                     break;
             }
+            first_ckpt = false;
         }
         if ((int)hops >= a.max_hops) {
             capped = true;
             break;
         }
-        hops += 1;
-        const uint32_t uw = pid[cur];
+        const int nexp = min(min(nsel, E), a.max_hops - (int)hops);
+        // mark the selected entries expanded; lane e holds the e-th vertex id
+        uint32_t myid = 0;
+        if (lane < nexp) {
+            const uint32_t w = pid[mysel];
+            myid = w & kIdMask;
+        }
         wsync();
-        if (lane == 0)
-            pid[cur] = uw | kExpBit;
-        lo = cur + 1;
-        const int64_t u = uw & kIdMask;
-        int nb = -1;
-        if (lane < a.R)
-            nb = a.adj[u * a.R + lane];
-        if (nb >= a.n || nb < -1) {
-            badid = true;
-            nb = -1;
+        if (lane < nexp)
+            pid[mysel] = pid[mysel] | kExpBit;
+        lo = rdl_i(mysel, nexp - 1) + 1;
+        hops += (uint32_t)nexp;
+        // ---- unvisited neighbours of the expanded vertices, in (vertex, slot) order
+        const int total = nexp * a.R;
+        int nf = 0;
+        const int64_t u0 = (int64_t)rdl_u(myid, 0);
+        for (int s0 = 0; s0 < total; s0 += 64) {
+            const int sl = s0 + lane;
+            const int e = min(sl / a.R, nexp - 1), r = sl - (sl / a.R) * a.R;
+            const int64_t u = (int64_t)(uint32_t)__shfl((int)myid, e, 64);
+            int nb = -1;
+            if (sl < total)
+                nb = (E == 1 && pf_id == u0) ? pf_nb : a.adj[u * a.R + r];
+            if (nb >= a.n || nb < -1) {
+                badid = true;
+                nb = -1;
+            }
+            bool fresh = false, unrec = false;
+            if (nb >= 0)
+                fresh = visit(vis, bitset, a.hash_log2, (uint32_t)nb, unrec);
+            // a vertex the hash could not record may repeat in this step
+            uint64_t ub = __ballot(unrec);
+            if (ub) {
+                for (uint64_t b = ub; b; b &= b - 1) {
+                    const int i = __ffsll((unsigned long long)b) - 1;
+                    if (unrec && lane > i && nb == rdl_i(nb, i))
+                        fresh = false;
+                }
+                if (s0 > 0)
+                    for (int i = 0; i < nf; ++i)
+                        if (unrec && (uint32_t)nb == sid[i])
+                            fresh = false;
+            }
+            const uint64_t fb = __ballot(fresh);
+            if (fresh)
+                sid[nf + lanes_below(fb)] = (uint32_t)nb;
+            nf += __popcll(fb);
         }
-        bool fresh = false, unrec = false;
-        if (nb >= 0)
-            fresh = visit(vis, bitset, a.hash_log2, (uint32_t)nb, unrec);
-        // a vertex the hash could not record may repeat inside this batch
-        uint64_t ub = __ballot(unrec);
-        while (ub) {
-            const int i = __ffsll((unsigned long long)ub) - 1;
-            ub &= ub - 1;
-            if (unrec && lane > i && nb == rdl_i(nb, i))
-                fresh = false;
+        if (E == 1) {
+            pf_id = -1;
+            if (nsel > 1) {
+                pf_id = pid[rdl_i(mysel, 1)] & kIdMask;
+                pf_nb = lane < a.R ? a.adj[pf_id * a.R + lane] : -1;
+            }
         }
-        const uint64_t fb = __ballot(fresh);
-        const int nf = __popcll(fb);
         if (nf == 0)
             continue;
-        if (fresh) {
-            const int c = chi_of(a.attr[nb], qword, qmask);
-            sid[lanes_below(fb)] = (uint32_t)nb | ((uint32_t)c << kChiShift);
-        }
         wsync();
         ndc += nf;
-        score_batch<DP, ST>(a.vecs, a.scale, qv, sid, skey, nf, mq, true);
+        score_batch<DP, ST>(a.vecs, a.scale, qv, sid, skey, nf, mq, 1, a.attr, qword, qmask);
         wsync();
-        const float ck = lane < nf ? skey[lane] : 0.0f;
-        const uint32_t cw = lane < nf ? sid[lane] : 0u;
-        int ins = 0;
-        size = pool_merge(pkey, pid, size, L, ck, cw, lane < nf, lo, &ins);
-        ins_window += ins;
+        for (int c0 = 0; c0 < nf; c0 += 64) {
+            const int j = c0 + lane;
+            const bool v = j < nf;
+            const float ck = v ? skey[j] : 0.0f;
+            const uint32_t cw = v ? sid[j] : 0u;
+            int ins = 0;
+            size = pool_merge(pkey, pid, size, L, ck, cw, v, lo, &ins);
+            if (CK)
+                ins_window += ins;
+        }
     }
-    if (a.trace_feat) {
+    if (CK && a.trace_feat) {
         int fk;
         uint32_t h;
         float kth;
@@ -628,7 +687,7 @@ __global__ __launch_bounds__(64) void k_search(const SearchArgs a)
     got = min(got, want);
     wsync();
     // delta^2 from the float32 copy (identical to the loop's for fp32 storage)
-    score_batch<DP, NHQ_STORAGE_FP32>(a.vec32, nullptr, qv, sid, skey, got, mq, false);
+    score_batch<DP, NHQ_STORAGE_FP32>(a.vec32, nullptr, qv, sid, skey, got, mq, 2);
     wsync();
     // final order into LDS (the pool is no longer needed), then one store
     // per output slot
@@ -683,7 +742,7 @@ __global__ __launch_bounds__(64) void k_search(const SearchArgs a)
 template <int DP, int ST>
 int launch_one(const SearchArgs &a, size_t lds, hipStream_t st)
 {
-    auto kern = k_search<DP, ST>;
+    auto kern = a.ckpt > 0 ? k_search<DP, ST, true> : k_search<DP, ST, false>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -742,6 +801,7 @@ int launch_search(const SearchLaunch &s)
     a.rerank_n = s.rerank_n;
     a.max_hops = s.max_hops;
     a.ckpt = (s.learned || s.trace) ? s.check_every : 0;
+    a.expand = s.expand;
     a.learned = s.learned;
     a.stop_logit = s.stop_logit;
     a.cap_factor = s.cap_factor;
@@ -755,7 +815,7 @@ int launch_search(const SearchLaunch &s)
         a.final_hash = s.trace->final_hash;
         a.trace_cap = s.trace->cap;
     }
-    const int want = s.rerank_n > 0 ? s.rerank_n : s.k;
+    const int want = std::max(s.rerank_n > 0 ? s.rerank_n : s.k, s.expand * ix->degree);
     a.scap = want > 64 ? ((want + 63) & ~63) : 64;
     // visited set: bitset when it is no larger than the hash would be
     int hb = s.hash_log2;

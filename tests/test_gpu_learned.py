@@ -207,3 +207,20 @@ def test_trained_network_gain_over_fixed_beam():
     r99, h99 = learned_pts[0.99]
     assert r99 >= fixed[128][0] - 0.02
     assert h99 < 0.8 * fixed[128][1]
+
+
+def test_trace_with_multi_expansion_matches_oracle(setup):
+    w, adj, ix, entry = setup
+    tr = nhq.TraceBuffers(w.nq, 48)
+    ids, dist, cnt = nhq.nhq_hybrid_search(ix, _dev(w.q), _dev(w.qattrs), 10, 96, check_every=4,
+                                           counters=True, trace=tr, expand=3)
+    o = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, 96, entry, key_mode=oracle.KEY32,
+                      check_every=4, trace_cap=48, expand=3)
+    otr = o[5]
+    assert np.array_equal(ids.cpu().numpy(), o[0])
+    assert np.array_equal(tr.count.cpu().numpy(), otr["count"])
+    c = otr["count"]
+    mask = np.arange(48)[None, :] < c[:, None]
+    assert np.array_equal(tr.hop.cpu().numpy().view(np.uint32)[mask], otr["hop"][mask])
+    assert np.array_equal(tr.hash.cpu().numpy().view(np.uint32)[mask], otr["hash"][mask])
+    assert np.allclose(tr.feat.cpu().numpy()[mask], otr["feat"][mask], atol=2e-6, rtol=1e-5)

@@ -219,3 +219,31 @@ def test_seed_rank_is_the_exact_best_of_the_entry_sample(n_entry, n_cand):
         got = cand[i]
         assert sorted(got[got >= 0].tolist()) == sorted(want[i][want[i] >= 0].tolist())
         assert (got >= 0).sum() == min(n_cand, ne)
+
+
+@pytest.mark.parametrize("expand,L", [(2, 64), (4, 100), (8, 256), (3, 17)])
+def test_multi_expansion_matches_oracle(int_set, expand, L):
+    # E best unexpanded entries expanded per step: ids, NDC and hops exact
+    w, adj = int_set
+    ix = _index(w, adj, n_entry=256)
+    entry = oracle.entry_points(w.build_seed, w.n, 256)
+    ids, dist, cnt = _gpu(ix, w, 10, L, expand=expand)
+    oi, og, ondc, ohops, _ = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, L, entry,
+                                           key_mode=oracle.KEY32, expand=expand)
+    assert np.array_equal(ids, oi)
+    assert np.array_equal(cnt[:, 0], ondc)
+    assert np.array_equal(cnt[:, 1], ohops)
+
+
+def test_multi_expansion_with_hash_visited_set():
+    w = synth.small(40000, 32, 48, seed=56, integer=True, n_centres=4)
+    adj = synth.random_graph(w.n, 24, seed=11, pad_frac=0.25)
+    ix = _index(w, adj, n_entry=128)
+    entry = oracle.entry_points(w.build_seed, w.n, 128)
+    for E, hb in ((4, 10), (2, 12)):
+        ids, dist, cnt = _gpu(ix, w, 10, 96, expand=E, visited_log2=hb)
+        oi, og, ondc, ohops, _ = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, 96, entry,
+                                               key_mode=oracle.KEY32, expand=E)
+        assert np.array_equal(ids, oi)
+        assert (cnt[:, 0] >= ondc).all()
+        assert np.array_equal(cnt[:, 1], ohops)

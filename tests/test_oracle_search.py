@@ -170,3 +170,24 @@ def test_rerank_uses_the_exact_vectors():
                 assert gv == pytest.approx(oracle.delta(w.q[i], w.x[v]), rel=1e-12)
         g = [x for x in gam[i] if np.isfinite(x)]
         assert g == sorted(g)
+
+
+def test_multi_expansion_is_exhaustive_with_a_large_beam():
+    w = synth.small(400, 12, 25, seed=39, wildcard_arity=True)
+    adj = synth.random_graph(w.n, 6, seed=3)
+    adj[:, 0] = (np.arange(w.n) + 1) % w.n
+    seeds = oracle.entry_points(9, w.n, 32)
+    gt, gd, _ = oracle.bruteforce(w.x, w.attrs, w.q, w.qattrs, 10)
+    for E in (1, 2, 5):
+        ids, gam, ndc, hops, _ = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, 512, seeds,
+                                               expand=E)
+        assert oracle.recall(ids, w.x, w.attrs, w.q, w.qattrs, gt, gd, 10).min() == 1.0
+        assert (ndc == w.n - 32).all() and (hops == w.n).all()
+
+
+def test_example2_with_two_expansions_per_step():
+    g, names, idx, x, attrs, adj, q, qa = _ex2()
+    seeds = np.array([idx[s] for s in g["seeds"]], np.int32)
+    ids, gam, ndc, hops, flag = oracle.search(adj, x, attrs, q, qa, k=1, L=2, seeds=seeds, n_init=1,
+                                              expand=2)
+    assert names[ids[0, 0]] == "u5"
