@@ -61,8 +61,8 @@ def main():
     ap.add_argument("--beam", type=int, default=0, help="fixed beam (skip the choice)")
     ap.add_argument("--storage", default="fp32", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--n-entry", type=int, default=4096)
-    ap.add_argument("--n-init", type=int, default=32)
-    ap.add_argument("--expand", type=int, default=1, help="vertices expanded per step")
+    ap.add_argument("--n-init", type=int, default=16)
+    ap.add_argument("--expand", type=int, default=4, help="vertices expanded per step")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -137,7 +137,7 @@ def main():
 
     # ---- beam sweep (Recall@10 vs QPS)
     sweep = []
-    beams = [args.beam] if args.beam else [10, 16, 24, 32, 48, 64, 96, 128, 256, 512]
+    beams = [args.beam] if args.beam else [10, 16, 24, 32, 40, 48, 56, 64, 96, 128, 256, 512]
     for beam in beams:
         if beam < k:
             continue

@@ -151,30 +151,38 @@ __global__ __launch_bounds__(64) void k_to_fp8(const float *__restrict__ v, uint
     }
 }
 
-__global__ void k_pad_queries(const float *__restrict__ q, const uint8_t *__restrict__ qa,
-                              int64_t nq, int d, int dp, int m, float *__restrict__ qpad,
-                              float *__restrict__ qnorm, uint32_t *__restrict__ qword,
-                              uint32_t *__restrict__ qmask)
+// one wave per query: zero-padded float32 row (coalesced), squared norm,
+// packed codes and constraint mask
+__global__ __launch_bounds__(64) void k_pad_queries(const float *__restrict__ q,
+                                                    const uint8_t *__restrict__ qa, int64_t nq, int d,
+                                                    int dp, int m, float *__restrict__ qpad,
+                                                    float *__restrict__ qnorm,
+                                                    uint32_t *__restrict__ qword,
+                                                    uint32_t *__restrict__ qmask)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nq;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x;
+    for (int64_t i = blockIdx.x; i < nq; i += gridDim.x) {
         float s = 0.0f;
-        for (int c = 0; c < dp; ++c) {
+        for (int c = lane; c < dp; c += 64) {
             const float v = c < d ? q[i * d + c] : 0.0f;
             qpad[i * dp + c] = v;
             s = fmaf(v, v, s);
         }
-        qnorm[i] = s;
-        uint32_t w = 0, mk = 0;
-        for (int j = 0; j < m; ++j) {
-            const uint32_t c = qa[i * m + j];
-            if (c != 0xFFu) {
-                w |= c << (8 * j);
-                mk |= 0xFFu << (8 * j);
+        for (int o = 32; o > 0; o >>= 1)
+            s += __shfl_xor(s, o, 64);
+        if (lane == 0) {
+            qnorm[i] = s;
+            uint32_t w = 0, mk = 0;
+            for (int j = 0; j < m; ++j) {
+                const uint32_t c = qa[i * m + j];
+                if (c != 0xFFu) {
+                    w |= c << (8 * j);
+                    mk |= 0xFFu << (8 * j);
+                }
             }
+            qword[i] = w;
+            qmask[i] = mk;
         }
-        qword[i] = w;
-        qmask[i] = mk;
     }
 }
 
@@ -231,7 +239,7 @@ int launch_pad_queries(const float *q, const uint8_t *qa, int64_t nq, int d, int
 {
     if (nq == 0)
         return NHQ_OK;
-    hipLaunchKernelGGL(k_pad_queries, dim3(grid_for(nq, 64)), dim3(64), 0, st, q, qa, nq, d, dp, m,
+    hipLaunchKernelGGL(k_pad_queries, dim3(grid_for(nq, 1)), dim3(64), 0, st, q, qa, nq, d, dp, m,
                        qpad, qnorm, qword, qmask);
     NHQ_HIP(hipGetLastError());
     return NHQ_OK;

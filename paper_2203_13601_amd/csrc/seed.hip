@@ -12,6 +12,7 @@
 // radix select on the float bit patterns (keys are non-negative, so their
 // bit patterns order like the values), and writes the positions of the
 // n_cand best by (key, position) -- unordered; the search re-scores them.
+// A bound from the lane minima first cuts the row down to a few candidates.
 #include "nhq_internal.h"
 
 namespace nhq {
@@ -39,78 +40,96 @@ struct KeyArgs {
 };
 
 template <int DP>
+struct KShape {
+    // dims staged per pass: the whole row up to 128, else 64 (or 32)
+    static constexpr int KC = DP <= 128 ? DP : (DP % 64 == 0 ? 64 : 32);
+    static constexpr int NK = DP / KC;
+    static constexpr int NT = KC / 16;   // float4 per lane per point per pass
+    static constexpr int LDSW = KC + 4;  // padded row stride (floats): no bank conflicts
+};
+
+// A workgroup of 4 waves: 64 queries (16 per wave) against 256 entries; the
+// entries' rows are staged through LDS 64 at a time and shared by the waves.
+template <int DP>
 __global__ __launch_bounds__(256) void k_entry_keys(const KeyArgs a)
 {
-    constexpr int NT = DP / 16;
-    constexpr bool ROWS_IN_REGS = NT <= 16;
+    using K = KShape<DP>;
+    __shared__ __align__(16) float tile[64 * K::LDSW];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int rl = lane & 15, lq = lane >> 4;
     const int64_t row = (int64_t)blockIdx.x * 64 + wave * 16 + rl;
     const bool row_ok = row < a.nq;
     const int64_t rowc = row_ok ? row : a.nq - 1;
     const float4 *qrow = reinterpret_cast<const float4 *>(a.qpad + rowc * DP);
-    float4 ra[ROWS_IN_REGS ? NT : 1];
-    if constexpr (ROWS_IN_REGS) {
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-            ra[t] = qrow[4 * t + lq];
-    }
     const float rn = a.qnorm[rowc];
     const uint32_t qw = a.qword[rowc], qm = a.qmask[rowc];
     const float mq = (float)(__popc(qm) / 8);
+    float4 ra[K::NT];
+    if constexpr (K::NK == 1) {
+#pragma unroll
+        for (int t = 0; t < K::NT; ++t)
+            ra[t] = qrow[4 * t + lq];
+    }
     const int cbeg = blockIdx.y * 256;
     for (int c0 = cbeg; c0 < cbeg + 256 && c0 < a.ne_pad; c0 += 64) {
         f32x4 acc[4];
-        const float4 *ecol[4];
-        float4 nrm[4];
-        uint4 atr[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
+        for (int s = 0; s < 4; ++s)
             acc[s] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-            const int col = min(c0 + 16 * s + rl, a.ne - 1);
-            ecol[s] = reinterpret_cast<const float4 *>(a.ev + (int64_t)col * DP);
-            const int cb0 = c0 + 16 * s + 4 * lq;
-            if (cb0 + 3 < a.ne) {
-                nrm[s] = *reinterpret_cast<const float4 *>(a.en + cb0);
-                atr[s] = *reinterpret_cast<const uint4 *>(a.ea + cb0);
-            } else {
-                const int c1 = min(cb0 + 1, a.ne - 1), c2 = min(cb0 + 2, a.ne - 1);
-                const int c3 = min(cb0 + 3, a.ne - 1), cz = min(cb0, a.ne - 1);
-                nrm[s] = make_float4(a.en[cz], a.en[c1], a.en[c2], a.en[c3]);
-                atr[s] = make_uint4(a.ea[cz], a.ea[c1], a.ea[c2], a.ea[c3]);
+        for (int kc = 0; kc < K::NK; ++kc) {
+            // stage 64 entry rows (dims kc*KC .. +KC) into LDS
+            __syncthreads();
+            for (int i = threadIdx.x; i < 64 * (K::KC / 4); i += 256) {
+                const int r = i / (K::KC / 4), c4 = i - r * (K::KC / 4);
+                const int col = min(c0 + r, a.ne - 1);
+                const float4 v = reinterpret_cast<const float4 *>(a.ev + (int64_t)col * DP + kc * K::KC)[c4];
+                *reinterpret_cast<float4 *>(tile + r * K::LDSW + 4 * c4) = v;
             }
-        }
+            __syncthreads();
+            if constexpr (K::NK > 1) {
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            float4 cb[4];
+                for (int t = 0; t < K::NT; ++t)
+                    ra[t] = qrow[kc * (K::KC / 4) + 4 * t + lq];
+            }
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-                cb[s] = ecol[s][4 * t + lq];
-            float4 rv;
-            if constexpr (ROWS_IN_REGS)
-                rv = ra[t];
-            else
-                rv = qrow[4 * t + lq];
+            for (int t = 0; t < K::NT; ++t) {
+                float4 cb[4];
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-                acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[s].x, rv.x, acc[s], 0, 0, 0);
+                for (int s = 0; s < 4; ++s)
+                    cb[s] = *reinterpret_cast<const float4 *>(tile + (16 * s + rl) * K::LDSW + 16 * t + 4 * lq);
+                const float4 rv = ra[t];
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-                acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[s].y, rv.y, acc[s], 0, 0, 0);
+                for (int s = 0; s < 4; ++s)
+                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[s].x, rv.x, acc[s], 0, 0, 0);
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-                acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[s].z, rv.z, acc[s], 0, 0, 0);
+                for (int s = 0; s < 4; ++s)
+                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[s].y, rv.y, acc[s], 0, 0, 0);
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-                acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[s].w, rv.w, acc[s], 0, 0, 0);
+                for (int s = 0; s < 4; ++s)
+                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[s].z, rv.z, acc[s], 0, 0, 0);
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[s].w, rv.w, acc[s], 0, 0, 0);
+            }
         }
         if (!row_ok)
             continue;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int cb0 = c0 + 16 * s + 4 * lq;
-            const float nb4[4] = {nrm[s].x, nrm[s].y, nrm[s].z, nrm[s].w};
-            const uint32_t at4[4] = {atr[s].x, atr[s].y, atr[s].z, atr[s].w};
+            float4 nrm;
+            uint4 atr;
+            if (cb0 + 3 < a.ne) {
+                nrm = *reinterpret_cast<const float4 *>(a.en + cb0);
+                atr = *reinterpret_cast<const uint4 *>(a.ea + cb0);
+            } else {
+                const int c1 = min(cb0 + 1, a.ne - 1), c2 = min(cb0 + 2, a.ne - 1);
+                const int c3 = min(cb0 + 3, a.ne - 1), cz = min(cb0, a.ne - 1);
+                nrm = make_float4(a.en[cz], a.en[c1], a.en[c2], a.en[c3]);
+                atr = make_uint4(a.ea[cz], a.ea[c1], a.ea[c2], a.ea[c3]);
+            }
+            const float nb4[4] = {nrm.x, nrm.y, nrm.z, nrm.w};
+            const uint32_t at4[4] = {atr.x, atr.y, atr.z, atr.w};
             float k4[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -124,67 +143,132 @@ __global__ __launch_bounds__(256) void k_entry_keys(const KeyArgs a)
     }
 }
 
-// sum over the wave
-__device__ __forceinline__ int wave_sum(int v)
+// The K-th smallest bit pattern over T values per lane (one bit at a time
+// from the top; counts by ballot).  Returns p with count(v <= p) >= K and
+// count(v < p) < K, or -- when some prefix holds exactly K values -- the
+// largest pattern under that prefix, so that count(v <= p) == K.
+template <int T>
+__device__ __forceinline__ uint32_t kth_pattern(const uint32_t (&v)[T], int K)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-template <int NJ>
-__global__ __launch_bounds__(64) void k_entry_select(const float *__restrict__ keys, int64_t nq,
-                                                     int ne, int ne_pad, int K, int32_t *__restrict__ cand)
-{
-    const int lane = threadIdx.x;
-    const int64_t qi = blockIdx.x;
-    if (qi >= nq)
-        return;
-    const float *row = keys + qi * ne_pad;
-    uint32_t v[NJ];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j)
-        v[j] = 64 * j + lane < ne ? __float_as_uint(row[64 * j + lane]) : 0xFFFFFFFFu;
-    // the K-th smallest bit pattern, one bit at a time from the top
     uint32_t p = 0;
     int want = K;
     for (int b = 31; b >= 0; --b) {
-        const uint32_t hi = b == 31 ? 0x80000000u : ~((1u << b) - 1u);
+        const uint32_t hi = ~((1u << b) - 1u);
         int cnt = 0;
 #pragma unroll
-        for (int j = 0; j < NJ; ++j)
-            cnt += (v[j] & hi) == p ? 1 : 0;
-        cnt = wave_sum(cnt);
+        for (int t = 0; t < T; ++t)
+            cnt += __popcll(__ballot((v[t] & hi) == p));
+        if (cnt == want) {
+            p |= (1u << b) - 1u;
+            break;
+        }
         if (cnt < want) {
             want -= cnt;
             p |= 1u << b;
         }
     }
-    // p is the K-th smallest pattern: take every smaller one, then the
-    // `want` equal ones with the smallest positions (position = 64 j + lane)
+    return p;
+}
+
+__device__ __forceinline__ int rank_below(uint64_t b)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+}
+
+// Write the K best by (pattern, order): every value below p, then values
+// equal to p in order until K are written.  Element t of lane l is the
+// (64 t + l)-th in order; its position is pos(t); positions >= ne are
+// padding and become -1.
+template <int T, typename Pos>
+__device__ __forceinline__ void emit_best(const uint32_t (&v)[T], Pos pos, uint32_t p, int K, int ne,
+                                          int32_t *__restrict__ out)
+{
     int base = 0;
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        const bool lt = v[j] < p;
+    for (int t = 0; t < T; ++t) {
+        const bool lt = v[t] < p;
         const uint64_t b = __ballot(lt);
         if (lt)
-            cand[qi * K + base + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
-                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u))] = 64 * j + lane;
+            out[base + rank_below(b)] = pos(t);
         base += __popcll(b);
     }
     int left = K - base;
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        const bool eq = v[j] == p && left > 0;
+    for (int t = 0; t < T; ++t) {
+        const bool eq = v[t] == p && left > 0;
         const uint64_t b = __ballot(eq);
-        const int r = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
-        if (eq && r < left)  // padding (only when K > n_entry) becomes -1
-            cand[qi * K + base + r] = 64 * j + lane < ne ? 64 * j + lane : -1;
+        const int r = rank_below(b);
+        if (eq && r < left) {
+            const int ps = pos(t);
+            out[base + r] = ps < ne ? ps : -1;
+        }
         const int took = min(left, __popcll(b));
         base += took;
         left -= took;
     }
+}
+
+// One wave per query.  For K <= 64 the K-th smallest of the 64 lane minima
+// bounds the K-th smallest key from above; the (usually few) keys at or
+// below that bound are compacted in position order into LDS and the exact
+// selection runs over them only.  The selected set and its output order are
+// the same as a selection over the whole row.
+template <int NJ>
+__global__ __launch_bounds__(64) void k_entry_select(const float *__restrict__ keys, int64_t nq,
+                                                     int ne, int ne_pad, int K, int32_t *__restrict__ cand)
+{
+    constexpr int kCap = 256;
+    __shared__ uint32_t sv[kCap];
+    __shared__ int32_t sp[kCap];
+    const int lane = threadIdx.x;
+    const int64_t qi = blockIdx.x;
+    if (qi >= nq)
+        return;
+    const float *row = keys + qi * ne_pad;
+    int32_t *out = cand + qi * K;
+    uint32_t v[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+        v[j] = 64 * j + lane < ne ? __float_as_uint(row[64 * j + lane]) : 0xFFFFFFFFu;
+    if (K <= 64) {
+        uint32_t mn[1] = {v[0]};
+#pragma unroll
+        for (int j = 1; j < NJ; ++j)
+            mn[0] = min(mn[0], v[j]);
+        const uint32_t u = kth_pattern<1>(mn, K);
+        int c = 0;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+            c += __popcll(__ballot(v[j] <= u));
+        if (c <= kCap) {
+            int base = 0;
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const bool in = v[j] <= u;
+                const uint64_t b = __ballot(in);
+                if (in) {
+                    const int r = base + rank_below(b);
+                    sv[r] = v[j];
+                    sp[r] = 64 * j + lane;
+                }
+                base += __popcll(b);
+            }
+            for (int i = base + lane; i < kCap; i += 64) {
+                sv[i] = 0xFFFFFFFFu;
+                sp[i] = -1;
+            }
+            __syncthreads();
+            uint32_t w[kCap / 64];
+#pragma unroll
+            for (int t = 0; t < kCap / 64; ++t)
+                w[t] = sv[64 * t + lane];
+            const uint32_t p = kth_pattern<kCap / 64>(w, K);
+            emit_best<kCap / 64>(w, [&](int t) { return sp[64 * t + lane]; }, p, K, ne, out);
+            return;
+        }
+    }
+    const uint32_t p = kth_pattern<NJ>(v, K);
+    emit_best<NJ>(v, [&](int t) { return 64 * t + lane; }, p, K, ne, out);
 }
 
 }  // namespace

@@ -221,6 +221,31 @@ def test_seed_rank_is_the_exact_best_of_the_entry_sample(n_entry, n_cand):
         assert (got >= 0).sum() == min(n_cand, ne)
 
 
+@pytest.mark.parametrize("distinct,n_cand", [(3, 40), (3, 64), (60, 32), (400, 48)])
+def test_seed_rank_ties_break_by_position(distinct, n_cand):
+    # few distinct vectors: keys tie in large groups, so the selection must
+    # take equal keys by smallest entry position (both the path that cuts
+    # the row down by the lane-minimum bound and the one over the whole row)
+    rng = np.random.default_rng(distinct)
+    base = rng.integers(0, 8, size=(distinct, 32)).astype(np.float32)
+    n = 30000
+    x = base[rng.integers(0, distinct, size=n)]
+    attrs = rng.integers(0, 2, size=(n, 2)).astype(np.uint8)
+    q = base[rng.integers(0, distinct, size=64)] + rng.integers(0, 2, size=(64, 32)).astype(np.float32)
+    qa = rng.integers(0, 2, size=(64, 2)).astype(np.uint8)
+    qa[::5, 1] = 0xFF
+    n_entry = 2048
+    ix = nhq.nhq_index_create(_dev(x), _dev(attrs), n_entry=n_entry, seed=3)
+    cand = nhq.nhq_seed_rank(ix, _dev(q), _dev(qa), n_cand).cpu().numpy()
+    entry = oracle.entry_points(3, n, n_entry)
+    noedge = np.full((n_entry, 1), -1, np.int32)
+    want, _, _, _, _ = oracle.search(noedge, x[entry], attrs[entry], q, qa, n_cand, n_cand,
+                                     np.arange(n_entry, dtype=np.int32), n_init=n_cand,
+                                     key_mode=oracle.KEY32, out_mode=1)
+    for i in range(len(q)):
+        assert sorted(cand[i].tolist()) == sorted(want[i].tolist())
+
+
 @pytest.mark.parametrize("expand,L", [(2, 64), (4, 100), (8, 256), (3, 17)])
 def test_multi_expansion_matches_oracle(int_set, expand, L):
     # E best unexpanded entries expanded per step: ids, NDC and hops exact
