@@ -254,6 +254,105 @@ int nhq_mlp_load(nhq_index *ix, const float *params, void *stream);
  * accumulation): X device [n][8], Z device [n][2]. */
 int nhq_mlp_eval(const nhq_index *ix, const float *X, int64_t n, float *Z, void *stream);
 
+/* ---------------------------------------------------------------- serving
+ *
+ * Continuous batching of hybrid queries (Def. 4, answered as by
+ * nhq_hybrid_search): a server keeps one persistent kernel per memory class
+ * resident on the device.  A class is the largest beam its slots hold and
+ * fixes each slot's LDS (pool, staging, visited set, entry-sample keys); a
+ * slot is one wavefront serving one request at a time.  Requests go to the
+ * smallest class whose beam covers theirs ("admission by memory") and are
+ * taken by the next free slot of that class as soon as they are published,
+ * while the other slots keep working: requests that arrive while others run
+ * share the device with them.  Requests and results travel through pinned
+ * host memory (a ring per class); the caller never synchronises a stream.
+ *
+ * Each request's result depends only on the request, the index and the
+ * server parameters (every slot has its own pool and visited set; the seed
+ * set is the n_cand best of the entry sample, ranked in-wave in float32
+ * direct form, then the search of nhq_search_seeded): the same request gives
+ * bit-identical ids, distances and counters alone or in any mix.
+ *
+ * The server reads the index (which must outlive it and stay unchanged) and
+ * the kernels hold their slots until nhq_server_free.  While a server runs,
+ * do not synchronise the whole device (hipDeviceSynchronize waits for the
+ * persistent kernels); synchronise streams instead.  Every kernel wait is
+ * bounded by the stop flag and by lifetime_s, after which the kernels end
+ * by themselves and later submits fail with NHQ_EDEVICE.  The server calls
+ * are not thread-safe: one host thread drives a server. */
+typedef struct nhq_server nhq_server;
+
+typedef struct {
+    int32_t beam_small;  /* largest beam of the small memory class        [128] */
+    int32_t beam_large;  /* largest beam of the large class; < 0: none     [512] */
+    int32_t slots_small; /* slots (concurrent requests) of the small class;
+                            0 = as many as 60% of the chip holds (30% for the
+                            large class)                                     [0] */
+    int32_t slots_large;
+    int32_t ring;        /* requests submitted and not yet polled, per class
+                            (host ring entries)                           [4096] */
+    int32_t max_k;       /* largest k of a request                          [100] */
+    int32_t n_init;      /* seed set size (as nhq_search_params)             [32] */
+    int32_t expand;      /* vertices expanded per step                        [1] */
+    int32_t rerank;      /* r > 0: rerank the first min(r*k, beam) eligible
+                            entries from the float32 copy                    [0] */
+    int32_t check_every; /* learned stop: checkpoint spacing in hops          [4] */
+    int32_t auto_beam;   /* beam of requests submitted with beam 0, which use
+                            the learned stop (needs nhq_mlp_load)   [beam_small] */
+    int32_t max_hops;    /* expansion cap                               [100000] */
+    float stop_threshold;/* learned stop threshold                          [0.5] */
+    float cap_factor;    /* learned hop budget factor (0 = none)              [0] */
+    double lifetime_s;   /* the kernels end by themselves after this long  [600] */
+} nhq_server_params;
+
+#define NHQ_SERVE_RAW 1 /* request flag: output_mode 1 (first k by Gamma) */
+#define NHQ_PENDING 1   /* nhq_server_poll: the request has not finished */
+
+/* Start a server on the index's device (launches the kernels; synchronises
+ * the device once before launching). */
+int nhq_server_create(nhq_index *ix, const nhq_server_params *params, nhq_server **out);
+
+/* Per class (host arrays of 2; class 1 reads 0 slots when absent): slots,
+ * LDS bytes per slot, largest beam; tick_hz: rate of the device wall clock
+ * that nhq_server_poll's ticks count. */
+int nhq_server_info(const nhq_server *s, int32_t *slots, int32_t *lds_bytes, int32_t *beam_max,
+                    double *tick_hz);
+
+/* Submit one request: q host float32 [d], qattr host uint8 [m] (0xFF =
+ * wildcard), 1 <= k <= min(max_k, beam), beam 0 = learned stop with
+ * auto_beam.  flags: 0 or NHQ_SERVE_RAW.  Returns NHQ_EBUSY (nothing
+ * submitted) when the class's next ring entry still holds an unpolled
+ * request.  *ticket identifies the request for nhq_server_poll. */
+int nhq_server_submit(nhq_server *s, const float *q, const uint8_t *qattr, int32_t k, int32_t beam,
+                      int32_t flags, uint64_t *ticket);
+
+/* Non-blocking: NHQ_PENDING while the request runs; NHQ_OK once it has
+ * finished, with ids host int32 [k] (-1 padded), dists host float32 [k]
+ * (Gamma, +inf padded), counters host uint32 [2] (NDC, hops; nullable) and
+ * ticks host uint64 [2] (device wall clock at the slot's start and end of
+ * the request; nullable).  A ticket can be polled to completion once. */
+int nhq_server_poll(nhq_server *s, uint64_t ticket, int32_t *ids, float *dists, uint32_t *counters,
+                    uint64_t *ticks);
+
+/* Open-loop driver in native code: submits request i at arrival_s[i] seconds
+ * after the call starts (non-decreasing; a request that finds its ring full
+ * waits and keeps its arrival time), polls completions and records
+ * latency_s[i] = time its result was seen - arrival_s[i].  All arrays are
+ * host memory: q [n][d], qattrs [n][m], k [n], beam [n], flags [n]
+ * (nullable), ids [n][max_k], dists [n][max_k] (padded past k), counters
+ * [n][2] and ticks [n][2] (nullable), latency_s [n]; *elapsed_s (nullable)
+ * = wall time until the last result.  Fails with NHQ_EDEVICE after
+ * timeout_s seconds (<= 0: 60). */
+int nhq_server_run(nhq_server *s, const float *q, const uint8_t *qattrs, const int32_t *k,
+                   const int32_t *beam, const int32_t *flags, const double *arrival_s, int64_t n,
+                   int32_t *ids, float *dists, uint32_t *counters, uint64_t *ticks, double *latency_s,
+                   double *elapsed_s, double timeout_s);
+
+/* Stop the kernels (waits up to 30 s for them to end) and release the
+ * server.  Returns NHQ_EDEVICE and keeps the server's memory if the kernels
+ * did not end. */
+int nhq_server_free(nhq_server *s);
+
 /* ------------------------------------------------------------------ misc */
 const char *nhq_strerror(int code);
 const char *nhq_last_error(void);

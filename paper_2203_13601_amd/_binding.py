@@ -49,6 +49,18 @@ class SearchParams(ctypes.Structure):
 
 
 MLP_PARAMS = 4866
+SERVE_RAW = 1
+PENDING = 1
+
+
+class ServerParams(ctypes.Structure):
+    _fields_ = [("beam_small", ctypes.c_int32), ("beam_large", ctypes.c_int32),
+                ("slots_small", ctypes.c_int32), ("slots_large", ctypes.c_int32),
+                ("ring", ctypes.c_int32), ("max_k", ctypes.c_int32), ("n_init", ctypes.c_int32),
+                ("expand", ctypes.c_int32), ("rerank", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("auto_beam", ctypes.c_int32), ("max_hops", ctypes.c_int32),
+                ("stop_threshold", ctypes.c_float), ("cap_factor", ctypes.c_float),
+                ("lifetime_s", ctypes.c_double)]
 
 
 _lib = None
@@ -86,6 +98,12 @@ def lib() -> ctypes.CDLL:
                            ctypes.c_uint64, P, P], i32),
         "nhq_mlp_load": ([P, P, P], i32),
         "nhq_mlp_eval": ([P, P, i64, P, P], i32),
+        "nhq_server_create": ([P, P, P], i32),
+        "nhq_server_info": ([P, P, P, P, P], i32),
+        "nhq_server_submit": ([P, P, P, i32, i32, i32, P], i32),
+        "nhq_server_poll": ([P, ctypes.c_uint64, P, P, P, P], i32),
+        "nhq_server_run": ([P, P, P, P, P, P, P, i64, P, P, P, P, P, P, ctypes.c_double], i32),
+        "nhq_server_free": ([P], i32),
         "nhq_strerror": ([i32], ctypes.c_char_p),
         "nhq_last_error": ([], ctypes.c_char_p),
         "nhq_version": ([], i32),
@@ -407,3 +425,115 @@ def nhq_mlp_eval(ix: Index, X: torch.Tensor, stream=None) -> torch.Tensor:
     _check(lib().nhq_mlp_eval(ix.handle, X.data_ptr(), X.shape[0], Z.data_ptr(), _stream(stream)),
            "nhq_mlp_eval")
     return Z
+
+
+# ------------------------------------------------------------------ serving
+
+def _host(a, dtype, name: str):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data
+
+
+class Server:
+    """Owning handle of an nhq_server (host-side arrays are numpy)."""
+
+    def __init__(self, ix: Index, **params):
+        import numpy as np
+        self._ix = ix
+        p = ServerParams(**params)
+        h = ctypes.c_void_p()
+        _check(lib().nhq_server_create(ix.handle, ctypes.byref(p), ctypes.byref(h)), "nhq_server_create")
+        self._h = h
+        info = nhq_index_info(ix)
+        self.d, self.m = info["d"], info["m"]
+        slots = (ctypes.c_int32 * 2)()
+        lds = (ctypes.c_int32 * 2)()
+        bmax = (ctypes.c_int32 * 2)()
+        hz = ctypes.c_double()
+        _check(lib().nhq_server_info(h, slots, lds, bmax, ctypes.byref(hz)), "nhq_server_info")
+        self.slots, self.lds_bytes, self.beam_max = list(slots), list(lds), list(bmax)
+        self.tick_hz = hz.value
+        self.max_k = params.get("max_k", 0) or 100
+        self._np = np
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("server was freed")
+        return self._h
+
+    def submit(self, q, qa, k: int, beam: int, flags: int = 0) -> int:
+        np = self._np
+        q, qp = _host(q, np.float32, "q")
+        qa, ap = _host(qa, np.uint8, "qattr")
+        if q.shape != (self.d,) or qa.shape != (self.m,):
+            raise ValueError("q must be [d] and qattr [m]")
+        t = ctypes.c_uint64()
+        rc = lib().nhq_server_submit(self.handle, qp, ap, int(k), int(beam), int(flags), ctypes.byref(t))
+        if rc == -7:
+            return -1
+        _check(rc, "nhq_server_submit")
+        return t.value
+
+    def poll(self, ticket: int, k: int):
+        """(ids, dists, counters, ticks) once finished, else None."""
+        np = self._np
+        ids = np.empty(k, np.int32)
+        dists = np.empty(k, np.float32)
+        cnt = np.empty(2, np.uint32)
+        ticks = np.empty(2, np.uint64)
+        rc = lib().nhq_server_poll(self.handle, ctypes.c_uint64(ticket), ids.ctypes.data, dists.ctypes.data,
+                                   cnt.ctypes.data, ticks.ctypes.data)
+        if rc == PENDING:
+            return None
+        _check(rc, "nhq_server_poll")
+        return ids, dists, cnt, ticks
+
+    def run(self, q, qa, k, beam, arrival_s, flags=None, timeout_s: float = 60.0):
+        """Open-loop stream in native code; returns a dict of host arrays."""
+        np = self._np
+        n = len(arrival_s)
+        q, qp = _host(q, np.float32, "q")
+        qa, ap = _host(qa, np.uint8, "qattrs")
+        k, kp = _host(k, np.int32, "k")
+        beam, bp = _host(beam, np.int32, "beam")
+        arr, tp = _host(arrival_s, np.float64, "arrival_s")
+        fp = None
+        if flags is not None:
+            flags, fp = _host(flags, np.int32, "flags")
+        if q.shape != (n, self.d) or qa.shape != (n, self.m) or k.shape != (n,) or beam.shape != (n,):
+            raise ValueError("q [n][d], qattrs [n][m], k [n], beam [n] expected")
+        ids = np.empty((n, self.max_k), np.int32)
+        dists = np.empty((n, self.max_k), np.float32)
+        cnt = np.empty((n, 2), np.uint32)
+        ticks = np.empty((n, 2), np.uint64)
+        lat = np.empty(n, np.float64)
+        el = ctypes.c_double()
+        _check(lib().nhq_server_run(self.handle, qp, ap, kp, bp, fp, tp, n, ids.ctypes.data, dists.ctypes.data,
+                                    cnt.ctypes.data, ticks.ctypes.data, lat.ctypes.data, ctypes.byref(el),
+                                    float(timeout_s)), "nhq_server_run")
+        return {"ids": ids, "dists": dists, "counters": cnt, "ticks": ticks, "latency_s": lat,
+                "elapsed_s": el.value}
+
+    def free(self) -> None:
+        if self._h:
+            rc = lib().nhq_server_free(self._h)
+            self._h = None
+            _check(rc, "nhq_server_free")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.free()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def nhq_server_create(ix: Index, **params) -> Server:
+    return Server(ix, **params)

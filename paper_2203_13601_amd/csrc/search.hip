@@ -15,728 +15,28 @@
 // Ordering key: Gamma = delta * (m_q + chi) / m_q is ordered through
 // key = delta^2 * (m_q + chi)^2 (delta^2 when m_q = 0), one float multiply of
 // the float32 delta^2.  Ties are broken by the smaller id.
-#include <algorithm>
-
-#include "nhq_internal.h"
+#include "search_core.h"
 
 namespace nhq {
 namespace {
 
-struct SearchArgs {
-    const void *vecs;
-    const float *vec32;
-    const float *scale;
-    const uint32_t *attr;
-    const int32_t *adj;
-    const int32_t *seed_cand;  // [nq][n_seed] positions in the entry sample (-1 padded)
-    const int32_t *entry;      // entry sample: position -> vertex id
-    const float *q;
-    const uint8_t *qa;
-    int32_t *out_ids;
-    float *out_dist;
-    uint32_t *counters;
-    uint32_t *err;
-    int64_t n;
-    int64_t nq;
-    int d, m, R, n_seed, n_entry;
-    int k, L, n_init, out_mode, rerank_n, max_hops;
-    int scap;       // staging capacity (entries)
-    int vis_words;  // visited-set words
-    int use_bitset;
-    int hash_log2;
-    // checkpoints every `ckpt` hops (0 = none): features for the stop network
-    int ckpt, learned;
-    int expand;           // vertices expanded per step (1 = Alg. 2 as printed)
-    float stop_logit;     // learned: stop when the stop logit >= this
-    float cap_factor;     // learned, > 0: hop budget cap_factor * 2^(beam output)
-    const uint16_t *mlp;  // fp16 weights of the stop network
-    const float *logp;    // [m][256] ln(count / n) per attribute code
-    float *trace_feat;    // [nq][trace_cap][8] (nullable: no trace)
-    uint32_t *trace_hop;  // [nq][trace_cap]
-    uint32_t *trace_hash; // [nq][trace_cap]
-    int32_t *trace_count; // [nq]
-    uint32_t *final_hash; // [nq]
-    int trace_cap;
-};
-
-template <int DP>
-struct Shape {
-    static constexpr int G = DP <= 512 ? 8 : 16;           // lanes per row
-    static constexpr int NG = 64 / G;                      // rows per round
-    static constexpr int NCH = DP / (4 * G);               // 4-element chunks per lane
-    static constexpr int RB = NCH <= 4 ? 2 : 1;  // rounds in flight
-    static_assert(DP % (4 * G) == 0, "padded width must split into lane chunks");
-};
-
-template <int ST>
-struct Chunk;
-template <>
-struct Chunk<NHQ_STORAGE_FP32> {
-    using T = float4;
-};
-template <>
-struct Chunk<NHQ_STORAGE_BF16> {
-    using T = uint2;
-};
-template <>
-struct Chunk<NHQ_STORAGE_FP8> {
-    using T = uint32_t;
-};
-
-__device__ __forceinline__ void wsync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
-__device__ __forceinline__ int rdl_i(int v, int i) { return __builtin_amdgcn_readlane(v, i); }
-__device__ __forceinline__ uint32_t rdl_u(uint32_t v, int i)
-{
-    return (uint32_t)__builtin_amdgcn_readlane((int)v, i);
-}
-__device__ __forceinline__ float rdl_f(float v, int i)
-{
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
-}
-__device__ __forceinline__ int lanes_below(uint64_t mask)
-{
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
-// number of constrained attribute bytes that differ (Eq. 4-5)
-__device__ __forceinline__ int chi_of(uint32_t a, uint32_t qword, uint32_t qmask)
-{
-    uint32_t x = (a ^ qword) & qmask;
-    uint32_t y = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;
-    return __popc(y & 0x80808080u);
-}
-
-__device__ __forceinline__ float key_mult(int chi, int mq)
-{
-    return mq == 0 ? 1.0f : (float)((mq + chi) * (mq + chi));
-}
-
-__device__ __forceinline__ bool lt_key(float ka, uint32_t ia, float kb, uint32_t ib)
-{
-    return ka < kb || (ka == kb && ia < ib);
-}
-
-template <int ST>
-__device__ __forceinline__ float4 decode(typename Chunk<ST>::T c, float s);
-
-template <>
-__device__ __forceinline__ float4 decode<NHQ_STORAGE_FP32>(float4 c, float)
-{
-    return c;
-}
-template <>
-__device__ __forceinline__ float4 decode<NHQ_STORAGE_BF16>(uint2 c, float)
-{
-    return make_float4(__uint_as_float(c.x << 16), __uint_as_float(c.x & 0xFFFF0000u),
-                       __uint_as_float(c.y << 16), __uint_as_float(c.y & 0xFFFF0000u));
-}
-template <>
-__device__ __forceinline__ float4 decode<NHQ_STORAGE_FP8>(uint32_t c, float s)
-{
-    // OCP e4m3 (gfx950 hardware conversion), then the per-vector scale
-    auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)c, false);
-    auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)c, true);
-    return make_float4(lo[0] * s, lo[1] * s, hi[0] * s, hi[1] * s);
-}
-
-template <int G>
-__device__ __forceinline__ float group_sum(float v)
-{
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1)
-        v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// Score staged candidates sid[0..nf): for each, delta^2 of the query and the
-// row (storage ST), written to out[j] as the ordering key or as delta^2.
-// mode 0: key, chi taken from the staged word; mode 1: key, chi computed
-// from the attribute word (fetched together with the row) and written into
-// the staged word; mode 2: delta^2.
-template <int DP, int ST>
-__device__ __forceinline__ void score_batch(const void *vbase, const float *scale,
-                                            const float4 (&qv)[Shape<DP>::NCH],
-                                            uint32_t *sid, float *out, int nf, int mq,
-                                            int mode, const uint32_t *attr = nullptr,
-                                            uint32_t qword = 0, uint32_t qmask = 0)
-{
-    using S = Shape<DP>;
-    using T = typename Chunk<ST>::T;
-    const int lane = threadIdx.x;
-    const int g = lane % S::G, gi = lane / S::G;
-    const int rounds = (nf + S::NG - 1) / S::NG;
-    for (int r0 = 0; r0 < rounds; r0 += S::RB) {
-        T buf[S::RB][S::NCH];
-        float sc[S::RB];
-        uint32_t w[S::RB], aw[S::RB];
-#pragma unroll
-        for (int rr = 0; rr < S::RB; ++rr) {
-            const int j = (r0 + rr) * S::NG + gi;
-            w[rr] = 0;
-            aw[rr] = 0;
-            sc[rr] = 1.0f;
-            if (j < nf) {
-                w[rr] = sid[j];
-                const int64_t id = w[rr] & kIdMask;
-                const T *row = reinterpret_cast<const T *>(vbase) + id * (DP / 4);
-#pragma unroll
-                for (int c = 0; c < S::NCH; ++c)
-                    buf[rr][c] = row[g + S::G * c];
-                if (ST == NHQ_STORAGE_FP8)
-                    sc[rr] = scale[id];
-                if (mode == 1 && g == 0)
-                    aw[rr] = attr[id];
-            }
-        }
-#pragma unroll
-        for (int rr = 0; rr < S::RB; ++rr) {
-            const int j = (r0 + rr) * S::NG + gi;
-            float a0 = 0.0f, a1 = 0.0f;
-            if (j < nf) {
-#pragma unroll
-                for (int c = 0; c < S::NCH; ++c) {
-                    const float4 x = decode<ST>(buf[rr][c], sc[rr]);
-                    const float t0 = qv[c].x - x.x, t1 = qv[c].y - x.y;
-                    const float t2 = qv[c].z - x.z, t3 = qv[c].w - x.w;
-                    a0 = fmaf(t0, t0, a0);
-                    a1 = fmaf(t1, t1, a1);
-                    a0 = fmaf(t2, t2, a0);
-                    a1 = fmaf(t3, t3, a1);
-                }
-            }
-            float d2 = group_sum<S::G>(a0 + a1);
-            if (j < nf && g == 0) {
-                int c = (int)((w[rr] >> kChiShift) & 7u);
-                if (mode == 1) {
-                    c = chi_of(aw[rr], qword, qmask);
-                    sid[j] = w[rr] | ((uint32_t)c << kChiShift);
-                }
-                out[j] = mode == 2 ? d2 : d2 * key_mult(c, mq);
-            }
-        }
-    }
-}
-
-// Merge one batch of candidates (lane j holds candidate j when `valid`) into
-// the sorted pool of capacity `cap`: the pool becomes the cap best of
-// pool + batch by (key, id).  Candidates already pooled are dropped.  `lo`
-// (first position that may hold an unexpanded entry) is lowered to the
-// first insertion point.  Returns the new size.
-__device__ int pool_merge(float *pkey, uint32_t *pid, int size, int cap, float ck, uint32_t cw,
-                          bool valid, int &lo, int *inserted = nullptr)
-{
-    const int lane = threadIdx.x;
-    const uint32_t cm = cw & kIdMask;
-    if (valid && size >= cap) {
-        const float wk = pkey[cap - 1];
-        const uint32_t wm = pid[cap - 1] & kIdMask;
-        valid = lt_key(ck, cm, wk, wm);
-    }
-    int p = 0;
-    if (valid) {
-        int a0 = 0, a1 = size;
-        while (a0 < a1) {
-            const int mid = (a0 + a1) >> 1;
-            if (lt_key(pkey[mid], pid[mid] & kIdMask, ck, cm))
-                a0 = mid + 1;
-            else
-                a1 = mid;
-        }
-        p = a0;
-        if (p < size && pkey[p] == ck && (pid[p] & kIdMask) == cm)
-            valid = false;
-    }
-    const uint64_t bal = __ballot(valid);
-    if (bal == 0) {
-        if (inserted)
-            *inserted = 0;
-        return size;
-    }
-    int rank = 0, pmin = size;
-    for (uint64_t b = bal; b; b &= b - 1) {
-        const int i = __ffsll((unsigned long long)b) - 1;
-        const float ki = rdl_f(ck, i);
-        const uint32_t mi = rdl_u(cm, i);
-        const int pi = rdl_i(p, i);
-        rank += lt_key(ki, mi, ck, cm) ? 1 : 0;
-        pmin = min(pmin, pi);
-    }
-    const int nv = __popcll(bal);
-    const int nsize = min(cap, size + nv);
-    if (pmin < size) {
-        for (int base = pmin + ((size - 1 - pmin) & ~63); base >= pmin; base -= 64) {
-            const int e = base + lane;
-            const bool act = e < size;
-            float ek = 0.0f;
-            uint32_t ew = 0;
-            if (act) {
-                ek = pkey[e];
-                ew = pid[e];
-            }
-            int sh = 0;
-            for (uint64_t b = bal; b; b &= b - 1) {
-                const int i = __ffsll((unsigned long long)b) - 1;
-                sh += (rdl_i(p, i) <= e) ? 1 : 0;
-            }
-            wsync();
-            if (act && e + sh < cap) {
-                pkey[e + sh] = ek;
-                pid[e + sh] = ew;
-            }
-            wsync();
-        }
-    }
-    if (valid && p + rank < cap) {
-        pkey[p + rank] = ck;
-        pid[p + rank] = cw;
-    }
-    if (inserted)
-        *inserted = __popcll(__ballot(valid && p + rank < cap));
-    wsync();
-    lo = min(lo, pmin);
-    return nsize;
-}
-
-// MurmurHash3's 32-bit finaliser; the eligible top-k is fingerprinted by the
-// sum (mod 2^32) of fmix32(id + 0x9E3779B9) over its ids (order-free)
-__device__ __forceinline__ uint32_t fmix32(uint32_t h)
-{
-    h ^= h >> 16;
-    h *= 0x85EBCA6Bu;
-    h ^= h >> 13;
-    h *= 0xC2B2AE35u;
-    h ^= h >> 16;
-    return h;
-}
-
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        v += (uint32_t)__shfl_xor((int)v, o, 64);
-    return v;
-}
-
-__device__ __forceinline__ float wave_sum_f32(float v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// The first k eligible pool entries (attribute matches; every entry in raw
-// mode): how many of the first k positions are eligible, their fingerprint,
-// and the key of the k-th one (has_kth false when fewer than k exist).
-__device__ void eligible_topk(const float *pkey, const uint32_t *pid, int size, int k, int out_mode,
-                              int &in_first_k, uint32_t &hash, float &key_kth, bool &has_kth)
-{
-    const int lane = threadIdx.x;
-    int nel = 0, fk = 0;
-    uint32_t h = 0;
-    has_kth = false;
-    key_kth = 0.0f;
-    for (int base = 0; base < size && nel < k; base += 64) {
-        const int e = base + lane;
-        const uint32_t w = e < size ? pid[e] : 0u;
-        const bool el = e < size && (out_mode == 1 || ((w >> kChiShift) & 7u) == 0);
-        const uint64_t bb = __ballot(el);
-        const int pos = nel + lanes_below(bb);
-        const bool take = el && pos < k;
-        h += take ? fmix32((w & kIdMask) + 0x9E3779B9u) : 0u;
-        fk += __popcll(__ballot(el && e < k));
-        const uint64_t kb = __ballot(el && pos == k - 1);
-        if (kb) {
-            has_kth = true;
-            key_kth = rdl_f(e < size ? pkey[e] : 0.0f, __ffsll((unsigned long long)kb) - 1);
-        }
-        nel += __popcll(bb);
-    }
-    hash = wave_sum_u32(h);
-    in_first_k = fk;
-}
-
-__device__ __forceinline__ float h2f(uint16_t b)
-{
-    _Float16 v;
-    __builtin_memcpy(&v, &b, 2);
-    return (float)v;
-}
-
-// The stop network (8 -> 64 -> 64 -> 2, ReLU, fp16 weights, fp32
-// accumulation).  Lane j computes hidden unit j; `scratch` holds 64 floats
-// of LDS.  Weight layout: W1 [64][8], b1 [64], W2 [64][64], b2 [64],
-// W3 [2][64], b3 [2].
-__device__ void mlp_eval(const uint16_t *w, const float (&f)[8], float *scratch, float &z0, float &z1)
-{
-    const int j = threadIdx.x & 63;
-    const uint16_t *W1 = w, *b1 = w + 512, *W2 = w + 576, *b2 = w + 4672, *W3 = w + 4736, *b3 = w + 4864;
-    float a1 = h2f(b1[j]);
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-        a1 = fmaf(h2f(W1[j * 8 + i]), f[i], a1);
-    scratch[j] = fmaxf(a1, 0.0f);
-    wsync();
-    float a2 = h2f(b2[j]);
-    for (int i = 0; i < 64; ++i)
-        a2 = fmaf(h2f(W2[j * 64 + i]), scratch[i], a2);
-    const float hh = fmaxf(a2, 0.0f);
-    z0 = h2f(b3[0]) + wave_sum_f32(h2f(W3[j]) * hh);
-    z1 = h2f(b3[1]) + wave_sum_f32(h2f(W3[64 + j]) * hh);
-    wsync();
-}
-
-// visited test-and-set; returns true when v was not yet visited.  `unrec`
-// reports a fresh vertex the hash could not record (table region full).
-__device__ __forceinline__ bool visit(uint32_t *vis, bool bitset, int hash_log2, uint32_t v,
-                                      bool &unrec)
-{
-    unrec = false;
-    if (bitset) {
-        const uint32_t bit = 1u << (v & 31u);
-        const uint32_t old = atomicOr(&vis[v >> 5], bit);
-        return (old & bit) == 0;
-    }
-    const uint32_t slots_mask = (1u << hash_log2) - 1u;
-    uint32_t h = (v * 0x9E3779B1u) >> (32 - hash_log2);
-#pragma unroll 1
-    for (int probe = 0; probe < 16; ++probe) {
-        const uint32_t s = (h + (uint32_t)probe) & slots_mask;
-        const uint32_t old = atomicCAS(&vis[s], kEmpty, v);
-        if (old == kEmpty)
-            return true;
-        if (old == v)
-            return false;
-    }
-    unrec = true;
-    return true;
-}
-
 template <int DP, int ST, bool CK>
 __global__ __launch_bounds__(64) void k_search(const SearchArgs a)
 {
-    using S = Shape<DP>;
     extern __shared__ __align__(16) uint32_t smem[];
-    const int lane = threadIdx.x;
     const int64_t qi = blockIdx.x;
     if (qi >= a.nq)
         return;
-    const int L = a.L;
-    float *pkey = reinterpret_cast<float *>(smem);
-    uint32_t *pid = smem + L;
-    float *skey = reinterpret_cast<float *>(smem + 2 * L);
-    uint32_t *sid = smem + 2 * L + a.scap;
-    uint32_t *vis = smem + 2 * L + 2 * a.scap;
-    const bool bitset = a.use_bitset != 0;
-    const int g = lane % S::G;
-
-    // query slice in registers, query attributes packed like the objects'
-    float4 qv[S::NCH];
-    const float *qp = a.q + qi * (int64_t)a.d;
-#pragma unroll
-    for (int c = 0; c < S::NCH; ++c) {
-        const int e = 4 * (g + S::G * c);
-        qv[c].x = e + 0 < a.d ? qp[e + 0] : 0.0f;
-        qv[c].y = e + 1 < a.d ? qp[e + 1] : 0.0f;
-        qv[c].z = e + 2 < a.d ? qp[e + 2] : 0.0f;
-        qv[c].w = e + 3 < a.d ? qp[e + 3] : 0.0f;
-    }
-    uint32_t qword = 0, qmask = 0;
-    int mq = 0;
-    for (int i = 0; i < a.m; ++i) {
-        const uint32_t c = a.qa[qi * a.m + i];
-        if (c != 0xFFu) {
-            qword |= c << (8 * i);
-            qmask |= 0xFFu << (8 * i);
-            mq += 1;
-        }
-    }
-    float logsel = 0.0f;
-    if (CK && a.ckpt > 0) {
-        for (int i = 0; i < a.m; ++i) {
-            const uint32_t c = a.qa[qi * a.m + i];
-            if (c != 0xFFu)
-                logsel += a.logp[i * 256 + c];
-        }
-    }
-    for (int i = lane; i < a.vis_words; i += 64)
-        vis[i] = bitset ? 0u : kEmpty;
-    wsync();
-
-    // ---- seed set: the n_init best members of the entry sample, re-scored
-    // exactly from the candidates the dense ranking kept
-    int size = 0, lo = 0;
-    const int cap0 = min(a.n_init, L);
-    for (int e0 = 0; e0 < a.n_seed; e0 += 64) {
-        const int e = e0 + lane;
-        const int32_t pos = e < a.n_seed ? a.seed_cand[qi * a.n_seed + e] : -1;
-        const int32_t v = (pos >= 0 && pos < a.n_entry) ? a.entry[pos] : -1;
-        const bool ok = v >= 0 && v < a.n;
-        const uint64_t vb = __ballot(ok);
-        const int ne = __popcll(vb);
-        if (ok)
-            sid[lanes_below(vb)] = (uint32_t)v;
-        wsync();
-        score_batch<DP, ST>(a.vecs, a.scale, qv, sid, skey, ne, mq, 1, a.attr, qword, qmask);
-        wsync();
-        const float ck = lane < ne ? skey[lane] : 0.0f;
-        const uint32_t cw = lane < ne ? sid[lane] : 0u;
-        size = pool_merge(pkey, pid, size, cap0, ck, cw, lane < ne, lo);
-    }
-    for (int e = lane; e < size; e += 64) {
-        bool unrec;
-        visit(vis, bitset, a.hash_log2, pid[e] & kIdMask, unrec);
-    }
-    wsync();
-    lo = 0;
-
-    // ---- expansion loop
-    uint32_t ndc = 0, hops = 0;
-    bool capped = false, badid = false;
-    // checkpoint state
-    float key_kth_first = 0.0f, budget = 3.0e38f;
-    bool have_first = false, have_prev = false;
-    uint32_t prev_hash = 0;
-    int last_change = 0, ins_window = 0, ntrace = 0;
-    // E = 1: the adjacency row of the runner-up is fetched one hop ahead (it
-    // is the next vertex to expand unless this hop inserts a better one)
-    const int E = a.expand;
-    int64_t pf_id = -1;
-    int pf_nb = -1;
-    uint32_t next_ckpt = (uint32_t)a.ckpt;
-    bool first_ckpt = true;
-    for (;;) {
-        // ---- the E best unexpanded entries (one more, unexpanded, when E = 1)
-        const int want_sel = E == 1 ? 2 : E;
-        int nsel = 0, mysel = -1;
-        for (int base = lo; base < size && nsel < want_sel; base += 64) {
-            const int e = base + lane;
-            const bool un = e < size && (pid[e] & kExpBit) == 0;
-            uint64_t bb = __ballot(un);
-            while (bb && nsel < want_sel) {
-                const int pos = base + __ffsll((unsigned long long)bb) - 1;
-                bb &= bb - 1;
-                if (lane == nsel)
-                    mysel = pos;
-                nsel += 1;
-            }
-        }
-        if (nsel == 0)
-            break;
-        const int cur = rdl_i(mysel, 0);
-        if (CK && a.ckpt > 0 && hops >= next_ckpt) {
-            while (next_ckpt <= hops)
-                next_ckpt += (uint32_t)a.ckpt;
-            // ---- checkpoint: search-state features (see the stop network)
-            int fk;
-            uint32_t h;
-            float kth;
-            bool has_kth;
-            eligible_topk(pkey, pid, size, a.k, a.out_mode, fk, h, kth, has_kth);
-            if (have_prev && h != prev_hash)
-                last_change = (int)hops;
-            prev_hash = h;
-            have_prev = true;
-            if (has_kth && !have_first) {
-                key_kth_first = kth;
-                have_first = true;
-            }
-            const float front = pkey[cur];
-            float f[8];
-            f[0] = logf(1.0f + (float)hops) * 0.125f;
-            f[1] = logf(1.0f + (float)ndc) * 0.125f;
-            f[2] = logsel * 0.125f;
-            f[3] = (float)fk / (float)a.k;
-            f[4] = has_kth ? logf(fmaxf(kth, 1e-30f) / fmaxf(key_kth_first, 1e-30f)) : 1.0f;
-            f[5] = has_kth ? logf(fmaxf(front, 1e-30f) / fmaxf(kth, 1e-30f)) : -1.0f;
-            f[6] = (float)ins_window / (float)(a.ckpt * a.R);
-            f[7] = fminf((float)((int)hops - last_change) / 64.0f, 1.0f);
-            ins_window = 0;
-            if (a.trace_feat && ntrace < a.trace_cap) {
-                const int64_t t = qi * a.trace_cap + ntrace;
-                float mine = f[0];
-#pragma unroll
-                for (int i = 1; i < 8; ++i)
-                    mine = lane == i ? f[i] : mine;
-                if (lane < 8)
-                    a.trace_feat[t * 8 + lane] = mine;
-                if (lane == 0) {
-                    a.trace_hop[t] = hops;
-                    a.trace_hash[t] = h;
-                }
-                ntrace += 1;
-            }
-            if (a.learned) {
-                float z0, z1;
-                mlp_eval(a.mlp, f, skey, z0, z1);
-                if (a.cap_factor > 0.0f && first_ckpt)
-                    budget = a.cap_factor * exp2f(z1);
-                first_ckpt = false;
-                if (z0 >= a.stop_logit || (float)hops >= budget)
-                    break;
-            }
-            first_ckpt = false;
-        }
-        if ((int)hops >= a.max_hops) {
-            capped = true;
-            break;
-        }
-        const int nexp = min(min(nsel, E), a.max_hops - (int)hops);
-        // mark the selected entries expanded; lane e holds the e-th vertex id
-        uint32_t myid = 0;
-        if (lane < nexp) {
-            const uint32_t w = pid[mysel];
-            myid = w & kIdMask;
-        }
-        wsync();
-        if (lane < nexp)
-            pid[mysel] = pid[mysel] | kExpBit;
-        lo = rdl_i(mysel, nexp - 1) + 1;
-        hops += (uint32_t)nexp;
-        // ---- unvisited neighbours of the expanded vertices, in (vertex, slot) order
-        const int total = nexp * a.R;
-        int nf = 0;
-        const int64_t u0 = (int64_t)rdl_u(myid, 0);
-        for (int s0 = 0; s0 < total; s0 += 64) {
-            const int sl = s0 + lane;
-            const int e = min(sl / a.R, nexp - 1), r = sl - (sl / a.R) * a.R;
-            const int64_t u = (int64_t)(uint32_t)__shfl((int)myid, e, 64);
-            int nb = -1;
-            if (sl < total)
-                nb = (E == 1 && pf_id == u0) ? pf_nb : a.adj[u * a.R + r];
-            if (nb >= a.n || nb < -1) {
-                badid = true;
-                nb = -1;
-            }
-            bool fresh = false, unrec = false;
-            if (nb >= 0)
-                fresh = visit(vis, bitset, a.hash_log2, (uint32_t)nb, unrec);
-            // a vertex the hash could not record may repeat in this step
-            uint64_t ub = __ballot(unrec);
-            if (ub) {
-                for (uint64_t b = ub; b; b &= b - 1) {
-                    const int i = __ffsll((unsigned long long)b) - 1;
-                    if (unrec && lane > i && nb == rdl_i(nb, i))
-                        fresh = false;
-                }
-                if (s0 > 0)
-                    for (int i = 0; i < nf; ++i)
-                        if (unrec && (uint32_t)nb == sid[i])
-                            fresh = false;
-            }
-            const uint64_t fb = __ballot(fresh);
-            if (fresh)
-                sid[nf + lanes_below(fb)] = (uint32_t)nb;
-            nf += __popcll(fb);
-        }
-        if (E == 1) {
-            pf_id = -1;
-            if (nsel > 1) {
-                pf_id = pid[rdl_i(mysel, 1)] & kIdMask;
-                pf_nb = lane < a.R ? a.adj[pf_id * a.R + lane] : -1;
-            }
-        }
-        if (nf == 0)
-            continue;
-        wsync();
-        ndc += nf;
-        score_batch<DP, ST>(a.vecs, a.scale, qv, sid, skey, nf, mq, 1, a.attr, qword, qmask);
-        wsync();
-        for (int c0 = 0; c0 < nf; c0 += 64) {
-            const int j = c0 + lane;
-            const bool v = j < nf;
-            const float ck = v ? skey[j] : 0.0f;
-            const uint32_t cw = v ? sid[j] : 0u;
-            int ins = 0;
-            size = pool_merge(pkey, pid, size, L, ck, cw, v, lo, &ins);
-            if (CK)
-                ins_window += ins;
-        }
-    }
-    if (CK && a.trace_feat) {
-        int fk;
-        uint32_t h;
-        float kth;
-        bool has_kth;
-        eligible_topk(pkey, pid, size, a.k, a.out_mode, fk, h, kth, has_kth);
-        if (lane == 0) {
-            a.final_hash[qi] = h;
-            a.trace_count[qi] = ntrace;
-        }
-    }
-
-    // ---- output: eligible entries in pool order (Def. 4 filter or raw)
-    const int want = a.rerank_n > 0 ? a.rerank_n : a.k;
-    int got = 0;
-    for (int base = 0; base < size && got < want; base += 64) {
-        const int e = base + lane;
-        const uint32_t w = e < size ? pid[e] : 0u;
-        const bool el = e < size && (a.out_mode == 1 || ((w >> kChiShift) & 7u) == 0);
-        const uint64_t bb = __ballot(el);
-        const int pos = got + lanes_below(bb);
-        if (el && pos < want)
-            sid[pos] = w & ~kExpBit;
-        got += __popcll(bb);
-    }
-    got = min(got, want);
-    wsync();
-    // delta^2 from the float32 copy (identical to the loop's for fp32 storage)
-    score_batch<DP, NHQ_STORAGE_FP32>(a.vec32, nullptr, qv, sid, skey, got, mq, 2);
-    wsync();
-    // final order into LDS (the pool is no longer needed), then one store
-    // per output slot
-    for (int j0 = 0; j0 < got; j0 += 64) {
-        const int j = j0 + lane;
-        if (j < got) {
-            const uint32_t w = sid[j];
-            const int c = (int)((w >> kChiShift) & 7u);
-            const float d2 = skey[j];
-            int slot = j;
-            if (a.rerank_n > 0) {
-                // rank by exact (key, id) among the re-scored entries
-                const float kj = d2 * key_mult(c, mq);
-                const uint32_t ij = w & kIdMask;
-                slot = 0;
-                for (int i = 0; i < got; ++i) {
-                    const uint32_t wi = sid[i];
-                    const float ki = skey[i] * key_mult((int)((wi >> kChiShift) & 7u), mq);
-                    slot += lt_key(ki, wi & kIdMask, kj, ij) ? 1 : 0;
-                }
-            }
-            if (slot < a.k) {
-                const float dl = sqrtf(d2);
-                pid[slot] = w & kIdMask;
-                pkey[slot] = mq == 0 ? dl : dl * ((float)(mq + c) / (float)mq);
-            }
-        }
-    }
-    wsync();
-    const int nout = min(got, a.k);
-    int32_t *oid = a.out_ids + qi * a.k;
-    float *od = a.out_dist + qi * a.k;
-    for (int j0 = 0; j0 < a.k; j0 += 64) {
-        const int j = j0 + lane;
-        if (j < a.k) {
-            oid[j] = j < nout ? (int32_t)pid[j] : -1;
-            od[j] = j < nout ? pkey[j] : __int_as_float(0x7F800000);
-        }
-    }
-    if (lane == 0) {
-        if (a.counters) {
-            a.counters[2 * qi + 0] = ndc;
-            a.counters[2 * qi + 1] = hops;
-        }
-        if (capped)
-            atomicOr(a.err, NHQ_DEVERR_HOPCAP);
-    }
-    if (badid && a.err)
-        atomicOr(a.err, NHQ_DEVERR_BADID);
+    QueryIO io;
+    io.q = a.q + qi * (int64_t)a.d;
+    pack_query_attrs(a.qa + qi * a.m, a.m, io.qword, io.qmask);
+    io.seeds = a.seed_cand + qi * a.n_seed;
+    io.n_seed = a.n_seed;
+    io.oid = a.out_ids + qi * a.k;
+    io.od = a.out_dist + qi * a.k;
+    io.cnt = a.counters ? a.counters + 2 * qi : nullptr;
+    io.trace_row = qi;
+    search_one<DP, ST, CK>(a, io, smem);
 }
 
 template <int DP, int ST>

@@ -14,6 +14,7 @@
 // n_cand best by (key, position) -- unordered; the search re-scores them.
 // A bound from the lane minima first cuts the row down to a few candidates.
 #include "nhq_internal.h"
+#include "wave_select.h"
 
 namespace nhq {
 namespace {
@@ -140,71 +141,6 @@ __global__ __launch_bounds__(256) void k_entry_keys(const KeyArgs a)
             }
             *reinterpret_cast<float4 *>(a.keys + row * a.ne_pad + cb0) = make_float4(k4[0], k4[1], k4[2], k4[3]);
         }
-    }
-}
-
-// The K-th smallest bit pattern over T values per lane (one bit at a time
-// from the top; counts by ballot).  Returns p with count(v <= p) >= K and
-// count(v < p) < K, or -- when some prefix holds exactly K values -- the
-// largest pattern under that prefix, so that count(v <= p) == K.
-template <int T>
-__device__ __forceinline__ uint32_t kth_pattern(const uint32_t (&v)[T], int K)
-{
-    uint32_t p = 0;
-    int want = K;
-    for (int b = 31; b >= 0; --b) {
-        const uint32_t hi = ~((1u << b) - 1u);
-        int cnt = 0;
-#pragma unroll
-        for (int t = 0; t < T; ++t)
-            cnt += __popcll(__ballot((v[t] & hi) == p));
-        if (cnt == want) {
-            p |= (1u << b) - 1u;
-            break;
-        }
-        if (cnt < want) {
-            want -= cnt;
-            p |= 1u << b;
-        }
-    }
-    return p;
-}
-
-__device__ __forceinline__ int rank_below(uint64_t b)
-{
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
-}
-
-// Write the K best by (pattern, order): every value below p, then values
-// equal to p in order until K are written.  Element t of lane l is the
-// (64 t + l)-th in order; its position is pos(t); positions >= ne are
-// padding and become -1.
-template <int T, typename Pos>
-__device__ __forceinline__ void emit_best(const uint32_t (&v)[T], Pos pos, uint32_t p, int K, int ne,
-                                          int32_t *__restrict__ out)
-{
-    int base = 0;
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-        const bool lt = v[t] < p;
-        const uint64_t b = __ballot(lt);
-        if (lt)
-            out[base + rank_below(b)] = pos(t);
-        base += __popcll(b);
-    }
-    int left = K - base;
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-        const bool eq = v[t] == p && left > 0;
-        const uint64_t b = __ballot(eq);
-        const int r = rank_below(b);
-        if (eq && r < left) {
-            const int ps = pos(t);
-            out[base + r] = ps < ne ? ps : -1;
-        }
-        const int took = min(left, __popcll(b));
-        base += took;
-        left -= took;
     }
 }
 

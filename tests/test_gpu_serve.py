@@ -1,0 +1,196 @@
+"""Serving loop (continuous batching) through the C ABI.
+
+- On integer-valued vectors every distance is exact in float32, so a request
+  served by the persistent kernel must give exactly the batch search's ids,
+  distances and counters (same seeds: the n_cand best of the entry sample).
+- Any request gives bit-identical results alone and inside a mixed stream of
+  requests with other k, beams, constraint arities and output modes, whose
+  work overlaps on the device.
+- Admission and failure handling: a full ring refuses a submit, an ended
+  kernel (lifetime reached, forced from the host) fails submits, bad requests
+  are refused.
+
+No GPU call other than the server's is made while a server runs (a device
+synchronisation would wait for its persistent kernels)."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+nhq = pytest.importorskip("paper_2203_13601_amd")
+from paper_2203_13601_amd.learned import init_params  # noqa: E402
+
+LIFE = 60.0
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module")
+def int_index():
+    w = synth.small(20000, 128, 192, seed=61, integer=True, n_centres=8, wildcard_arity=True)
+    ix = nhq.nhq_build_index(_dev(w.x), _dev(w.attrs), degree=32, cand=64, n_entry=1024,
+                             seed=w.build_seed)
+    torch.cuda.synchronize()
+    return w, ix
+
+
+@pytest.fixture(scope="module")
+def float_index():
+    w = synth.small(12000, 96, 160, cards=(2, 3, 5, 10), seed=62, wildcard_arity=True, n_centres=16)
+    ix = nhq.nhq_build_index(_dev(w.x), _dev(w.attrs), degree=32, cand=64, n_entry=512,
+                             seed=w.build_seed)
+    torch.cuda.synchronize()
+    return w, ix
+
+
+def _batch(ix, w, k, beam, **kw):
+    ids, d, cnt = nhq.nhq_hybrid_search(ix, _dev(w.q), _dev(w.qattrs), k, beam, counters=True, **kw)
+    torch.cuda.synchronize()
+    return ids.cpu().numpy(), d.cpu().numpy(), cnt.cpu().numpy().astype(np.uint32)
+
+
+def _alone(srv, q, qa, k, beam, flags):
+    out = []
+    for i in range(len(k)):
+        t = srv.submit(q[i], qa[i], int(k[i]), int(beam[i]), int(flags[i]))
+        assert t >= 0
+        t_end = time.time() + 20.0
+        r = None
+        while r is None:
+            assert time.time() < t_end, "request %d did not finish" % i
+            r = srv.poll(t, int(k[i]))
+        out.append(r)
+    return out
+
+
+@pytest.mark.parametrize("expand", [1, 4])
+def test_serve_equals_batch_search_on_integer_data(int_index, expand):
+    w, ix = int_index
+    cases = [(10, 16), (10, 64), (50, 100), (10, 300)]  # the last uses the large class
+    want = {c: _batch(ix, w, c[0], c[1], n_init=32, expand=expand) for c in cases}
+    n = w.nq
+    rng = np.random.default_rng(7)
+    pick = rng.integers(0, len(cases), size=n)
+    k = np.array([cases[p][0] for p in pick], np.int32)
+    beam = np.array([cases[p][1] for p in pick], np.int32)
+    with nhq.Server(ix, n_init=32, expand=expand, lifetime_s=LIFE, ring=256, slots_small=96,
+                    slots_large=32) as srv:
+        r = srv.run(w.q, w.qattrs, k, beam, np.zeros(n), timeout_s=30.0)
+    for i in range(n):
+        wi, wd, wc = want[cases[pick[i]]]
+        kk = k[i]
+        assert np.array_equal(r["ids"][i, :kk], wi[i]), i
+        assert np.array_equal(r["dists"][i, :kk].view(np.uint32), wd[i].view(np.uint32)), i
+        assert np.array_equal(r["counters"][i], wc[i]), i
+        assert (r["ids"][i, kk:] == -1).all()
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+def test_serve_alone_equals_mix(float_index, storage):
+    w, ix0 = float_index
+    ix = ix0
+    if storage != "fp32":
+        ix = nhq.nhq_index_create(_dev(w.x), _dev(w.attrs), storage=storage, n_entry=512,
+                                  seed=w.build_seed, degree=32)
+        nhq.nhq_index_set_graph(ix, nhq.nhq_index_get_graph(ix0))
+    nhq.nhq_mlp_load(ix, init_params(5))
+    torch.cuda.synchronize()
+    n = w.nq
+    rng = np.random.default_rng(11)
+    k = rng.choice(np.array([1, 10, 50, 100], np.int32), size=n)
+    beam = np.maximum(k, rng.choice(np.array([0, 32, 100, 128, 300, 512], np.int32), size=n)).astype(np.int32)
+    beam[rng.random(n) < 0.15] = 0  # learned stop at the automatic beam
+    flags = (rng.random(n) < 0.2).astype(np.int32) * nhq.SERVE_RAW
+    arrival = synth.poisson_arrivals(n, 200_000.0, 12)
+    with nhq.Server(ix, n_init=16, expand=2, rerank=2, lifetime_s=LIFE, ring=512, slots_small=64,
+                    slots_large=16, auto_beam=128) as srv:
+        mix = srv.run(w.q, w.qattrs, k, beam, arrival, flags=flags, timeout_s=30.0)
+        alone = _alone(srv, w.q, w.qattrs, k, beam, flags)
+        hz = srv.tick_hz
+    for i in range(n):
+        ids, d, cnt, _ = alone[i]
+        assert np.array_equal(mix["ids"][i, :k[i]], ids), i
+        assert np.array_equal(mix["dists"][i, :k[i]].view(np.uint32), d.view(np.uint32)), i
+        assert np.array_equal(mix["counters"][i], cnt), i
+    # the mix really overlapped: requests ran on the device at the same time
+    tb = mix["ticks"][:, 0].astype(np.float64)
+    te = mix["ticks"][:, 1].astype(np.float64)
+    ev = sorted([(t, 1) for t in tb] + [(t, -1) for t in te], key=lambda x: (x[0], x[1]))
+    cur = peak = 0
+    for _, dlt in ev:
+        cur += dlt
+        peak = max(peak, cur)
+    assert peak >= 4, peak
+    assert (te >= tb).all() and hz > 0
+    # results are the hybrid query's: matching attributes (filtered requests)
+    for i in range(n):
+        if flags[i]:
+            continue
+        for v in mix["ids"][i, :k[i]]:
+            if v >= 0:
+                assert oracle.chi(w.qattrs[i], w.attrs[v]) == 0
+    if ix is not ix0:
+        ix.free()
+
+
+def test_serve_learned_requests_equal_batch_learned_search(int_index):
+    w, ix = int_index
+    nhq.nhq_mlp_load(ix, init_params(3))
+    torch.cuda.synchronize()
+    wi, wd, wc = _batch(ix, w, 10, 128, n_init=32, learned=True, stop_threshold=0.7, check_every=4)
+    n = w.nq
+    with nhq.Server(ix, n_init=32, lifetime_s=LIFE, ring=256, slots_small=64, beam_large=-1,
+                    auto_beam=128, stop_threshold=0.7, check_every=4) as srv:
+        r = srv.run(w.q, w.qattrs, np.full(n, 10, np.int32), np.zeros(n, np.int32), np.zeros(n),
+                    timeout_s=30.0)
+    nhq.nhq_mlp_load(ix, None)
+    torch.cuda.synchronize()
+    assert np.array_equal(r["ids"][:, :10], wi)
+    assert np.array_equal(r["dists"][:, :10].view(np.uint32), wd.view(np.uint32))
+    assert np.array_equal(r["counters"], wc)
+
+
+def test_serve_full_ring_refuses_then_recovers(int_index):
+    w, ix = int_index
+    with nhq.Server(ix, lifetime_s=LIFE, ring=4, slots_small=8, beam_large=-1) as srv:
+        tickets = [srv.submit(w.q[i], w.qattrs[i], 10, 64) for i in range(4)]
+        assert min(tickets) >= 0
+        assert srv.submit(w.q[4], w.qattrs[4], 10, 64) == -1  # NHQ_EBUSY: ring full
+        for t in tickets:
+            t_end = time.time() + 20.0
+            while srv.poll(t, 10) is None:
+                assert time.time() < t_end
+        assert srv.submit(w.q[4], w.qattrs[4], 10, 64) >= 0
+        with pytest.raises(nhq.NHQError):
+            srv.poll(tickets[0], 10)  # already polled
+
+
+def test_serve_kernel_lifetime_ends_the_server(int_index):
+    w, ix = int_index
+    srv = nhq.Server(ix, lifetime_s=0.3, ring=16, slots_small=4, beam_large=-1)
+    time.sleep(1.5)
+    with pytest.raises(nhq.NHQError) as e:
+        srv.submit(w.q[0], w.qattrs[0], 10, 64)
+    assert e.value.code == -4  # NHQ_EDEVICE
+    srv.free()
+
+
+def test_serve_rejects_bad_requests(int_index):
+    w, ix = int_index
+    with nhq.Server(ix, lifetime_s=LIFE, ring=16, slots_small=4, beam_large=256, slots_large=2,
+                    max_k=20) as srv:
+        for k, beam in ((21, 64), (0, 64), (10, 5), (10, 257), (10, 0)):
+            with pytest.raises(nhq.NHQError):
+                srv.submit(w.q[0], w.qattrs[0], k, beam)
+        with pytest.raises(nhq.NHQError):
+            srv.submit(w.q[0], w.qattrs[0], 10, 64, flags=8)
+    with pytest.raises(nhq.NHQError):
+        nhq.Server(ix, beam_small=128, beam_large=64)
