@@ -79,7 +79,7 @@ def lib():
         L.or_search.restype = None
         L.or_search.argtypes = [P, i32, P, P, P, i64, i32, i32, P, P, i64, i32, i32, P, i32,
                                 i32, i32, i32, i32, i64, P, P, P, P, P, i32, P, P, P, P, P, i32,
-                                P, ctypes.c_double, ctypes.c_double, i32, i32]
+                                P, ctypes.c_double, ctypes.c_double, i32, i32, i32]
         _lib = L
     return _lib
 
@@ -220,12 +220,14 @@ def search(adj, xs, attrs, q, qa, k: int, L: int, seeds, n_init: int = 32, key_m
            out_mode: int = 0, rerank_n: int = 0, xr=None, max_hops: int = 1 << 40,
            threads: Optional[int] = None, check_every: int = 0, trace_cap: int = 0,
            mlp: Optional[np.ndarray] = None, stop_threshold: float = 0.5, cap_factor: float = 0.0,
-           expand: int = 1):
+           expand: int = 1, learned_mode: int = 1):
     """Joint pruning in beam form; see ``or_search`` in nhq_oracle.c.
     Returns (ids [nq,k], gamma [nq,k], ndc [nq], hops [nq], flag [nq]); with
     trace_cap > 0 also a dict of checkpoint traces (feat [nq,cap,8], hop,
     hash, count, final_hash).  ``mlp`` (float64 [4866], weights as the GPU
-    holds them) turns on the learned stop with threshold stop_threshold.
+    holds them) turns on the learned stop with threshold stop_threshold;
+    learned_mode 2 evaluates it at the first checkpoint only, whose beam
+    output (times cap_factor) then bounds the hops.
     ``expand`` E > 1 expands the E best unexpanded entries per step (a
     batched form of Alg. 2 lines 3-8; E = 1 is the algorithm as printed)."""
     adj = np.ascontiguousarray(adj, dtype=np.int32)
@@ -254,7 +256,7 @@ def search(adj, xs, attrs, q, qa, k: int, L: int, seeds, n_init: int = 32, key_m
                     _p(tr["feat"]) if tr else None, _p(tr["hop"]) if tr else None,
                     _p(tr["hash"]) if tr else None, _p(tr["count"]) if tr else None,
                     _p(tr["final_hash"]) if tr else None, int(trace_cap), _p(w), logit,
-                    float(cap_factor), int(expand), _threads(threads))
+                    float(cap_factor), int(learned_mode), int(expand), _threads(threads))
     if tr is not None:
         return ids, gam, ndc, hops, flag, tr
     return ids, gam, ndc, hops, flag

@@ -415,7 +415,13 @@ static void mlp_forward(const double *w, const double *f, double *z)
  *            1: the first k pool entries, unfiltered;
  *   rerank_n >0 with xr: re-score the first rerank_n output candidates from
  *            xr in FP64, re-sort by (key, id), then cut to k;
- *   max_hops expansion cap (flag set when reached).
+ *   max_hops expansion cap (flag set when reached);
+ *   mlp      (nullable) the stop network: at every checkpoint (each
+ *            check_every hops) it stops the search when its stop logit
+ *            reaches stop_logit; with cap_factor > 0 the beam output of the
+ *            first checkpoint sets a hop budget cap_factor * 2^z1, checked
+ *            before every step; learned_mode 2 takes the first checkpoint
+ *            only (its budget then bounds the search).
  * Outputs ids (-1 padded), Gamma (+inf padded), NDC (neighbour distance
  * evaluations; the entry sample is not counted) and H (expansions). */
 void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
@@ -425,7 +431,8 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
                int32_t *out_ids, double *out_gamma, int64_t *out_ndc, int64_t *out_hops,
                int32_t *out_flag, int check_every, double *tr_feat, uint32_t *tr_hop,
                uint32_t *tr_hash, int32_t *tr_count, uint32_t *tr_final, int tr_cap,
-               const double *mlp, double stop_logit, double cap_factor, int expand, int nthreads)
+               const double *mlp, double stop_logit, double cap_factor, int learned_mode, int expand,
+               int nthreads)
 {
     if (expand < 1)
         expand = 1;
@@ -610,11 +617,15 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
                         if (cap_factor > 0 && first_ckpt)
                             budget = cap_factor * pow(2.0, z[1]);
                         first_ckpt = 0;
-                        if (z[0] >= stop_logit || (double)hops >= budget)
+                        if (z[0] >= stop_logit)
                             break;
+                        if (learned_mode == 2) /* one checkpoint: its budget bounds the rest */
+                            next_ckpt = INT64_MAX;
                     }
                     first_ckpt = 0;
                 }
+                if (mlp && (double)hops >= budget)
+                    break;
                 if (hops >= max_hops) {
                     flag = 1;
                     break;

@@ -60,6 +60,7 @@ class ServerParams(ctypes.Structure):
                 ("expand", ctypes.c_int32), ("rerank", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("auto_beam", ctypes.c_int32), ("max_hops", ctypes.c_int32),
                 ("stop_threshold", ctypes.c_float), ("cap_factor", ctypes.c_float),
+                ("learned_mode", ctypes.c_int32), ("reserved1", ctypes.c_int32),
                 ("lifetime_s", ctypes.c_double)]
 
 
@@ -265,7 +266,7 @@ def nhq_index_device_error(ix: Index, stream=None) -> int:
 
 def nhq_hybrid_search(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, k: int, beam: int,
                       n_init: int = 32, rerank: int = 0, output_mode: int = 0, max_hops: int = 0,
-                      visited_log2: int = 0, learned: bool = False, stop_threshold: float = 0.0,
+                      visited_log2: int = 0, learned: int = 0, stop_threshold: float = 0.0,
                       check_every: int = 0, counters: bool = False, stream=None,
                       out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None,
                       cap_factor: float = 0.0, trace: Optional["TraceBuffers"] = None,
@@ -284,7 +285,7 @@ def nhq_hybrid_search(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, k:
         ids, dists = out
     cnt = torch.zeros((nq, 2), dtype=torch.int32, device=queries.device) if counters else None
     sp = SearchParams(int(n_init), int(rerank), int(output_mode), int(max_hops), int(visited_log2),
-                      int(bool(learned)), float(stop_threshold), int(check_every),
+                      int(learned), float(stop_threshold), int(check_every),
                       cnt.data_ptr() if cnt is not None else None, float(cap_factor),
                       ctypes.cast(ctypes.byref(trace.c), ctypes.c_void_p) if trace is not None else None,
                       int(expand))
@@ -307,7 +308,7 @@ def nhq_seed_rank(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, n_cand
 
 def nhq_search_seeded(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, cand: torch.Tensor,
                       k: int, beam: int, n_init: int = 32, rerank: int = 0, output_mode: int = 0,
-                      max_hops: int = 0, visited_log2: int = 0, learned: bool = False,
+                      max_hops: int = 0, visited_log2: int = 0, learned: int = 0,
                       stop_threshold: float = 0.0, check_every: int = 0, counters: bool = False,
                       stream=None, out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None,
                       cap_factor: float = 0.0, trace: Optional["TraceBuffers"] = None,
@@ -323,7 +324,7 @@ def nhq_search_seeded(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, ca
         ids, dists = out
     cnt = torch.zeros((nq, 2), dtype=torch.int32, device=queries.device) if counters else None
     sp = SearchParams(int(n_init), int(rerank), int(output_mode), int(max_hops), int(visited_log2),
-                      int(bool(learned)), float(stop_threshold), int(check_every),
+                      int(learned), float(stop_threshold), int(check_every),
                       cnt.data_ptr() if cnt is not None else None, float(cap_factor),
                       ctypes.cast(ctypes.byref(trace.c), ctypes.c_void_p) if trace is not None else None,
                       int(expand))

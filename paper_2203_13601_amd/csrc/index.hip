@@ -635,8 +635,12 @@ int nhq_search_seeded(const nhq_index *h, const float *queries, const uint8_t *q
         return fail(NHQ_EINVAL, "rerank * k must not exceed beam");
     if (p.visited_log2 != 0 && (p.visited_log2 < 10 || p.visited_log2 > 13))
         return fail(NHQ_EINVAL, "visited_log2 must be 0 or in [10, 13]");
+    if (p.learned < 0 || p.learned > 2)
+        return fail(NHQ_EINVAL, "learned must be 0, 1 or 2");
     if (p.learned && !ix->mlp)
         return fail(NHQ_EINVAL, "learned stop requested but no network is loaded");
+    if (p.learned == 2 && !(p.cap_factor > 0.0f))
+        return fail(NHQ_EINVAL, "learned mode 2 needs cap_factor > 0 (its hop budget)");
     SearchLaunch s{};
     s.ix = ix;
     s.seed_cand = cand;

@@ -11,6 +11,7 @@
 #include <numeric>
 #include <vector>
 
+#include "mlp_infer.h"
 #include "nhq_internal.h"
 
 namespace nhq {
@@ -226,52 +227,31 @@ __global__ void k_mlp_reduce(const float *__restrict__ gpart, const float *__res
     }
 }
 
+// parameters -> fp16 in the device inference layout
 __global__ void k_to_half(const float *__restrict__ p, uint16_t *__restrict__ h, int n)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const _Float16 v = (_Float16)p[i];
         uint16_t b;
         __builtin_memcpy(&b, &v, 2);
-        h[i] = b;
+        h[mlp_device_index(i)] = b;
     }
 }
 
-__device__ __forceinline__ float h2f(uint16_t b)
-{
-    _Float16 v;
-    __builtin_memcpy(&v, &b, 2);
-    return (float)v;
-}
-
-__device__ __forceinline__ float wave_sum_f32(float v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// one wave per sample, the same arithmetic as the search's in-loop inference
 __global__ __launch_bounds__(64) void k_mlp_eval(const uint16_t *__restrict__ w, const float *__restrict__ X,
                                                  int64_t n, float *__restrict__ Z)
 {
-    __shared__ float scratch[64];
+    __shared__ __align__(16) float scratch[64];
+    __shared__ __align__(16) float f[8];
     const int j = threadIdx.x;
     const int64_t s = blockIdx.x;
     if (s >= n)
         return;
-    const uint16_t *W1 = w, *b1 = w + 512, *W2 = w + 576, *b2 = w + 4672, *W3 = w + 4736, *b3 = w + 4864;
-    float a1 = h2f(b1[j]);
-    for (int i = 0; i < 8; ++i)
-        a1 = fmaf(h2f(W1[j * 8 + i]), X[s * 8 + i], a1);
-    scratch[j] = fmaxf(a1, 0.0f);
+    if (j < 8)
+        f[j] = X[s * 8 + j];
     __syncthreads();
-    float a2 = h2f(b2[j]);
-    for (int i = 0; i < 64; ++i)
-        a2 = fmaf(h2f(W2[j * 64 + i]), scratch[i], a2);
-    const float hh = fmaxf(a2, 0.0f);
-    const float z0 = h2f(b3[0]) + wave_sum_f32(h2f(W3[j]) * hh);
-    const float z1 = h2f(b3[1]) + wave_sum_f32(h2f(W3[64 + j]) * hh);
+    float z0, z1;
+    mlp_infer(w, f, scratch, z0, z1);
     if (j == 0) {
         Z[s * 2] = z0;
         Z[s * 2 + 1] = z1;

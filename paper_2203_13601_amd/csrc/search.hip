@@ -21,7 +21,7 @@ namespace nhq {
 namespace {
 
 template <int DP, int ST, bool CK>
-__global__ __launch_bounds__(64) void k_search(const SearchArgs a)
+__device__ __forceinline__ void search_block(const SearchArgs &a)
 {
     extern __shared__ __align__(16) uint32_t smem[];
     const int64_t qi = blockIdx.x;
@@ -36,13 +36,36 @@ __global__ __launch_bounds__(64) void k_search(const SearchArgs a)
     io.od = a.out_dist + qi * a.k;
     io.cnt = a.counters ? a.counters + 2 * qi : nullptr;
     io.trace_row = qi;
+    io.mlp = a.mlp;
     search_one<DP, ST, CK>(a, io, smem);
+}
+
+// The checkpoint code raises the kernel's register count enough for the
+// compiler to settle at 4 waves per SIMD; for rows up to 128 elements asking
+// for 6 costs a few spills at the checkpoints but runs the search faster
+// (measured).  Wider rows keep the compiler's choice.
+#ifndef NHQ_CK_WAVES
+#define NHQ_CK_WAVES 6
+#endif
+#define NHQ_CK_ATTR __attribute__((amdgpu_waves_per_eu(DP <= 128 ? NHQ_CK_WAVES : 1)))
+
+template <int DP, int ST>
+__global__ __launch_bounds__(64) void k_search(const SearchArgs a)
+{
+    search_block<DP, ST, false>(a);
+}
+
+// with checkpoints (traces, learned stop)
+template <int DP, int ST>
+__global__ __launch_bounds__(64) NHQ_CK_ATTR void k_search_ck(const SearchArgs a)
+{
+    search_block<DP, ST, true>(a);
 }
 
 template <int DP, int ST>
 int launch_one(const SearchArgs &a, size_t lds, hipStream_t st)
 {
-    auto kern = a.ckpt > 0 ? k_search<DP, ST, true> : k_search<DP, ST, false>;
+    auto kern = a.ckpt > 0 ? k_search_ck<DP, ST> : k_search<DP, ST>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -137,7 +160,7 @@ int launch_search(const SearchLaunch &s)
         a.vis_words = 1 << hb;
         a.hash_log2 = hb;
     }
-    const size_t lds = sizeof(uint32_t) * ((size_t)2 * a.L + (size_t)2 * a.scap + (size_t)a.vis_words);
+    const size_t lds = sizeof(uint32_t) * ((size_t)ck_offset(a.L, a.scap, a.vis_words) + kCkWords);
     if (s.nq > 0x7FFFFFFF)
         return fail(NHQ_EINVAL, "too many queries in one call");
     switch (ix->dp) {

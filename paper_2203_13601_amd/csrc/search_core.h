@@ -5,6 +5,7 @@
 #pragma once
 #include <algorithm>
 
+#include "mlp_infer.h"
 #include "nhq_internal.h"
 
 namespace nhq {
@@ -158,7 +159,7 @@ __device__ __forceinline__ void score_batch(const void *vbase, const float *scal
 {
     using S = Shape<DP>;
     using T = typename Chunk<ST>::T;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const int g = lane % S::G, gi = lane / S::G;
     const int rounds = (nf + S::NG - 1) / S::NG;
     for (int r0 = 0; r0 < rounds; r0 += S::RB) {
@@ -221,7 +222,7 @@ __device__ __forceinline__ void score_batch(const void *vbase, const float *scal
 __device__ int pool_merge(float *pkey, uint32_t *pid, int size, int cap, float ck, uint32_t cw,
                           bool valid, int &lo, int *inserted = nullptr)
 {
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const uint32_t cm = cw & kIdMask;
     if (valid && size >= cap) {
         const float wk = pkey[cap - 1];
@@ -327,7 +328,7 @@ __device__ __forceinline__ float wave_sum_f32(float v)
 __device__ void eligible_topk(const float *pkey, const uint32_t *pid, int size, int k, int out_mode,
                               int &in_first_k, uint32_t &hash, float &key_kth, bool &has_kth)
 {
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     int nel = 0, fk = 0;
     uint32_t h = 0;
     has_kth = false;
@@ -359,29 +360,6 @@ __device__ __forceinline__ float h2f(uint16_t b)
     return (float)v;
 }
 
-// The stop network (8 -> 64 -> 64 -> 2, ReLU, fp16 weights, fp32
-// accumulation).  Lane j computes hidden unit j; `scratch` holds 64 floats
-// of LDS.  Weight layout: W1 [64][8], b1 [64], W2 [64][64], b2 [64],
-// W3 [2][64], b3 [2].
-__device__ void mlp_eval(const uint16_t *w, const float (&f)[8], float *scratch, float &z0, float &z1)
-{
-    const int j = threadIdx.x & 63;
-    const uint16_t *W1 = w, *b1 = w + 512, *W2 = w + 576, *b2 = w + 4672, *W3 = w + 4736, *b3 = w + 4864;
-    float a1 = h2f(b1[j]);
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-        a1 = fmaf(h2f(W1[j * 8 + i]), f[i], a1);
-    scratch[j] = fmaxf(a1, 0.0f);
-    wsync();
-    float a2 = h2f(b2[j]);
-    for (int i = 0; i < 64; ++i)
-        a2 = fmaf(h2f(W2[j * 64 + i]), scratch[i], a2);
-    const float hh = fmaxf(a2, 0.0f);
-    z0 = h2f(b3[0]) + wave_sum_f32(h2f(W3[j]) * hh);
-    z1 = h2f(b3[1]) + wave_sum_f32(h2f(W3[64 + j]) * hh);
-    wsync();
-}
-
 // visited test-and-set; returns true when v was not yet visited.  `unrec`
 // reports a fresh vertex the hash could not record (table region full).
 __device__ __forceinline__ bool visit(uint32_t *vis, bool bitset, int hash_log2, uint32_t v,
@@ -408,6 +386,24 @@ __device__ __forceinline__ bool visit(uint32_t *vis, bool bitset, int hash_log2,
     return true;
 }
 
+// Per-query state of the checkpoints, kept in LDS (after the visited set, 16-
+// byte aligned) rather than in registers across the expansion loop.
+struct CkState {
+    float h1[64];  // the stop network's hidden layer
+    float f[8];    // the features of the current checkpoint
+    float logsel, key_kth_first;
+    uint32_t prev_hash;
+    int last_change, ntrace, have_first, have_prev, first_ckpt;
+};
+constexpr int kCkWords = 96;  // LDS words reserved for CkState
+static_assert(sizeof(CkState) <= 4 * kCkWords, "checkpoint state size");
+
+// LDS word offset of the checkpoint state: after pool, staging and visited set
+__host__ __device__ inline int ck_offset(int L, int scap, int vis_words)
+{
+    return (2 * L + 2 * scap + vis_words + 3) & ~3;
+}
+
 // One query's inputs and outputs.  The query vector has d floats; `seeds`
 // holds n_seed entry-sample positions (-1 padded) in global memory or LDS.
 struct QueryIO {
@@ -419,6 +415,7 @@ struct QueryIO {
     float *od;        // [k]
     uint32_t *cnt;    // [2] NDC, hops (nullable)
     int64_t trace_row;
+    const uint16_t *mlp;  // stop network weights (device layout; LDS or global)
 };
 
 __device__ __forceinline__ void pack_query_attrs(const uint8_t *qa, int m, uint32_t &qword, uint32_t &qmask)
@@ -436,7 +433,7 @@ __device__ __forceinline__ void pack_query_attrs(const uint8_t *qa, int m, uint3
 
 // The search of one query by one wave (Alg. 2 in beam form), LDS at smem:
 // pool keys [L], pool words [L], staged keys [scap], staged words [scap],
-// visited set [vis_words].
+// visited set [vis_words], checkpoint state [kCkWords] at ck_offset.
 template <int DP, int ST, bool CK>
 __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *smem)
 {
@@ -448,6 +445,8 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
     float *skey = reinterpret_cast<float *>(smem + 2 * L);
     uint32_t *sid = smem + 2 * L + a.scap;
     uint32_t *vis = smem + 2 * L + 2 * a.scap;
+    CkState *cks = reinterpret_cast<CkState *>(
+        __builtin_assume_aligned(smem + ck_offset(L, a.scap, a.vis_words), 16));
     const bool bitset = a.use_bitset != 0;
     const int g = lane % S::G;
 
@@ -464,11 +463,21 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
     }
     const uint32_t qword = io.qword, qmask = io.qmask;
     const int mq = __popc(qmask) / 8;
-    float logsel = 0.0f;
     if (CK && a.ckpt > 0) {
+        float logsel = 0.0f;
         for (int i = 0; i < a.m; ++i)
             if ((qmask >> (8 * i)) & 0xFFu)
                 logsel += a.logp[i * 256 + ((qword >> (8 * i)) & 0xFFu)];
+        if (lane == 0) {
+            cks->logsel = logsel;
+            cks->key_kth_first = 0.0f;
+            cks->prev_hash = 0;
+            cks->last_change = 0;
+            cks->ntrace = 0;
+            cks->have_first = 0;
+            cks->have_prev = 0;
+            cks->first_ckpt = 1;
+        }
     }
     for (int i = lane; i < a.vis_words; i += 64)
         vis[i] = bitset ? 0u : kEmpty;
@@ -504,18 +513,15 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
     // ---- expansion loop
     uint32_t ndc = 0, hops = 0;
     bool capped = false, badid = false;
-    // checkpoint state
-    float key_kth_first = 0.0f, budget = 3.0e38f;
-    bool have_first = false, have_prev = false;
-    uint32_t prev_hash = 0;
-    int last_change = 0, ins_window = 0, ntrace = 0;
+    // checkpoint state (the rest is in LDS)
+    int ins_window = 0;
+    float budget = 3.0e38f;  // learned hop budget
     // E = 1: the adjacency row of the runner-up is fetched one hop ahead (it
     // is the next vertex to expand unless this hop inserts a better one)
     const int E = a.expand;
     int64_t pf_id = -1;
     int pf_nb = -1;
     uint32_t next_ckpt = (uint32_t)a.ckpt;
-    bool first_ckpt = true;
     for (;;) {
         // ---- the E best unexpanded entries (one more, unexpanded, when E = 1)
         const int want_sel = E == 1 ? 2 : E;
@@ -538,56 +544,95 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
         if (CK && a.ckpt > 0 && hops >= next_ckpt) {
             while (next_ckpt <= hops)
                 next_ckpt += (uint32_t)a.ckpt;
-            // ---- checkpoint: search-state features (see the stop network)
+            // ---- checkpoint: search-state features (see the stop network);
+            // lane i computes feature i
             int fk;
             uint32_t h;
             float kth;
             bool has_kth;
             eligible_topk(pkey, pid, size, a.k, a.out_mode, fk, h, kth, has_kth);
-            if (have_prev && h != prev_hash)
+            int last_change = cks->last_change;
+            if (cks->have_prev && h != cks->prev_hash)
                 last_change = (int)hops;
-            prev_hash = h;
-            have_prev = true;
-            if (has_kth && !have_first) {
-                key_kth_first = kth;
-                have_first = true;
-            }
+            float kfirst = cks->key_kth_first;
+            const bool have_first = cks->have_first || has_kth;
+            if (has_kth && !cks->have_first)
+                kfirst = kth;
             const float front = pkey[cur];
-            float f[8];
-            f[0] = logf(1.0f + (float)hops) * 0.125f;
-            f[1] = logf(1.0f + (float)ndc) * 0.125f;
-            f[2] = logsel * 0.125f;
-            f[3] = (float)fk / (float)a.k;
-            f[4] = has_kth ? logf(fmaxf(kth, 1e-30f) / fmaxf(key_kth_first, 1e-30f)) : 1.0f;
-            f[5] = has_kth ? logf(fmaxf(front, 1e-30f) / fmaxf(kth, 1e-30f)) : -1.0f;
-            f[6] = (float)ins_window / (float)(a.ckpt * a.R);
-            f[7] = fminf((float)((int)hops - last_change) / 64.0f, 1.0f);
+            float arg = 1.0f;
+            if (lane == 0)
+                arg = 1.0f + (float)hops;
+            else if (lane == 1)
+                arg = 1.0f + (float)ndc;
+            else if (lane == 4)
+                arg = fmaxf(kth, 1e-30f) / fmaxf(kfirst, 1e-30f);
+            else if (lane == 5)
+                arg = fmaxf(front, 1e-30f) / fmaxf(kth, 1e-30f);
+            const float lg = logf(arg);
+            float myf;
+            switch (lane) {
+            case 0:
+            case 1:
+                myf = lg * 0.125f;
+                break;
+            case 2:
+                myf = cks->logsel * 0.125f;
+                break;
+            case 3:
+                myf = (float)fk / (float)a.k;
+                break;
+            case 4:
+                myf = has_kth ? lg : 1.0f;
+                break;
+            case 5:
+                myf = has_kth ? lg : -1.0f;
+                break;
+            case 6:
+                myf = (float)ins_window / (float)(a.ckpt * a.R);
+                break;
+            default:
+                myf = fminf((float)((int)hops - last_change) / 64.0f, 1.0f);
+                break;
+            }
             ins_window = 0;
+            const int ntrace = cks->ntrace;
+            const bool first_ckpt = cks->first_ckpt != 0;
+            wsync();
+            if (lane < 8)
+                cks->f[lane] = myf;
             if (a.trace_feat && ntrace < a.trace_cap) {
                 const int64_t t = io.trace_row * a.trace_cap + ntrace;
-                float mine = f[0];
-#pragma unroll
-                for (int i = 1; i < 8; ++i)
-                    mine = lane == i ? f[i] : mine;
                 if (lane < 8)
-                    a.trace_feat[t * 8 + lane] = mine;
+                    a.trace_feat[t * 8 + lane] = myf;
                 if (lane == 0) {
                     a.trace_hop[t] = hops;
                     a.trace_hash[t] = h;
                 }
-                ntrace += 1;
             }
+            if (lane == 0) {
+                cks->last_change = last_change;
+                cks->prev_hash = h;
+                cks->have_prev = 1;
+                cks->key_kth_first = kfirst;
+                cks->have_first = have_first ? 1 : 0;
+                cks->first_ckpt = 0;
+                if (a.trace_feat && ntrace < a.trace_cap)
+                    cks->ntrace = ntrace + 1;
+            }
+            wsync();
             if (a.learned) {
                 float z0, z1;
-                mlp_eval(a.mlp, f, skey, z0, z1);
+                mlp_infer(io.mlp, cks->f, cks->h1, z0, z1);
                 if (a.cap_factor > 0.0f && first_ckpt)
                     budget = a.cap_factor * exp2f(z1);
-                first_ckpt = false;
-                if (z0 >= a.stop_logit || (float)hops >= budget)
+                if (z0 >= a.stop_logit)
                     break;
+                if (a.learned == 2)  // one checkpoint: its budget bounds the rest
+                    next_ckpt = 0xFFFFFFFFu;
             }
-            first_ckpt = false;
         }
+        if (CK && a.learned && (float)hops >= budget)
+            break;
         if ((int)hops >= a.max_hops) {
             capped = true;
             break;
@@ -672,7 +717,7 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
         eligible_topk(pkey, pid, size, a.k, a.out_mode, fk, h, kth, has_kth);
         if (lane == 0) {
             a.final_hash[io.trace_row] = h;
-            a.trace_count[io.trace_row] = ntrace;
+            a.trace_count[io.trace_row] = cks->ntrace;
         }
     }
 

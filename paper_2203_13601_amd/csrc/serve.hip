@@ -58,6 +58,7 @@ struct ServeArgs {
     uint32_t *stop_dev;              // device: copy of the stop reason
     int cap, rec_bytes, out_bytes, max_k;
     int n_cand, ne_pad, seed_off, check_every;
+    int learned_mode;
     unsigned long long life_ticks;
 };
 
@@ -211,7 +212,7 @@ __global__ __launch_bounds__(64) void k_serve(const SearchArgs base, const Serve
         a.out_mode = (flags & NHQ_SERVE_RAW) ? 1 : 0;
         a.max_hops = max_hops;
         const bool learned = (flags & kReqLearned) != 0;
-        a.learned = learned ? 1 : 0;
+        a.learned = learned ? s.learned_mode : 0;
         a.ckpt = learned ? s.check_every : 0;
         // the visited set the batch search would choose for this beam
         int slots = 1024;
@@ -249,6 +250,7 @@ __global__ __launch_bounds__(64) void k_serve(const SearchArgs base, const Serve
         io.od = reinterpret_cast<float *>(io.oid + s.max_k);
         io.cnt = &o->ndc;
         io.trace_row = 0;
+        io.mlp = base.mlp;
         if (learned)
             search_one<DP, ST, true>(a, io, smem);
         else
@@ -313,7 +315,7 @@ struct ServeClass {
 // LDS words before the seed region (16-byte aligned for the query rows)
 int seed_offset(const ServeClass &c)
 {
-    return (2 * c.lmax + 2 * c.scap + c.vis + 3) & ~3;
+    return (ck_offset(c.lmax, c.scap, c.vis) + kCkWords + 3) & ~3;
 }
 
 double now_s()
@@ -424,6 +426,7 @@ int launch_class(Server &s, ServeClass &c, const void *kern, const SearchArgs &b
     a.ne_pad = s.ne_pad;
     a.seed_off = seed_offset(c);
     a.check_every = s.p.check_every;
+    a.learned_mode = s.p.learned_mode;
     a.life_ticks = (unsigned long long)(s.p.lifetime_s * s.tick_hz);
     if (c.lds > 64 * 1024)
         NHQ_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds));
@@ -471,6 +474,10 @@ int nhq_server_create(nhq_index *h, const nhq_server_params *pp, nhq_server **ou
         p.stop_threshold = 0.5f;
     if (p.lifetime_s == 0.0)
         p.lifetime_s = 600.0;
+    if (p.learned_mode == 0)
+        p.learned_mode = 1;
+    if (p.learned_mode < 1 || p.learned_mode > 2 || (p.learned_mode == 2 && !(p.cap_factor > 0.0f)))
+        return fail(NHQ_EINVAL, "learned_mode must be 1, or 2 with cap_factor > 0");
     if (p.beam_small < 1 || p.beam_small > NHQ_MAX_BEAM || (p.beam_large > 0 && p.beam_large <= p.beam_small) ||
         p.beam_large > NHQ_MAX_BEAM)
         return fail(NHQ_EINVAL, "need 1 <= beam_small < beam_large <= 1024 (beam_large < 0: no large class)");

@@ -29,21 +29,21 @@ def init_params(seed: int = 0, device="cuda") -> torch.Tensor:
 
 
 def collect(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, k: int, beam: int,
-            check_every: int = 4, n_init: int = 32, trace_cap: int = 0):
+            check_every: int = 4, n_init: int = 32, trace_cap: int = 0, expand: int = 1):
     """Plain fixed-beam search of the training queries with traces; returns
     (X, y_stop, y_beam) device tensors."""
     cap = trace_cap or (2 * beam) // check_every + 16
     tr = TraceBuffers(queries.shape[0], cap, device=queries.device)
     _, _, cnt = nhq_hybrid_search(ix, queries, qattrs, k, beam, n_init=n_init, check_every=check_every,
-                                  counters=True, trace=tr)
+                                  counters=True, trace=tr, expand=expand)
     return nhq_trace_samples(tr, cnt)
 
 
 def train_stop_network(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, k: int, beam: int,
                        epochs: int = 30, check_every: int = 4, n_init: int = 32, lr: float = 2e-3,
-                       lam: float = 0.5, batch: int = 1024, seed: int = 0
+                       lam: float = 0.5, batch: int = 1024, seed: int = 0, expand: int = 1
                        ) -> Tuple[torch.Tensor, Dict]:
-    X, ys, yb = collect(ix, queries, qattrs, k, beam, check_every, n_init)
+    X, ys, yb = collect(ix, queries, qattrs, k, beam, check_every, n_init, expand=expand)
     params = init_params(seed, queries.device)
     state = torch.zeros(2 * MLP_PARAMS, dtype=torch.float32, device=queries.device)
     step, losses = nhq_mlp_train(params, state, 0, X, ys, yb, epochs, batch, lr, lam, seed)

@@ -214,6 +214,15 @@ def config2(n: int = 1_000_000, nq: int = 10_000) -> Workload:
                     build_seed=205, integer=True)
 
 
+def config2_train_queries(nq: int = 20_000):
+    """Training queries of the config-2 distribution (same clusters and
+    attribute law, seeds disjoint from the evaluation queries): for the
+    stop network, which is evaluated on the held-out config-2 queries."""
+    q = integer_clusters(nq, 128, 256, seed=206, sigma=CONFIG2_SIGMA, centre_seed=1201)
+    qa = uniform_attrs(nq, (3, 4, 5), 207)
+    return q, qa
+
+
 def config3(n: int = 1_000_000, nq: int = 10_000) -> Workload:
     """Precision form: d = 960 Gaussian mixture (64 centres), 4 uniform
     attributes of cardinality 2/3/5/10, all four constrained."""

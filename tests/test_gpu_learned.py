@@ -159,6 +159,15 @@ def test_learned_search_matches_oracle(setup):
         same = (ids.cpu().numpy() == o[0]).all(axis=1) & (cnt.cpu().numpy()[:, 1] == o[3])
         # a decision can flip only where the logit sits within rounding of the threshold
         assert same.mean() >= 0.97, same.mean()
+    # the hop budget (checked before every step) and the one-checkpoint mode
+    for mode, tau, cf, ce in ((1, 0.6, 1.5, 4), (2, 0.6, 2.0, 8), (2, 0.99, 1.0, 4)):
+        ids, dist, cnt = nhq.nhq_hybrid_search(ix, _dev(w.q), _dev(w.qattrs), 10, 128, learned=mode,
+                                               stop_threshold=tau, check_every=ce, cap_factor=cf,
+                                               counters=True)
+        o = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, 128, entry, key_mode=oracle.KEY32,
+                          check_every=ce, mlp=wh, stop_threshold=tau, cap_factor=cf, learned_mode=mode)
+        same = (ids.cpu().numpy() == o[0]).all(axis=1) & (cnt.cpu().numpy()[:, 1] == o[3])
+        assert same.mean() >= 0.97, (mode, same.mean())
     nhq.nhq_mlp_load(ix, None)
     with pytest.raises(nhq.NHQError):
         nhq.nhq_hybrid_search(ix, _dev(w.q), _dev(w.qattrs), 10, 64, learned=True)

@@ -87,3 +87,29 @@ def test_learned_stop_extremes(traced):
     b = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, 96, entry, key_mode=oracle.KEY32,
                       check_every=4, mlp=always)
     assert (b[3] == np.minimum(hops, 4)).all()
+
+
+def test_learned_hop_budget_and_single_checkpoint(traced):
+    # a network whose outputs are its biases: stop logit b3[0], beam output
+    # b3[1].  The budget cap_factor * 2^b3[1] bounds the hops before every
+    # step; mode 2 takes one checkpoint only.
+    w, adj, entry, (ids, gam, ndc, hops, flag, tr) = traced
+    net = np.zeros(oracle.MLPRef.SIZE if hasattr(oracle.MLPRef, "SIZE") else 4866)
+    net[4864] = -1e6   # never stops by the stop logit
+    net[4865] = 4.0    # beam output: 2^4 = 16
+    for mode in (1, 2):
+        for cf, want in ((1.0, 16), (1.5, 24), (0.5, 8)):
+            o = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, 96, entry, key_mode=oracle.KEY32,
+                              check_every=4, mlp=net, cap_factor=cf, learned_mode=mode)
+            # E = 1: one hop per step, so the search ends at exactly the budget
+            # unless it has converged before (budget set at the checkpoint at hop 4)
+            assert (o[3] == np.minimum(hops, max(want, 4))).all(), (mode, cf)
+    # the number of checkpoints: every 4 hops (mode 1) or one (mode 2)
+    o1 = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, 96, entry, key_mode=oracle.KEY32,
+                       check_every=4, trace_cap=64, mlp=net, cap_factor=8.0, learned_mode=1)
+    o2 = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, 96, entry, key_mode=oracle.KEY32,
+                       check_every=4, trace_cap=64, mlp=net, cap_factor=8.0, learned_mode=2)
+    assert np.array_equal(o1[3], o2[3]) and np.array_equal(o1[0], o2[0])
+    reached = o2[3] > 4
+    assert (o2[5]["count"][reached] == 1).all()
+    assert (o1[5]["count"][reached] == np.minimum(64, (o1[3][reached] - 1) // 4)).all()
