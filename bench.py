@@ -1,18 +1,31 @@
-"""Benchmark: hybrid QPS at Recall@10 = 0.95 on one MI355X.
+"""Benchmark: hybrid QPS at Recall@10 = 0.95 on one MI355X, plain FP32 fixed
+beam against BF16 storage + learned stop, and p99 latency of the serving
+loop.
 
-Workload (default): the plain method at scale -- 1,000,000 integer-valued
-128-d vectors from 256 clusters, 3 uniform attributes of cardinality 3/4/5,
-10,000 queries with full constraints, out-degree 32, k = 10, float32
-throughout.  The composite index is built on the GPU (not timed), the exact
-answers come from the GPU brute force (parity-tested against the CPU
-oracle), a beam sweep finds the smallest beam reaching Recall@10 >= 0.95,
-and one timed "step" is one full pass of the hot path over the 10,000
-queries at that beam: seed ranking of the entry sample (matrix cores) plus
-the joint-pruning search (one wavefront per query).  Inputs are resident in
-HBM before the timed region.
+Workload: the plain method at scale -- 1,000,000 integer-valued 128-d
+vectors from 256 clusters, 3 uniform attributes of cardinality 3/4/5,
+10,000 queries with full constraints, out-degree 32, k = 10.  The composite
+index is built on the GPU (not timed); the exact answers come from the GPU
+brute force (parity-tested against the CPU oracle).
 
-Prints ONE JSON line (see README of the measurement protocol in the design
-notes).  ``--gpus N`` with N > 1 exits: this build runs on one GPU.
+1. Plain form (the reported ``value``): float32 storage, fixed beam.  A beam
+   sweep finds the smallest beam reaching Recall@10 >= 0.95; one timed
+   "step" is one full pass of the hot path over the 10,000 queries at that
+   beam: seed ranking of the entry sample (matrix cores) plus the
+   joint-pruning search (one wavefront per query).
+2. BF16 + learned stop: the same graph with bf16 row storage; the stop
+   network is trained on the GPU from traces of 20,000 separate training
+   queries and runs inside the search (one checkpoint, whose beam output
+   sets the hop budget); the budget factor is swept for Recall@10 >= 0.95
+   and the same step is timed.
+3. Serving: the bf16 index under a Poisson stream of requests (k uniform in
+   {1, 10, 50, 100}, 1 to 3 constrained attributes, the beam left to a stop
+   network trained on queries with that constraint law), through the
+   continuous-batching server: p50 / p99 latency from arrival to result,
+   sustained QPS, Recall@10 of the k >= 10 requests.
+
+Inputs are resident in HBM before every timed region.  Prints ONE JSON line.
+``--gpus N`` with N > 1 exits: this build runs on one GPU.
 """
 from __future__ import annotations
 
@@ -36,10 +49,13 @@ def _profiled_traffic(kernel: str, source: str, tag: str):
     import glob
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
-    try:
-        h = hashlib.sha256(open(os.path.join(root, source), "rb").read()).hexdigest()[:16]
-    except OSError:
-        return None
+    h = hashlib.sha256()
+    for src in source.split(","):
+        try:
+            h.update(open(os.path.join(root, src), "rb").read())
+        except OSError:
+            return None
+    h = h.hexdigest()[:16]
     for fn in sorted(glob.glob(os.path.join(root, "profiles", "%s_*%s.md" % (kernel, tag)))):
         txt = open(fn).read()
         if "source_sha256_16[%s]: %s" % (source, h) not in txt:
@@ -48,6 +64,9 @@ def _profiled_traffic(kernel: str, source: str, tag: str):
             if line.startswith("traffic_bytes_per_launch[%s]:" % kernel):
                 return float(line.split(":")[1])
     return None
+
+
+SEARCH_SOURCES = "paper_2203_13601_amd/csrc/search.hip,paper_2203_13601_amd/csrc/search_core.h"
 
 
 def main():
@@ -59,10 +78,12 @@ def main():
     ap.add_argument("--nq", type=int, default=10_000)
     ap.add_argument("--target", type=float, default=0.95)
     ap.add_argument("--beam", type=int, default=0, help="fixed beam (skip the choice)")
-    ap.add_argument("--storage", default="fp32", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--n-entry", type=int, default=4096)
     ap.add_argument("--n-init", type=int, default=16)
     ap.add_argument("--expand", type=int, default=4, help="vertices expanded per step")
+    ap.add_argument("--plain-only", action="store_true", help="skip the bf16/learned and serving legs")
+    ap.add_argument("--serve-rate", type=float, default=50_000.0)
+    ap.add_argument("--serve-requests", type=int, default=50_000)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -78,6 +99,7 @@ def main():
     import torch
     import synth
     import paper_2203_13601_amd as nhq
+    from paper_2203_13601_amd.learned import train_stop_network
     from paper_2203_13601_amd.metrics import qps_at_recall, recall_at_k, search_bytes_per_query
 
     dev = torch.device("cuda:0")
@@ -91,12 +113,11 @@ def main():
     torch.cuda.synchronize()
 
     t0 = time.time()
-    ix = nhq.nhq_build_index(x, a, degree=w.degree, cand=w.cand, storage=args.storage,
+    ix = nhq.nhq_build_index(x, a, degree=w.degree, cand=w.cand, storage="fp32",
                              n_entry=args.n_entry, seed=w.build_seed)
     torch.cuda.synchronize()
     build_s = time.time() - t0
     log("built the composite index in %.2fs" % build_s)
-    del x
 
     t0 = time.time()
     gi, gd = nhq.nhq_bruteforce_hybrid_knn(ix, q, qa, w.k)
@@ -111,80 +132,79 @@ def main():
     ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
     dists = torch.empty((nq, k), dtype=torch.float32, device=dev)
 
-    def step(beam, counters=False, ev=None):
+    def step(index, beam, counters=False, ev=None, **kw):
         if ev is not None:
             ev[0].record()
-        nhq.nhq_seed_rank(ix, q, qa, n_cand, out=cand)
+        nhq.nhq_seed_rank(index, q, qa, n_cand, out=cand)
         if ev is not None:
             ev[1].record()
-        r = nhq.nhq_search_seeded(ix, q, qa, cand, k, beam, n_init=args.n_init, counters=counters,
-                                  out=(ids, dists), expand=args.expand)
+        r = nhq.nhq_search_seeded(index, q, qa, cand, k, beam, n_init=args.n_init, counters=counters,
+                                  out=(ids, dists), expand=args.expand, **kw)
         if ev is not None:
             ev[2].record()
         return r
 
-    def timed(beam, reps):
+    def timed(index, beam, reps, **kw):
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
         torch.cuda.synchronize()
         t = time.time()
         for e in evs:
-            step(beam, ev=e)
+            step(index, beam, ev=e, **kw)
         torch.cuda.synchronize()
         wall = time.time() - t
         rank_ms = [e[0].elapsed_time(e[1]) for e in evs]
         search_ms = [e[1].elapsed_time(e[2]) for e in evs]
         return wall, rank_ms, search_ms
 
-    # ---- beam sweep (Recall@10 vs QPS)
+    def point(index, beam, **kw):
+        _, _, cnt = step(index, beam, counters=True, **kw)
+        torch.cuda.synchronize()
+        rec = recall_at_k(ids.cpu().numpy(), dists.cpu().numpy(), gi, gd, w.attrs, w.qattrs, k)
+        cnt = cnt.cpu().numpy().astype(np.float64)
+        step(index, beam, **kw)
+        wall, rk, se = timed(index, beam, 3, **kw)
+        return {"beam": beam, "recall": float(rec.mean()), "qps": nq * 3 / wall,
+                "ndc": float(cnt[:, 0].mean()), "hops": float(cnt[:, 1].mean()),
+                "hops_p99": float(np.percentile(cnt[:, 1], 99)),
+                "rank_ms": float(np.median(rk)), "search_ms": float(np.median(se))}
+
+    # ---- 1. plain form: float32 storage, fixed beam
     sweep = []
     beams = [args.beam] if args.beam else [10, 16, 24, 32, 40, 48, 56, 64, 96, 128, 256, 512]
     for beam in beams:
         if beam < k:
             continue
-        _, _, cnt = step(beam, counters=True)
-        torch.cuda.synchronize()
-        rec = recall_at_k(ids.cpu().numpy(), dists.cpu().numpy(), gi, gd, w.attrs, w.qattrs, k)
-        cnt = cnt.cpu().numpy().astype(np.float64)
-        step(beam)
-        wall, rk, se = timed(beam, 3)
-        qps = nq * 3 / wall
-        sweep.append({"beam": beam, "recall": float(rec.mean()), "qps": qps,
-                      "ndc": float(cnt[:, 0].mean()), "hops": float(cnt[:, 1].mean()),
-                      "rank_ms": float(np.median(rk)), "search_ms": float(np.median(se))})
-        log("beam %4d recall %.4f qps %.0f ndc %.0f hops %.0f rank %.3fms search %.3fms" % (
-            beam, rec.mean(), qps, cnt[:, 0].mean(), cnt[:, 1].mean(), np.median(rk), np.median(se)))
-        if not args.beam and rec.mean() >= args.target and beam >= 64:
+        p = point(ix, beam)
+        sweep.append(p)
+        log("fp32 beam %4d recall %.4f ndc %.0f hops %.0f rank %.3fms search %.3fms" % (
+            beam, p["recall"], p["ndc"], p["hops"], p["rank_ms"], p["search_ms"]))
+        if not args.beam and p["recall"] >= args.target and beam >= 64:
             break
     ok = [s for s in sweep if s["recall"] >= args.target]
     op = ok[0] if ok else sweep[-1]
     beam = op["beam"]
     q_at = qps_at_recall([s["beam"] for s in sweep], [s["recall"] for s in sweep],
                          [s["qps"] for s in sweep], args.target)
-
-    # ---- timed steps at the operating beam
     for _ in range(args.warmup):
-        step(beam)
-    wall, rank_ms, search_ms = timed(beam, args.steps)
+        step(ix, beam)
+    wall, rank_ms, search_ms = timed(ix, beam, args.steps)
     value = nq * args.steps / wall
     ms_per_step = wall * 1000.0 / args.steps
-    log("timed %d steps at beam %d: %.1f ms/step, %.0f QPS" % (args.steps, beam, ms_per_step, value))
+    log("plain fp32: %d steps at beam %d: %.3f ms/step, %.0f QPS" % (args.steps, beam, ms_per_step, value))
 
     # ---- roofline of the dominant kernel (the search)
-    elem = {"fp32": 4, "bf16": 2, "fp8": 1}[args.storage]
-    bq = search_bytes_per_query(d_pad=128, elem_bytes=elem, R=w.degree, k=k, n_cand=n_cand,
-                                ndc=op["ndc"], hops=op["hops"], d=w.d, m=w.m,
-                                scale_bytes=4 if args.storage == "fp8" else 0)
+    bq = search_bytes_per_query(d_pad=128, elem_bytes=4, R=w.degree, k=k, n_cand=n_cand,
+                                ndc=op["ndc"], hops=op["hops"], d=w.d, m=w.m)
     search_avg_s = float(np.mean(search_ms)) / 1000.0
     traffic = None
-    if args.n == 1_000_000 and args.nq == 10_000 and args.storage == "fp32":
-        traffic = _profiled_traffic("k_search", "paper_2203_13601_amd/csrc/search.hip",
-                                    "_beam%d" % beam)
+    if args.n == 1_000_000 and args.nq == 10_000:
+        traffic = _profiled_traffic("k_search", SEARCH_SOURCES, "_beam%d" % beam)
     achieved = bq * nq / search_avg_s / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": 8000.0, "unit": "GB/s",
             "frac": round(achieved / 8000.0, 5), "traffic": traffic,
-            "kernel": "k_search", "bytes_per_query": round(bq, 1),
+            "kernel": "k_search", "bytes_per_query": round(bq, 1), "queries_per_launch": nq,
             "kernel_avg_ms": round(search_avg_s * 1000.0, 4),
-            "rank_kernel_avg_ms": round(float(np.mean(rank_ms)), 4)}
+            "rank_kernels_avg_ms": round(float(np.mean(rank_ms)), 4)}
 
     if args.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
@@ -192,7 +212,116 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
+        del src, dst
         log("copy calibration: 3 copies of 1 GiB")
+
+    forms = {"fp32_fixed": {"qps": round(value, 1), "recall": round(op["recall"], 5), "beam": beam,
+                            "ms_per_step": round(ms_per_step, 4),
+                            "qps_at_target_interp": None if q_at is None else round(q_at, 1)}}
+    serving = None
+    if not args.plain_only:
+        # ---- 2. bf16 storage + learned stop (same graph and entry sample)
+        ixb = nhq.nhq_index_create(x, a, storage="bf16", n_entry=args.n_entry, seed=w.build_seed,
+                                   degree=w.degree)
+        nhq.nhq_index_set_graph(ixb, nhq.nhq_index_get_graph(ix))
+        tq_np, tqa_np = synth.config2_train_queries(20_000)
+        tq, tqa = torch.from_numpy(tq_np).to(dev), torch.from_numpy(tqa_np).to(dev)
+        t0 = time.time()
+        l_train, ce = 64, 8
+        params, info = train_stop_network(ixb, tq, tqa, k, l_train, epochs=30, check_every=ce,
+                                          n_init=args.n_init, expand=args.expand, seed=1)
+        nhq.nhq_mlp_load(ixb, params)
+        torch.cuda.synchronize()
+        train_s = time.time() - t0
+        log("stop network: %d trace samples, trained in %.2fs (loss %.4f)" % (
+            info["samples"], train_s, info["losses"][-1]))
+        lsweep = []
+        lkw = None
+        for cf in (1.25, 1.5, 1.75, 2.0, 2.5, 3.0):
+            kw = dict(learned=2, stop_threshold=0.9, check_every=ce, cap_factor=cf)
+            p = point(ixb, l_train, **kw)
+            p["cap_factor"] = cf
+            lsweep.append(p)
+            log("bf16+learned cap %.2f recall %.4f hops %.1f (p99 %.0f) search %.3fms" % (
+                cf, p["recall"], p["hops"], p["hops_p99"], p["search_ms"]))
+            if p["recall"] >= args.target:
+                lkw = kw
+                break
+        lop = lsweep[-1]
+        if lkw is None:
+            lkw = dict(learned=2, stop_threshold=0.9, check_every=ce, cap_factor=lop["cap_factor"])
+        for _ in range(args.warmup):
+            step(ixb, l_train, **lkw)
+        lwall, lrank, lsearch = timed(ixb, l_train, args.steps, **lkw)
+        lvalue = nq * args.steps / lwall
+        log("bf16+learned: %d steps: %.3f ms/step, %.0f QPS" % (args.steps, lwall * 1000 / args.steps, lvalue))
+        forms["bf16_learned"] = {
+            "qps": round(lvalue, 1), "recall": round(lop["recall"], 5), "beam": l_train,
+            "learned_mode": 2, "check_every": ce, "cap_factor": lkw["cap_factor"],
+            "hops_mean": round(lop["hops"], 2), "hops_p99": lop["hops_p99"],
+            "ms_per_step": round(lwall * 1000.0 / args.steps, 4),
+            "search_kernel_avg_ms": round(float(np.mean(lsearch)), 4),
+            "train_samples": info["samples"], "train_s": round(train_s, 2),
+            "speedup_vs_fp32_fixed": round(lvalue / value, 4),
+            "sweep": [{kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in s.items()}
+                      for s in lsweep]}
+
+        # ---- 3. serving: Poisson stream through the continuous-batching server
+        ns = args.serve_requests
+        rng = np.random.default_rng(502)
+        s_q = np.ascontiguousarray(w.q[rng.integers(0, nq, size=ns)])
+        s_qa = synth.partial_constraints(ns, w.cards, 504)
+        s_k = rng.choice(np.array([1, 10, 50, 100], dtype=np.int32), size=ns)
+        s_arr = synth.poisson_arrivals(ns, args.serve_rate, 501)
+        s_beam = np.zeros(ns, dtype=np.int32)  # the stop network chooses (automatic beam)
+        sq_d, sqa_d = torch.from_numpy(s_q).to(dev), torch.from_numpy(s_qa).to(dev)
+        gsi, gsd = nhq.nhq_bruteforce_hybrid_knn(ix, sq_d, sqa_d, k)
+        gsi, gsd = gsi.cpu().numpy(), gsd.cpu().numpy()
+        # the serving network: traces of training queries with the stream's
+        # constraint law (1..3 constrained attributes) at the automatic beam
+        s_beam_auto, s_ce = 256, 8
+        tqa_p = torch.from_numpy(synth.partial_constraints(tq.shape[0], w.cards, 505)).to(dev)
+        sparams, sinfo = train_stop_network(ixb, tq, tqa_p, k, s_beam_auto, epochs=30, check_every=s_ce,
+                                            n_init=args.n_init, expand=args.expand, seed=2)
+        nhq.nhq_mlp_load(ixb, sparams)
+        # budget factor: the smallest reaching the target on a validation slice (batch search)
+        nv = min(5000, ns)
+        s_cf = None
+        for cf in (1.5, 2.0, 2.5, 3.0, 4.0, 6.0):
+            vi, vd = nhq.nhq_hybrid_search(ixb, sq_d[:nv], sqa_d[:nv], k, s_beam_auto, n_init=args.n_init,
+                                           expand=args.expand, learned=2, stop_threshold=0.9,
+                                           check_every=s_ce, cap_factor=cf)
+            vr = recall_at_k(vi.cpu().numpy(), vd.cpu().numpy(), gsi[:nv], gsd[:nv], w.attrs, s_qa[:nv], k)
+            log("serving network: cap %.1f validation recall %.4f" % (cf, vr.mean()))
+            s_cf = cf
+            if vr.mean() >= args.target + 0.005:
+                break
+        torch.cuda.synchronize()
+        with nhq.Server(ixb, n_init=args.n_init, expand=args.expand, auto_beam=s_beam_auto,
+                        beam_small=s_beam_auto, beam_large=-1, max_k=100, ring=8192, learned_mode=2,
+                        cap_factor=s_cf, stop_threshold=0.9, check_every=s_ce, lifetime_s=120.0) as srv:
+            r = srv.run(s_q, s_qa, s_k, s_beam, s_arr, timeout_s=60.0)
+            slots = srv.slots
+            hz = srv.tick_hz
+        lat_ms = r["latency_s"] * 1000.0
+        svc_ms = (r["ticks"][:, 1].astype(np.float64) - r["ticks"][:, 0]) / hz * 1000.0
+        big = s_k >= 10
+        srec = recall_at_k(r["ids"][big, :10], r["dists"][big, :10], gsi[big], gsd[big], w.attrs,
+                           s_qa[big], k)
+        serving = {"offered_qps": args.serve_rate, "requests": ns,
+                   "sustained_qps": round(ns / r["elapsed_s"], 1),
+                   "p50_ms": round(float(np.percentile(lat_ms, 50)), 4),
+                   "p99_ms": round(float(np.percentile(lat_ms, 99)), 4),
+                   "max_ms": round(float(lat_ms.max()), 4),
+                   "device_service_p50_ms": round(float(np.percentile(svc_ms, 50)), 4),
+                   "device_service_p99_ms": round(float(np.percentile(svc_ms, 99)), 4),
+                   "recall_at_10_k_ge_10": round(float(srec.mean()), 5),
+                   "hops_mean": round(float(r["counters"][:, 1].mean()), 2),
+                   "k_mix": [1, 10, 50, 100], "constrained_attrs": "1..3 of 3",
+                   "beam": "learned budget at automatic beam %d (cap factor %.1f)" % (s_beam_auto, s_cf),
+                   "storage": "bf16", "slots": slots[0], "latency": "arrival to result seen by the host"}
+        log("serving: %d requests at %.0f/s offered: p50 %.3f ms, p99 %.3f ms, recall@10 %.4f" % (
+            ns, args.serve_rate, serving["p50_ms"], serving["p99_ms"], serving["recall_at_10_k_ge_10"]))
 
     # ---- CPU oracle on a bounded sample (same graph, entry sample, beam)
     cpu = None
@@ -202,23 +331,23 @@ def main():
         entry = oracle.entry_points(w.build_seed, w.n, args.n_entry)
         threads = os.cpu_count() or 1
         nsamp = 64
+        kw = dict(n_init=args.n_init, key_mode=oracle.KEY32, threads=threads, expand=args.expand)
         t = time.time()
-        oracle.search(adj, w.x, w.attrs, w.q[:nsamp], w.qattrs[:nsamp], k, beam, entry,
-                      n_init=args.n_init, key_mode=oracle.KEY32, threads=threads)
+        oracle.search(adj, w.x, w.attrs, w.q[:nsamp], w.qattrs[:nsamp], k, beam, entry, **kw)
         el = time.time() - t
         if el < args.cpu_seconds:
             nsamp = int(min(nq, max(nsamp, nsamp * args.cpu_seconds / max(el, 1e-3))))
             t = time.time()
-            oracle.search(adj, w.x, w.attrs, w.q[:nsamp], w.qattrs[:nsamp], k, beam, entry,
-                          n_init=args.n_init, key_mode=oracle.KEY32, threads=threads)
+            oracle.search(adj, w.x, w.attrs, w.q[:nsamp], w.qattrs[:nsamp], k, beam, entry, **kw)
             el = time.time() - t
         cpu = {"value": round(nsamp / el, 1), "unit": "queries/s", "cores": threads, "kind": "oracle",
-               "sample": "%d of %d queries, beam %d, same graph and entry sample, FP64 C oracle "
-                         "(entry-sample scan + joint pruning), %d threads" % (nsamp, nq, beam, threads)}
+               "sample": "%d of %d queries, beam %d, expand %d, same graph and entry sample, FP64 C "
+                         "oracle (entry-sample scan + joint pruning), %d threads" % (
+                             nsamp, nq, beam, args.expand, threads)}
         log("cpu oracle: %.1f QPS on %d threads" % (nsamp / el, threads))
 
     out = {
-        "metric": "hybrid QPS at Recall@10=0.95 on 1 GPU (plain FP32 fixed beam)",
+        "metric": "hybrid QPS at Recall@10=0.95 on 1 GPU, plain FP32 vs BF16+learned-stop; p99 ms",
         "value": round(value, 1),
         "unit": "queries/s",
         "n_gpus": 1,
@@ -228,16 +357,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.storage == "fp32" else args.storage,
+        "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "n": w.n, "d": w.d, "m": w.m, "cards": list(w.cards),
-                   "queries_per_step": nq, "k": k, "beam": beam, "degree": w.degree,
-                   "cand": w.cand, "n_entry": args.n_entry, "n_init": args.n_init,
-                   "expand": args.expand,
-                   "storage": args.storage, "recall_at_beam": round(op["recall"], 5),
-                   "qps_at_target_interp": None if q_at is None else round(q_at, 1),
+        "config": {"workload": w.name, "form": "plain FP32 fixed beam", "n": w.n, "d": w.d, "m": w.m,
+                   "cards": list(w.cards), "queries_per_step": nq, "k": k, "beam": beam,
+                   "degree": w.degree, "cand": w.cand, "n_entry": args.n_entry, "n_init": args.n_init,
+                   "expand": args.expand, "recall_at_beam": round(op["recall"], 5),
                    "build_s": round(build_s, 3), "exact_knn_s": round(gt_s, 3),
                    "parallelism": "single GPU"},
+        "p99_ms": None if serving is None else serving["p99_ms"],
+        "forms": forms,
+        "serving": serving,
         "sweep": sweep,
         "roofline": roof,
         "cpu_baseline": cpu,

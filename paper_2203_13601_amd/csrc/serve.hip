@@ -75,14 +75,18 @@ __device__ void doorbell(const ServeArgs &s, unsigned long long t_end)
     unsigned long long last = 0;
     uint32_t why = 0;
     for (;;) {
+        // relaxed polls (an acquire would invalidate caches on every poll);
+        // one acquire fence once new entries are seen
         unsigned long long t = 0;
         uint32_t stop = 0;
         if (lane == 0) {
-            t = __hip_atomic_load(s.tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+            t = __hip_atomic_load(s.tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             stop = __hip_atomic_load(s.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         }
         t = bcast64(t);
         stop = (uint32_t)__builtin_amdgcn_readfirstlane((int)stop);
+        if (t > last)
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
         for (unsigned long long idx = last + lane; idx < t; idx += 64)
             __hip_atomic_store(s.ready + (idx % (unsigned)s.cap), idx + 1, __ATOMIC_RELEASE,
                                __HIP_MEMORY_SCOPE_AGENT);
@@ -168,8 +172,8 @@ __global__ __launch_bounds__(64) void k_serve(const SearchArgs base, const Serve
         bool go = false;
         for (int polls = 0;; ++polls) {
             unsigned long long r = 0;
-            if (lane == 0)
-                r = __hip_atomic_load(s.ready + slot, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0)  // relaxed: an acquire per poll would invalidate the CU's L1
+                r = __hip_atomic_load(s.ready + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             r = bcast64(r);
             if (r == i + 1) {
                 go = true;
