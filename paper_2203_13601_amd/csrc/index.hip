@@ -8,6 +8,8 @@
 #include <unordered_set>
 #include <vector>
 
+#include <cstring>
+
 #include "nhq_internal.h"
 
 namespace nhq {
@@ -158,18 +160,24 @@ __global__ __launch_bounds__(64) void k_pad_queries(const float *__restrict__ q,
                                                     int dp, int m, float *__restrict__ qpad,
                                                     float *__restrict__ qnorm,
                                                     uint32_t *__restrict__ qword,
-                                                    uint32_t *__restrict__ qmask)
+                                                    uint32_t *__restrict__ qmask,
+                                                    uint32_t *__restrict__ qexact)
 {
     const int lane = threadIdx.x;
     for (int64_t i = blockIdx.x; i < nq; i += gridDim.x) {
         float s = 0.0f;
+        bool exact = true;
         for (int c = lane; c < dp; c += 64) {
             const float v = c < d ? q[i * d + c] : 0.0f;
             qpad[i * dp + c] = v;
             s = fmaf(v, v, s);
+            exact = exact && v == rintf(v) && fabsf(v) <= 256.0f;
         }
         for (int o = 32; o > 0; o >>= 1)
             s += __shfl_xor(s, o, 64);
+        const bool all_exact = __ballot(!exact) == 0;
+        if (lane == 0 && qexact)
+            qexact[i] = all_exact ? 1u : 0u;
         if (lane == 0) {
             qnorm[i] = s;
             uint32_t w = 0, mk = 0;
@@ -226,7 +234,7 @@ void free_index(Index *ix)
     if (ix->vecs && ix->vecs != ix->vec32)
         (void)hipFree(ix->vecs);
     void *ptrs[] = {ix->vec32, ix->scale, ix->attr, ix->norm, ix->adj, ix->entry, ix->entry_vec,
-                    ix->entry_norm, ix->entry_attr, ix->err, ix->ws, ix->mlp, ix->logp};
+                    ix->entry_norm, ix->entry_attr, ix->entry_bf16, ix->err, ix->ws, ix->mlp, ix->logp};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -235,12 +243,13 @@ void free_index(Index *ix)
 }  // namespace
 
 int launch_pad_queries(const float *q, const uint8_t *qa, int64_t nq, int d, int dp, int m,
-                       float *qpad, float *qnorm, uint32_t *qword, uint32_t *qmask, hipStream_t st)
+                       float *qpad, float *qnorm, uint32_t *qword, uint32_t *qmask, uint32_t *qexact,
+                       hipStream_t st)
 {
     if (nq == 0)
         return NHQ_OK;
     hipLaunchKernelGGL(k_pad_queries, dim3(grid_for(nq, 1)), dim3(64), 0, st, q, qa, nq, d, dp, m,
-                       qpad, qnorm, qword, qmask);
+                       qpad, qnorm, qword, qmask, qexact);
     NHQ_HIP(hipGetLastError());
     return NHQ_OK;
 }
@@ -442,6 +451,31 @@ int nhq_index_create(const float *vecs, const uint8_t *attrs, int64_t n, int32_t
             rc = fail(NHQ_EHIP, "log-frequency upload failed");
             break;
         }
+        // exact bf16 copy of the entry sample (integer values of magnitude <= 256)
+        if (ix->dp <= 128) {
+            std::vector<float> ev((size_t)ne * ix->dp);
+            if (hipMemcpy(ev.data(), ix->entry_vec, sizeof(float) * ev.size(), hipMemcpyDeviceToHost) != hipSuccess) {
+                rc = fail(NHQ_EHIP, "entry sample read-back failed");
+                break;
+            }
+            bool exact = true;
+            std::vector<uint16_t> eb(ev.size());
+            for (size_t t = 0; t < ev.size() && exact; ++t) {
+                const float v = ev[t];
+                uint32_t bits;
+                std::memcpy(&bits, &v, 4);
+                exact = v == std::nearbyint(v) && std::fabs(v) <= 256.0f && (bits & 0xFFFFu) == 0;
+                eb[t] = (uint16_t)(bits >> 16);
+            }
+            if (exact) {
+                if (hipMalloc(&ix->entry_bf16, sizeof(uint16_t) * eb.size()) != hipSuccess ||
+                    hipMemcpy(ix->entry_bf16, eb.data(), sizeof(uint16_t) * eb.size(), hipMemcpyHostToDevice) !=
+                        hipSuccess) {
+                    rc = fail(NHQ_ENOMEM, "bf16 entry sample allocation failed");
+                    break;
+                }
+            }
+        }
     } while (0);
     if (rc != NHQ_OK) {
         free_index(ix);
@@ -567,24 +601,30 @@ int nhq_seed_rank(const nhq_index *h, const float *queries, const uint8_t *qattr
     if (!queries || !cand || (ix->m > 0 && !qattrs))
         return fail(NHQ_EINVAL, "null array argument");
     hipStream_t st = (hipStream_t)stream;
-    float *qpad = nullptr, *qnorm = nullptr;
-    uint32_t *qw = nullptr, *qm = nullptr;
-    NHQ_HIP(hipMallocAsync((void **)&qpad, sizeof(float) * (size_t)nq * ix->dp, st));
-    NHQ_HIP(hipMallocAsync((void **)&qnorm, sizeof(float) * (size_t)nq, st));
-    NHQ_HIP(hipMallocAsync((void **)&qw, sizeof(uint32_t) * (size_t)nq, st));
-    NHQ_HIP(hipMallocAsync((void **)&qm, sizeof(uint32_t) * (size_t)nq, st));
-    int rc = launch_pad_queries(queries, qattrs, nq, ix->d, ix->dp, ix->m, qpad, qnorm, qw, qm, st);
+    // one stream-ordered block: padded rows, norms, codes, masks, exactness
+    // flags and (for the matrix-core ranking) the key matrix
+    const size_t ne_pad = (size_t)(ix->n_entry + 63) / 64 * 64;
+    const bool dense = ix->n_entry <= 8192;
+    const size_t f_rows = (size_t)nq * ix->dp, f_small = (size_t)nq;
+    const size_t words = f_rows + 5 * f_small + (dense ? (size_t)nq * ne_pad : 0) + 64;
+    uint32_t *blk = nullptr;
+    NHQ_HIP(hipMallocAsync((void **)&blk, sizeof(uint32_t) * words, st));
+    float *qpad = reinterpret_cast<float *>(blk);
+    float *qnorm = qpad + f_rows;
+    uint32_t *qw = reinterpret_cast<uint32_t *>(qnorm + f_small);
+    uint32_t *qm = qw + f_small;
+    uint32_t *qx = qm + f_small;
+    float *keys = reinterpret_cast<float *>((reinterpret_cast<uintptr_t>(qx + f_small) + 255) & ~uintptr_t(255));
+    int rc = launch_pad_queries(queries, qattrs, nq, ix->d, ix->dp, ix->m, qpad, qnorm, qw, qm, qx, st);
     if (rc == NHQ_OK) {
-        if (ix->n_entry <= 8192)
-            rc = launch_seed_rank(ix, qpad, qnorm, qw, qm, nq, n_cand, cand, st);
+        if (dense)
+            rc = launch_seed_rank(ix, qpad, qnorm, qw, qm, qx, nq, n_cand, keys, cand, st);
         else
             rc = launch_dense_topk(qpad, qnorm, qw, qm, nq, ix->entry_vec, ix->entry_norm,
                                    ix->entry_attr, ix->n_entry, ix->dp, ix->m, 0, 0, n_cand, cand,
                                    nullptr, st);
     }
-    void *bufs[] = {qpad, qnorm, qw, qm};
-    for (void *b : bufs)
-        (void)hipFreeAsync(b, st);
+    (void)hipFreeAsync(blk, st);
     return rc;
 }
 

@@ -56,6 +56,10 @@ struct Index {
     float *entry_vec = nullptr;     // [n_entry][dp] float32 rows of the entry sample
     float *entry_norm = nullptr;    // [n_entry]
     uint32_t *entry_attr = nullptr; // [n_entry]
+    // bf16 copy of entry_vec when every value is an integer of magnitude
+    // <= 256 and dp <= 128: then bf16 products summed in float32 are exact,
+    // and the ranking uses the bf16 matrix-core instructions (else null)
+    uint16_t *entry_bf16 = nullptr;
     uint32_t *err = nullptr;    // device error word
     // per-index workspace (grown on demand)
     void *ws = nullptr;
@@ -104,12 +108,17 @@ int launch_dense_topk(const float *A, const float *A_norm, const uint32_t *A_att
                       int self_exclude, int K, int32_t *out_ids, float *out_keys, hipStream_t st);
 
 // seed ranking of the entry sample (see seed.hip): positions of the K best
+// keys: scratch of nq * ((n_entry + 63) / 64 * 64) floats; qexact (nullable):
+// per query, nonzero when every value is an integer of magnitude <= 256
 int launch_seed_rank(const Index *ix, const float *qpad, const float *qnorm, const uint32_t *qword,
-                     const uint32_t *qmask, int64_t nq, int K, int32_t *cand, hipStream_t st);
+                     const uint32_t *qmask, const uint32_t *qexact, int64_t nq, int K, float *keys,
+                     int32_t *cand, hipStream_t st);
 
-// queries -> zero-padded float32 rows, squared norms, packed codes and masks
+// queries -> zero-padded float32 rows, squared norms, packed codes and masks,
+// and (qexact nullable) whether every value is an integer of magnitude <= 256
 int launch_pad_queries(const float *q, const uint8_t *qa, int64_t nq, int d, int dp, int m,
-                       float *qpad, float *qnorm, uint32_t *qword, uint32_t *qmask, hipStream_t st);
+                       float *qpad, float *qnorm, uint32_t *qword, uint32_t *qmask, uint32_t *qexact,
+                       hipStream_t st);
 
 }  // namespace nhq
 

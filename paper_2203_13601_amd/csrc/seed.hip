@@ -20,6 +20,7 @@ namespace nhq {
 namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ int chi_of(uint32_t a, uint32_t qword, uint32_t qmask)
 {
@@ -35,6 +36,8 @@ struct KeyArgs {
     const float *ev;      // [ne][DP]
     const float *en;      // [ne]
     const uint32_t *ea;   // [ne]
+    const uint16_t *eb;   // [ne][DP] exact bf16 copy of ev, or null
+    const uint32_t *qx;   // [nq] query rows exact in bf16 (nullable)
     float *keys;          // [nq][ne_pad]
     int64_t nq;
     int ne, ne_pad;
@@ -49,13 +52,74 @@ struct KShape {
     static constexpr int LDSW = KC + 4;  // padded row stride (floats): no bank conflicts
 };
 
+// Keys of one 64-entry tile for a wave's 16 queries: lane (rl, lq) holds
+// query rl against entries c0 + 16 s + 4 lq + r in acc[s][r].  They go
+// through the wave's LDS area (16 rows of 68 floats) so that every store
+// instruction writes four whole 256-byte rows of the key matrix.
+__device__ __forceinline__ void store_keys(const KeyArgs &a, const f32x4 (&acc)[4], int c0, int64_t row0, int rl,
+                                           int lq, float rn, uint32_t qw, uint32_t qm, float mq, float *stage)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int cb0 = c0 + 16 * s + 4 * lq;
+        float4 nrm;
+        uint4 atr;
+        if (cb0 + 3 < a.ne) {
+            nrm = *reinterpret_cast<const float4 *>(a.en + cb0);
+            atr = *reinterpret_cast<const uint4 *>(a.ea + cb0);
+        } else {
+            const int c1 = min(cb0 + 1, a.ne - 1), c2 = min(cb0 + 2, a.ne - 1);
+            const int c3 = min(cb0 + 3, a.ne - 1), cz = min(cb0, a.ne - 1);
+            nrm = make_float4(a.en[cz], a.en[c1], a.en[c2], a.en[c3]);
+            atr = make_uint4(a.ea[cz], a.ea[c1], a.ea[c2], a.ea[c3]);
+        }
+        const float nb4[4] = {nrm.x, nrm.y, nrm.z, nrm.w};
+        const uint32_t at4[4] = {atr.x, atr.y, atr.z, atr.w};
+        float k4[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float d2 = fmaxf(rn + nb4[r] - 2.0f * acc[s][r], 0.0f);
+            const int c = chi_of(at4[r], qw, qm);
+            const float mult = mq == 0.0f ? 1.0f : (mq + c) * (mq + c);
+            k4[r] = cb0 + r < a.ne ? d2 * mult : __int_as_float(0x7F800000);
+        }
+        *reinterpret_cast<float4 *>(stage + rl * 68 + 16 * s + 4 * lq) = make_float4(k4[0], k4[1], k4[2], k4[3]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int idx = 64 * u + lane, r = idx >> 4, c4 = idx & 15;
+        const int64_t row = row0 + r;
+        if (row < a.nq)
+            *reinterpret_cast<float4 *>(a.keys + row * a.ne_pad + c0 + 4 * c4) =
+                *reinterpret_cast<const float4 *>(stage + r * 68 + 4 * c4);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Whether the workgroup's 64 queries are all exact in bf16 and the index
+// holds the exact bf16 entry copy (the bf16 kernel's share of the work).
+template <int DP>
+__device__ __forceinline__ bool group_exact(const KeyArgs &a, int64_t rowc)
+{
+    if (!(DP <= 128 && DP % 32 == 0) || a.eb == nullptr || a.qx == nullptr)
+        return false;
+    return __syncthreads_and(a.qx[rowc] != 0u) != 0;
+}
+
 // A workgroup of 4 waves: 64 queries (16 per wave) against 256 entries; the
 // entries' rows are staged through LDS 64 at a time and shared by the waves.
+// Float32 products (v_mfma_f32_16x16x4f32); workgroups whose queries are
+// all exact in bf16 are left to k_entry_keys_b16.
 template <int DP>
 __global__ __launch_bounds__(256) void k_entry_keys(const KeyArgs a)
 {
     using K = KShape<DP>;
-    __shared__ __align__(16) float tile[64 * K::LDSW];
+    // entry tile; afterwards the key staging of the four waves
+    __shared__ __align__(16) float tile[64 * K::LDSW > 4 * 16 * 68 ? 64 * K::LDSW : 4 * 16 * 68];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int rl = lane & 15, lq = lane >> 4;
     const int64_t row = (int64_t)blockIdx.x * 64 + wave * 16 + rl;
@@ -65,6 +129,8 @@ __global__ __launch_bounds__(256) void k_entry_keys(const KeyArgs a)
     const float rn = a.qnorm[rowc];
     const uint32_t qw = a.qword[rowc], qm = a.qmask[rowc];
     const float mq = (float)(__popc(qm) / 8);
+    if (group_exact<DP>(a, rowc))
+        return;  // done by k_entry_keys_b16
     float4 ra[K::NT];
     if constexpr (K::NK == 1) {
 #pragma unroll
@@ -77,70 +143,116 @@ __global__ __launch_bounds__(256) void k_entry_keys(const KeyArgs a)
 #pragma unroll
         for (int s = 0; s < 4; ++s)
             acc[s] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        for (int kc = 0; kc < K::NK; ++kc) {
-            // stage 64 entry rows (dims kc*KC .. +KC) into LDS
+        {
+            for (int kc = 0; kc < K::NK; ++kc) {
+                // stage 64 entry rows (dims kc*KC .. +KC) into LDS
+                __syncthreads();
+                for (int i = threadIdx.x; i < 64 * (K::KC / 4); i += 256) {
+                    const int r = i / (K::KC / 4), c4 = i - r * (K::KC / 4);
+                    const int col = min(c0 + r, a.ne - 1);
+                    const float4 v = reinterpret_cast<const float4 *>(a.ev + (int64_t)col * DP + kc * K::KC)[c4];
+                    *reinterpret_cast<float4 *>(tile + r * K::LDSW + 4 * c4) = v;
+                }
+                __syncthreads();
+                if constexpr (K::NK > 1) {
+#pragma unroll
+                    for (int t = 0; t < K::NT; ++t)
+                        ra[t] = qrow[kc * (K::KC / 4) + 4 * t + lq];
+                }
+#pragma unroll
+                for (int t = 0; t < K::NT; ++t) {
+                    float4 cb[4];
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        cb[s] = *reinterpret_cast<const float4 *>(tile + (16 * s + rl) * K::LDSW + 16 * t + 4 * lq);
+                    const float4 rv = ra[t];
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[s].x, rv.x, acc[s], 0, 0, 0);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[s].y, rv.y, acc[s], 0, 0, 0);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[s].z, rv.z, acc[s], 0, 0, 0);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[s].w, rv.w, acc[s], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();  // the tile's products are done: its LDS stages the keys
+        store_keys(a, acc, c0, (int64_t)blockIdx.x * 64 + wave * 16, rl, lq, rn, qw, qm, mq, tile + wave * 16 * 68);
+    }
+}
+
+// The same product on the bf16 matrix cores (v_mfma_f32_16x16x32_bf16) for
+// workgroups whose queries are all integers of magnitude <= 256 against the
+// exact bf16 copy of the entry sample: every product is exact in float32 and
+// every partial sum is an integer below 2^24 (rows of at most 128
+// elements), so the keys are bit-identical to the float32 kernel's.
+template <int DP>
+__global__ __launch_bounds__(256) void k_entry_keys_b16(const KeyArgs a)
+{
+    static_assert(DP <= 128 && DP % 32 == 0, "bf16 path: rows of at most 128 elements");
+    __shared__ __align__(16) uint16_t t16[64 * (DP + 8) < 2 * 4 * 16 * 68 ? 2 * 4 * 16 * 68 : 64 * (DP + 8)];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int rl = lane & 15, lq = lane >> 4;
+    const int64_t row = (int64_t)blockIdx.x * 64 + wave * 16 + rl;
+    const bool row_ok = row < a.nq;
+    const int64_t rowc = row_ok ? row : a.nq - 1;
+    const float rn = a.qnorm[rowc];
+    const uint32_t qw = a.qword[rowc], qm = a.qmask[rowc];
+    const float mq = (float)(__popc(qm) / 8);
+    constexpr int NB = DP / 32;   // 32-element chunks
+    constexpr int LDSB = DP + 8;  // row stride in LDS (elements)
+    if (!group_exact<DP>(a, rowc))
+        return;  // left to the float32 kernel
+    bf16x8 qb[NB];
+    {
+        // query elements 32 t + 8 lq + 0..7, exact in bf16 (the top half of the float)
+        const float *qf = a.qpad + rowc * DP;
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+            uint32_t u[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t lo = __float_as_uint(qf[32 * t + 8 * lq + 2 * e]);
+                const uint32_t hi = __float_as_uint(qf[32 * t + 8 * lq + 2 * e + 1]);
+                u[e] = (lo >> 16) | (hi & 0xFFFF0000u);
+            }
+            qb[t] = __builtin_bit_cast(bf16x8, make_uint4(u[0], u[1], u[2], u[3]));
+        }
+    }
+    const int cbeg = blockIdx.y * 256;
+    for (int c0 = cbeg; c0 < cbeg + 256 && c0 < a.ne_pad; c0 += 64) {
+        f32x4 acc[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            acc[s] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        {
+            // stage 64 bf16 entry rows, then 4 x NB matrix-core products
             __syncthreads();
-            for (int i = threadIdx.x; i < 64 * (K::KC / 4); i += 256) {
-                const int r = i / (K::KC / 4), c4 = i - r * (K::KC / 4);
+            for (int i = threadIdx.x; i < 64 * (DP / 8); i += 256) {
+                const int r = i / (DP / 8), c8 = i - r * (DP / 8);
                 const int col = min(c0 + r, a.ne - 1);
-                const float4 v = reinterpret_cast<const float4 *>(a.ev + (int64_t)col * DP + kc * K::KC)[c4];
-                *reinterpret_cast<float4 *>(tile + r * K::LDSW + 4 * c4) = v;
+                const uint4 v = reinterpret_cast<const uint4 *>(a.eb + (int64_t)col * DP)[c8];
+                *reinterpret_cast<uint4 *>(t16 + r * LDSB + 8 * c8) = v;
             }
             __syncthreads();
-            if constexpr (K::NK > 1) {
 #pragma unroll
-                for (int t = 0; t < K::NT; ++t)
-                    ra[t] = qrow[kc * (K::KC / 4) + 4 * t + lq];
-            }
+            for (int t = 0; t < NB; ++t) {
 #pragma unroll
-            for (int t = 0; t < K::NT; ++t) {
-                float4 cb[4];
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    cb[s] = *reinterpret_cast<const float4 *>(tile + (16 * s + rl) * K::LDSW + 16 * t + 4 * lq);
-                const float4 rv = ra[t];
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[s].x, rv.x, acc[s], 0, 0, 0);
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[s].y, rv.y, acc[s], 0, 0, 0);
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[s].z, rv.z, acc[s], 0, 0, 0);
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[s].w, rv.w, acc[s], 0, 0, 0);
+                for (int s = 0; s < 4; ++s) {
+                    const uint4 ev = *reinterpret_cast<const uint4 *>(t16 + (16 * s + rl) * LDSB + 32 * t + 8 * lq);
+                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ev), qb[t],
+                                                                    acc[s], 0, 0, 0);
+                }
             }
         }
-        if (!row_ok)
-            continue;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int cb0 = c0 + 16 * s + 4 * lq;
-            float4 nrm;
-            uint4 atr;
-            if (cb0 + 3 < a.ne) {
-                nrm = *reinterpret_cast<const float4 *>(a.en + cb0);
-                atr = *reinterpret_cast<const uint4 *>(a.ea + cb0);
-            } else {
-                const int c1 = min(cb0 + 1, a.ne - 1), c2 = min(cb0 + 2, a.ne - 1);
-                const int c3 = min(cb0 + 3, a.ne - 1), cz = min(cb0, a.ne - 1);
-                nrm = make_float4(a.en[cz], a.en[c1], a.en[c2], a.en[c3]);
-                atr = make_uint4(a.ea[cz], a.ea[c1], a.ea[c2], a.ea[c3]);
-            }
-            const float nb4[4] = {nrm.x, nrm.y, nrm.z, nrm.w};
-            const uint32_t at4[4] = {atr.x, atr.y, atr.z, atr.w};
-            float k4[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float d2 = fmaxf(rn + nb4[r] - 2.0f * acc[s][r], 0.0f);
-                const int c = chi_of(at4[r], qw, qm);
-                const float mult = mq == 0.0f ? 1.0f : (mq + c) * (mq + c);
-                k4[r] = cb0 + r < a.ne ? d2 * mult : __int_as_float(0x7F800000);
-            }
-            *reinterpret_cast<float4 *>(a.keys + row * a.ne_pad + cb0) = make_float4(k4[0], k4[1], k4[2], k4[3]);
-        }
+        __syncthreads();  // the tile's products are done: its LDS stages the keys
+        store_keys(a, acc, c0, (int64_t)blockIdx.x * 64 + wave * 16, rl, lq, rn, qw, qm, mq,
+                   reinterpret_cast<float *>(t16) + wave * 16 * 68);
     }
 }
 
@@ -211,16 +323,16 @@ __global__ __launch_bounds__(64) void k_entry_select(const float *__restrict__ k
 
 // positions of the n_cand best entry-sample members per query (unordered)
 int launch_seed_rank(const Index *ix, const float *qpad, const float *qnorm, const uint32_t *qword,
-                     const uint32_t *qmask, int64_t nq, int K, int32_t *cand, hipStream_t st)
+                     const uint32_t *qmask, const uint32_t *qexact, int64_t nq, int K, float *keys,
+                     int32_t *cand, hipStream_t st)
 {
     const int ne = ix->n_entry;
     const int ne_pad = (ne + 63) / 64 * 64;
     const int nj = ne_pad / 64;
     if (nj > 128)
         return fail(NHQ_EINVAL, "entry sample larger than 8192");
-    float *keys = nullptr;
-    NHQ_HIP(hipMallocAsync((void **)&keys, sizeof(float) * (size_t)nq * ne_pad, st));
-    KeyArgs a{qpad, qnorm, qword, qmask, ix->entry_vec, ix->entry_norm, ix->entry_attr, keys, nq, ne, ne_pad};
+    KeyArgs a{qpad, qnorm, qword, qmask, ix->entry_vec, ix->entry_norm, ix->entry_attr, ix->entry_bf16,
+              qexact, keys, nq, ne, ne_pad};
     const dim3 grid((unsigned)((nq + 63) / 64), (unsigned)((ne_pad + 255) / 256));
     int rc = NHQ_OK;
     switch (ix->dp) {
@@ -228,14 +340,21 @@ int launch_seed_rank(const Index *ix, const float *qpad, const float *qnorm, con
     case DPV:                                                                      \
         hipLaunchKernelGGL(k_entry_keys<DPV>, grid, dim3(256), 0, st, a);          \
         break;
-        NHQ_K(32)
-        NHQ_K(64)
-        NHQ_K(96)
-        NHQ_K(128)
+#define NHQ_KB(DPV)                                                                \
+    case DPV:                                                                      \
+        if (a.eb && a.qx)                                                          \
+            hipLaunchKernelGGL(k_entry_keys_b16<DPV>, grid, dim3(256), 0, st, a);  \
+        hipLaunchKernelGGL(k_entry_keys<DPV>, grid, dim3(256), 0, st, a);          \
+        break;
+        NHQ_KB(32)
+        NHQ_KB(64)
+        NHQ_KB(96)
+        NHQ_KB(128)
         NHQ_K(256)
         NHQ_K(512)
         NHQ_K(960)
         NHQ_K(1024)
+#undef NHQ_KB
 #undef NHQ_K
     default:
         rc = fail(NHQ_EINVAL, "unsupported padded dimension");
@@ -255,7 +374,6 @@ int launch_seed_rank(const Index *ix, const float *qpad, const float *qnorm, con
         if (hipGetLastError() != hipSuccess)
             rc = fail(NHQ_EHIP, "entry select launch failed");
     }
-    (void)hipFreeAsync(keys, st);
     return rc;
 }
 
