@@ -80,7 +80,7 @@ def main():
     ap.add_argument("--beam", type=int, default=0, help="fixed beam (skip the choice)")
     ap.add_argument("--n-entry", type=int, default=4096)
     ap.add_argument("--n-init", type=int, default=16)
-    ap.add_argument("--expand", type=int, default=4, help="vertices expanded per step")
+    ap.add_argument("--expand", type=int, default=6, help="vertices expanded per step")
     ap.add_argument("--plain-only", action="store_true", help="skip the bf16/learned and serving legs")
     ap.add_argument("--serve-rate", type=float, default=50_000.0)
     ap.add_argument("--serve-requests", type=int, default=50_000)
@@ -170,7 +170,7 @@ def main():
 
     # ---- 1. plain form: float32 storage, fixed beam
     sweep = []
-    beams = [args.beam] if args.beam else [10, 16, 24, 32, 40, 48, 56, 64, 96, 128, 256, 512]
+    beams = [args.beam] if args.beam else [10, 16, 20, 24, 28, 32, 36, 40, 48, 56, 64, 96, 128, 256, 512]
     for beam in beams:
         if beam < k:
             continue
@@ -237,7 +237,7 @@ def main():
             info["samples"], train_s, info["losses"][-1]))
         lsweep = []
         lkw = None
-        for cf in (1.25, 1.5, 1.75, 2.0, 2.5, 3.0):
+        for cf in (1.0, 1.125, 1.25, 1.5, 1.75, 2.0, 2.5, 3.0):
             kw = dict(learned=2, stop_threshold=0.9, check_every=ce, cap_factor=cf)
             p = point(ixb, l_train, **kw)
             p["cap_factor"] = cf
