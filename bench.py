@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (counter scaling)")
+    ap.add_argument("--workload", default="plain", choices=["plain", "precision"],
+                    help="precision: the d = 960 storage forms (fp32 / bf16 / fp8 + exact rerank)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -102,6 +104,8 @@ def main():
     from paper_2203_13601_amd.learned import train_stop_network
     from paper_2203_13601_amd.metrics import qps_at_recall, recall_at_k, search_bytes_per_query
 
+    if args.workload == "precision":
+        return precision_form(args)
     dev = torch.device("cuda:0")
     t_gen = time.time()
     w = synth.config2(n=args.n, nq=args.nq)
@@ -156,17 +160,20 @@ def main():
         search_ms = [e[1].elapsed_time(e[2]) for e in evs]
         return wall, rank_ms, search_ms
 
-    def point(index, beam, **kw):
+    def point(index, beam, elem=4, **kw):
         _, _, cnt = step(index, beam, counters=True, **kw)
         torch.cuda.synchronize()
         rec = recall_at_k(ids.cpu().numpy(), dists.cpu().numpy(), gi, gd, w.attrs, w.qattrs, k)
         cnt = cnt.cpu().numpy().astype(np.float64)
         step(index, beam, **kw)
         wall, rk, se = timed(index, beam, 3, **kw)
+        bq_p = search_bytes_per_query(d_pad=128, elem_bytes=elem, R=w.degree, k=k, n_cand=n_cand,
+                                      ndc=float(cnt[:, 0].mean()), hops=float(cnt[:, 1].mean()), d=w.d, m=w.m)
         return {"beam": beam, "recall": float(rec.mean()), "qps": nq * 3 / wall,
                 "ndc": float(cnt[:, 0].mean()), "hops": float(cnt[:, 1].mean()),
                 "hops_p99": float(np.percentile(cnt[:, 1], 99)),
-                "rank_ms": float(np.median(rk)), "search_ms": float(np.median(se))}
+                "rank_ms": float(np.median(rk)), "search_ms": float(np.median(se)),
+                "search_hbm_frac": bq_p * nq / (float(np.median(se)) / 1000.0) / 8.0e12}
 
     # ---- 1. plain form: float32 storage, fixed beam
     sweep = []
@@ -206,6 +213,22 @@ def main():
             "kernel_avg_ms": round(search_avg_s * 1000.0, 4),
             "rank_kernels_avg_ms": round(float(np.mean(rank_ms)), 4)}
 
+    # random-row gather ceiling at the same row size and lane layout
+    waves, rounds = 65536, 20
+    nhq.nhq_gather_probe(ix, waves, rounds)
+    pe = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    pe[0].record()
+    for _ in range(3):
+        _, rows = nhq.nhq_gather_probe(ix, waves, rounds)
+    pe[1].record()
+    torch.cuda.synchronize()
+    gather_gbs = rows * 128 * 4 / (pe[0].elapsed_time(pe[1]) / 3 / 1000.0) / 1e9
+    roof["gather_ceiling"] = round(gather_gbs, 1)
+    roof["frac_of_gather_ceiling"] = round(achieved / gather_gbs, 4)
+    log("random 512-byte row gathers: %.0f GB/s; the search reaches %.1f%% of that" % (
+        gather_gbs, 100.0 * achieved / gather_gbs))
+
     if args.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
         dst = torch.empty_like(src)
@@ -239,7 +262,7 @@ def main():
         lkw = None
         for cf in (1.0, 1.125, 1.25, 1.5, 1.75, 2.0, 2.5, 3.0):
             kw = dict(learned=2, stop_threshold=0.9, check_every=ce, cap_factor=cf)
-            p = point(ixb, l_train, **kw)
+            p = point(ixb, l_train, elem=2, **kw)
             p["cap_factor"] = cf
             lsweep.append(p)
             log("bf16+learned cap %.2f recall %.4f hops %.1f (p99 %.0f) search %.3fms" % (
@@ -340,7 +363,12 @@ def main():
             t = time.time()
             oracle.search(adj, w.x, w.attrs, w.q[:nsamp], w.qattrs[:nsamp], k, beam, entry, **kw)
             el = time.time() - t
+        n1 = min(nq, max(16, int(nsamp / threads)))
+        t = time.time()
+        oracle.search(adj, w.x, w.attrs, w.q[:n1], w.qattrs[:n1], k, beam, entry, **dict(kw, threads=1))
+        el1 = time.time() - t
         cpu = {"value": round(nsamp / el, 1), "unit": "queries/s", "cores": threads, "kind": "oracle",
+               "single_thread_value": round(n1 / el1, 1),
                "sample": "%d of %d queries, beam %d, expand %d, same graph and entry sample, FP64 C "
                          "oracle (entry-sample scan + joint pruning), %d threads" % (
                              nsamp, nq, beam, args.expand, threads)}
@@ -372,6 +400,163 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    print(json.dumps(out), flush=True)
+
+
+def precision_form(args):
+    """The storage forms on the precision-form shape: d = 960 Gaussian mixture
+    (64 centres), 4 attributes of cardinality 2/3/5/10, all constrained.  One
+    graph (built from the float32 rows) serves float32, bf16 and fp8 e4m3
+    (per-row scale) storage; bf16 and fp8 re-score the first 4k eligible
+    entries from the float32 copy.  For each form: the smallest beam reaching
+    Recall@10 >= target, its timed step, the search kernel's HBM fraction and
+    the relative error of every returned distance against FP64."""
+    import torch
+    import synth
+    import paper_2203_13601_amd as nhq
+    from paper_2203_13601_amd.metrics import recall_at_k, search_bytes_per_query
+    dev = torch.device("cuda:0")
+    w = synth.config3(n=args.n, nq=args.nq)
+
+    # FP64 references of the measurement (plain numpy): Gamma = delta (1 + chi / m_q)
+    def gamma_fp64(qv, qattr, xv, xattr):
+        cons = qattr != 0xFF
+        mq = int(cons.sum())
+        chi = int((cons & (qattr != xattr)).sum())
+        dl = float(np.sqrt(((qv.astype(np.float64) - xv.astype(np.float64)) ** 2).sum()))
+        return dl if mq == 0 else dl * (1.0 + chi / mq)
+
+    def decode_bf16(bits):
+        return (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+    def decode_e4m3(codes, scales):
+        c = codes.astype(np.int64)
+        sgn = np.where(c >> 7, -1.0, 1.0)
+        e, mnt = (c >> 3) & 15, c & 7
+        val = np.where(e == 0, mnt / 8.0 * 2.0 ** -6, (1.0 + mnt / 8.0) * 2.0 ** (e - 7.0))
+        return sgn * val * scales[:, None]
+    x = torch.from_numpy(w.x).to(dev)
+    a = torch.from_numpy(w.attrs).to(dev)
+    q = torch.from_numpy(w.q).to(dev)
+    qa = torch.from_numpy(w.qattrs).to(dev)
+    t0 = time.time()
+    ix = nhq.nhq_build_index(x, a, degree=w.degree, cand=w.cand, n_entry=args.n_entry, seed=w.build_seed)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    log("built %s in %.1fs" % (w.name, build_s))
+    gi, gd = nhq.nhq_bruteforce_hybrid_knn(ix, q, qa, w.k)
+    gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
+    adj = nhq.nhq_index_get_graph(ix)
+    k, nq = w.k, w.nq
+    n_cand = min(args.n_entry, args.n_init + 16)
+    cand = torch.empty((nq, n_cand), dtype=torch.int32, device=dev)
+    nsamp = min(nq, 1000)
+
+    def gamma64(ids, dist):
+        """|Gamma returned - Gamma FP64| / Gamma FP64 for every returned result of the sample"""
+        errs = []
+        for i in range(nsamp):
+            for v, g in zip(ids[i], dist[i]):
+                if v < 0:
+                    continue
+                ex = gamma_fp64(w.q[i], w.qattrs[i], w.x[v], w.attrs[v])
+                errs.append(abs(float(g) - ex) / max(ex, 1e-30))
+        e = np.asarray(errs)
+        return {"results": int(e.size), "max": float(e.max()), "p99": float(np.percentile(e, 99)),
+                "mean": float(e.mean())}
+
+    forms = {}
+    for storage, elem, scale_b, rr in (("fp32", 4, 0, 0), ("bf16", 2, 0, 4), ("fp8", 1, 4, 4)):
+        index = ix if storage == "fp32" else nhq.nhq_index_create(x, a, storage=storage, n_entry=args.n_entry,
+                                                                   seed=w.build_seed, degree=w.degree)
+        if index is not ix:
+            nhq.nhq_index_set_graph(index, adj)
+        kw = dict(n_init=args.n_init, expand=args.expand, rerank=rr)
+
+        def step(beam, counters=False):
+            nhq.nhq_seed_rank(index, q, qa, n_cand, out=cand)
+            return nhq.nhq_search_seeded(index, q, qa, cand, k, beam, counters=counters, **kw)
+
+        chosen = None
+        sweep = []
+        beams = (10, 16, 24, 32, 40, 48, 64, 96, 128, 192, 256, 384, 512)
+        for beam in beams:
+            if beam < rr * k:
+                continue
+            ids, dist, cnt = step(beam, counters=True)
+            torch.cuda.synchronize()
+            ids_np, dist_np = ids.cpu().numpy(), dist.cpu().numpy()
+            rec = float(recall_at_k(ids_np, dist_np, gi, gd, w.attrs, w.qattrs, k).mean())
+            c = cnt.cpu().numpy().astype(np.float64)
+            sweep.append({"beam": beam, "recall": round(rec, 5), "ndc": round(c[:, 0].mean(), 1),
+                          "hops": round(c[:, 1].mean(), 1)})
+            log("%s beam %d recall %.4f" % (storage, beam, rec))
+            if rec >= args.target:
+                chosen = (beam, rec, c, ids_np, dist_np)
+                break
+        if chosen is None:
+            chosen = (beam, rec, c, ids_np, dist_np)
+        beam, rec, c, ids_np, dist_np = chosen
+        for _ in range(args.warmup):
+            step(beam)
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t = time.time()
+        for e in evs:
+            e[0].record()
+            nhq.nhq_seed_rank(index, q, qa, n_cand, out=cand)
+            e[1].record()
+            nhq.nhq_search_seeded(index, q, qa, cand, k, beam, **kw)
+            e[2].record()
+        torch.cuda.synchronize()
+        wall = time.time() - t
+        search_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+        bq = search_bytes_per_query(d_pad=960, elem_bytes=elem, R=w.degree, k=k, n_cand=n_cand,
+                                    ndc=c[:, 0].mean(), hops=c[:, 1].mean(), d=w.d, m=w.m,
+                                    scale_bytes=scale_b, out_rows=(rr * k if rr else k))
+        err = gamma64(ids_np, dist_np)
+        form = {"beam": beam, "recall": round(rec, 5), "qps": round(nq * args.steps / wall, 1),
+                "ms_per_step": round(wall * 1000 / args.steps, 4), "search_kernel_ms": round(search_ms, 4),
+                "bytes_per_query": round(bq, 1),
+                "search_hbm_frac": round(bq * nq / (search_ms / 1000.0) / 8.0e12, 4),
+                "rerank": rr, "gamma_rel_err_vs_fp64": err, "sweep": sweep}
+        if storage != "fp32":
+            # Gamma from the stored (decoded) rows of the returned objects: the
+            # approximation the loop orders by before the float32 re-score
+            rows, scales = nhq.nhq_index_get_storage(index)
+            sel = torch.from_numpy(ids_np[:nsamp].clip(min=0).astype(np.int64)).to(dev)
+            r_np = rows[sel.reshape(-1)].cpu().numpy()
+            if storage == "bf16":
+                dec = decode_bf16(r_np.view(np.uint16))
+            else:
+                dec = decode_e4m3(r_np, scales[sel.reshape(-1)].cpu().numpy().astype(np.float64))
+            dec = dec.reshape(nsamp, k, -1)[:, :, : w.d]
+            errs = []
+            for i in range(nsamp):
+                for j in range(k):
+                    v = ids_np[i, j]
+                    if v < 0:
+                        continue
+                    ex = gamma_fp64(w.q[i], w.qattrs[i], w.x[v], w.attrs[v])
+                    ap = gamma_fp64(w.q[i], w.qattrs[i], dec[i, j], w.attrs[v])
+                    errs.append(abs(ap - ex) / max(ex, 1e-30))
+            e = np.asarray(errs)
+            form["stored_form_gamma_rel_err"] = {"results": int(e.size), "max": float(e.max()),
+                                                 "p99": float(np.percentile(e, 99)), "mean": float(e.mean())}
+            del rows
+        forms[storage] = form
+        log("%s: beam %d recall %.4f %.0f QPS, search %.3f ms (%.1f%% of HBM), max rel err %.2e" % (
+            storage, beam, rec, form["qps"], search_ms, 100 * form["search_hbm_frac"], err["max"]))
+        if index is not ix:
+            index.free()
+    out = {"metric": "hybrid QPS at Recall@10=0.95 on 1 GPU, storage forms (precision form)",
+           "value": forms["bf16"]["qps"], "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": w.name, "n": w.n, "d": w.d, "m": w.m, "cards": list(w.cards),
+                      "queries_per_step": nq, "k": k, "expand": args.expand, "n_entry": args.n_entry,
+                      "build_s": round(build_s, 2)},
+           "forms": forms}
     print(json.dumps(out), flush=True)
 
 

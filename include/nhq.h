@@ -361,6 +361,19 @@ int nhq_server_run(nhq_server *s, const float *q, const uint8_t *qattrs, const i
  * did not end. */
 int nhq_server_free(nhq_server *s);
 
+/* ------------------------------------------------------------ measurement */
+
+/* Random-row gather probe: `waves` wavefronts (a multiple of 4) each read
+ * rounds * (64 / G) whole stored rows of the index at pseudo-random
+ * positions (a counter-based hash of seed, wave and row), with the search's
+ * lane layout and rounds in flight, and write per-lane sums to sink (device
+ * float32 [waves][64]) so that nothing is optimised away.  *rows_read (host,
+ * nullable) = rows read.  Timing it gives the bandwidth ceiling of the
+ * search's row gathers.  rounds must be a multiple of the rounds the search
+ * keeps in flight: 2 when the padded width is at most 128, else 1. */
+int nhq_gather_probe(const nhq_index *ix, int64_t waves, int32_t rounds, uint64_t seed, float *sink,
+                     int64_t *rows_read, void *stream);
+
 /* ------------------------------------------------------------------ misc */
 const char *nhq_strerror(int code);
 const char *nhq_last_error(void);

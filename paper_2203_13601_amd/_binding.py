@@ -105,6 +105,7 @@ def lib() -> ctypes.CDLL:
         "nhq_server_poll": ([P, ctypes.c_uint64, P, P, P, P], i32),
         "nhq_server_run": ([P, P, P, P, P, P, P, i64, P, P, P, P, P, P, ctypes.c_double], i32),
         "nhq_server_free": ([P], i32),
+        "nhq_gather_probe": ([P, i64, i32, ctypes.c_uint64, P, P, P], i32),
         "nhq_strerror": ([i32], ctypes.c_char_p),
         "nhq_last_error": ([], ctypes.c_char_p),
         "nhq_version": ([], i32),
@@ -538,3 +539,12 @@ class Server:
 
 def nhq_server_create(ix: Index, **params) -> Server:
     return Server(ix, **params)
+
+
+def nhq_gather_probe(ix: Index, waves: int, rounds: int, seed: int = 1, stream=None):
+    """Random-row gather probe; returns (sink tensor, rows read)."""
+    sink = torch.empty((waves, 64), dtype=torch.float32, device="cuda")
+    rows = ctypes.c_int64()
+    _check(lib().nhq_gather_probe(ix.handle, int(waves), int(rounds), int(seed), sink.data_ptr(),
+                                  ctypes.byref(rows), _stream(stream)), "nhq_gather_probe")
+    return sink, rows.value

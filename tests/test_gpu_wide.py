@@ -1,0 +1,80 @@
+"""Wide rows (the precision form's d = 960, and d = 1000 padded to 1024):
+the kernels' 16-lane row groups, the one-round-in-flight scoring and the
+wide matrix-core tiles, against the CPU oracle.
+
+Float vectors: orders can differ from the FP64 oracle only at near-ties, so
+results must overlap and every returned distance must be Gamma of the
+returned object to 1e-4 relative (FP64)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+nhq = pytest.importorskip("paper_2203_13601_amd")
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_graph_matches_oracle_d960():
+    w = synth.small(1500, 960, 1, seed=91, n_centres=6, cards=(2, 3, 5, 10))
+    ix = nhq.nhq_build_index(_dev(w.x), _dev(w.attrs), degree=32, cand=48, n_entry=64, seed=1)
+    adj = nhq.nhq_index_get_graph(ix).cpu().numpy()
+    want = oracle.build_graph(w.x, w.attrs, l=48, R=32)
+    same = (adj == want).all(axis=1)
+    assert same.mean() >= 0.995, same.mean()
+
+
+@pytest.mark.parametrize("d", [960, 1000])
+@pytest.mark.parametrize("storage", ["fp32", "bf16", "fp8"])
+def test_search_matches_oracle_wide(d, storage):
+    w = synth.small(4000, d, 48, seed=92, n_centres=8, cards=(2, 3, 5))
+    adj = synth.random_graph(w.n, 32, seed=5)
+    if storage == "fp32":
+        xs = w.x
+    elif storage == "bf16":
+        xs = oracle.from_bf16_bits(oracle.to_bf16_bits(w.x)).astype(np.float32)
+    else:
+        codes, s = oracle.fp8_rows(w.x)
+        xs = oracle.fp8_decode_rows(codes, s).astype(np.float32)
+    rr = 0 if storage == "fp32" else 4
+    ix = nhq.nhq_index_create(_dev(w.x), _dev(w.attrs), storage=storage, n_entry=256, seed=w.build_seed,
+                              degree=32)
+    nhq.nhq_index_set_graph(ix, _dev(adj))
+    entry = oracle.entry_points(w.build_seed, w.n, 256)
+    ids, dist = nhq.nhq_hybrid_search(ix, _dev(w.q), _dev(w.qattrs), 10, 64, rerank=rr, expand=4)
+    ids, dist = ids.cpu().numpy(), dist.cpu().numpy()
+    oi, og, _, _, _ = oracle.search(adj, xs, w.attrs, w.q, w.qattrs, 10, 64, entry, rerank_n=10 * rr,
+                                    xr=w.x if rr else None, expand=4)
+    overlap = np.mean([len(set(a[a >= 0]) & set(b[b >= 0])) / max(1, (b >= 0).sum())
+                       for a, b in zip(ids, oi)])
+    assert overlap >= 0.97, overlap
+    for i in range(w.nq):
+        mq = oracle.arity(w.qattrs[i])
+        for v, g in zip(ids[i], dist[i]):
+            if v < 0:
+                assert np.isinf(g)
+                continue
+            c = oracle.chi(w.qattrs[i], w.attrs[v])
+            assert c == 0
+            want = oracle.gamma(oracle.delta(w.q[i], w.x[v]), c, mq)
+            assert abs(g - want) <= 1e-4 * max(want, 1e-30), (i, v, g, want)
+
+
+def test_bruteforce_knn_d960():
+    w = synth.small(6000, 960, 40, seed=93, n_centres=8, cards=(2, 3, 5), wildcard_arity=True)
+    ix = nhq.nhq_index_create(_dev(w.x), _dev(w.attrs), n_entry=64)
+    gi, gd = nhq.nhq_bruteforce_hybrid_knn(ix, _dev(w.q), _dev(w.qattrs), 10)
+    gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
+    oi, og, _ = oracle.bruteforce(w.x, w.attrs, w.q, w.qattrs, 10)
+    # ids equal except where two exact distances tie in float32
+    for i in range(w.nq):
+        ok = (gi[i] == oi[i]) | np.isclose(gd[i], og[i], rtol=1e-6)
+        assert ok.all(), i
+        fin = np.isfinite(og[i])
+        assert np.allclose(gd[i][fin], og[i][fin], rtol=1e-5)
