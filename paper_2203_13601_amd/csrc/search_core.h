@@ -136,12 +136,24 @@ __device__ __forceinline__ float4 decode<NHQ_STORAGE_FP8>(uint32_t c, float s)
     return make_float4(lo[0] * s, lo[1] * s, hi[0] * s, hi[1] * s);
 }
 
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// Sum over a group of G (8 or 16) adjacent lanes, every lane receiving the
+// total: DPP lane moves (quad swaps of 1 and 2, then the half-row and row
+// mirrors), no LDS traffic.
 template <int G>
 __device__ __forceinline__ float group_sum(float v)
 {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1)
-        v += __shfl_xor(v, o, 64);
+    static_assert(G == 8 || G == 16, "row groups of 8 or 16 lanes");
+    v += dpp_mov<0xB1>(v);   // quad_perm(1, 0, 3, 2)
+    v += dpp_mov<0x4E>(v);   // quad_perm(2, 3, 0, 1)
+    v += dpp_mov<0x141>(v);  // row_half_mirror: lane i <-> 7 - i
+    if constexpr (G == 16)
+        v += dpp_mov<0x140>(v);  // row_mirror: lane i <-> 15 - i
     return v;
 }
 
@@ -519,6 +531,7 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
     // E = 1: the adjacency row of the runner-up is fetched one hop ahead (it
     // is the next vertex to expand unless this hop inserts a better one)
     const int E = a.expand;
+    const int rshift = (a.R & (a.R - 1)) == 0 ? __ffs(a.R) - 1 : -1;  // R a power of two
     int64_t pf_id = -1;
     int pf_nb = -1;
     uint32_t next_ckpt = (uint32_t)a.ckpt;
@@ -655,7 +668,12 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
         const int64_t u0 = (int64_t)rdl_u(myid, 0);
         for (int s0 = 0; s0 < total; s0 += 64) {
             const int sl = s0 + lane;
-            const int e = min(sl / a.R, nexp - 1), r = sl - (sl / a.R) * a.R;
+            int qv_;
+            if (rshift >= 0)
+                qv_ = sl >> rshift;
+            else
+                qv_ = sl / a.R;
+            const int e = min(qv_, nexp - 1), r = sl - qv_ * a.R;
             const int64_t u = (int64_t)(uint32_t)__shfl((int)myid, e, 64);
             int nb = -1;
             if (sl < total)
