@@ -118,6 +118,15 @@ typedef struct {
     int32_t expand;      /* vertices expanded per step: the `expand` best
                             unexpanded pool entries are expanded together and
                             their neighbours merged as one batch (1..8)    [1] */
+    int32_t route_h;     /* h >= 2: two-stage routing (Sec. 4.2).  In stage
+                            S1 an expanded vertex u evaluates only its slots r
+                            with (r + fmix32(u * 0x9E3779B1 + t)) mod h = 0,
+                            t its expansion number (hops before it), i.e.
+                            about ceil(R / h) neighbours; at the first step
+                            that inserts nothing into the pool every pool
+                            entry becomes unexpanded again and stage S2 (all
+                            neighbours, Alg. 2) runs to the end.  0 or 1: off
+                                                                          [0] */
 } nhq_search_params;
 
 /* Device error word bits (accumulated per index; nhq_index_device_error). */

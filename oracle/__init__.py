@@ -79,7 +79,7 @@ def lib():
         L.or_search.restype = None
         L.or_search.argtypes = [P, i32, P, P, P, i64, i32, i32, P, P, i64, i32, i32, P, i32,
                                 i32, i32, i32, i32, i64, P, P, P, P, P, i32, P, P, P, P, P, i32,
-                                P, ctypes.c_double, ctypes.c_double, i32, i32, i32]
+                                P, ctypes.c_double, ctypes.c_double, i32, i32, i32, i32]
         _lib = L
     return _lib
 
@@ -220,7 +220,7 @@ def search(adj, xs, attrs, q, qa, k: int, L: int, seeds, n_init: int = 32, key_m
            out_mode: int = 0, rerank_n: int = 0, xr=None, max_hops: int = 1 << 40,
            threads: Optional[int] = None, check_every: int = 0, trace_cap: int = 0,
            mlp: Optional[np.ndarray] = None, stop_threshold: float = 0.5, cap_factor: float = 0.0,
-           expand: int = 1, learned_mode: int = 1):
+           expand: int = 1, learned_mode: int = 1, route_h: int = 0):
     """Joint pruning in beam form; see ``or_search`` in nhq_oracle.c.
     Returns (ids [nq,k], gamma [nq,k], ndc [nq], hops [nq], flag [nq]); with
     trace_cap > 0 also a dict of checkpoint traces (feat [nq,cap,8], hop,
@@ -229,7 +229,10 @@ def search(adj, xs, attrs, q, qa, k: int, L: int, seeds, n_init: int = 32, key_m
     learned_mode 2 evaluates it at the first checkpoint only, whose beam
     output (times cap_factor) then bounds the hops.
     ``expand`` E > 1 expands the E best unexpanded entries per step (a
-    batched form of Alg. 2 lines 3-8; E = 1 is the algorithm as printed)."""
+    batched form of the algorithm's expansion loop; E = 1 is Alg. 2 itself).
+    ``route_h`` h >= 2 runs two-stage routing (Sec. 4.2): a first stage that
+    looks at a random 1-in-h subset of each expanded vertex's neighbours until
+    a step adds nothing to the pool, then Alg. 2 over the whole pool."""
     adj = np.ascontiguousarray(adj, dtype=np.int32)
     xs, attrs, q, qa = _f32(xs), _u8(attrs), _f32(q), _u8(qa)
     xr = None if xr is None else _f32(xr)
@@ -256,7 +259,7 @@ def search(adj, xs, attrs, q, qa, k: int, L: int, seeds, n_init: int = 32, key_m
                     _p(tr["feat"]) if tr else None, _p(tr["hop"]) if tr else None,
                     _p(tr["hash"]) if tr else None, _p(tr["count"]) if tr else None,
                     _p(tr["final_hash"]) if tr else None, int(trace_cap), _p(w), logit,
-                    float(cap_factor), int(learned_mode), int(expand), _threads(threads))
+                    float(cap_factor), int(learned_mode), int(expand), int(route_h), _threads(threads))
     if tr is not None:
         return ids, gam, ndc, hops, flag, tr
     return ids, gam, ndc, hops, flag

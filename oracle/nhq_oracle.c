@@ -421,7 +421,11 @@ static void mlp_forward(const double *w, const double *f, double *z)
  *            reaches stop_logit; with cap_factor > 0 the beam output of the
  *            first checkpoint sets a hop budget cap_factor * 2^z1, checked
  *            before every step; learned_mode 2 takes the first checkpoint
- *            only (its budget then bounds the search).
+ *            only (its budget then bounds the search);
+ *   route_h  >= 2: two-stage routing (Sec. 4.2): stage S1 expands with a
+ *            random 1-in-route_h subset of each vertex's slots until a step
+ *            adds nothing to the pool, then S2 re-expands the whole pool with
+ *            all slots (Alg. 2); 0 or 1 is Alg. 2 throughout.
  * Outputs ids (-1 padded), Gamma (+inf padded), NDC (neighbour distance
  * evaluations; the entry sample is not counted) and H (expansions). */
 void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
@@ -432,7 +436,7 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
                int32_t *out_flag, int check_every, double *tr_feat, uint32_t *tr_hop,
                uint32_t *tr_hash, int32_t *tr_count, uint32_t *tr_final, int tr_cap,
                const double *mlp, double stop_logit, double cap_factor, int learned_mode, int expand,
-               int nthreads)
+               int route_h, int nthreads)
 {
     if (expand < 1)
         expand = 1;
@@ -554,6 +558,7 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
                     logsel += logp[i][qav[i]];
             int64_t next_ckpt = check_every;
             int first_ckpt = 1;
+            int stage1 = route_h > 1; /* two-stage routing, Sec. 4.2 */
             for (;;) {
                 /* the E best unexpanded entries (E = expand), in pool order */
                 int nsel = 0;
@@ -637,12 +642,24 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
                     pool[selpos[e]].expanded = 1;
                     us[e] = pool[selpos[e]].id;
                 }
+                const int64_t hops_before = hops;
                 hops += nsel;
                 /* unvisited neighbours of the selected vertices, in (vertex,
-                 * slot) order; each is scored once */
+                 * slot) order; each is scored once.  Stage S1 of two-stage
+                 * routing looks at one slot in route_h only: slot t of the
+                 * vertex u expanded as the x-th expansion of the search
+                 * (x counted from 0) is looked at iff
+                 * t + fmix32(u * 0x9E3779B1 + x mod 2^32) is a multiple of
+                 * route_h, a random subset of about R / route_h slots. */
                 int nf = 0;
                 for (int e = 0; e < nsel; ++e)
                     for (int t = 0; t < R; ++t) {
+                        if (stage1) {
+                            uint32_t x = (uint32_t)(hops_before + e);
+                            uint32_t f = fmix32((uint32_t)us[e] * 0x9E3779B1u + x);
+                            if (((uint64_t)t + (uint64_t)f) % (uint64_t)route_h != 0)
+                                continue;
+                        }
                         int64_t v = adj[us[e] * (int64_t)R + t];
                         if (v < 0 || v >= n)
                             continue;
@@ -653,13 +670,23 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
                     }
                 /* offered to the pool in batches of 64; entries of a batch
                  * still pooled after it count as joined */
+                int64_t joined_step = 0;
                 for (int c0 = 0; c0 < nf; c0 += 64) {
                     chunk_stamp += 1;
                     for (int c = c0; c < nf && c < c0 + 64; ++c)
                         OFFER(fresh[c]);
                     for (int t = 0; t < size; ++t)
                         if (pool[t].born == chunk_stamp)
-                            ins_window += 1;
+                            joined_step += 1;
+                }
+                ins_window += joined_step;
+                /* S1 ends at the first step that adds nothing to the pool;
+                 * S2 then expands every pool entry again, with all of its
+                 * neighbours (greedy routing of Alg. 2 from the S1 pool) */
+                if (stage1 && joined_step == 0) {
+                    stage1 = 0;
+                    for (int t = 0; t < size; ++t)
+                        pool[t].expanded = 0;
                 }
             }
 #undef OFFER

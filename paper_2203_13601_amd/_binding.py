@@ -45,7 +45,8 @@ class SearchParams(ctypes.Structure):
                 ("visited_log2", ctypes.c_int32), ("learned", ctypes.c_int32),
                 ("stop_threshold", ctypes.c_float), ("check_every", ctypes.c_int32),
                 ("counters", ctypes.c_void_p), ("cap_factor", ctypes.c_float),
-                ("trace", ctypes.c_void_p), ("expand", ctypes.c_int32)]
+                ("trace", ctypes.c_void_p), ("expand", ctypes.c_int32),
+                ("route_h", ctypes.c_int32)]
 
 
 MLP_PARAMS = 4866
@@ -271,9 +272,10 @@ def nhq_hybrid_search(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, k:
                       check_every: int = 0, counters: bool = False, stream=None,
                       out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None,
                       cap_factor: float = 0.0, trace: Optional["TraceBuffers"] = None,
-                      expand: int = 1):
+                      expand: int = 1, route_h: int = 0):
     """Returns (ids int32 [nq,k], dists float32 [nq,k]) and, with
-    counters=True, a uint32-valued int32 tensor [nq,2] of (NDC, H)."""
+    counters=True, a uint32-valued int32 tensor [nq,2] of (NDC, H).
+    route_h >= 2 turns on two-stage routing (Sec. 4.2)."""
     queries = _dev(queries, torch.float32, "queries", 2)
     qattrs = _dev(qattrs, torch.uint8, "qattrs", 2)
     nq = queries.shape[0]
@@ -289,7 +291,7 @@ def nhq_hybrid_search(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, k:
                       int(learned), float(stop_threshold), int(check_every),
                       cnt.data_ptr() if cnt is not None else None, float(cap_factor),
                       ctypes.cast(ctypes.byref(trace.c), ctypes.c_void_p) if trace is not None else None,
-                      int(expand))
+                      int(expand), int(route_h))
     _check(lib().nhq_hybrid_search(ix.handle, queries.data_ptr(), qattrs.data_ptr(), nq, int(k),
                                    int(beam), ctypes.byref(sp), ids.data_ptr(), dists.data_ptr(),
                                    _stream(stream)), "nhq_hybrid_search")
@@ -313,7 +315,7 @@ def nhq_search_seeded(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, ca
                       stop_threshold: float = 0.0, check_every: int = 0, counters: bool = False,
                       stream=None, out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None,
                       cap_factor: float = 0.0, trace: Optional["TraceBuffers"] = None,
-                      expand: int = 1):
+                      expand: int = 1, route_h: int = 0):
     queries = _dev(queries, torch.float32, "queries", 2)
     qattrs = _dev(qattrs, torch.uint8, "qattrs", 2)
     cand = _dev(cand, torch.int32, "cand", 2)
@@ -328,7 +330,7 @@ def nhq_search_seeded(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, ca
                       int(learned), float(stop_threshold), int(check_every),
                       cnt.data_ptr() if cnt is not None else None, float(cap_factor),
                       ctypes.cast(ctypes.byref(trace.c), ctypes.c_void_p) if trace is not None else None,
-                      int(expand))
+                      int(expand), int(route_h))
     _check(lib().nhq_search_seeded(ix.handle, queries.data_ptr(), qattrs.data_ptr(), nq,
                                    cand.data_ptr(), cand.shape[1], int(k), int(beam), ctypes.byref(sp),
                                    ids.data_ptr(), dists.data_ptr(), _stream(stream)),

@@ -675,6 +675,8 @@ int nhq_search_seeded(const nhq_index *h, const float *queries, const uint8_t *q
         return fail(NHQ_EINVAL, "rerank * k must not exceed beam");
     if (p.visited_log2 != 0 && (p.visited_log2 < 10 || p.visited_log2 > 13))
         return fail(NHQ_EINVAL, "visited_log2 must be 0 or in [10, 13]");
+    if (p.route_h < 0 || p.route_h > NHQ_MAX_DEGREE)
+        return fail(NHQ_EINVAL, "route_h must be in [0, 64]");
     if (p.learned < 0 || p.learned > 2)
         return fail(NHQ_EINVAL, "learned must be 0, 1 or 2");
     if (p.learned && !ix->mlp)
@@ -700,6 +702,7 @@ int nhq_search_seeded(const nhq_index *h, const float *queries, const uint8_t *q
     s.stop_logit = logf(p.stop_threshold / (1.0f - p.stop_threshold));
     s.cap_factor = p.cap_factor;
     s.expand = p.expand;
+    s.route_h = p.route_h;
     s.trace = p.trace;
     s.ids = ids;
     s.dists = dists;

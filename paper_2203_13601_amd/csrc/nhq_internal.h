@@ -93,6 +93,7 @@ struct SearchLaunch {
     int k, L, n_init, out_mode, rerank_n, max_hops, hash_log2, learned, check_every;
     float stop_logit, cap_factor;
     int expand;
+    int route_h;
     const nhq_trace *trace;
     int32_t *ids;
     float *dists;

@@ -125,6 +125,7 @@ int launch_search(const SearchLaunch &s)
     a.max_hops = s.max_hops;
     a.ckpt = (s.learned || s.trace) ? s.check_every : 0;
     a.expand = s.expand;
+    a.route_h = s.route_h;
     a.learned = s.learned;
     a.stop_logit = s.stop_logit;
     a.cap_factor = s.cap_factor;

@@ -38,6 +38,7 @@ struct SearchArgs {
     // checkpoints every `ckpt` hops (0 = none): features for the stop network
     int ckpt, learned;
     int expand;           // vertices expanded per step (1 = Alg. 2 as printed)
+    int route_h;          // >= 2: two-stage routing, stage S1 evaluates 1 slot in h
     float stop_logit;     // learned: stop when the stop logit >= this
     float cap_factor;     // learned, > 0: hop budget cap_factor * 2^(beam output)
     const uint16_t *mlp;  // fp16 weights of the stop network
@@ -532,6 +533,9 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
     // is the next vertex to expand unless this hop inserts a better one)
     const int E = a.expand;
     const int rshift = (a.R & (a.R - 1)) == 0 ? __ffs(a.R) - 1 : -1;  // R a power of two
+    // two-stage routing (Sec. 4.2): stage S1 until a step inserts nothing
+    const int route_h = a.route_h;
+    bool s1 = route_h > 1;
     int64_t pf_id = -1;
     int pf_nb = -1;
     uint32_t next_ckpt = (uint32_t)a.ckpt;
@@ -676,7 +680,14 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
             const int e = min(qv_, nexp - 1), r = sl - qv_ * a.R;
             const int64_t u = (int64_t)(uint32_t)__shfl((int)myid, e, 64);
             int nb = -1;
-            if (sl < total)
+            bool take = sl < total;
+            if (s1 && take) {
+                // S1: slot r of the e-th vertex of this step, expansion number t
+                const uint32_t t = hops - (uint32_t)nexp + (uint32_t)e;
+                const uint32_t off = fmix32((uint32_t)u * 0x9E3779B1u + t) % (uint32_t)route_h;
+                take = ((uint32_t)r + off) % (uint32_t)route_h == 0;
+            }
+            if (take)
                 nb = (E == 1 && pf_id == u0) ? pf_nb : a.adj[u * a.R + r];
             if (nb >= a.n || nb < -1) {
                 badid = true;
@@ -710,12 +721,23 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
                 pf_nb = lane < a.R ? a.adj[pf_id * a.R + lane] : -1;
             }
         }
-        if (nf == 0)
+        if (nf == 0) {
+            if (s1) {
+                // nothing to insert: stage S2 from here on, every pool entry
+                // to be expanded again with all of its neighbours
+                s1 = false;
+                for (int e = lane; e < size; e += 64)
+                    pid[e] &= ~kExpBit;
+                wsync();
+                lo = 0;
+            }
             continue;
+        }
         wsync();
         ndc += nf;
         score_batch<DP, ST>(a.vecs, a.scale, qv, sid, skey, nf, mq, 1, a.attr, qword, qmask);
         wsync();
+        int step_ins = 0;
         for (int c0 = 0; c0 < nf; c0 += 64) {
             const int j = c0 + lane;
             const bool v = j < nf;
@@ -725,6 +747,14 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
             size = pool_merge(pkey, pid, size, L, ck, cw, v, lo, &ins);
             if (CK)
                 ins_window += ins;
+            step_ins += ins;
+        }
+        if (s1 && step_ins == 0) {
+            s1 = false;
+            for (int e = lane; e < size; e += 64)
+                pid[e] &= ~kExpBit;
+            wsync();
+            lo = 0;
         }
     }
     if (CK && a.trace_feat) {
