@@ -54,6 +54,24 @@ extern "C" {
 #define NHQ_STORAGE_BF16 1
 #define NHQ_STORAGE_FP8 2 /* OCP e4m3 with one float32 scale per vector */
 
+/* Weight settings of the fusion distance Gamma (Eq. 6), fixed per index:
+ * the build and every search of the index use the same one.  delta is the
+ * Euclidean distance (Eq. 1), chi the number of mismatched constrained
+ * attributes (Eq. 4-5), m_q the number of constrained attributes (m between
+ * two objects), p the index's weight_param.  Sec. 6.5 compares them.      */
+#define NHQ_WEIGHTS_DEFAULT 0    /* w_v = 1, w_l = delta / m_q:
+                                    Gamma = delta (1 + chi / m_q) (Sec. 3.2) */
+#define NHQ_WEIGHTS_HARMONIC 1   /* w_v = chi / (delta + chi),
+                                    w_l = delta / (delta + chi):
+                                    Gamma = 2 delta chi / (delta + chi), 0 when
+                                    delta + chi = 0                           */
+#define NHQ_WEIGHTS_HARMONIC_C 2 /* the harmonic form with chi replaced by 1
+                                    when chi = 0 and by p * chi otherwise
+                                    (Eq. 8, p = c > 1)                        */
+#define NHQ_WEIGHTS_NORMALISED 3 /* w_v = 1 / p (p = delta_max),
+                                    w_l = 1 / m_q (chi term 0 when m_q = 0)   */
+#define NHQ_WEIGHTS_FIXED 4      /* w_v = 1, w_l = p (the ratio w_l / w_v)  */
+
 #define NHQ_MAX_DEGREE 64
 #define NHQ_MAX_BEAM 1024
 #define NHQ_MAX_ATTRS 4
@@ -70,8 +88,12 @@ typedef struct {
     int32_t storage;       /* NHQ_STORAGE_*: form the search scores with   [0] */
     int32_t n_entry;       /* size of the random entry sample from which each
                               query's seed set is taken                  [1024] */
-    int32_t reserved0;
+    int32_t weights;       /* NHQ_WEIGHTS_*: weight setting of Gamma, for the
+                              build and every search of this index          [0] */
     uint64_t seed;         /* splitmix64 seed of the entry sample          [0] */
+    double weight_param;   /* p of the weight setting: c > 1 (HARMONIC_C),
+                              delta_max > 0 (NORMALISED), w_l / w_v >= 0
+                              (FIXED); ignored otherwise                   [0] */
 } nhq_build_params;
 
 /* Per-checkpoint search traces (training data of the stop network).  Every

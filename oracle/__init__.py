@@ -22,6 +22,7 @@ Readings of the paper that the oracle takes are listed in each docstring.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import math
 import os
@@ -76,6 +77,8 @@ def lib():
         L.or_build.argtypes = [P, P, i64, i32, i32, i32, i32, i32, P, i64, P, P, i32]
         L.or_knn_rows.restype = None
         L.or_knn_rows.argtypes = [P, P, i64, i32, i32, i32, P, i64, i32, P, i32]
+        L.or_set_weights.restype = None
+        L.or_set_weights.argtypes = [i32, ctypes.c_double]
         L.or_search.restype = None
         L.or_search.argtypes = [P, i32, P, P, P, i64, i32, i32, P, P, i64, i32, i32, P, i32,
                                 i32, i32, i32, i32, i64, P, P, P, P, P, i32, P, P, P, P, P, i32,
@@ -119,8 +122,27 @@ def arity(qa: Sequence[int]) -> int:
 
 
 def gamma(dlt: float, c: int, mq: int) -> float:
-    """Eq. 6 with w_v = 1 and w_l = delta / m_q (Sec. 3.2)."""
+    """Eq. 6 under the current weight setting (default: w_v = 1 and
+    w_l = delta / m_q, Sec. 3.2)."""
     return float(lib().or_gamma(float(dlt), int(c), int(mq)))
+
+
+# weight settings of Sec. 6.5 (Fig. 10 (i), curves iv, i, ii, iii, v)
+WEIGHTS = {"default": 0, "harmonic": 1, "harmonic_c": 2, "normalised": 3, "fixed": 4}
+
+
+@contextlib.contextmanager
+def weights(mode, param: float = 0.0):
+    """Run the enclosed oracle calls under one weight setting of Eq. 6:
+    'default' (curve iv), 'harmonic' (i), 'harmonic_c' (ii, Eq. 8 with
+    c = param), 'normalised' (iii, delta_max = param) or 'fixed' (v, the
+    ratio w_l / w_v = param)."""
+    code = WEIGHTS[mode] if isinstance(mode, str) else int(mode)
+    lib().or_set_weights(code, float(param))
+    try:
+        yield
+    finally:
+        lib().or_set_weights(0, 0.0)
 
 
 def order_key(d2: float, c: int, mq: int, mode: int = KEY64) -> float:
@@ -131,7 +153,8 @@ def order_key(d2: float, c: int, mq: int, mode: int = KEY64) -> float:
 def bruteforce(x, attrs, q, qa, k: int, by_gamma: bool = False,
                threads: Optional[int] = None):
     """Def. 4 exact answer: ids [nq,k] (-1 padded), distances [nq,k]
-    (delta of each match, +inf padded), |P| per query."""
+    (delta of each match, +inf padded), |P| per query.  by_gamma ranks every
+    object by (Gamma, id) instead and returns Gamma."""
     x, attrs, q, qa = _f32(x), _u8(attrs), _f32(q), _u8(qa)
     n, d = x.shape
     m = attrs.shape[1]

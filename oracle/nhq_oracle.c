@@ -11,7 +11,8 @@
  *           attributes of a query (wildcards contribute nothing);
  *   delta2  squared Euclidean distance, Eq. (1), FP64 direct form;
  *   gamma   fusion distance, Eq. (6), with the default weights of Sec. 3.2
- *           ("optimal weight configuration"): w_v = 1, w_l = delta / m;
+ *           (w_v = 1, w_l = delta / m) or one of the other settings that
+ *           Sec. 6.5 compares (Eq. 8 among them);
  *   bruteforce   exact hybrid top-k (Def. 4 with Def. 2): exact attribute
  *           filter, then exact vector top-k ordered by (delta, id);
  *   build   composite index (Alg. 1 in degree-bounded form): exact l nearest
@@ -74,17 +75,96 @@ int or_arity(const uint8_t *qa, int m)
 }
 
 /* ---------------------------------------------------------------- Eq. 6 */
-double or_gamma(double delta, int chi, int mq)
+/* The weight settings of Sec. 6.5 (Fig. 10 (i), curves i-v).  Set once per
+ * call through or_set_weights; every Gamma and ordering key below follows it.
+ *   OR_W_DEFAULT     w_v = 1, w_l = delta / m_q             (curve iv)
+ *   OR_W_HARMONIC    w_v = chi / (delta + chi), w_l = delta / (delta + chi):
+ *                    Gamma = 2 delta chi / (delta + chi), 0 when both are 0
+ *                                                            (curve i)
+ *   OR_W_HARMONIC_C  curve i with chi replaced by 1 when chi = 0 and by
+ *                    c * chi otherwise (Eq. 8), c = the weight parameter
+ *                                                            (curve ii)
+ *   OR_W_NORMALISED  w_v = 1 / delta_max, w_l = 1 / chi_max, chi_max = m_q
+ *                    (chi / chi_max read as 0 when m_q = 0), delta_max = the
+ *                    weight parameter                        (curve iii)
+ *   OR_W_FIXED       w_v = 1, w_l = the weight parameter (the ratio
+ *                    w_l / w_v)                              (curve v) */
+#define OR_W_DEFAULT 0
+#define OR_W_HARMONIC 1
+#define OR_W_HARMONIC_C 2
+#define OR_W_NORMALISED 3
+#define OR_W_FIXED 4
+static int g_wmode = OR_W_DEFAULT;
+static double g_wparam = 0.0;
+
+void or_set_weights(int mode, double param)
 {
-    if (mq == 0)
-        return delta;
-    double w_v = 1.0;
-    double w_l = delta / (double)mq;
-    return w_v * delta + w_l * (double)chi;
+    g_wmode = mode;
+    g_wparam = param;
 }
 
+double or_gamma(double delta, int chi, int mq)
+{
+    double c = (double)chi;
+    switch (g_wmode) {
+    case OR_W_HARMONIC:
+        return (delta + c == 0.0) ? 0.0 : (2.0 * delta * c) / (delta + c);
+    case OR_W_HARMONIC_C:
+        c = (chi == 0) ? 1.0 : g_wparam * c;
+        return (2.0 * delta * c) / (delta + c);
+    case OR_W_NORMALISED:
+        return delta / g_wparam + (mq == 0 ? 0.0 : c / (double)mq);
+    case OR_W_FIXED:
+        return delta + g_wparam * c;
+    default:
+        if (mq == 0)
+            return delta;
+        return 1.0 * delta + (delta / (double)mq) * c;
+    }
+}
+
+/* The same Gamma with every operation rounded to float32 (sqrt included),
+ * in the order written above: the precision a float32 kernel decides in. */
+static float gamma32(double d2, int chi, int mq)
+{
+    volatile float delta = sqrtf((float)d2);
+    volatile float c = (float)chi, p = (float)g_wparam, t, u;
+    switch (g_wmode) {
+    case OR_W_HARMONIC:
+        u = delta + c;
+        if (u == 0.0f)
+            return 0.0f;
+        t = 2.0f * delta;
+        t = t * c;
+        return t / u;
+    case OR_W_HARMONIC_C:
+        if (chi == 0)
+            c = 1.0f;
+        else
+            c = p * c;
+        t = 2.0f * delta;
+        t = t * c;
+        u = delta + c;
+        return t / u;
+    case OR_W_NORMALISED:
+        t = delta / p;
+        u = mq == 0 ? 0.0f : c / (float)mq;
+        return t + u;
+    default: /* OR_W_FIXED */
+        t = p * c;
+        return delta + t;
+    }
+}
+
+/* Ordering key.  Default weights: (m_q Gamma)^2 = delta^2 (m_q + chi)^2,
+ * free of square roots; the other settings order by Gamma itself. */
 double or_order_key(double d2, int chi, int mq, int mode)
 {
+    if (g_wmode != OR_W_DEFAULT) {
+        if (mode == OR_KEY32)
+            return (double)gamma32(d2, chi, mq);
+        return or_gamma(sqrt(d2), chi, mq);
+    }
     double mult = (mq == 0) ? 1.0 : (double)((mq + chi) * (mq + chi));
     if (mode == OR_KEY32) {
         volatile float f = (float)d2;
@@ -151,7 +231,7 @@ void or_bruteforce(const float *x, const uint8_t *attrs, int64_t n, int d, int m
                 out_ids[iq * k + j] = (int32_t)e;
                 double d2 = or_delta2(qv, x + e * (int64_t)d, d);
                 int c = or_chi(qav, attrs + e * (int64_t)m, m);
-                out_dist[iq * k + j] = or_gamma(sqrt(d2), c, mq);
+                out_dist[iq * k + j] = by_gamma ? or_gamma(sqrt(d2), c, mq) : sqrt(d2);
             } else {
                 out_ids[iq * k + j] = -1;
                 out_dist[iq * k + j] = INFINITY;

@@ -30,8 +30,8 @@ class NHQError(RuntimeError):
 class BuildParams(ctypes.Structure):
     _fields_ = [("degree", ctypes.c_int32), ("cand", ctypes.c_int32),
                 ("reverse_edges", ctypes.c_int32), ("storage", ctypes.c_int32),
-                ("n_entry", ctypes.c_int32), ("reserved0", ctypes.c_int32),
-                ("seed", ctypes.c_uint64)]
+                ("n_entry", ctypes.c_int32), ("weights", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("weight_param", ctypes.c_double)]
 
 
 class Trace(ctypes.Structure):
@@ -165,10 +165,16 @@ class Index:
             pass
 
 
-def _params(degree=32, cand=64, reverse_edges=False, storage="fp32", n_entry=1024, seed=0):
+# weight settings of Gamma (Eq. 6; compared in Sec. 6.5)
+WEIGHTS = {"default": 0, "harmonic": 1, "harmonic_c": 2, "normalised": 3, "fixed": 4}
+
+
+def _params(degree=32, cand=64, reverse_edges=False, storage="fp32", n_entry=1024, seed=0,
+            weights="default", weight_param=0.0):
     return BuildParams(int(degree), int(cand), int(bool(reverse_edges)),
                        STORAGE[storage] if isinstance(storage, str) else int(storage),
-                       int(n_entry), 0, int(seed))
+                       int(n_entry), WEIGHTS[weights] if isinstance(weights, str) else int(weights),
+                       int(seed), float(weight_param))
 
 
 def nhq_index_create(vecs: torch.Tensor, attrs: torch.Tensor, stream=None, **params) -> Index:

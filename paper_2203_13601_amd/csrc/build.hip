@@ -36,7 +36,7 @@ int nhq_index_build_graph(nhq_index *h, void *stream)
     int32_t *cand = nullptr, *fwd = nullptr;
     NHQ_HIP(hipMallocAsync((void **)&cand, sizeof(int32_t) * (size_t)ix->n * K, st));
     int rc = launch_dense_topk(ix->vec32, ix->norm, ix->attr, nullptr, ix->n, ix->vec32, ix->norm,
-                               ix->attr, ix->n, ix->dp, ix->m, 0, 1, K, cand, nullptr, st);
+                               ix->attr, ix->n, ix->dp, ix->m, 0, 1, K, cand, nullptr, st, &ix->w);
     if (rc == NHQ_OK) {
         if (ix->reverse_edges) {
             if (hipMallocAsync((void **)&fwd, sizeof(int32_t) * (size_t)ix->n * ix->degree, st) != hipSuccess)

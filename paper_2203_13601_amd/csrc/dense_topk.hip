@@ -44,6 +44,7 @@ struct TopkArgs {
     int splits;           // gridDim.y
     int32_t *out_ids;     // [na][splits][K] (splits == 1: the final lists)
     float *out_keys;      // [na][splits][K]
+    Weights w;            // weight setting of the fusion key (mode 0)
 };
 
 __device__ __forceinline__ void wsync()
@@ -168,7 +169,6 @@ __global__ __launch_bounds__(128) void k_dense_topk(const TopkArgs a)
     const uint32_t full = a.m >= 4 ? 0xFFFFFFFFu : ((1u << (8 * a.m)) - 1u);
     const uint32_t rmask = a.A_mask ? a.A_mask[rowc] : full;
     const int mq = __popc(rmask) / 8;
-    const float mult_base = (float)mq;
 
     const int64_t cbeg = (int64_t)blockIdx.y * a.col_span;
     const int64_t cend = min(a.nb, cbeg + a.col_span);
@@ -244,8 +244,7 @@ __global__ __launch_bounds__(128) void k_dense_topk(const TopkArgs a)
                     continue;
                 float d2 = rn + nb4[r] - 2.0f * acc[s][r];
                 d2 = fmaxf(d2, 0.0f);
-                const float mult = mult_base == 0.0f ? 1.0f : (mult_base + c) * (mult_base + c);
-                const float key = a.mode == 0 ? d2 * mult : d2;
+                const float key = a.mode == 0 ? w_key32(d2, c, mq, a.w) : d2;
                 if (lt_key(key, (uint32_t)col, tk, ti)) {
                     const int slot = atomicAdd(&cnt[rl], 1);
                     bk[rl * cap + slot] = key;
@@ -342,7 +341,8 @@ int launch_dp(const TopkArgs &a, hipStream_t st)
 int launch_dense_topk(const float *A, const float *A_norm, const uint32_t *A_attr,
                       const uint32_t *A_mask, int64_t na, const float *B, const float *B_norm,
                       const uint32_t *B_attr, int64_t nb, int dp, int m, int mode,
-                      int self_exclude, int K, int32_t *out_ids, float *out_keys, hipStream_t st)
+                      int self_exclude, int K, int32_t *out_ids, float *out_keys, hipStream_t st,
+                      const Weights *w)
 {
     if (K < 1 || K > 160)
         return fail(NHQ_EINVAL, "dense top-K supports 1 <= K <= 160");
@@ -362,6 +362,7 @@ int launch_dense_topk(const float *A, const float *A_norm, const uint32_t *A_att
     // re-ranked only after at least 64 new survivors
     a.cap = ((K + 128 + 15) / 16) * 16;
     a.mode = mode;
+    a.w = w ? *w : Weights{NHQ_WEIGHTS_DEFAULT, 0.0f, 0.0};
     a.self_exclude = self_exclude;
     if (na == 0 || nb == 0)
         return NHQ_OK;

@@ -318,6 +318,13 @@ int nhq_index_create(const float *vecs, const uint8_t *attrs, int64_t n, int32_t
         return fail(NHQ_EINVAL, "storage must be 0, 1 or 2");
     if (p.n_entry < 1 || p.n_entry > 65536)
         return fail(NHQ_EINVAL, "n_entry must be in [1, 65536]");
+    if (p.weights < NHQ_WEIGHTS_DEFAULT || p.weights > NHQ_WEIGHTS_FIXED)
+        return fail(NHQ_EINVAL, "weights must be an NHQ_WEIGHTS_* value");
+    if ((p.weights == NHQ_WEIGHTS_HARMONIC_C && !(p.weight_param > 1.0)) ||
+        (p.weights == NHQ_WEIGHTS_NORMALISED && !(p.weight_param > 0.0)) ||
+        (p.weights == NHQ_WEIGHTS_FIXED && !(p.weight_param >= 0.0)) ||
+        !(p.weight_param < 3.0e38))
+        return fail(NHQ_EINVAL, "weight_param out of range for the weight setting");
 
     hipStream_t st = (hipStream_t)stream;
     nhq_index *h = new (std::nothrow) nhq_index();
@@ -338,6 +345,10 @@ int nhq_index_create(const float *vecs, const uint8_t *attrs, int64_t n, int32_t
         ix->cand = p.cand;
         ix->reverse_edges = p.reverse_edges ? 1 : 0;
         ix->seed = p.seed;
+        ix->w.mode = p.weights;
+        ix->w.pd = p.weights == NHQ_WEIGHTS_DEFAULT || p.weights == NHQ_WEIGHTS_HARMONIC
+                       ? 0.0 : p.weight_param;
+        ix->w.p = (float)ix->w.pd;
         ix->degree = 0;
         const int want_degree = p.degree;
         const size_t rows = (size_t)n * ix->dp;
@@ -622,7 +633,7 @@ int nhq_seed_rank(const nhq_index *h, const float *queries, const uint8_t *qattr
         else
             rc = launch_dense_topk(qpad, qnorm, qw, qm, nq, ix->entry_vec, ix->entry_norm,
                                    ix->entry_attr, ix->n_entry, ix->dp, ix->m, 0, 0, n_cand, cand,
-                                   nullptr, st);
+                                   nullptr, st, &ix->w);
     }
     (void)hipFreeAsync(blk, st);
     return rc;

@@ -9,6 +9,7 @@
 #include <string>
 
 #include "nhq.h"
+#include "weights.h"
 
 // ------------------------------------------------------------------ errors
 namespace nhq {
@@ -46,6 +47,7 @@ struct Index {
     int reverse_edges = 0;
     int n_entry = 0;
     uint64_t seed = 0;
+    Weights w{NHQ_WEIGHTS_DEFAULT, 0.0f, 0.0};  // weight setting of Gamma
     float *vec32 = nullptr;     // [n][dp] float32 copy (rerank / fp32 storage)
     void *vecs = nullptr;       // storage form [n][dp] (== vec32 for fp32)
     float *scale = nullptr;     // fp8: per-row scale [n]
@@ -106,7 +108,8 @@ int launch_search(const SearchLaunch &s);
 int launch_dense_topk(const float *A, const float *A_norm, const uint32_t *A_attr,
                       const uint32_t *A_mask, int64_t na, const float *B, const float *B_norm,
                       const uint32_t *B_attr, int64_t nb, int dp, int m, int mode,
-                      int self_exclude, int K, int32_t *out_ids, float *out_keys, hipStream_t st);
+                      int self_exclude, int K, int32_t *out_ids, float *out_keys, hipStream_t st,
+                      const Weights *w = nullptr);
 
 // seed ranking of the entry sample (see seed.hip): positions of the K best
 // keys: scratch of nq * ((n_entry + 63) / 64 * 64) floats; qexact (nullable):

@@ -126,6 +126,7 @@ int launch_search(const SearchLaunch &s)
     a.ckpt = (s.learned || s.trace) ? s.check_every : 0;
     a.expand = s.expand;
     a.route_h = s.route_h;
+    a.w = ix->w;
     a.learned = s.learned;
     a.stop_logit = s.stop_logit;
     a.cap_factor = s.cap_factor;
@@ -161,7 +162,9 @@ int launch_search(const SearchLaunch &s)
         a.vis_words = 1 << hb;
         a.hash_log2 = hb;
     }
-    const size_t lds = sizeof(uint32_t) * ((size_t)ck_offset(a.L, a.scap, a.vis_words) + kCkWords);
+    // the checkpoint state exists only in the checkpointing kernel
+    const size_t lds = sizeof(uint32_t) *
+                       ((size_t)ck_offset(a.L, a.scap, a.vis_words) + (a.ckpt > 0 ? kCkWords : 0));
     if (s.nq > 0x7FFFFFFF)
         return fail(NHQ_EINVAL, "too many queries in one call");
     switch (ix->dp) {

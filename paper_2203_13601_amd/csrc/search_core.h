@@ -39,6 +39,7 @@ struct SearchArgs {
     int ckpt, learned;
     int expand;           // vertices expanded per step (1 = Alg. 2 as printed)
     int route_h;          // >= 2: two-stage routing, stage S1 evaluates 1 slot in h
+    Weights w;            // weight setting of Gamma (the index's)
     float stop_logit;     // learned: stop when the stop logit >= this
     float cap_factor;     // learned, > 0: hop budget cap_factor * 2^(beam output)
     const uint16_t *mlp;  // fp16 weights of the stop network
@@ -104,11 +105,6 @@ __device__ __forceinline__ int chi_of(uint32_t a, uint32_t qword, uint32_t qmask
     return __popc(y & 0x80808080u);
 }
 
-__device__ __forceinline__ float key_mult(int chi, int mq)
-{
-    return mq == 0 ? 1.0f : (float)((mq + chi) * (mq + chi));
-}
-
 __device__ __forceinline__ bool lt_key(float ka, uint32_t ia, float kb, uint32_t ib)
 {
     return ka < kb || (ka == kb && ia < ib);
@@ -167,7 +163,8 @@ template <int DP, int ST>
 __device__ __forceinline__ void score_batch(const void *vbase, const float *scale,
                                             const float4 (&qv)[Shape<DP>::NCH],
                                             uint32_t *sid, float *out, int nf, int mq,
-                                            int mode, const uint32_t *attr = nullptr,
+                                            int mode, const Weights &wt,
+                                            const uint32_t *attr = nullptr,
                                             uint32_t qword = 0, uint32_t qmask = 0)
 {
     using S = Shape<DP>;
@@ -221,10 +218,24 @@ __device__ __forceinline__ void score_batch(const void *vbase, const float *scal
                     c = chi_of(aw[rr], qword, qmask);
                     sid[j] = w[rr] | ((uint32_t)c << kChiShift);
                 }
-                out[j] = mode == 2 ? d2 : d2 * key_mult(c, mq);
+                // the default key inline; the other weight settings take
+                // delta^2 here and finish in weigh_keys
+                out[j] = (mode == 2 || wt.mode != NHQ_WEIGHTS_DEFAULT)
+                             ? d2
+                             : (mq == 0 ? d2 : d2 * (float)((mq + c) * (mq + c)));
             }
         }
     }
+}
+
+// Non-default weight settings: turn the staged delta^2 into the key (Gamma),
+// chi taken from the staged words.
+__device__ __forceinline__ void weigh_keys(float *skey, const uint32_t *sid, int n, int mq,
+                                        const Weights &w)
+{
+    for (int j = threadIdx.x & 63; j < n; j += 64)
+        skey[j] = w_key32(skey[j], (int)((sid[j] >> kChiShift) & 7u), mq, w);
+    wsync();
 }
 
 // Merge one batch of candidates (lane j holds candidate j when `valid`) into
@@ -409,6 +420,7 @@ struct CkState {
     int last_change, ntrace, have_first, have_prev, first_ckpt;
 };
 constexpr int kCkWords = 96;  // LDS words reserved for CkState
+constexpr int kNbBatch = 4;   // 64-slot adjacency chunks loaded together
 static_assert(sizeof(CkState) <= 4 * kCkWords, "checkpoint state size");
 
 // LDS word offset of the checkpoint state: after pool, staging and visited set
@@ -510,8 +522,10 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
         if (ok)
             sid[lanes_below(vb)] = (uint32_t)v;
         wsync();
-        score_batch<DP, ST>(a.vecs, a.scale, qv, sid, skey, ne, mq, 1, a.attr, qword, qmask);
+        score_batch<DP, ST>(a.vecs, a.scale, qv, sid, skey, ne, mq, 1, a.w, a.attr, qword, qmask);
         wsync();
+        if (a.w.mode != NHQ_WEIGHTS_DEFAULT)
+            weigh_keys(skey, sid, ne, mq, a.w);
         const float ck = lane < ne ? skey[lane] : 0.0f;
         const uint32_t cw = lane < ne ? sid[lane] : 0u;
         size = pool_merge(pkey, pid, size, cap0, ck, cw, lane < ne, lo);
@@ -666,12 +680,14 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
             pid[mysel] = pid[mysel] | kExpBit;
         lo = rdl_i(mysel, nexp - 1) + 1;
         hops += (uint32_t)nexp;
-        // ---- unvisited neighbours of the expanded vertices, in (vertex, slot) order
+        // ---- unvisited neighbours of the expanded vertices, in (vertex, slot)
+        // order.  With several vertices per step the adjacency words of up to
+        // kNbBatch 64-slot chunks are loaded before any is examined, so the
+        // step waits for one round trip, not one per chunk.
         const int total = nexp * a.R;
         int nf = 0;
         const int64_t u0 = (int64_t)rdl_u(myid, 0);
-        for (int s0 = 0; s0 < total; s0 += 64) {
-            const int sl = s0 + lane;
+        auto load_slot = [&](int sl) -> int {
             int qv_;
             if (rshift >= 0)
                 qv_ = sl >> rshift;
@@ -679,7 +695,6 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
                 qv_ = sl / a.R;
             const int e = min(qv_, nexp - 1), r = sl - qv_ * a.R;
             const int64_t u = (int64_t)(uint32_t)__shfl((int)myid, e, 64);
-            int nb = -1;
             bool take = sl < total;
             if (s1 && take) {
                 // S1: slot r of the e-th vertex of this step, expansion number t
@@ -687,8 +702,11 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
                 const uint32_t off = fmix32((uint32_t)u * 0x9E3779B1u + t) % (uint32_t)route_h;
                 take = ((uint32_t)r + off) % (uint32_t)route_h == 0;
             }
-            if (take)
-                nb = (E == 1 && pf_id == u0) ? pf_nb : a.adj[u * a.R + r];
+            if (!take)
+                return -1;
+            return (E == 1 && pf_id == u0) ? pf_nb : a.adj[u * a.R + r];
+        };
+        auto take_fresh = [&](int nb, int s0) {
             if (nb >= a.n || nb < -1) {
                 badid = true;
                 nb = -1;
@@ -713,6 +731,20 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
             if (fresh)
                 sid[nf + lanes_below(fb)] = (uint32_t)nb;
             nf += __popcll(fb);
+        };
+        if (total <= 64) {
+            take_fresh(load_slot(lane), 0);
+        } else {
+            for (int sb = 0; sb < total; sb += 64 * kNbBatch) {
+                int nbv[kNbBatch];
+#pragma unroll
+                for (int c = 0; c < kNbBatch; ++c)
+                    nbv[c] = sb + 64 * c < total ? load_slot(sb + 64 * c + lane) : -1;
+#pragma unroll
+                for (int c = 0; c < kNbBatch; ++c)
+                    if (sb + 64 * c < total)
+                        take_fresh(nbv[c], sb + 64 * c);
+            }
         }
         if (E == 1) {
             pf_id = -1;
@@ -735,8 +767,10 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
         }
         wsync();
         ndc += nf;
-        score_batch<DP, ST>(a.vecs, a.scale, qv, sid, skey, nf, mq, 1, a.attr, qword, qmask);
+        score_batch<DP, ST>(a.vecs, a.scale, qv, sid, skey, nf, mq, 1, a.w, a.attr, qword, qmask);
         wsync();
+        if (a.w.mode != NHQ_WEIGHTS_DEFAULT)
+            weigh_keys(skey, sid, nf, mq, a.w);
         int step_ins = 0;
         for (int c0 = 0; c0 < nf; c0 += 64) {
             const int j = c0 + lane;
@@ -785,7 +819,7 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
     got = min(got, want);
     wsync();
     // delta^2 from the float32 copy (identical to the loop's for fp32 storage)
-    score_batch<DP, NHQ_STORAGE_FP32>(a.vec32, nullptr, qv, sid, skey, got, mq, 2);
+    score_batch<DP, NHQ_STORAGE_FP32>(a.vec32, nullptr, qv, sid, skey, got, mq, 2, a.w);
     wsync();
     // final order into LDS (the pool is no longer needed), then one store
     // per output slot
@@ -798,19 +832,19 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
             int slot = j;
             if (a.rerank_n > 0) {
                 // rank by exact (key, id) among the re-scored entries
-                const float kj = d2 * key_mult(c, mq);
+                const float kj = w_key32(d2, c, mq, a.w);
                 const uint32_t ij = w & kIdMask;
                 slot = 0;
                 for (int i = 0; i < got; ++i) {
                     const uint32_t wi = sid[i];
-                    const float ki = skey[i] * key_mult((int)((wi >> kChiShift) & 7u), mq);
+                    const float ki = w_key32(skey[i], (int)((wi >> kChiShift) & 7u), mq, a.w);
                     slot += lt_key(ki, wi & kIdMask, kj, ij) ? 1 : 0;
                 }
             }
             if (slot < a.k) {
                 const float dl = sqrtf(d2);
                 pid[slot] = w & kIdMask;
-                pkey[slot] = mq == 0 ? dl : dl * ((float)(mq + c) / (float)mq);
+                pkey[slot] = w_gamma32(dl, c, mq, a.w);
             }
         }
     }

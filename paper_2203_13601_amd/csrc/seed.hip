@@ -41,6 +41,7 @@ struct KeyArgs {
     float *keys;          // [nq][ne_pad]
     int64_t nq;
     int ne, ne_pad;
+    Weights w;            // weight setting of Gamma
 };
 
 template <int DP>
@@ -81,8 +82,7 @@ __device__ __forceinline__ void store_keys(const KeyArgs &a, const f32x4 (&acc)[
         for (int r = 0; r < 4; ++r) {
             const float d2 = fmaxf(rn + nb4[r] - 2.0f * acc[s][r], 0.0f);
             const int c = chi_of(at4[r], qw, qm);
-            const float mult = mq == 0.0f ? 1.0f : (mq + c) * (mq + c);
-            k4[r] = cb0 + r < a.ne ? d2 * mult : __int_as_float(0x7F800000);
+            k4[r] = cb0 + r < a.ne ? w_key32(d2, c, (int)mq, a.w) : __int_as_float(0x7F800000);
         }
         *reinterpret_cast<float4 *>(stage + rl * 68 + 16 * s + 4 * lq) = make_float4(k4[0], k4[1], k4[2], k4[3]);
     }
@@ -332,7 +332,7 @@ int launch_seed_rank(const Index *ix, const float *qpad, const float *qnorm, con
     if (nj > 128)
         return fail(NHQ_EINVAL, "entry sample larger than 8192");
     KeyArgs a{qpad, qnorm, qword, qmask, ix->entry_vec, ix->entry_norm, ix->entry_attr, ix->entry_bf16,
-              qexact, keys, nq, ne, ne_pad};
+              qexact, keys, nq, ne, ne_pad, ix->w};
     const dim3 grid((unsigned)((nq + 63) / 64), (unsigned)((ne_pad + 255) / 256));
     int rc = NHQ_OK;
     switch (ix->dp) {

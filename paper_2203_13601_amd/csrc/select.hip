@@ -46,11 +46,13 @@ struct SShape {
 };
 
 // float64 key of `center` (row held in registers as qv) against ids[0..n):
-// out[j] = delta^2 * (m + chi)^2 (delta^2 when m = 0).
+// the fusion key of the weight setting w over m attributes (default:
+// delta^2 * (m + chi)^2, and delta^2 when m = 0).
 template <int DP>
 __device__ void exact_keys(const float *vec32, const uint32_t *attr, uint32_t cattr,
-                           uint32_t mask, int m, const float4 (&qv)[SShape<DP>::NCH],
-                           const uint32_t *ids, double *out, int n)
+                           uint32_t mask, int m, const Weights &w,
+                           const float4 (&qv)[SShape<DP>::NCH], const uint32_t *ids, double *out,
+                           int n)
 {
     using S = SShape<DP>;
     const int lane = threadIdx.x & 63;
@@ -81,8 +83,7 @@ __device__ void exact_keys(const float *vec32, const uint32_t *attr, uint32_t ca
             d2 += __shfl_xor(d2, o, 64);
         if (j < n && g == 0) {
             const int c = chi_full(attr[id], cattr, mask);
-            const double mult = m == 0 ? 1.0 : (double)((m + c) * (m + c));
-            out[j] = d2 * mult;
+            out[j] = w_key64(d2, c, m, w);
         }
     }
 }
@@ -140,8 +141,8 @@ __device__ void sort_pairs(double *k, uint32_t *id, int n)
 // ids go to sel[0..), returns their count (<= R).
 template <int DP>
 __device__ int landing_walk(const float *vec32, const uint32_t *attr, uint32_t mask, int m,
-                            const double *ck, const uint32_t *ci, int nc, int R, uint32_t *sel,
-                            double *scratch)
+                            const Weights &w, const double *ck, const uint32_t *ci, int nc, int R,
+                            uint32_t *sel, double *scratch)
 {
     const int lane = threadIdx.x & 63;
     int nsel = 0;
@@ -151,7 +152,7 @@ __device__ int landing_walk(const float *vec32, const uint32_t *attr, uint32_t m
         bool ok = true;
         if (nsel > 0) {
             load_center<DP>(vec32, p, pv);
-            exact_keys<DP>(vec32, attr, attr[p], mask, m, pv, sel, scratch, nsel);
+            exact_keys<DP>(vec32, attr, attr[p], mask, m, w, pv, sel, scratch, nsel);
             wsync();
             const double kpi = ck[t];
             const bool blocked = lane < nsel && !(kpi < scratch[lane]);
@@ -174,6 +175,7 @@ struct SelArgs {
     int32_t *adj;         // [n][R]
     int64_t n;
     int m, K, l, R;
+    Weights w;
 };
 
 template <int DP>
@@ -203,11 +205,11 @@ __global__ __launch_bounds__(64) void k_select(const SelArgs a)
     wsync();
     float4 qv[SShape<DP>::NCH];
     load_center<DP>(a.vec32, i, qv);
-    exact_keys<DP>(a.vec32, a.attr, a.attr[i], mask, a.m, qv, ci, ck, nc);
+    exact_keys<DP>(a.vec32, a.attr, a.attr[i], mask, a.m, a.w, qv, ci, ck, nc);
     wsync();
     sort_pairs<4>(ck, ci, nc);
     const int nl = min(nc, a.l);
-    const int ns = landing_walk<DP>(a.vec32, a.attr, mask, a.m, ck, ci, nl, a.R, sel, scratch);
+    const int ns = landing_walk<DP>(a.vec32, a.attr, mask, a.m, a.w, ck, ci, nl, a.R, sel, scratch);
     for (int e = lane; e < a.R; e += 64)
         a.adj[i * a.R + e] = e < ns ? (int32_t)sel[e] : -1;
 }
@@ -225,6 +227,7 @@ struct RevArgs {
     const int64_t *poff;     // [n+1] offsets into wk / wi
     int64_t n;
     int m, R;
+    Weights w;
 };
 
 template <int DP>
@@ -265,7 +268,7 @@ __global__ __launch_bounds__(64) void k_reverse(const RevArgs a)
     wsync();
     float4 qv[SShape<DP>::NCH];
     load_center<DP>(a.vec32, j, qv);
-    exact_keys<DP>(a.vec32, a.attr, a.attr[j], mask, a.m, qv, pi, pk, np);
+    exact_keys<DP>(a.vec32, a.attr, a.attr[j], mask, a.m, a.w, qv, pi, pk, np);
     __threadfence();
     wsync();
     // landing-zone walk in (key, id) order: extract the next smallest entry
@@ -300,7 +303,7 @@ __global__ __launch_bounds__(64) void k_reverse(const RevArgs a)
         if (nsel > 0) {
             float4 pv[SShape<DP>::NCH];
             load_center<DP>(a.vec32, bi, pv);
-            exact_keys<DP>(a.vec32, a.attr, a.attr[bi], mask, a.m, pv, sel, scratch, nsel);
+            exact_keys<DP>(a.vec32, a.attr, a.attr[bi], mask, a.m, a.w, pv, sel, scratch, nsel);
             wsync();
             const bool blocked = lane < nsel && !(bk < scratch[lane]);
             ok = __ballot(blocked) == 0;
@@ -363,7 +366,7 @@ int launch_select(const Index *ix, const int32_t *cand, int K, int l, int32_t *a
 {
     if (K > 256)
         return fail(NHQ_EINVAL, "candidate list longer than 256");
-    SelArgs a{ix->vec32, ix->attr, cand, adj, ix->n, ix->m, K, l, ix->degree};
+    SelArgs a{ix->vec32, ix->attr, cand, adj, ix->n, ix->m, K, l, ix->degree, ix->w};
     switch (ix->dp) {
     case 32: return launch_select_dp<32>(a, st);
     case 64: return launch_select_dp<64>(a, st);
@@ -414,7 +417,9 @@ __global__ __launch_bounds__(64) void k_refine(const RefArgs a)
     wsync();
     float4 qv[SShape<DP>::NCH];
     load_center<DP>(a.qpad, qi, qv);
-    exact_keys<DP>(a.vec32, a.attr, 0u, 0u, 0, qv, ci, ck, nc);
+    // Def. 4 ground truth: exact matches ranked by delta alone
+    exact_keys<DP>(a.vec32, a.attr, 0u, 0u, 0, Weights{NHQ_WEIGHTS_DEFAULT, 0.0f, 0.0}, qv, ci, ck,
+                   nc);
     wsync();
     sort_pairs<4>(ck, ci, nc);
     for (int e = lane; e < a.k; e += 64) {
@@ -484,7 +489,7 @@ int launch_reverse(const Index *ix, const int32_t *fwd, int32_t *adj, hipStream_
     NHQ_HIP(hipMemcpyAsync(off, h.data(), sizeof(int64_t) * (size_t)(n + 1), hipMemcpyHostToDevice, st));
     NHQ_HIP(hipMemcpyAsync(dpoff, poff.data(), sizeof(int64_t) * (size_t)(n + 1), hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_fill_incoming, dim3(grid), dim3(256), 0, st, fwd, n, R, off, fill, inc);
-    RevArgs a{ix->vec32, ix->attr, fwd, off, inc, adj, wk, wi, dpoff, n, ix->m, R};
+    RevArgs a{ix->vec32, ix->attr, fwd, off, inc, adj, wk, wi, dpoff, n, ix->m, R, ix->w};
     int rc = NHQ_OK;
     switch (ix->dp) {
     case 32: rc = launch_reverse_dp<32>(a, st); break;

@@ -112,7 +112,7 @@ __device__ void doorbell(const ServeArgs &s, unsigned long long t_end)
 // rows (lane per entry, four entries per pass), as bit patterns into kb.
 template <int DP>
 __device__ void entry_keys_wave(const float *ev, const uint32_t *ea, int ne, const float *qlds,
-                                uint32_t qword, uint32_t qmask, uint32_t *kb)
+                                uint32_t qword, uint32_t qmask, const Weights &w, uint32_t *kb)
 {
     const int lane = threadIdx.x & 63;
     const int mq = __popc(qmask) / 8;
@@ -143,7 +143,7 @@ __device__ void entry_keys_wave(const float *ev, const uint32_t *ea, int ne, con
         for (int r = 0; r < 4; ++r) {
             const int e = e0 + 64 * r + lane;
             if (e < ne)
-                kb[e] = __float_as_uint(acc[r] * key_mult(chi_of(ea[e], qword, qmask), mq));
+                kb[e] = __float_as_uint(w_key32(acc[r], chi_of(ea[e], qword, qmask), mq, w));
         }
     }
 }
@@ -236,7 +236,8 @@ __global__ __launch_bounds__(64) void k_serve(const SearchArgs base, const Serve
         a.scap = want > 64 ? (want + 63) & ~63 : 64;
 
         // seed set: the n_cand best of the entry sample, then as in the batch search
-        entry_keys_wave<DP>(base.entry_vec_f, base.entry_attr, base.n_entry, qlds, qword, qmask, kb);
+        entry_keys_wave<DP>(base.entry_vec_f, base.entry_attr, base.n_entry, qlds, qword, qmask,
+                            base.w, kb);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         select_lds(kb, base.n_entry, s.n_cand, cv, cp, seedpos);
@@ -534,6 +535,7 @@ int nhq_server_create(nhq_index *h, const nhq_server_params *pp, nhq_server **ou
     base.n_entry = ix->n_entry;
     base.n_init = p.n_init;
     base.expand = p.expand;
+    base.w = ix->w;
     base.stop_logit = s.stop_logit;
     base.cap_factor = p.cap_factor;
     base.mlp = reinterpret_cast<const uint16_t *>(ix->mlp);

@@ -1,0 +1,98 @@
+"""GPU parity of the weight settings of Gamma (Eq. 6; Sec. 6.5, Eq. 8)
+against the CPU oracle, through the C ABI: the composite-index build and the
+search, on integer-valued vectors (exact distances), for every setting."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+nhq = pytest.importorskip("paper_2203_13601_amd")
+
+SETTINGS = [("harmonic", 0.0), ("harmonic_c", 100.0), ("normalised", 1500.0), ("fixed", 200.0),
+            ("default", 0.0)]
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module")
+def int_set():
+    return synth.small(3000, 32, 64, seed=83, integer=True, n_centres=6, cards=(2, 3, 4))
+
+
+@pytest.mark.parametrize("mode,p", SETTINGS)
+def test_build_matches_oracle(int_set, mode, p):
+    w = int_set
+    ix = nhq.nhq_build_index(_dev(w.x), _dev(w.attrs), degree=16, cand=32, n_entry=64, seed=1,
+                             weights=mode, weight_param=p)
+    adj = nhq.nhq_index_get_graph(ix).cpu().numpy()
+    with oracle.weights(mode, p):
+        want = oracle.build_graph(w.x, w.attrs, l=32, R=16)
+    same = (adj == want).all(axis=1)
+    assert same.mean() >= 0.999, same.mean()
+
+
+@pytest.mark.parametrize("mode,p", SETTINGS)
+@pytest.mark.parametrize("E", [1, 4])
+def test_search_matches_oracle(int_set, mode, p, E):
+    w = int_set
+    with oracle.weights(mode, p):
+        adj = oracle.build_graph(w.x, w.attrs, l=32, R=16)
+    ix = nhq.nhq_index_create(_dev(w.x), _dev(w.attrs), n_entry=128, seed=w.build_seed, degree=16,
+                              weights=mode, weight_param=p)
+    nhq.nhq_index_set_graph(ix, _dev(adj))
+    entry = oracle.entry_points(w.build_seed, w.n, 128)
+    ids, dist, cnt = nhq.nhq_hybrid_search(ix, _dev(w.q), _dev(w.qattrs), 10, 48, expand=E,
+                                           counters=True)
+    ids, dist, cnt = ids.cpu().numpy(), dist.cpu().numpy(), cnt.cpu().numpy()
+    for out_mode in (0, 1):
+        with oracle.weights(mode, p):
+            oi, og, ondc, ohops, _ = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, 48, entry,
+                                                   key_mode=oracle.KEY32, expand=E,
+                                                   out_mode=out_mode)
+        if out_mode == 1:
+            gi, gd = nhq.nhq_hybrid_search(ix, _dev(w.q), _dev(w.qattrs), 10, 48, expand=E,
+                                           output_mode=1)
+            ids, dist = gi.cpu().numpy(), gd.cpu().numpy()
+        assert np.array_equal(ids, oi)
+        fin = np.isfinite(og)
+        assert np.array_equal(np.isfinite(dist), fin)
+        assert np.allclose(dist[fin], og[fin], rtol=1e-4, atol=0.0)
+        if out_mode == 0:
+            assert np.array_equal(cnt[:, 0], ondc)
+            assert np.array_equal(cnt[:, 1], ohops)
+
+
+def test_rerank_under_weights(int_set):
+    # the exact re-score of the precision form re-sorts by the same setting
+    w = int_set
+    with oracle.weights("fixed", 200.0):
+        adj = oracle.build_graph(w.x, w.attrs, l=32, R=16)
+    ix = nhq.nhq_index_create(_dev(w.x), _dev(w.attrs), n_entry=128, seed=w.build_seed, degree=16,
+                              storage="bf16", weights="fixed", weight_param=200.0)
+    nhq.nhq_index_set_graph(ix, _dev(adj))
+    entry = oracle.entry_points(w.build_seed, w.n, 128)
+    ids, dist = nhq.nhq_hybrid_search(ix, _dev(w.q), _dev(w.qattrs), 10, 48, rerank=4)
+    ids, dist = ids.cpu().numpy(), dist.cpu().numpy()
+    xs = oracle.from_bf16_bits(oracle.to_bf16_bits(w.x)).astype(np.float32)
+    with oracle.weights("fixed", 200.0):
+        oi, og, _, _, _ = oracle.search(adj, xs, w.attrs, w.q, w.qattrs, 10, 48, entry,
+                                        key_mode=oracle.KEY32, rerank_n=40, xr=w.x)
+    assert np.array_equal(ids, oi)
+    fin = np.isfinite(og)
+    assert np.allclose(dist[fin], og[fin], rtol=1e-4)
+
+
+def test_weight_argument_checks(int_set):
+    w = int_set
+    x, a = _dev(w.x[:100]), _dev(w.attrs[:100])
+    for kw in ({"weights": 7}, {"weights": "harmonic_c", "weight_param": 1.0},
+               {"weights": "normalised", "weight_param": 0.0},
+               {"weights": "fixed", "weight_param": -1.0}):
+        with pytest.raises(Exception):
+            nhq.nhq_index_create(x, a, **kw)
