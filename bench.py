@@ -88,8 +88,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (counter scaling)")
-    ap.add_argument("--workload", default="plain", choices=["plain", "precision"],
-                    help="precision: the d = 960 storage forms (fp32 / bf16 / fp8 + exact rerank)")
+    ap.add_argument("--workload", default="plain", choices=["plain", "precision", "ablation"],
+                    help="precision: the d = 960 storage forms (fp32 / bf16 / fp8 + exact rerank); "
+                         "ablation: weight settings, selectivity and post-filtering sweeps")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -106,6 +107,8 @@ def main():
 
     if args.workload == "precision":
         return precision_form(args)
+    if args.workload == "ablation":
+        return ablation(args)
     dev = torch.device("cuda:0")
     t_gen = time.time()
     w = synth.config2(n=args.n, nq=args.nq)
@@ -558,6 +561,152 @@ def precision_form(args):
                       "build_s": round(build_s, 2)},
            "forms": forms}
     print(json.dumps(out), flush=True)
+
+
+def ablation(args):
+    """Parameter studies of the paper's Sec. 6.5 on the config-2 shape (1M x
+    128 integer clusters, 10,000 queries, k = 10), each a Recall@10 / QPS
+    curve over the beam (one step = seed ranking + search, E = --expand):
+      weights      the five weight settings of Gamma (Fig. 10 (i), curves
+                   i-v; Eq. 8 with c = 100), each with its own index;
+      selectivity  attribute cardinalities giving |P|/|S| = 1/8 ... 1/4000
+                   (full constraints, default weights);
+      post_filter  strategy B(1) on the default composite index: a search
+                   by vector alone (every attribute a wildcard) whose raw
+                   pool is then filtered to exact matches; the filter runs on
+                   the host and is not timed, so its QPS is an upper bound.
+    Recall is computed from the true vector distance of each returned
+    object, since Gamma differs from delta under the other settings."""
+    import torch
+    import synth
+    import paper_2203_13601_amd as nhq
+    from paper_2203_13601_amd.metrics import qps_at_recall, recall_at_k
+
+    dev = torch.device("cuda:0")
+    w = synth.config2(n=args.n, nq=args.nq)
+    log("generated %s" % w.name)
+    x = torch.from_numpy(w.x).to(dev)
+    q = torch.from_numpy(w.q).to(dev)
+    nq, k = w.nq, w.k
+    n_cand = min(args.n_entry, args.n_init + 16)
+    beams = [10, 16, 32, 64, 128, 256, 512]
+
+    def true_delta(ids):
+        v = np.where(ids >= 0, ids, 0)
+        dd = np.sqrt(((w.x[v].astype(np.float64) - w.q[:, None, :]) ** 2).sum(-1))
+        return np.where(ids >= 0, dd, np.inf)
+
+    def curve(ix, attrs_np, qattrs_np, gi, gd, label, raw_filter=False):
+        qa_dev = torch.from_numpy(qattrs_np).to(dev)
+        qa_search = torch.full_like(qa_dev, 255) if raw_filter else qa_dev
+        rows = []
+        for beam in beams:
+            kk = beam if raw_filter else k
+
+            def step():
+                cand = nhq.nhq_seed_rank(ix, q, qa_search, n_cand)
+                return nhq.nhq_search_seeded(ix, q, qa_search, cand, kk, beam, n_init=args.n_init,
+                                             expand=args.expand, output_mode=1 if raw_filter else 0)
+            ids, _ = step()
+            ids = ids.cpu().numpy()
+            if raw_filter:
+                keep = np.full((nq, k), -1, dtype=np.int64)
+                for i in range(nq):
+                    m_ = ids[i][ids[i] >= 0]
+                    m_ = m_[(attrs_np[m_] == qattrs_np[i]).all(axis=1)][:k]
+                    keep[i, :len(m_)] = m_
+                ids = keep
+            rec = float(recall_at_k(ids, true_delta(ids), gi, gd, attrs_np, qattrs_np, k).mean())
+            step()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(3):
+                step()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 3
+            rows.append({"beam": beam, "recall": round(rec, 5), "qps": round(nq / (ms / 1000.0), 1)})
+            log("%s beam %d recall %.4f %.0f QPS" % (label, beam, rec, rows[-1]["qps"]))
+            if rec >= 0.999:
+                break
+        at = qps_at_recall([r["beam"] for r in rows], [r["recall"] for r in rows],
+                           [r["qps"] for r in rows], args.target)
+        return {"curve": rows, "qps_at_target": None if at is None else round(at, 1),
+                "best_recall": max(r["recall"] for r in rows)}
+
+    def index_for(attrs_np, **params):
+        a_dev = torch.from_numpy(attrs_np).to(dev)
+        t = time.time()
+        ix = nhq.nhq_build_index(x, a_dev, degree=w.degree, cand=w.cand, n_entry=args.n_entry,
+                                 seed=w.build_seed, **params)
+        torch.cuda.synchronize()
+        return ix, a_dev, time.time() - t
+
+    out = {}
+    # ---- weight settings
+    ix0, a0, b0 = index_for(w.attrs)
+    gi, gd = nhq.nhq_bruteforce_hybrid_knn(ix0, q, torch.from_numpy(w.qattrs).to(dev), k)
+    gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
+    # delta statistics of the object set: the largest distance from 1,000
+    # sampled objects to all objects (delta_max of curve iii) and the median
+    # over 100,000 random pairs (the ratio of curve v, which the paper puts
+    # close to the median delta)
+    rng = np.random.default_rng(5)
+    smp = torch.from_numpy(rng.integers(0, w.n, 1000)).to(dev)
+    xs = x[smp].double()
+    dmax2 = 0.0
+    for c0 in range(0, w.n, 100_000):
+        blk = x[c0:c0 + 100_000].double()
+        d2 = (xs * xs).sum(1)[:, None] + (blk * blk).sum(1)[None, :] - 2.0 * xs @ blk.T
+        dmax2 = max(dmax2, float(d2.max()))
+    pa, pb = rng.integers(0, w.n, 100_000), rng.integers(0, w.n, 100_000)
+    dmed = float(np.median(np.sqrt(((w.x[pa].astype(np.float64) - w.x[pb]) ** 2).sum(1))))
+    dmax = float(np.sqrt(dmax2))
+    log("delta_max %.1f, median delta %.1f" % (dmax, dmed))
+    settings = [("iv", "default", 0.0), ("i", "harmonic", 0.0), ("ii", "harmonic_c", 100.0),
+                ("iii", "normalised", dmax), ("v", "fixed", dmed)]
+    wres = {}
+    for curve_id, mode, p in settings:
+        if mode == "default":
+            ix, bs = ix0, b0
+        else:
+            ix, _, bs = index_for(w.attrs, weights=mode, weight_param=p)
+        r = curve(ix, w.attrs, w.qattrs, gi, gd, "weights %s (%s)" % (curve_id, mode))
+        r.update({"setting": mode, "param": p, "build_s": round(bs, 2)})
+        wres[curve_id] = r
+        if ix is not ix0:
+            ix.free()
+    out["weights"] = wres
+    # ---- strategy B(1): vector-only search, then the attribute filter
+    out["post_filter"] = curve(ix0, w.attrs, w.qattrs, gi, gd, "post-filter B(1)", raw_filter=True)
+    # ---- selectivity
+    sres = {}
+    for cards in ((2, 2, 2), (3, 4, 5), (5, 8, 10), (10, 20, 20)):
+        if cards == tuple(w.cards):
+            ix, a_np, qa_np, g_i, g_d = ix0, w.attrs, w.qattrs, gi, gd
+        else:
+            a_np = synth.uniform_attrs(w.n, cards, 202)
+            qa_np = synth.uniform_attrs(nq, cards, 204)
+            ix, a_dev, _ = index_for(a_np)
+            g_i, g_d = nhq.nhq_bruteforce_hybrid_knn(ix, q, torch.from_numpy(qa_np).to(dev), k)
+            g_i, g_d = g_i.cpu().numpy(), g_d.cpu().numpy()
+        frac = 1.0 / float(np.prod(cards))
+        r = curve(ix, a_np, qa_np, g_i, g_d, "selectivity 1-1/%d" % int(np.prod(cards)))
+        r.update({"cards": list(cards), "match_fraction": frac, "selectivity": 1.0 - frac})
+        sres["1/%d" % int(np.prod(cards))] = r
+        if ix is not ix0:
+            ix.free()
+    out["selectivity"] = sres
+    print(json.dumps({"metric": "parameter studies (Sec. 6.5): Recall@10 / QPS curves on 1 GPU",
+                      "value": wres["iv"]["qps_at_target"], "unit": "queries/s", "n_gpus": 1,
+                      "higher_is_better": True, "vs_baseline": None, "dtype": "f32",
+                      "data": "synthetic",
+                      "config": {"workload": w.name, "n": w.n, "d": w.d, "queries_per_step": nq,
+                                 "k": k, "expand": args.expand, "n_init": args.n_init,
+                                 "n_entry": args.n_entry, "delta_max": dmax, "delta_median": dmed},
+                      **out}), flush=True)
 
 
 if __name__ == "__main__":
