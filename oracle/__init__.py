@@ -77,6 +77,10 @@ def lib():
         L.or_build.argtypes = [P, P, i64, i32, i32, i32, i32, i32, P, i64, P, P, i32]
         L.or_knn_rows.restype = None
         L.or_knn_rows.argtypes = [P, P, i64, i32, i32, i32, P, i64, i32, P, i32]
+        L.or_nndescent.restype = None
+        L.or_nndescent.argtypes = [P, P, i64, i32, i32, i32, i32, i32, ctypes.c_uint64, i32, P, P, i32]
+        L.or_select_lists.restype = None
+        L.or_select_lists.argtypes = [P, P, i64, i32, i32, P, i32, i32, P, i32]
         L.or_set_weights.restype = None
         L.or_set_weights.argtypes = [i32, ctypes.c_double]
         L.or_search.restype = None
@@ -186,6 +190,37 @@ def build_graph(x, attrs, l: int, R: int, reverse: bool = False,
     return (adj, cand) if want_cand else adj
 
 
+def nndescent(x, attrs, l: int, s: int, rounds: int, seed: int, key_mode: int = KEY32,
+              threads: Optional[int] = None):
+    """Candidate lists of NPG_kgraph (Sec. 4.3): random lists refined through
+    neighbours of neighbours in synchronous rounds; see or_nndescent.
+    Returns (ids [n, l] sorted by (key, id), updates [rounds])."""
+    x, attrs = _f32(x), _u8(attrs)
+    n, d = x.shape
+    m = attrs.shape[1]
+    if n <= l:
+        raise ValueError("NN-descent needs n > l")
+    ids = np.empty((n, l), dtype=np.int32)
+    upd = np.zeros(max(rounds, 1), dtype=np.int64)
+    lib().or_nndescent(_p(x), _p(attrs), n, d, m, int(l), int(s), int(rounds),
+                       ctypes.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), int(key_mode), _p(ids),
+                       _p(upd), _threads(threads))
+    return ids, upd[:rounds]
+
+
+def select_lists(x, attrs, lists, R: int, threads: Optional[int] = None) -> np.ndarray:
+    """Edge selection (Sec. 4.1 (2)-(3)) over given candidate lists, each
+    re-ordered by the exact FP64 key (forward pass only)."""
+    x, attrs = _f32(x), _u8(attrs)
+    n, d = x.shape
+    m = attrs.shape[1]
+    lists = np.ascontiguousarray(lists, dtype=np.int32)
+    adj = np.empty((n, R), dtype=np.int32)
+    lib().or_select_lists(_p(x), _p(attrs), n, d, m, _p(lists), lists.shape[1], int(R), _p(adj),
+                          _threads(threads))
+    return adj
+
+
 def knn_rows(x, attrs, rows, k: int, use_attrs: bool = True,
              threads: Optional[int] = None) -> np.ndarray:
     x, attrs = _f32(x), _u8(attrs)
@@ -223,7 +258,7 @@ def splitmix64(state: int):
 
 
 def entry_points(build_seed: int, n: int, n_seeds: int = 32) -> np.ndarray:
-    """Seed set B of Alg. 2 ("usually selected randomly", Sec. 3.2): the
+    """Seed set B of Alg. 2 (random seeds, Sec. 3.2): the
     first min(n_seeds, n) distinct values of splitmix64(build_seed) mod n."""
     want = min(n_seeds, n)
     out: List[int] = []

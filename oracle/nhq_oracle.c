@@ -402,6 +402,180 @@ void or_build(const float *x, const uint8_t *attrs, int64_t n, int d, int m, int
     free(offer_cnt);
 }
 
+/* ------------------------------------------- NN-descent (Sec. 4.3, NPG_kgraph) */
+/* splitmix64 (Steele, Lea and Flood, 2014): one step of the generator */
+static uint64_t sm64_next(uint64_t *state)
+{
+    uint64_t z = (*state += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+typedef struct {
+    double key;
+    int64_t id;
+    int isnew;
+} nnd_entry;
+
+static int nnd_cmp(const void *pa, const void *pb)
+{
+    const nnd_entry *a = (const nnd_entry *)pa, *b = (const nnd_entry *)pb;
+    if (lt(a->key, a->id, b->key, b->id))
+        return -1;
+    if (lt(b->key, b->id, a->key, a->id))
+        return 1;
+    return 0;
+}
+
+/* Candidate lists C(i) of l entries refined through neighbours of
+ * neighbours, in synchronous rounds (round t reads only the lists of round
+ * t - 1):
+ *   round 0: C(i) = the first l distinct values v != i of (splitmix64 with
+ *            state seed ^ (i * 0xD1B54A32D192ED03)) mod n, ordered by
+ *            (key, id); every entry is new;
+ *   round t: J = the first s new entries of C(i) in list order.  The
+ *            candidates are the ids of C(j), j in J, that are neither i nor
+ *            in C(i), each taken once.  C(i) becomes the l best of C(i) and
+ *            the candidates by (key, id); candidates enter as new, the
+ *            entries of J become old, the other entries keep their state.
+ * Keys are the object-object fusion keys (all m attributes) in key_mode.
+ * Needs n > l.  out_ids [n][l] holds the lists after `rounds` rounds;
+ * updates[t - 1] = sum over i of |C_t(i) \ C_(t-1)(i)|. */
+void or_nndescent(const float *x, const uint8_t *attrs, int64_t n, int d, int m, int l, int s,
+                  int rounds, uint64_t seed, int key_mode, int32_t *out_ids, int64_t *updates,
+                  int nthreads)
+{
+    nnd_entry *cur = (nnd_entry *)malloc(sizeof(nnd_entry) * (size_t)n * l);
+    nnd_entry *nxt = (nnd_entry *)malloc(sizeof(nnd_entry) * (size_t)n * l);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        nnd_entry *row = cur + i * l;
+        uint64_t st = seed ^ ((uint64_t)i * 0xD1B54A32D192ED03ull);
+        int got = 0;
+        while (got < l) {
+            int64_t v = (int64_t)(sm64_next(&st) % (uint64_t)n);
+            int dup = v == i;
+            for (int t = 0; t < got && !dup; ++t)
+                dup = row[t].id == v;
+            if (dup)
+                continue;
+            double d2 = or_delta2(x + i * (int64_t)d, x + v * (int64_t)d, d);
+            int c = or_chi(attrs + i * (int64_t)m, attrs + v * (int64_t)m, m);
+            row[got].key = or_order_key(d2, c, m, key_mode);
+            row[got].id = v;
+            row[got].isnew = 1;
+            got += 1;
+        }
+        qsort(row, (size_t)l, sizeof(nnd_entry), nnd_cmp);
+    }
+    for (int r = 1; r <= rounds; ++r) {
+        int64_t upd = 0;
+#ifdef _OPENMP
+#pragma omp parallel reduction(+ : upd) num_threads(nthreads)
+#endif
+        {
+            int64_t *stamp = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+            for (int64_t v = 0; v < n; ++v)
+                stamp[v] = -1;
+            nnd_entry *pool = (nnd_entry *)malloc(sizeof(nnd_entry) * (size_t)(l + (int64_t)s * l));
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 16)
+#endif
+            for (int64_t i = 0; i < n; ++i) {
+                const nnd_entry *row = cur + i * l;
+                int np = 0;
+                int64_t J[64];
+                int nj = 0;
+                stamp[i] = i;
+                for (int t = 0; t < l; ++t) {
+                    pool[np] = row[t];
+                    stamp[row[t].id] = i;
+                    if (row[t].isnew && nj < s) {
+                        J[nj++] = row[t].id;
+                        pool[np].isnew = 0;
+                    }
+                    np += 1;
+                }
+                for (int e = 0; e < nj; ++e) {
+                    const nnd_entry *rj = cur + J[e] * l;
+                    for (int t = 0; t < l; ++t) {
+                        int64_t v = rj[t].id;
+                        if (stamp[v] == i)
+                            continue;
+                        stamp[v] = i;
+                        double d2 = or_delta2(x + i * (int64_t)d, x + v * (int64_t)d, d);
+                        int c = or_chi(attrs + i * (int64_t)m, attrs + v * (int64_t)m, m);
+                        pool[np].key = or_order_key(d2, c, m, key_mode);
+                        pool[np].id = v;
+                        pool[np].isnew = 2; /* a candidate of this round */
+                        np += 1;
+                    }
+                }
+                qsort(pool, (size_t)np, sizeof(nnd_entry), nnd_cmp);
+                nnd_entry *out = nxt + i * l;
+                for (int t = 0; t < l; ++t) {
+                    out[t] = pool[t];
+                    if (pool[t].isnew == 2) {
+                        out[t].isnew = 1;
+                        upd += 1;
+                    }
+                }
+            }
+            free(pool);
+            free(stamp);
+        }
+        if (updates)
+            updates[r - 1] = upd;
+        nnd_entry *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+    for (int64_t i = 0; i < n * l; ++i)
+        out_ids[i] = (int32_t)cur[i].id;
+    free(cur);
+    free(nxt);
+}
+
+/* Edge selection (Sec. 4.1 (2)-(3)) over given candidate lists [n][l]
+ * (-1 padded), re-ordered by the exact FP64 key; forward pass only. */
+void or_select_lists(const float *x, const uint8_t *attrs, int64_t n, int d, int m,
+                     const int32_t *lists, int l, int R, int32_t *adj_out, int nthreads)
+{
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        nnd_entry *e = (nnd_entry *)malloc(sizeof(nnd_entry) * (size_t)l);
+        double *ck = (double *)malloc(sizeof(double) * (size_t)l);
+        int64_t *ci = (int64_t *)malloc(sizeof(int64_t) * (size_t)l);
+        int nc = 0;
+        for (int t = 0; t < l; ++t) {
+            int64_t v = lists[i * l + t];
+            if (v < 0 || v == i)
+                continue;
+            e[nc].key = obj_key(x, attrs, d, m, i, v);
+            e[nc].id = v;
+            e[nc].isnew = 0;
+            nc += 1;
+        }
+        qsort(e, (size_t)nc, sizeof(nnd_entry), nnd_cmp);
+        for (int t = 0; t < nc; ++t) {
+            ck[t] = e[t].key;
+            ci[t] = e[t].id;
+        }
+        int32_t *row = adj_out + i * (int64_t)R;
+        int ns = landing_zone_select(x, attrs, d, m, i, ck, ci, nc, R, row);
+        for (int t = ns; t < R; ++t)
+            row[t] = -1;
+        free(e);
+        free(ck);
+        free(ci);
+    }
+}
+
 /* exact k nearest of listed rows (graph quality, Eq. 7): use_attrs selects
  * the fusion key (composite index) or plain delta (vector-only graph). */
 void or_knn_rows(const float *x, const uint8_t *attrs, int64_t n, int d, int m, int use_attrs,
