@@ -88,9 +88,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (counter scaling)")
-    ap.add_argument("--workload", default="plain", choices=["plain", "precision", "ablation"],
+    ap.add_argument("--workload", default="plain",
+                    choices=["plain", "precision", "ablation", "build"],
                     help="precision: the d = 960 storage forms (fp32 / bf16 / fp8 + exact rerank); "
-                         "ablation: weight settings, selectivity and post-filtering sweeps")
+                         "ablation: weight settings, selectivity and post-filtering sweeps; "
+                         "build: exact vs NN-descent candidate lists (1M and 10M sets)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -109,6 +111,8 @@ def main():
         return precision_form(args)
     if args.workload == "ablation":
         return ablation(args)
+    if args.workload == "build":
+        return build_study(args)
     dev = torch.device("cuda:0")
     t_gen = time.time()
     w = synth.config2(n=args.n, nq=args.nq)
@@ -561,6 +565,91 @@ def precision_form(args):
                       "build_s": round(build_s, 2)},
            "forms": forms}
     print(json.dumps(out), flush=True)
+
+
+def build_study(args):
+    """Composite-index builds (Alg. 1 / Sec. 4.3): the exact all-pairs
+    candidate lists against NN-descent (NPG_kgraph's refinement) on the
+    config-2 set (1M x 128), then NN-descent alone on the config-4 set at its
+    full size (10M x 96, Zipf attributes), where all pairs would take
+    minutes.  For each graph: build time, rounds, and the Recall@10 / QPS of
+    the search over the beam (E = --expand)."""
+    import torch
+    import synth
+    import paper_2203_13601_amd as nhq
+    from paper_2203_13601_amd.metrics import qps_at_recall, recall_at_k
+
+    dev = torch.device("cuda:0")
+    n_cand = min(args.n_entry, args.n_init + 16)
+    out = {}
+
+    def curve(ix, w, q, qa, gi, gd, beams):
+        rows = []
+        for beam in beams:
+            def step():
+                cand = nhq.nhq_seed_rank(ix, q, qa, n_cand)
+                return nhq.nhq_search_seeded(ix, q, qa, cand, w.k, beam, n_init=args.n_init,
+                                             expand=args.expand)
+            ids, d = step()
+            rec = float(recall_at_k(ids.cpu().numpy(), d.cpu().numpy(), gi, gd, w.attrs, w.qattrs,
+                                    w.k).mean())
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(3):
+                step()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 3
+            rows.append({"beam": beam, "recall": round(rec, 5), "qps": round(w.nq / (ms / 1000.0), 1)})
+            log("  beam %d recall %.4f %.0f QPS" % (beam, rec, rows[-1]["qps"]))
+        at = qps_at_recall([r["beam"] for r in rows], [r["recall"] for r in rows],
+                           [r["qps"] for r in rows], args.target)
+        return rows, None if at is None else round(at, 1)
+
+    for name, make, builders, beams in (
+            ("config2", lambda: synth.config2(n=args.n, nq=args.nq),
+             (("exact", args.n_entry), ("nndescent", args.n_entry)), [16, 28, 48, 96]),
+            ("config4", lambda: synth.config4(nq=args.nq),
+             (("nndescent", args.n_entry), ("nndescent", 16384)), [32, 64, 128, 256])):
+        t = time.time()
+        w = make()
+        log("generated %s in %.1fs" % (w.name, time.time() - t))
+        x = torch.from_numpy(w.x).to(dev)
+        a = torch.from_numpy(w.attrs).to(dev)
+        q = torch.from_numpy(w.q).to(dev)
+        qa = torch.from_numpy(w.qattrs).to(dev)
+        gi = gd = None
+        res = {}
+        for b, ne in builders:
+            torch.cuda.synchronize()
+            t = time.time()
+            ix = nhq.nhq_build_index(x, a, degree=w.degree, cand=w.cand, n_entry=ne,
+                                     seed=w.build_seed, builder=b)
+            torch.cuda.synchronize()
+            bs = time.time() - t
+            rounds = nhq.nhq_index_build_report(ix)["nnd_rounds_run"]
+            log("%s %s build %.2fs (%d NN-descent rounds), entry sample %d" % (name, b, bs, rounds, ne))
+            if gi is None:
+                gi, gd = nhq.nhq_bruteforce_hybrid_knn(ix, q, qa, w.k)
+                gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
+            rows, at = curve(ix, w, q, qa, gi, gd, beams)
+            res["%s_entry%d" % (b, ne)] = {"build_s": round(bs, 2), "nnd_rounds": rounds,
+                                           "curve": rows, "qps_at_target": at}
+            ix.free()
+        out[name] = {"workload": w.name, "n": w.n, "d": w.d, **res}
+        del x, a, q, qa, w
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "composite-index build: exact vs NN-descent lists, on 1 GPU",
+                      "value": out["config4"]["nndescent_entry%d" % args.n_entry]["build_s"],
+                      "unit": "s",
+                      "n_gpus": 1, "higher_is_better": False, "vs_baseline": None, "dtype": "f32",
+                      "data": "synthetic",
+                      "config": {"workload": "config2 1M x 128 and config4 10M x 96",
+                                 "expand": args.expand, "n_init": args.n_init,
+                                 "n_entry": args.n_entry},
+                      **out}), flush=True)
 
 
 def ablation(args):

@@ -94,7 +94,47 @@ typedef struct {
     double weight_param;   /* p of the weight setting: c > 1 (HARMONIC_C),
                               delta_max > 0 (NORMALISED), w_l / w_v >= 0
                               (FIXED); ignored otherwise                   [0] */
+    int32_t builder;       /* where the edge candidates come from:
+                              NHQ_BUILD_EXACT: the exact l nearest (all pairs
+                              on the matrix cores);
+                              NHQ_BUILD_NNDESCENT: NN-descent lists (the
+                              NPG_kgraph build, Sec. 4.3) of l = cand entries
+                              from nhq_nndescent_lists with this index's seed,
+                              re-ordered by the exact FP64 key before the
+                              edge selection; needs cand <= 128 < n       [0] */
+    int32_t nnd_rounds;    /* NN-descent: most rounds after the start     [12] */
+    int32_t nnd_sample;    /* NN-descent: new entries explored per list
+                              and round (s)                                [24] */
+    float nnd_stop;        /* NN-descent: stop after a round that brings
+                              fewer than nnd_stop * n * l new entries  [0.001] */
 } nhq_build_params;
+
+#define NHQ_BUILD_EXACT 0
+#define NHQ_BUILD_NNDESCENT 1
+
+/* NN-descent candidate lists (the refinement of NPG_kgraph, Sec. 4.3; Eq. 7
+ * measures their quality), in synchronous rounds so that the result does
+ * not depend on scheduling:
+ *   round 0: C(i) = the first l distinct values v != i of splitmix64 with
+ *            state seed ^ (i * 0xD1B54A32D192ED03), taken mod n, ordered by
+ *            (key, id), all entries new;
+ *   round t: J = the first s new entries of C(i); the ids of C(j), j in J,
+ *            that are neither i nor in C(i) are scored; C(i) becomes the l
+ *            best of C(i) and them by (key, id); they enter new, J turns old.
+ * Keys: float32 object-object fusion keys of the index's weight setting
+ * over all m attributes.  Runs `rounds` rounds, or stops after the first
+ * round that brings fewer than stop_frac * n * l new entries (stop_frac
+ * <= 0: never).  ids: DEVICE int32 [n][l] (caller-owned), each row sorted
+ * by (key, id).  updates: nullable HOST int64 [rounds], the new entries of
+ * each round.  rounds_run: nullable HOST, the rounds done.  Needs
+ * 1 <= l <= 128, n > l, 0 <= s <= 64.  Synchronises the stream once per
+ * round. */
+int nhq_nndescent_lists(const nhq_index *ix, int32_t l, int32_t s, int32_t rounds,
+                        double stop_frac, uint64_t seed, int32_t *ids, int64_t *updates,
+                        int32_t *rounds_run, void *stream);
+
+/* Rounds the last NN-descent build of the index ran (0 for an exact build). */
+int nhq_index_build_report(const nhq_index *ix, int32_t *nnd_rounds_run);
 
 /* Per-checkpoint search traces (training data of the stop network).  Every
  * check_every hops the search records 8 state features, the hop count and a

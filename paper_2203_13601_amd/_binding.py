@@ -11,6 +11,7 @@ import ctypes
 import os
 from typing import Optional, Tuple
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -31,7 +32,9 @@ class BuildParams(ctypes.Structure):
     _fields_ = [("degree", ctypes.c_int32), ("cand", ctypes.c_int32),
                 ("reverse_edges", ctypes.c_int32), ("storage", ctypes.c_int32),
                 ("n_entry", ctypes.c_int32), ("weights", ctypes.c_int32),
-                ("seed", ctypes.c_uint64), ("weight_param", ctypes.c_double)]
+                ("seed", ctypes.c_uint64), ("weight_param", ctypes.c_double),
+                ("builder", ctypes.c_int32), ("nnd_rounds", ctypes.c_int32),
+                ("nnd_sample", ctypes.c_int32), ("nnd_stop", ctypes.c_float)]
 
 
 class Trace(ctypes.Structure):
@@ -82,6 +85,8 @@ def lib() -> ctypes.CDLL:
     sig = {
         "nhq_index_create": ([P, P, i64, i32, i32, P, P, P], i32),
         "nhq_index_build_graph": ([P, P], i32),
+        "nhq_nndescent_lists": ([P, i32, i32, i32, ctypes.c_double, ctypes.c_uint64, P, P, P, P], i32),
+        "nhq_index_build_report": ([P, P], i32),
         "nhq_build_index": ([P, P, i64, i32, i32, P, P, P], i32),
         "nhq_index_set_graph": ([P, P, i32, P], i32),
         "nhq_index_get_graph": ([P, P, P], i32),
@@ -169,12 +174,18 @@ class Index:
 WEIGHTS = {"default": 0, "harmonic": 1, "harmonic_c": 2, "normalised": 3, "fixed": 4}
 
 
+BUILDERS = {"exact": 0, "nndescent": 1}
+
+
 def _params(degree=32, cand=64, reverse_edges=False, storage="fp32", n_entry=1024, seed=0,
-            weights="default", weight_param=0.0):
+            weights="default", weight_param=0.0, builder="exact", nnd_rounds=0, nnd_sample=0,
+            nnd_stop=0.0):
     return BuildParams(int(degree), int(cand), int(bool(reverse_edges)),
                        STORAGE[storage] if isinstance(storage, str) else int(storage),
                        int(n_entry), WEIGHTS[weights] if isinstance(weights, str) else int(weights),
-                       int(seed), float(weight_param))
+                       int(seed), float(weight_param),
+                       BUILDERS[builder] if isinstance(builder, str) else int(builder),
+                       int(nnd_rounds), int(nnd_sample), float(nnd_stop))
 
 
 def nhq_index_create(vecs: torch.Tensor, attrs: torch.Tensor, stream=None, **params) -> Index:
@@ -188,6 +199,28 @@ def nhq_index_create(vecs: torch.Tensor, attrs: torch.Tensor, stream=None, **par
                                   attrs.shape[1], ctypes.byref(p), _stream(stream), ctypes.byref(h)),
            "nhq_index_create")
     return Index(h)
+
+
+def nhq_nndescent_lists(ix: Index, l: int, s: int, rounds: int, seed: int, stop_frac: float = 0.0,
+                        stream=None):
+    """NN-descent candidate lists (Sec. 4.3): (ids int32 [n, l] on the
+    device, updates per round as a numpy int64 array, rounds run)."""
+    n = nhq_index_info(ix)["n"]
+    dev = torch.device("cuda", torch.cuda.current_device())
+    ids = torch.empty((n, l), dtype=torch.int32, device=dev)
+    upd = np.zeros(max(rounds, 1), dtype=np.int64)
+    done = ctypes.c_int32()
+    _check(lib().nhq_nndescent_lists(ix.handle, int(l), int(s), int(rounds), float(stop_frac),
+                                     ctypes.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), ids.data_ptr(),
+                                     upd.ctypes.data, ctypes.byref(done), _stream(stream)),
+           "nhq_nndescent_lists")
+    return ids, upd[:done.value], done.value
+
+
+def nhq_index_build_report(ix: Index) -> dict:
+    r = ctypes.c_int32()
+    _check(lib().nhq_index_build_report(ix.handle, ctypes.byref(r)), "nhq_index_build_report")
+    return {"nnd_rounds_run": r.value}
 
 
 def nhq_index_build_graph(ix: Index, stream=None) -> None:

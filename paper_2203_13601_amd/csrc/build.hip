@@ -32,11 +32,21 @@ int nhq_index_build_graph(nhq_index *h, void *stream)
     if (ix->n < 2)
         return fail(NHQ_EINVAL, "a graph needs at least two objects");
     const int l = (int)std::min<int64_t>(ix->cand, ix->n - 1);
-    const int K = (int)std::min<int64_t>(std::min(l + kMargin, 160), ix->n - 1);
+    const bool nnd = ix->builder == NHQ_BUILD_NNDESCENT && ix->n > l && l <= 128;
+    // NN-descent lists hold l candidates; the dense tiles keep a margin more
+    const int K = nnd ? l : (int)std::min<int64_t>(std::min(l + kMargin, 160), ix->n - 1);
     int32_t *cand = nullptr, *fwd = nullptr;
     NHQ_HIP(hipMallocAsync((void **)&cand, sizeof(int32_t) * (size_t)ix->n * K, st));
-    int rc = launch_dense_topk(ix->vec32, ix->norm, ix->attr, nullptr, ix->n, ix->vec32, ix->norm,
+    int rc = NHQ_OK;
+    if (nnd) {
+        int done = 0;
+        rc = nnd_lists(ix, l, ix->nnd_sample, ix->nnd_rounds, ix->nnd_stop, ix->seed,
+                       cand, nullptr, &done, st);
+        ix->nnd_rounds_run = done;
+    } else {
+        rc = launch_dense_topk(ix->vec32, ix->norm, ix->attr, nullptr, ix->n, ix->vec32, ix->norm,
                                ix->attr, ix->n, ix->dp, ix->m, 0, 1, K, cand, nullptr, st, &ix->w);
+    }
     if (rc == NHQ_OK) {
         if (ix->reverse_edges) {
             if (hipMallocAsync((void **)&fwd, sizeof(int32_t) * (size_t)ix->n * ix->degree, st) != hipSuccess)
@@ -53,6 +63,15 @@ int nhq_index_build_graph(nhq_index *h, void *stream)
     if (fwd)
         (void)hipFreeAsync(fwd, st);
     return rc;
+}
+
+int nhq_index_build_report(const nhq_index *h, int32_t *nnd_rounds_run)
+{
+    if (!h)
+        return fail(NHQ_EINVAL, "null index");
+    if (nnd_rounds_run)
+        *nnd_rounds_run = h->impl.nnd_rounds_run;
+    return NHQ_OK;
 }
 
 int nhq_build_index(const float *vecs, const uint8_t *attrs, int64_t n, int32_t d, int32_t m,

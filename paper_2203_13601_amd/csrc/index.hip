@@ -325,6 +325,17 @@ int nhq_index_create(const float *vecs, const uint8_t *attrs, int64_t n, int32_t
         (p.weights == NHQ_WEIGHTS_FIXED && !(p.weight_param >= 0.0)) ||
         !(p.weight_param < 3.0e38))
         return fail(NHQ_EINVAL, "weight_param out of range for the weight setting");
+    if (p.nnd_rounds == 0)
+        p.nnd_rounds = 12;
+    if (p.nnd_sample == 0)
+        p.nnd_sample = 24;
+    if (p.nnd_stop == 0.0f)
+        p.nnd_stop = 0.001f;
+    if (p.builder != NHQ_BUILD_EXACT && p.builder != NHQ_BUILD_NNDESCENT)
+        return fail(NHQ_EINVAL, "builder must be NHQ_BUILD_EXACT or NHQ_BUILD_NNDESCENT");
+    if (p.nnd_rounds < 0 || p.nnd_rounds > 1000 || p.nnd_sample < 1 || p.nnd_sample > 64 ||
+        !(p.nnd_stop >= 0.0f))
+        return fail(NHQ_EINVAL, "NN-descent needs rounds in [0, 1000], sample in [1, 64], stop >= 0");
 
     hipStream_t st = (hipStream_t)stream;
     nhq_index *h = new (std::nothrow) nhq_index();
@@ -349,6 +360,10 @@ int nhq_index_create(const float *vecs, const uint8_t *attrs, int64_t n, int32_t
         ix->w.pd = p.weights == NHQ_WEIGHTS_DEFAULT || p.weights == NHQ_WEIGHTS_HARMONIC
                        ? 0.0 : p.weight_param;
         ix->w.p = (float)ix->w.pd;
+        ix->builder = p.builder;
+        ix->nnd_rounds = p.nnd_rounds;
+        ix->nnd_sample = p.nnd_sample;
+        ix->nnd_stop = p.nnd_stop;
         ix->degree = 0;
         const int want_degree = p.degree;
         const size_t rows = (size_t)n * ix->dp;

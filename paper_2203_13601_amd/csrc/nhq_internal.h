@@ -48,6 +48,11 @@ struct Index {
     int n_entry = 0;
     uint64_t seed = 0;
     Weights w{NHQ_WEIGHTS_DEFAULT, 0.0f, 0.0};  // weight setting of Gamma
+    // edge candidates: exact all-pairs or NN-descent (rounds, sample, stop)
+    int builder = NHQ_BUILD_EXACT;
+    int nnd_rounds = 12, nnd_sample = 24;
+    float nnd_stop = 0.001f;
+    int nnd_rounds_run = 0;  // rounds the last NN-descent build ran
     float *vec32 = nullptr;     // [n][dp] float32 copy (rerank / fp32 storage)
     void *vecs = nullptr;       // storage form [n][dp] (== vec32 for fp32)
     float *scale = nullptr;     // fp8: per-row scale [n]
@@ -74,8 +79,12 @@ struct Index {
 
 int ensure_workspace(Index *ix, size_t bytes);
 
+// NN-descent candidate lists (nndescent.hip)
+int nnd_lists(const Index *ix, int l, int s, int rounds, double stop_frac, uint64_t seed,
+              int32_t *ids, int64_t *updates_host, int *rounds_run, hipStream_t st);
+
 // splitmix64 (Steele, Lea and Flood, 2014)
-inline uint64_t splitmix64_next(uint64_t &state)
+__host__ __device__ inline uint64_t splitmix64_next(uint64_t &state)
 {
     state += 0x9E3779B97F4A7C15ull;
     uint64_t z = state;
