@@ -569,7 +569,8 @@ def precision_form(args):
 
 def build_study(args):
     """Composite-index builds (Alg. 1 / Sec. 4.3): the exact all-pairs
-    candidate lists against NN-descent (NPG_kgraph's refinement) on the
+    candidate lists against NN-descent (NPG_kgraph's refinement) and
+    insertion in batches of 10,000 (NPG_nsw, insertion beam 96) on the
     config-2 set (1M x 128), then NN-descent alone on the config-4 set at its
     full size (10M x 96, Zipf attributes), where all pairs would take
     minutes.  For each graph: build time, rounds, and the Recall@10 / QPS of
@@ -610,7 +611,8 @@ def build_study(args):
 
     for name, make, builders, beams in (
             ("config2", lambda: synth.config2(n=args.n, nq=args.nq),
-             (("exact", args.n_entry), ("nndescent", args.n_entry)), [16, 28, 48, 96]),
+             (("exact", args.n_entry), ("nndescent", args.n_entry), ("nsw", args.n_entry)),
+             [16, 28, 48, 96]),
             ("config4", lambda: synth.config4(nq=args.nq),
              (("nndescent", args.n_entry), ("nndescent", 16384)), [32, 64, 128, 256])):
         t = time.time()
@@ -626,7 +628,7 @@ def build_study(args):
             torch.cuda.synchronize()
             t = time.time()
             ix = nhq.nhq_build_index(x, a, degree=w.degree, cand=w.cand, n_entry=ne,
-                                     seed=w.build_seed, builder=b)
+                                     seed=w.build_seed, builder=b, nsw_batch=10000, nsw_beam=96)
             torch.cuda.synchronize()
             bs = time.time() - t
             rounds = nhq.nhq_index_build_report(ix)["nnd_rounds_run"]

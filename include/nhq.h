@@ -101,16 +101,34 @@ typedef struct {
                               NPG_kgraph build, Sec. 4.3) of l = cand entries
                               from nhq_nndescent_lists with this index's seed,
                               re-ordered by the exact FP64 key before the
-                              edge selection; needs cand <= 128 < n       [0] */
+                              edge selection; needs cand <= 128 < n;
+                              NHQ_BUILD_NSW: see below                     [0] */
     int32_t nnd_rounds;    /* NN-descent: most rounds after the start     [12] */
     int32_t nnd_sample;    /* NN-descent: new entries explored per list
                               and round (s)                                [24] */
     float nnd_stop;        /* NN-descent: stop after a round that brings
                               fewer than nnd_stop * n * l new entries  [0.001] */
+    int32_t nsw_batch;     /* NSW insertion: vertices inserted per batch
+                              (1: one at a time)                       [10000] */
+    int32_t nsw_beam;      /* NSW insertion: beam of each insertion search
+                              (>= cand)                                 [cand] */
 } nhq_build_params;
 
 #define NHQ_BUILD_EXACT 0
 #define NHQ_BUILD_NNDESCENT 1
+#define NHQ_BUILD_NSW 2 /* NPG_nsw (Sec. 4.3): vertices inserted in id order
+                           in batches of nsw_batch.  The first batch takes the
+                           exact cand nearest within itself; every later batch
+                           searches the graph built so far (the search of
+                           nhq_hybrid_search with the object's attributes all
+                           constrained, beam nsw_beam, first cand pool entries,
+                           seeds: the 16 best of the first min(s, 256)
+                           distinct splitmix64(seed) values mod s, s the
+                           vertices already in).  New rows are selected from
+                           their candidates; every vertex a new row names
+                           re-selects its row with the new vertex offered.
+                           Reverse links are part of it (reverse_edges is
+                           ignored).  Synchronises the stream per batch. */
 
 /* NN-descent candidate lists (the refinement of NPG_kgraph, Sec. 4.3; Eq. 7
  * measures their quality), in synchronous rounds so that the result does

@@ -81,6 +81,8 @@ def lib():
         L.or_nndescent.argtypes = [P, P, i64, i32, i32, i32, i32, i32, ctypes.c_uint64, i32, P, P, i32]
         L.or_select_lists.restype = None
         L.or_select_lists.argtypes = [P, P, i64, i32, i32, P, i32, i32, P, i32]
+        L.or_build_nsw.restype = None
+        L.or_build_nsw.argtypes = [P, P, i64, i32, i32, i32, i32, i64, i32, ctypes.c_uint64, P, i32]
         L.or_set_weights.restype = None
         L.or_set_weights.argtypes = [i32, ctypes.c_double]
         L.or_search.restype = None
@@ -218,6 +220,19 @@ def select_lists(x, attrs, lists, R: int, threads: Optional[int] = None) -> np.n
     adj = np.empty((n, R), dtype=np.int32)
     lib().or_select_lists(_p(x), _p(attrs), n, d, m, _p(lists), lists.shape[1], int(R), _p(adj),
                           _threads(threads))
+    return adj
+
+
+def build_nsw(x, attrs, l: int, R: int, batch: int, beam: int, seed: int,
+              threads: Optional[int] = None) -> np.ndarray:
+    """NPG_nsw (Sec. 4.3) by insertion in batches of `batch` vertices (id
+    order); see or_build_nsw.  batch = 1 inserts one vertex at a time."""
+    x, attrs = _f32(x), _u8(attrs)
+    n, d = x.shape
+    m = attrs.shape[1]
+    adj = np.empty((n, R), dtype=np.int32)
+    lib().or_build_nsw(_p(x), _p(attrs), n, d, m, int(l), int(R), int(batch), int(beam),
+                       ctypes.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), _p(adj), _threads(threads))
     return adj
 
 

@@ -576,6 +576,161 @@ void or_select_lists(const float *x, const uint8_t *attrs, int64_t n, int d, int
     }
 }
 
+/* -------------------------------------- NPG_nsw, batched insertion (Sec. 4.3) */
+void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
+               const uint8_t *attrs, int64_t n, int d, int m, const float *q,
+               const uint8_t *qa, int64_t nq, int k, int L, const int32_t *seeds,
+               int nseeds, int ninit, int key_mode, int out_mode, int rerank_n, int64_t max_hops,
+               int32_t *out_ids, double *out_gamma, int64_t *out_ndc, int64_t *out_hops,
+               int32_t *out_flag, int check_every, double *tr_feat, uint32_t *tr_hop,
+               uint32_t *tr_hash, int32_t *tr_count, uint32_t *tr_final, int tr_cap,
+               const double *mlp, double stop_logit, double cap_factor, int learned_mode, int expand,
+               int route_h, int nthreads);
+
+/* One vertex j re-selects N(j) from N(j) united with the offered ids (each
+ * once), ordered by (exact key to j, id) (Sec. 4.1 (2)-(3)). */
+static void reselect_row(const float *x, const uint8_t *attrs, int d, int m, int64_t j, int R,
+                         const int64_t *offers, int noff, int32_t *adj)
+{
+    int cap = R + noff;
+    nnd_entry *e = (nnd_entry *)malloc(sizeof(nnd_entry) * (size_t)cap);
+    double *ck = (double *)malloc(sizeof(double) * (size_t)cap);
+    int64_t *ci = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+    int nc = 0;
+    for (int t = 0; t < cap; ++t) {
+        int64_t v = t < R ? adj[j * R + t] : offers[t - R];
+        if (v < 0 || v == j)
+            continue;
+        int dup = 0;
+        for (int u = 0; u < nc && !dup; ++u)
+            dup = e[u].id == v;
+        if (dup)
+            continue;
+        e[nc].key = obj_key(x, attrs, d, m, j, v);
+        e[nc].id = v;
+        e[nc].isnew = 0;
+        nc += 1;
+    }
+    qsort(e, (size_t)nc, sizeof(nnd_entry), nnd_cmp);
+    for (int t = 0; t < nc; ++t) {
+        ck[t] = e[t].key;
+        ci[t] = e[t].id;
+    }
+    int32_t *row = adj + j * (int64_t)R;
+    int32_t *tmp = (int32_t *)malloc(sizeof(int32_t) * (size_t)R);
+    int ns = landing_zone_select(x, attrs, d, m, j, ck, ci, nc, R, tmp);
+    for (int t = 0; t < R; ++t)
+        row[t] = t < ns ? tmp[t] : -1;
+    free(tmp);
+    free(e);
+    free(ck);
+    free(ci);
+}
+
+/* Every vertex j named in a row of [s, s + nb) is offered that row's vertex
+ * and re-selects N(j) (the reverse links of insertion). */
+static void nsw_reverse(const float *x, const uint8_t *attrs, int64_t n, int d, int m, int R,
+                        int64_t s, int64_t nb, int32_t *adj)
+{
+    int64_t *cnt = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    for (int64_t e = s; e < s + nb; ++e)
+        for (int t = 0; t < R; ++t)
+            if (adj[e * R + t] >= 0)
+                cnt[adj[e * R + t] + 1] += 1;
+    for (int64_t v = 0; v < n; ++v)
+        cnt[v + 1] += cnt[v];
+    int64_t *off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    memcpy(off, cnt, sizeof(int64_t) * (size_t)(n + 1));
+    int64_t *inc = (int64_t *)malloc(sizeof(int64_t) * (size_t)(cnt[n] + 1));
+    for (int64_t e = s; e < s + nb; ++e)
+        for (int t = 0; t < R; ++t) {
+            int32_t j = adj[e * R + t];
+            if (j >= 0)
+                inc[cnt[j]++] = e;
+        }
+    for (int64_t j = 0; j < n; ++j)
+        if (off[j + 1] > off[j])
+            reselect_row(x, attrs, d, m, j, R, inc + off[j], (int)(off[j + 1] - off[j]), adj);
+    free(cnt);
+    free(off);
+    free(inc);
+}
+
+/* NPG_nsw in batches of B: vertices enter in id order.  The first batch
+ * takes the exact l nearest within itself as candidates; every later batch
+ * [s, s + nb) searches the graph of the s vertices already in (Alg. 2 in
+ * beam form, beam L, the object's attributes all constrained, float32 keys,
+ * raw pool order, the first min(s, 256) distinct values of splitmix64(seed)
+ * mod s as the entry sample and its 16 best as seeds) for its l candidates.
+ * Each new row is selected from its candidates (Sec. 4.1), then every vertex
+ * it names re-selects its own row with the new vertex offered.  B = 1 is
+ * one-at-a-time insertion. */
+void or_build_nsw(const float *x, const uint8_t *attrs, int64_t n, int d, int m, int l, int R,
+                  int64_t B, int L, uint64_t seed, int32_t *adj, int nthreads)
+{
+    for (int64_t t = 0; t < n * R; ++t)
+        adj[t] = -1;
+    int64_t b0 = B < n ? B : n;
+    int l0 = (int)(l < b0 - 1 ? l : b0 - 1);
+    if (l0 > 0) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+#endif
+        for (int64_t i = 0; i < b0; ++i) {
+            double *ck = (double *)malloc(sizeof(double) * (size_t)l0);
+            int64_t *ci = (int64_t *)malloc(sizeof(int64_t) * (size_t)l0);
+            int nc = nearest_l(x, attrs, b0, d, m, 1, i, l0, ck, ci);
+            int32_t *row = adj + i * (int64_t)R;
+            int ns = landing_zone_select(x, attrs, d, m, i, ck, ci, nc, R, row);
+            for (int t = ns; t < R; ++t)
+                row[t] = -1;
+            free(ck);
+            free(ci);
+        }
+        nsw_reverse(x, attrs, n, d, m, R, 0, b0, adj);
+    }
+    int32_t *cand = (int32_t *)malloc(sizeof(int32_t) * (size_t)(B * l + 1));
+    double *gam = (double *)malloc(sizeof(double) * (size_t)(B * l + 1));
+    int64_t *ndc = (int64_t *)malloc(sizeof(int64_t) * (size_t)(B + 1));
+    int64_t *hops = (int64_t *)malloc(sizeof(int64_t) * (size_t)(B + 1));
+    int32_t *flag = (int32_t *)malloc(sizeof(int32_t) * (size_t)(B + 1));
+    int32_t seeds[256];
+    for (int64_t s = b0; s < n; s += B) {
+        int64_t nb = (n - s) < B ? (n - s) : B;
+        int ns = 0;
+        uint64_t st = seed;
+        int want = s < 256 ? (int)s : 256;
+        while (ns < want) {
+            int32_t v = (int32_t)(sm64_next(&st) % (uint64_t)s);
+            int dup = 0;
+            for (int t = 0; t < ns && !dup; ++t)
+                dup = seeds[t] == v;
+            if (!dup)
+                seeds[ns++] = v;
+        }
+        or_search(adj, R, x, NULL, attrs, n, d, m, x + s * (int64_t)d, attrs + s * (int64_t)m, nb, l,
+                  L, seeds, ns, ns < 16 ? ns : 16, OR_KEY32, 1, 0, INT64_MAX, cand, gam, ndc, hops,
+                  flag, 0, NULL, NULL, NULL, NULL, NULL, 0, NULL, 0.0, 0.0, 1, 1, 0, nthreads);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+#endif
+        for (int64_t e = 0; e < nb; ++e) {
+            int64_t offers[256];
+            int no = 0;
+            for (int t = 0; t < l && no < 256; ++t)
+                if (cand[e * l + t] >= 0)
+                    offers[no++] = cand[e * l + t];
+            reselect_row(x, attrs, d, m, s + e, R, offers, no, adj);
+        }
+        nsw_reverse(x, attrs, n, d, m, R, s, nb, adj);
+    }
+    free(cand);
+    free(gam);
+    free(ndc);
+    free(hops);
+    free(flag);
+}
+
 /* exact k nearest of listed rows (graph quality, Eq. 7): use_attrs selects
  * the fusion key (composite index) or plain delta (vector-only graph). */
 void or_knn_rows(const float *x, const uint8_t *attrs, int64_t n, int d, int m, int use_attrs,

@@ -34,7 +34,8 @@ class BuildParams(ctypes.Structure):
                 ("n_entry", ctypes.c_int32), ("weights", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("weight_param", ctypes.c_double),
                 ("builder", ctypes.c_int32), ("nnd_rounds", ctypes.c_int32),
-                ("nnd_sample", ctypes.c_int32), ("nnd_stop", ctypes.c_float)]
+                ("nnd_sample", ctypes.c_int32), ("nnd_stop", ctypes.c_float),
+                ("nsw_batch", ctypes.c_int32), ("nsw_beam", ctypes.c_int32)]
 
 
 class Trace(ctypes.Structure):
@@ -174,18 +175,19 @@ class Index:
 WEIGHTS = {"default": 0, "harmonic": 1, "harmonic_c": 2, "normalised": 3, "fixed": 4}
 
 
-BUILDERS = {"exact": 0, "nndescent": 1}
+BUILDERS = {"exact": 0, "nndescent": 1, "nsw": 2}
 
 
 def _params(degree=32, cand=64, reverse_edges=False, storage="fp32", n_entry=1024, seed=0,
             weights="default", weight_param=0.0, builder="exact", nnd_rounds=0, nnd_sample=0,
-            nnd_stop=0.0):
+            nnd_stop=0.0, nsw_batch=0, nsw_beam=0):
     return BuildParams(int(degree), int(cand), int(bool(reverse_edges)),
                        STORAGE[storage] if isinstance(storage, str) else int(storage),
                        int(n_entry), WEIGHTS[weights] if isinstance(weights, str) else int(weights),
                        int(seed), float(weight_param),
                        BUILDERS[builder] if isinstance(builder, str) else int(builder),
-                       int(nnd_rounds), int(nnd_sample), float(nnd_stop))
+                       int(nnd_rounds), int(nnd_sample), float(nnd_stop), int(nsw_batch),
+                       int(nsw_beam))
 
 
 def nhq_index_create(vecs: torch.Tensor, attrs: torch.Tensor, stream=None, **params) -> Index:

@@ -32,6 +32,10 @@ int nhq_index_build_graph(nhq_index *h, void *stream)
     if (ix->n < 2)
         return fail(NHQ_EINVAL, "a graph needs at least two objects");
     const int l = (int)std::min<int64_t>(ix->cand, ix->n - 1);
+    if (ix->builder == NHQ_BUILD_NSW) {
+        ix->nnd_rounds_run = 0;
+        return nsw_build(ix, l, ix->nsw_batch, std::max(ix->nsw_beam, l), ix->seed, st);
+    }
     const bool nnd = ix->builder == NHQ_BUILD_NNDESCENT && ix->n > l && l <= 128;
     // NN-descent lists hold l candidates; the dense tiles keep a margin more
     const int K = nnd ? l : (int)std::min<int64_t>(std::min(l + kMargin, 160), ix->n - 1);

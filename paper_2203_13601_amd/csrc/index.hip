@@ -331,8 +331,14 @@ int nhq_index_create(const float *vecs, const uint8_t *attrs, int64_t n, int32_t
         p.nnd_sample = 24;
     if (p.nnd_stop == 0.0f)
         p.nnd_stop = 0.001f;
-    if (p.builder != NHQ_BUILD_EXACT && p.builder != NHQ_BUILD_NNDESCENT)
-        return fail(NHQ_EINVAL, "builder must be NHQ_BUILD_EXACT or NHQ_BUILD_NNDESCENT");
+    if (p.nsw_batch == 0)
+        p.nsw_batch = 10000;
+    if (p.nsw_beam == 0)
+        p.nsw_beam = p.cand;
+    if (p.builder < NHQ_BUILD_EXACT || p.builder > NHQ_BUILD_NSW)
+        return fail(NHQ_EINVAL, "builder must be an NHQ_BUILD_* value");
+    if (p.nsw_batch < 1 || p.nsw_beam < p.cand || p.nsw_beam > NHQ_MAX_BEAM)
+        return fail(NHQ_EINVAL, "NSW needs nsw_batch >= 1 and cand <= nsw_beam <= 1024");
     if (p.nnd_rounds < 0 || p.nnd_rounds > 1000 || p.nnd_sample < 1 || p.nnd_sample > 64 ||
         !(p.nnd_stop >= 0.0f))
         return fail(NHQ_EINVAL, "NN-descent needs rounds in [0, 1000], sample in [1, 64], stop >= 0");
@@ -364,6 +370,8 @@ int nhq_index_create(const float *vecs, const uint8_t *attrs, int64_t n, int32_t
         ix->nnd_rounds = p.nnd_rounds;
         ix->nnd_sample = p.nnd_sample;
         ix->nnd_stop = p.nnd_stop;
+        ix->nsw_batch = p.nsw_batch;
+        ix->nsw_beam = p.nsw_beam;
         ix->degree = 0;
         const int want_degree = p.degree;
         const size_t rows = (size_t)n * ix->dp;

@@ -53,6 +53,7 @@ struct Index {
     int nnd_rounds = 12, nnd_sample = 24;
     float nnd_stop = 0.001f;
     int nnd_rounds_run = 0;  // rounds the last NN-descent build ran
+    int nsw_batch = 10000, nsw_beam = 0;  // NSW insertion (beam 0: cand)
     float *vec32 = nullptr;     // [n][dp] float32 copy (rerank / fp32 storage)
     void *vecs = nullptr;       // storage form [n][dp] (== vec32 for fp32)
     float *scale = nullptr;     // fp8: per-row scale [n]
@@ -78,6 +79,9 @@ struct Index {
 };
 
 int ensure_workspace(Index *ix, size_t bytes);
+
+// NPG_nsw by batched insertion (nsw.hip)
+int nsw_build(Index *ix, int l, int64_t B, int L, uint64_t seed, hipStream_t st);
 
 // NN-descent candidate lists (nndescent.hip)
 int nnd_lists(const Index *ix, int l, int s, int rounds, double stop_frac, uint64_t seed,
@@ -106,12 +110,24 @@ struct SearchLaunch {
     int expand;
     int route_h;
     const nhq_trace *trace;
+    // nullable: the entry sample the seed positions index (else the index's),
+    // and whether every query shares the first row of seed_cand
+    const int32_t *entry_override;
+    int n_entry_override;
+    int seeds_shared;
     int32_t *ids;
     float *dists;
     uint32_t *counters;
     hipStream_t stream;
 };
 int launch_search(const SearchLaunch &s);
+
+// edge selection of rows row0 .. row0 + nrows - 1, and re-selection of
+// listed rows with offers (select.hip)
+int launch_select_rows(const Index *ix, const int32_t *cand, int K, int l, int32_t *adj,
+                       int64_t row0, int64_t nrows, hipStream_t st);
+int launch_reselect_targets(const Index *ix, int32_t *adj, const int32_t *targets, int64_t nt,
+                            const int64_t *off, const int32_t *inc, hipStream_t st);
 
 // dense tiles with a streaming top-K (see dense_topk.hip)
 int launch_dense_topk(const float *A, const float *A_norm, const uint32_t *A_attr,

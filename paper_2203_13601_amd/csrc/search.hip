@@ -30,7 +30,7 @@ __device__ __forceinline__ void search_block(const SearchArgs &a)
     QueryIO io;
     io.q = a.q + qi * (int64_t)a.d;
     pack_query_attrs(a.qa + qi * a.m, a.m, io.qword, io.qmask);
-    io.seeds = a.seed_cand + qi * a.n_seed;
+    io.seeds = a.seed_cand + (a.seeds_shared ? 0 : qi * a.n_seed);
     io.n_seed = a.n_seed;
     io.oid = a.out_ids + qi * a.k;
     io.od = a.out_dist + qi * a.k;
@@ -103,7 +103,8 @@ int launch_search(const SearchLaunch &s)
     a.attr = ix->attr;
     a.adj = ix->adj;
     a.seed_cand = s.seed_cand;
-    a.entry = ix->entry;
+    a.entry = s.entry_override ? s.entry_override : ix->entry;
+    a.seeds_shared = s.seeds_shared;
     a.q = s.q;
     a.qa = s.qa;
     a.out_ids = s.ids;
@@ -116,7 +117,7 @@ int launch_search(const SearchLaunch &s)
     a.m = ix->m;
     a.R = ix->degree;
     a.n_seed = s.n_seed_cand;
-    a.n_entry = ix->n_entry;
+    a.n_entry = s.entry_override ? s.n_entry_override : ix->n_entry;
     a.k = s.k;
     a.L = s.L;
     a.n_init = s.n_init;

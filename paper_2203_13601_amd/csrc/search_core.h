@@ -39,6 +39,7 @@ struct SearchArgs {
     int ckpt, learned;
     int expand;           // vertices expanded per step (1 = Alg. 2 as printed)
     int route_h;          // >= 2: two-stage routing, stage S1 evaluates 1 slot in h
+    int seeds_shared;     // every query reads the first row of seed_cand
     Weights w;            // weight setting of Gamma (the index's)
     float stop_logit;     // learned: stop when the stop logit >= this
     float cap_factor;     // learned, > 0: hop budget cap_factor * 2^(beam output)

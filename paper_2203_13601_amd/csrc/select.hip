@@ -176,15 +176,18 @@ struct SelArgs {
     int64_t n;
     int m, K, l, R;
     Weights w;
+    int64_t row0;   // rows row0 .. row0 + nrows - 1 (cand holds their lists)
+    int64_t nrows;
 };
 
 template <int DP>
 __global__ __launch_bounds__(64) void k_select(const SelArgs a)
 {
     const int lane = threadIdx.x;
-    const int64_t i = blockIdx.x;
-    if (i >= a.n)
+    if ((int64_t)blockIdx.x >= a.nrows)
         return;
+    const int64_t i = a.row0 + blockIdx.x;
+    const int32_t *crow = a.cand + (int64_t)blockIdx.x * a.K;
     extern __shared__ __align__(16) uint32_t smem[];
     double *ck = reinterpret_cast<double *>(smem);      // [K]
     double *scratch = ck + a.K;                         // [64]
@@ -195,7 +198,7 @@ __global__ __launch_bounds__(64) void k_select(const SelArgs a)
     int nc = 0;
     for (int e0 = 0; e0 < a.K; e0 += 64) {
         const int e = e0 + lane;
-        const int32_t v = e < a.K ? a.cand[i * a.K + e] : -1;
+        const int32_t v = e < a.K ? crow[e] : -1;
         const bool ok = v >= 0 && v < a.n && v != i;
         const uint64_t b = __ballot(ok);
         if (ok)
@@ -228,22 +231,25 @@ struct RevArgs {
     int64_t n;
     int m, R;
     Weights w;
+    const int32_t *targets;  // nullable: re-select these rows only (t -> row)
+    int64_t nt;              // rows re-selected (grid)
 };
 
 template <int DP>
 __global__ __launch_bounds__(64) void k_reverse(const RevArgs a)
 {
     const int lane = threadIdx.x;
-    const int64_t j = blockIdx.x;
-    if (j >= a.n)
+    const int64_t ti = blockIdx.x;
+    if (ti >= a.nt)
         return;
+    const int64_t j = a.targets ? (int64_t)a.targets[ti] : ti;
     extern __shared__ __align__(16) uint32_t smem[];
     double *scratch = reinterpret_cast<double *>(smem);          // [64]
     uint32_t *sel = reinterpret_cast<uint32_t *>(scratch + 64);  // [64]
     const uint32_t mask = a.m >= 4 ? 0xFFFFFFFFu : ((1u << (8 * a.m)) - 1u);
-    double *pk = a.wk + a.poff[j];
-    uint32_t *pi = a.wi + a.poff[j];
-    const int64_t ninc = a.off[j + 1] - a.off[j];
+    double *pk = a.wk + a.poff[ti];
+    uint32_t *pi = a.wi + a.poff[ti];
+    const int64_t ninc = a.off[ti + 1] - a.off[ti];
     // the pool: the forward row, then incoming ids not already in it
     int np = 0;
     const int64_t total = a.R + ninc;
@@ -251,7 +257,7 @@ __global__ __launch_bounds__(64) void k_reverse(const RevArgs a)
         const int64_t e = e0 + lane;
         int32_t v = -1;
         if (e < total)
-            v = e < a.R ? a.fwd[j * a.R + e] : a.inc[a.off[j] + (e - a.R)];
+            v = e < a.R ? a.fwd[j * a.R + e] : a.inc[a.off[ti] + (e - a.R)];
         bool ok = v >= 0;
         if (ok && e >= a.R) {
             for (int t = 0; t < a.R; ++t)
@@ -346,7 +352,7 @@ template <int DP>
 int launch_select_dp(const SelArgs &a, hipStream_t st)
 {
     const size_t lds = sizeof(double) * ((size_t)a.K + 64) + sizeof(uint32_t) * ((size_t)a.K + 64);
-    hipLaunchKernelGGL(k_select<DP>, dim3((unsigned)a.n), dim3(64), lds, st, a);
+    hipLaunchKernelGGL(k_select<DP>, dim3((unsigned)a.nrows), dim3(64), lds, st, a);
     NHQ_HIP(hipGetLastError());
     return NHQ_OK;
 }
@@ -355,7 +361,7 @@ template <int DP>
 int launch_reverse_dp(const RevArgs &a, hipStream_t st)
 {
     const size_t lds = sizeof(double) * 64 + sizeof(uint32_t) * 64;
-    hipLaunchKernelGGL(k_reverse<DP>, dim3((unsigned)a.n), dim3(64), lds, st, a);
+    hipLaunchKernelGGL(k_reverse<DP>, dim3((unsigned)a.nt), dim3(64), lds, st, a);
     NHQ_HIP(hipGetLastError());
     return NHQ_OK;
 }
@@ -366,7 +372,7 @@ int launch_select(const Index *ix, const int32_t *cand, int K, int l, int32_t *a
 {
     if (K > 256)
         return fail(NHQ_EINVAL, "candidate list longer than 256");
-    SelArgs a{ix->vec32, ix->attr, cand, adj, ix->n, ix->m, K, l, ix->degree, ix->w};
+    SelArgs a{ix->vec32, ix->attr, cand, adj, ix->n, ix->m, K, l, ix->degree, ix->w, 0, ix->n};
     switch (ix->dp) {
     case 32: return launch_select_dp<32>(a, st);
     case 64: return launch_select_dp<64>(a, st);
@@ -456,6 +462,70 @@ int launch_refine(const Index *ix, const float *qpad, const int32_t *cand, int64
     return NHQ_OK;
 }
 
+// Edge selection for rows row0 .. row0 + nrows - 1 from cand [nrows][K]
+int launch_select_rows(const Index *ix, const int32_t *cand, int K, int l, int32_t *adj,
+                       int64_t row0, int64_t nrows, hipStream_t st)
+{
+    if (K > 256)
+        return fail(NHQ_EINVAL, "candidate list longer than 256");
+    if (nrows <= 0)
+        return NHQ_OK;
+    SelArgs a{ix->vec32, ix->attr, cand, adj, ix->n, ix->m, K, l, ix->degree, ix->w, row0, nrows};
+    switch (ix->dp) {
+    case 32: return launch_select_dp<32>(a, st);
+    case 64: return launch_select_dp<64>(a, st);
+    case 96: return launch_select_dp<96>(a, st);
+    case 128: return launch_select_dp<128>(a, st);
+    case 256: return launch_select_dp<256>(a, st);
+    case 512: return launch_select_dp<512>(a, st);
+    case 960: return launch_select_dp<960>(a, st);
+    case 1024: return launch_select_dp<1024>(a, st);
+    }
+    return fail(NHQ_EINVAL, "unsupported padded dimension");
+}
+
+// Re-selection of the rows targets[0..nt) of adj (in place) from the row
+// united with the offers inc[off[t] .. off[t+1]) (device arrays)
+int launch_reselect_targets(const Index *ix, int32_t *adj, const int32_t *targets, int64_t nt,
+                            const int64_t *off, const int32_t *inc, hipStream_t st)
+{
+    if (nt <= 0)
+        return NHQ_OK;
+    const int R = ix->degree;
+    std::vector<int64_t> hoff((size_t)nt + 1);
+    NHQ_HIP(hipMemcpyAsync(hoff.data(), off, sizeof(int64_t) * (size_t)(nt + 1), hipMemcpyDeviceToHost, st));
+    NHQ_HIP(hipStreamSynchronize(st));
+    std::vector<int64_t> poff((size_t)nt + 1);
+    poff[0] = 0;
+    for (int64_t t = 0; t < nt; ++t)
+        poff[t + 1] = poff[t] + R + (hoff[t + 1] - hoff[t]);
+    int64_t *dpoff = nullptr;
+    double *wk = nullptr;
+    uint32_t *wi = nullptr;
+    NHQ_HIP(hipMallocAsync((void **)&dpoff, sizeof(int64_t) * (size_t)(nt + 1), st));
+    NHQ_HIP(hipMallocAsync((void **)&wk, sizeof(double) * (size_t)poff[nt], st));
+    NHQ_HIP(hipMallocAsync((void **)&wi, sizeof(uint32_t) * (size_t)poff[nt], st));
+    NHQ_HIP(hipMemcpyAsync(dpoff, poff.data(), sizeof(int64_t) * (size_t)(nt + 1), hipMemcpyHostToDevice, st));
+    RevArgs a{ix->vec32, ix->attr, adj, off, inc, adj, wk, wi, dpoff, ix->n, ix->m, R, ix->w, targets, nt};
+    int rc = NHQ_OK;
+    switch (ix->dp) {
+    case 32: rc = launch_reverse_dp<32>(a, st); break;
+    case 64: rc = launch_reverse_dp<64>(a, st); break;
+    case 96: rc = launch_reverse_dp<96>(a, st); break;
+    case 128: rc = launch_reverse_dp<128>(a, st); break;
+    case 256: rc = launch_reverse_dp<256>(a, st); break;
+    case 512: rc = launch_reverse_dp<512>(a, st); break;
+    case 960: rc = launch_reverse_dp<960>(a, st); break;
+    case 1024: rc = launch_reverse_dp<1024>(a, st); break;
+    default: rc = fail(NHQ_EINVAL, "unsupported padded dimension");
+    }
+    void *bufs[] = {dpoff, wk, wi};
+    for (void *b : bufs)
+        (void)hipFreeAsync(b, st);
+    NHQ_HIP(hipStreamSynchronize(st));
+    return rc;
+}
+
 int launch_reverse(const Index *ix, const int32_t *fwd, int32_t *adj, hipStream_t st)
 {
     const int64_t n = ix->n;
@@ -489,7 +559,7 @@ int launch_reverse(const Index *ix, const int32_t *fwd, int32_t *adj, hipStream_
     NHQ_HIP(hipMemcpyAsync(off, h.data(), sizeof(int64_t) * (size_t)(n + 1), hipMemcpyHostToDevice, st));
     NHQ_HIP(hipMemcpyAsync(dpoff, poff.data(), sizeof(int64_t) * (size_t)(n + 1), hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_fill_incoming, dim3(grid), dim3(256), 0, st, fwd, n, R, off, fill, inc);
-    RevArgs a{ix->vec32, ix->attr, fwd, off, inc, adj, wk, wi, dpoff, n, ix->m, R, ix->w};
+    RevArgs a{ix->vec32, ix->attr, fwd, off, inc, adj, wk, wi, dpoff, n, ix->m, R, ix->w, nullptr, n};
     int rc = NHQ_OK;
     switch (ix->dp) {
     case 32: rc = launch_reverse_dp<32>(a, st); break;

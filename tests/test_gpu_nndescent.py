@@ -79,4 +79,34 @@ def test_argument_checks(int_set):
         with pytest.raises(Exception):
             nhq.nhq_nndescent_lists(ix, l, s, r, seed=1)
     with pytest.raises(Exception):
-        nhq.nhq_index_create(_dev(w.x), _dev(w.attrs), builder=2)
+        nhq.nhq_index_create(_dev(w.x), _dev(w.attrs), builder=3)
+
+
+# ---------------------------------------------------------------- NPG_nsw
+@pytest.mark.parametrize("n,batch,beam", [(3000, 3000, 48), (3000, 500, 48), (3000, 64, 32),
+                                          (300, 1, 24)])
+def test_nsw_build_matches_oracle(int_set, n, batch, beam):
+    w = int_set
+    x, at = w.x[:n], w.attrs[:n]
+    ix = nhq.nhq_build_index(_dev(x), _dev(at), degree=12, cand=24, n_entry=64, seed=21,
+                             builder="nsw", nsw_batch=batch, nsw_beam=beam)
+    adj = nhq.nhq_index_get_graph(ix).cpu().numpy()
+    want = oracle.build_nsw(x, at, 24, 12, batch, beam, 21)
+    assert np.array_equal(adj, want)
+    assert nhq.nhq_index_device_error(ix) == 0
+
+
+def test_nsw_float_data_searchable():
+    # float vectors: the insertion build serves the search about as well as
+    # the exact-candidate build of the same parameters
+    w = synth.config1(n=6000, nq=64)
+    gi, gd, _ = oracle.bruteforce(w.x, w.attrs, w.q, w.qattrs, 10)
+    got = {}
+    for builder in ("exact", "nsw"):
+        ix = nhq.nhq_build_index(_dev(w.x), _dev(w.attrs), degree=32, cand=64, n_entry=256, seed=4,
+                                 builder=builder, nsw_batch=1000, nsw_beam=96)
+        ids, dist = nhq.nhq_hybrid_search(ix, _dev(w.q), _dev(w.qattrs), 10, 96)
+        ids = ids.cpu().numpy()
+        got[builder] = np.mean([len(set(a[a >= 0]) & set(b[b >= 0])) / max(1, (b >= 0).sum())
+                                for a, b in zip(ids, gi)])
+    assert got["nsw"] >= got["exact"] - 0.1, got

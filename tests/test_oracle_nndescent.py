@@ -97,3 +97,43 @@ def test_converges_toward_the_exact_lists(small):
     # edge selection over the exact lists equals the reference build
     adj = oracle.select_lists(w.x, w.attrs, knn, 12)
     assert np.array_equal(adj, oracle.build_graph(w.x, w.attrs, l=24, R=12))
+
+
+# ---------------------------------------------------------------- NPG_nsw
+def test_nsw_single_batch_is_the_reference_build_with_reverse_edges(small):
+    # one batch holding every vertex: exact candidates within it, then every
+    # named vertex re-selects with its offers -- the reference build with
+    # its reverse pass
+    w = small
+    adj = oracle.build_nsw(w.x, w.attrs, 24, 12, w.n, 48, 1)
+    assert np.array_equal(adj, oracle.build_graph(w.x, w.attrs, l=24, R=12, reverse=True))
+
+
+@pytest.mark.parametrize("batch", [1, 7, 400])
+def test_nsw_rows_are_valid_and_searchable(small, batch):
+    w = small
+    n = 700 if batch == 1 else w.n
+    x, at = w.x[:n], w.attrs[:n]
+    adj = oracle.build_nsw(x, at, 16, 8, batch, 32, 2)
+    for i in range(n):
+        row = [int(v) for v in adj[i] if v >= 0]
+        assert i not in row and len(set(row)) == len(row) and all(0 <= v < n for v in row)
+        assert (adj[i][len(row):] == -1).all()
+    # nearly every row has edges, and the search finds most answers
+    assert ((adj >= 0).sum(1) > 0).mean() > 0.99
+    entry = oracle.entry_points(5, n, 64)
+    gi, gd, _ = oracle.bruteforce(x, at, w.q, w.qattrs, 10)
+    ids, gam, _, _, _ = oracle.search(adj, x, at, w.q, w.qattrs, 10, 64, entry)
+    got = np.mean([len(set(a[a >= 0]) & set(b[b >= 0])) / max(1, (b >= 0).sum()) for a, b in zip(ids, gi)])
+    assert got >= 0.5
+
+
+def test_nsw_batches_see_only_earlier_vertices(small):
+    # a batch sees only earlier vertices, and nothing is inserted after the
+    # last batch: its rows name only vertices of the earlier batches
+    w = small
+    n = 1200
+    adj = oracle.build_nsw(w.x[:n], w.attrs[:n], 16, 8, 300, 32, 4)
+    for i in range(900, 1200):
+        assert (adj[i][adj[i] >= 0] < 1200).all()
+        assert (adj[i][adj[i] >= 0] < 900).all()
