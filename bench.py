@@ -662,6 +662,8 @@ def ablation(args):
                    i-v; Eq. 8 with c = 100), each with its own index;
       selectivity  attribute cardinalities giving |P|/|S| = 1/8 ... 1/4000
                    (full constraints, default weights);
+      attribute dimension  m = 6 and 9 binary attributes (|P|/|S| = 1/64
+                   and 1/512) against the m = 3 set;
       post_filter  strategy B(1) on the default composite index: a search
                    by vector alone (every attribute a wildcard) whose raw
                    pool is then filtered to exact matches; the filter runs on
@@ -790,6 +792,21 @@ def ablation(args):
         if ix is not ix0:
             ix.free()
     out["selectivity"] = sres
+    # ---- attribute dimension (m = 6 and 9; binary attributes, so m = 6
+    # matches the 1/60 selectivity of the m = 3 set closely)
+    mres = {"3": {"cards": list(w.cards), "match_fraction": 1.0 / float(np.prod(w.cards)),
+                  **sres["1/%d" % int(np.prod(w.cards))]}}
+    for m_, cards in ((6, (2,) * 6), (9, (2,) * 9)):
+        a_np = synth.uniform_attrs(w.n, cards, 202)
+        qa_np = synth.uniform_attrs(nq, cards, 204)
+        ix, _, _ = index_for(a_np)
+        g_i, g_d = nhq.nhq_bruteforce_hybrid_knn(ix, q, torch.from_numpy(qa_np).to(dev), k)
+        g_i, g_d = g_i.cpu().numpy(), g_d.cpu().numpy()
+        r = curve(ix, a_np, qa_np, g_i, g_d, "m = %d" % m_)
+        r.update({"cards": list(cards), "match_fraction": 1.0 / float(np.prod(cards))})
+        mres[str(m_)] = r
+        ix.free()
+    out["attribute_dimension"] = mres
     print(json.dumps({"metric": "parameter studies (Sec. 6.5): Recall@10 / QPS curves on 1 GPU",
                       "value": wres["iv"]["qps_at_target"], "unit": "queries/s", "n_gpus": 1,
                       "higher_is_better": True, "vs_baseline": None, "dtype": "f32",

@@ -12,8 +12,11 @@
  * Conventions for every entry point:
  *  - Array arguments are DEVICE pointers owned by the caller unless marked
  *    "host".  Vectors are row-major float32 [rows][d]; attribute codes are
- *    row-major uint8 [rows][m] with m <= 4 and object codes < 255; in query
- *    codes 255 (0xFF) marks an unconstrained attribute (wildcard).
+ *    row-major uint8 [rows][m], m <= 12.  The index packs an object's codes
+ *    into one 32-bit word, 8 bits each for m <= 4, 4 bits for m <= 8 and 2
+ *    bits for m <= 12, so object codes must stay below 255, 15 and 3
+ *    respectively.  In query codes 255 (0xFF) marks an unconstrained
+ *    attribute (wildcard); other query codes no object holds match nothing.
  *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
  *    is asynchronous unless stated otherwise: outputs are valid once the
  *    stream has been synchronised.
@@ -74,7 +77,7 @@ extern "C" {
 
 #define NHQ_MAX_DEGREE 64
 #define NHQ_MAX_BEAM 1024
-#define NHQ_MAX_ATTRS 4
+#define NHQ_MAX_ATTRS 12
 
 typedef struct nhq_index nhq_index;
 

@@ -39,6 +39,7 @@
 #endif
 
 #define OR_WILDCARD 0xFF
+#define OR_MAXM 16 /* attributes the learned-stop features read */
 #define OR_KEY64 0
 #define OR_KEY32 1
 
@@ -852,17 +853,17 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
     if (expand > 64)
         expand = 64;
     /* ln(count / n) of every attribute code (count 0 read as 0.5) */
-    double logp[4][256];
-    for (int i = 0; i < 4; ++i)
+    double logp[OR_MAXM][256];
+    for (int i = 0; i < OR_MAXM; ++i)
         for (int c = 0; c < 256; ++c)
             logp[i][c] = 0.0;
     if (check_every > 0) {
-        int64_t cnt[4][256];
+        int64_t cnt[OR_MAXM][256];
         memset(cnt, 0, sizeof(cnt));
         for (int64_t e = 0; e < n; ++e)
-            for (int i = 0; i < m && i < 4; ++i)
+            for (int i = 0; i < m && i < OR_MAXM; ++i)
                 cnt[i][attrs[e * (int64_t)m + i]] += 1;
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < OR_MAXM; ++i)
             for (int c = 0; c < 256; ++c)
                 logp[i][c] = log((cnt[i][c] > 0 ? (double)cnt[i][c] : 0.5) / (double)n);
     }
@@ -962,7 +963,7 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
             uint32_t prev_hash = 0;
             int64_t last_change = 0, ins_window = 0;
             double logsel = 0.0;
-            for (int i = 0; i < m && i < 4; ++i)
+            for (int i = 0; i < m && i < OR_MAXM; ++i)
                 if (qav[i] != OR_WILDCARD)
                     logsel += logp[i][qav[i]];
             int64_t next_ckpt = check_every;

@@ -49,7 +49,8 @@ int nhq_index_build_graph(nhq_index *h, void *stream)
         ix->nnd_rounds_run = done;
     } else {
         rc = launch_dense_topk(ix->vec32, ix->norm, ix->attr, nullptr, ix->n, ix->vec32, ix->norm,
-                               ix->attr, ix->n, ix->dp, ix->m, 0, 1, K, cand, nullptr, st, &ix->w);
+                               ix->attr, ix->n, ix->dp, ix->m, ix->abits, 0, 1, K, cand, nullptr, st,
+                               &ix->w);
     }
     if (rc == NHQ_OK) {
         if (ix->reverse_edges) {
@@ -114,10 +115,11 @@ int nhq_bruteforce_hybrid_knn(const nhq_index *h, const float *queries, const ui
     NHQ_HIP(hipMallocAsync((void **)&qw, sizeof(uint32_t) * (size_t)nq, st));
     NHQ_HIP(hipMallocAsync((void **)&qm, sizeof(uint32_t) * (size_t)nq, st));
     NHQ_HIP(hipMallocAsync((void **)&cand, sizeof(int32_t) * (size_t)nq * K, st));
-    int rc = launch_pad_queries(queries, qattrs, nq, ix->d, ix->dp, ix->m, qpad, qnorm, qw, qm, nullptr, st);
+    int rc = launch_pad_queries(queries, qattrs, nq, ix->d, ix->dp, ix->m, ix->abits, qpad, qnorm, qw, qm,
+                                nullptr, st);
     if (rc == NHQ_OK)
         rc = launch_dense_topk(qpad, qnorm, qw, qm, nq, ix->vec32, ix->norm, ix->attr, ix->n, ix->dp,
-                               ix->m, 1, 0, K, cand, nullptr, st);
+                               ix->m, ix->abits, 1, 0, K, cand, nullptr, st);
     if (rc == NHQ_OK)
         rc = launch_refine(ix, qpad, cand, nq, K, k, ids, dists, st);
     void *bufs[] = {qpad, qnorm, qw, qm, cand};

@@ -39,6 +39,8 @@ struct TopkArgs {
     const uint32_t *B_attr;  // [nb]
     int64_t na, nb;
     int m, K, cap, mode;  // mode 0 fusion key, 1 exact-match filter
+    int abits;            // bits per attribute field
+    uint32_t hmask;       // high bit of every field
     int self_exclude;     // skip column == row (A and B are the same set)
     int64_t col_span;     // columns per split (multiple of 64)
     int splits;           // gridDim.y
@@ -53,12 +55,6 @@ __device__ __forceinline__ void wsync()
     __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ int chi_of(uint32_t a, uint32_t qword, uint32_t qmask)
-{
-    uint32_t x = (a ^ qword) & qmask;
-    uint32_t y = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;
-    return __popc(y & 0x80808080u);
-}
 
 __device__ __forceinline__ bool lt_key(float ka, uint32_t ia, float kb, uint32_t ib)
 {
@@ -166,9 +162,9 @@ __global__ __launch_bounds__(128) void k_dense_topk(const TopkArgs a)
     }
     const float rn = a.A_norm[rowc];
     const uint32_t rattr = a.A_attr ? a.A_attr[rowc] : 0u;
-    const uint32_t full = a.m >= 4 ? 0xFFFFFFFFu : ((1u << (8 * a.m)) - 1u);
+    const uint32_t full = attr_full_mask(a.m, a.abits);
     const uint32_t rmask = a.A_mask ? a.A_mask[rowc] : full;
-    const int mq = __popc(rmask) / 8;
+    const int mq = __popc(rmask) / a.abits;
 
     const int64_t cbeg = (int64_t)blockIdx.y * a.col_span;
     const int64_t cend = min(a.nb, cbeg + a.col_span);
@@ -239,7 +235,7 @@ __global__ __launch_bounds__(128) void k_dense_topk(const TopkArgs a)
                     continue;
                 if (a.self_exclude && col == row)
                     continue;
-                const int c = chi_of(at4[r], rattr, rmask);
+                const int c = chi_of(at4[r], rattr, rmask, a.hmask);
                 if (a.mode == 1 && c != 0)
                     continue;
                 float d2 = rn + nb4[r] - 2.0f * acc[s][r];
@@ -340,7 +336,7 @@ int launch_dp(const TopkArgs &a, hipStream_t st)
 
 int launch_dense_topk(const float *A, const float *A_norm, const uint32_t *A_attr,
                       const uint32_t *A_mask, int64_t na, const float *B, const float *B_norm,
-                      const uint32_t *B_attr, int64_t nb, int dp, int m, int mode,
+                      const uint32_t *B_attr, int64_t nb, int dp, int m, int abits, int mode,
                       int self_exclude, int K, int32_t *out_ids, float *out_keys, hipStream_t st,
                       const Weights *w)
 {
@@ -362,6 +358,8 @@ int launch_dense_topk(const float *A, const float *A_norm, const uint32_t *A_att
     // re-ranked only after at least 64 new survivors
     a.cap = ((K + 128 + 15) / 16) * 16;
     a.mode = mode;
+    a.abits = abits;
+    a.hmask = attr_hmask(abits);
     a.w = w ? *w : Weights{NHQ_WEIGHTS_DEFAULT, 0.0f, 0.0};
     a.self_exclude = self_exclude;
     if (na == 0 || nb == 0)

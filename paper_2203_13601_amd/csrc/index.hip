@@ -66,19 +66,16 @@ __global__ void k_pad_copy(const float *__restrict__ src, float *__restrict__ ds
     }
 }
 
-// attribute codes (one byte each) packed little-endian into one word
+// attribute codes (one byte each) packed into one word, b bits per code,
+// attribute j in bits b*j .. (the codes fit: checked from their histogram)
 __global__ void k_pack_attr(const uint8_t *__restrict__ a, uint32_t *__restrict__ out, int64_t n,
-                            int m, uint32_t *__restrict__ bad)
+                            int m, int b)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         uint32_t w = 0;
-        for (int j = 0; j < m; ++j) {
-            const uint32_t c = a[i * m + j];
-            if (c == 0xFFu)
-                atomicOr(bad, 1u);
-            w |= c << (8 * j);
-        }
+        for (int j = 0; j < m; ++j)
+            w |= (uint32_t)a[i * m + j] << (b * j);
         out[i] = w;
     }
 }
@@ -157,7 +154,7 @@ __global__ __launch_bounds__(64) void k_to_fp8(const float *__restrict__ v, uint
 // packed codes and constraint mask
 __global__ __launch_bounds__(64) void k_pad_queries(const float *__restrict__ q,
                                                     const uint8_t *__restrict__ qa, int64_t nq, int d,
-                                                    int dp, int m, float *__restrict__ qpad,
+                                                    int dp, int m, int abits, float *__restrict__ qpad,
                                                     float *__restrict__ qnorm,
                                                     uint32_t *__restrict__ qword,
                                                     uint32_t *__restrict__ qmask,
@@ -181,13 +178,7 @@ __global__ __launch_bounds__(64) void k_pad_queries(const float *__restrict__ q,
         if (lane == 0) {
             qnorm[i] = s;
             uint32_t w = 0, mk = 0;
-            for (int j = 0; j < m; ++j) {
-                const uint32_t c = qa[i * m + j];
-                if (c != 0xFFu) {
-                    w |= c << (8 * j);
-                    mk |= 0xFFu << (8 * j);
-                }
-            }
+            attr_pack_query(qa + i * m, m, abits, w, mk);
             qword[i] = w;
             qmask[i] = mk;
         }
@@ -243,13 +234,13 @@ void free_index(Index *ix)
 }  // namespace
 
 int launch_pad_queries(const float *q, const uint8_t *qa, int64_t nq, int d, int dp, int m,
-                       float *qpad, float *qnorm, uint32_t *qword, uint32_t *qmask, uint32_t *qexact,
-                       hipStream_t st)
+                       int abits, float *qpad, float *qnorm, uint32_t *qword, uint32_t *qmask,
+                       uint32_t *qexact, hipStream_t st)
 {
     if (nq == 0)
         return NHQ_OK;
     hipLaunchKernelGGL(k_pad_queries, dim3(grid_for(nq, 1)), dim3(64), 0, st, q, qa, nq, d, dp, m,
-                       qpad, qnorm, qword, qmask, qexact);
+                       abits, qpad, qnorm, qword, qmask, qexact);
     NHQ_HIP(hipGetLastError());
     return NHQ_OK;
 }
@@ -394,9 +385,48 @@ int nhq_index_create(const float *vecs, const uint8_t *attrs, int64_t n, int32_t
         }
         hipLaunchKernelGGL(k_pad_copy, dim3(grid_for((int64_t)rows, 256)), dim3(256), 0, st, vecs,
                            ix->vec32, n, d, ix->dp);
+        // per-attribute code counts: the widest code sets the packing; the
+        // counts also give ln(count / n), the selectivity estimate the stop
+        // network reads (ln(0.5 / n) for absent codes)
+        std::vector<uint32_t> hh((size_t)NHQ_MAX_ATTRS * 256, 0u);
+        {
+            uint32_t *hist = nullptr;
+            if (hipMalloc(&hist, sizeof(uint32_t) * hh.size()) != hipSuccess) {
+                rc = fail(NHQ_ENOMEM, "histogram allocation failed");
+                break;
+            }
+            (void)hipMemsetAsync(hist, 0, sizeof(uint32_t) * hh.size(), st);
+            if (m > 0)
+                hipLaunchKernelGGL(k_code_hist, dim3(grid_for(n * m, 256)), dim3(256), 0, st, attrs, n,
+                                   m, hist);
+            const bool ok = hipMemcpyAsync(hh.data(), hist, sizeof(uint32_t) * hh.size(),
+                                           hipMemcpyDeviceToHost, st) == hipSuccess &&
+                            hipStreamSynchronize(st) == hipSuccess;
+            (void)hipFree(hist);
+            if (!ok) {
+                rc = fail(NHQ_EHIP, "ingest synchronisation failed");
+                break;
+            }
+        }
+        int max_code = 0;
+        for (int j = 0; j < m; ++j)
+            for (int c = 0; c < 256; ++c)
+                if (hh[(size_t)j * 256 + c])
+                    max_code = std::max(max_code, c);
+        if (m > 0 && hh.size() && max_code == 255) {
+            rc = fail(NHQ_EINVAL, "object attribute code 255 is reserved for query wildcards");
+            break;
+        }
+        ix->abits = m > 0 ? attr_bits(m, max_code) : 8;
+        if (ix->abits == 0) {
+            rc = fail(NHQ_EINVAL, "attribute codes too wide for m attributes in 32 bits (codes <= 14 "
+                                  "for m <= 8, <= 2 for m <= 12)");
+            break;
+        }
+        ix->hmask = attr_hmask(ix->abits);
         if (m > 0) {
             hipLaunchKernelGGL(k_pack_attr, dim3(grid_for(n, 256)), dim3(256), 0, st, attrs,
-                               ix->attr, n, m, ix->err + 1);
+                               ix->attr, n, m, ix->abits);
         } else {
             (void)hipMemsetAsync(ix->attr, 0, (size_t)n * sizeof(uint32_t), st);
         }
@@ -454,31 +484,11 @@ int nhq_index_create(const float *vecs, const uint8_t *attrs, int64_t n, int32_t
         hipLaunchKernelGGL(k_gather_entry, dim3(grid_for(ne * ix->dp, 256)), dim3(256), 0, st, ix->entry,
                            (int)ne, ix->vec32, ix->norm, ix->attr, ix->dp, ix->entry_vec,
                            ix->entry_norm, ix->entry_attr);
-        // per-attribute code frequencies: ln(count / n), the selectivity
-        // estimate the stop network reads (ln(0.5 / n) for absent codes)
-        uint32_t *hist = nullptr;
-        std::vector<uint32_t> hh((size_t)4 * 256, 0u);
-        if (hipMalloc(&hist, sizeof(uint32_t) * 4 * 256) != hipSuccess ||
-            hipMalloc(&ix->logp, sizeof(float) * 4 * 256) != hipSuccess) {
+        if (hipMalloc(&ix->logp, sizeof(float) * hh.size()) != hipSuccess) {
             rc = fail(NHQ_ENOMEM, "histogram allocation failed");
             break;
         }
-        (void)hipMemsetAsync(hist, 0, sizeof(uint32_t) * 4 * 256, st);
-        if (m > 0)
-            hipLaunchKernelGGL(k_code_hist, dim3(grid_for(n * m, 256)), dim3(256), 0, st, attrs, n, m, hist);
-        uint32_t bad = 0;
-        if (hipMemcpyAsync(hh.data(), hist, sizeof(uint32_t) * 4 * 256, hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipMemcpyAsync(&bad, ix->err + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess) {
-            rc = fail(NHQ_EHIP, "ingest synchronisation failed");
-            break;
-        }
-        (void)hipFree(hist);
-        if (bad) {
-            rc = fail(NHQ_EINVAL, "object attribute code 255 is reserved for query wildcards");
-            break;
-        }
-        std::vector<float> lp((size_t)4 * 256);
+        std::vector<float> lp(hh.size());
         for (size_t t = 0; t < lp.size(); ++t)
             lp[t] = (float)std::log((hh[t] > 0 ? (double)hh[t] : 0.5) / (double)n);
         if (hipMemcpy(ix->logp, lp.data(), sizeof(float) * lp.size(), hipMemcpyHostToDevice) != hipSuccess) {
@@ -649,13 +659,15 @@ int nhq_seed_rank(const nhq_index *h, const float *queries, const uint8_t *qattr
     uint32_t *qm = qw + f_small;
     uint32_t *qx = qm + f_small;
     float *keys = reinterpret_cast<float *>((reinterpret_cast<uintptr_t>(qx + f_small) + 255) & ~uintptr_t(255));
-    int rc = launch_pad_queries(queries, qattrs, nq, ix->d, ix->dp, ix->m, qpad, qnorm, qw, qm, qx, st);
+    int rc = launch_pad_queries(queries, qattrs, nq, ix->d, ix->dp, ix->m, ix->abits, qpad, qnorm, qw, qm,
+                                qx, st);
     if (rc == NHQ_OK) {
         if (dense)
             rc = launch_seed_rank(ix, qpad, qnorm, qw, qm, qx, nq, n_cand, keys, cand, st);
         else
             rc = launch_dense_topk(qpad, qnorm, qw, qm, nq, ix->entry_vec, ix->entry_norm,
-                                   ix->entry_attr, ix->n_entry, ix->dp, ix->m, 0, 0, n_cand, cand,
+                                   ix->entry_attr, ix->n_entry, ix->dp, ix->m, ix->abits, 0, 0, n_cand,
+                                   cand,
                                    nullptr, st, &ix->w);
     }
     (void)hipFreeAsync(blk, st);

@@ -9,6 +9,7 @@
 #include <string>
 
 #include "nhq.h"
+#include "attr.h"
 #include "weights.h"
 
 // ------------------------------------------------------------------ errors
@@ -25,13 +26,14 @@ int fail(int code, const std::string &msg);
     } while (0)
 
 // --------------------------------------------------------------- packing
-// Pool / candidate id word: vertex id in the low 28 bits, chi (0..4) in bits
-// 28..30, the "expanded" flag in bit 31.  Order comparisons use the id bits.
-constexpr uint32_t kIdMask = 0x0FFFFFFFu;
+// Pool / candidate id word: vertex id in the low 27 bits, chi (0..12) in bits
+// 27..30, the "expanded" flag in bit 31.  Order comparisons use the id bits.
+constexpr uint32_t kIdMask = 0x07FFFFFFu;
 constexpr uint32_t kExpBit = 0x80000000u;
-constexpr int kChiShift = 28;
+constexpr int kChiShift = 27;
+constexpr uint32_t kChiMask = 15u;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
-constexpr int64_t kMaxN = int64_t(1) << 28;
+constexpr int64_t kMaxN = int64_t(1) << 27;
 
 // Padded widths the kernels are instantiated for (the stored rows are padded
 // with zeros to the next one; zeros change no distance).
@@ -48,6 +50,8 @@ struct Index {
     int n_entry = 0;
     uint64_t seed = 0;
     Weights w{NHQ_WEIGHTS_DEFAULT, 0.0f, 0.0};  // weight setting of Gamma
+    int abits = 8;                 // bits per attribute in the packed words
+    uint32_t hmask = 0x80808080u;  // high bit of every attribute field
     // edge candidates: exact all-pairs or NN-descent (rounds, sample, stop)
     int builder = NHQ_BUILD_EXACT;
     int nnd_rounds = 12, nnd_sample = 24;
@@ -132,7 +136,7 @@ int launch_reselect_targets(const Index *ix, int32_t *adj, const int32_t *target
 // dense tiles with a streaming top-K (see dense_topk.hip)
 int launch_dense_topk(const float *A, const float *A_norm, const uint32_t *A_attr,
                       const uint32_t *A_mask, int64_t na, const float *B, const float *B_norm,
-                      const uint32_t *B_attr, int64_t nb, int dp, int m, int mode,
+                      const uint32_t *B_attr, int64_t nb, int dp, int m, int abits, int mode,
                       int self_exclude, int K, int32_t *out_ids, float *out_keys, hipStream_t st,
                       const Weights *w = nullptr);
 
@@ -146,7 +150,7 @@ int launch_seed_rank(const Index *ix, const float *qpad, const float *qnorm, con
 // queries -> zero-padded float32 rows, squared norms, packed codes and masks,
 // and (qexact nullable) whether every value is an integer of magnitude <= 256
 int launch_pad_queries(const float *q, const uint8_t *qa, int64_t nq, int d, int dp, int m,
-                       float *qpad, float *qnorm, uint32_t *qword, uint32_t *qmask, uint32_t *qexact,
+                       int abits, float *qpad, float *qnorm, uint32_t *qword, uint32_t *qmask, uint32_t *qexact,
                        hipStream_t st);
 
 }  // namespace nhq

@@ -35,6 +35,8 @@ struct NndArgs {
     int init;       // 1: round 0 (random start)
     int hash_log2;  // visited hash: 2^hash_log2 slots
     Weights w;
+    int abits;        // attribute field width
+    uint32_t hmask;   // high bit of every attribute field
 };
 
 // LDS words of one wave: pool keys and words [l], the previous list's ids [l],
@@ -69,7 +71,7 @@ __global__ __launch_bounds__(64) void k_nnd_round(const NndArgs a)
     for (int c = 0; c < S::NCH; ++c)
         qv[c] = *reinterpret_cast<const float4 *>(qp + 4 * (g + S::G * c));
     const uint32_t qword = a.attr[i];
-    const uint32_t qmask = a.m >= 4 ? 0xFFFFFFFFu : ((1u << (8 * a.m)) - 1u);
+    const uint32_t qmask = attr_full_mask(a.m, a.abits);
     const int mq = a.m;
     for (int e = lane; e < (1 << a.hash_log2); e += 64)
         vis[e] = kEmpty;
@@ -84,7 +86,7 @@ __global__ __launch_bounds__(64) void k_nnd_round(const NndArgs a)
     auto score_merge = [&](int nf) {
         wsync();
         score_batch<DP, NHQ_STORAGE_FP32>(a.vec32, nullptr, qv, sid, skey, nf, mq, 1, a.w, a.attr,
-                                          qword, qmask);
+                                          qword, qmask, a.hmask);
         wsync();
         if (a.w.mode != NHQ_WEIGHTS_DEFAULT)
             weigh_keys(skey, sid, nf, mq, a.w);
@@ -241,6 +243,8 @@ int nnd_lists(const Index *ix, int l, int s, int rounds, double stop_frac, uint6
     a.seed = seed;
     a.hash_log2 = hb;
     a.w = ix->w;
+    a.abits = ix->abits;
+    a.hmask = ix->hmask;
     const size_t cells = (size_t)n * l;
     char *blk = nullptr;
     const size_t bytes = 4 * cells * sizeof(uint32_t) + 256;

@@ -18,6 +18,19 @@ namespace nhq {
 
 constexpr int kNswMargin = 16;  // dense-tile candidates kept beyond l
 
+// the codes of objects s .. s + nb - 1 from their packed words
+__global__ void k_unpack_attr(const uint32_t *__restrict__ words, int64_t nb, int m, int b,
+                              uint8_t *__restrict__ codes)
+{
+    const uint32_t fm = (1u << b) - 1u;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nb * m;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = t / m;
+        const int j = (int)(t - e * m);
+        codes[t] = (uint8_t)((words[e] >> (b * j)) & fm);
+    }
+}
+
 // Offers of the rows [s, s + nb) to the vertices they name, grouped by
 // target on the host, then the targets' re-selection on the device.
 static int nsw_reverse(Index *ix, int64_t s, int64_t nb, hipStream_t st)
@@ -82,7 +95,7 @@ int nsw_build(Index *ix, int l, int64_t B, int L, uint64_t seed, hipStream_t st)
         int32_t *cand = nullptr;
         NHQ_HIP(hipMallocAsync((void **)&cand, sizeof(int32_t) * (size_t)b0 * K, st));
         rc = launch_dense_topk(ix->vec32, ix->norm, ix->attr, nullptr, b0, ix->vec32, ix->norm,
-                               ix->attr, b0, dp, m, 0, 1, K, cand, nullptr, st, &ix->w);
+                               ix->attr, b0, dp, m, ix->abits, 0, 1, K, cand, nullptr, st, &ix->w);
         if (rc == NHQ_OK)
             rc = launch_select_rows(ix, cand, K, l0, ix->adj, 0, b0, st);
         (void)hipFreeAsync(cand, st);
@@ -121,12 +134,14 @@ int nsw_build(Index *ix, int l, int64_t B, int L, uint64_t seed, hipStream_t st)
         if (hipMemcpyAsync(ent, seeds.data(), sizeof(int32_t) * (size_t)want, hipMemcpyHostToDevice,
                            st) != hipSuccess ||
             hipMemcpy2DAsync(q, sizeof(float) * d, ix->vec32 + s * dp, sizeof(float) * dp,
-                             sizeof(float) * d, (size_t)nb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
-            (m > 0 && hipMemcpy2DAsync(qa, (size_t)m, reinterpret_cast<const uint8_t *>(ix->attr + s),
-                                       sizeof(uint32_t), (size_t)m, (size_t)nb,
-                                       hipMemcpyDeviceToDevice, st) != hipSuccess)) {
+                             sizeof(float) * d, (size_t)nb, hipMemcpyDeviceToDevice, st) != hipSuccess) {
             rc = fail(NHQ_EHIP, "NSW batch staging failed");
             break;
+        }
+        if (m > 0) {
+            const unsigned blocks = (unsigned)std::min<int64_t>(65536, (nb * m + 255) / 256);
+            hipLaunchKernelGGL(k_unpack_attr, dim3(blocks), dim3(256), 0, st, ix->attr + s, nb, m,
+                               ix->abits, qa);
         }
         SearchLaunch sl{};
         sl.ix = ix;

@@ -29,7 +29,7 @@ __device__ __forceinline__ void search_block(const SearchArgs &a)
         return;
     QueryIO io;
     io.q = a.q + qi * (int64_t)a.d;
-    pack_query_attrs(a.qa + qi * a.m, a.m, io.qword, io.qmask);
+    pack_query_attrs(a.qa + qi * a.m, a.m, a.abits, io.qword, io.qmask);
     io.seeds = a.seed_cand + (a.seeds_shared ? 0 : qi * a.n_seed);
     io.n_seed = a.n_seed;
     io.oid = a.out_ids + qi * a.k;
@@ -128,6 +128,8 @@ int launch_search(const SearchLaunch &s)
     a.expand = s.expand;
     a.route_h = s.route_h;
     a.w = ix->w;
+    a.abits = ix->abits;
+    a.hmask = ix->hmask;
     a.learned = s.learned;
     a.stop_logit = s.stop_logit;
     a.cap_factor = s.cap_factor;

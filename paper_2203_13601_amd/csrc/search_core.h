@@ -40,6 +40,8 @@ struct SearchArgs {
     int expand;           // vertices expanded per step (1 = Alg. 2 as printed)
     int route_h;          // >= 2: two-stage routing, stage S1 evaluates 1 slot in h
     int seeds_shared;     // every query reads the first row of seed_cand
+    int abits;            // attribute field width of the packed words
+    uint32_t hmask;       // high bit of every attribute field
     Weights w;            // weight setting of Gamma (the index's)
     float stop_logit;     // learned: stop when the stop logit >= this
     float cap_factor;     // learned, > 0: hop budget cap_factor * 2^(beam output)
@@ -98,13 +100,6 @@ __device__ __forceinline__ int lanes_below(uint64_t mask)
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// number of constrained attribute bytes that differ (Eq. 4-5)
-__device__ __forceinline__ int chi_of(uint32_t a, uint32_t qword, uint32_t qmask)
-{
-    uint32_t x = (a ^ qword) & qmask;
-    uint32_t y = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;
-    return __popc(y & 0x80808080u);
-}
 
 __device__ __forceinline__ bool lt_key(float ka, uint32_t ia, float kb, uint32_t ib)
 {
@@ -166,7 +161,8 @@ __device__ __forceinline__ void score_batch(const void *vbase, const float *scal
                                             uint32_t *sid, float *out, int nf, int mq,
                                             int mode, const Weights &wt,
                                             const uint32_t *attr = nullptr,
-                                            uint32_t qword = 0, uint32_t qmask = 0)
+                                            uint32_t qword = 0, uint32_t qmask = 0,
+                                            uint32_t hmask = 0x80808080u)
 {
     using S = Shape<DP>;
     using T = typename Chunk<ST>::T;
@@ -214,9 +210,9 @@ __device__ __forceinline__ void score_batch(const void *vbase, const float *scal
             }
             float d2 = group_sum<S::G>(a0 + a1);
             if (j < nf && g == 0) {
-                int c = (int)((w[rr] >> kChiShift) & 7u);
+                int c = (int)((w[rr] >> kChiShift) & kChiMask);
                 if (mode == 1) {
-                    c = chi_of(aw[rr], qword, qmask);
+                    c = chi_of(aw[rr], qword, qmask, hmask);
                     sid[j] = w[rr] | ((uint32_t)c << kChiShift);
                 }
                 // the default key inline; the other weight settings take
@@ -235,7 +231,7 @@ __device__ __forceinline__ void weigh_keys(float *skey, const uint32_t *sid, int
                                         const Weights &w)
 {
     for (int j = threadIdx.x & 63; j < n; j += 64)
-        skey[j] = w_key32(skey[j], (int)((sid[j] >> kChiShift) & 7u), mq, w);
+        skey[j] = w_key32(skey[j], (int)((sid[j] >> kChiShift) & kChiMask), mq, w);
     wsync();
 }
 
@@ -361,7 +357,7 @@ __device__ void eligible_topk(const float *pkey, const uint32_t *pid, int size, 
     for (int base = 0; base < size && nel < k; base += 64) {
         const int e = base + lane;
         const uint32_t w = e < size ? pid[e] : 0u;
-        const bool el = e < size && (out_mode == 1 || ((w >> kChiShift) & 7u) == 0);
+        const bool el = e < size && (out_mode == 1 || ((w >> kChiShift) & kChiMask) == 0);
         const uint64_t bb = __ballot(el);
         const int pos = nel + lanes_below(bb);
         const bool take = el && pos < k;
@@ -444,17 +440,10 @@ struct QueryIO {
     const uint16_t *mlp;  // stop network weights (device layout; LDS or global)
 };
 
-__device__ __forceinline__ void pack_query_attrs(const uint8_t *qa, int m, uint32_t &qword, uint32_t &qmask)
+__device__ __forceinline__ void pack_query_attrs(const uint8_t *qa, int m, int b, uint32_t &qword,
+                                                 uint32_t &qmask)
 {
-    qword = 0;
-    qmask = 0;
-    for (int i = 0; i < m; ++i) {
-        const uint32_t c = qa[i];
-        if (c != 0xFFu) {
-            qword |= c << (8 * i);
-            qmask |= 0xFFu << (8 * i);
-        }
-    }
+    attr_pack_query(qa, m, b, qword, qmask);
 }
 
 // The search of one query by one wave (Alg. 2 in beam form), LDS at smem:
@@ -488,12 +477,13 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
         qv[c].w = e + 3 < a.d ? qp[e + 3] : 0.0f;
     }
     const uint32_t qword = io.qword, qmask = io.qmask;
-    const int mq = __popc(qmask) / 8;
+    const int mq = __popc(qmask) / a.abits;
     if (CK && a.ckpt > 0) {
         float logsel = 0.0f;
+        const uint32_t fm = (1u << a.abits) - 1u;
         for (int i = 0; i < a.m; ++i)
-            if ((qmask >> (8 * i)) & 0xFFu)
-                logsel += a.logp[i * 256 + ((qword >> (8 * i)) & 0xFFu)];
+            if ((qmask >> (a.abits * i)) & fm)
+                logsel += a.logp[i * 256 + ((qword >> (a.abits * i)) & fm)];
         if (lane == 0) {
             cks->logsel = logsel;
             cks->key_kth_first = 0.0f;
@@ -523,7 +513,7 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
         if (ok)
             sid[lanes_below(vb)] = (uint32_t)v;
         wsync();
-        score_batch<DP, ST>(a.vecs, a.scale, qv, sid, skey, ne, mq, 1, a.w, a.attr, qword, qmask);
+        score_batch<DP, ST>(a.vecs, a.scale, qv, sid, skey, ne, mq, 1, a.w, a.attr, qword, qmask, a.hmask);
         wsync();
         if (a.w.mode != NHQ_WEIGHTS_DEFAULT)
             weigh_keys(skey, sid, ne, mq, a.w);
@@ -768,7 +758,7 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
         }
         wsync();
         ndc += nf;
-        score_batch<DP, ST>(a.vecs, a.scale, qv, sid, skey, nf, mq, 1, a.w, a.attr, qword, qmask);
+        score_batch<DP, ST>(a.vecs, a.scale, qv, sid, skey, nf, mq, 1, a.w, a.attr, qword, qmask, a.hmask);
         wsync();
         if (a.w.mode != NHQ_WEIGHTS_DEFAULT)
             weigh_keys(skey, sid, nf, mq, a.w);
@@ -810,7 +800,7 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
     for (int base = 0; base < size && got < want; base += 64) {
         const int e = base + lane;
         const uint32_t w = e < size ? pid[e] : 0u;
-        const bool el = e < size && (a.out_mode == 1 || ((w >> kChiShift) & 7u) == 0);
+        const bool el = e < size && (a.out_mode == 1 || ((w >> kChiShift) & kChiMask) == 0);
         const uint64_t bb = __ballot(el);
         const int pos = got + lanes_below(bb);
         if (el && pos < want)
@@ -828,7 +818,7 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
         const int j = j0 + lane;
         if (j < got) {
             const uint32_t w = sid[j];
-            const int c = (int)((w >> kChiShift) & 7u);
+            const int c = (int)((w >> kChiShift) & kChiMask);
             const float d2 = skey[j];
             int slot = j;
             if (a.rerank_n > 0) {
@@ -838,7 +828,7 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
                 slot = 0;
                 for (int i = 0; i < got; ++i) {
                     const uint32_t wi = sid[i];
-                    const float ki = w_key32(skey[i], (int)((wi >> kChiShift) & 7u), mq, a.w);
+                    const float ki = w_key32(skey[i], (int)((wi >> kChiShift) & kChiMask), mq, a.w);
                     slot += lt_key(ki, wi & kIdMask, kj, ij) ? 1 : 0;
                 }
             }

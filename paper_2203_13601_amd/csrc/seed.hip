@@ -22,12 +22,6 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-__device__ __forceinline__ int chi_of(uint32_t a, uint32_t qword, uint32_t qmask)
-{
-    uint32_t x = (a ^ qword) & qmask;
-    uint32_t y = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;
-    return __popc(y & 0x80808080u);
-}
 
 // 64-entry tiles per key workgroup (measured: 8 beats 1, 2 and 4)
 constexpr int kKeyTiles = 8;
@@ -45,6 +39,8 @@ struct KeyArgs {
     int64_t nq;
     int ne, ne_pad;
     Weights w;            // weight setting of Gamma
+    int abits;            // attribute field width
+    uint32_t hmask;       // high bit of every attribute field
 };
 
 template <int DP>
@@ -84,7 +80,7 @@ __device__ __forceinline__ void store_keys(const KeyArgs &a, const f32x4 (&acc)[
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const float d2 = fmaxf(rn + nb4[r] - 2.0f * acc[s][r], 0.0f);
-            const int c = chi_of(at4[r], qw, qm);
+            const int c = chi_of(at4[r], qw, qm, a.hmask);
             k4[r] = cb0 + r < a.ne ? w_key32(d2, c, (int)mq, a.w) : __int_as_float(0x7F800000);
         }
         *reinterpret_cast<float4 *>(stage + rl * 68 + 16 * s + 4 * lq) = make_float4(k4[0], k4[1], k4[2], k4[3]);
@@ -131,7 +127,7 @@ __global__ __launch_bounds__(256) void k_entry_keys(const KeyArgs a)
     const float4 *qrow = reinterpret_cast<const float4 *>(a.qpad + rowc * DP);
     const float rn = a.qnorm[rowc];
     const uint32_t qw = a.qword[rowc], qm = a.qmask[rowc];
-    const float mq = (float)(__popc(qm) / 8);
+    const float mq = (float)(__popc(qm) / a.abits);
     if (group_exact<DP>(a, rowc))
         return;  // done by k_entry_keys_b16
     float4 ra[K::NT];
@@ -206,7 +202,7 @@ __global__ __launch_bounds__(256) void k_entry_keys_b16(const KeyArgs a)
     const int64_t rowc = row_ok ? row : a.nq - 1;
     const float rn = a.qnorm[rowc];
     const uint32_t qw = a.qword[rowc], qm = a.qmask[rowc];
-    const float mq = (float)(__popc(qm) / 8);
+    const float mq = (float)(__popc(qm) / a.abits);
     constexpr int NB = DP / 32;   // 32-element chunks
     constexpr int LDSB = DP + 8;  // row stride in LDS (elements)
     if (!group_exact<DP>(a, rowc))
@@ -335,7 +331,7 @@ int launch_seed_rank(const Index *ix, const float *qpad, const float *qnorm, con
     if (nj > 128)
         return fail(NHQ_EINVAL, "entry sample larger than 8192");
     KeyArgs a{qpad, qnorm, qword, qmask, ix->entry_vec, ix->entry_norm, ix->entry_attr, ix->entry_bf16,
-              qexact, keys, nq, ne, ne_pad, ix->w};
+              qexact, keys, nq, ne, ne_pad, ix->w, ix->abits, ix->hmask};
     const dim3 grid((unsigned)((nq + 63) / 64), (unsigned)((ne_pad + 64 * kKeyTiles - 1) / (64 * kKeyTiles)));
     int rc = NHQ_OK;
     switch (ix->dp) {

@@ -26,12 +26,6 @@ __device__ __forceinline__ void wsync()
     __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ int chi_full(uint32_t a, uint32_t b, uint32_t mask)
-{
-    uint32_t x = (a ^ b) & mask;
-    uint32_t y = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;
-    return __popc(y & 0x80808080u);
-}
 
 __device__ __forceinline__ bool lt64(double ka, uint32_t ia, double kb, uint32_t ib)
 {
@@ -50,7 +44,7 @@ struct SShape {
 // delta^2 * (m + chi)^2, and delta^2 when m = 0).
 template <int DP>
 __device__ void exact_keys(const float *vec32, const uint32_t *attr, uint32_t cattr,
-                           uint32_t mask, int m, const Weights &w,
+                           uint32_t mask, uint32_t hmask, int m, const Weights &w,
                            const float4 (&qv)[SShape<DP>::NCH], const uint32_t *ids, double *out,
                            int n)
 {
@@ -82,7 +76,7 @@ __device__ void exact_keys(const float *vec32, const uint32_t *attr, uint32_t ca
         for (int o = S::G / 2; o > 0; o >>= 1)
             d2 += __shfl_xor(d2, o, 64);
         if (j < n && g == 0) {
-            const int c = chi_full(attr[id], cattr, mask);
+            const int c = chi_of(attr[id], cattr, mask, hmask);
             out[j] = w_key64(d2, c, m, w);
         }
     }
@@ -140,8 +134,8 @@ __device__ void sort_pairs(double *k, uint32_t *id, int n)
 // Greedy landing-zone walk over sorted candidates ck/ci[0..nc); the chosen
 // ids go to sel[0..), returns their count (<= R).
 template <int DP>
-__device__ int landing_walk(const float *vec32, const uint32_t *attr, uint32_t mask, int m,
-                            const Weights &w, const double *ck, const uint32_t *ci, int nc, int R,
+__device__ int landing_walk(const float *vec32, const uint32_t *attr, uint32_t mask, uint32_t hmask,
+                            int m, const Weights &w, const double *ck, const uint32_t *ci, int nc, int R,
                             uint32_t *sel, double *scratch)
 {
     const int lane = threadIdx.x & 63;
@@ -152,7 +146,7 @@ __device__ int landing_walk(const float *vec32, const uint32_t *attr, uint32_t m
         bool ok = true;
         if (nsel > 0) {
             load_center<DP>(vec32, p, pv);
-            exact_keys<DP>(vec32, attr, attr[p], mask, m, w, pv, sel, scratch, nsel);
+            exact_keys<DP>(vec32, attr, attr[p], mask, hmask, m, w, pv, sel, scratch, nsel);
             wsync();
             const double kpi = ck[t];
             const bool blocked = lane < nsel && !(kpi < scratch[lane]);
@@ -178,6 +172,7 @@ struct SelArgs {
     Weights w;
     int64_t row0;   // rows row0 .. row0 + nrows - 1 (cand holds their lists)
     int64_t nrows;
+    int abits;      // attribute field width
 };
 
 template <int DP>
@@ -193,7 +188,8 @@ __global__ __launch_bounds__(64) void k_select(const SelArgs a)
     double *scratch = ck + a.K;                         // [64]
     uint32_t *ci = reinterpret_cast<uint32_t *>(scratch + 64);  // [K]
     uint32_t *sel = ci + a.K;                           // [64]
-    const uint32_t mask = a.m >= 4 ? 0xFFFFFFFFu : ((1u << (8 * a.m)) - 1u);
+    const uint32_t mask = attr_full_mask(a.m, a.abits);
+    const uint32_t hmask = attr_hmask(a.abits);
 
     int nc = 0;
     for (int e0 = 0; e0 < a.K; e0 += 64) {
@@ -208,11 +204,11 @@ __global__ __launch_bounds__(64) void k_select(const SelArgs a)
     wsync();
     float4 qv[SShape<DP>::NCH];
     load_center<DP>(a.vec32, i, qv);
-    exact_keys<DP>(a.vec32, a.attr, a.attr[i], mask, a.m, a.w, qv, ci, ck, nc);
+    exact_keys<DP>(a.vec32, a.attr, a.attr[i], mask, hmask, a.m, a.w, qv, ci, ck, nc);
     wsync();
     sort_pairs<4>(ck, ci, nc);
     const int nl = min(nc, a.l);
-    const int ns = landing_walk<DP>(a.vec32, a.attr, mask, a.m, a.w, ck, ci, nl, a.R, sel, scratch);
+    const int ns = landing_walk<DP>(a.vec32, a.attr, mask, hmask, a.m, a.w, ck, ci, nl, a.R, sel, scratch);
     for (int e = lane; e < a.R; e += 64)
         a.adj[i * a.R + e] = e < ns ? (int32_t)sel[e] : -1;
 }
@@ -233,6 +229,7 @@ struct RevArgs {
     Weights w;
     const int32_t *targets;  // nullable: re-select these rows only (t -> row)
     int64_t nt;              // rows re-selected (grid)
+    int abits;               // attribute field width
 };
 
 template <int DP>
@@ -246,7 +243,8 @@ __global__ __launch_bounds__(64) void k_reverse(const RevArgs a)
     extern __shared__ __align__(16) uint32_t smem[];
     double *scratch = reinterpret_cast<double *>(smem);          // [64]
     uint32_t *sel = reinterpret_cast<uint32_t *>(scratch + 64);  // [64]
-    const uint32_t mask = a.m >= 4 ? 0xFFFFFFFFu : ((1u << (8 * a.m)) - 1u);
+    const uint32_t mask = attr_full_mask(a.m, a.abits);
+    const uint32_t hmask = attr_hmask(a.abits);
     double *pk = a.wk + a.poff[ti];
     uint32_t *pi = a.wi + a.poff[ti];
     const int64_t ninc = a.off[ti + 1] - a.off[ti];
@@ -274,7 +272,7 @@ __global__ __launch_bounds__(64) void k_reverse(const RevArgs a)
     wsync();
     float4 qv[SShape<DP>::NCH];
     load_center<DP>(a.vec32, j, qv);
-    exact_keys<DP>(a.vec32, a.attr, a.attr[j], mask, a.m, a.w, qv, pi, pk, np);
+    exact_keys<DP>(a.vec32, a.attr, a.attr[j], mask, hmask, a.m, a.w, qv, pi, pk, np);
     __threadfence();
     wsync();
     // landing-zone walk in (key, id) order: extract the next smallest entry
@@ -309,7 +307,7 @@ __global__ __launch_bounds__(64) void k_reverse(const RevArgs a)
         if (nsel > 0) {
             float4 pv[SShape<DP>::NCH];
             load_center<DP>(a.vec32, bi, pv);
-            exact_keys<DP>(a.vec32, a.attr, a.attr[bi], mask, a.m, a.w, pv, sel, scratch, nsel);
+            exact_keys<DP>(a.vec32, a.attr, a.attr[bi], mask, hmask, a.m, a.w, pv, sel, scratch, nsel);
             wsync();
             const bool blocked = lane < nsel && !(bk < scratch[lane]);
             ok = __ballot(blocked) == 0;
@@ -372,7 +370,7 @@ int launch_select(const Index *ix, const int32_t *cand, int K, int l, int32_t *a
 {
     if (K > 256)
         return fail(NHQ_EINVAL, "candidate list longer than 256");
-    SelArgs a{ix->vec32, ix->attr, cand, adj, ix->n, ix->m, K, l, ix->degree, ix->w, 0, ix->n};
+    SelArgs a{ix->vec32, ix->attr, cand, adj, ix->n, ix->m, K, l, ix->degree, ix->w, 0, ix->n, ix->abits};
     switch (ix->dp) {
     case 32: return launch_select_dp<32>(a, st);
     case 64: return launch_select_dp<64>(a, st);
@@ -424,8 +422,8 @@ __global__ __launch_bounds__(64) void k_refine(const RefArgs a)
     float4 qv[SShape<DP>::NCH];
     load_center<DP>(a.qpad, qi, qv);
     // Def. 4 ground truth: exact matches ranked by delta alone
-    exact_keys<DP>(a.vec32, a.attr, 0u, 0u, 0, Weights{NHQ_WEIGHTS_DEFAULT, 0.0f, 0.0}, qv, ci, ck,
-                   nc);
+    exact_keys<DP>(a.vec32, a.attr, 0u, 0u, 0x80808080u, 0, Weights{NHQ_WEIGHTS_DEFAULT, 0.0f, 0.0}, qv,
+                   ci, ck, nc);
     wsync();
     sort_pairs<4>(ck, ci, nc);
     for (int e = lane; e < a.k; e += 64) {
@@ -470,7 +468,7 @@ int launch_select_rows(const Index *ix, const int32_t *cand, int K, int l, int32
         return fail(NHQ_EINVAL, "candidate list longer than 256");
     if (nrows <= 0)
         return NHQ_OK;
-    SelArgs a{ix->vec32, ix->attr, cand, adj, ix->n, ix->m, K, l, ix->degree, ix->w, row0, nrows};
+    SelArgs a{ix->vec32, ix->attr, cand, adj, ix->n, ix->m, K, l, ix->degree, ix->w, row0, nrows, ix->abits};
     switch (ix->dp) {
     case 32: return launch_select_dp<32>(a, st);
     case 64: return launch_select_dp<64>(a, st);
@@ -506,7 +504,8 @@ int launch_reselect_targets(const Index *ix, int32_t *adj, const int32_t *target
     NHQ_HIP(hipMallocAsync((void **)&wk, sizeof(double) * (size_t)poff[nt], st));
     NHQ_HIP(hipMallocAsync((void **)&wi, sizeof(uint32_t) * (size_t)poff[nt], st));
     NHQ_HIP(hipMemcpyAsync(dpoff, poff.data(), sizeof(int64_t) * (size_t)(nt + 1), hipMemcpyHostToDevice, st));
-    RevArgs a{ix->vec32, ix->attr, adj, off, inc, adj, wk, wi, dpoff, ix->n, ix->m, R, ix->w, targets, nt};
+    RevArgs a{ix->vec32, ix->attr, adj, off, inc, adj, wk, wi, dpoff, ix->n, ix->m, R, ix->w, targets, nt,
+              ix->abits};
     int rc = NHQ_OK;
     switch (ix->dp) {
     case 32: rc = launch_reverse_dp<32>(a, st); break;
@@ -559,7 +558,8 @@ int launch_reverse(const Index *ix, const int32_t *fwd, int32_t *adj, hipStream_
     NHQ_HIP(hipMemcpyAsync(off, h.data(), sizeof(int64_t) * (size_t)(n + 1), hipMemcpyHostToDevice, st));
     NHQ_HIP(hipMemcpyAsync(dpoff, poff.data(), sizeof(int64_t) * (size_t)(n + 1), hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_fill_incoming, dim3(grid), dim3(256), 0, st, fwd, n, R, off, fill, inc);
-    RevArgs a{ix->vec32, ix->attr, fwd, off, inc, adj, wk, wi, dpoff, n, ix->m, R, ix->w, nullptr, n};
+    RevArgs a{ix->vec32, ix->attr, fwd, off, inc, adj, wk, wi, dpoff, n, ix->m, R, ix->w, nullptr, n,
+              ix->abits};
     int rc = NHQ_OK;
     switch (ix->dp) {
     case 32: rc = launch_reverse_dp<32>(a, st); break;

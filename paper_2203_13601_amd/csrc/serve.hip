@@ -112,10 +112,11 @@ __device__ void doorbell(const ServeArgs &s, unsigned long long t_end)
 // rows (lane per entry, four entries per pass), as bit patterns into kb.
 template <int DP>
 __device__ void entry_keys_wave(const float *ev, const uint32_t *ea, int ne, const float *qlds,
-                                uint32_t qword, uint32_t qmask, const Weights &w, uint32_t *kb)
+                                uint32_t qword, uint32_t qmask, const Weights &w, int abits,
+                                uint32_t hmask, uint32_t *kb)
 {
     const int lane = threadIdx.x & 63;
-    const int mq = __popc(qmask) / 8;
+    const int mq = __popc(qmask) / abits;
     const float4 *q4 = reinterpret_cast<const float4 *>(qlds);
     for (int e0 = 0; e0 < ne; e0 += 256) {
         const float4 *row[4];
@@ -143,7 +144,7 @@ __device__ void entry_keys_wave(const float *ev, const uint32_t *ea, int ne, con
         for (int r = 0; r < 4; ++r) {
             const int e = e0 + 64 * r + lane;
             if (e < ne)
-                kb[e] = __float_as_uint(w_key32(acc[r], chi_of(ea[e], qword, qmask), mq, w));
+                kb[e] = __float_as_uint(w_key32(acc[r], chi_of(ea[e], qword, qmask, hmask), mq, w));
         }
     }
 }
@@ -237,7 +238,7 @@ __global__ __launch_bounds__(64) void k_serve(const SearchArgs base, const Serve
 
         // seed set: the n_cand best of the entry sample, then as in the batch search
         entry_keys_wave<DP>(base.entry_vec_f, base.entry_attr, base.n_entry, qlds, qword, qmask,
-                            base.w, kb);
+                            base.w, base.abits, base.hmask, kb);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         select_lds(kb, base.n_entry, s.n_cand, cv, cp, seedpos);
@@ -536,6 +537,8 @@ int nhq_server_create(nhq_index *h, const nhq_server_params *pp, nhq_server **ou
     base.n_init = p.n_init;
     base.expand = p.expand;
     base.w = ix->w;
+    base.abits = ix->abits;
+    base.hmask = ix->hmask;
     base.stop_logit = s.stop_logit;
     base.cap_factor = p.cap_factor;
     base.mlp = reinterpret_cast<const uint16_t *>(ix->mlp);
@@ -657,13 +660,7 @@ int nhq_server_submit(nhq_server *h, const float *q, const uint8_t *qattr, int32
     r.flags = (flags & NHQ_SERVE_RAW) | (learned ? kReqLearned : 0);
     r.rerank_n = s.p.rerank > 0 ? std::min(s.p.rerank * k, beam) : 0;
     r.max_hops = s.p.max_hops;
-    for (int i = 0; i < ix->m; ++i) {
-        const uint32_t code = qattr[i];
-        if (code != 0xFFu) {
-            r.qword |= code << (8 * i);
-            r.qmask |= 0xFFu << (8 * i);
-        }
-    }
+    attr_pack_query(qattr, ix->m, ix->abits, r.qword, r.qmask);
     uint8_t *rec = c.ring + slot * (size_t)s.rec_bytes;
     memcpy(rec, &r, sizeof r);
     memcpy(rec + sizeof r, q, sizeof(float) * (size_t)ix->d);
