@@ -115,6 +115,8 @@ typedef struct {
                               (1: one at a time)                       [10000] */
     int32_t nsw_beam;      /* NSW insertion: beam of each insertion search
                               (>= cand)                                 [cand] */
+    int64_t capacity;      /* rows the index can hold: nhq_index_insert
+                              appends up to capacity - n objects           [n] */
 } nhq_build_params;
 
 #define NHQ_BUILD_EXACT 0
@@ -153,6 +155,17 @@ typedef struct {
 int nhq_nndescent_lists(const nhq_index *ix, int32_t l, int32_t s, int32_t rounds,
                         double stop_frac, uint64_t seed, int32_t *ids, int64_t *updates,
                         int32_t *rounds_run, void *stream);
+
+/* Incremental insertion (NPG_nsw, Sec. 4.3): appends nb objects (DEVICE
+ * float32 [nb][d], DEVICE uint8 codes [nb][m]) as ids n .. n + nb - 1 and
+ * links them into the graph exactly as the NSW build's later batches do
+ * (batches of nsw_batch, insertion beam nsw_beam, the index's seed).  Needs
+ * a graph, n + nb <= capacity, and codes that fit the index's packed fields
+ * (NHQ_EINVAL otherwise; nothing changes then).  The entry sample and the
+ * per-code statistics keep the values of the objects present at creation.
+ * Synchronises the stream per batch. */
+int nhq_index_insert(nhq_index *ix, const float *vecs, const uint8_t *attrs, int64_t nb,
+                     void *stream);
 
 /* Rounds the last NN-descent build of the index ran (0 for an exact build). */
 int nhq_index_build_report(const nhq_index *ix, int32_t *nnd_rounds_run);

@@ -81,6 +81,9 @@ def lib():
         L.or_nndescent.argtypes = [P, P, i64, i32, i32, i32, i32, i32, ctypes.c_uint64, i32, P, P, i32]
         L.or_select_lists.restype = None
         L.or_select_lists.argtypes = [P, P, i64, i32, i32, P, i32, i32, P, i32]
+        L.or_nsw_insert.restype = None
+        L.or_nsw_insert.argtypes = [P, P, i64, i32, i32, i32, i32, i64, i64, i32, ctypes.c_uint64, P,
+                                    i32]
         L.or_build_nsw.restype = None
         L.or_build_nsw.argtypes = [P, P, i64, i32, i32, i32, i32, i64, i32, ctypes.c_uint64, P, i32]
         L.or_set_weights.restype = None
@@ -233,6 +236,21 @@ def build_nsw(x, attrs, l: int, R: int, batch: int, beam: int, seed: int,
     adj = np.empty((n, R), dtype=np.int32)
     lib().or_build_nsw(_p(x), _p(attrs), n, d, m, int(l), int(R), int(batch), int(beam),
                        ctypes.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), _p(adj), _threads(threads))
+    return adj
+
+
+def nsw_insert(x, attrs, adj_prefix, l: int, batch: int, beam: int, seed: int,
+               threads: Optional[int] = None) -> np.ndarray:
+    """Insertion of the rows after the prefix graph adj_prefix [s0, R] into
+    it, in batches (the later batches of build_nsw).  Returns adj [n, R]."""
+    x, attrs = _f32(x), _u8(attrs)
+    n, d = x.shape
+    m = attrs.shape[1]
+    s0, R = adj_prefix.shape
+    adj = np.full((n, R), -1, dtype=np.int32)
+    adj[:s0] = adj_prefix
+    lib().or_nsw_insert(_p(x), _p(attrs), n, d, m, int(l), int(R), int(s0), int(batch), int(beam),
+                        ctypes.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), _p(adj), _threads(threads))
     return adj
 
 

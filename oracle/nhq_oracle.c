@@ -666,6 +666,9 @@ static void nsw_reverse(const float *x, const uint8_t *attrs, int64_t n, int d, 
  * Each new row is selected from its candidates (Sec. 4.1), then every vertex
  * it names re-selects its own row with the new vertex offered.  B = 1 is
  * one-at-a-time insertion. */
+void or_nsw_insert(const float *x, const uint8_t *attrs, int64_t n, int d, int m, int l, int R,
+                   int64_t s0, int64_t B, int L, uint64_t seed, int32_t *adj, int nthreads);
+
 void or_build_nsw(const float *x, const uint8_t *attrs, int64_t n, int d, int m, int l, int R,
                   int64_t B, int L, uint64_t seed, int32_t *adj, int nthreads)
 {
@@ -690,13 +693,23 @@ void or_build_nsw(const float *x, const uint8_t *attrs, int64_t n, int d, int m,
         }
         nsw_reverse(x, attrs, n, d, m, R, 0, b0, adj);
     }
+    or_nsw_insert(x, attrs, n, d, m, l, R, b0, B, L, seed, adj, nthreads);
+}
+
+/* Vertices s0 .. n - 1 (their rows -1) enter the graph of the vertices
+ * below s0 in batches of B, as the later batches of or_build_nsw do. */
+void or_nsw_insert(const float *x, const uint8_t *attrs, int64_t n, int d, int m, int l, int R,
+                   int64_t s0, int64_t B, int L, uint64_t seed, int32_t *adj, int nthreads)
+{
+    if (s0 < 1)
+        return;
     int32_t *cand = (int32_t *)malloc(sizeof(int32_t) * (size_t)(B * l + 1));
     double *gam = (double *)malloc(sizeof(double) * (size_t)(B * l + 1));
     int64_t *ndc = (int64_t *)malloc(sizeof(int64_t) * (size_t)(B + 1));
     int64_t *hops = (int64_t *)malloc(sizeof(int64_t) * (size_t)(B + 1));
     int32_t *flag = (int32_t *)malloc(sizeof(int32_t) * (size_t)(B + 1));
     int32_t seeds[256];
-    for (int64_t s = b0; s < n; s += B) {
+    for (int64_t s = s0; s < n; s += B) {
         int64_t nb = (n - s) < B ? (n - s) : B;
         int ns = 0;
         uint64_t st = seed;

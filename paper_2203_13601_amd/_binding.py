@@ -35,7 +35,8 @@ class BuildParams(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("weight_param", ctypes.c_double),
                 ("builder", ctypes.c_int32), ("nnd_rounds", ctypes.c_int32),
                 ("nnd_sample", ctypes.c_int32), ("nnd_stop", ctypes.c_float),
-                ("nsw_batch", ctypes.c_int32), ("nsw_beam", ctypes.c_int32)]
+                ("nsw_batch", ctypes.c_int32), ("nsw_beam", ctypes.c_int32),
+                ("capacity", ctypes.c_int64)]
 
 
 class Trace(ctypes.Structure):
@@ -88,6 +89,7 @@ def lib() -> ctypes.CDLL:
         "nhq_index_build_graph": ([P, P], i32),
         "nhq_nndescent_lists": ([P, i32, i32, i32, ctypes.c_double, ctypes.c_uint64, P, P, P, P], i32),
         "nhq_index_build_report": ([P, P], i32),
+        "nhq_index_insert": ([P, P, P, i64, P], i32),
         "nhq_build_index": ([P, P, i64, i32, i32, P, P, P], i32),
         "nhq_index_set_graph": ([P, P, i32, P], i32),
         "nhq_index_get_graph": ([P, P, P], i32),
@@ -180,14 +182,14 @@ BUILDERS = {"exact": 0, "nndescent": 1, "nsw": 2}
 
 def _params(degree=32, cand=64, reverse_edges=False, storage="fp32", n_entry=1024, seed=0,
             weights="default", weight_param=0.0, builder="exact", nnd_rounds=0, nnd_sample=0,
-            nnd_stop=0.0, nsw_batch=0, nsw_beam=0):
+            nnd_stop=0.0, nsw_batch=0, nsw_beam=0, capacity=0):
     return BuildParams(int(degree), int(cand), int(bool(reverse_edges)),
                        STORAGE[storage] if isinstance(storage, str) else int(storage),
                        int(n_entry), WEIGHTS[weights] if isinstance(weights, str) else int(weights),
                        int(seed), float(weight_param),
                        BUILDERS[builder] if isinstance(builder, str) else int(builder),
                        int(nnd_rounds), int(nnd_sample), float(nnd_stop), int(nsw_batch),
-                       int(nsw_beam))
+                       int(nsw_beam), int(capacity))
 
 
 def nhq_index_create(vecs: torch.Tensor, attrs: torch.Tensor, stream=None, **params) -> Index:
@@ -217,6 +219,16 @@ def nhq_nndescent_lists(ix: Index, l: int, s: int, rounds: int, seed: int, stop_
                                      upd.ctypes.data, ctypes.byref(done), _stream(stream)),
            "nhq_nndescent_lists")
     return ids, upd[:done.value], done.value
+
+
+def nhq_index_insert(ix: Index, vecs: torch.Tensor, attrs: torch.Tensor, stream=None) -> None:
+    """Append objects (ids n .. n + nb - 1) and link them in by NSW insertion."""
+    vecs = _dev(vecs, torch.float32, "vecs", 2)
+    attrs = _dev(attrs, torch.uint8, "attrs", 2)
+    if attrs.shape[0] != vecs.shape[0]:
+        raise ValueError("vecs and attrs differ in rows")
+    _check(lib().nhq_index_insert(ix.handle, vecs.data_ptr(), attrs.data_ptr(), vecs.shape[0],
+                                  _stream(stream)), "nhq_index_insert")
 
 
 def nhq_index_build_report(ix: Index) -> dict:

@@ -326,6 +326,10 @@ int nhq_index_create(const float *vecs, const uint8_t *attrs, int64_t n, int32_t
         p.nsw_batch = 10000;
     if (p.nsw_beam == 0)
         p.nsw_beam = p.cand;
+    if (p.capacity == 0)
+        p.capacity = n;
+    if (p.capacity < n || p.capacity >= kMaxN)
+        return fail(NHQ_EINVAL, "capacity must be in [n, 2^27)");
     if (p.builder < NHQ_BUILD_EXACT || p.builder > NHQ_BUILD_NSW)
         return fail(NHQ_EINVAL, "builder must be an NHQ_BUILD_* value");
     if (p.nsw_batch < 1 || p.nsw_beam < p.cand || p.nsw_beam > NHQ_MAX_BEAM)
@@ -364,21 +368,23 @@ int nhq_index_create(const float *vecs, const uint8_t *attrs, int64_t n, int32_t
         ix->nsw_batch = p.nsw_batch;
         ix->nsw_beam = p.nsw_beam;
         ix->degree = 0;
+        ix->cap = p.capacity;
         const int want_degree = p.degree;
         const size_t rows = (size_t)n * ix->dp;
-        if (hipMalloc(&ix->vec32, rows * sizeof(float)) != hipSuccess ||
-            hipMalloc(&ix->attr, (size_t)n * sizeof(uint32_t)) != hipSuccess ||
-            hipMalloc(&ix->norm, (size_t)n * sizeof(float)) != hipSuccess ||
+        const size_t cap_rows = (size_t)ix->cap * ix->dp;
+        if (hipMalloc(&ix->vec32, cap_rows * sizeof(float)) != hipSuccess ||
+            hipMalloc(&ix->attr, (size_t)ix->cap * sizeof(uint32_t)) != hipSuccess ||
+            hipMalloc(&ix->norm, (size_t)ix->cap * sizeof(float)) != hipSuccess ||
             hipMalloc(&ix->err, 2 * sizeof(uint32_t)) != hipSuccess) {
             rc = fail(NHQ_ENOMEM, "index allocation failed");
             break;
         }
         ix->degree = want_degree;  // graph allocated now, filled by build/set
-        if (hipMalloc(&ix->adj, (size_t)n * want_degree * sizeof(int32_t)) != hipSuccess) {
+        if (hipMalloc(&ix->adj, (size_t)ix->cap * want_degree * sizeof(int32_t)) != hipSuccess) {
             rc = fail(NHQ_ENOMEM, "graph allocation failed");
             break;
         }
-        if (hipMemsetAsync(ix->adj, 0xFF, (size_t)n * want_degree * sizeof(int32_t), st) != hipSuccess ||
+        if (hipMemsetAsync(ix->adj, 0xFF, (size_t)ix->cap * want_degree * sizeof(int32_t), st) != hipSuccess ||
             hipMemsetAsync(ix->err, 0, 2 * sizeof(uint32_t), st) != hipSuccess) {
             rc = fail(NHQ_EHIP, "memset failed");
             break;
@@ -435,15 +441,15 @@ int nhq_index_create(const float *vecs, const uint8_t *attrs, int64_t n, int32_t
         if (ix->storage == NHQ_STORAGE_FP32) {
             ix->vecs = ix->vec32;
         } else if (ix->storage == NHQ_STORAGE_BF16) {
-            if (hipMalloc(&ix->vecs, rows * sizeof(uint16_t)) != hipSuccess) {
+            if (hipMalloc(&ix->vecs, cap_rows * sizeof(uint16_t)) != hipSuccess) {
                 rc = fail(NHQ_ENOMEM, "bf16 storage allocation failed");
                 break;
             }
             hipLaunchKernelGGL(k_to_bf16, dim3(grid_for((int64_t)rows, 256)), dim3(256), 0, st,
                                ix->vec32, (uint16_t *)ix->vecs, (int64_t)rows);
         } else {
-            if (hipMalloc(&ix->vecs, rows) != hipSuccess ||
-                hipMalloc(&ix->scale, (size_t)n * sizeof(float)) != hipSuccess) {
+            if (hipMalloc(&ix->vecs, cap_rows) != hipSuccess ||
+                hipMalloc(&ix->scale, (size_t)ix->cap * sizeof(float)) != hipSuccess) {
                 rc = fail(NHQ_ENOMEM, "fp8 storage allocation failed");
                 break;
             }
@@ -543,13 +549,66 @@ int nhq_index_set_graph(nhq_index *h, const int32_t *adj, int32_t degree, void *
         if (ix->adj)
             NHQ_HIP(hipFree(ix->adj));
         ix->adj = nullptr;
-        if (hipMalloc(&ix->adj, (size_t)ix->n * degree * sizeof(int32_t)) != hipSuccess)
+        if (hipMalloc(&ix->adj, (size_t)ix->cap * degree * sizeof(int32_t)) != hipSuccess)
             return fail(NHQ_ENOMEM, "graph allocation failed");
         ix->degree = degree;
+        if (ix->cap > ix->n)
+            NHQ_HIP(hipMemsetAsync(ix->adj + ix->n * degree, 0xFF,
+                                   (size_t)(ix->cap - ix->n) * degree * sizeof(int32_t), st));
     }
     NHQ_HIP(hipMemcpyAsync(ix->adj, adj, (size_t)ix->n * degree * sizeof(int32_t),
                            hipMemcpyDeviceToDevice, st));
     return NHQ_OK;
+}
+
+int nhq_index_insert(nhq_index *h, const float *vecs, const uint8_t *attrs, int64_t nb, void *stream)
+{
+    if (!h)
+        return fail(NHQ_EINVAL, "null index");
+    Index *ix = &h->impl;
+    if (nb < 0)
+        return fail(NHQ_EINVAL, "nb must be >= 0");
+    if (nb == 0)
+        return NHQ_OK;
+    if (!vecs || (ix->m > 0 && !attrs))
+        return fail(NHQ_EINVAL, "vecs/attrs is null");
+    if (ix->n + nb > ix->cap)
+        return fail(NHQ_EINVAL, "insertion beyond the index's capacity");
+    if (ix->degree < 1)
+        return fail(NHQ_EINVAL, "the index has no graph");
+    hipStream_t st = (hipStream_t)stream;
+    const int m = ix->m, d = ix->d, dp = ix->dp;
+    if (m > 0) {
+        std::vector<uint8_t> hc((size_t)nb * m);
+        NHQ_HIP(hipMemcpyAsync(hc.data(), attrs, hc.size(), hipMemcpyDeviceToHost, st));
+        NHQ_HIP(hipStreamSynchronize(st));
+        int mx = 0;
+        for (uint8_t c : hc)
+            mx = std::max(mx, (int)c);
+        if (mx == 255 || mx + 2 > (1 << ix->abits))
+            return fail(NHQ_EINVAL, "attribute code too wide for the index's packed fields");
+    }
+    const int64_t s0 = ix->n;
+    const size_t rows = (size_t)nb * dp;
+    hipLaunchKernelGGL(k_pad_copy, dim3(grid_for((int64_t)rows, 256)), dim3(256), 0, st, vecs,
+                       ix->vec32 + s0 * dp, nb, d, dp);
+    if (m > 0)
+        hipLaunchKernelGGL(k_pack_attr, dim3(grid_for(nb, 256)), dim3(256), 0, st, attrs, ix->attr + s0,
+                           nb, m, ix->abits);
+    else
+        NHQ_HIP(hipMemsetAsync(ix->attr + s0, 0, (size_t)nb * sizeof(uint32_t), st));
+    hipLaunchKernelGGL(k_row_norm, dim3(grid_for(nb, 256)), dim3(256), 0, st, ix->vec32 + s0 * dp,
+                       ix->norm + s0, nb, dp);
+    if (ix->storage == NHQ_STORAGE_BF16)
+        hipLaunchKernelGGL(k_to_bf16, dim3(grid_for((int64_t)rows, 256)), dim3(256), 0, st,
+                           ix->vec32 + s0 * dp, (uint16_t *)ix->vecs + s0 * dp, (int64_t)rows);
+    else if (ix->storage == NHQ_STORAGE_FP8)
+        hipLaunchKernelGGL(k_to_fp8, dim3(grid_for(nb, 1)), dim3(64), 0, st, ix->vec32 + s0 * dp,
+                           (uint8_t *)ix->vecs + s0 * dp, ix->scale + s0, nb, dp);
+    NHQ_HIP(hipGetLastError());
+    ix->n = s0 + nb;
+    return nsw_insert(ix, s0, s0 + nb, ix->cand, ix->nsw_batch, std::max(ix->nsw_beam, ix->cand), ix->seed,
+                      st);
 }
 
 int nhq_index_get_graph(const nhq_index *h, int32_t *adj_out, void *stream)

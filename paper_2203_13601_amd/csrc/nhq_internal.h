@@ -42,6 +42,7 @@ int padded_dim(int d);
 struct Index {
     int device = 0;
     int64_t n = 0;
+    int64_t cap = 0;  // rows allocated (n <= cap; nhq_index_insert appends)
     int d = 0, dp = 0, m = 0;
     int degree = 0;  // 0 until a graph exists
     int storage = NHQ_STORAGE_FP32;
@@ -86,6 +87,8 @@ int ensure_workspace(Index *ix, size_t bytes);
 
 // NPG_nsw by batched insertion (nsw.hip)
 int nsw_build(Index *ix, int l, int64_t B, int L, uint64_t seed, hipStream_t st);
+int nsw_insert(Index *ix, int64_t s0, int64_t s1, int l, int64_t B, int L, uint64_t seed,
+               hipStream_t st);
 
 // NN-descent candidate lists (nndescent.hip)
 int nnd_lists(const Index *ix, int l, int s, int rounds, double stop_frac, uint64_t seed,

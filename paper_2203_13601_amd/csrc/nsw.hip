@@ -82,7 +82,7 @@ int nsw_build(Index *ix, int l, int64_t B, int L, uint64_t seed, hipStream_t st)
 {
     const int64_t n = ix->n;
     const int R = ix->degree;
-    const int d = ix->d, m = ix->m, dp = ix->dp;
+    const int m = ix->m, dp = ix->dp;
     if (B < 1 || L < l || l < 1 || L > NHQ_MAX_BEAM)
         return fail(NHQ_EINVAL, "NSW build needs batch >= 1 and 1 <= l <= beam <= 1024");
     NHQ_HIP(hipMemsetAsync(ix->adj, 0xFF, sizeof(int32_t) * (size_t)n * R, st));
@@ -104,8 +104,23 @@ int nsw_build(Index *ix, int l, int64_t B, int L, uint64_t seed, hipStream_t st)
     }
     if (rc != NHQ_OK || b0 == n)
         return rc;
-    // ---- later batches: searches of the graph built so far
-    const int64_t bmax = std::min(B, n - b0);
+    return nsw_insert(ix, b0, n, l, B, L, seed, st);
+}
+
+// Vertices s0 .. s1 - 1 (rows already in the index, no edges yet) enter the
+// graph of the vertices below s0, in batches of B: each batch searches the
+// graph built so far for its candidates, selects its rows, and every vertex a
+// new row names re-selects its own row with the new vertex offered.
+int nsw_insert(Index *ix, int64_t s0, int64_t s1, int l, int64_t B, int L, uint64_t seed,
+               hipStream_t st)
+{
+    const int d = ix->d, m = ix->m, dp = ix->dp;
+    if (s0 < 1 || s1 <= s0)
+        return s1 == s0 ? NHQ_OK : fail(NHQ_EINVAL, "insertion needs a non-empty graph");
+    if (B < 1 || L < l || l < 1 || L > NHQ_MAX_BEAM)
+        return fail(NHQ_EINVAL, "insertion needs batch >= 1 and 1 <= l <= beam <= 1024");
+    int rc = NHQ_OK;
+    const int64_t bmax = std::min(B, s1 - s0);
     float *q = nullptr, *dist = nullptr;
     uint8_t *qa = nullptr;
     int32_t *cand = nullptr, *ent = nullptr, *pos = nullptr;
@@ -120,8 +135,8 @@ int nsw_build(Index *ix, int l, int64_t B, int L, uint64_t seed, hipStream_t st)
         hpos[(size_t)t] = t;
     NHQ_HIP(hipMemcpyAsync(pos, hpos.data(), sizeof(int32_t) * 256, hipMemcpyHostToDevice, st));
     std::vector<int32_t> seeds;
-    for (int64_t s = b0; s < n && rc == NHQ_OK; s += B) {
-        const int64_t nb = std::min(B, n - s);
+    for (int64_t s = s0; s < s1 && rc == NHQ_OK; s += B) {
+        const int64_t nb = std::min(B, s1 - s);
         // entry sample of the inserted vertices
         const int want = (int)std::min<int64_t>(s, 256);
         seeds.clear();

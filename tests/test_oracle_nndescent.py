@@ -137,3 +137,13 @@ def test_nsw_batches_see_only_earlier_vertices(small):
     for i in range(900, 1200):
         assert (adj[i][adj[i] >= 0] < 1200).all()
         assert (adj[i][adj[i] >= 0] < 900).all()
+
+
+def test_nsw_insert_continues_the_build(small):
+    # inserting the rest of the set into an NSW graph of a batch-aligned
+    # prefix is the NSW build of the whole set
+    w = small
+    n0, B = 900, 300
+    pre = oracle.build_nsw(w.x[:n0], w.attrs[:n0], 16, 8, B, 32, 6)
+    got = oracle.nsw_insert(w.x, w.attrs, pre, 16, B, 32, 6)
+    assert np.array_equal(got, oracle.build_nsw(w.x, w.attrs, 16, 8, B, 32, 6))
