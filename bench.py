@@ -256,45 +256,64 @@ def main():
         nhq.nhq_index_set_graph(ixb, nhq.nhq_index_get_graph(ix))
         tq_np, tqa_np = synth.config2_train_queries(20_000)
         tq, tqa = torch.from_numpy(tq_np).to(dev), torch.from_numpy(tqa_np).to(dev)
-        t0 = time.time()
-        l_train, ce = 64, 8
-        params, info = train_stop_network(ixb, tq, tqa, k, l_train, epochs=30, check_every=ce,
-                                          n_init=args.n_init, expand=args.expand, seed=1)
-        nhq.nhq_mlp_load(ixb, params)
-        torch.cuda.synchronize()
-        train_s = time.time() - t0
-        log("stop network: %d trace samples, trained in %.2fs (loss %.4f)" % (
-            info["samples"], train_s, info["losses"][-1]))
-        lsweep = []
-        lkw = None
-        for cf in (1.0, 1.125, 1.25, 1.5, 1.75, 2.0, 2.5, 3.0):
-            kw = dict(learned=2, stop_threshold=0.9, check_every=ce, cap_factor=cf)
-            p = point(ixb, l_train, elem=2, **kw)
-            p["cap_factor"] = cf
-            lsweep.append(p)
-            log("bf16+learned cap %.2f recall %.4f hops %.1f (p99 %.0f) search %.3fms" % (
-                cf, p["recall"], p["hops"], p["hops_p99"], p["search_ms"]))
-            if p["recall"] >= args.target:
-                lkw = kw
-                break
-        lop = lsweep[-1]
-        if lkw is None:
-            lkw = dict(learned=2, stop_threshold=0.9, check_every=ce, cap_factor=lop["cap_factor"])
+        ce = 8
+        # bf16 with a fixed beam first (same beam as the plain form): the
+        # reference the learned stop has to beat at equal storage
+        bp = point(ixb, beam, elem=2)
         for _ in range(args.warmup):
-            step(ixb, l_train, **lkw)
-        lwall, lrank, lsearch = timed(ixb, l_train, args.steps, **lkw)
-        lvalue = nq * args.steps / lwall
-        log("bf16+learned: %d steps: %.3f ms/step, %.0f QPS" % (args.steps, lwall * 1000 / args.steps, lvalue))
-        forms["bf16_learned"] = {
-            "qps": round(lvalue, 1), "recall": round(lop["recall"], 5), "beam": l_train,
-            "learned_mode": 2, "check_every": ce, "cap_factor": lkw["cap_factor"],
-            "hops_mean": round(lop["hops"], 2), "hops_p99": lop["hops_p99"],
-            "ms_per_step": round(lwall * 1000.0 / args.steps, 4),
-            "search_kernel_avg_ms": round(float(np.mean(lsearch)), 4),
-            "train_samples": info["samples"], "train_s": round(train_s, 2),
-            "speedup_vs_fp32_fixed": round(lvalue / value, 4),
-            "sweep": [{kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in s.items()}
-                      for s in lsweep]}
+            step(ixb, beam)
+        bwall, _, bsearch = timed(ixb, beam, args.steps)
+        forms["bf16_fixed"] = {"qps": round(nq * args.steps / bwall, 1), "recall": round(bp["recall"], 5),
+                               "beam": beam, "ms_per_step": round(bwall * 1000.0 / args.steps, 4),
+                               "search_kernel_avg_ms": round(float(np.mean(bsearch)), 4)}
+        log("bf16 fixed beam %d: recall %.4f, %.0f QPS" % (beam, bp["recall"], forms["bf16_fixed"]["qps"]))
+        # the stop network per training beam; each beam's cap sweep stops at
+        # the first factor that reaches the target; the fastest beam is kept
+        best = None
+        for l_train in (40, 64):
+            t0 = time.time()
+            params, info = train_stop_network(ixb, tq, tqa, k, l_train, epochs=30, check_every=ce,
+                                              n_init=args.n_init, expand=args.expand, seed=1)
+            nhq.nhq_mlp_load(ixb, params)
+            torch.cuda.synchronize()
+            train_s = time.time() - t0
+            log("stop network at beam %d: %d trace samples, trained in %.2fs (loss %.4f)" % (
+                l_train, info["samples"], train_s, info["losses"][-1]))
+            lsweep = []
+            lkw = None
+            for cf in (1.0, 1.125, 1.25, 1.5, 1.75, 2.0, 2.5, 3.0):
+                kw = dict(learned=2, stop_threshold=0.9, check_every=ce, cap_factor=cf)
+                p = point(ixb, l_train, elem=2, **kw)
+                p["cap_factor"] = cf
+                lsweep.append(p)
+                log("bf16+learned beam %d cap %.2f recall %.4f hops %.1f (p99 %.0f) search %.3fms" % (
+                    l_train, cf, p["recall"], p["hops"], p["hops_p99"], p["search_ms"]))
+                if p["recall"] >= args.target:
+                    lkw = kw
+                    break
+            if lkw is None:
+                continue
+            lop = lsweep[-1]
+            for _ in range(args.warmup):
+                step(ixb, l_train, **lkw)
+            lwall, lrank, lsearch = timed(ixb, l_train, args.steps, **lkw)
+            lvalue = nq * args.steps / lwall
+            log("bf16+learned beam %d: %d steps: %.3f ms/step, %.0f QPS" % (
+                l_train, args.steps, lwall * 1000 / args.steps, lvalue))
+            cand_form = {
+                "qps": round(lvalue, 1), "recall": round(lop["recall"], 5), "beam": l_train,
+                "learned_mode": 2, "check_every": ce, "cap_factor": lkw["cap_factor"],
+                "hops_mean": round(lop["hops"], 2), "hops_p99": lop["hops_p99"],
+                "ms_per_step": round(lwall * 1000.0 / args.steps, 4),
+                "search_kernel_avg_ms": round(float(np.mean(lsearch)), 4),
+                "train_samples": info["samples"], "train_s": round(train_s, 2),
+                "speedup_vs_fp32_fixed": round(lvalue / value, 4),
+                "sweep": [{kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in sp.items()}
+                          for sp in lsweep]}
+            if best is None or cand_form["qps"] > best["qps"]:
+                best = cand_form
+        if best is not None:
+            forms["bf16_learned"] = best
 
         # ---- 3. serving: Poisson stream through the continuous-batching server
         ns = args.serve_requests
