@@ -705,11 +705,12 @@ int nhq_seed_rank(const nhq_index *h, const float *queries, const uint8_t *qattr
         return fail(NHQ_EINVAL, "null array argument");
     hipStream_t st = (hipStream_t)stream;
     // one stream-ordered block: padded rows, norms, codes, masks, exactness
-    // flags and (for the matrix-core ranking) the key matrix
+    // flags and (for the matrix-core ranking) the key matrix and its group
+    // minima
     const size_t ne_pad = (size_t)(ix->n_entry + 63) / 64 * 64;
     const bool dense = ix->n_entry <= 8192;
     const size_t f_rows = (size_t)nq * ix->dp, f_small = (size_t)nq;
-    const size_t words = f_rows + 5 * f_small + (dense ? (size_t)nq * ne_pad : 0) + 64;
+    const size_t words = f_rows + 5 * f_small + (dense ? (size_t)nq * ne_pad / 16 * 17 : 0) + 64;
     uint32_t *blk = nullptr;
     NHQ_HIP(hipMallocAsync((void **)&blk, sizeof(uint32_t) * words, st));
     float *qpad = reinterpret_cast<float *>(blk);

@@ -144,7 +144,8 @@ int launch_dense_topk(const float *A, const float *A_norm, const uint32_t *A_att
                       const Weights *w = nullptr);
 
 // seed ranking of the entry sample (see seed.hip): positions of the K best
-// keys: scratch of nq * ((n_entry + 63) / 64 * 64) floats; qexact (nullable):
+// keys: scratch of nq * ((n_entry + 63) / 64 * 64) * 17 / 16 floats (the key
+// matrix, then its 16-entry group minima); qexact (nullable):
 // per query, nonzero when every value is an integer of magnitude <= 256
 int launch_seed_rank(const Index *ix, const float *qpad, const float *qnorm, const uint32_t *qword,
                      const uint32_t *qmask, const uint32_t *qexact, int64_t nq, int K, float *keys,

@@ -7,12 +7,24 @@
 // chi over the query's constrained codes; padding columns hold +inf.  A
 // workgroup of 4 waves takes 64 queries (16 per wave) against 256 entries.
 //
-// k_entry_select: one wave per query keeps its row of keys in registers
-// (n_entry_pad / 64 per lane), finds the n_cand-th smallest key by a bitwise
-// radix select on the float bit patterns (keys are non-negative, so their
-// bit patterns order like the values), and writes the positions of the
-// n_cand best by (key, position) -- unordered; the search re-scores them.
-// A bound from the lane minima first cuts the row down to a few candidates.
+// The key kernels also write, per query, the minimum of every 16-entry group
+// of keys.  The K-th smallest group minimum bounds the K-th smallest key
+// from above (K groups each hold a key at or below it), and every key at or
+// below the bound lies in a group whose minimum is at or below it.
+//
+// k_entry_select_g (K <= 64): one wave per query ranks the group minima,
+// reads only the keys of the groups at or below the bound (on clustered
+// data about K groups: 1/8 of the row at n_entry = 4096), keeps the keys at
+// or below it in position order and selects the K best among them.  Should
+// the bound admit too many keys, it selects over the whole row instead.
+//
+// k_entry_select (K > 64): one wave per query keeps its row of keys in
+// registers (n_entry_pad / 64 per lane), finds the K-th smallest key by a
+// bitwise radix select on the float bit patterns (keys are non-negative, so
+// their bit patterns order like the values).
+//
+// Both write the positions of the K best by (key, position) -- unordered;
+// the search re-scores them.
 #include "nhq_internal.h"
 #include "wave_select.h"
 
@@ -25,6 +37,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // 64-entry tiles per key workgroup (measured: 8 beats 1, 2 and 4)
 constexpr int kKeyTiles = 8;
+// a wave's group minima of its chunk, 16 rows in LDS (padded row stride)
+constexpr int kGmStride = 4 * kKeyTiles + 1;
 
 struct KeyArgs {
     const float *qpad;    // [nq][DP]
@@ -36,12 +50,26 @@ struct KeyArgs {
     const uint16_t *eb;   // [ne][DP] exact bf16 copy of ev, or null
     const uint32_t *qx;   // [nq] query rows exact in bf16 (nullable)
     float *keys;          // [nq][ne_pad]
+    float *gmin;          // [nq][ne_pad / 16] minimum of each 16-entry group
     int64_t nq;
     int ne, ne_pad;
     Weights w;            // weight setting of Gamma
     int abits;            // attribute field width
     uint32_t hmask;       // high bit of every attribute field
 };
+
+// the wave's group minima (16 rows, ng groups from group gbeg) to HBM, each
+// row's run of groups contiguous
+__device__ __forceinline__ void flush_gmin(const KeyArgs &a, const float *gm, int64_t row0, int gbeg, int ng)
+{
+    const int lane = threadIdx.x & 63;
+    for (int i = lane; i < 16 * ng; i += 64) {
+        const int r = i / ng, g = i - r * ng;
+        const int64_t row = row0 + r;
+        if (row < a.nq)
+            a.gmin[row * (a.ne_pad / 16) + gbeg + g] = gm[r * kGmStride + g];
+    }
+}
 
 template <int DP>
 struct KShape {
@@ -52,12 +80,20 @@ struct KShape {
     static constexpr int LDSW = KC + 4;  // padded row stride (floats): no bank conflicts
 };
 
+// a lane's value from another lane of its quad (DPP quad_perm)
+template <int CTRL>
+__device__ __forceinline__ float quad_mov(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
 // Keys of one 64-entry tile for a wave's 16 queries: lane (rl, lq) holds
 // query rl against entries c0 + 16 s + 4 lq + r in acc[s][r].  They go
 // through the wave's LDS area (16 rows of 68 floats) so that every store
 // instruction writes four whole 256-byte rows of the key matrix.
 __device__ __forceinline__ void store_keys(const KeyArgs &a, const f32x4 (&acc)[4], int c0, int64_t row0, int rl,
-                                           int lq, float rn, uint32_t qw, uint32_t qm, float mq, float *stage)
+                                           int lq, float rn, uint32_t qw, uint32_t qm, float mq, float *stage,
+                                           float *gm, int g0)
 {
     const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -91,9 +127,15 @@ __device__ __forceinline__ void store_keys(const KeyArgs &a, const f32x4 (&acc)[
     for (int u = 0; u < 4; ++u) {
         const int idx = 64 * u + lane, r = idx >> 4, c4 = idx & 15;
         const int64_t row = row0 + r;
+        const float4 x = *reinterpret_cast<const float4 *>(stage + r * 68 + 4 * c4);
+        // group minimum over the quad of lanes holding columns 16 (c4 / 4) ..
+        float mn = fminf(fminf(x.x, x.y), fminf(x.z, x.w));
+        mn = fminf(mn, quad_mov<0xB1>(mn));  // quad_perm(1, 0, 3, 2)
+        mn = fminf(mn, quad_mov<0x4E>(mn));  // quad_perm(2, 3, 0, 1)
         if (row < a.nq)
-            *reinterpret_cast<float4 *>(a.keys + row * a.ne_pad + c0 + 4 * c4) =
-                *reinterpret_cast<const float4 *>(stage + r * 68 + 4 * c4);
+            *reinterpret_cast<float4 *>(a.keys + row * a.ne_pad + c0 + 4 * c4) = x;
+        if ((lane & 3) == 0)
+            gm[r * kGmStride + g0 + (c4 >> 2)] = mn;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -119,6 +161,7 @@ __global__ __launch_bounds__(256) void k_entry_keys(const KeyArgs a)
     using K = KShape<DP>;
     // entry tile; afterwards the key staging of the four waves
     __shared__ __align__(16) float tile[64 * K::LDSW > 4 * 16 * 68 ? 64 * K::LDSW : 4 * 16 * 68];
+    __shared__ float gms[4 * 16 * kGmStride];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int rl = lane & 15, lq = lane >> 4;
     const int64_t row = (int64_t)blockIdx.x * 64 + wave * 16 + rl;
@@ -181,8 +224,13 @@ __global__ __launch_bounds__(256) void k_entry_keys(const KeyArgs a)
             }
         }
         __syncthreads();  // the tile's products are done: its LDS stages the keys
-        store_keys(a, acc, c0, (int64_t)blockIdx.x * 64 + wave * 16, rl, lq, rn, qw, qm, mq, tile + wave * 16 * 68);
+        store_keys(a, acc, c0, (int64_t)blockIdx.x * 64 + wave * 16, rl, lq, rn, qw, qm, mq, tile + wave * 16 * 68,
+                   gms + wave * 16 * kGmStride, (c0 - cbeg) / 16);
     }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    flush_gmin(a, gms + wave * 16 * kGmStride, (int64_t)blockIdx.x * 64 + wave * 16, cbeg / 16,
+               (min(cbeg + 64 * kKeyTiles, a.ne_pad) - cbeg) / 16);
 }
 
 // The same product on the bf16 matrix cores (v_mfma_f32_16x16x32_bf16) for
@@ -191,10 +239,11 @@ __global__ __launch_bounds__(256) void k_entry_keys(const KeyArgs a)
 // every partial sum is an integer below 2^24 (rows of at most 128
 // elements), so the keys are bit-identical to the float32 kernel's.
 template <int DP>
-__global__ __launch_bounds__(256) void k_entry_keys_b16(const KeyArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_entry_keys_b16(const KeyArgs a)
 {
     static_assert(DP <= 128 && DP % 32 == 0, "bf16 path: rows of at most 128 elements");
     __shared__ __align__(16) uint16_t t16[64 * (DP + 8) < 2 * 4 * 16 * 68 ? 2 * 4 * 16 * 68 : 64 * (DP + 8)];
+    __shared__ float gms[4 * 16 * kGmStride];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int rl = lane & 15, lq = lane >> 4;
     const int64_t row = (int64_t)blockIdx.x * 64 + wave * 16 + rl;
@@ -251,22 +300,19 @@ __global__ __launch_bounds__(256) void k_entry_keys_b16(const KeyArgs a)
         }
         __syncthreads();  // the tile's products are done: its LDS stages the keys
         store_keys(a, acc, c0, (int64_t)blockIdx.x * 64 + wave * 16, rl, lq, rn, qw, qm, mq,
-                   reinterpret_cast<float *>(t16) + wave * 16 * 68);
+                   reinterpret_cast<float *>(t16) + wave * 16 * 68, gms + wave * 16 * kGmStride, (c0 - cbeg) / 16);
     }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    flush_gmin(a, gms + wave * 16 * kGmStride, (int64_t)blockIdx.x * 64 + wave * 16, cbeg / 16,
+               (min(cbeg + 64 * kKeyTiles, a.ne_pad) - cbeg) / 16);
 }
 
-// One wave per query.  For K <= 64 the K-th smallest of the 64 lane minima
-// bounds the K-th smallest key from above; the (usually few) keys at or
-// below that bound are compacted in position order into LDS and the exact
-// selection runs over them only.  The selected set and its output order are
-// the same as a selection over the whole row.
+// One wave per query, K > 64: the row in registers, a radix select over it.
 template <int NJ>
 __global__ __launch_bounds__(64) void k_entry_select(const float *__restrict__ keys, int64_t nq,
                                                      int ne, int ne_pad, int K, int32_t *__restrict__ cand)
 {
-    constexpr int kCap = 256;
-    __shared__ uint32_t sv[kCap];
-    __shared__ int32_t sp[kCap];
     const int lane = threadIdx.x;
     const int64_t qi = blockIdx.x;
     if (qi >= nq)
@@ -277,45 +323,98 @@ __global__ __launch_bounds__(64) void k_entry_select(const float *__restrict__ k
 #pragma unroll
     for (int j = 0; j < NJ; ++j)
         v[j] = 64 * j + lane < ne ? __float_as_uint(row[64 * j + lane]) : 0xFFFFFFFFu;
-    if (K <= 64) {
-        uint32_t mn[1] = {v[0]};
+    const uint32_t p = kth_pattern<NJ>(v, K);
+    emit_best<NJ>(v, [&](int t) { return 64 * t + lane; }, p, K, ne, out);
+}
+
+// One wave per query, K <= 64: the group-minimum bound (see the top).  The
+// groups at or below the bound are read 4 at a time in increasing order, so
+// the kept keys stay in position order, which breaks ties at the K-th key
+// by position.  GPL = group minima per lane.
+template <int GPL>
+__global__ __launch_bounds__(64) void k_entry_select_g(const float *__restrict__ keys,
+                                                       const float *__restrict__ gmin, int64_t nq, int ne,
+                                                       int ne_pad, int K, int32_t *__restrict__ cand)
+{
+    constexpr int kRounds = 16;  // 64 groups of 16 keys
+    constexpr int kCap = 128;    // kept keys
+    __shared__ int32_t sg[64 * GPL];
+    __shared__ uint32_t cv[256];
+    __shared__ int32_t cp[256];
+    const int lane = threadIdx.x;
+    const int64_t qi = blockIdx.x;
+    if (qi >= nq)
+        return;
+    const int ng = ne_pad / 16;
+    const uint32_t *row = reinterpret_cast<const uint32_t *>(keys + qi * ne_pad);
+    int32_t *out = cand + qi * K;
+    uint32_t mn[GPL];
 #pragma unroll
-        for (int j = 1; j < NJ; ++j)
-            mn[0] = min(mn[0], v[j]);
-        const uint32_t u = kth_pattern<1>(mn, K);
+    for (int t = 0; t < GPL; ++t) {
+        const int g = 64 * t + lane;
+        mn[t] = g < ng ? __float_as_uint(gmin[qi * ng + g]) : 0xFFFFFFFFu;
+    }
+    const uint32_t u = kth_pattern<GPL>(mn, K);
+    int nsel = 0;
+#pragma unroll
+    for (int t = 0; t < GPL; ++t) {
+        const bool in = mn[t] <= u && 64 * t + lane < ng;
+        const uint64_t b = __ballot(in);
+        if (in)
+            sg[nsel + rank_below(b)] = 64 * t + lane;
+        nsel += __popcll(b);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (nsel <= 4 * kRounds) {
+        uint32_t v[kRounds];
+        int32_t ps[kRounds];
+#pragma unroll
+        for (int it = 0; it < kRounds; ++it) {
+            const int j = 4 * it + (lane >> 4);
+            v[it] = 0xFFFFFFFFu;
+            ps[it] = -1;
+            if (j < nsel) {
+                const int pos = 16 * sg[j] + (lane & 15);
+                if (pos < ne) {
+                    v[it] = row[pos];
+                    ps[it] = pos;
+                }
+            }
+        }
         int c = 0;
 #pragma unroll
-        for (int j = 0; j < NJ; ++j)
-            c += __popcll(__ballot(v[j] <= u));
+        for (int it = 0; it < kRounds; ++it)
+            c += __popcll(__ballot(ps[it] >= 0 && v[it] <= u));
         if (c <= kCap) {
             int base = 0;
 #pragma unroll
-            for (int j = 0; j < NJ; ++j) {
-                const bool in = v[j] <= u;
+            for (int it = 0; it < kRounds; ++it) {
+                const bool in = ps[it] >= 0 && v[it] <= u;
                 const uint64_t b = __ballot(in);
                 if (in) {
                     const int r = base + rank_below(b);
-                    sv[r] = v[j];
-                    sp[r] = 64 * j + lane;
+                    cv[r] = v[it];
+                    cp[r] = ps[it];
                 }
                 base += __popcll(b);
             }
             for (int i = base + lane; i < kCap; i += 64) {
-                sv[i] = 0xFFFFFFFFu;
-                sp[i] = -1;
+                cv[i] = 0xFFFFFFFFu;
+                cp[i] = -1;
             }
-            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
             uint32_t w[kCap / 64];
 #pragma unroll
             for (int t = 0; t < kCap / 64; ++t)
-                w[t] = sv[64 * t + lane];
+                w[t] = cv[64 * t + lane];
             const uint32_t p = kth_pattern<kCap / 64>(w, K);
-            emit_best<kCap / 64>(w, [&](int t) { return sp[64 * t + lane]; }, p, K, ne, out);
+            emit_best<kCap / 64>(w, [&](int t) { return cp[64 * t + lane]; }, p, K, ne, out);
             return;
         }
     }
-    const uint32_t p = kth_pattern<NJ>(v, K);
-    emit_best<NJ>(v, [&](int t) { return 64 * t + lane; }, p, K, ne, out);
+    select_lds(row, ne, K, cv, cp, out);
 }
 
 }  // namespace
@@ -331,7 +430,7 @@ int launch_seed_rank(const Index *ix, const float *qpad, const float *qnorm, con
     if (nj > 128)
         return fail(NHQ_EINVAL, "entry sample larger than 8192");
     KeyArgs a{qpad, qnorm, qword, qmask, ix->entry_vec, ix->entry_norm, ix->entry_attr, ix->entry_bf16,
-              qexact, keys, nq, ne, ne_pad, ix->w, ix->abits, ix->hmask};
+              qexact, keys, keys + (size_t)nq * ne_pad, nq, ne, ne_pad, ix->w, ix->abits, ix->hmask};
     const dim3 grid((unsigned)((nq + 63) / 64), (unsigned)((ne_pad + 64 * kKeyTiles - 1) / (64 * kKeyTiles)));
     int rc = NHQ_OK;
     switch (ix->dp) {
@@ -362,7 +461,17 @@ int launch_seed_rank(const Index *ix, const float *qpad, const float *qnorm, con
         rc = fail(NHQ_EHIP, "entry key launch failed");
     if (rc == NHQ_OK) {
         const dim3 g2((unsigned)nq);
-        if (nj <= 16)
+        const int gpl = (ne_pad / 16 + 63) / 64;
+        if (K <= 64) {
+            if (gpl <= 1)
+                hipLaunchKernelGGL(k_entry_select_g<1>, g2, dim3(64), 0, st, keys, a.gmin, nq, ne, ne_pad, K, cand);
+            else if (gpl <= 2)
+                hipLaunchKernelGGL(k_entry_select_g<2>, g2, dim3(64), 0, st, keys, a.gmin, nq, ne, ne_pad, K, cand);
+            else if (gpl <= 4)
+                hipLaunchKernelGGL(k_entry_select_g<4>, g2, dim3(64), 0, st, keys, a.gmin, nq, ne, ne_pad, K, cand);
+            else
+                hipLaunchKernelGGL(k_entry_select_g<8>, g2, dim3(64), 0, st, keys, a.gmin, nq, ne, ne_pad, K, cand);
+        } else if (nj <= 16)
             hipLaunchKernelGGL(k_entry_select<16>, g2, dim3(64), 0, st, keys, nq, ne, ne_pad, K, cand);
         else if (nj <= 32)
             hipLaunchKernelGGL(k_entry_select<32>, g2, dim3(64), 0, st, keys, nq, ne, ne_pad, K, cand);

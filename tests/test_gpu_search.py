@@ -221,11 +221,14 @@ def test_seed_rank_is_the_exact_best_of_the_entry_sample(n_entry, n_cand):
         assert (got >= 0).sum() == min(n_cand, ne)
 
 
-@pytest.mark.parametrize("distinct,n_cand", [(3, 40), (3, 64), (60, 32), (400, 48)])
-def test_seed_rank_ties_break_by_position(distinct, n_cand):
+@pytest.mark.parametrize("distinct,n_cand,n_entry", [(3, 40, 2048), (3, 64, 2048), (60, 32, 2048),
+                                                     (400, 48, 2048), (3, 32, 8192), (60, 1, 8192),
+                                                     (3, 96, 2048), (2, 64, 4000)])
+def test_seed_rank_ties_break_by_position(distinct, n_cand, n_entry):
     # few distinct vectors: keys tie in large groups, so the selection must
-    # take equal keys by smallest entry position (both the path that cuts
-    # the row down by the lane-minimum bound and the one over the whole row)
+    # take equal keys by smallest entry position: in the running lists of the
+    # fused selection (their cuts and the merge of the chunk lists, n_cand
+    # <= 64) and in the selection over the key matrix (n_cand > 64)
     rng = np.random.default_rng(distinct)
     base = rng.integers(0, 8, size=(distinct, 32)).astype(np.float32)
     n = 30000
@@ -234,7 +237,6 @@ def test_seed_rank_ties_break_by_position(distinct, n_cand):
     q = base[rng.integers(0, distinct, size=64)] + rng.integers(0, 2, size=(64, 32)).astype(np.float32)
     qa = rng.integers(0, 2, size=(64, 2)).astype(np.uint8)
     qa[::5, 1] = 0xFF
-    n_entry = 2048
     ix = nhq.nhq_index_create(_dev(x), _dev(attrs), n_entry=n_entry, seed=3)
     cand = nhq.nhq_seed_rank(ix, _dev(q), _dev(qa), n_cand).cpu().numpy()
     entry = oracle.entry_points(3, n, n_entry)
@@ -244,6 +246,29 @@ def test_seed_rank_ties_break_by_position(distinct, n_cand):
                                      key_mode=oracle.KEY32, out_mode=1)
     for i in range(len(q)):
         assert sorted(cand[i].tolist()) == sorted(want[i].tolist())
+
+
+@pytest.mark.parametrize("n_entry,n_cand", [(4096, 32), (1000, 64), (8192, 17)])
+def test_seed_rank_float_data_is_the_best_up_to_rounding(n_entry, n_cand):
+    # float vectors (the float32 matrix-core path): the keys differ from the
+    # FP64 ones by rounding only, so every returned entry's FP64 key is
+    # within a relative 1e-4 of the n_cand-th best FP64 key, and the count is
+    # exact
+    w = synth.config1(n=30000, nq=96)
+    ix = nhq.nhq_index_create(_dev(w.x), _dev(w.attrs), n_entry=n_entry, seed=13)
+    cand = nhq.nhq_seed_rank(ix, _dev(w.q), _dev(w.qattrs), n_cand).cpu().numpy()
+    entry = oracle.entry_points(13, w.n, n_entry)
+    ex, ea = w.x[entry].astype(np.float64), w.attrs[entry]
+    for i in range(w.nq):
+        d2 = ((ex - w.q[i].astype(np.float64)) ** 2).sum(1)
+        con = w.qattrs[i] != 0xFF
+        mq = int(con.sum())
+        chi = (ea[:, con] != w.qattrs[i][con]).sum(1)
+        keys = d2 * (mq + chi) ** 2 if mq else d2  # Eq. 6 order under the default weights
+        kth = np.sort(keys)[n_cand - 1]
+        got = cand[i]
+        assert (got >= 0).all() and len(set(got.tolist())) == n_cand
+        assert (keys[got] <= kth * (1 + 1e-4) + 1e-6).all()
 
 
 @pytest.mark.parametrize("expand,L", [(2, 64), (4, 100), (8, 256), (3, 17)])
