@@ -295,8 +295,10 @@ int nhq_hybrid_search(const nhq_index *ix, const float *queries, const uint8_t *
  * entry sample (Sec. 3.2: seeds are usually drawn at random); this ranks the
  * whole sample for every query by Gamma on the matrix cores and writes the
  * positions (in the entry sample) of the n_cand best, -1 padded, to cand:
- * device int32 [nq][n_cand], 1 <= n_cand <= 144.  Uses stream-ordered
- * temporary allocations.
+ * device int32 [nq][n_cand], 1 <= n_cand <= 144.  Its scratch (about
+ * nq * (4 d + 4.25 n_entry) bytes) lives in the index's workspace, which a
+ * call that needs more than any call before it grows (that call synchronises
+ * the device); nhq_hybrid_search keeps the candidates there too.
  *
  * nhq_search_seeded: the joint-pruning search given those candidates: it
  * re-scores them exactly, starts the pool with the best n_init of them and

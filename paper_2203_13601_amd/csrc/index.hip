@@ -150,8 +150,16 @@ __global__ __launch_bounds__(64) void k_to_fp8(const float *__restrict__ v, uint
     }
 }
 
-// one wave per query: zero-padded float32 row (coalesced), squared norm,
-// packed codes and constraint mask
+// a lane's value from another lane of its 16-lane row (DPP)
+template <int CTRL>
+__device__ __forceinline__ float row_mov(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// 16 lanes per query (4 queries per wave): zero-padded float32 row,
+// squared norm, packed codes and constraint mask, and whether every value
+// is an integer of magnitude <= 256
 __global__ __launch_bounds__(64) void k_pad_queries(const float *__restrict__ q,
                                                     const uint8_t *__restrict__ qa, int64_t nq, int d,
                                                     int dp, int m, int abits, float *__restrict__ qpad,
@@ -160,22 +168,29 @@ __global__ __launch_bounds__(64) void k_pad_queries(const float *__restrict__ q,
                                                     uint32_t *__restrict__ qmask,
                                                     uint32_t *__restrict__ qexact)
 {
-    const int lane = threadIdx.x;
-    for (int64_t i = blockIdx.x; i < nq; i += gridDim.x) {
+    const int lane = threadIdx.x, sub = lane & 15, grp = lane >> 4;
+    for (int64_t i0 = 4 * (int64_t)blockIdx.x; i0 < nq; i0 += 4 * (int64_t)gridDim.x) {
+        const int64_t i = i0 + grp;
+        const bool live = i < nq;
         float s = 0.0f;
         bool exact = true;
-        for (int c = lane; c < dp; c += 64) {
-            const float v = c < d ? q[i * d + c] : 0.0f;
-            qpad[i * dp + c] = v;
-            s = fmaf(v, v, s);
-            exact = exact && v == rintf(v) && fabsf(v) <= 256.0f;
+        if (live) {
+            for (int c = sub; c < dp; c += 16) {
+                const float v = c < d ? q[i * d + c] : 0.0f;
+                qpad[i * dp + c] = v;
+                s = fmaf(v, v, s);
+                exact = exact && v == rintf(v) && fabsf(v) <= 256.0f;
+            }
         }
-        for (int o = 32; o > 0; o >>= 1)
-            s += __shfl_xor(s, o, 64);
-        const bool all_exact = __ballot(!exact) == 0;
-        if (lane == 0 && qexact)
-            qexact[i] = all_exact ? 1u : 0u;
-        if (lane == 0) {
+        // sum over the 16 lanes of the row
+        s += row_mov<0xB1>(s);   // quad_perm(1, 0, 3, 2)
+        s += row_mov<0x4E>(s);   // quad_perm(2, 3, 0, 1)
+        s += row_mov<0x141>(s);  // row_half_mirror
+        s += row_mov<0x140>(s);  // row_mirror
+        const bool all_exact = ((__ballot(!exact) >> (16 * grp)) & 0xFFFFull) == 0;
+        if (live && sub == 0) {
+            if (qexact)
+                qexact[i] = all_exact ? 1u : 0u;
             qnorm[i] = s;
             uint32_t w = 0, mk = 0;
             attr_pack_query(qa + i * m, m, abits, w, mk);
@@ -239,7 +254,7 @@ int launch_pad_queries(const float *q, const uint8_t *qa, int64_t nq, int d, int
 {
     if (nq == 0)
         return NHQ_OK;
-    hipLaunchKernelGGL(k_pad_queries, dim3(grid_for(nq, 1)), dim3(64), 0, st, q, qa, nq, d, dp, m,
+    hipLaunchKernelGGL(k_pad_queries, dim3(grid_for(nq, 4)), dim3(64), 0, st, q, qa, nq, d, dp, m,
                        abits, qpad, qnorm, qword, qmask, qexact);
     NHQ_HIP(hipGetLastError());
     return NHQ_OK;
@@ -691,12 +706,29 @@ void nhq_index_free(nhq_index *h)
     delete h;
 }
 
-int nhq_seed_rank(const nhq_index *h, const float *queries, const uint8_t *qattrs, int64_t nq,
-                  int32_t n_cand, int32_t *cand, void *stream)
+}  // extern "C"
+
+namespace {
+
+// 32-bit words of the seed ranking's scratch: padded rows, norms, codes,
+// masks, exactness flags and (for the matrix-core ranking) the key matrix and
+// its group minima
+size_t seed_rank_words(const Index *ix, int64_t nq)
+{
+    const size_t ne_pad = (size_t)(ix->n_entry + 63) / 64 * 64;
+    const bool dense = ix->n_entry <= 8192;
+    return (size_t)nq * ix->dp + 5 * (size_t)nq + (dense ? (size_t)nq * ne_pad / 16 * 17 : 0) + 64;
+}
+
+// nhq_seed_rank with its scratch at byte ws_off of the index's workspace
+// (grown when too small; calls on one index are ordered on one stream, so
+// the workspace is theirs in turn)
+int seed_rank_ws(const nhq_index *h, const float *queries, const uint8_t *qattrs, int64_t nq, int32_t n_cand,
+                 int32_t *cand, void *stream, size_t ws_off)
 {
     if (!h)
         return fail(NHQ_EINVAL, "null index");
-    const Index *ix = &h->impl;
+    Index *ix = const_cast<Index *>(&h->impl);
     if (nq < 0 || n_cand < 1 || n_cand > 144)
         return fail(NHQ_EINVAL, "need nq >= 0 and 1 <= n_cand <= 144");
     if (nq == 0)
@@ -704,34 +736,38 @@ int nhq_seed_rank(const nhq_index *h, const float *queries, const uint8_t *qattr
     if (!queries || !cand || (ix->m > 0 && !qattrs))
         return fail(NHQ_EINVAL, "null array argument");
     hipStream_t st = (hipStream_t)stream;
-    // one stream-ordered block: padded rows, norms, codes, masks, exactness
-    // flags and (for the matrix-core ranking) the key matrix and its group
-    // minima
-    const size_t ne_pad = (size_t)(ix->n_entry + 63) / 64 * 64;
     const bool dense = ix->n_entry <= 8192;
     const size_t f_rows = (size_t)nq * ix->dp, f_small = (size_t)nq;
-    const size_t words = f_rows + 5 * f_small + (dense ? (size_t)nq * ne_pad / 16 * 17 : 0) + 64;
-    uint32_t *blk = nullptr;
-    NHQ_HIP(hipMallocAsync((void **)&blk, sizeof(uint32_t) * words, st));
+    int rc = ensure_workspace(ix, ws_off + sizeof(uint32_t) * seed_rank_words(ix, nq));
+    if (rc != NHQ_OK)
+        return rc;
+    uint32_t *blk = reinterpret_cast<uint32_t *>(static_cast<char *>(ix->ws) + ws_off);
     float *qpad = reinterpret_cast<float *>(blk);
     float *qnorm = qpad + f_rows;
     uint32_t *qw = reinterpret_cast<uint32_t *>(qnorm + f_small);
     uint32_t *qm = qw + f_small;
     uint32_t *qx = qm + f_small;
     float *keys = reinterpret_cast<float *>((reinterpret_cast<uintptr_t>(qx + f_small) + 255) & ~uintptr_t(255));
-    int rc = launch_pad_queries(queries, qattrs, nq, ix->d, ix->dp, ix->m, ix->abits, qpad, qnorm, qw, qm,
-                                qx, st);
+    rc = launch_pad_queries(queries, qattrs, nq, ix->d, ix->dp, ix->m, ix->abits, qpad, qnorm, qw, qm, qx, st);
     if (rc == NHQ_OK) {
         if (dense)
             rc = launch_seed_rank(ix, qpad, qnorm, qw, qm, qx, nq, n_cand, keys, cand, st);
         else
-            rc = launch_dense_topk(qpad, qnorm, qw, qm, nq, ix->entry_vec, ix->entry_norm,
-                                   ix->entry_attr, ix->n_entry, ix->dp, ix->m, ix->abits, 0, 0, n_cand,
-                                   cand,
-                                   nullptr, st, &ix->w);
+            rc = launch_dense_topk(qpad, qnorm, qw, qm, nq, ix->entry_vec, ix->entry_norm, ix->entry_attr,
+                                   ix->n_entry, ix->dp, ix->m, ix->abits, 0, 0, n_cand, cand, nullptr, st,
+                                   &ix->w);
     }
-    (void)hipFreeAsync(blk, st);
     return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nhq_seed_rank(const nhq_index *h, const float *queries, const uint8_t *qattrs, int64_t nq,
+                  int32_t n_cand, int32_t *cand, void *stream)
+{
+    return seed_rank_ws(h, queries, qattrs, nq, n_cand, cand, stream, 0);
 }
 
 int nhq_search_seeded(const nhq_index *h, const float *queries, const uint8_t *qattrs, int64_t nq,
@@ -832,13 +868,17 @@ int nhq_hybrid_search(const nhq_index *h, const float *queries, const uint8_t *q
     if (n_init > 128)
         return fail(NHQ_EINVAL, "need 1 <= n_init <= 128");
     const int ks = std::min(ix->n_entry, n_init + 16);
-    hipStream_t st = (hipStream_t)stream;
-    int32_t *cand = nullptr;
-    NHQ_HIP(hipMallocAsync((void **)&cand, sizeof(int32_t) * (size_t)nq * ks, st));
-    int rc = nhq_seed_rank(h, queries, qattrs, nq, ks, cand, stream);
+    // the candidates at the start of the index's workspace, the ranking's
+    // scratch after them
+    const size_t cbytes = (sizeof(int32_t) * (size_t)nq * ks + 255) & ~size_t(255);
+    Index *mix = const_cast<Index *>(ix);
+    int rc = ensure_workspace(mix, cbytes + sizeof(uint32_t) * seed_rank_words(ix, nq));
+    if (rc != NHQ_OK)
+        return rc;
+    int32_t *cand = static_cast<int32_t *>(mix->ws);
+    rc = seed_rank_ws(h, queries, qattrs, nq, ks, cand, stream, cbytes);
     if (rc == NHQ_OK)
         rc = nhq_search_seeded(h, queries, qattrs, nq, cand, ks, k, beam, sp, ids, dists, stream);
-    (void)hipFreeAsync(cand, st);
     return rc;
 }
 
