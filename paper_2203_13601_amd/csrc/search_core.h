@@ -79,6 +79,26 @@ struct Chunk<NHQ_STORAGE_FP8> {
     using T = uint32_t;
 };
 
+// A lane's 4-element chunks of a row: fp8 rows take K4 neighbouring chunks
+// per load (up to 16 bytes); the other forms load 16 (fp32) or 8 (bf16)
+// bytes per chunk already.  Lane g's c-th chunk is chunk
+// K4 (g + G (c / K4)) + c % K4 of the row.
+template <int DP, int ST>
+struct Lay {
+    static constexpr int NCH = Shape<DP>::NCH;
+    static constexpr int K4 = ST != NHQ_STORAGE_FP8 ? 1
+                              : NCH % 4 == 0       ? 4
+                              : NCH % 3 == 0       ? 3
+                              : NCH % 2 == 0       ? 2
+                                                   : 1;
+};
+
+template <int DP, int K4>
+__device__ __forceinline__ int lane_chunk(int g, int c)
+{
+    return K4 * (g + Shape<DP>::G * (c / K4)) + c % K4;
+}
+
 __device__ __forceinline__ void wsync()
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -155,7 +175,7 @@ __device__ __forceinline__ float group_sum(float v)
 // mode 0: key, chi taken from the staged word; mode 1: key, chi computed
 // from the attribute word (fetched together with the row) and written into
 // the staged word; mode 2: delta^2.
-template <int DP, int ST>
+template <int DP, int ST, int K4 = Lay<DP, ST>::K4>
 __device__ __forceinline__ void score_batch(const void *vbase, const float *scale,
                                             const float4 (&qv)[Shape<DP>::NCH],
                                             uint32_t *sid, float *out, int nf, int mq,
@@ -185,7 +205,7 @@ __device__ __forceinline__ void score_batch(const void *vbase, const float *scal
                 const T *row = reinterpret_cast<const T *>(vbase) + id * (DP / 4);
 #pragma unroll
                 for (int c = 0; c < S::NCH; ++c)
-                    buf[rr][c] = row[g + S::G * c];
+                    buf[rr][c] = row[lane_chunk<DP, K4>(g, c)];
                 if (ST == NHQ_STORAGE_FP8)
                     sc[rr] = scale[id];
                 if (mode == 1 && g == 0)
@@ -470,7 +490,7 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
     const float *qp = io.q;
 #pragma unroll
     for (int c = 0; c < S::NCH; ++c) {
-        const int e = 4 * (g + S::G * c);
+        const int e = 4 * lane_chunk<DP, Lay<DP, ST>::K4>(g, c);
         qv[c].x = e + 0 < a.d ? qp[e + 0] : 0.0f;
         qv[c].y = e + 1 < a.d ? qp[e + 1] : 0.0f;
         qv[c].z = e + 2 < a.d ? qp[e + 2] : 0.0f;
@@ -810,7 +830,7 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
     got = min(got, want);
     wsync();
     // delta^2 from the float32 copy (identical to the loop's for fp32 storage)
-    score_batch<DP, NHQ_STORAGE_FP32>(a.vec32, nullptr, qv, sid, skey, got, mq, 2, a.w);
+    score_batch<DP, NHQ_STORAGE_FP32, Lay<DP, ST>::K4>(a.vec32, nullptr, qv, sid, skey, got, mq, 2, a.w);
     wsync();
     // final order into LDS (the pool is no longer needed), then one store
     // per output slot
