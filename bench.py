@@ -79,7 +79,7 @@ def main():
     ap.add_argument("--target", type=float, default=0.95)
     ap.add_argument("--beam", type=int, default=0, help="fixed beam (skip the choice)")
     ap.add_argument("--n-entry", type=int, default=4096)
-    ap.add_argument("--n-init", type=int, default=16)
+    ap.add_argument("--n-init", type=int, default=4)
     ap.add_argument("--expand", type=int, default=6, help="vertices expanded per step")
     ap.add_argument("--plain-only", action="store_true", help="skip the bf16/learned and serving legs")
     ap.add_argument("--serve-rate", type=float, default=50_000.0)
