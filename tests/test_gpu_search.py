@@ -297,3 +297,25 @@ def test_multi_expansion_with_hash_visited_set():
         assert np.array_equal(ids, oi)
         assert (cnt[:, 0] >= ondc).all()
         assert np.array_equal(cnt[:, 1], ohops)
+
+
+def test_workspace_reuse_across_batch_sizes(int_set):
+    # the seed ranking keeps its scratch (and nhq_hybrid_search its
+    # candidates) in the index's workspace, grown on demand: batches of
+    # different sizes in a row, on one index, each equal the oracle's
+    w, adj = int_set
+    ix = _index(w, adj, n_entry=256)
+    entry = oracle.entry_points(w.build_seed, w.n, 256)
+    oi, _, ondc, ohops, _ = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, 40, entry,
+                                          key_mode=oracle.KEY32, n_init=8)
+    for lo, hi in ((0, 5), (0, w.nq), (7, 9), (3, 60), (0, 1)):
+        ids, _, cnt = nhq.nhq_hybrid_search(ix, _dev(w.q[lo:hi]), _dev(w.qattrs[lo:hi]), 10, 40,
+                                            n_init=8, counters=True)
+        cand = nhq.nhq_seed_rank(ix, _dev(w.q[lo:hi]), _dev(w.qattrs[lo:hi]), 24)
+        sid, _ = nhq.nhq_search_seeded(ix, _dev(w.q[lo:hi]), _dev(w.qattrs[lo:hi]), cand, 10, 40,
+                                       n_init=8)
+        torch.cuda.synchronize()
+        assert np.array_equal(ids.cpu().numpy(), oi[lo:hi])
+        assert np.array_equal(sid.cpu().numpy(), oi[lo:hi])
+        assert np.array_equal(cnt.cpu().numpy()[:, 0], ondc[lo:hi])
+        assert np.array_equal(cnt.cpu().numpy()[:, 1], ohops[lo:hi])
