@@ -275,6 +275,21 @@ int nhq_index_device_error(nhq_index *ix, void *stream, uint32_t *bits_out);
 
 void nhq_index_free(nhq_index *ix);
 
+/* Index files (the "save / load" of a built index; Alg. 1's output with
+ * everything the search reads).  nhq_index_save synchronises `stream`, then
+ * writes the index's parameters and its first n rows of every array --
+ * float32 rows, storage form (and fp8 scales), packed codes, norms, graph,
+ * entry sample (and its exact bf16 copy), code log-frequencies and the stop
+ * network when loaded -- to `path` (host path, overwritten).
+ * nhq_index_load reads such a file onto the current device and returns a new
+ * index with the saved capacity (rows past n free for nhq_index_insert) that
+ * answers every call as the saved one did.  NHQ_EIO: the file cannot be
+ * opened, written or read, is not an index file of this version, is
+ * truncated or has trailing bytes, or its header is inconsistent; the index
+ * is then not created. */
+int nhq_index_save(const nhq_index *ix, const char *path, void *stream);
+int nhq_index_load(const char *path, void *stream, nhq_index **out);
+
 /* ----------------------------------------------------------------- search */
 
 /* Hybrid query (Def. 4) answered by joint pruning (Alg. 2) in beam form: one

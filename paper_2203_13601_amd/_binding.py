@@ -98,6 +98,8 @@ def lib() -> ctypes.CDLL:
         "nhq_index_get_storage": ([P, P, P, P, P], i32),
         "nhq_index_device_error": ([P, P, P], i32),
         "nhq_index_free": ([P], None),
+        "nhq_index_save": ([P, ctypes.c_char_p, P], i32),
+        "nhq_index_load": ([ctypes.c_char_p, P, P], i32),
         "nhq_hybrid_search": ([P, P, P, i64, i32, i32, P, P, P, P], i32),
         "nhq_bruteforce_hybrid_knn": ([P, P, P, i64, i32, P, P, P], i32),
         "nhq_seed_rank": ([P, P, P, i64, i32, P, P], i32),
@@ -235,6 +237,19 @@ def nhq_index_build_report(ix: Index) -> dict:
     r = ctypes.c_int32()
     _check(lib().nhq_index_build_report(ix.handle, ctypes.byref(r)), "nhq_index_build_report")
     return {"nnd_rounds_run": r.value}
+
+
+def nhq_index_save(ix: Index, path: str, stream=None) -> None:
+    """Write the index to a file (include/nhq.h: nhq_index_save)."""
+    _check(lib().nhq_index_save(ix.handle, os.fsencode(path), _stream(stream)), "nhq_index_save")
+
+
+def nhq_index_load(path: str, stream=None) -> Index:
+    """A new index on the current device from a file written by
+    nhq_index_save."""
+    h = ctypes.c_void_p()
+    _check(lib().nhq_index_load(os.fsencode(path), _stream(stream), ctypes.byref(h)), "nhq_index_load")
+    return Index(h)
 
 
 def nhq_index_build_graph(ix: Index, stream=None) -> None:

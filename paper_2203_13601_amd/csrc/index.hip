@@ -233,6 +233,8 @@ int grid_for(int64_t work, int block)
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
 }
 
+}  // namespace
+
 void free_index(Index *ix)
 {
     if (!ix)
@@ -245,8 +247,6 @@ void free_index(Index *ix)
         if (p)
             (void)hipFree(p);
 }
-
-}  // namespace
 
 int launch_pad_queries(const float *q, const uint8_t *qa, int64_t nq, int d, int dp, int m,
                        int abits, float *qpad, float *qnorm, uint32_t *qword, uint32_t *qmask,
@@ -302,11 +302,11 @@ int nhq_index_create(const float *vecs, const uint8_t *attrs, int64_t n, int32_t
     if (!vecs || (m > 0 && !attrs))
         return fail(NHQ_EINVAL, "vecs/attrs is null");
     if (n < 1 || n >= kMaxN)
-        return fail(NHQ_EINVAL, "n must be in [1, 2^28)");
+        return fail(NHQ_EINVAL, "n must be in [1, 2^27)");
     if (d < 1 || d > 1024)
         return fail(NHQ_EINVAL, "d must be in [1, 1024]");
     if (m < 0 || m > NHQ_MAX_ATTRS)
-        return fail(NHQ_EINVAL, "m must be in [0, 4]");
+        return fail(NHQ_EINVAL, "m must be in [0, 12]");
     nhq_build_params p{};
     if (params)
         p = *params;

@@ -84,6 +84,7 @@ struct Index {
 };
 
 int ensure_workspace(Index *ix, size_t bytes);
+void free_index(Index *ix);  // every device array the index holds
 
 // NPG_nsw by batched insertion (nsw.hip)
 int nsw_build(Index *ix, int l, int64_t B, int L, uint64_t seed, hipStream_t st);
