@@ -25,7 +25,8 @@
  *    detailed message.  No C++ exception crosses this boundary.
  *  - An index owns every device copy it makes; it never aliases caller memory
  *    after a call returns.  Calls that use one index must be ordered on one
- *    stream (they share the index's workspace).
+ *    stream and made from one host thread at a time (they share the index's
+ *    workspace).
  *  - Fusion distance: Gamma(q, e) = delta * (1 + chi / m_q) where delta is the
  *    Euclidean distance (Eq. 1), chi the number of constrained attributes on
  *    which the codes differ (Eq. 4-5) and m_q the number of constrained
