@@ -281,7 +281,9 @@ void nhq_index_free(nhq_index *ix);
  * writes the index's parameters and its first n rows of every array --
  * float32 rows, storage form (and fp8 scales), packed codes, norms, graph,
  * entry sample (and its exact bf16 copy), code log-frequencies and the stop
- * network when loaded -- to `path` (host path, overwritten).
+ * network when loaded -- to `path` (host path; written as `path`.partial and
+ * renamed over `path` once complete, so a failed save leaves `path` as it
+ * was).
  * nhq_index_load reads such a file onto the current device and returns a new
  * index with the saved capacity (rows past n free for nhq_index_insert) that
  * answers every call as the saved one did.  NHQ_EIO: the file cannot be

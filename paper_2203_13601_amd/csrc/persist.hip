@@ -75,6 +75,26 @@ int read_dev(FILE *f, void **dev, size_t bytes, size_t alloc, std::vector<char> 
     return NHQ_OK;
 }
 
+// bytes after the header that a file with header `hd` holds
+uint64_t payload_bytes(const FileHeader &hd)
+{
+    const uint64_t n = (uint64_t)hd.n, ne = (uint64_t)hd.n_entry, dp = (uint64_t)hd.dp;
+    uint64_t b = 4 * n * dp;                                        // float32 rows
+    if (hd.storage != NHQ_STORAGE_FP32)
+        b += storage_elem(hd.storage) * n * dp;                     // storage form
+    if (hd.storage == NHQ_STORAGE_FP8)
+        b += 4 * n;                                                 // scales
+    b += 4 * n + 4 * n;                                             // codes, norms
+    b += 4 * n * (uint64_t)hd.degree;                               // graph
+    b += 4 * ne + 4 * ne * dp + 4 * ne + 4 * ne;                    // entry sample
+    if (hd.has_entry_bf16)
+        b += 2 * ne * dp;
+    b += 4 * (uint64_t)NHQ_MAX_ATTRS * 256;                         // code log-frequencies
+    if (hd.has_mlp)
+        b += 2 * (uint64_t)NHQ_MLP_PARAMS;                          // stop network
+    return b;
+}
+
 struct FileCloser {
     FILE *f;
     ~FileCloser()
@@ -127,12 +147,16 @@ int nhq_index_save(const nhq_index *h, const char *path, void *stream)
     hd.nsw_beam = ix->nsw_beam;
     hd.has_entry_bf16 = ix->entry_bf16 ? 1 : 0;
     hd.has_mlp = ix->mlp ? 1 : 0;
-    FILE *f = std::fopen(path, "wb");
+    // written to a temporary name, renamed into place once complete
+    const std::string tmp = std::string(path) + ".partial";
+    FILE *f = std::fopen(tmp.c_str(), "wb");
     if (!f)
-        return fail(NHQ_EIO, std::string("cannot open for writing: ") + path);
+        return fail(NHQ_EIO, std::string("cannot open for writing: ") + tmp);
     FileCloser fc{f};
-    if (std::fwrite(&hd, sizeof(hd), 1, f) != 1)
+    if (std::fwrite(&hd, sizeof(hd), 1, f) != 1) {
+        std::remove(tmp.c_str());
         return fail(NHQ_EIO, "index file write failed");
+    }
     std::vector<char> buf(kChunk);
     const size_t n = (size_t)ix->n, ne = (size_t)ix->n_entry, dp = (size_t)ix->dp;
     int rc = write_dev(f, ix->vec32, sizeof(float) * n * dp, buf);
@@ -162,6 +186,14 @@ int nhq_index_save(const nhq_index *h, const char *path, void *stream)
         rc = write_dev(f, ix->mlp, sizeof(uint16_t) * NHQ_MLP_PARAMS, buf);
     if (rc == NHQ_OK && std::fflush(f) != 0)
         rc = fail(NHQ_EIO, "index file write failed");
+    const bool closed = std::fclose(f) == 0;
+    fc.f = nullptr;
+    if (rc == NHQ_OK && !closed)
+        rc = fail(NHQ_EIO, "index file write failed");
+    if (rc == NHQ_OK && std::rename(tmp.c_str(), path) != 0)
+        rc = fail(NHQ_EIO, std::string("cannot rename the index file to ") + path);
+    if (rc != NHQ_OK)
+        std::remove(tmp.c_str());
     return rc;
 }
 
@@ -186,6 +218,22 @@ int nhq_index_load(const char *path, void *stream, nhq_index **out)
         hd.n_entry > 65536 || hd.n_entry > hd.n || hd.w_mode < NHQ_WEIGHTS_DEFAULT ||
         hd.w_mode > NHQ_WEIGHTS_FIXED || (hd.abits != 1 && hd.abits != 2 && hd.abits != 4 && hd.abits != 8))
         return fail(NHQ_EIO, "index file header is inconsistent");
+    // the file must hold exactly what the header announces (checked before
+    // any allocation)
+    {
+        const long here = std::ftell(f);
+        if (here < 0 || std::fseek(f, 0, SEEK_END) != 0)
+            return fail(NHQ_EIO, "index file is not seekable");
+        const long end = std::ftell(f);
+        if (end < 0 || std::fseek(f, here, SEEK_SET) != 0)
+            return fail(NHQ_EIO, "index file is not seekable");
+        const uint64_t have = (uint64_t)(end - here);
+        const uint64_t want = payload_bytes(hd);
+        if (have < want)
+            return fail(NHQ_EIO, "index file is truncated");
+        if (have > want)
+            return fail(NHQ_EIO, "index file has trailing bytes");
+    }
     nhq_index *h = new nhq_index();
     Index *ix = &h->impl;
     int rc = NHQ_OK;

@@ -115,3 +115,9 @@ def test_damaged_files_are_refused(data, tmp_path):
     with pytest.raises(nhq.NHQError):
         nhq.nhq_index_save(ix, str(tmp_path / "no_such_dir" / "x.nhq"))
     assert os.path.getsize(path) == len(raw)
+    assert not os.path.exists(path + ".partial")
+    # a save over an existing file replaces it whole
+    iy = nhq.nhq_build_index(_dev(w.x[:300]), _dev(w.attrs[:300]), degree=12, cand=24, n_entry=32)
+    nhq.nhq_index_save(iy, path)
+    assert nhq.nhq_index_info(nhq.nhq_index_load(path))["n"] == 300
+    assert not os.path.exists(path + ".partial")
