@@ -42,6 +42,10 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+# seed candidates beyond n_init, as nhq_hybrid_search keeps them
+SEED_MARGIN = 8
+
+
 def _profiled_traffic(kernel: str, source: str, tag: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when no
@@ -138,7 +142,7 @@ def main():
     log("exact answers in %.2fs" % gt_s)
 
     nq, k = w.nq, w.k
-    n_cand = min(args.n_entry, args.n_init + 16)
+    n_cand = min(args.n_entry, args.n_init + SEED_MARGIN)
     cand = torch.empty((nq, n_cand), dtype=torch.int32, device=dev)
     ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
     dists = torch.empty((nq, k), dtype=torch.float32, device=dev)
@@ -481,7 +485,7 @@ def precision_form(args):
     gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
     adj = nhq.nhq_index_get_graph(ix)
     k, nq = w.k, w.nq
-    n_cand = min(args.n_entry, args.n_init + 16)
+    n_cand = min(args.n_entry, args.n_init + SEED_MARGIN)
     cand = torch.empty((nq, n_cand), dtype=torch.int32, device=dev)
     nsamp = min(nq, 1000)
 
@@ -607,7 +611,7 @@ def build_study(args):
     from paper_2203_13601_amd.metrics import qps_at_recall, recall_at_k
 
     dev = torch.device("cuda:0")
-    n_cand = min(args.n_entry, args.n_init + 16)
+    n_cand = min(args.n_entry, args.n_init + SEED_MARGIN)
     out = {}
 
     def curve(ix, w, q, qa, gi, gd, beams):
@@ -707,7 +711,7 @@ def ablation(args):
     x = torch.from_numpy(w.x).to(dev)
     q = torch.from_numpy(w.q).to(dev)
     nq, k = w.nq, w.k
-    n_cand = min(args.n_entry, args.n_init + 16)
+    n_cand = min(args.n_entry, args.n_init + SEED_MARGIN)
     beams = [10, 16, 32, 64, 128, 256, 512]
 
     def true_delta(ids):

@@ -321,9 +321,11 @@ int nhq_hybrid_search(const nhq_index *ix, const float *queries, const uint8_t *
  * nhq_search_seeded: the joint-pruning search given those candidates: it
  * re-scores them exactly, starts the pool with the best n_init of them and
  * runs the expansion loop.  nhq_hybrid_search passes n_cand = min(n_entry,
- * n_init + 16); the result then equals a search started from the best n_init
+ * n_init + 8); the result then equals a search started from the best n_init
  * members of the whole entry sample unless the dense ranking (float32 GEMM
- * form of delta^2) misplaces one past the 16-entry margin. */
+ * form of delta^2) misplaces one past the 8-entry margin (never when the
+ * queries and the entry sample hold integers of magnitude <= 256 and rows
+ * have at most 128 elements: then the ranking is exact). */
 int nhq_seed_rank(const nhq_index *ix, const float *queries, const uint8_t *qattrs, int64_t nq,
                   int32_t n_cand, int32_t *cand, void *stream);
 int nhq_search_seeded(const nhq_index *ix, const float *queries, const uint8_t *qattrs, int64_t nq,

@@ -867,7 +867,7 @@ int nhq_hybrid_search(const nhq_index *h, const float *queries, const uint8_t *q
     const int n_init = (sp && sp->n_init > 0) ? sp->n_init : 32;
     if (n_init > 128)
         return fail(NHQ_EINVAL, "need 1 <= n_init <= 128");
-    const int ks = std::min(ix->n_entry, n_init + 16);
+    const int ks = std::min(ix->n_entry, n_init + kSeedMargin);
     // the candidates at the start of the index's workspace, the ranking's
     // scratch after them
     const size_t cbytes = (sizeof(int32_t) * (size_t)nq * ks + 255) & ~size_t(255);

@@ -34,6 +34,9 @@ constexpr int kChiShift = 27;
 constexpr uint32_t kChiMask = 15u;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr int64_t kMaxN = int64_t(1) << 27;
+// seed candidates kept beyond n_init for the direct-form re-score (guards
+// the GEMM form's rounding at near-ties of the dense ranking)
+constexpr int kSeedMargin = 8;
 
 // Padded widths the kernels are instantiated for (the stored rows are padded
 // with zeros to the next one; zeros change no distance).

@@ -508,7 +508,7 @@ int nhq_server_create(nhq_index *h, const nhq_server_params *pp, nhq_server **ou
     Server &s = hs->impl;
     s.ix = ix;
     s.p = p;
-    s.n_cand = std::min(ix->n_entry, p.n_init + 16);
+    s.n_cand = std::min(ix->n_entry, p.n_init + kSeedMargin);
     s.ne_pad = (ix->n_entry + 63) & ~63;
     s.rec_bytes = (int)((sizeof(ReqHead) + 4 * (size_t)ix->d + 63) & ~(size_t)63);
     s.out_bytes = (int)((sizeof(OutHead) + 8 * (size_t)p.max_k + 63) & ~(size_t)63);
