@@ -82,7 +82,9 @@ def main():
     ap.add_argument("--nq", type=int, default=10_000)
     ap.add_argument("--target", type=float, default=0.95)
     ap.add_argument("--beam", type=int, default=0, help="fixed beam (skip the choice)")
-    ap.add_argument("--n-entry", type=int, default=4096)
+    ap.add_argument("--n-entry", type=int, default=None,
+                    help="entry sample size (default 4096; 1024 for the precision workload, whose "
+                         "64 clusters need fewer entries)")
     ap.add_argument("--n-init", type=int, default=4)
     ap.add_argument("--expand", type=int, default=6, help="vertices expanded per step")
     ap.add_argument("--plain-only", action="store_true", help="skip the bf16/learned and serving legs")
@@ -98,6 +100,8 @@ def main():
                          "ablation: weight settings, selectivity and post-filtering sweeps; "
                          "build: exact vs NN-descent candidate lists (1M and 10M sets)")
     args = ap.parse_args()
+    if args.n_entry is None:
+        args.n_entry = 1024 if args.workload == "precision" else 4096
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
