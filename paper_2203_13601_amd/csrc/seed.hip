@@ -1,11 +1,14 @@
 // Seed ranking: every query against the index's random entry sample (the
-// seed set B of Alg. 2 is drawn from it), in two kernels.
+// seed set B of Alg. 2 is drawn from it): a key kernel, then a selection.
 //
 // k_entry_keys (matrix cores): the full key matrix [nq][n_entry_pad] with
 //   key = delta^2 (m_q + chi)^2 (delta^2 when m_q = 0),
-//   delta^2 = |q|^2 + |e|^2 - 2 q.e   (q.e from v_mfma_f32_16x16x4f32),
+//   delta^2 = |q|^2 + |e|^2 - 2 q.e   (q.e from v_mfma_f32_16x16x4f32, or
+//   from v_mfma_f32_16x16x32_bf16 in k_entry_keys_b16 where both sides are
+//   exact in bf16),
 // chi over the query's constrained codes; padding columns hold +inf.  A
-// workgroup of 4 waves takes 64 queries (16 per wave) against 256 entries.
+// workgroup of 4 waves takes 64 queries (16 per wave) against kKeyTiles
+// tiles of 64 entries.
 //
 // The key kernels also write, per query, the minimum of every 16-entry group
 // of keys.  The K-th smallest group minimum bounds the K-th smallest key
