@@ -74,6 +74,31 @@ __device__ __forceinline__ void flush_gmin(const KeyArgs &a, const float *gm, in
     }
 }
 
+// The norm and attribute word of the tile's 64 entries (columns past the
+// sample's end repeat its last entry; their keys become +inf): loaded by
+// the first wave together with the tile's rows, written to LDS after them.
+struct EntryMeta {
+    float n;
+    uint32_t w;
+};
+__device__ __forceinline__ EntryMeta load_entry_meta(const KeyArgs &a, int c0)
+{
+    EntryMeta m{0.0f, 0u};
+    if (threadIdx.x < 64) {
+        const int col = min(c0 + (int)threadIdx.x, a.ne - 1);
+        m.n = a.en[col];
+        m.w = a.ea[col];
+    }
+    return m;
+}
+__device__ __forceinline__ void put_entry_meta(const EntryMeta &m, float *ten, uint32_t *tea)
+{
+    if (threadIdx.x < 64) {
+        ten[threadIdx.x] = m.n;
+        tea[threadIdx.x] = m.w;
+    }
+}
+
 template <int DP>
 struct KShape {
     // dims staged per pass: the whole row up to 128, else 64 (or 32)
@@ -90,29 +115,39 @@ __device__ __forceinline__ float quad_mov(float v)
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
+// The ordering key of one pair.  DEF (the default weights, chosen once per
+// launch): delta^2 (m_q + chi)^2, with m1 = max(m_q, 1) -- a query with no
+// constrained attribute has chi = 0, so its factor is 1 and the key is
+// delta^2, as the definition asks; the factor is an integer below 2^24, so
+// it is exact in float32 and the key is rounded once, as in w_key32.
+template <bool DEF>
+__device__ __forceinline__ float pair_key(float d2, int c, int mq, float m1, const Weights &w)
+{
+    if constexpr (DEF) {
+        const float f = m1 + (float)c;
+        return d2 * (f * f);
+    } else {
+        return w_key32(d2, c, mq, w);
+    }
+}
+
 // Keys of one 64-entry tile for a wave's 16 queries: lane (rl, lq) holds
-// query rl against entries c0 + 16 s + 4 lq + r in acc[s][r].  They go
+// query rl against entries c0 + 16 s + 4 lq + r in acc[s][r]; the tile's
+// entry norms and attribute words are in LDS (ten, tea).  The keys go
 // through the wave's LDS area (16 rows of 68 floats) so that every store
 // instruction writes four whole 256-byte rows of the key matrix.
+template <bool DEF>
 __device__ __forceinline__ void store_keys(const KeyArgs &a, const f32x4 (&acc)[4], int c0, int64_t row0, int rl,
-                                           int lq, float rn, uint32_t qw, uint32_t qm, float mq, float *stage,
-                                           float *gm, int g0)
+                                           int lq, float rn, uint32_t qw, uint32_t qm, float mq, const float *ten,
+                                           const uint32_t *tea, float *stage, float *gm, int g0)
 {
     const int lane = threadIdx.x & 63;
+    const float m1 = fmaxf(mq, 1.0f);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const int cb0 = c0 + 16 * s + 4 * lq;
-        float4 nrm;
-        uint4 atr;
-        if (cb0 + 3 < a.ne) {
-            nrm = *reinterpret_cast<const float4 *>(a.en + cb0);
-            atr = *reinterpret_cast<const uint4 *>(a.ea + cb0);
-        } else {
-            const int c1 = min(cb0 + 1, a.ne - 1), c2 = min(cb0 + 2, a.ne - 1);
-            const int c3 = min(cb0 + 3, a.ne - 1), cz = min(cb0, a.ne - 1);
-            nrm = make_float4(a.en[cz], a.en[c1], a.en[c2], a.en[c3]);
-            atr = make_uint4(a.ea[cz], a.ea[c1], a.ea[c2], a.ea[c3]);
-        }
+        const float4 nrm = *reinterpret_cast<const float4 *>(ten + 16 * s + 4 * lq);
+        const uint4 atr = *reinterpret_cast<const uint4 *>(tea + 16 * s + 4 * lq);
         const float nb4[4] = {nrm.x, nrm.y, nrm.z, nrm.w};
         const uint32_t at4[4] = {atr.x, atr.y, atr.z, atr.w};
         float k4[4];
@@ -120,7 +155,7 @@ __device__ __forceinline__ void store_keys(const KeyArgs &a, const f32x4 (&acc)[
         for (int r = 0; r < 4; ++r) {
             const float d2 = fmaxf(rn + nb4[r] - 2.0f * acc[s][r], 0.0f);
             const int c = chi_of(at4[r], qw, qm, a.hmask);
-            k4[r] = cb0 + r < a.ne ? w_key32(d2, c, (int)mq, a.w) : __int_as_float(0x7F800000);
+            k4[r] = cb0 + r < a.ne ? pair_key<DEF>(d2, c, (int)mq, m1, a.w) : __int_as_float(0x7F800000);
         }
         *reinterpret_cast<float4 *>(stage + rl * 68 + 16 * s + 4 * lq) = make_float4(k4[0], k4[1], k4[2], k4[3]);
     }
@@ -158,13 +193,15 @@ __device__ __forceinline__ bool group_exact(const KeyArgs &a, int64_t rowc)
 // entries' rows are staged through LDS 64 at a time and shared by the waves.
 // Float32 products (v_mfma_f32_16x16x4f32); workgroups whose queries are
 // all exact in bf16 are left to k_entry_keys_b16.
-template <int DP>
+template <int DP, bool DEF>
 __global__ __launch_bounds__(256) void k_entry_keys(const KeyArgs a)
 {
     using K = KShape<DP>;
     // entry tile; afterwards the key staging of the four waves
     __shared__ __align__(16) float tile[64 * K::LDSW > 4 * 16 * 68 ? 64 * K::LDSW : 4 * 16 * 68];
     __shared__ float gms[4 * 16 * kGmStride];
+    __shared__ __align__(16) float ten[64];
+    __shared__ __align__(16) uint32_t tea[64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int rl = lane & 15, lq = lane >> 4;
     const int64_t row = (int64_t)blockIdx.x * 64 + wave * 16 + rl;
@@ -190,14 +227,28 @@ __global__ __launch_bounds__(256) void k_entry_keys(const KeyArgs a)
             acc[s] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
         {
             for (int kc = 0; kc < K::NK; ++kc) {
-                // stage 64 entry rows (dims kc*KC .. +KC) into LDS
+                // stage 64 entry rows (dims kc*KC .. +KC) into LDS, every
+                // load issued before the first write
+                constexpr int kIt = 64 * (K::KC / 4) / 256;
+                static_assert(kIt * 256 == 64 * (K::KC / 4), "whole staging rounds");
                 __syncthreads();
-                for (int i = threadIdx.x; i < 64 * (K::KC / 4); i += 256) {
-                    const int r = i / (K::KC / 4), c4 = i - r * (K::KC / 4);
+                float4 v[kIt];
+#pragma unroll
+                for (int it = 0; it < kIt; ++it) {
+                    const int i = (int)threadIdx.x + 256 * it, r = i / (K::KC / 4), c4 = i - r * (K::KC / 4);
                     const int col = min(c0 + r, a.ne - 1);
-                    const float4 v = reinterpret_cast<const float4 *>(a.ev + (int64_t)col * DP + kc * K::KC)[c4];
-                    *reinterpret_cast<float4 *>(tile + r * K::LDSW + 4 * c4) = v;
+                    v[it] = reinterpret_cast<const float4 *>(a.ev + (int64_t)col * DP + kc * K::KC)[c4];
                 }
+                EntryMeta em{0.0f, 0u};
+                if (kc == 0)
+                    em = load_entry_meta(a, c0);
+#pragma unroll
+                for (int it = 0; it < kIt; ++it) {
+                    const int i = (int)threadIdx.x + 256 * it, r = i / (K::KC / 4), c4 = i - r * (K::KC / 4);
+                    *reinterpret_cast<float4 *>(tile + r * K::LDSW + 4 * c4) = v[it];
+                }
+                if (kc == 0)
+                    put_entry_meta(em, ten, tea);
                 __syncthreads();
                 if constexpr (K::NK > 1) {
 #pragma unroll
@@ -227,8 +278,8 @@ __global__ __launch_bounds__(256) void k_entry_keys(const KeyArgs a)
             }
         }
         __syncthreads();  // the tile's products are done: its LDS stages the keys
-        store_keys(a, acc, c0, (int64_t)blockIdx.x * 64 + wave * 16, rl, lq, rn, qw, qm, mq, tile + wave * 16 * 68,
-                   gms + wave * 16 * kGmStride, (c0 - cbeg) / 16);
+        store_keys<DEF>(a, acc, c0, (int64_t)blockIdx.x * 64 + wave * 16, rl, lq, rn, qw, qm, mq, ten, tea,
+                        tile + wave * 16 * 68, gms + wave * 16 * kGmStride, (c0 - cbeg) / 16);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -241,12 +292,14 @@ __global__ __launch_bounds__(256) void k_entry_keys(const KeyArgs a)
 // exact bf16 copy of the entry sample: every product is exact in float32 and
 // every partial sum is an integer below 2^24 (rows of at most 128
 // elements), so the keys are bit-identical to the float32 kernel's.
-template <int DP>
+template <int DP, bool DEF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_entry_keys_b16(const KeyArgs a)
 {
     static_assert(DP <= 128 && DP % 32 == 0, "bf16 path: rows of at most 128 elements");
     __shared__ __align__(16) uint16_t t16[64 * (DP + 8) < 2 * 4 * 16 * 68 ? 2 * 4 * 16 * 68 : 64 * (DP + 8)];
     __shared__ float gms[4 * 16 * kGmStride];
+    __shared__ __align__(16) float ten[64];
+    __shared__ __align__(16) uint32_t tea[64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int rl = lane & 15, lq = lane >> 4;
     const int64_t row = (int64_t)blockIdx.x * 64 + wave * 16 + rl;
@@ -282,14 +335,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         for (int s = 0; s < 4; ++s)
             acc[s] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
         {
-            // stage 64 bf16 entry rows, then 4 x NB matrix-core products
+            // stage 64 bf16 entry rows (every load issued before the first
+            // write), then 4 x NB matrix-core products
+            constexpr int kIt = 64 * (DP / 8) / 256;
+            static_assert(kIt * 256 == 64 * (DP / 8), "whole staging rounds");
             __syncthreads();
-            for (int i = threadIdx.x; i < 64 * (DP / 8); i += 256) {
-                const int r = i / (DP / 8), c8 = i - r * (DP / 8);
+            uint4 v[kIt];
+#pragma unroll
+            for (int it = 0; it < kIt; ++it) {
+                const int i = (int)threadIdx.x + 256 * it, r = i / (DP / 8), c8 = i - r * (DP / 8);
                 const int col = min(c0 + r, a.ne - 1);
-                const uint4 v = reinterpret_cast<const uint4 *>(a.eb + (int64_t)col * DP)[c8];
-                *reinterpret_cast<uint4 *>(t16 + r * LDSB + 8 * c8) = v;
+                v[it] = reinterpret_cast<const uint4 *>(a.eb + (int64_t)col * DP)[c8];
             }
+            const EntryMeta em = load_entry_meta(a, c0);
+#pragma unroll
+            for (int it = 0; it < kIt; ++it) {
+                const int i = (int)threadIdx.x + 256 * it, r = i / (DP / 8), c8 = i - r * (DP / 8);
+                *reinterpret_cast<uint4 *>(t16 + r * LDSB + 8 * c8) = v[it];
+            }
+            put_entry_meta(em, ten, tea);
             __syncthreads();
 #pragma unroll
             for (int t = 0; t < NB; ++t) {
@@ -302,8 +366,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             }
         }
         __syncthreads();  // the tile's products are done: its LDS stages the keys
-        store_keys(a, acc, c0, (int64_t)blockIdx.x * 64 + wave * 16, rl, lq, rn, qw, qm, mq,
-                   reinterpret_cast<float *>(t16) + wave * 16 * 68, gms + wave * 16 * kGmStride, (c0 - cbeg) / 16);
+        store_keys<DEF>(a, acc, c0, (int64_t)blockIdx.x * 64 + wave * 16, rl, lq, rn, qw, qm, mq, ten, tea,
+                        reinterpret_cast<float *>(t16) + wave * 16 * 68, gms + wave * 16 * kGmStride,
+                        (c0 - cbeg) / 16);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -436,16 +501,27 @@ int launch_seed_rank(const Index *ix, const float *qpad, const float *qnorm, con
               qexact, keys, keys + (size_t)nq * ne_pad, nq, ne, ne_pad, ix->w, ix->abits, ix->hmask};
     const dim3 grid((unsigned)((nq + 63) / 64), (unsigned)((ne_pad + 64 * kKeyTiles - 1) / (64 * kKeyTiles)));
     int rc = NHQ_OK;
+    const bool def = ix->w.mode == NHQ_WEIGHTS_DEFAULT;
     switch (ix->dp) {
-#define NHQ_K(DPV)                                                                 \
-    case DPV:                                                                      \
-        hipLaunchKernelGGL(k_entry_keys<DPV>, grid, dim3(256), 0, st, a);          \
+#define NHQ_K(DPV)                                                                       \
+    case DPV:                                                                            \
+        if (def)                                                                         \
+            hipLaunchKernelGGL((k_entry_keys<DPV, true>), grid, dim3(256), 0, st, a);    \
+        else                                                                             \
+            hipLaunchKernelGGL((k_entry_keys<DPV, false>), grid, dim3(256), 0, st, a);   \
         break;
-#define NHQ_KB(DPV)                                                                \
-    case DPV:                                                                      \
-        if (a.eb && a.qx)                                                          \
-            hipLaunchKernelGGL(k_entry_keys_b16<DPV>, grid, dim3(256), 0, st, a);  \
-        hipLaunchKernelGGL(k_entry_keys<DPV>, grid, dim3(256), 0, st, a);          \
+#define NHQ_KB(DPV)                                                                      \
+    case DPV:                                                                            \
+        if (a.eb && a.qx) {                                                              \
+            if (def)                                                                     \
+                hipLaunchKernelGGL((k_entry_keys_b16<DPV, true>), grid, dim3(256), 0, st, a);  \
+            else                                                                         \
+                hipLaunchKernelGGL((k_entry_keys_b16<DPV, false>), grid, dim3(256), 0, st, a); \
+        }                                                                                \
+        if (def)                                                                         \
+            hipLaunchKernelGGL((k_entry_keys<DPV, true>), grid, dim3(256), 0, st, a);    \
+        else                                                                             \
+            hipLaunchKernelGGL((k_entry_keys<DPV, false>), grid, dim3(256), 0, st, a);   \
         break;
         NHQ_KB(32)
         NHQ_KB(64)
