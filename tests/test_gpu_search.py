@@ -248,6 +248,34 @@ def test_seed_rank_ties_break_by_position(distinct, n_cand, n_entry):
         assert sorted(cand[i].tolist()) == sorted(want[i].tolist())
 
 
+@pytest.mark.parametrize("d", [20, 64, 90, 128])
+@pytest.mark.parametrize("integer", [True, False])
+def test_seed_rank_exact_at_every_padded_width(d, integer):
+    # the key kernels stage a tile's entry rows in 1 to 8 rounds of loads
+    # depending on the padded width (32, 64, 96, 128) and the path (bf16 for
+    # integer data, float32 otherwise); a ragged sample (1,000 entries: the
+    # last tile holds 40) checks the clamped columns and their +inf keys.
+    # Data on a 1/8 grid keeps every float32 product and sum exact, so both
+    # paths must return exactly the oracle's best entries.
+    rng = np.random.default_rng(d + 1000 * integer)
+    n, nq, ne, K = 6000, 80, 1000, 24
+    scale = 1.0 if integer else 0.125
+    x = (rng.integers(0, 256 if integer else 64, size=(n, d)) * scale).astype(np.float32)
+    q = (rng.integers(0, 256 if integer else 64, size=(nq, d)) * scale).astype(np.float32)
+    attrs = rng.integers(0, 3, size=(n, 3)).astype(np.uint8)
+    qa = rng.integers(0, 3, size=(nq, 3)).astype(np.uint8)
+    qa[::4, 0] = 0xFF
+    qa[::7] = 0xFF
+    ix = nhq.nhq_index_create(_dev(x), _dev(attrs), n_entry=ne, seed=17)
+    cand = nhq.nhq_seed_rank(ix, _dev(q), _dev(qa), K).cpu().numpy()
+    entry = oracle.entry_points(17, n, ne)
+    noedge = np.full((ne, 1), -1, np.int32)
+    want, _, _, _, _ = oracle.search(noedge, x[entry], attrs[entry], q, qa, K, K, np.arange(ne, dtype=np.int32),
+                                     n_init=K, key_mode=oracle.KEY32, out_mode=1)
+    for i in range(nq):
+        assert sorted(cand[i].tolist()) == sorted(want[i].tolist()), i
+
+
 @pytest.mark.parametrize("n_entry,n_cand", [(4096, 32), (1000, 64), (8192, 17)])
 def test_seed_rank_float_data_is_the_best_up_to_rounding(n_entry, n_cand):
     # float vectors (the float32 matrix-core path): the keys differ from the
