@@ -8,7 +8,9 @@
 //   exact in bf16),
 // chi over the query's constrained codes; padding columns hold +inf.  A
 // workgroup of 4 waves takes 64 queries (16 per wave) against kKeyTiles
-// tiles of 64 entries.
+// tiles of 64 entries.  Each tile's entry rows, norms and attribute words
+// are staged in LDS with all of the tile's loads in flight at once, and the
+// weight setting is a template argument chosen once per launch.
 //
 // The key kernels also write, per query, the minimum of every 16-entry group
 // of keys.  The K-th smallest group minimum bounds the K-th smallest key
