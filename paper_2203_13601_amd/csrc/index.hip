@@ -169,17 +169,42 @@ __global__ __launch_bounds__(64) void k_pad_queries(const float *__restrict__ q,
                                                     uint32_t *__restrict__ qexact)
 {
     const int lane = threadIdx.x, sub = lane & 15, grp = lane >> 4;
+    const uint32_t fm = (abits >= 32) ? 0xFFFFFFFFu : ((1u << abits) - 1u);
     for (int64_t i0 = 4 * (int64_t)blockIdx.x; i0 < nq; i0 += 4 * (int64_t)gridDim.x) {
         const int64_t i = i0 + grp;
         const bool live = i < nq;
+        // code `sub` of the query (m <= 12), loaded with the row
+        const uint32_t code = (live && sub < m) ? (uint32_t)qa[i * m + sub] : 0xFFu;
         float s = 0.0f;
         bool exact = true;
         if (live) {
-            for (int c = sub; c < dp; c += 16) {
-                const float v = c < d ? q[i * d + c] : 0.0f;
-                qpad[i * dp + c] = v;
-                s = fmaf(v, v, s);
-                exact = exact && v == rintf(v) && fabsf(v) <= 256.0f;
+            // 128 elements per round: every load of a round before its stores;
+            // each lane sums its elements in increasing order
+            for (int c0 = 0; c0 < dp; c0 += 128) {
+                float v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int c = c0 + 16 * u + sub;
+                    v[u] = c < d ? q[i * d + c] : 0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int c = c0 + 16 * u + sub;
+                    if (c < dp) {
+                        qpad[i * dp + c] = v[u];
+                        s = fmaf(v[u], v[u], s);
+                        exact = exact && v[u] == rintf(v[u]) && fabsf(v[u]) <= 256.0f;
+                    }
+                }
+            }
+        }
+        // the codes packed like attr_pack_query, gathered from the group's lanes
+        uint32_t w = 0, mk = 0;
+        for (int j = 0; j < m; ++j) {
+            const uint32_t c = (uint32_t)__shfl((int)code, 16 * grp + j);
+            if (c != 0xFFu) {
+                w |= (c < fm ? c : fm) << (abits * j);
+                mk |= fm << (abits * j);
             }
         }
         // sum over the 16 lanes of the row
@@ -192,8 +217,6 @@ __global__ __launch_bounds__(64) void k_pad_queries(const float *__restrict__ q,
             if (qexact)
                 qexact[i] = all_exact ? 1u : 0u;
             qnorm[i] = s;
-            uint32_t w = 0, mk = 0;
-            attr_pack_query(qa + i * m, m, abits, w, mk);
             qword[i] = w;
             qmask[i] = mk;
         }
