@@ -40,7 +40,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 
-// 64-entry tiles per key workgroup (measured: 8 beats 1, 2 and 4)
+// 64-entry tiles per key workgroup (measured: 8 beats 1, 2, 4 and 16)
 constexpr int kKeyTiles = 8;
 // a wave's group minima of its chunk, 16 rows in LDS (padded row stride)
 constexpr int kGmStride = 4 * kKeyTiles + 1;
