@@ -121,10 +121,12 @@ __device__ void entry_keys_wave(const float *ev, const uint32_t *ea, int ne, con
     for (int e0 = 0; e0 < ne; e0 += 256) {
         const float4 *row[4];
         float acc[4];
+        uint32_t at[4];  // attribute words, loaded with the rows
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int e = min(e0 + 64 * r + lane, ne - 1);
             row[r] = reinterpret_cast<const float4 *>(ev + (int64_t)e * DP);
+            at[r] = ea[e];
             acc[r] = 0.0f;
         }
 #pragma unroll 4
@@ -144,7 +146,7 @@ __device__ void entry_keys_wave(const float *ev, const uint32_t *ea, int ne, con
         for (int r = 0; r < 4; ++r) {
             const int e = e0 + 64 * r + lane;
             if (e < ne)
-                kb[e] = __float_as_uint(w_key32(acc[r], chi_of(ea[e], qword, qmask, hmask), mq, w));
+                kb[e] = __float_as_uint(w_key32(acc[r], chi_of(at[r], qword, qmask, hmask), mq, w));
         }
     }
 }
