@@ -190,9 +190,9 @@ typedef struct {
 typedef struct {
     int32_t n_init;      /* seed set size: the best n_init members of the
                             entry sample start the pool                   [32] */
-    int32_t rerank;      /* r > 0: re-score the first r*k eligible pool entries
-                            from the float32 copy and re-sort (precision form;
-                            r*k <= beam); 0: off                           [0] */
+    int32_t rerank;      /* r in [1, 64]: re-score the first min(r*k, beam)
+                            eligible pool entries from the float32 copy and
+                            re-sort (precision form); 0: off               [0] */
     int32_t output_mode; /* 0: exact attribute matches only (Def. 4);
                             1: the first k pool entries by Gamma           [0] */
     int32_t max_hops;    /* expansion cap; reaching it sets the error word

@@ -771,7 +771,7 @@ typedef struct {
     int64_t id;
     int chi;
     int expanded;
-    int64_t born; /* expansion during which the entry entered the pool */
+    int64_t born; /* expansion step during which the entry entered the pool */
 } pentry;
 
 /* ---------------------------------------------------------- stop network */
@@ -788,6 +788,8 @@ typedef struct {
  *   f6 = ln(key of the next entry to expand / key of k-th eligible), -1 if
  *        fewer than k eligible,
  *   f7 = entries that joined the pool since the last checkpoint / (S R),
+ *        an entry joining in a step when it is still pooled at the end of
+ *        that step (all of the step's neighbours offered),
  *   f8 = min((H - last H at which the eligible top-k changed) / 64, 1);
  *   the top-k fingerprint is the sum mod 2^32 of fmix32(id + 0x9E3779B9)
  *   (MurmurHash3's finaliser) over the first k eligible ids. */
@@ -901,7 +903,7 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
             const uint8_t *qav = qa + iq * (int64_t)m;
             int mq = or_arity(qav, m);
             int size = 0;
-            int64_t ndc = 0, hops = 0, chunk_stamp = 0;
+            int64_t ndc = 0, hops = 0, step_stamp = 0;
             int flag = 0;
 
             /* score v and offer it to the pool (insertion keeps (key, id) order) */
@@ -924,7 +926,7 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
         pool[pos_].id = v_;                                                              \
         pool[pos_].chi = c_;                                                             \
         pool[pos_].expanded = 0;                                                         \
-        pool[pos_].born = chunk_stamp;                                                   \
+        pool[pos_].born = step_stamp;                                                    \
         if (size < L)                                                                    \
             size += 1;                                                                   \
     } while (0)
@@ -1091,17 +1093,17 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
                         stamp[v] = iq;
                         fresh[nf++] = v;
                     }
-                /* offered to the pool in batches of 64; entries of a batch
-                 * still pooled after it count as joined */
+                /* every fresh neighbour is offered to the pool; the step's
+                 * joined count is the number of them still pooled once all
+                 * have been offered (an entry admitted and then pushed out
+                 * by a better one of the same step does not count) */
+                step_stamp += 1;
+                for (int c = 0; c < nf; ++c)
+                    OFFER(fresh[c]);
                 int64_t joined_step = 0;
-                for (int c0 = 0; c0 < nf; c0 += 64) {
-                    chunk_stamp += 1;
-                    for (int c = c0; c < nf && c < c0 + 64; ++c)
-                        OFFER(fresh[c]);
-                    for (int t = 0; t < size; ++t)
-                        if (pool[t].born == chunk_stamp)
-                            joined_step += 1;
-                }
+                for (int t = 0; t < size; ++t)
+                    if (pool[t].born == step_stamp)
+                        joined_step += 1;
                 ins_window += joined_step;
                 /* S1 ends at the first step that adds nothing to the pool;
                  * S2 then expands every pool entry again, with all of its

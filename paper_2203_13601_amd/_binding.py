@@ -140,6 +140,44 @@ def _stream(stream=None) -> ctypes.c_void_p:
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _query_inputs(ix: "Index", queries: torch.Tensor, qattrs: torch.Tensor):
+    """Checks queries float32 [nq][d] and qattrs uint8 [nq][m] against the
+    index (shapes first, then the device), returns contiguous tensors."""
+    d, m = ix.dims()
+    for name, t, dt, wd in (("queries", queries, torch.float32, d), ("qattrs", qattrs, torch.uint8, m)):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError("%s must be a tensor" % name)
+        if t.dtype != dt:
+            raise TypeError("%s must be %s, got %s" % (name, dt, t.dtype))
+        if t.dim() != 2 or t.shape[1] != wd:
+            raise ValueError("%s must be [nq][%d] for this index, got %s" % (name, wd, tuple(t.shape)))
+    if qattrs.shape[0] != queries.shape[0]:
+        raise ValueError("queries and qattrs differ in rows")
+    for name, t in (("queries", queries), ("qattrs", qattrs)):
+        if t.device != ix.device:
+            raise ValueError("%s must be on the index's device %s, got %s" % (name, ix.device, t.device))
+    return queries.contiguous(), qattrs.contiguous()
+
+
+def _out_pair(ix: "Index", out, nq: int, k: int):
+    """The (ids int32 [nq][k], dists float32 [nq][k]) outputs: new tensors,
+    or the caller's after checking shape, dtype, contiguity and device."""
+    if out is None:
+        return (torch.empty((nq, k), dtype=torch.int32, device=ix.device),
+                torch.empty((nq, k), dtype=torch.float32, device=ix.device))
+    ids, dists = out
+    for name, t, dt in (("out ids", ids, torch.int32), ("out dists", dists, torch.float32)):
+        if not isinstance(t, torch.Tensor) or t.dtype != dt:
+            raise TypeError("%s must be a %s tensor" % (name, dt))
+        if tuple(t.shape) != (nq, k):
+            raise ValueError("%s must be [%d][%d], got %s" % (name, nq, k, tuple(t.shape)))
+        if not t.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+        if t.device != ix.device:
+            raise ValueError("%s must be on the index's device %s" % (name, ix.device))
+    return ids, dists
+
+
 def _dev(t: torch.Tensor, dtype, name: str, ndim: int) -> torch.Tensor:
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError("%s must be a CUDA (HIP) tensor" % name)
@@ -151,11 +189,25 @@ def _dev(t: torch.Tensor, dtype, name: str, ndim: int) -> torch.Tensor:
 
 
 class Index:
-    """Owning handle of an nhq_index."""
+    """Owning handle of an nhq_index.  Remembers the device it lives on and
+    (once read) its vector width d and attribute count m, against which the
+    wrappers check every query tensor before a pointer reaches the library
+    (the C calls take no widths)."""
 
-    def __init__(self, handle: ctypes.c_void_p, keep=()):
+    def __init__(self, handle: ctypes.c_void_p, keep=(), device=None, d=None, m=None):
         self._h = handle
         self._keep = keep
+        if device is None:
+            device = torch.device("cuda", torch.cuda.current_device())
+        self.device = torch.device(device)
+        self._d, self._m = d, m
+
+    def dims(self) -> Tuple[int, int]:
+        """(d, m) of the index."""
+        if self._d is None:
+            info = nhq_index_info(self)
+            self._d, self._m = info["d"], info["m"]
+        return self._d, self._m
 
     @property
     def handle(self) -> ctypes.c_void_p:
@@ -204,7 +256,7 @@ def nhq_index_create(vecs: torch.Tensor, attrs: torch.Tensor, stream=None, **par
     _check(lib().nhq_index_create(vecs.data_ptr(), attrs.data_ptr(), vecs.shape[0], vecs.shape[1],
                                   attrs.shape[1], ctypes.byref(p), _stream(stream), ctypes.byref(h)),
            "nhq_index_create")
-    return Index(h)
+    return Index(h, device=vecs.device, d=vecs.shape[1], m=attrs.shape[1])
 
 
 def nhq_nndescent_lists(ix: Index, l: int, s: int, rounds: int, seed: int, stop_frac: float = 0.0,
@@ -266,7 +318,7 @@ def nhq_build_index(vecs: torch.Tensor, attrs: torch.Tensor, stream=None, **para
     _check(lib().nhq_build_index(vecs.data_ptr(), attrs.data_ptr(), vecs.shape[0], vecs.shape[1],
                                  attrs.shape[1], ctypes.byref(p), _stream(stream), ctypes.byref(h)),
            "nhq_build_index")
-    return Index(h)
+    return Index(h, device=vecs.device, d=vecs.shape[1], m=attrs.shape[1])
 
 
 def nhq_index_set_graph(ix: Index, adj: torch.Tensor, stream=None) -> None:
@@ -290,14 +342,14 @@ def nhq_index_info(ix: Index) -> dict:
 
 def nhq_index_get_graph(ix: Index, stream=None) -> torch.Tensor:
     info = nhq_index_info(ix)
-    out = torch.empty((info["n"], info["degree"]), dtype=torch.int32, device="cuda")
+    out = torch.empty((info["n"], info["degree"]), dtype=torch.int32, device=ix.device)
     _check(lib().nhq_index_get_graph(ix.handle, out.data_ptr(), _stream(stream)), "nhq_index_get_graph")
     return out
 
 
 def nhq_index_get_entry(ix: Index, stream=None) -> torch.Tensor:
     info = nhq_index_info(ix)
-    out = torch.empty((info["n_entry"],), dtype=torch.int32, device="cuda")
+    out = torch.empty((info["n_entry"],), dtype=torch.int32, device=ix.device)
     _check(lib().nhq_index_get_entry(ix.handle, out.data_ptr(), _stream(stream)), "nhq_index_get_entry")
     return out
 
@@ -310,8 +362,8 @@ def nhq_index_get_storage(ix: Index, stream=None):
     dp = ctypes.c_int32()
     _d = _padded_dim(info["d"])
     dt = {0: torch.float32, 1: torch.int16, 2: torch.uint8}[st]
-    rows = torch.empty((info["n"], _d), dtype=dt, device="cuda")
-    scales = torch.empty((info["n"],), dtype=torch.float32, device="cuda") if st == 2 else None
+    rows = torch.empty((info["n"], _d), dtype=dt, device=ix.device)
+    scales = torch.empty((info["n"],), dtype=torch.float32, device=ix.device) if st == 2 else None
     _check(lib().nhq_index_get_storage(ix.handle, rows.data_ptr(),
                                        scales.data_ptr() if scales is not None else None,
                                        ctypes.byref(dp), _stream(stream)), "nhq_index_get_storage")
@@ -344,16 +396,11 @@ def nhq_hybrid_search(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, k:
     """Returns (ids int32 [nq,k], dists float32 [nq,k]) and, with
     counters=True, a uint32-valued int32 tensor [nq,2] of (NDC, H).
     route_h >= 2 turns on two-stage routing (Sec. 4.2)."""
-    queries = _dev(queries, torch.float32, "queries", 2)
-    qattrs = _dev(qattrs, torch.uint8, "qattrs", 2)
+    queries, qattrs = _query_inputs(ix, queries, qattrs)
     nq = queries.shape[0]
-    if qattrs.shape[0] != nq:
-        raise ValueError("queries and qattrs differ in rows")
-    if out is None:
-        ids = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
-        dists = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
-    else:
-        ids, dists = out
+    ids, dists = _out_pair(ix, out, nq, int(k))
+    if trace is not None and (trace.nq != nq or trace.feat.device != ix.device):
+        raise ValueError("trace buffers must be for %d queries on %s" % (nq, ix.device))
     cnt = torch.zeros((nq, 2), dtype=torch.int32, device=queries.device) if counters else None
     sp = SearchParams(int(n_init), int(rerank), int(output_mode), int(max_hops), int(visited_log2),
                       int(learned), float(stop_threshold), int(check_every),
@@ -368,10 +415,16 @@ def nhq_hybrid_search(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, k:
 
 def nhq_seed_rank(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, n_cand: int,
                   stream=None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    queries = _dev(queries, torch.float32, "queries", 2)
-    qattrs = _dev(qattrs, torch.uint8, "qattrs", 2)
+    queries, qattrs = _query_inputs(ix, queries, qattrs)
     nq = queries.shape[0]
-    cand = out if out is not None else torch.empty((nq, n_cand), dtype=torch.int32, device=queries.device)
+    if out is None:
+        cand = torch.empty((nq, n_cand), dtype=torch.int32, device=queries.device)
+    else:
+        cand = out
+        if (not isinstance(cand, torch.Tensor) or cand.dtype != torch.int32
+                or tuple(cand.shape) != (nq, int(n_cand)) or not cand.is_contiguous()
+                or cand.device != ix.device):
+            raise ValueError("out must be a contiguous int32 [%d][%d] tensor on %s" % (nq, n_cand, ix.device))
     _check(lib().nhq_seed_rank(ix.handle, queries.data_ptr(), qattrs.data_ptr(), nq, int(n_cand),
                                cand.data_ptr(), _stream(stream)), "nhq_seed_rank")
     return cand
@@ -384,15 +437,17 @@ def nhq_search_seeded(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, ca
                       stream=None, out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None,
                       cap_factor: float = 0.0, trace: Optional["TraceBuffers"] = None,
                       expand: int = 1, route_h: int = 0):
-    queries = _dev(queries, torch.float32, "queries", 2)
-    qattrs = _dev(qattrs, torch.uint8, "qattrs", 2)
-    cand = _dev(cand, torch.int32, "cand", 2)
+    queries, qattrs = _query_inputs(ix, queries, qattrs)
     nq = queries.shape[0]
-    if out is None:
-        ids = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
-        dists = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
-    else:
-        ids, dists = out
+    if (not isinstance(cand, torch.Tensor) or cand.dtype != torch.int32 or cand.dim() != 2
+            or cand.shape[0] != nq):
+        raise ValueError("cand must be an int32 [nq][n_cand] tensor")
+    if cand.device != ix.device:
+        raise ValueError("cand must be on the index's device %s" % ix.device)
+    cand = cand.contiguous()
+    ids, dists = _out_pair(ix, out, nq, int(k))
+    if trace is not None and (trace.nq != nq or trace.feat.device != ix.device):
+        raise ValueError("trace buffers must be for %d queries on %s" % (nq, ix.device))
     cnt = torch.zeros((nq, 2), dtype=torch.int32, device=queries.device) if counters else None
     sp = SearchParams(int(n_init), int(rerank), int(output_mode), int(max_hops), int(visited_log2),
                       int(learned), float(stop_threshold), int(check_every),
@@ -408,11 +463,9 @@ def nhq_search_seeded(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, ca
 
 def nhq_bruteforce_hybrid_knn(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, k: int,
                               stream=None):
-    queries = _dev(queries, torch.float32, "queries", 2)
-    qattrs = _dev(qattrs, torch.uint8, "qattrs", 2)
+    queries, qattrs = _query_inputs(ix, queries, qattrs)
     nq = queries.shape[0]
-    ids = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
-    dists = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
+    ids, dists = _out_pair(ix, None, nq, int(k))
     _check(lib().nhq_bruteforce_hybrid_knn(ix.handle, queries.data_ptr(), qattrs.data_ptr(), nq,
                                            int(k), ids.data_ptr(), dists.data_ptr(), _stream(stream)),
            "nhq_bruteforce_hybrid_knn")
@@ -437,6 +490,9 @@ def nhq_trace_samples(trace: TraceBuffers, counters: Optional[torch.Tensor] = No
     """(X [n,8], y_stop [n], y_beam [n]) training samples of a trace."""
     rows = trace.nq * trace.cap
     dev = trace.feat.device
+    if counters is not None and (counters.dtype != torch.int32 or tuple(counters.shape) != (trace.nq, 2)
+                                 or not counters.is_contiguous() or counters.device != dev):
+        raise ValueError("counters must be a contiguous int32 [%d][2] tensor on %s" % (trace.nq, dev))
     X = torch.empty((max(rows, 1), 8), dtype=torch.float32, device=dev)
     ys = torch.empty((max(rows, 1),), dtype=torch.float32, device=dev)
     yb = torch.empty((max(rows, 1),), dtype=torch.float32, device=dev)
@@ -448,13 +504,33 @@ def nhq_trace_samples(trace: TraceBuffers, counters: Optional[torch.Tensor] = No
     return X[: n.value], ys[: n.value], yb[: n.value]
 
 
-def nhq_mlp_grad(params: torch.Tensor, X: torch.Tensor, y_stop: torch.Tensor, y_beam: torch.Tensor,
-                 lam: float = 1.0, want_z: bool = False, stream=None):
-    """(grad [4866], loss [1], z [n,2] or None) of the mean loss at params."""
-    params = _dev(params, torch.float32, "params", 1)
+def _samples(X: torch.Tensor, y_stop: torch.Tensor, y_beam: torch.Tensor, device):
+    """Training samples X float32 [n][8], y_stop [n], y_beam [n] on `device`."""
+    n = X.shape[0]
+    if (X.dim() != 2 or X.shape[1] != 8 or tuple(y_stop.shape) != (n,)
+            or tuple(y_beam.shape) != (n,)):
+        raise ValueError("X must be [n][8] and y_stop, y_beam [n]")
     X = _dev(X, torch.float32, "X", 2)
     y_stop = _dev(y_stop, torch.float32, "y_stop", 1)
     y_beam = _dev(y_beam, torch.float32, "y_beam", 1)
+    for name, t in (("X", X), ("y_stop", y_stop), ("y_beam", y_beam)):
+        if t.device != device:
+            raise ValueError("%s must be on %s" % (name, device))
+    return X, y_stop, y_beam
+
+
+def _mlp_params(t: torch.Tensor, name: str = "params") -> torch.Tensor:
+    t = _dev(t, torch.float32, name, 1)
+    if t.shape[0] != MLP_PARAMS:
+        raise ValueError("%s must hold %d values" % (name, MLP_PARAMS))
+    return t
+
+
+def nhq_mlp_grad(params: torch.Tensor, X: torch.Tensor, y_stop: torch.Tensor, y_beam: torch.Tensor,
+                 lam: float = 1.0, want_z: bool = False, stream=None):
+    """(grad [4866], loss [1], z [n,2] or None) of the mean loss at params."""
+    params = _mlp_params(params)
+    X, y_stop, y_beam = _samples(X, y_stop, y_beam, params.device)
     n = X.shape[0]
     grad = torch.empty_like(params)
     loss = torch.empty((1,), dtype=torch.float32, device=params.device)
@@ -469,12 +545,12 @@ def nhq_mlp_train(params: torch.Tensor, adam_state: torch.Tensor, step: int, X: 
                   y_stop: torch.Tensor, y_beam: torch.Tensor, epochs: int, batch: int = 1024,
                   lr: float = 1e-3, lam: float = 1.0, seed: int = 0, stream=None):
     """Trains params in place; returns (new step count, loss per epoch)."""
-    for name, t in (("params", params), ("adam_state", adam_state)):
+    for name, t, size in (("params", params, MLP_PARAMS), ("adam_state", adam_state, 2 * MLP_PARAMS)):
         if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
             raise TypeError("%s must be a contiguous float32 CUDA tensor" % name)
-    X = _dev(X, torch.float32, "X", 2)
-    y_stop = _dev(y_stop, torch.float32, "y_stop", 1)
-    y_beam = _dev(y_beam, torch.float32, "y_beam", 1)
+        if t.dim() != 1 or t.shape[0] != size or t.device != params.device:
+            raise ValueError("%s must be [%d] on %s" % (name, size, params.device))
+    X, y_stop, y_beam = _samples(X, y_stop, y_beam, params.device)
     st = ctypes.c_int64(int(step))
     losses = torch.zeros((max(epochs, 1),), dtype=torch.float32, device=params.device)
     _check(lib().nhq_mlp_train(params.data_ptr(), adam_state.data_ptr(), ctypes.byref(st), X.data_ptr(),
@@ -486,13 +562,17 @@ def nhq_mlp_train(params: torch.Tensor, adam_state: torch.Tensor, step: int, X: 
 
 def nhq_mlp_load(ix: Index, params: Optional[torch.Tensor], stream=None) -> None:
     if params is not None:
-        params = _dev(params, torch.float32, "params", 1)
+        params = _mlp_params(params)
+        if params.device != ix.device:
+            raise ValueError("params must be on the index's device %s" % ix.device)
     _check(lib().nhq_mlp_load(ix.handle, params.data_ptr() if params is not None else None,
                               _stream(stream)), "nhq_mlp_load")
 
 
 def nhq_mlp_eval(ix: Index, X: torch.Tensor, stream=None) -> torch.Tensor:
     X = _dev(X, torch.float32, "X", 2)
+    if X.shape[1] != 8 or X.device != ix.device:
+        raise ValueError("X must be [n][8] on the index's device %s" % ix.device)
     Z = torch.empty((X.shape[0], 2), dtype=torch.float32, device=X.device)
     _check(lib().nhq_mlp_eval(ix.handle, X.data_ptr(), X.shape[0], Z.data_ptr(), _stream(stream)),
            "nhq_mlp_eval")
@@ -613,7 +693,7 @@ def nhq_server_create(ix: Index, **params) -> Server:
 
 def nhq_gather_probe(ix: Index, waves: int, rounds: int, seed: int = 1, stream=None):
     """Random-row gather probe; returns (sink tensor, rows read)."""
-    sink = torch.empty((waves, 64), dtype=torch.float32, device="cuda")
+    sink = torch.empty((waves, 64), dtype=torch.float32, device=ix.device)
     rows = ctypes.c_int64()
     _check(lib().nhq_gather_probe(ix.handle, int(waves), int(rounds), int(seed), sink.data_ptr(),
                                   ctypes.byref(rows), _stream(stream)), "nhq_gather_probe")

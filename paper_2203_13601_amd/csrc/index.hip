@@ -836,8 +836,8 @@ int nhq_search_seeded(const nhq_index *h, const float *queries, const uint8_t *q
         return fail(NHQ_EINVAL, "need 1 <= n_init <= 128 and max_hops >= 1");
     if (p.output_mode != 0 && p.output_mode != 1)
         return fail(NHQ_EINVAL, "output_mode must be 0 or 1");
-    if (p.rerank < 0 || (int64_t)p.rerank * k > beam)
-        return fail(NHQ_EINVAL, "rerank * k must not exceed beam");
+    if (p.rerank < 0 || p.rerank > 64)
+        return fail(NHQ_EINVAL, "rerank must be in [0, 64]");
     if (p.visited_log2 != 0 && (p.visited_log2 < 10 || p.visited_log2 > 13))
         return fail(NHQ_EINVAL, "visited_log2 must be 0 or in [10, 13]");
     if (p.route_h < 0 || p.route_h > NHQ_MAX_DEGREE)
@@ -859,7 +859,7 @@ int nhq_search_seeded(const nhq_index *h, const float *queries, const uint8_t *q
     s.L = beam;
     s.n_init = p.n_init;
     s.out_mode = p.output_mode;
-    s.rerank_n = p.rerank * k;
+    s.rerank_n = (int)std::min<int64_t>((int64_t)p.rerank * k, beam);
     s.max_hops = p.max_hops;
     s.hash_log2 = p.visited_log2;
     s.learned = p.learned;

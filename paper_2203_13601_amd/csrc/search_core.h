@@ -259,9 +259,11 @@ __device__ __forceinline__ void weigh_keys(float *skey, const uint32_t *sid, int
 // the sorted pool of capacity `cap`: the pool becomes the cap best of
 // pool + batch by (key, id).  Candidates already pooled are dropped.  `lo`
 // (first position that may hold an unexpanded entry) is lowered to the
-// first insertion point.  Returns the new size.
+// first insertion point.  Returns the new size; `inserted` (nullable) gets
+// the number of candidates written into the pool and `mine` (nullable) each
+// lane's own outcome.
 __device__ int pool_merge(float *pkey, uint32_t *pid, int size, int cap, float ck, uint32_t cw,
-                          bool valid, int &lo, int *inserted = nullptr)
+                          bool valid, int &lo, int *inserted = nullptr, bool *mine = nullptr)
 {
     const int lane = threadIdx.x & 63;
     const uint32_t cm = cw & kIdMask;
@@ -285,6 +287,8 @@ __device__ int pool_merge(float *pkey, uint32_t *pid, int size, int cap, float c
             valid = false;
     }
     const uint64_t bal = __ballot(valid);
+    if (mine)
+        *mine = false;
     if (bal == 0) {
         if (inserted)
             *inserted = 0;
@@ -330,6 +334,8 @@ __device__ int pool_merge(float *pkey, uint32_t *pid, int size, int cap, float c
     }
     if (inserted)
         *inserted = __popcll(__ballot(valid && p + rank < cap));
+    if (mine)
+        *mine = valid && p + rank < cap;
     wsync();
     lo = min(lo, pmin);
     return nsize;
@@ -789,10 +795,36 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
             const float ck = v ? skey[j] : 0.0f;
             const uint32_t cw = v ? sid[j] : 0u;
             int ins = 0;
-            size = pool_merge(pkey, pid, size, L, ck, cw, v, lo, &ins);
-            if (CK)
-                ins_window += ins;
+            bool mine = false;
+            size = pool_merge(pkey, pid, size, L, ck, cw, v, lo, &ins, &mine);
+            // several chunks: mark the staged entries that entered the pool
+            // (bit 31 of a staged word is free) for the count below
+            if (CK && nf > 64 && mine)
+                sid[j] = cw | kExpBit;
             step_ins += ins;
+        }
+        if (CK) {
+            // entries that joined in this step: still pooled once all of its
+            // neighbours were offered.  With one chunk that is every insertion;
+            // with several, an entry admitted by an early chunk may have been
+            // pushed out by a later one.  An admitted entry is still pooled iff
+            // it is no worse, by (key, id), than the final pool's worst entry
+            // (the worst of a full pool only improves).
+            int joined = step_ins;
+            if (nf > 64) {
+                wsync();
+                const bool full = size >= L;
+                const float wk = pkey[size - 1];
+                const uint32_t wm = pid[size - 1] & kIdMask;
+                int cnt = 0;
+                for (int j = lane; j < nf; j += 64) {
+                    const uint32_t sw = sid[j];
+                    if (sw & kExpBit)
+                        cnt += (!full || !lt_key(wk, wm, skey[j], sw & kIdMask)) ? 1 : 0;
+                }
+                joined = (int)wave_sum_u32((uint32_t)cnt);
+            }
+            ins_window += joined;
         }
         if (s1 && step_ins == 0) {
             s1 = false;

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 import torch
 
+import hand_walks
 import oracle
 import synth
 
@@ -233,3 +234,39 @@ def test_trace_with_multi_expansion_matches_oracle(setup):
     assert np.array_equal(tr.hop.cpu().numpy().view(np.uint32)[mask], otr["hop"][mask])
     assert np.array_equal(tr.hash.cpu().numpy().view(np.uint32)[mask], otr["hash"][mask])
     assert np.allclose(tr.feat.cpu().numpy()[mask], otr["feat"][mask], atol=2e-6, rtol=1e-5)
+
+
+# ---- hand-built walks: every checkpoint feature worked out by hand (tests/hand_walks.py)
+
+
+@pytest.mark.parametrize("walk", [hand_walks.chain(), hand_walks.wide_step(1), hand_walks.wide_step(2)],
+                         ids=["chain", "wide_step_S1", "wide_step_S2"])
+def test_trace_features_on_hand_walks(walk):
+    n = len(walk["x"])
+    x = np.asarray(walk["x"], np.float32)[:, None]
+    attrs = np.asarray(walk["attrs"], np.uint8)[:, None]
+    adj = np.asarray(walk["adj"], np.int32)
+    ix = nhq.nhq_index_create(_dev(x), _dev(attrs), n_entry=n, seed=1, degree=adj.shape[1])
+    nhq.nhq_index_set_graph(ix, _dev(adj))
+    entry = nhq.nhq_index_get_entry(ix).cpu().numpy()
+    pos = [int(np.nonzero(entry == s)[0][0]) for s in walk["seeds"]]   # every vertex is in the sample
+    cand = _dev(np.asarray([pos], np.int32))
+    q = _dev(np.zeros((1, 1), np.float32))
+    qa = _dev(np.zeros((1, 1), np.uint8))
+    tr = nhq.TraceBuffers(1, 64)
+    ids, dist, cnt = nhq.nhq_search_seeded(ix, q, qa, cand, walk["k"], walk["L"], n_init=len(pos),
+                                           check_every=walk["check_every"], counters=True, trace=tr,
+                                           expand=walk["expand"])
+    torch.cuda.synchronize()
+    assert ids.cpu().numpy()[0].tolist() == walk["ids"]
+    assert np.allclose(dist.cpu().numpy()[0], walk["gamma"], rtol=1e-6)
+    assert cnt.cpu().numpy()[0].tolist() == [walk["ndc"], walk["hops"]]
+    nck = len(walk["feat"])
+    assert tr.count.cpu().numpy()[0] >= nck
+    assert tr.hop.cpu().numpy()[0, :nck].tolist() == walk["hop"]
+    f = tr.feat.cpu().numpy()[0, :nck].astype(np.float64)
+    assert np.allclose(f, np.asarray(walk["feat"]), rtol=0, atol=2e-6), f
+    hs = tr.hash.cpu().numpy().view(np.uint32)[0, :nck]
+    assert [int(h) for h in hs] == [hand_walks.fingerprint(t) for t in walk["topk"]]
+    assert int(tr.final_hash.cpu().numpy().view(np.uint32)[0]) == hand_walks.fingerprint(walk["ids"])
+    ix.free()

@@ -190,7 +190,7 @@ def test_argument_errors(int_set):
     ix = _index(w, adj, n_entry=32)
     q, qa = _dev(w.q[:2]), _dev(w.qattrs[:2])
     for kw in (dict(k=11, beam=10), dict(k=1, beam=1025), dict(k=0, beam=8),
-               dict(k=10, beam=30, rerank=4), dict(k=10, beam=64, visited_log2=14)):
+               dict(k=10, beam=30, rerank=65), dict(k=10, beam=64, visited_log2=14)):
         k = kw.pop("k")
         beam = kw.pop("beam")
         with pytest.raises(nhq.NHQError):

@@ -194,3 +194,97 @@ def test_serve_rejects_bad_requests(int_index):
             srv.submit(w.q[0], w.qattrs[0], 10, 64, flags=8)
     with pytest.raises(nhq.NHQError):
         nhq.Server(ix, beam_small=128, beam_large=64)
+
+
+# ---- served results against the CPU oracle (graph from the oracle's build)
+@pytest.fixture(scope="module")
+def oracle_int_index():
+    w = synth.small(20000, 128, 240, seed=63, integer=True, n_centres=8, wildcard_arity=True)
+    adj = oracle.build_graph(w.x, w.attrs, l=48, R=32)
+    ix = nhq.nhq_index_create(_dev(w.x), _dev(w.attrs), n_entry=1024, seed=w.build_seed, degree=32)
+    nhq.nhq_index_set_graph(ix, _dev(adj))
+    torch.cuda.synchronize()
+    return w, adj, ix, oracle.entry_points(w.build_seed, w.n, 1024)
+
+
+@pytest.fixture(scope="module")
+def oracle_float_index():
+    w = synth.small(12000, 96, 200, cards=(2, 3, 5, 10), seed=64, wildcard_arity=True, n_centres=16)
+    adj = oracle.build_graph(w.x, w.attrs, l=48, R=32)
+    ix = nhq.nhq_index_create(_dev(w.x), _dev(w.attrs), n_entry=512, seed=w.build_seed, degree=32)
+    nhq.nhq_index_set_graph(ix, _dev(adj))
+    torch.cuda.synchronize()
+    return w, adj, ix, oracle.entry_points(w.build_seed, w.n, 512)
+
+
+def _mixed_stream(w, seed):
+    rng = np.random.default_rng(seed)
+    n = w.nq
+    k = rng.choice(np.array([1, 10, 50, 100], np.int32), size=n)
+    beam = np.maximum(k, rng.choice(np.array([16, 64, 128, 300], np.int32), size=n)).astype(np.int32)
+    flags = (rng.random(n) < 0.2).astype(np.int32) * nhq.SERVE_RAW
+    return k, beam, flags
+
+
+@pytest.mark.parametrize("expand", [1, 4])
+def test_serve_equals_oracle_on_integer_data(oracle_int_index, expand):
+    # mixed k, beams (both memory classes), constraint arities (1..3 of 3
+    # attributes constrained) and output modes in one overlapping stream;
+    # every request must equal the oracle's search id for id and counter for
+    # counter, with distances within 1e-4 of the FP64 Gamma
+    w, adj, ix, entry = oracle_int_index
+    k, beam, flags = _mixed_stream(w, 21 + expand)
+    with nhq.Server(ix, n_init=32, expand=expand, lifetime_s=LIFE, ring=512, slots_small=96,
+                    slots_large=32) as srv:
+        r = srv.run(w.q, w.qattrs, k, beam, synth.poisson_arrivals(w.nq, 100_000.0, 5), flags=flags,
+                    timeout_s=30.0)
+    for kk in np.unique(k):
+        for bb in np.unique(beam):
+            for ff in (0, nhq.SERVE_RAW):
+                sel = np.nonzero((k == kk) & (beam == bb) & (flags == ff))[0]
+                if sel.size == 0:
+                    continue
+                oi, og, ondc, ohops, _ = oracle.search(
+                    adj, w.x, w.attrs, w.q[sel], w.qattrs[sel], int(kk), int(bb), entry, n_init=32,
+                    key_mode=oracle.KEY32, expand=expand, out_mode=1 if ff else 0)
+                assert np.array_equal(r["ids"][sel, :kk], oi), (kk, bb, ff)
+                assert np.array_equal(r["counters"][sel, 0], ondc), (kk, bb, ff)
+                assert np.array_equal(r["counters"][sel, 1], ohops), (kk, bb, ff)
+                got = r["dists"][sel, :kk].astype(np.float64)
+                fin = np.isfinite(og)
+                assert np.array_equal(np.isfinite(got), fin)
+                assert np.allclose(got[fin], og[fin], rtol=1e-4)
+
+
+def test_serve_float_data_against_oracle(oracle_float_index):
+    # float data: orders can differ only at near-ties.  Results must overlap
+    # the oracle's search (FP64 keys) at >= 0.99, carry FP64-exact Gamma, and
+    # score the same Recall@k against the exact answers (oracle brute force)
+    # within 0.005
+    w, adj, ix, entry = oracle_float_index
+    n = w.nq
+    k = np.full(n, 10, np.int32)
+    beam = np.full(n, 64, np.int32)
+    with nhq.Server(ix, n_init=16, expand=2, lifetime_s=LIFE, ring=512, slots_small=64,
+                    beam_large=-1) as srv:
+        r = srv.run(w.q, w.qattrs, k, beam, synth.poisson_arrivals(n, 100_000.0, 6), timeout_s=30.0)
+    ids, dist = r["ids"][:, :10], r["dists"][:, :10]
+    oi, og, _, _, _ = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, 64, entry, n_init=16,
+                                    expand=2)
+    # share of each result set found in the other (two empty answers agree)
+    overlap = np.mean([len(set(a[a >= 0]) & set(b[b >= 0])) / max(1, (a >= 0).sum(), (b >= 0).sum())
+                       if (a >= 0).any() or (b >= 0).any() else 1.0 for a, b in zip(ids, oi)])
+    assert overlap >= 0.99, overlap
+    for i in range(n):
+        mq = oracle.arity(w.qattrs[i])
+        for v, g in zip(ids[i], dist[i]):
+            if v < 0:
+                assert np.isinf(g)
+                continue
+            assert oracle.chi(w.qattrs[i], w.attrs[v]) == 0
+            want = oracle.gamma(oracle.delta(w.q[i], w.x[v]), 0, mq)
+            assert abs(g - want) <= 1e-4 * max(want, 1e-30)
+    gi, gd, _ = oracle.bruteforce(w.x, w.attrs, w.q, w.qattrs, 10)
+    rs = oracle.recall(ids, w.x, w.attrs, w.q, w.qattrs, gi, gd, 10).mean()
+    ro = oracle.recall(oi, w.x, w.attrs, w.q, w.qattrs, gi, gd, 10).mean()
+    assert abs(rs - ro) <= 0.005, (rs, ro)

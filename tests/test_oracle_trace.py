@@ -1,10 +1,12 @@
 """Pins of the oracle's checkpoint traces and learned stop (the stop
-network's inputs), by properties that hold whatever the data."""
+network's inputs): every feature worked out by hand on small hand-built walks
+(tests/hand_walks.py), and properties that hold whatever the data."""
 import math
 
 import numpy as np
 import pytest
 
+import hand_walks
 import oracle
 import synth
 
@@ -113,3 +115,41 @@ def test_learned_hop_budget_and_single_checkpoint(traced):
     reached = o2[3] > 4
     assert (o2[5]["count"][reached] == 1).all()
     assert (o1[5]["count"][reached] == np.minimum(64, (o1[3][reached] - 1) // 4)).all()
+
+
+# ---- every feature pinned exactly on hand-built walks (tests/hand_walks.py)
+
+def _run_hand(walk, key_mode):
+    x = np.asarray(walk["x"], np.float32)[:, None]
+    attrs = np.asarray(walk["attrs"], np.uint8)[:, None]
+    adj = np.asarray(walk["adj"], np.int32)
+    q = np.zeros((1, 1), np.float32)
+    qa = np.zeros((1, 1), np.uint8)
+    return oracle.search(adj, x, attrs, q, qa, walk["k"], walk["L"], np.asarray(walk["seeds"], np.int32),
+                         n_init=len(walk["seeds"]), key_mode=key_mode, check_every=walk["check_every"],
+                         trace_cap=64, expand=walk["expand"])
+
+
+@pytest.mark.parametrize("walk", [hand_walks.chain(), hand_walks.wide_step(1), hand_walks.wide_step(2)],
+                         ids=["chain", "wide_step_S1", "wide_step_S2"])
+@pytest.mark.parametrize("key_mode", [oracle.KEY64, oracle.KEY32])
+def test_features_exact_on_hand_walks(walk, key_mode):
+    ids, gam, ndc, hops, flag, tr = _run_hand(walk, key_mode)
+    assert ids[0].tolist() == walk["ids"]
+    assert np.allclose(gam[0], walk["gamma"], rtol=1e-12)
+    assert int(ndc[0]) == walk["ndc"] and int(hops[0]) == walk["hops"]
+    nck = len(walk["feat"])
+    assert tr["count"][0] >= nck
+    assert tr["hop"][0, :nck].tolist() == walk["hop"]
+    for t in range(nck):
+        assert np.allclose(tr["feat"][0, t], walk["feat"][t], rtol=0, atol=1e-12), (t, tr["feat"][0, t])
+        assert int(tr["hash"][0, t]) == hand_walks.fingerprint(walk["topk"][t])
+    assert int(tr["final_hash"][0]) == hand_walks.fingerprint(walk["ids"])
+
+
+def test_joined_counts_survivors_of_the_whole_step():
+    # the wide step offers 128 neighbours, of which the first 64 are all
+    # pushed out by the last 64: f7 counts 64 joins, whatever the batching
+    walk = hand_walks.wide_step(1)
+    _, _, _, _, _, tr = _run_hand(walk, oracle.KEY32)
+    assert tr["feat"][0, 0, 6] == 1.0
