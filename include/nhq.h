@@ -332,6 +332,28 @@ int nhq_search_seeded(const nhq_index *ix, const float *queries, const uint8_t *
                       const int32_t *cand, int32_t n_cand, int32_t k, int32_t beam,
                       const nhq_search_params *sp, int32_t *ids, float *dists, void *stream);
 
+/* Allocation-free nhq_hybrid_search, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments and results as
+ * nhq_hybrid_search (bit-identical outputs), but the seed ranking's scratch
+ * (the candidates and the ranking's padded queries, key matrix and group
+ * minima) lives in a fixed array of NHQ_NOALLOC_SCRATCH_BYTES in each
+ * device's memory, which the library holds until the process ends; the call
+ * itself allocates and frees nothing (its first call on a device looks the
+ * array's address up once).  The batch must fit: with ks = min(n_entry,
+ * n_init + 8), dp the padded width and E = n_entry rounded up to 64, it
+ * needs roundup256(4 nq ks) + 4 (nq dp + 5 nq + nq E 17 / 16 + 64) bytes;
+ * larger batches fail with NHQ_EINVAL (split them), and an entry sample of
+ * more than 8192 with NHQ_ENOTSUP.  Every call on a device shares that
+ * device's array and leaves its contents behind (nothing in it needs to start
+ * at zero): calls that overlap on one device -- on different streams or from
+ * different host threads -- race and must not be made; calls ordered on one
+ * stream are safe. */
+#define NHQ_NOALLOC_SCRATCH_BYTES (64u << 20)
+int nhq_hybrid_search_noalloc(const nhq_index *ix, const float *queries, const uint8_t *qattrs,
+                              int64_t nq, int32_t k, int32_t beam, const nhq_search_params *sp,
+                              int32_t *ids, float *dists, void *stream);
+
 /* Exact hybrid k-NN (Def. 4 with Def. 2): exact attribute filter, then the k
  * nearest matches by (delta, id).  Same argument layout as the search; k in
  * [1, 128].  dists are delta (= Gamma for matches), rounded to float32 from a

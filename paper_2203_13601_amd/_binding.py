@@ -102,6 +102,7 @@ def lib() -> ctypes.CDLL:
         "nhq_index_load": ([ctypes.c_char_p, P, P], i32),
         "nhq_hybrid_search": ([P, P, P, i64, i32, i32, P, P, P, P], i32),
         "nhq_bruteforce_hybrid_knn": ([P, P, P, i64, i32, P, P, P], i32),
+        "nhq_hybrid_search_noalloc": ([P, P, P, i64, i32, i32, P, P, P, P], i32),
         "nhq_seed_rank": ([P, P, P, i64, i32, P, P], i32),
         "nhq_search_seeded": ([P, P, P, i64, P, i32, i32, i32, P, P, P, P], i32),
         "nhq_trace_samples": ([P, i64, P, P, P, P, P, P], i32),
@@ -411,6 +412,32 @@ def nhq_hybrid_search(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, k:
                                    int(beam), ctypes.byref(sp), ids.data_ptr(), dists.data_ptr(),
                                    _stream(stream)), "nhq_hybrid_search")
     return (ids, dists, cnt) if counters else (ids, dists)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def nhq_hybrid_search_noalloc(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, k: int, beam: int,
+                              out: Tuple[torch.Tensor, torch.Tensor], n_init: int = 32,
+                              counters: Optional[torch.Tensor] = None, stream=None, **kw):
+    """nhq_hybrid_search through the allocation-free entry point: the caller
+    passes the outputs (and, optionally, an int32 [nq][2] counters tensor);
+    the library uses its fixed per-device scratch.  Other keywords as
+    nhq_hybrid_search (rerank, output_mode, expand, ...)."""
+    queries, qattrs = _query_inputs(ix, queries, qattrs)
+    nq = queries.shape[0]
+    ids, dists = _out_pair(ix, out, nq, int(k))
+    if counters is not None and (counters.dtype != torch.int32 or tuple(counters.shape) != (nq, 2)
+                                 or not counters.is_contiguous() or counters.device != ix.device):
+        raise ValueError("counters must be a contiguous int32 [%d][2] tensor on %s" % (nq, ix.device))
+    sp = SearchParams(int(n_init), int(kw.get("rerank", 0)), int(kw.get("output_mode", 0)),
+                      int(kw.get("max_hops", 0)), int(kw.get("visited_log2", 0)), 0, 0.0, 0,
+                      counters.data_ptr() if counters is not None else None, 0.0, None,
+                      int(kw.get("expand", 1)), int(kw.get("route_h", 0)))
+    _check(lib().nhq_hybrid_search_noalloc(ix.handle, queries.data_ptr(), qattrs.data_ptr(), nq, int(k),
+                                           int(beam), ctypes.byref(sp), ids.data_ptr(), dists.data_ptr(),
+                                           _stream(stream)), "nhq_hybrid_search_noalloc")
+    return ids, dists
 
 
 def nhq_seed_rank(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, n_cand: int,

@@ -743,35 +743,31 @@ size_t seed_rank_words(const Index *ix, int64_t nq)
     return (size_t)nq * ix->dp + 5 * (size_t)nq + (dense ? (size_t)nq * ne_pad / 16 * 17 : 0) + 64;
 }
 
-// nhq_seed_rank with its scratch at byte ws_off of the index's workspace
-// (grown when too small; calls on one index are ordered on one stream, so
-// the workspace is theirs in turn)
-int seed_rank_ws(const nhq_index *h, const float *queries, const uint8_t *qattrs, int64_t nq, int32_t n_cand,
-                 int32_t *cand, void *stream, size_t ws_off)
+int check_seed_rank_args(const Index *ix, const float *queries, const uint8_t *qattrs, int64_t nq,
+                         int32_t n_cand, const int32_t *cand)
 {
-    if (!h)
-        return fail(NHQ_EINVAL, "null index");
-    Index *ix = const_cast<Index *>(&h->impl);
     if (nq < 0 || n_cand < 1 || n_cand > 144)
         return fail(NHQ_EINVAL, "need nq >= 0 and 1 <= n_cand <= 144");
-    if (nq == 0)
-        return NHQ_OK;
-    if (!queries || !cand || (ix->m > 0 && !qattrs))
+    if (nq > 0 && (!queries || !cand || (ix->m > 0 && !qattrs)))
         return fail(NHQ_EINVAL, "null array argument");
-    hipStream_t st = (hipStream_t)stream;
+    return NHQ_OK;
+}
+
+// the seed ranking with its scratch (seed_rank_words(ix, nq) words, 256-byte
+// aligned) at blk; allocates nothing
+int seed_rank_at(const Index *cix, const float *queries, const uint8_t *qattrs, int64_t nq, int32_t n_cand,
+                 int32_t *cand, hipStream_t st, uint32_t *blk)
+{
+    Index *ix = const_cast<Index *>(cix);
     const bool dense = ix->n_entry <= 8192;
     const size_t f_rows = (size_t)nq * ix->dp, f_small = (size_t)nq;
-    int rc = ensure_workspace(ix, ws_off + sizeof(uint32_t) * seed_rank_words(ix, nq));
-    if (rc != NHQ_OK)
-        return rc;
-    uint32_t *blk = reinterpret_cast<uint32_t *>(static_cast<char *>(ix->ws) + ws_off);
     float *qpad = reinterpret_cast<float *>(blk);
     float *qnorm = qpad + f_rows;
     uint32_t *qw = reinterpret_cast<uint32_t *>(qnorm + f_small);
     uint32_t *qm = qw + f_small;
     uint32_t *qx = qm + f_small;
     float *keys = reinterpret_cast<float *>((reinterpret_cast<uintptr_t>(qx + f_small) + 255) & ~uintptr_t(255));
-    rc = launch_pad_queries(queries, qattrs, nq, ix->d, ix->dp, ix->m, ix->abits, qpad, qnorm, qw, qm, qx, st);
+    int rc = launch_pad_queries(queries, qattrs, nq, ix->d, ix->dp, ix->m, ix->abits, qpad, qnorm, qw, qm, qx, st);
     if (rc == NHQ_OK) {
         if (dense)
             rc = launch_seed_rank(ix, qpad, qnorm, qw, qm, qx, nq, n_cand, keys, cand, st);
@@ -781,6 +777,58 @@ int seed_rank_ws(const nhq_index *h, const float *queries, const uint8_t *qattrs
                                    &ix->w);
     }
     return rc;
+}
+
+// nhq_seed_rank with its scratch at byte ws_off of the index's workspace
+// (grown when too small; calls on one index are ordered on one stream, so
+// the workspace is theirs in turn)
+int seed_rank_ws(const nhq_index *h, const float *queries, const uint8_t *qattrs, int64_t nq, int32_t n_cand,
+                 int32_t *cand, void *stream, size_t ws_off)
+{
+    if (!h)
+        return fail(NHQ_EINVAL, "null index");
+    Index *ix = const_cast<Index *>(&h->impl);
+    int rc = check_seed_rank_args(ix, queries, qattrs, nq, n_cand, cand);
+    if (rc != NHQ_OK || nq == 0)
+        return rc;
+    rc = ensure_workspace(ix, ws_off + sizeof(uint32_t) * seed_rank_words(ix, nq));
+    if (rc != NHQ_OK)
+        return rc;
+    uint32_t *blk = reinterpret_cast<uint32_t *>(static_cast<char *>(ix->ws) + ws_off);
+    return seed_rank_at(ix, queries, qattrs, nq, n_cand, cand, (hipStream_t)stream, blk);
+}
+
+// ---- the fixed scratch of nhq_hybrid_search_noalloc: one array in every
+// device's memory (each device that runs the library holds its own copy
+// until the process ends).  Host code never passes `scratch` itself to a
+// kernel (on the host the name is only a stand-in for the symbol); it takes
+// each device's address once, with that device current, and uses that.
+__device__ __align__(256) uint8_t scratch[NHQ_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+int scratch_of_device(int dev, void **out)
+{
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(NHQ_ENOTSUP, "device ordinal beyond the library's scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = 0;
+        NHQ_HIP(hipGetDevice(&cur));
+        if (cur != dev)
+            NHQ_HIP(hipSetDevice(dev));
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != dev)
+            (void)hipSetDevice(cur);
+        if (e != hipSuccess || !ptr)
+            return fail(NHQ_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return NHQ_OK;
 }
 
 }  // namespace
@@ -900,6 +948,46 @@ int nhq_hybrid_search(const nhq_index *h, const float *queries, const uint8_t *q
         return rc;
     int32_t *cand = static_cast<int32_t *>(mix->ws);
     rc = seed_rank_ws(h, queries, qattrs, nq, ks, cand, stream, cbytes);
+    if (rc == NHQ_OK)
+        rc = nhq_search_seeded(h, queries, qattrs, nq, cand, ks, k, beam, sp, ids, dists, stream);
+    return rc;
+}
+
+int nhq_hybrid_search_noalloc(const nhq_index *h, const float *queries, const uint8_t *qattrs,
+                              int64_t nq, int32_t k, int32_t beam, const nhq_search_params *sp,
+                              int32_t *ids, float *dists, void *stream)
+{
+    if (!h)
+        return fail(NHQ_EINVAL, "null index");
+    const Index *ix = &h->impl;
+    if (nq < 0)
+        return fail(NHQ_EINVAL, "nq < 0");
+    if (nq == 0)
+        return NHQ_OK;
+    if (ix->n_entry > 8192)
+        return fail(NHQ_ENOTSUP, "the allocation-free search needs an entry sample of at most 8192");
+    const int n_init = (sp && sp->n_init > 0) ? sp->n_init : 32;
+    if (n_init > 128)
+        return fail(NHQ_EINVAL, "need 1 <= n_init <= 128");
+    const int ks = std::min(ix->n_entry, n_init + kSeedMargin);
+    int rc = check_seed_rank_args(ix, queries, qattrs, nq, ks, ids);
+    if (rc != NHQ_OK)
+        return rc;
+    // the candidates at the start of the scratch, the ranking's scratch after them
+    const size_t cbytes = (sizeof(int32_t) * (size_t)nq * ks + 255) & ~size_t(255);
+    const size_t need = cbytes + sizeof(uint32_t) * seed_rank_words(ix, nq);
+    if (need > (size_t)NHQ_NOALLOC_SCRATCH_BYTES)
+        return fail(NHQ_EINVAL, "batch too large for the allocation-free search: it needs " +
+                                    std::to_string(need) + " bytes of scratch, the fixed scratch holds " +
+                                    std::to_string((size_t)NHQ_NOALLOC_SCRATCH_BYTES) +
+                                    "; split the batch");
+    void *base = nullptr;
+    rc = scratch_of_device(ix->device, &base);
+    if (rc != NHQ_OK)
+        return rc;
+    int32_t *cand = static_cast<int32_t *>(base);
+    uint32_t *blk = reinterpret_cast<uint32_t *>(static_cast<char *>(base) + cbytes);
+    rc = seed_rank_at(ix, queries, qattrs, nq, ks, cand, (hipStream_t)stream, blk);
     if (rc == NHQ_OK)
         rc = nhq_search_seeded(h, queries, qattrs, nq, cand, ks, k, beam, sp, ids, dists, stream);
     return rc;
