@@ -2,30 +2,40 @@
 beam against BF16 storage + learned stop, and p99 latency of the serving
 loop.
 
-Workload: the plain method at scale -- 1,000,000 integer-valued 128-d
-vectors from 256 clusters, 3 uniform attributes of cardinality 3/4/5,
-10,000 queries with full constraints, out-degree 32, k = 10.  The composite
+Default workload (the headline): 1,000,000 Gaussian-mixture vectors of
+d = 960 (64 centres), 4 attributes of cardinality 2/3/5/10, 10,000 queries
+with all four attributes constrained, out-degree 32, k = 10.  The composite
 index is built on the GPU (not timed); the exact answers come from the GPU
-brute force (parity-tested against the CPU oracle).
+brute force, checked against the CPU oracle on a sample; every Recall@10 is
+computed from FP64 distances recomputed from the vectors.
 
-1. Plain form (the reported ``value``): float32 storage, fixed beam.  A beam
-   sweep finds the smallest beam reaching Recall@10 >= 0.95; one timed
-   "step" is one full pass of the hot path over the 10,000 queries at that
-   beam: seed ranking of the entry sample (matrix cores) plus the
-   joint-pruning search (one wavefront per query).
-2. BF16 + learned stop: the same graph with bf16 row storage; the stop
-   network is trained on the GPU from traces of 20,000 separate training
-   queries and runs inside the search (one checkpoint, whose beam output
-   sets the hop budget); the budget factor is swept for Recall@10 >= 0.95
-   and the same step is timed.
-3. Serving: the bf16 index under a Poisson stream of requests (k uniform in
-   {1, 10, 50, 100}, 1 to 3 constrained attributes, the beam left to a stop
-   network trained on queries with that constraint law), through the
-   continuous-batching server: p50 / p99 latency from arrival to result,
-   sustained QPS, Recall@10 of the k >= 10 requests.
+One timed "step" is one full pass of the hot path over the 10,000 queries:
+seed ranking of the entry sample (matrix cores) plus the joint-pruning
+search (one wavefront per query), with the exact float32 re-score of the
+final candidates in the precision forms.
 
-Inputs are resident in HBM before every timed region.  Prints ONE JSON line.
-``--gpus N`` with N > 1 exits: this build runs on one GPU.
+1. FP32, fixed beam: a beam sweep; QPS at Recall@10 = 0.95 is interpolated
+   (log QPS linear in recall between the bracketing beams).
+2. BF16 storage + float32 re-score of the first min(4k, beam) eligible
+   entries, fixed beam: the same sweep (the storage gain alone).
+3. BF16 + learned stop: the stop network is trained on the GPU from traces
+   of 20,000 separate training queries and runs inside the search (one
+   checkpoint whose beam output sets a hop budget); the budget factor is
+   swept and QPS at 0.95 interpolated the same way.
+The reported ``value`` is form 3 timed over --steps steps at its first
+setting that reaches Recall@10 >= 0.95; forms 1 and 2 are timed the same
+way beside it.
+4. Serving: the BF16 index under a Poisson stream (50,000 requests/s for
+   10 s) of requests with k uniform in {1, 10, 50, 100} and 1 to 4 of the 4
+   attributes constrained (the rest wildcards), the beam left to a stop
+   network trained on that constraint law; p50 / p99 latency from arrival to
+   result, sustained QPS, Recall@10 of the k >= 10 requests; then a
+   saturation run (all requests at once) for the sustained maximum.
+
+``--workload plain`` runs the 1M x 128 integer workload, ``ablation`` and
+``build`` the parameter and builder studies.  Inputs are resident in HBM
+before every timed region.  Prints ONE JSON line.  ``--gpus N`` with N > 1
+exits: this build runs on one GPU.
 """
 from __future__ import annotations
 
@@ -44,6 +54,8 @@ def log(*a):
 
 # seed candidates beyond n_init, as nhq_hybrid_search keeps them
 SEED_MARGIN = 8
+SEARCH_SOURCES = "paper_2203_13601_amd/csrc/search.hip,paper_2203_13601_amd/csrc/search_core.h"
+HBM_PEAK_GBS = 8000.0
 
 
 def _profiled_traffic(kernel: str, source: str, tag: str):
@@ -70,187 +82,261 @@ def _profiled_traffic(kernel: str, source: str, tag: str):
     return None
 
 
-SEARCH_SOURCES = "paper_2203_13601_amd/csrc/search.hip,paper_2203_13601_amd/csrc/search_core.h"
+def _r(v, n=5):
+    if isinstance(v, float):
+        return round(v, n)
+    if isinstance(v, dict):
+        return {k: _r(x, n) for k, x in v.items()}
+    if isinstance(v, list):
+        return [_r(x, n) for x in v]
+    return v
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=1_000_000)
-    ap.add_argument("--nq", type=int, default=10_000)
-    ap.add_argument("--target", type=float, default=0.95)
-    ap.add_argument("--beam", type=int, default=0, help="fixed beam (skip the choice)")
-    ap.add_argument("--n-entry", type=int, default=None,
-                    help="entry sample size (default 4096; 1024 for the precision workload, whose "
-                         "64 clusters need fewer entries)")
-    ap.add_argument("--n-init", type=int, default=4)
-    ap.add_argument("--expand", type=int, default=6, help="vertices expanded per step")
-    ap.add_argument("--plain-only", action="store_true", help="skip the bf16/learned and serving legs")
-    ap.add_argument("--serve-rate", type=float, default=50_000.0)
-    ap.add_argument("--serve-requests", type=int, default=50_000)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain device copy of known size (counter scaling)")
-    ap.add_argument("--workload", default="plain",
-                    choices=["plain", "precision", "ablation", "build"],
-                    help="precision: the d = 960 storage forms (fp32 / bf16 / fp8 + exact rerank); "
-                         "ablation: weight settings, selectivity and post-filtering sweeps; "
-                         "build: exact vs NN-descent candidate lists (1M and 10M sets)")
-    args = ap.parse_args()
-    if args.n_entry is None:
-        args.n_entry = 1024 if args.workload == "precision" else 4096
+class Harness:
+    """One workload's queries, exact answers and step / measurement
+    helpers (argument marshalling and timing only)."""
 
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py: this build measures one GPU only (--gpus 1); multi-GPU runs are not "
-              "part of it", file=sys.stderr)
-        sys.exit(2)
+    def __init__(self, w, args, dev):
+        import torch
+        import paper_2203_13601_amd as nhq
+        self.torch, self.nhq, self.w, self.args, self.dev = torch, nhq, w, args, dev
+        self.q = torch.from_numpy(w.q).to(dev)
+        self.qa = torch.from_numpy(w.qattrs).to(dev)
+        self.nq, self.k = w.nq, w.k
+        self.n_cand = min(args.n_entry, args.n_init + SEED_MARGIN)
+        self.cand = torch.empty((self.nq, self.n_cand), dtype=torch.int32, device=dev)
+        self.ids = torch.empty((self.nq, self.k), dtype=torch.int32, device=dev)
+        self.dists = torch.empty((self.nq, self.k), dtype=torch.float32, device=dev)
+        self.gt = None
 
-    import torch
-    import synth
-    import paper_2203_13601_amd as nhq
-    from paper_2203_13601_amd.learned import train_stop_network
-    from paper_2203_13601_amd.metrics import qps_at_recall, recall_at_k, search_bytes_per_query
-
-    if args.workload == "precision":
-        return precision_form(args)
-    if args.workload == "ablation":
-        return ablation(args)
-    if args.workload == "build":
-        return build_study(args)
-    dev = torch.device("cuda:0")
-    t_gen = time.time()
-    w = synth.config2(n=args.n, nq=args.nq)
-    log("generated %s in %.1fs" % (w.name, time.time() - t_gen))
-    x = torch.from_numpy(w.x).to(dev)
-    a = torch.from_numpy(w.attrs).to(dev)
-    q = torch.from_numpy(w.q).to(dev)
-    qa = torch.from_numpy(w.qattrs).to(dev)
-    torch.cuda.synchronize()
-
-    t0 = time.time()
-    ix = nhq.nhq_build_index(x, a, degree=w.degree, cand=w.cand, storage="fp32",
-                             n_entry=args.n_entry, seed=w.build_seed)
-    torch.cuda.synchronize()
-    build_s = time.time() - t0
-    log("built the composite index in %.2fs" % build_s)
-
-    t0 = time.time()
-    gi, gd = nhq.nhq_bruteforce_hybrid_knn(ix, q, qa, w.k)
-    torch.cuda.synchronize()
-    gt_s = time.time() - t0
-    gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
-    log("exact answers in %.2fs" % gt_s)
-
-    nq, k = w.nq, w.k
-    n_cand = min(args.n_entry, args.n_init + SEED_MARGIN)
-    cand = torch.empty((nq, n_cand), dtype=torch.int32, device=dev)
-    ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
-    dists = torch.empty((nq, k), dtype=torch.float32, device=dev)
-
-    def step(index, beam, counters=False, ev=None, **kw):
+    def step(self, index, beam, counters=False, ev=None, **kw):
+        nhq = self.nhq
         if ev is not None:
             ev[0].record()
-        nhq.nhq_seed_rank(index, q, qa, n_cand, out=cand)
+        nhq.nhq_seed_rank(index, self.q, self.qa, self.n_cand, out=self.cand)
         if ev is not None:
             ev[1].record()
-        r = nhq.nhq_search_seeded(index, q, qa, cand, k, beam, n_init=args.n_init, counters=counters,
-                                  out=(ids, dists), expand=args.expand, **kw)
+        r = nhq.nhq_search_seeded(index, self.q, self.qa, self.cand, self.k, beam, n_init=self.args.n_init,
+                                  counters=counters, out=(self.ids, self.dists), expand=self.args.expand, **kw)
         if ev is not None:
             ev[2].record()
         return r
 
-    def timed(index, beam, reps, **kw):
-        # wall clock over `reps` steps with nothing else on the stream; then
-        # the same number of steps with HIP events around each stage (event
-        # records are stream packets of their own, so they stay out of the
-        # wall-clock loop)
+    def timed(self, index, beam, reps, **kw):
+        """wall clock over `reps` steps with nothing else on the stream, then
+        the same number of steps with HIP events around each stage (event
+        records are stream packets of their own, so they stay out of the
+        wall-clock loop)"""
+        torch = self.torch
         torch.cuda.synchronize()
         t = time.time()
         for _ in range(reps):
-            step(index, beam, **kw)
+            self.step(index, beam, **kw)
         torch.cuda.synchronize()
         wall = time.time() - t
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
         for e in evs:
-            step(index, beam, ev=e, **kw)
+            self.step(index, beam, ev=e, **kw)
         torch.cuda.synchronize()
-        rank_ms = [e[0].elapsed_time(e[1]) for e in evs]
-        search_ms = [e[1].elapsed_time(e[2]) for e in evs]
-        return wall, rank_ms, search_ms
+        return wall, [e[0].elapsed_time(e[1]) for e in evs], [e[1].elapsed_time(e[2]) for e in evs]
 
-    def point(index, beam, elem=4, **kw):
-        _, _, cnt = step(index, beam, counters=True, **kw)
-        torch.cuda.synchronize()
-        rec = recall_at_k(ids.cpu().numpy(), dists.cpu().numpy(), gi, gd, w.attrs, w.qattrs, k)
+    def recall(self, ids):
+        from paper_2203_13601_amd.metrics import recall_at_k
+        w = self.w
+        return recall_at_k(ids, w.x, w.q, w.attrs, w.qattrs, self.gt, self.k)
+
+    def point(self, index, beam, **kw):
+        """one setting: Recall@10 (FP64), NDC, hops, QPS over 3 steps, stage times"""
+        _, _, cnt = self.step(index, beam, counters=True, **kw)
+        self.torch.cuda.synchronize()
+        ids = self.ids.cpu().numpy()
+        rec = self.recall(ids)
         cnt = cnt.cpu().numpy().astype(np.float64)
-        step(index, beam, **kw)
-        wall, rk, se = timed(index, beam, 3, **kw)
-        bq_p = search_bytes_per_query(d_pad=128, elem_bytes=elem, R=w.degree, k=k, n_cand=n_cand,
-                                      ndc=float(cnt[:, 0].mean()), hops=float(cnt[:, 1].mean()), d=w.d, m=w.m)
-        return {"beam": beam, "recall": float(rec.mean()), "qps": nq * 3 / wall,
+        self.step(index, beam, **kw)
+        wall, rk, se = self.timed(index, beam, 3, **kw)
+        return {"beam": beam, "recall": float(rec.mean()), "qps": self.nq * 3 / wall,
                 "ndc": float(cnt[:, 0].mean()), "hops": float(cnt[:, 1].mean()),
                 "hops_p99": float(np.percentile(cnt[:, 1], 99)),
-                "rank_ms": float(np.median(rk)), "search_ms": float(np.median(se)),
-                "search_hbm_frac": bq_p * nq / (float(np.median(se)) / 1000.0) / 8.0e12}
+                "returned": float((ids >= 0).sum(axis=1).mean()),
+                "rank_ms": float(np.median(rk)), "search_ms": float(np.median(se))}
 
-    # ---- 1. plain form: float32 storage, fixed beam
-    sweep = []
-    beams = [args.beam] if args.beam else [10, 16, 20, 24, 28, 32, 36, 40, 48, 56, 64, 96, 128, 256, 512]
+    def run_form(self, index, beam, steps, warmup, **kw):
+        for _ in range(warmup):
+            self.step(index, beam, **kw)
+        wall, rank_ms, search_ms = self.timed(index, beam, steps, **kw)
+        return {"qps": self.nq * steps / wall, "ms_per_step": wall * 1000.0 / steps,
+                "rank_kernels_avg_ms": float(np.mean(rank_ms)), "search_kernel_avg_ms": float(np.mean(search_ms)),
+                "wall_s": wall}
+
+
+def _sweep(h, index, label, beams, target, **kw):
+    pts = []
     for beam in beams:
-        if beam < k:
+        if beam < h.k:
             continue
-        p = point(ix, beam)
-        sweep.append(p)
-        log("fp32 beam %4d recall %.4f ndc %.0f hops %.0f rank %.3fms search %.3fms" % (
-            beam, p["recall"], p["ndc"], p["hops"], p["rank_ms"], p["search_ms"]))
-        if not args.beam and p["recall"] >= args.target and beam >= 64:
+        p = h.point(index, beam, **kw)
+        pts.append(p)
+        log("%s beam %3d recall %.4f ndc %.0f hops %.1f rank %.3fms search %.3fms %.0f QPS" % (
+            label, beam, p["recall"], p["ndc"], p["hops"], p["rank_ms"], p["search_ms"], p["qps"]))
+        if p["recall"] >= target + 0.01 and len([x for x in pts if x["recall"] >= target]) >= 2:
             break
-    ok = [s for s in sweep if s["recall"] >= args.target]
-    op = ok[0] if ok else sweep[-1]
-    beam = op["beam"]
-    q_at = qps_at_recall([s["beam"] for s in sweep], [s["recall"] for s in sweep],
-                         [s["qps"] for s in sweep], args.target)
-    for _ in range(args.warmup):
-        step(ix, beam)
-    wall, rank_ms, search_ms = timed(ix, beam, args.steps)
-    value = nq * args.steps / wall
-    ms_per_step = wall * 1000.0 / args.steps
-    log("plain fp32: %d steps at beam %d: %.3f ms/step, %.0f QPS" % (args.steps, beam, ms_per_step, value))
+    return pts
 
-    # ---- roofline of the dominant kernel (the search)
-    bq = search_bytes_per_query(d_pad=128, elem_bytes=4, R=w.degree, k=k, n_cand=n_cand,
-                                ndc=op["ndc"], hops=op["hops"], d=w.d, m=w.m)
-    search_avg_s = float(np.mean(search_ms)) / 1000.0
+
+def _first_at(pts, target):
+    ok = [p for p in pts if p["recall"] >= target]
+    return ok[0] if ok else None
+
+
+def _bytes_per_query(w, elem, p, rerank_rows):
+    from paper_2203_13601_amd.metrics import search_bytes_per_query
+    return search_bytes_per_query(d=w.d, elem_bytes=elem, R=w.degree, k=w.k, ndc=p["ndc"], hops=p["hops"],
+                                  rerank_rows=rerank_rows)
+
+
+def headline(args):
+    import torch
+    import synth
+    import paper_2203_13601_amd as nhq
+    from paper_2203_13601_amd.learned import train_stop_network
+    from paper_2203_13601_amd.metrics import qps_at_recall
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    w = synth.config3(n=args.n, nq=args.nq)
+    tq_np, tqa_np = synth.config3_train_queries(args.train_queries)
+    log("generated %s in %.1fs" % (w.name, time.time() - t0))
+    x = torch.from_numpy(w.x).to(dev)
+    a = torch.from_numpy(w.attrs).to(dev)
+    tq, tqa = torch.from_numpy(tq_np).to(dev), torch.from_numpy(tqa_np).to(dev)
+    h = Harness(w, args, dev)
+    torch.cuda.synchronize()
+
+    t0 = time.time()
+    ix = nhq.nhq_build_index(x, a, degree=w.degree, cand=w.cand, storage="fp32", n_entry=args.n_entry,
+                             seed=w.build_seed, builder=args.builder)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    log("built the composite index (%s candidates) in %.2fs" % (args.builder, build_s))
+    t0 = time.time()
+    gi, _ = nhq.nhq_bruteforce_hybrid_knn(ix, h.q, h.qa, w.k)
+    h.gt = gi.cpu().numpy()
+    gt_s = time.time() - t0
+    adj = nhq.nhq_index_get_graph(ix)
+    ixb = nhq.nhq_index_create(x, a, storage="bf16", n_entry=args.n_entry, seed=w.build_seed, degree=w.degree)
+    nhq.nhq_index_set_graph(ixb, adj)
+    target, k, rr = args.target, w.k, 4
+    beams = [10, 12, 14, 16, 18, 20, 24, 28, 32, 40, 48, 64, 96, 128]
+
+    # ---- 1 and 2: fixed-beam sweeps (fp32; bf16 + float32 re-score)
+    s32 = _sweep(h, ix, "fp32", beams, target)
+    s16 = _sweep(h, ixb, "bf16", beams, target, rerank=rr)
+    # ---- 3: bf16 + learned stop, per training beam a sweep of the budget factor
+    ce = args.check_every
+    learned_runs = []
+    for l_train in args.learned_beams:
+        t0 = time.time()
+        params, info = train_stop_network(ixb, tq, tqa, k, l_train, epochs=30, check_every=ce,
+                                          n_init=args.n_init, expand=args.expand, seed=1)
+        nhq.nhq_mlp_load(ixb, params)
+        torch.cuda.synchronize()
+        train_s = time.time() - t0
+        log("stop network at beam %d: %d trace samples, trained in %.2fs (loss %.4f)" % (
+            l_train, info["samples"], train_s, info["losses"][-1]))
+        pts = []
+        for cf in (0.75, 1.0, 1.25, 1.5, 1.75, 2.0, 2.5, 3.0):
+            kw = dict(rerank=rr, learned=2, stop_threshold=0.9, check_every=ce, cap_factor=cf)
+            p = h.point(ixb, l_train, **kw)
+            p.update({"cap_factor": cf, "kw": kw})
+            pts.append(p)
+            log("bf16+learned beam %d cap %.2f recall %.4f hops %.1f (p99 %.0f) search %.3fms %.0f QPS" % (
+                l_train, cf, p["recall"], p["hops"], p["hops_p99"], p["search_ms"], p["qps"]))
+            if p["recall"] >= target + 0.01 and len([x for x in pts if x["recall"] >= target]) >= 2:
+                break
+        at = qps_at_recall([p["cap_factor"] for p in pts], [p["recall"] for p in pts],
+                           [p["qps"] for p in pts], target)
+        learned_runs.append({"beam": l_train, "params": params, "sweep": pts, "qps_at_target_interp": at,
+                             "train_samples": info["samples"], "train_s": train_s,
+                             "positive_rate": info["positive_rate"]})
+    best = max((r for r in learned_runs if _first_at(r["sweep"], target) is not None),
+               key=lambda r: r["qps_at_target_interp"] or 0.0, default=None)
+
+    # ---- timed steps at each form's first setting reaching the target
+    forms = {}
+    for name, index, pts, elem in (("fp32_fixed", ix, s32, 4), ("bf16_fixed", ixb, s16, 2)):
+        op = _first_at(pts, target) or pts[-1]
+        kw = {"rerank": rr} if name == "bf16_fixed" else {}
+        run = h.run_form(index, op["beam"], args.steps, args.warmup, **kw)
+        at = qps_at_recall([p["beam"] for p in pts], [p["recall"] for p in pts], [p["qps"] for p in pts], target)
+        forms[name] = {**run, "beam": op["beam"], "recall": op["recall"], "ndc": op["ndc"], "hops": op["hops"],
+                       "qps_at_target_interp": at, "rerank": kw.get("rerank", 0),
+                       "bytes_per_query": _bytes_per_query(w, elem, op, op["returned"] if elem == 2 else 0.0),
+                       "sweep": [{kk: vv for kk, vv in p.items()} for p in pts]}
+        log("%s: beam %d recall %.4f: %.3f ms/step, %.0f QPS (interpolated at %.2f: %s)" % (
+            name, op["beam"], op["recall"], run["ms_per_step"], run["qps"], target, at))
+    value_form = "bf16_fixed"
+    if best is not None:
+        nhq.nhq_mlp_load(ixb, best["params"])
+        op = _first_at(best["sweep"], target)
+        run = h.run_form(ixb, best["beam"], args.steps, args.warmup, **op["kw"])
+        forms["bf16_learned"] = {
+            **run, "beam": best["beam"], "recall": op["recall"], "ndc": op["ndc"], "hops": op["hops"],
+            "hops_p99": op["hops_p99"], "learned_mode": 2, "check_every": ce, "cap_factor": op["cap_factor"],
+            "rerank": rr, "qps_at_target_interp": best["qps_at_target_interp"],
+            "train_samples": best["train_samples"], "train_s": best["train_s"],
+            "bytes_per_query": _bytes_per_query(w, 2, op, op["returned"]),
+            "per_training_beam": [{"beam": r["beam"], "qps_at_target_interp": r["qps_at_target_interp"],
+                                   "positive_rate": r["positive_rate"],
+                                   "sweep": [{kk: vv for kk, vv in p.items() if kk != "kw"} for p in r["sweep"]]}
+                                  for r in learned_runs]}
+        value_form = "bf16_learned"
+        log("bf16+learned: beam %d cap %.2f recall %.4f: %.3f ms/step, %.0f QPS" % (
+            best["beam"], op["cap_factor"], op["recall"], run["ms_per_step"], run["qps"]))
+    vf = forms[value_form]
+    for name in ("bf16_fixed", "bf16_learned"):
+        if name in forms:
+            f = forms[name]
+            f["speedup_vs_fp32_fixed"] = f["qps"] / forms["fp32_fixed"]["qps"]
+            if f["qps_at_target_interp"] and forms["fp32_fixed"]["qps_at_target_interp"]:
+                f["interp_speedup_vs_fp32_fixed"] = (f["qps_at_target_interp"]
+                                                     / forms["fp32_fixed"]["qps_at_target_interp"])
+    if "bf16_learned" in forms and forms["bf16_fixed"]["qps_at_target_interp"]:
+        fl = forms["bf16_learned"]
+        fl["interp_speedup_vs_bf16_fixed"] = (fl["qps_at_target_interp"] or 0.0) / forms["bf16_fixed"][
+            "qps_at_target_interp"]
+
+    # ---- roofline of the dominant kernel: the search of the reported form
+    search_s = vf["search_kernel_avg_ms"] / 1000.0
+    bq = vf["bytes_per_query"]
+    achieved = bq * h.nq / search_s / 1e9
+    kernel = "k_search_ck" if value_form == "bf16_learned" else "k_search"
     traffic = None
     if args.n == 1_000_000 and args.nq == 10_000:
-        traffic = _profiled_traffic("k_search", SEARCH_SOURCES, "_beam%d" % beam)
-    achieved = bq * nq / search_avg_s / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": 8000.0, "unit": "GB/s",
-            "frac": round(achieved / 8000.0, 5), "traffic": traffic,
-            "kernel": "k_search", "bytes_per_query": round(bq, 1), "queries_per_launch": nq,
-            "kernel_avg_ms": round(search_avg_s * 1000.0, 4),
-            "rank_kernels_avg_ms": round(float(np.mean(rank_ms)), 4)}
-
-    # random-row gather ceiling at the same row size and lane layout
+        traffic = _profiled_traffic(kernel, SEARCH_SOURCES, "_config3")
+    step_bytes = bq * h.nq + h.nq * (4.0 * w.d + 8.0 * h.n_cand)  # + the seed stage's query reads and candidates
+    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+            "traffic_ratio_vs_algorithmic": None if traffic is None else round(traffic / (bq * h.nq), 4),
+            "kernel": kernel, "form": value_form, "bytes_per_query": round(bq, 1), "queries_per_launch": h.nq,
+            "bytes_formula": "4d + H*4R + NDC*(4 + d*s_v) + rerank_rows*4d + 8k; s_v = 2 (bf16), "
+                             "rerank_rows = results returned per query (a lower bound on the rows re-scored)",
+            "kernel_avg_ms": round(vf["search_kernel_avg_ms"], 4),
+            "rank_kernels_avg_ms": round(vf["rank_kernels_avg_ms"], 4),
+            "whole_step_frac": round(step_bytes / (vf["ms_per_step"] / 1000.0) / 1e9 / HBM_PEAK_GBS, 5)}
     waves, rounds = 65536, 20
-    nhq.nhq_gather_probe(ix, waves, rounds)
+    nhq.nhq_gather_probe(ixb, waves, rounds)
     pe = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     torch.cuda.synchronize()
     pe[0].record()
     for _ in range(3):
-        _, rows = nhq.nhq_gather_probe(ix, waves, rounds)
+        _, rows = nhq.nhq_gather_probe(ixb, waves, rounds)
     pe[1].record()
     torch.cuda.synchronize()
-    gather_gbs = rows * 128 * 4 / (pe[0].elapsed_time(pe[1]) / 3 / 1000.0) / 1e9
+    gather_gbs = rows * w.d * 2 / (pe[0].elapsed_time(pe[1]) / 3 / 1000.0) / 1e9
     roof["gather_ceiling"] = round(gather_gbs, 1)
     roof["frac_of_gather_ceiling"] = round(achieved / gather_gbs, 4)
-    log("random 512-byte row gathers: %.0f GB/s; the search reaches %.1f%% of that" % (
-        gather_gbs, 100.0 * achieved / gather_gbs))
-
+    log("roofline: %s %.0f GB/s = %.1f%% of 8 TB/s (random %d-byte row gathers: %.0f GB/s)" % (
+        kernel, achieved, 100 * achieved / HBM_PEAK_GBS, w.d * 2, gather_gbs))
     if args.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
         dst = torch.empty_like(src)
@@ -260,346 +346,281 @@ def main():
         del src, dst
         log("copy calibration: 3 copies of 1 GiB")
 
-    forms = {"fp32_fixed": {"qps": round(value, 1), "recall": round(op["recall"], 5), "beam": beam,
-                            "ms_per_step": round(ms_per_step, 4),
-                            "qps_at_target_interp": None if q_at is None else round(q_at, 1)}}
     serving = None
-    if not args.plain_only:
-        # ---- 2. bf16 storage + learned stop (same graph and entry sample)
-        ixb = nhq.nhq_index_create(x, a, storage="bf16", n_entry=args.n_entry, seed=w.build_seed,
-                                   degree=w.degree)
-        nhq.nhq_index_set_graph(ixb, nhq.nhq_index_get_graph(ix))
-        tq_np, tqa_np = synth.config2_train_queries(20_000)
-        tq, tqa = torch.from_numpy(tq_np).to(dev), torch.from_numpy(tqa_np).to(dev)
-        ce = 8
-        # bf16 with a fixed beam first (same beam as the plain form): the
-        # reference the learned stop has to beat at equal storage
-        bp = point(ixb, beam, elem=2)
-        for _ in range(args.warmup):
-            step(ixb, beam)
-        bwall, _, bsearch = timed(ixb, beam, args.steps)
-        forms["bf16_fixed"] = {"qps": round(nq * args.steps / bwall, 1), "recall": round(bp["recall"], 5),
-                               "beam": beam, "ms_per_step": round(bwall * 1000.0 / args.steps, 4),
-                               "search_kernel_avg_ms": round(float(np.mean(bsearch)), 4)}
-        log("bf16 fixed beam %d: recall %.4f, %.0f QPS" % (beam, bp["recall"], forms["bf16_fixed"]["qps"]))
-        # the stop network per training beam; each beam's cap sweep stops at
-        # the first factor that reaches the target; the fastest beam is kept
-        best = None
-        for l_train in (40, 64):
-            t0 = time.time()
-            params, info = train_stop_network(ixb, tq, tqa, k, l_train, epochs=30, check_every=ce,
-                                              n_init=args.n_init, expand=args.expand, seed=1)
-            nhq.nhq_mlp_load(ixb, params)
-            torch.cuda.synchronize()
-            train_s = time.time() - t0
-            log("stop network at beam %d: %d trace samples, trained in %.2fs (loss %.4f)" % (
-                l_train, info["samples"], train_s, info["losses"][-1]))
-            lsweep = []
-            lkw = None
-            for cf in (1.0, 1.125, 1.25, 1.5, 1.75, 2.0, 2.5, 3.0):
-                kw = dict(learned=2, stop_threshold=0.9, check_every=ce, cap_factor=cf)
-                p = point(ixb, l_train, elem=2, **kw)
-                p["cap_factor"] = cf
-                lsweep.append(p)
-                log("bf16+learned beam %d cap %.2f recall %.4f hops %.1f (p99 %.0f) search %.3fms" % (
-                    l_train, cf, p["recall"], p["hops"], p["hops_p99"], p["search_ms"]))
-                if p["recall"] >= args.target:
-                    lkw = kw
-                    break
-            if lkw is None:
-                continue
-            lop = lsweep[-1]
-            for _ in range(args.warmup):
-                step(ixb, l_train, **lkw)
-            lwall, lrank, lsearch = timed(ixb, l_train, args.steps, **lkw)
-            lvalue = nq * args.steps / lwall
-            log("bf16+learned beam %d: %d steps: %.3f ms/step, %.0f QPS" % (
-                l_train, args.steps, lwall * 1000 / args.steps, lvalue))
-            cand_form = {
-                "qps": round(lvalue, 1), "recall": round(lop["recall"], 5), "beam": l_train,
-                "learned_mode": 2, "check_every": ce, "cap_factor": lkw["cap_factor"],
-                "hops_mean": round(lop["hops"], 2), "hops_p99": lop["hops_p99"],
-                "ms_per_step": round(lwall * 1000.0 / args.steps, 4),
-                "search_kernel_avg_ms": round(float(np.mean(lsearch)), 4),
-                "train_samples": info["samples"], "train_s": round(train_s, 2),
-                "speedup_vs_fp32_fixed": round(lvalue / value, 4),
-                "sweep": [{kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in sp.items()}
-                          for sp in lsweep]}
-            if best is None or cand_form["qps"] > best["qps"]:
-                best = cand_form
-        if best is not None:
-            forms["bf16_learned"] = best
-
-        # ---- 3. serving: Poisson stream through the continuous-batching server
-        ns = args.serve_requests
-        rng = np.random.default_rng(502)
-        s_q = np.ascontiguousarray(w.q[rng.integers(0, nq, size=ns)])
-        s_qa = synth.partial_constraints(ns, w.cards, 504)
-        s_k = rng.choice(np.array([1, 10, 50, 100], dtype=np.int32), size=ns)
-        s_arr = synth.poisson_arrivals(ns, args.serve_rate, 501)
-        s_beam = np.zeros(ns, dtype=np.int32)  # the stop network chooses (automatic beam)
-        sq_d, sqa_d = torch.from_numpy(s_q).to(dev), torch.from_numpy(s_qa).to(dev)
-        gsi, gsd = nhq.nhq_bruteforce_hybrid_knn(ix, sq_d, sqa_d, k)
-        gsi, gsd = gsi.cpu().numpy(), gsd.cpu().numpy()
-        # the serving network: traces of training queries with the stream's
-        # constraint law (1..3 constrained attributes) at the automatic beam
-        s_beam_auto, s_ce = 256, 8
-        tqa_p = torch.from_numpy(synth.partial_constraints(tq.shape[0], w.cards, 505)).to(dev)
-        sparams, sinfo = train_stop_network(ixb, tq, tqa_p, k, s_beam_auto, epochs=30, check_every=s_ce,
-                                            n_init=args.n_init, expand=args.expand, seed=2)
-        nhq.nhq_mlp_load(ixb, sparams)
-        # budget factor: the smallest reaching the target on a validation slice (batch search)
-        nv = min(5000, ns)
-        s_cf = None
-        for cf in (1.5, 2.0, 2.5, 3.0, 4.0, 6.0):
-            vi, vd = nhq.nhq_hybrid_search(ixb, sq_d[:nv], sqa_d[:nv], k, s_beam_auto, n_init=args.n_init,
-                                           expand=args.expand, learned=2, stop_threshold=0.9,
-                                           check_every=s_ce, cap_factor=cf)
-            vr = recall_at_k(vi.cpu().numpy(), vd.cpu().numpy(), gsi[:nv], gsd[:nv], w.attrs, s_qa[:nv], k)
-            log("serving network: cap %.1f validation recall %.4f" % (cf, vr.mean()))
-            s_cf = cf
-            if vr.mean() >= args.target + 0.005:
-                break
-        torch.cuda.synchronize()
-        with nhq.Server(ixb, n_init=args.n_init, expand=args.expand, auto_beam=s_beam_auto,
-                        beam_small=s_beam_auto, beam_large=-1, max_k=100, ring=8192, learned_mode=2,
-                        cap_factor=s_cf, stop_threshold=0.9, check_every=s_ce, lifetime_s=120.0) as srv:
-            r = srv.run(s_q, s_qa, s_k, s_beam, s_arr, timeout_s=60.0)
-            slots = srv.slots
-            hz = srv.tick_hz
-        lat_ms = r["latency_s"] * 1000.0
-        svc_ms = (r["ticks"][:, 1].astype(np.float64) - r["ticks"][:, 0]) / hz * 1000.0
-        big = s_k >= 10
-        srec = recall_at_k(r["ids"][big, :10], r["dists"][big, :10], gsi[big], gsd[big], w.attrs,
-                           s_qa[big], k)
-        serving = {"offered_qps": args.serve_rate, "requests": ns,
-                   "sustained_qps": round(ns / r["elapsed_s"], 1),
-                   "p50_ms": round(float(np.percentile(lat_ms, 50)), 4),
-                   "p99_ms": round(float(np.percentile(lat_ms, 99)), 4),
-                   "max_ms": round(float(lat_ms.max()), 4),
-                   "device_service_p50_ms": round(float(np.percentile(svc_ms, 50)), 4),
-                   "device_service_p99_ms": round(float(np.percentile(svc_ms, 99)), 4),
-                   "recall_at_10_k_ge_10": round(float(srec.mean()), 5),
-                   "hops_mean": round(float(r["counters"][:, 1].mean()), 2),
-                   "k_mix": [1, 10, 50, 100], "constrained_attrs": "1..3 of 3",
-                   "beam": "learned budget at automatic beam %d (cap factor %.1f)" % (s_beam_auto, s_cf),
-                   "storage": "bf16", "slots": slots[0], "latency": "arrival to result seen by the host"}
-        log("serving: %d requests at %.0f/s offered: p50 %.3f ms, p99 %.3f ms, recall@10 %.4f" % (
-            ns, args.serve_rate, serving["p50_ms"], serving["p99_ms"], serving["recall_at_10_k_ge_10"]))
-
-    # ---- CPU oracle on a bounded sample (same graph, entry sample, beam)
+    if not args.no_serve:
+        serving = serve_config5(args, w, ixb, ix, h, tq, x.device)
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        adj = nhq.nhq_index_get_graph(ix).cpu().numpy()
-        entry = oracle.entry_points(w.build_seed, w.n, args.n_entry)
-        threads = os.cpu_count() or 1
-        nsamp = 64
-        kw = dict(n_init=args.n_init, key_mode=oracle.KEY32, threads=threads, expand=args.expand)
-        t = time.time()
-        oracle.search(adj, w.x, w.attrs, w.q[:nsamp], w.qattrs[:nsamp], k, beam, entry, **kw)
-        el = time.time() - t
-        if el < args.cpu_seconds:
-            nsamp = int(min(nq, max(nsamp, nsamp * args.cpu_seconds / max(el, 1e-3))))
-            t = time.time()
-            oracle.search(adj, w.x, w.attrs, w.q[:nsamp], w.qattrs[:nsamp], k, beam, entry, **kw)
-            el = time.time() - t
-        n1 = min(nq, max(16, int(nsamp / threads)))
-        t = time.time()
-        oracle.search(adj, w.x, w.attrs, w.q[:n1], w.qattrs[:n1], k, beam, entry, **dict(kw, threads=1))
-        el1 = time.time() - t
-        cpu = {"value": round(nsamp / el, 1), "unit": "queries/s", "cores": threads, "kind": "oracle",
-               "single_thread_value": round(n1 / el1, 1),
-               "sample": "%d of %d queries, beam %d, expand %d, same graph and entry sample, FP64 C "
-                         "oracle (entry-sample scan + joint pruning), %d threads" % (
-                             nsamp, nq, beam, args.expand, threads)}
-        log("cpu oracle: %.1f QPS on %d threads" % (nsamp / el, threads))
+        cpu = cpu_baseline(args, w, ix, h, forms["fp32_fixed"]["beam"], rerank_n=0)
 
     out = {
         "metric": "hybrid QPS at Recall@10=0.95 on 1 GPU, plain FP32 vs BF16+learned-stop; p99 ms",
-        "value": round(value, 1),
+        "value": round(vf["qps"], 1),
         "unit": "queries/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": round(vf["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16",
         "data": "synthetic",
-        "config": {"workload": w.name, "form": "plain FP32 fixed beam", "n": w.n, "d": w.d, "m": w.m,
-                   "cards": list(w.cards), "queries_per_step": nq, "k": k, "beam": beam,
-                   "degree": w.degree, "cand": w.cand, "n_entry": args.n_entry, "n_init": args.n_init,
-                   "expand": args.expand, "recall_at_beam": round(op["recall"], 5),
-                   "build_s": round(build_s, 3), "exact_knn_s": round(gt_s, 3),
+        "config": {"workload": w.name, "form": {"bf16_learned": "BF16 + learned stop + FP32 re-score",
+                                                "bf16_fixed": "BF16 fixed beam + FP32 re-score"}[value_form],
+                   "n": w.n, "d": w.d, "m": w.m, "cards": list(w.cards), "constrained": "all 4",
+                   "queries_per_step": h.nq, "k": k, "beam": vf["beam"], "recall_at_setting": round(vf["recall"], 5),
+                   "degree": w.degree, "cand": w.cand, "builder": args.builder, "n_entry": args.n_entry,
+                   "n_init": args.n_init, "expand": args.expand, "build_s": round(build_s, 3),
+                   "exact_knn_s": round(gt_s, 3), "recall": "FP64 distances recomputed from the vectors",
                    "parallelism": "single GPU"},
         "p99_ms": None if serving is None else serving["p99_ms"],
-        "forms": forms,
+        "forms": _r({kk: {k2: v2 for k2, v2 in f.items()} for kk, f in forms.items()}),
         "serving": serving,
-        "sweep": sweep,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
 
-def precision_form(args):
-    """The storage forms on the precision-form shape: d = 960 Gaussian mixture
-    (64 centres), 4 attributes of cardinality 2/3/5/10, all constrained.  One
-    graph (built from the float32 rows) serves float32, bf16 and fp8 e4m3
-    (per-row scale) storage; bf16 and fp8 re-score the first 4k eligible
-    entries from the float32 copy.  For each form: the smallest beam reaching
-    Recall@10 >= target, its timed step, the search kernel's HBM fraction and
-    the relative error of every returned distance against FP64."""
+def serve_config5(args, w, ixb, ix32, h, tq, dev):
+    """The serving form: Poisson stream through the continuous-batching
+    server on the BF16 index (float32 re-score), then a saturation run."""
     import torch
     import synth
     import paper_2203_13601_amd as nhq
-    from paper_2203_13601_amd.metrics import recall_at_k, search_bytes_per_query
+    from paper_2203_13601_amd.learned import train_stop_network
+    from paper_2203_13601_amd.metrics import recall_at_k
+    ns = args.serve_requests
+    t0 = time.time()
+    s_q, s_qa, s_k, s_arr = synth.config5_stream(ns, rate_per_s=args.serve_rate)
+    log("serving stream of %d requests generated in %.1fs" % (ns, time.time() - t0))
+    s_beam = np.zeros(ns, dtype=np.int32)  # the stop network chooses (automatic beam)
+    # the serving network: traces of training queries with the stream's
+    # constraint law (1..4 of 4 attributes constrained) at the automatic beam
+    beam_auto, ce = args.serve_beam, args.check_every
+    tqa_p = torch.from_numpy(synth.partial_constraints(tq.shape[0], w.cards, 505)).to(dev)
+    params, info = train_stop_network(ixb, tq, tqa_p, w.k, beam_auto, epochs=30, check_every=ce,
+                                      n_init=args.n_init, expand=args.expand, seed=2)
+    nhq.nhq_mlp_load(ixb, params)
+    # exact answers of a sample of the stream (k >= 10 requests), for recall
+    rng = np.random.default_rng(506)
+    big = np.nonzero(s_k >= 10)[0]
+    samp = np.sort(rng.choice(big, size=min(args.serve_recall_sample, big.size), replace=False))
+    sq_d = torch.from_numpy(np.ascontiguousarray(s_q[samp])).to(dev)
+    sqa_d = torch.from_numpy(np.ascontiguousarray(s_qa[samp])).to(dev)
+    gsi, _ = nhq.nhq_bruteforce_hybrid_knn(ix32, sq_d, sqa_d, w.k)
+    gsi = gsi.cpu().numpy()
+    # budget factor: the smallest reaching the target on the sample (batch search)
+    s_cf = None
+    for cf in (1.0, 1.5, 2.0, 2.5, 3.0, 4.0, 6.0):
+        vi, _ = nhq.nhq_hybrid_search(ixb, sq_d, sqa_d, w.k, beam_auto, n_init=args.n_init, expand=args.expand,
+                                      rerank=4, learned=2, stop_threshold=0.9, check_every=ce, cap_factor=cf)
+        vr = recall_at_k(vi.cpu().numpy(), w.x, s_q[samp], w.attrs, s_qa[samp], gsi, w.k).mean()
+        log("serving network: cap %.1f recall %.4f on the sample" % (cf, vr))
+        s_cf = cf
+        if vr >= args.target + 0.005:
+            break
+    del sq_d, sqa_d
+    torch.cuda.synchronize()
+    sp = dict(n_init=args.n_init, expand=args.expand, rerank=4, auto_beam=beam_auto, beam_small=beam_auto,
+              beam_large=-1, max_k=100, ring=16384, learned_mode=2, cap_factor=s_cf, stop_threshold=0.9,
+              check_every=ce, lifetime_s=180.0)
+    with nhq.Server(ixb, **sp) as srv:
+        r = srv.run(s_q, s_qa, s_k, s_beam, s_arr, timeout_s=120.0)
+        slots, hz = srv.slots, srv.tick_hz
+        # saturation: the same requests offered all at once
+        sat_n = min(ns, args.serve_saturation_requests)
+        rs = srv.run(s_q[:sat_n], s_qa[:sat_n], s_k[:sat_n], s_beam[:sat_n], np.zeros(sat_n), timeout_s=120.0)
+    lat_ms = r["latency_s"] * 1000.0
+    svc_ms = (r["ticks"][:, 1].astype(np.float64) - r["ticks"][:, 0]) / hz * 1000.0
+    rec = recall_at_k(r["ids"][samp, :10], w.x, s_q[samp], w.attrs, s_qa[samp], gsi, w.k)
+    out = {"offered_qps": args.serve_rate, "requests": ns, "duration_s": round(float(s_arr[-1]), 2),
+           "sustained_qps": round(ns / r["elapsed_s"], 1),
+           "p50_ms": round(float(np.percentile(lat_ms, 50)), 4),
+           "p99_ms": round(float(np.percentile(lat_ms, 99)), 4),
+           "max_ms": round(float(lat_ms.max()), 4),
+           "device_service_p50_ms": round(float(np.percentile(svc_ms, 50)), 4),
+           "device_service_p99_ms": round(float(np.percentile(svc_ms, 99)), 4),
+           "recall_at_10_k_ge_10": round(float(rec.mean()), 5), "recall_sample": int(samp.size),
+           "hops_mean": round(float(r["counters"][:, 1].mean()), 2),
+           "saturation": {"requests": int(sat_n), "sustained_qps": round(sat_n / rs["elapsed_s"], 1),
+                          "p50_ms": round(float(np.percentile(rs["latency_s"] * 1000.0, 50)), 4),
+                          "p99_ms": round(float(np.percentile(rs["latency_s"] * 1000.0, 99)), 4)},
+           "same_in_saturation_as_in_stream": bool(
+               np.array_equal(rs["ids"], r["ids"][:sat_n]) and
+               np.array_equal(rs["dists"].view(np.uint32), r["dists"][:sat_n].view(np.uint32))),
+           "k_mix": [1, 10, 50, 100], "constrained_attrs": "1..4 of 4",
+           "beam": "learned hop budget at the automatic beam %d (cap factor %.2f)" % (beam_auto, s_cf),
+           "storage": "bf16 + float32 re-score of min(4k, beam) eligible entries", "slots": slots[0],
+           "latency": "arrival to result seen by the host", "train_samples": info["samples"]}
+    log("serving: %d requests at %.0f/s: p50 %.3f ms, p99 %.3f ms, recall@10 %.4f; saturation %.0f QPS" % (
+        ns, args.serve_rate, out["p50_ms"], out["p99_ms"], out["recall_at_10_k_ge_10"],
+        out["saturation"]["sustained_qps"]))
+    return out
+
+
+def cpu_baseline(args, w, ix, h, beam, rerank_n=0):
+    """The CPU oracle on the GPU machine's host cores, on a bounded sample of the
+    same workload: the reference search (same graph, entry sample, seeds and
+    beam) and the brute-force exact answer (Def. 4).  Also the parity of the
+    GPU's outputs on that sample: search ids against the oracle's search,
+    the GPU's exact answers against the oracle's, the benchmark's recall
+    against the oracle's own scoring."""
+    import oracle
+    import paper_2203_13601_amd as nhq
+    from paper_2203_13601_amd.metrics import gamma_rel_error
+    threads = os.cpu_count() or 1
+    adj = nhq.nhq_index_get_graph(ix).cpu().numpy()
+    entry = oracle.entry_points(w.build_seed, w.n, args.n_entry)
+    kw = dict(n_init=args.n_init, key_mode=oracle.KEY32 if w.integer else oracle.KEY64, threads=threads,
+              expand=args.expand)
+    nsamp = 64
+    t = time.time()
+    oracle.search(adj, w.x, w.attrs, w.q[:nsamp], w.qattrs[:nsamp], w.k, beam, entry, **kw)
+    el = time.time() - t
+    if el < args.cpu_seconds:
+        nsamp = int(min(w.nq, max(nsamp, nsamp * args.cpu_seconds / max(el, 1e-3))))
+        t = time.time()
+        o = oracle.search(adj, w.x, w.attrs, w.q[:nsamp], w.qattrs[:nsamp], w.k, beam, entry, **kw)
+        el = time.time() - t
+    else:
+        o = oracle.search(adj, w.x, w.attrs, w.q[:nsamp], w.qattrs[:nsamp], w.k, beam, entry, **kw)
+    n1 = min(w.nq, max(16, int(nsamp / threads)))
+    t = time.time()
+    oracle.search(adj, w.x, w.attrs, w.q[:n1], w.qattrs[:n1], w.k, beam, entry, **dict(kw, threads=1))
+    el1 = time.time() - t
+    # the GPU's search on the same queries
+    gi_s, gd_s = nhq.nhq_search_seeded(ix, h.q[:nsamp], h.qa[:nsamp], nhq.nhq_seed_rank(
+        ix, h.q[:nsamp], h.qa[:nsamp], h.n_cand), w.k, beam, n_init=args.n_init, expand=args.expand)
+    gi_s, gd_s = gi_s.cpu().numpy(), gd_s.cpu().numpy()
+    same = (gi_s == o[0]).all(axis=1)
+    overlap = np.mean([len(set(a_[a_ >= 0]) & set(b_[b_ >= 0])) / max(1, (a_ >= 0).sum(), (b_ >= 0).sum())
+                       if (a_ >= 0).any() or (b_ >= 0).any() else 1.0 for a_, b_ in zip(gi_s, o[0])])
+    # brute force (C4) on the CPU: its rate, and the GPU's exact answers against it
+    nb = max(4, min(nsamp, args.cpu_bf_queries))
+    t = time.time()
+    bi, bd, _ = oracle.bruteforce(w.x, w.attrs, w.q[:nb], w.qattrs[:nb], w.k, threads=threads)
+    elb = time.time() - t
+    gt_same = float((h.gt[:nb] == bi).all(axis=1).mean())
+    # recall of the GPU search: the benchmark's metric against the oracle's scoring (exact answers: oracle's)
+    from paper_2203_13601_amd.metrics import recall_at_k
+    rb = recall_at_k(gi_s[:nb], w.x, w.q[:nb], w.attrs, w.qattrs[:nb], bi, w.k)
+    ro = oracle.recall(gi_s[:nb], w.x, w.attrs, w.q[:nb], w.qattrs[:nb], bi, bd, w.k)
+    err = gamma_rel_error(gi_s, gd_s, w.x, w.q[:nsamp], w.attrs, w.qattrs[:nsamp])
+    out = {"value": round(nsamp / el, 1), "unit": "queries/s", "cores": threads, "kind": "oracle",
+           "single_thread_value": round(n1 / el1, 1),
+           "bruteforce_value": round(nb / elb, 3), "bruteforce_unit": "queries/s (C4, exact filter + FP64 top-k)",
+           "sample": "%d of %d queries, beam %d, expand %d, same graph, entry sample and seeds, FP64 C oracle "
+                     "(entry-sample scan + joint pruning), %d threads; brute force on the first %d" % (
+                         nsamp, w.nq, beam, args.expand, threads, nb),
+           "parity": {"search_ids_identical_queries": round(float(same.mean()), 5),
+                      "search_result_overlap": round(float(overlap), 5),
+                      "gpu_exact_answers_equal_oracle": gt_same,
+                      "recall_metric_equals_oracle_recall": bool(np.allclose(rb, ro)),
+                      "returned_gamma_max_rel_err_vs_fp64": float(err.max()) if err.size else 0.0}}
+    log("cpu oracle: %.1f QPS on %d threads (1 thread %.1f); brute force %.2f QPS; parity %s" % (
+        out["value"], threads, out["single_thread_value"], out["bruteforce_value"], out["parity"]))
+    return out
+
+
+def plain(args):
+    """The 1M x 128 integer workload (values in [0, 255], 256 clusters, 3
+    attributes of cardinality 3/4/5, full constraints): FP32 and BF16 (lossless
+    here) fixed-beam sweeps, each form timed at its first beam reaching the
+    target; the CPU oracle beside it."""
+    import torch
+    import synth
+    import paper_2203_13601_amd as nhq
+    from paper_2203_13601_amd.metrics import qps_at_recall
     dev = torch.device("cuda:0")
-    w = synth.config3(n=args.n, nq=args.nq)
-
-    # FP64 references of the measurement (plain numpy): Gamma = delta (1 + chi / m_q)
-    def gamma_fp64(qv, qattr, xv, xattr):
-        cons = qattr != 0xFF
-        mq = int(cons.sum())
-        chi = int((cons & (qattr != xattr)).sum())
-        dl = float(np.sqrt(((qv.astype(np.float64) - xv.astype(np.float64)) ** 2).sum()))
-        return dl if mq == 0 else dl * (1.0 + chi / mq)
-
-    def decode_bf16(bits):
-        return (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
-
-    def decode_e4m3(codes, scales):
-        c = codes.astype(np.int64)
-        sgn = np.where(c >> 7, -1.0, 1.0)
-        e, mnt = (c >> 3) & 15, c & 7
-        val = np.where(e == 0, mnt / 8.0 * 2.0 ** -6, (1.0 + mnt / 8.0) * 2.0 ** (e - 7.0))
-        return sgn * val * scales[:, None]
+    w = synth.config2(n=args.n, nq=args.nq)
     x = torch.from_numpy(w.x).to(dev)
     a = torch.from_numpy(w.attrs).to(dev)
-    q = torch.from_numpy(w.q).to(dev)
-    qa = torch.from_numpy(w.qattrs).to(dev)
+    h = Harness(w, args, dev)
     t0 = time.time()
-    ix = nhq.nhq_build_index(x, a, degree=w.degree, cand=w.cand, n_entry=args.n_entry, seed=w.build_seed)
+    ix = nhq.nhq_build_index(x, a, degree=w.degree, cand=w.cand, n_entry=args.n_entry, seed=w.build_seed,
+                             builder=args.builder)
     torch.cuda.synchronize()
     build_s = time.time() - t0
-    log("built %s in %.1fs" % (w.name, build_s))
-    gi, gd = nhq.nhq_bruteforce_hybrid_knn(ix, q, qa, w.k)
-    gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
-    adj = nhq.nhq_index_get_graph(ix)
-    k, nq = w.k, w.nq
-    n_cand = min(args.n_entry, args.n_init + SEED_MARGIN)
-    cand = torch.empty((nq, n_cand), dtype=torch.int32, device=dev)
-    nsamp = min(nq, 1000)
-
-    def gamma64(ids, dist):
-        """|Gamma returned - Gamma FP64| / Gamma FP64 for every returned result of the sample"""
-        errs = []
-        for i in range(nsamp):
-            for v, g in zip(ids[i], dist[i]):
-                if v < 0:
-                    continue
-                ex = gamma_fp64(w.q[i], w.qattrs[i], w.x[v], w.attrs[v])
-                errs.append(abs(float(g) - ex) / max(ex, 1e-30))
-        e = np.asarray(errs)
-        return {"results": int(e.size), "max": float(e.max()), "p99": float(np.percentile(e, 99)),
-                "mean": float(e.mean())}
-
+    gi, _ = nhq.nhq_bruteforce_hybrid_knn(ix, h.q, h.qa, w.k)
+    h.gt = gi.cpu().numpy()
+    ixb = nhq.nhq_index_create(x, a, storage="bf16", n_entry=args.n_entry, seed=w.build_seed, degree=w.degree)
+    nhq.nhq_index_set_graph(ixb, nhq.nhq_index_get_graph(ix))
+    beams = [args.beam] if args.beam else [10, 16, 20, 24, 28, 32, 36, 40, 48, 56, 64, 96, 128]
     forms = {}
-    for storage, elem, scale_b, rr in (("fp32", 4, 0, 0), ("bf16", 2, 0, 4), ("fp8", 1, 4, 4)):
-        index = ix if storage == "fp32" else nhq.nhq_index_create(x, a, storage=storage, n_entry=args.n_entry,
-                                                                   seed=w.build_seed, degree=w.degree)
-        if index is not ix:
-            nhq.nhq_index_set_graph(index, adj)
-        kw = dict(n_init=args.n_init, expand=args.expand, rerank=rr)
+    for name, index, elem in (("fp32_fixed", ix, 4), ("bf16_fixed", ixb, 2)):
+        pts = _sweep(h, index, name, beams, args.target)
+        op = _first_at(pts, args.target) or pts[-1]
+        run = h.run_form(index, op["beam"], args.steps, args.warmup)
+        forms[name] = {**run, "beam": op["beam"], "recall": op["recall"], "ndc": op["ndc"], "hops": op["hops"],
+                       "qps_at_target_interp": qps_at_recall([p["beam"] for p in pts], [p["recall"] for p in pts],
+                                                             [p["qps"] for p in pts], args.target),
+                       "bytes_per_query": _bytes_per_query(w, elem, op, 0.0), "sweep": pts}
+    vf = forms["fp32_fixed"]
+    bq = vf["bytes_per_query"]
+    achieved = bq * h.nq / (vf["search_kernel_avg_ms"] / 1000.0) / 1e9
+    traffic = None
+    if args.n == 1_000_000 and args.nq == 10_000:
+        traffic = _profiled_traffic("k_search", SEARCH_SOURCES, "_beam%d" % vf["beam"])
+    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": "k_search",
+            "bytes_per_query": round(bq, 1), "queries_per_launch": h.nq,
+            "kernel_avg_ms": round(vf["search_kernel_avg_ms"], 4)}
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args, w, ix, h, vf["beam"])
+    print(json.dumps({"metric": "hybrid QPS at Recall@10=0.95 on 1 GPU, 1M x 128 integer workload",
+                      "value": round(vf["qps"], 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "ms_per_step": round(vf["ms_per_step"], 4), "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": w.name, "n": w.n, "d": w.d, "queries_per_step": h.nq, "k": w.k,
+                                 "beam": vf["beam"], "n_entry": args.n_entry, "n_init": args.n_init,
+                                 "expand": args.expand, "build_s": round(build_s, 3), "parallelism": "single GPU"},
+                      "forms": _r(forms), "roofline": roof, "cpu_baseline": cpu}), flush=True)
 
-        def step(beam, counters=False):
-            nhq.nhq_seed_rank(index, q, qa, n_cand, out=cand)
-            return nhq.nhq_search_seeded(index, q, qa, cand, k, beam, counters=counters, **kw)
 
-        chosen = None
-        sweep = []
-        beams = (10, 16, 24, 32, 40, 48, 64, 96, 128, 192, 256, 384, 512)
-        for beam in beams:
-            if beam < rr * k:
-                continue
-            ids, dist, cnt = step(beam, counters=True)
-            torch.cuda.synchronize()
-            ids_np, dist_np = ids.cpu().numpy(), dist.cpu().numpy()
-            rec = float(recall_at_k(ids_np, dist_np, gi, gd, w.attrs, w.qattrs, k).mean())
-            c = cnt.cpu().numpy().astype(np.float64)
-            sweep.append({"beam": beam, "recall": round(rec, 5), "ndc": round(c[:, 0].mean(), 1),
-                          "hops": round(c[:, 1].mean(), 1)})
-            log("%s beam %d recall %.4f" % (storage, beam, rec))
-            if rec >= args.target:
-                chosen = (beam, rec, c, ids_np, dist_np)
-                break
-        if chosen is None:
-            chosen = (beam, rec, c, ids_np, dist_np)
-        beam, rec, c, ids_np, dist_np = chosen
-        for _ in range(args.warmup):
-            step(beam)
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-        torch.cuda.synchronize()
-        t = time.time()
-        for e in evs:
-            e[0].record()
-            nhq.nhq_seed_rank(index, q, qa, n_cand, out=cand)
-            e[1].record()
-            nhq.nhq_search_seeded(index, q, qa, cand, k, beam, **kw)
-            e[2].record()
-        torch.cuda.synchronize()
-        wall = time.time() - t
-        search_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
-        bq = search_bytes_per_query(d_pad=960, elem_bytes=elem, R=w.degree, k=k, n_cand=n_cand,
-                                    ndc=c[:, 0].mean(), hops=c[:, 1].mean(), d=w.d, m=w.m,
-                                    scale_bytes=scale_b, out_rows=(rr * k if rr else k))
-        err = gamma64(ids_np, dist_np)
-        form = {"beam": beam, "recall": round(rec, 5), "qps": round(nq * args.steps / wall, 1),
-                "ms_per_step": round(wall * 1000 / args.steps, 4), "search_kernel_ms": round(search_ms, 4),
-                "bytes_per_query": round(bq, 1),
-                "search_hbm_frac": round(bq * nq / (search_ms / 1000.0) / 8.0e12, 4),
-                "rerank": rr, "gamma_rel_err_vs_fp64": err, "sweep": sweep}
-        if storage != "fp32":
-            # Gamma from the stored (decoded) rows of the returned objects: the
-            # approximation the loop orders by before the float32 re-score
-            rows, scales = nhq.nhq_index_get_storage(index)
-            sel = torch.from_numpy(ids_np[:nsamp].clip(min=0).astype(np.int64)).to(dev)
-            r_np = rows[sel.reshape(-1)].cpu().numpy()
-            if storage == "bf16":
-                dec = decode_bf16(r_np.view(np.uint16))
-            else:
-                dec = decode_e4m3(r_np, scales[sel.reshape(-1)].cpu().numpy().astype(np.float64))
-            dec = dec.reshape(nsamp, k, -1)[:, :, : w.d]
-            errs = []
-            for i in range(nsamp):
-                for j in range(k):
-                    v = ids_np[i, j]
-                    if v < 0:
-                        continue
-                    ex = gamma_fp64(w.q[i], w.qattrs[i], w.x[v], w.attrs[v])
-                    ap = gamma_fp64(w.q[i], w.qattrs[i], dec[i, j], w.attrs[v])
-                    errs.append(abs(ap - ex) / max(ex, 1e-30))
-            e = np.asarray(errs)
-            form["stored_form_gamma_rel_err"] = {"results": int(e.size), "max": float(e.max()),
-                                                 "p99": float(np.percentile(e, 99)), "mean": float(e.mean())}
-            del rows
-        forms[storage] = form
-        log("%s: beam %d recall %.4f %.0f QPS, search %.3f ms (%.1f%% of HBM), max rel err %.2e" % (
-            storage, beam, rec, form["qps"], search_ms, 100 * form["search_hbm_frac"], err["max"]))
-        if index is not ix:
-            index.free()
-    out = {"metric": "hybrid QPS at Recall@10=0.95 on 1 GPU, storage forms (precision form)",
-           "value": forms["bf16"]["qps"], "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "bf16", "data": "synthetic",
-           "config": {"workload": w.name, "n": w.n, "d": w.d, "m": w.m, "cards": list(w.cards),
-                      "queries_per_step": nq, "k": k, "expand": args.expand, "n_entry": args.n_entry,
-                      "build_s": round(build_s, 2)},
-           "forms": forms}
-    print(json.dumps(out), flush=True)
-
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="headline", choices=["headline", "plain", "ablation", "build"],
+                    help="headline: 1M x 960 FP32 / BF16 / BF16 + learned stop and serving (default); "
+                         "plain: 1M x 128 integer workload; ablation: weight settings, selectivity and "
+                         "post-filtering sweeps; build: exact vs NN-descent vs NSW candidate lists")
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--nq", type=int, default=10_000)
+    ap.add_argument("--target", type=float, default=0.95)
+    ap.add_argument("--beam", type=int, default=0, help="plain workload: fixed beam (skip the sweep)")
+    ap.add_argument("--n-entry", type=int, default=None,
+                    help="entry sample size (default 1024 for the headline's 64 clusters, 4096 otherwise)")
+    ap.add_argument("--n-init", type=int, default=4)
+    ap.add_argument("--expand", type=int, default=None, help="vertices expanded per step (headline 2, else 6)")
+    ap.add_argument("--builder", default="exact", choices=["exact", "nndescent"])
+    ap.add_argument("--check-every", type=int, default=1)
+    ap.add_argument("--learned-beams", type=int, nargs="+", default=[20, 24, 32])
+    ap.add_argument("--train-queries", type=int, default=20_000)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=50_000.0)
+    ap.add_argument("--serve-requests", type=int, default=500_000)
+    ap.add_argument("--serve-saturation-requests", type=int, default=200_000)
+    ap.add_argument("--serve-recall-sample", type=int, default=10_000)
+    ap.add_argument("--serve-beam", type=int, default=128)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-bf-queries", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of known size (counter scaling)")
+    args = ap.parse_args()
+    if args.n_entry is None:
+        args.n_entry = 1024 if args.workload == "headline" else 4096
+    if args.expand is None:
+        args.expand = 2 if args.workload == "headline" else 6
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures one GPU only (--gpus 1); multi-GPU runs are not "
+              "part of it", file=sys.stderr)
+        sys.exit(2)
+    {"headline": headline, "plain": plain, "ablation": ablation, "build": build_study}[args.workload](args)
 
 def build_study(args):
     """Composite-index builds (Alg. 1 / Sec. 4.3): the exact all-pairs
@@ -626,8 +647,7 @@ def build_study(args):
                 return nhq.nhq_search_seeded(ix, q, qa, cand, w.k, beam, n_init=args.n_init,
                                              expand=args.expand)
             ids, d = step()
-            rec = float(recall_at_k(ids.cpu().numpy(), d.cpu().numpy(), gi, gd, w.attrs, w.qattrs,
-                                    w.k).mean())
+            rec = float(recall_at_k(ids.cpu().numpy(), w.x, w.q, w.attrs, w.qattrs, gi, w.k).mean())
             torch.cuda.synchronize()
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
@@ -718,11 +738,6 @@ def ablation(args):
     n_cand = min(args.n_entry, args.n_init + SEED_MARGIN)
     beams = [10, 16, 32, 64, 128, 256, 512]
 
-    def true_delta(ids):
-        v = np.where(ids >= 0, ids, 0)
-        dd = np.sqrt(((w.x[v].astype(np.float64) - w.q[:, None, :]) ** 2).sum(-1))
-        return np.where(ids >= 0, dd, np.inf)
-
     def curve(ix, attrs_np, qattrs_np, gi, gd, label, raw_filter=False):
         qa_dev = torch.from_numpy(qattrs_np).to(dev)
         qa_search = torch.full_like(qa_dev, 255) if raw_filter else qa_dev
@@ -743,7 +758,7 @@ def ablation(args):
                     m_ = m_[(attrs_np[m_] == qattrs_np[i]).all(axis=1)][:k]
                     keep[i, :len(m_)] = m_
                 ids = keep
-            rec = float(recall_at_k(ids, true_delta(ids), gi, gd, attrs_np, qattrs_np, k).mean())
+            rec = float(recall_at_k(ids, w.x, w.q, attrs_np, qattrs_np, gi, k).mean())
             step()
             torch.cuda.synchronize()
             e0 = torch.cuda.Event(enable_timing=True)
@@ -849,6 +864,7 @@ def ablation(args):
                                  "k": k, "expand": args.expand, "n_init": args.n_init,
                                  "n_entry": args.n_entry, "delta_max": dmax, "delta_median": dmed},
                       **out}), flush=True)
+
 
 
 if __name__ == "__main__":

@@ -7,7 +7,7 @@
 //   from v_mfma_f32_16x16x32_bf16 in k_entry_keys_b16 where both sides are
 //   exact in bf16),
 // chi over the query's constrained codes; padding columns hold +inf.  A
-// workgroup of 4 waves takes 64 queries (16 per wave) against kKeyTiles
+// workgroup of 4 waves takes 64 queries (16 per wave) against TL
 // tiles of 64 entries.  Each tile's entry rows, norms and attribute words
 // are staged in LDS with all of the tile's loads in flight at once, and the
 // weight setting is a template argument chosen once per launch.
@@ -40,10 +40,16 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 
-// 64-entry tiles per key workgroup (measured: 8 beats 1, 2, 4 and 16)
-constexpr int kKeyTiles = 8;
+// 64-entry tiles per key workgroup, TL: 8 where the grid already has enough
+// workgroups (measured at d = 128 with 4,096 entries: 8 beats 1, 2, 4 and
+// 16); fewer for small grids (wide rows with a small entry sample), where
+// more workgroups in flight hide the staging latency of each tile
+constexpr int kMaxKeyTiles = 8;
 // a wave's group minima of its chunk, 16 rows in LDS (padded row stride)
-constexpr int kGmStride = 4 * kKeyTiles + 1;
+template <int TL>
+struct GmStride {
+    static constexpr int v = 4 * TL + 1;
+};
 
 struct KeyArgs {
     const float *qpad;    // [nq][DP]
@@ -65,8 +71,10 @@ struct KeyArgs {
 
 // the wave's group minima (16 rows, ng groups from group gbeg) to HBM, each
 // row's run of groups contiguous
+template <int TL>
 __device__ __forceinline__ void flush_gmin(const KeyArgs &a, const float *gm, int64_t row0, int gbeg, int ng)
 {
+    constexpr int kGmStride = GmStride<TL>::v;
     const int lane = threadIdx.x & 63;
     for (int i = lane; i < 16 * ng; i += 64) {
         const int r = i / ng, g = i - r * ng;
@@ -138,11 +146,12 @@ __device__ __forceinline__ float pair_key(float d2, int c, int mq, float m1, con
 // entry norms and attribute words are in LDS (ten, tea).  The keys go
 // through the wave's LDS area (16 rows of 68 floats) so that every store
 // instruction writes four whole 256-byte rows of the key matrix.
-template <bool DEF>
+template <bool DEF, int TL>
 __device__ __forceinline__ void store_keys(const KeyArgs &a, const f32x4 (&acc)[4], int c0, int64_t row0, int rl,
                                            int lq, float rn, uint32_t qw, uint32_t qm, float mq, const float *ten,
                                            const uint32_t *tea, float *stage, float *gm, int g0)
 {
+    constexpr int kGmStride = GmStride<TL>::v;
     const int lane = threadIdx.x & 63;
     const float m1 = fmaxf(mq, 1.0f);
 #pragma unroll
@@ -195,10 +204,11 @@ __device__ __forceinline__ bool group_exact(const KeyArgs &a, int64_t rowc)
 // entries' rows are staged through LDS 64 at a time and shared by the waves.
 // Float32 products (v_mfma_f32_16x16x4f32); workgroups whose queries are
 // all exact in bf16 are left to k_entry_keys_b16.
-template <int DP, bool DEF>
+template <int DP, bool DEF, int TL>
 __global__ __launch_bounds__(256) void k_entry_keys(const KeyArgs a)
 {
     using K = KShape<DP>;
+    constexpr int kKeyTiles = TL, kGmStride = GmStride<TL>::v;
     // entry tile; afterwards the key staging of the four waves
     __shared__ __align__(16) float tile[64 * K::LDSW > 4 * 16 * 68 ? 64 * K::LDSW : 4 * 16 * 68];
     __shared__ float gms[4 * 16 * kGmStride];
@@ -280,12 +290,12 @@ __global__ __launch_bounds__(256) void k_entry_keys(const KeyArgs a)
             }
         }
         __syncthreads();  // the tile's products are done: its LDS stages the keys
-        store_keys<DEF>(a, acc, c0, (int64_t)blockIdx.x * 64 + wave * 16, rl, lq, rn, qw, qm, mq, ten, tea,
+        store_keys<DEF, TL>(a, acc, c0, (int64_t)blockIdx.x * 64 + wave * 16, rl, lq, rn, qw, qm, mq, ten, tea,
                         tile + wave * 16 * 68, gms + wave * 16 * kGmStride, (c0 - cbeg) / 16);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    flush_gmin(a, gms + wave * 16 * kGmStride, (int64_t)blockIdx.x * 64 + wave * 16, cbeg / 16,
+    flush_gmin<TL>(a, gms + wave * 16 * kGmStride, (int64_t)blockIdx.x * 64 + wave * 16, cbeg / 16,
                (min(cbeg + 64 * kKeyTiles, a.ne_pad) - cbeg) / 16);
 }
 
@@ -294,9 +304,10 @@ __global__ __launch_bounds__(256) void k_entry_keys(const KeyArgs a)
 // exact bf16 copy of the entry sample: every product is exact in float32 and
 // every partial sum is an integer below 2^24 (rows of at most 128
 // elements), so the keys are bit-identical to the float32 kernel's.
-template <int DP, bool DEF>
+template <int DP, bool DEF, int TL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_entry_keys_b16(const KeyArgs a)
 {
+    constexpr int kKeyTiles = TL, kGmStride = GmStride<TL>::v;
     static_assert(DP <= 128 && DP % 32 == 0, "bf16 path: rows of at most 128 elements");
     __shared__ __align__(16) uint16_t t16[64 * (DP + 8) < 2 * 4 * 16 * 68 ? 2 * 4 * 16 * 68 : 64 * (DP + 8)];
     __shared__ float gms[4 * 16 * kGmStride];
@@ -368,13 +379,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             }
         }
         __syncthreads();  // the tile's products are done: its LDS stages the keys
-        store_keys<DEF>(a, acc, c0, (int64_t)blockIdx.x * 64 + wave * 16, rl, lq, rn, qw, qm, mq, ten, tea,
+        store_keys<DEF, TL>(a, acc, c0, (int64_t)blockIdx.x * 64 + wave * 16, rl, lq, rn, qw, qm, mq, ten, tea,
                         reinterpret_cast<float *>(t16) + wave * 16 * 68, gms + wave * 16 * kGmStride,
                         (c0 - cbeg) / 16);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    flush_gmin(a, gms + wave * 16 * kGmStride, (int64_t)blockIdx.x * 64 + wave * 16, cbeg / 16,
+    flush_gmin<TL>(a, gms + wave * 16 * kGmStride, (int64_t)blockIdx.x * 64 + wave * 16, cbeg / 16,
                (min(cbeg + 64 * kKeyTiles, a.ne_pad) - cbeg) / 16);
 }
 
@@ -501,29 +512,41 @@ int launch_seed_rank(const Index *ix, const float *qpad, const float *qnorm, con
         return fail(NHQ_EINVAL, "entry sample larger than 8192");
     KeyArgs a{qpad, qnorm, qword, qmask, ix->entry_vec, ix->entry_norm, ix->entry_attr, ix->entry_bf16,
               qexact, keys, keys + (size_t)nq * ne_pad, nq, ne, ne_pad, ix->w, ix->abits, ix->hmask};
-    const dim3 grid((unsigned)((nq + 63) / 64), (unsigned)((ne_pad + 64 * kKeyTiles - 1) / (64 * kKeyTiles)));
+    // tiles per workgroup: the most (up to 8) that still give >= 1024 workgroups
+    const int64_t qgroups = (nq + 63) / 64;
+    int tl = 1;
+    for (int t : {kMaxKeyTiles, 2})
+        if (qgroups * ((nj + t - 1) / t) >= 1024) {
+            tl = t;
+            break;
+        }
+    const dim3 grid((unsigned)qgroups, (unsigned)((nj + tl - 1) / tl));
     int rc = NHQ_OK;
     const bool def = ix->w.mode == NHQ_WEIGHTS_DEFAULT;
+#define NHQ_KT(KER, DPV, TLV)                                                               \
+    if (def)                                                                                \
+        hipLaunchKernelGGL((KER<DPV, true, TLV>), grid, dim3(256), 0, st, a);               \
+    else                                                                                    \
+        hipLaunchKernelGGL((KER<DPV, false, TLV>), grid, dim3(256), 0, st, a);
+#define NHQ_KTL(KER, DPV)                                                                   \
+    if (tl == kMaxKeyTiles) {                                                               \
+        NHQ_KT(KER, DPV, kMaxKeyTiles)                                                      \
+    } else if (tl == 2) {                                                                   \
+        NHQ_KT(KER, DPV, 2)                                                                 \
+    } else {                                                                                \
+        NHQ_KT(KER, DPV, 1)                                                                 \
+    }
     switch (ix->dp) {
 #define NHQ_K(DPV)                                                                       \
     case DPV:                                                                            \
-        if (def)                                                                         \
-            hipLaunchKernelGGL((k_entry_keys<DPV, true>), grid, dim3(256), 0, st, a);    \
-        else                                                                             \
-            hipLaunchKernelGGL((k_entry_keys<DPV, false>), grid, dim3(256), 0, st, a);   \
+        NHQ_KTL(k_entry_keys, DPV)                                                       \
         break;
 #define NHQ_KB(DPV)                                                                      \
     case DPV:                                                                            \
         if (a.eb && a.qx) {                                                              \
-            if (def)                                                                     \
-                hipLaunchKernelGGL((k_entry_keys_b16<DPV, true>), grid, dim3(256), 0, st, a);  \
-            else                                                                         \
-                hipLaunchKernelGGL((k_entry_keys_b16<DPV, false>), grid, dim3(256), 0, st, a); \
+            NHQ_KTL(k_entry_keys_b16, DPV)                                               \
         }                                                                                \
-        if (def)                                                                         \
-            hipLaunchKernelGGL((k_entry_keys<DPV, true>), grid, dim3(256), 0, st, a);    \
-        else                                                                             \
-            hipLaunchKernelGGL((k_entry_keys<DPV, false>), grid, dim3(256), 0, st, a);   \
+        NHQ_KTL(k_entry_keys, DPV)                                                       \
         break;
         NHQ_KB(32)
         NHQ_KB(64)
@@ -535,6 +558,8 @@ int launch_seed_rank(const Index *ix, const float *qpad, const float *qnorm, con
         NHQ_K(1024)
 #undef NHQ_KB
 #undef NHQ_K
+#undef NHQ_KTL
+#undef NHQ_KT
     default:
         rc = fail(NHQ_EINVAL, "unsupported padded dimension");
     }

@@ -236,6 +236,15 @@ def config3(n: int = 1_000_000, nq: int = 10_000) -> Workload:
                     build_seed=305, integer=False)
 
 
+def config3_train_queries(nq: int = 20_000):
+    """Training queries of the precision-form distribution (same mixture
+    and attribute law, seeds disjoint from the evaluation queries): for the
+    stop network, evaluated on the held-out precision-form queries."""
+    q = gaussian_mixture(nq, 960, 64, seed=306, centre_seed=1301)
+    qa = uniform_attrs(nq, (2, 3, 5, 10), 307)
+    return q, qa
+
+
 def config4(n: int = 10_000_000, nq: int = 10_000, train: bool = False) -> Workload:
     """Learned-stop form: d = 96 Gaussian mixture (1024 centres), attributes
     3/4/5 Zipf(1.1)-skewed, full constraints with combinations drawn from

@@ -185,12 +185,11 @@ def test_trained_network_gain_over_fixed_beam():
     qte, qate = _dev(w.q[800:]), _dev(w.qattrs[800:])
     params, info = learned.train_stop_network(ix, qtr, qatr, k=10, beam=128, epochs=30, seed=1)
     nhq.nhq_mlp_load(ix, params)
-    gi, gd = nhq.nhq_bruteforce_hybrid_knn(ix, qte, qate, 10)
-    gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
     qa_np = w.qattrs[800:]
+    gi, _, _ = oracle.bruteforce(w.x, w.attrs, w.q[800:], qa_np, 10)   # exact answers, FP64
     def run(**kw):
         ids, dist, cnt = nhq.nhq_hybrid_search(ix, qte, qate, 10, kw.pop("beam"), counters=True, **kw)
-        r = recall_at_k(ids.cpu().numpy(), dist.cpu().numpy(), gi, gd, w.attrs, qa_np, 10).mean()
+        r = recall_at_k(ids.cpu().numpy(), w.x, w.q[800:], w.attrs, qa_np, gi, 10).mean()
         return r, cnt.cpu().numpy()[:, 1].mean()
     fixed = {L: run(beam=L) for L in (12, 16, 24, 32, 48, 64, 96, 128)}
     learned_pts = {tau: run(beam=128, learned=True, stop_threshold=tau, check_every=4)
@@ -217,6 +216,12 @@ def test_trained_network_gain_over_fixed_beam():
     r99, h99 = learned_pts[0.99]
     assert r99 >= fixed[128][0] - 0.02
     assert h99 < 0.8 * fixed[128][1]
+    # the gain over the method without the network: at the recall a threshold
+    # reaches, the fixed beam needs more expansions than the learned stop
+    gains = [(tau, fixed_hops_at(r) - h) for tau, (r, h) in learned_pts.items()
+             if fixed_hops_at(r) is not None]
+    assert gains, report
+    assert max(g for _, g in gains) > 0, report
 
 
 def test_trace_with_multi_expansion_matches_oracle(setup):
