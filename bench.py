@@ -346,9 +346,15 @@ def headline(args):
         del src, dst
         log("copy calibration: 3 copies of 1 GiB")
 
+    # ---- 5. where selectivity varies: the serving stream's constraint law
+    # (1 to 4 of the 4 attributes constrained) on the same query vectors; the
+    # fixed beam against the learned budget at one large beam
+    mixed, mixed_net = None, None
+    if not args.no_mixed:
+        mixed, mixed_net = mixed_selectivity(args, w, ix, ixb, tq)
     serving = None
     if not args.no_serve:
-        serving = serve_config5(args, w, ixb, ix, h, tq, x.device)
+        serving = serve_config5(args, w, ixb, ix, h, tq, x.device, mixed_net)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args, w, ix, h, forms["fp32_fixed"]["beam"], rerank_n=0)
@@ -376,6 +382,7 @@ def headline(args):
                    "parallelism": "single GPU"},
         "p99_ms": None if serving is None else serving["p99_ms"],
         "forms": _r({kk: {k2: v2 for k2, v2 in f.items()} for kk, f in forms.items()}),
+        "mixed_selectivity": mixed,
         "serving": serving,
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -383,7 +390,69 @@ def headline(args):
     print(json.dumps(out), flush=True)
 
 
-def serve_config5(args, w, ixb, ix32, h, tq, dev):
+def mixed_selectivity(args, w, ix, ixb, tq):
+    """The learned stop where queries differ in difficulty: 10,000 queries
+    with 1 to 4 of the 4 attributes constrained (|P|/|S| from 1/2 to 1/300)
+    on the BF16 index.  A fixed-beam sweep against the stop network's hop
+    budget at the serving beam (network trained on training queries of the
+    same constraint law), each QPS at Recall@10 = 0.95 interpolated; the
+    mean hops at equal recall."""
+    import dataclasses
+    import torch
+    import synth
+    import paper_2203_13601_amd as nhq
+    from paper_2203_13601_amd.learned import train_stop_network
+    from paper_2203_13601_amd.metrics import qps_at_recall
+    dev = torch.device("cuda:0")
+    wm = dataclasses.replace(w, qattrs=synth.partial_constraints(w.nq, w.cards, 508))
+    hm = Harness(wm, args, dev)
+    gi, _ = nhq.nhq_bruteforce_hybrid_knn(ix, hm.q, hm.qa, w.k)
+    hm.gt = gi.cpu().numpy()
+    target, rr, ce, big = args.target, 4, args.check_every, args.serve_beam
+    fixed = _sweep(hm, ixb, "mixed bf16", [16, 32, 48, 64, 96, 128, 160, 192, 256, 320, 384, 512], target, rerank=rr)
+    tqa_p = torch.from_numpy(synth.partial_constraints(tq.shape[0], w.cards, 505)).to(dev)
+    t0 = time.time()
+    params, info = train_stop_network(ixb, tq, tqa_p, w.k, big, epochs=30, check_every=ce, n_init=args.n_init,
+                                      expand=args.expand, seed=2)
+    nhq.nhq_mlp_load(ixb, params)
+    torch.cuda.synchronize()
+    train_s = time.time() - t0
+    log("mixed: stop network at beam %d: %d samples in %.2fs" % (big, info["samples"], train_s))
+    learned = []
+    for cf in (0.5, 0.75, 1.0, 1.25, 1.5, 2.0, 2.5, 3.0, 4.0):
+        p = hm.point(ixb, big, rerank=rr, learned=2, stop_threshold=0.9, check_every=ce, cap_factor=cf)
+        p["cap_factor"] = cf
+        learned.append(p)
+        log("mixed bf16+learned beam %d cap %.2f recall %.4f hops %.1f (p99 %.0f) %.0f QPS" % (
+            big, cf, p["recall"], p["hops"], p["hops_p99"], p["qps"]))
+        if p["recall"] >= target + 0.01 and len([x for x in learned if x["recall"] >= target]) >= 2:
+            break
+    fa = qps_at_recall([p["beam"] for p in fixed], [p["recall"] for p in fixed], [p["qps"] for p in fixed], target)
+    la = qps_at_recall([p["cap_factor"] for p in learned], [p["recall"] for p in learned],
+                       [p["qps"] for p in learned], target)
+
+    def hops_at(pts, key):
+        prev = None
+        for p in pts:
+            if p["recall"] >= target:
+                if prev is None or prev["recall"] >= p["recall"]:
+                    return p["hops"]
+                t = (target - prev["recall"]) / (p["recall"] - prev["recall"])
+                return prev["hops"] + t * (p["hops"] - prev["hops"])
+            prev = p
+        return None
+    out = {"workload": "%s queries, 1..4 of 4 attributes constrained" % w.name, "queries": w.nq,
+           "fixed_qps_at_target_interp": fa, "learned_qps_at_target_interp": la,
+           "learned_speedup_vs_fixed": None if not (fa and la) else la / fa,
+           "fixed_hops_at_target": hops_at(fixed, "beam"), "learned_hops_at_target": hops_at(learned, "cap_factor"),
+           "learned_beam": big, "learned_mode": 2, "train_samples": info["samples"], "train_s": train_s,
+           "fixed_sweep": fixed, "learned_sweep": learned}
+    log("mixed selectivity: fixed %s QPS, learned %s QPS at Recall@10 %.2f (hops %s vs %s)" % (
+        fa, la, target, out["fixed_hops_at_target"], out["learned_hops_at_target"]))
+    return _r(out), params
+
+
+def serve_config5(args, w, ixb, ix32, h, tq, dev, params=None):
     """The serving form: Poisson stream through the continuous-batching
     server on the BF16 index (float32 re-score), then a saturation run."""
     import torch
@@ -399,9 +468,10 @@ def serve_config5(args, w, ixb, ix32, h, tq, dev):
     # the serving network: traces of training queries with the stream's
     # constraint law (1..4 of 4 attributes constrained) at the automatic beam
     beam_auto, ce = args.serve_beam, args.check_every
-    tqa_p = torch.from_numpy(synth.partial_constraints(tq.shape[0], w.cards, 505)).to(dev)
-    params, info = train_stop_network(ixb, tq, tqa_p, w.k, beam_auto, epochs=30, check_every=ce,
-                                      n_init=args.n_init, expand=args.expand, seed=2)
+    if params is None:
+        tqa_p = torch.from_numpy(synth.partial_constraints(tq.shape[0], w.cards, 505)).to(dev)
+        params, info = train_stop_network(ixb, tq, tqa_p, w.k, beam_auto, epochs=30, check_every=ce,
+                                          n_init=args.n_init, expand=args.expand, seed=2)
     nhq.nhq_mlp_load(ixb, params)
     # exact answers of a sample of the stream (k >= 10 requests), for recall
     rng = np.random.default_rng(506)
@@ -413,7 +483,7 @@ def serve_config5(args, w, ixb, ix32, h, tq, dev):
     gsi = gsi.cpu().numpy()
     # budget factor: the smallest reaching the target on the sample (batch search)
     s_cf = None
-    for cf in (1.0, 1.5, 2.0, 2.5, 3.0, 4.0, 6.0):
+    for cf in (0.75, 1.0, 1.25, 1.5, 2.0, 2.5, 3.0, 4.0, 6.0):
         vi, _ = nhq.nhq_hybrid_search(ixb, sq_d, sqa_d, w.k, beam_auto, n_init=args.n_init, expand=args.expand,
                                       rerank=4, learned=2, stop_threshold=0.9, check_every=ce, cap_factor=cf)
         vr = recall_at_k(vi.cpu().numpy(), w.x, s_q[samp], w.attrs, s_qa[samp], gsi, w.k).mean()
@@ -453,7 +523,7 @@ def serve_config5(args, w, ixb, ix32, h, tq, dev):
            "k_mix": [1, 10, 50, 100], "constrained_attrs": "1..4 of 4",
            "beam": "learned hop budget at the automatic beam %d (cap factor %.2f)" % (beam_auto, s_cf),
            "storage": "bf16 + float32 re-score of min(4k, beam) eligible entries", "slots": slots[0],
-           "latency": "arrival to result seen by the host", "train_samples": info["samples"]}
+           "latency": "arrival to result seen by the host"}
     log("serving: %d requests at %.0f/s: p50 %.3f ms, p99 %.3f ms, recall@10 %.4f; saturation %.0f QPS" % (
         ns, args.serve_rate, out["p50_ms"], out["p99_ms"], out["recall_at_10_k_ge_10"],
         out["saturation"]["sustained_qps"]))
@@ -604,7 +674,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=500_000)
     ap.add_argument("--serve-saturation-requests", type=int, default=200_000)
     ap.add_argument("--serve-recall-sample", type=int, default=10_000)
-    ap.add_argument("--serve-beam", type=int, default=128)
+    ap.add_argument("--serve-beam", type=int, default=256)
+    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cpu-bf-queries", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -118,6 +118,23 @@ typedef struct {
                               (>= cand)                                 [cand] */
     int64_t capacity;      /* rows the index can hold: nhq_index_insert
                               appends up to capacity - n objects           [n] */
+    int32_t entry_per_pattern; /* > 0: stratified entry sample.  Besides the
+                              n_entry random members, the index keeps one
+                              block per attribute pattern (full code tuple)
+                              that objects hold: the min(entry_per_pattern,
+                              count) objects of the pattern with the smallest
+                              (h(i), i), h(i) the first splitmix64 output
+                              from state (seed ^ 0x8F14E45FCEEA167A) ^
+                              (i * 0xD1B54A32D192ED03).  A query that
+                              constrains every attribute takes its seeds from
+                              its pattern's block (ranked by Gamma as the
+                              global sample is); other queries, and patterns
+                              no object holds, from the global sample.  The
+                              seed set B of Alg. 2 is drawn at random
+                              (Sec. 3.2); this keeps it random within each
+                              pattern.  Needs m >= 1, n_entry and
+                              entry_per_pattern <= 8192 and at most 4096
+                              patterns.  0: off                        [0] */
 } nhq_build_params;
 
 #define NHQ_BUILD_EXACT 0
@@ -256,9 +273,22 @@ int nhq_build_index(const float *vecs, const uint8_t *attrs, int64_t n, int32_t 
 int nhq_index_set_graph(nhq_index *ix, const int32_t *adj, int32_t degree, void *stream);
 
 /* Copy the graph (device int32 [n][degree]) / the entry sample (device int32
- * [n_entry]) out of the index. */
+ * [n_entry], the global members only) out of the index. */
 int nhq_index_get_graph(const nhq_index *ix, int32_t *adj_out, void *stream);
 int nhq_index_get_entry(const nhq_index *ix, int32_t *entry_out, void *stream);
+
+/* The blocks of a stratified entry sample (entry_per_pattern > 0): *n_blocks
+ * (host) = number of patterns the objects hold (0 when off); codes (host,
+ * nullable) uint8 [n_blocks][m]: each block's attribute codes, blocks in
+ * increasing order of their packed codes; offsets (host, nullable) int32
+ * [n_blocks + 1]: block b holds entry positions offsets[b] ..
+ * offsets[b + 1] - 1 (offsets[0] = n_entry: the positions after the global
+ * members, as nhq_seed_rank returns them); ids (device, nullable) int32
+ * [offsets[n_blocks] - n_entry]: the block members' vertex ids, block after
+ * block, each block in increasing (h(i), i).  Synchronises the stream when
+ * ids is given. */
+int nhq_index_entry_blocks(const nhq_index *ix, int32_t *n_blocks, uint8_t *codes, int32_t *offsets,
+                           int32_t *ids, void *stream);
 
 /* Copy the storage form the search scores with: rows padded to the kernel
  * width dp (returned in *dp_out): float32 [n][dp], bf16 bit patterns uint16

@@ -306,6 +306,67 @@ def entry_points(build_seed: int, n: int, n_seeds: int = 32) -> np.ndarray:
     return np.asarray(out, dtype=np.int32)
 
 
+def _splitmix64_first(states: np.ndarray) -> np.ndarray:
+    """The first splitmix64 output (Steele, Lea and Flood) from each uint64
+    state: z = s + 0x9E3779B97F4A7C15, then the two xor-shift-multiply
+    rounds and a final xor-shift (wrapping uint64 arithmetic)."""
+    with np.errstate(over="ignore"):
+        z = states + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def entry_strata(build_seed: int, attrs, per_pattern: int):
+    """Stratified seed sets (the flagged entry-sample option): for every code
+    tuple the objects hold, the min(per_pattern, count) objects of that tuple
+    with the smallest (h(i), i), h(i) = the first splitmix64 output from
+    state (seed ^ 0x8F14E45FCEEA167A) ^ (i * 0xD1B54A32D192ED03) mod 2^64.
+    Returns {code tuple: int32 ids in (h, id) order}.  Seeds stay random
+    (Sec. 3.2), within each attribute pattern."""
+    attrs = _u8(attrs)
+    n = attrs.shape[0]
+    i = np.arange(n, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        states = np.uint64((build_seed ^ 0x8F14E45FCEEA167A) & 0xFFFFFFFFFFFFFFFF) ^ (
+            i * np.uint64(0xD1B54A32D192ED03))
+    h = _splitmix64_first(states)
+    out = {}
+    tuples = [tuple(int(c) for c in row) for row in attrs]
+    groups: Dict[Tuple[int, ...], List[int]] = {}
+    for v, t in enumerate(tuples):
+        groups.setdefault(t, []).append(v)
+    for t, ids in groups.items():
+        ids = sorted(ids, key=lambda v: (int(h[v]), v))[:per_pattern]
+        out[t] = np.asarray(ids, dtype=np.int32)
+    return out
+
+
+def search_strata(adj, xs, attrs, q, qa, k: int, L: int, global_seeds, strata, **kw):
+    """Joint pruning (``search``) where each query draws its seed set from
+    the stratified sample: a query that constrains every attribute takes the
+    block of its code tuple (when an object holds it), any other query the
+    global sample.  Same outputs as ``search``."""
+    q, qa = _f32(q), _u8(qa)
+    nq = q.shape[0]
+    key = [tuple(int(c) for c in row) if (row != WILDCARD).all() else None for row in qa]
+    groups: Dict[object, List[int]] = {}
+    for i, t in enumerate(key):
+        groups.setdefault(t if t in strata else None, []).append(i)
+    res = None
+    for t, rows in groups.items():
+        rows = np.asarray(rows)
+        seeds = strata[t] if t is not None else np.asarray(global_seeds, dtype=np.int32)
+        o = search(adj, xs, attrs, q[rows], qa[rows], k, L, seeds, **kw)
+        if res is None:
+            res = [np.empty((nq,) + a.shape[1:], dtype=a.dtype) if isinstance(a, np.ndarray) else None
+                   for a in o]
+        for r, a in zip(res, o):
+            if isinstance(a, np.ndarray):
+                r[rows] = a
+    return tuple(res)
+
+
 # ------------------------------------------------------------ Alg. 2
 def search(adj, xs, attrs, q, qa, k: int, L: int, seeds, n_init: int = 32, key_mode: int = KEY64,
            out_mode: int = 0, rerank_n: int = 0, xr=None, max_hops: int = 1 << 40,

@@ -14,4 +14,5 @@ from ._binding import (BuildParams, Index, NHQError, SearchParams, lib,  # noqa:
                        nhq_trace_samples, Server, ServerParams, nhq_server_create, SERVE_RAW, nhq_gather_probe,
                        nhq_nndescent_lists, nhq_index_build_report, WEIGHTS, BUILDERS,
                        nhq_index_insert, nhq_index_save, nhq_index_load,
-                       nhq_hybrid_search_noalloc, NOALLOC_SCRATCH_BYTES)
+                       nhq_hybrid_search_noalloc, NOALLOC_SCRATCH_BYTES,
+                       nhq_index_entry_blocks)

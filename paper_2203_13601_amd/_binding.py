@@ -36,7 +36,7 @@ class BuildParams(ctypes.Structure):
                 ("builder", ctypes.c_int32), ("nnd_rounds", ctypes.c_int32),
                 ("nnd_sample", ctypes.c_int32), ("nnd_stop", ctypes.c_float),
                 ("nsw_batch", ctypes.c_int32), ("nsw_beam", ctypes.c_int32),
-                ("capacity", ctypes.c_int64)]
+                ("capacity", ctypes.c_int64), ("entry_per_pattern", ctypes.c_int32)]
 
 
 class Trace(ctypes.Structure):
@@ -94,6 +94,7 @@ def lib() -> ctypes.CDLL:
         "nhq_index_set_graph": ([P, P, i32, P], i32),
         "nhq_index_get_graph": ([P, P, P], i32),
         "nhq_index_get_entry": ([P, P, P], i32),
+        "nhq_index_entry_blocks": ([P, P, P, P, P, P], i32),
         "nhq_index_info": ([P, P, P, P, P, P, P], i32),
         "nhq_index_get_storage": ([P, P, P, P, P], i32),
         "nhq_index_device_error": ([P, P, P], i32),
@@ -237,14 +238,14 @@ BUILDERS = {"exact": 0, "nndescent": 1, "nsw": 2}
 
 def _params(degree=32, cand=64, reverse_edges=False, storage="fp32", n_entry=1024, seed=0,
             weights="default", weight_param=0.0, builder="exact", nnd_rounds=0, nnd_sample=0,
-            nnd_stop=0.0, nsw_batch=0, nsw_beam=0, capacity=0):
+            nnd_stop=0.0, nsw_batch=0, nsw_beam=0, capacity=0, entry_per_pattern=0):
     return BuildParams(int(degree), int(cand), int(bool(reverse_edges)),
                        STORAGE[storage] if isinstance(storage, str) else int(storage),
                        int(n_entry), WEIGHTS[weights] if isinstance(weights, str) else int(weights),
                        int(seed), float(weight_param),
                        BUILDERS[builder] if isinstance(builder, str) else int(builder),
                        int(nnd_rounds), int(nnd_sample), float(nnd_stop), int(nsw_batch),
-                       int(nsw_beam), int(capacity))
+                       int(nsw_beam), int(capacity), int(entry_per_pattern))
 
 
 def nhq_index_create(vecs: torch.Tensor, attrs: torch.Tensor, stream=None, **params) -> Index:
@@ -353,6 +354,26 @@ def nhq_index_get_entry(ix: Index, stream=None) -> torch.Tensor:
     out = torch.empty((info["n_entry"],), dtype=torch.int32, device=ix.device)
     _check(lib().nhq_index_get_entry(ix.handle, out.data_ptr(), _stream(stream)), "nhq_index_get_entry")
     return out
+
+
+def nhq_index_entry_blocks(ix: Index, stream=None):
+    """Blocks of a stratified entry sample: (codes uint8 [B][m], offsets
+    int32 [B + 1] in entry positions, member ids int32 tensor on the device),
+    or None when the index has none."""
+    nb = ctypes.c_int32()
+    _check(lib().nhq_index_entry_blocks(ix.handle, ctypes.byref(nb), None, None, None, _stream(stream)),
+           "nhq_index_entry_blocks")
+    if nb.value == 0:
+        return None
+    m = ix.dims()[1]
+    codes = np.empty((nb.value, m), dtype=np.uint8)
+    offs = np.empty(nb.value + 1, dtype=np.int32)
+    _check(lib().nhq_index_entry_blocks(ix.handle, ctypes.byref(nb), codes.ctypes.data, offs.ctypes.data, None,
+                                        _stream(stream)), "nhq_index_entry_blocks")
+    ids = torch.empty((int(offs[-1] - offs[0]),), dtype=torch.int32, device=ix.device)
+    _check(lib().nhq_index_entry_blocks(ix.handle, ctypes.byref(nb), None, None, ids.data_ptr(), _stream(stream)),
+           "nhq_index_entry_blocks")
+    return codes, offs, ids
 
 
 def nhq_index_get_storage(ix: Index, stream=None):

@@ -258,6 +258,47 @@ int grid_for(int64_t work, int block)
 
 }  // namespace
 
+// The stratified entry sample: for every packed attribute word the objects
+// hold (in increasing order), the min(per, count) objects with the smallest
+// (h(i), i), h(i) = the first splitmix64 output from state
+// (seed ^ 0x8F14E45FCEEA167A) ^ (i * 0xD1B54A32D192ED03); appended to ent,
+// with each block's word and its first position (plus the end) recorded.
+int stratify(const std::vector<uint32_t> &aw, uint64_t seed, int per, std::vector<int32_t> &ent,
+             std::vector<uint32_t> &words, std::vector<int32_t> &offs)
+{
+    struct Key {
+        uint32_t w;
+        int32_t id;
+        uint64_t h;
+    };
+    const size_t n = aw.size();
+    std::vector<Key> keys(n);
+    const uint64_t base = seed ^ 0x8F14E45FCEEA167Aull;
+    for (size_t i = 0; i < n; ++i) {
+        uint64_t state = base ^ ((uint64_t)i * 0xD1B54A32D192ED03ull);
+        keys[i] = Key{aw[i], (int32_t)i, splitmix64_next(state)};
+    }
+    std::sort(keys.begin(), keys.end(), [](const Key &a, const Key &b) {
+        return a.w != b.w ? a.w < b.w : (a.h != b.h ? a.h < b.h : a.id < b.id);
+    });
+    words.clear();
+    offs.clear();
+    for (size_t i = 0; i < n;) {
+        size_t j = i;
+        while (j < n && keys[j].w == keys[i].w)
+            ++j;
+        words.push_back(keys[i].w);
+        offs.push_back((int32_t)ent.size());
+        for (size_t t = i; t < std::min(j, i + (size_t)per); ++t)
+            ent.push_back(keys[t].id);
+        i = j;
+    }
+    offs.push_back((int32_t)ent.size());
+    if (words.size() > 4096)
+        return fail(NHQ_EINVAL, "a stratified entry sample holds at most 4096 attribute patterns");
+    return NHQ_OK;
+}
+
 void free_index(Index *ix)
 {
     if (!ix)
@@ -265,7 +306,8 @@ void free_index(Index *ix)
     if (ix->vecs && ix->vecs != ix->vec32)
         (void)hipFree(ix->vecs);
     void *ptrs[] = {ix->vec32, ix->scale, ix->attr, ix->norm, ix->adj, ix->entry, ix->entry_vec,
-                    ix->entry_norm, ix->entry_attr, ix->entry_bf16, ix->err, ix->ws, ix->mlp, ix->logp};
+                    ix->entry_norm, ix->entry_attr, ix->entry_bf16, ix->err, ix->ws, ix->mlp, ix->logp,
+                    ix->block_word, ix->block_off};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -375,6 +417,10 @@ int nhq_index_create(const float *vecs, const uint8_t *attrs, int64_t n, int32_t
     if (p.nnd_rounds < 0 || p.nnd_rounds > 1000 || p.nnd_sample < 1 || p.nnd_sample > 64 ||
         !(p.nnd_stop >= 0.0f))
         return fail(NHQ_EINVAL, "NN-descent needs rounds in [0, 1000], sample in [1, 64], stop >= 0");
+    if (p.entry_per_pattern < 0 || p.entry_per_pattern > 8192 ||
+        (p.entry_per_pattern > 0 && (m < 1 || p.n_entry > 8192)))
+        return fail(NHQ_EINVAL, "a stratified entry sample needs m >= 1, n_entry <= 8192 and "
+                                "entry_per_pattern in [1, 8192]");
 
     hipStream_t st = (hipStream_t)stream;
     nhq_index *h = new (std::nothrow) nhq_index();
@@ -510,23 +556,51 @@ int nhq_index_create(const float *vecs, const uint8_t *attrs, int64_t n, int32_t
                 ent.push_back((int32_t)v);
         }
         ix->n_entry = (int)ne;
-        if (hipMalloc(&ix->entry, (size_t)ne * sizeof(int32_t)) != hipSuccess) {
+        // stratified: per attribute pattern (packed word), the members with
+        // the smallest (h(i), i) after the global ones
+        if (p.entry_per_pattern > 0) {
+            std::vector<uint32_t> aw((size_t)n);
+            if (hipMemcpyAsync(aw.data(), ix->attr, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToHost,
+                               st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess) {
+                rc = fail(NHQ_EHIP, "attribute read-back failed");
+                break;
+            }
+            rc = stratify(aw, p.seed, p.entry_per_pattern, ent, ix->block_word_h, ix->block_off_h);
+            if (rc != NHQ_OK)
+                break;
+            ix->n_blocks = (int)ix->block_word_h.size();
+            ix->per_pattern = p.entry_per_pattern;
+            if (hipMalloc(&ix->block_word, sizeof(uint32_t) * std::max<size_t>(1, ix->block_word_h.size())) !=
+                    hipSuccess ||
+                hipMalloc(&ix->block_off, sizeof(int32_t) * ix->block_off_h.size()) != hipSuccess ||
+                hipMemcpy(ix->block_word, ix->block_word_h.data(), sizeof(uint32_t) * ix->block_word_h.size(),
+                          hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemcpy(ix->block_off, ix->block_off_h.data(), sizeof(int32_t) * ix->block_off_h.size(),
+                          hipMemcpyHostToDevice) != hipSuccess) {
+                rc = fail(NHQ_ENOMEM, "entry block table allocation failed");
+                break;
+            }
+        }
+        const int64_t ne_all = (int64_t)ent.size();
+        ix->n_entry_total = (int)ne_all;
+        if (hipMalloc(&ix->entry, (size_t)ne_all * sizeof(int32_t)) != hipSuccess) {
             rc = fail(NHQ_ENOMEM, "entry allocation failed");
             break;
         }
-        if (hipMemcpyAsync(ix->entry, ent.data(), (size_t)ne * sizeof(int32_t), hipMemcpyHostToDevice,
+        if (hipMemcpyAsync(ix->entry, ent.data(), (size_t)ne_all * sizeof(int32_t), hipMemcpyHostToDevice,
                            st) != hipSuccess) {
             rc = fail(NHQ_EHIP, "entry upload failed");
             break;
         }
-        if (hipMalloc(&ix->entry_vec, (size_t)ne * ix->dp * sizeof(float)) != hipSuccess ||
-            hipMalloc(&ix->entry_norm, (size_t)ne * sizeof(float)) != hipSuccess ||
-            hipMalloc(&ix->entry_attr, (size_t)ne * sizeof(uint32_t)) != hipSuccess) {
+        if (hipMalloc(&ix->entry_vec, (size_t)ne_all * ix->dp * sizeof(float)) != hipSuccess ||
+            hipMalloc(&ix->entry_norm, (size_t)ne_all * sizeof(float)) != hipSuccess ||
+            hipMalloc(&ix->entry_attr, (size_t)ne_all * sizeof(uint32_t)) != hipSuccess) {
             rc = fail(NHQ_ENOMEM, "entry sample allocation failed");
             break;
         }
-        hipLaunchKernelGGL(k_gather_entry, dim3(grid_for(ne * ix->dp, 256)), dim3(256), 0, st, ix->entry,
-                           (int)ne, ix->vec32, ix->norm, ix->attr, ix->dp, ix->entry_vec,
+        hipLaunchKernelGGL(k_gather_entry, dim3(grid_for(ne_all * ix->dp, 256)), dim3(256), 0, st, ix->entry,
+                           (int)ne_all, ix->vec32, ix->norm, ix->attr, ix->dp, ix->entry_vec,
                            ix->entry_norm, ix->entry_attr);
         if (hipMalloc(&ix->logp, sizeof(float) * hh.size()) != hipSuccess) {
             rc = fail(NHQ_ENOMEM, "histogram allocation failed");
@@ -659,6 +733,32 @@ int nhq_index_get_graph(const nhq_index *h, int32_t *adj_out, void *stream)
     return NHQ_OK;
 }
 
+int nhq_index_entry_blocks(const nhq_index *h, int32_t *n_blocks, uint8_t *codes, int32_t *offsets,
+                           int32_t *ids, void *stream)
+{
+    if (!h || !n_blocks)
+        return fail(NHQ_EINVAL, "null argument");
+    const Index *ix = &h->impl;
+    const int B = ix->n_blocks;
+    *n_blocks = B;
+    if (codes) {
+        const uint32_t fm = (1u << ix->abits) - 1u;
+        for (int b = 0; b < B; ++b)
+            for (int i = 0; i < ix->m; ++i)
+                codes[(size_t)b * ix->m + i] = (uint8_t)((ix->block_word_h[b] >> (ix->abits * i)) & fm);
+    }
+    if (offsets)
+        for (int b = 0; b <= B; ++b)
+            offsets[b] = B > 0 ? ix->block_off_h[b] : ix->n_entry;
+    if (ids && B > 0) {
+        const size_t cnt = (size_t)(ix->block_off_h[B] - ix->n_entry);
+        NHQ_HIP(hipMemcpyAsync(ids, ix->entry + ix->n_entry, cnt * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                               (hipStream_t)stream));
+        NHQ_HIP(hipStreamSynchronize((hipStream_t)stream));
+    }
+    return NHQ_OK;
+}
+
 int nhq_index_get_entry(const nhq_index *h, int32_t *entry_out, void *stream)
 {
     if (!h || !entry_out)
@@ -736,11 +836,14 @@ namespace {
 // 32-bit words of the seed ranking's scratch: padded rows, norms, codes,
 // masks, exactness flags and (for the matrix-core ranking) the key matrix and
 // its group minima
-size_t seed_rank_words(const Index *ix, int64_t nq)
+size_t seed_rank_words(const Index *ix, int64_t nq, int K)
 {
     const size_t ne_pad = (size_t)(ix->n_entry + 63) / 64 * 64;
     const bool dense = ix->n_entry <= 8192;
-    return (size_t)nq * ix->dp + 5 * (size_t)nq + (dense ? (size_t)nq * ne_pad / 16 * 17 : 0) + 64;
+    const size_t pad = (size_t)nq * ix->dp + 5 * (size_t)nq + 64;
+    if (ix->n_blocks > 0)
+        return pad + strata_rank_words(ix, nq, K);
+    return pad + (dense ? (size_t)nq * ne_pad / 16 * 17 : 0);
 }
 
 int check_seed_rank_args(const Index *ix, const float *queries, const uint8_t *qattrs, int64_t nq,
@@ -769,7 +872,10 @@ int seed_rank_at(const Index *cix, const float *queries, const uint8_t *qattrs, 
     float *keys = reinterpret_cast<float *>((reinterpret_cast<uintptr_t>(qx + f_small) + 255) & ~uintptr_t(255));
     int rc = launch_pad_queries(queries, qattrs, nq, ix->d, ix->dp, ix->m, ix->abits, qpad, qnorm, qw, qm, qx, st);
     if (rc == NHQ_OK) {
-        if (dense)
+        if (ix->n_blocks > 0)
+            rc = launch_strata_rank(ix, qpad, qnorm, qw, qm, nq, n_cand, reinterpret_cast<uint32_t *>(keys),
+                                    cand, st);
+        else if (dense)
             rc = launch_seed_rank(ix, qpad, qnorm, qw, qm, qx, nq, n_cand, keys, cand, st);
         else
             rc = launch_dense_topk(qpad, qnorm, qw, qm, nq, ix->entry_vec, ix->entry_norm, ix->entry_attr,
@@ -791,7 +897,7 @@ int seed_rank_ws(const nhq_index *h, const float *queries, const uint8_t *qattrs
     int rc = check_seed_rank_args(ix, queries, qattrs, nq, n_cand, cand);
     if (rc != NHQ_OK || nq == 0)
         return rc;
-    rc = ensure_workspace(ix, ws_off + sizeof(uint32_t) * seed_rank_words(ix, nq));
+    rc = ensure_workspace(ix, ws_off + sizeof(uint32_t) * seed_rank_words(ix, nq, n_cand));
     if (rc != NHQ_OK)
         return rc;
     uint32_t *blk = reinterpret_cast<uint32_t *>(static_cast<char *>(ix->ws) + ws_off);
@@ -938,12 +1044,12 @@ int nhq_hybrid_search(const nhq_index *h, const float *queries, const uint8_t *q
     const int n_init = (sp && sp->n_init > 0) ? sp->n_init : 32;
     if (n_init > 128)
         return fail(NHQ_EINVAL, "need 1 <= n_init <= 128");
-    const int ks = std::min(ix->n_entry, n_init + kSeedMargin);
+    const int ks = std::min(std::max(ix->n_entry, ix->n_blocks > 0 ? ix->per_pattern : 0), n_init + kSeedMargin);
     // the candidates at the start of the index's workspace, the ranking's
     // scratch after them
     const size_t cbytes = (sizeof(int32_t) * (size_t)nq * ks + 255) & ~size_t(255);
     Index *mix = const_cast<Index *>(ix);
-    int rc = ensure_workspace(mix, cbytes + sizeof(uint32_t) * seed_rank_words(ix, nq));
+    int rc = ensure_workspace(mix, cbytes + sizeof(uint32_t) * seed_rank_words(ix, nq, ks));
     if (rc != NHQ_OK)
         return rc;
     int32_t *cand = static_cast<int32_t *>(mix->ws);
@@ -969,13 +1075,13 @@ int nhq_hybrid_search_noalloc(const nhq_index *h, const float *queries, const ui
     const int n_init = (sp && sp->n_init > 0) ? sp->n_init : 32;
     if (n_init > 128)
         return fail(NHQ_EINVAL, "need 1 <= n_init <= 128");
-    const int ks = std::min(ix->n_entry, n_init + kSeedMargin);
+    const int ks = std::min(std::max(ix->n_entry, ix->n_blocks > 0 ? ix->per_pattern : 0), n_init + kSeedMargin);
     int rc = check_seed_rank_args(ix, queries, qattrs, nq, ks, ids);
     if (rc != NHQ_OK)
         return rc;
     // the candidates at the start of the scratch, the ranking's scratch after them
     const size_t cbytes = (sizeof(int32_t) * (size_t)nq * ks + 255) & ~size_t(255);
-    const size_t need = cbytes + sizeof(uint32_t) * seed_rank_words(ix, nq);
+    const size_t need = cbytes + sizeof(uint32_t) * seed_rank_words(ix, nq, ks);
     if (need > (size_t)NHQ_NOALLOC_SCRATCH_BYTES)
         return fail(NHQ_EINVAL, "batch too large for the allocation-free search: it needs " +
                                     std::to_string(need) + " bytes of scratch, the fixed scratch holds " +

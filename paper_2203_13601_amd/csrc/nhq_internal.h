@@ -7,6 +7,7 @@
 
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "nhq.h"
 #include "attr.h"
@@ -76,6 +77,16 @@ struct Index {
     // <= 256 and dp <= 128: then bf16 products summed in float32 are exact,
     // and the ranking uses the bf16 matrix-core instructions (else null)
     uint16_t *entry_bf16 = nullptr;
+    // stratified entry sample (entry_per_pattern > 0): after the n_entry
+    // global members, one block per attribute pattern the objects hold, in
+    // increasing packed-word order; block b holds entry positions
+    // block_off[b] .. block_off[b + 1] - 1
+    int n_blocks = 0, per_pattern = 0;
+    int n_entry_total = 0;           // n_entry + every block
+    uint32_t *block_word = nullptr;  // device [n_blocks] packed codes
+    int32_t *block_off = nullptr;    // device [n_blocks + 1]
+    std::vector<uint32_t> block_word_h;
+    std::vector<int32_t> block_off_h;
     uint32_t *err = nullptr;    // device error word
     // per-index workspace (grown on demand)
     void *ws = nullptr;
@@ -146,6 +157,14 @@ int launch_dense_topk(const float *A, const float *A_norm, const uint32_t *A_att
                       const uint32_t *B_attr, int64_t nb, int dp, int m, int abits, int mode,
                       int self_exclude, int K, int32_t *out_ids, float *out_keys, hipStream_t st,
                       const Weights *w = nullptr);
+
+// seed ranking of a stratified entry sample (see seed.hip): each query
+// ranked against its pattern's block, or the global members; scratch of
+// strata_rank_words(ix, nq, K) 32-bit words at blk
+size_t strata_rank_words(const Index *ix, int64_t nq, int K);
+int launch_strata_rank(const Index *ix, const float *qpad, const float *qnorm, const uint32_t *qword,
+                       const uint32_t *qmask, int64_t nq, int K, uint32_t *blk, int32_t *cand,
+                       hipStream_t st);
 
 // seed ranking of the entry sample (see seed.hip): positions of the K best
 // keys: scratch of nq * ((n_entry + 63) / 64 * 64) * 17 / 16 floats (the key

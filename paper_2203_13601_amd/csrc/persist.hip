@@ -38,7 +38,10 @@ struct FileHeader {
     float nnd_stop;
     int32_t nnd_rounds_run, nsw_batch, nsw_beam;
     int32_t has_entry_bf16, has_mlp;
-    int32_t reserved[9];
+    // stratified entry sample: block count, members per pattern, and all
+    // entry positions (the global members and every block); 0 when off
+    int32_t n_blocks, per_pattern, n_entry_total;
+    int32_t reserved[6];
 };
 
 size_t storage_elem(int storage)
@@ -78,7 +81,8 @@ int read_dev(FILE *f, void **dev, size_t bytes, size_t alloc, std::vector<char> 
 // bytes after the header that a file with header `hd` holds
 uint64_t payload_bytes(const FileHeader &hd)
 {
-    const uint64_t n = (uint64_t)hd.n, ne = (uint64_t)hd.n_entry, dp = (uint64_t)hd.dp;
+    const uint64_t n = (uint64_t)hd.n, dp = (uint64_t)hd.dp;
+    const uint64_t ne = (uint64_t)(hd.n_blocks > 0 ? hd.n_entry_total : hd.n_entry);
     uint64_t b = 4 * n * dp;                                        // float32 rows
     if (hd.storage != NHQ_STORAGE_FP32)
         b += storage_elem(hd.storage) * n * dp;                     // storage form
@@ -88,7 +92,9 @@ uint64_t payload_bytes(const FileHeader &hd)
     b += 4 * n * (uint64_t)hd.degree;                               // graph
     b += 4 * ne + 4 * ne * dp + 4 * ne + 4 * ne;                    // entry sample
     if (hd.has_entry_bf16)
-        b += 2 * ne * dp;
+        b += 2 * (uint64_t)hd.n_entry * dp;                         // (global members)
+    if (hd.n_blocks > 0)
+        b += 4 * (uint64_t)hd.n_blocks + 4 * ((uint64_t)hd.n_blocks + 1);  // block words, offsets
     b += 4 * (uint64_t)NHQ_MAX_ATTRS * 256;                         // code log-frequencies
     if (hd.has_mlp)
         b += 2 * (uint64_t)NHQ_MLP_PARAMS;                          // stop network
@@ -147,6 +153,9 @@ int nhq_index_save(const nhq_index *h, const char *path, void *stream)
     hd.nsw_beam = ix->nsw_beam;
     hd.has_entry_bf16 = ix->entry_bf16 ? 1 : 0;
     hd.has_mlp = ix->mlp ? 1 : 0;
+    hd.n_blocks = ix->n_blocks;
+    hd.per_pattern = ix->per_pattern;
+    hd.n_entry_total = ix->n_blocks > 0 ? ix->n_entry_total : 0;
     // written to a temporary name, renamed into place once complete
     const std::string tmp = std::string(path) + ".partial";
     FILE *f = std::fopen(tmp.c_str(), "wb");
@@ -158,7 +167,7 @@ int nhq_index_save(const nhq_index *h, const char *path, void *stream)
         return fail(NHQ_EIO, "index file write failed");
     }
     std::vector<char> buf(kChunk);
-    const size_t n = (size_t)ix->n, ne = (size_t)ix->n_entry, dp = (size_t)ix->dp;
+    const size_t n = (size_t)ix->n, ne = (size_t)ix->n_entry_total, dp = (size_t)ix->dp;
     int rc = write_dev(f, ix->vec32, sizeof(float) * n * dp, buf);
     if (rc == NHQ_OK && ix->storage != NHQ_STORAGE_FP32)
         rc = write_dev(f, ix->vecs, storage_elem(ix->storage) * n * dp, buf);
@@ -179,7 +188,12 @@ int nhq_index_save(const nhq_index *h, const char *path, void *stream)
     if (rc == NHQ_OK)
         rc = write_dev(f, ix->entry_attr, sizeof(uint32_t) * ne, buf);
     if (rc == NHQ_OK && ix->entry_bf16)
-        rc = write_dev(f, ix->entry_bf16, sizeof(uint16_t) * ne * dp, buf);
+        rc = write_dev(f, ix->entry_bf16, sizeof(uint16_t) * (size_t)ix->n_entry * dp, buf);
+    if (rc == NHQ_OK && ix->n_blocks > 0 &&
+        (std::fwrite(ix->block_word_h.data(), sizeof(uint32_t), (size_t)ix->n_blocks, f) != (size_t)ix->n_blocks ||
+         std::fwrite(ix->block_off_h.data(), sizeof(int32_t), (size_t)ix->n_blocks + 1, f) !=
+             (size_t)ix->n_blocks + 1))
+        rc = fail(NHQ_EIO, "index file write failed");
     if (rc == NHQ_OK)
         rc = write_dev(f, ix->logp, sizeof(float) * NHQ_MAX_ATTRS * 256, buf);
     if (rc == NHQ_OK && ix->mlp)
@@ -215,7 +229,10 @@ int nhq_index_load(const char *path, void *stream, nhq_index **out)
     if (hd.n < 1 || hd.n >= kMaxN || hd.cap < hd.n || hd.cap >= kMaxN || hd.d < 1 || hd.d > 1024 ||
         padded_dim(hd.d) != hd.dp || hd.m < 0 || hd.m > NHQ_MAX_ATTRS || hd.degree < 0 ||
         hd.degree > NHQ_MAX_DEGREE || hd.storage < 0 || hd.storage > 2 || hd.n_entry < 1 ||
-        hd.n_entry > 65536 || hd.n_entry > hd.n || hd.w_mode < NHQ_WEIGHTS_DEFAULT ||
+        hd.n_entry > 65536 || hd.n_entry > hd.n || hd.n_blocks < 0 || hd.n_blocks > 4096 ||
+        (hd.n_blocks > 0 && (hd.per_pattern < 1 || hd.per_pattern > 8192 || hd.n_entry_total < hd.n_entry ||
+                             hd.n_entry_total > hd.n_entry + hd.n_blocks * hd.per_pattern)) ||
+        hd.w_mode < NHQ_WEIGHTS_DEFAULT ||
         hd.w_mode > NHQ_WEIGHTS_FIXED || (hd.abits != 1 && hd.abits != 2 && hd.abits != 4 && hd.abits != 8))
         return fail(NHQ_EIO, "index file header is inconsistent");
     // the file must hold exactly what the header announces (checked before
@@ -266,7 +283,10 @@ int nhq_index_load(const char *path, void *stream, nhq_index **out)
         ix->nsw_batch = hd.nsw_batch;
         ix->nsw_beam = hd.nsw_beam;
         std::vector<char> buf(kChunk);
-        const size_t n = (size_t)hd.n, cap = (size_t)hd.cap, ne = (size_t)hd.n_entry, dp = (size_t)hd.dp;
+        ix->n_blocks = hd.n_blocks;
+        ix->per_pattern = hd.per_pattern;
+        ix->n_entry_total = hd.n_blocks > 0 ? hd.n_entry_total : hd.n_entry;
+        const size_t n = (size_t)hd.n, cap = (size_t)hd.cap, ne = (size_t)ix->n_entry_total, dp = (size_t)hd.dp;
         // every array goes straight into its field, so free_index releases
         // whatever a failed load had allocated
         if ((rc = read_dev(f, (void **)&ix->vec32, sizeof(float) * n * dp, sizeof(float) * cap * dp, buf)) !=
@@ -307,9 +327,38 @@ int nhq_index_load(const char *path, void *stream, nhq_index **out)
         if ((rc = read_dev(f, (void **)&ix->entry_attr, sizeof(uint32_t) * ne, sizeof(uint32_t) * ne, buf)) !=
             NHQ_OK)
             break;
-        if (hd.has_entry_bf16 && (rc = read_dev(f, (void **)&ix->entry_bf16, sizeof(uint16_t) * ne * dp,
-                                                sizeof(uint16_t) * ne * dp, buf)) != NHQ_OK)
+        const size_t neg = (size_t)hd.n_entry;
+        if (hd.has_entry_bf16 && (rc = read_dev(f, (void **)&ix->entry_bf16, sizeof(uint16_t) * neg * dp,
+                                                sizeof(uint16_t) * neg * dp, buf)) != NHQ_OK)
             break;
+        if (hd.n_blocks > 0) {
+            const size_t B = (size_t)hd.n_blocks;
+            ix->block_word_h.resize(B);
+            ix->block_off_h.resize(B + 1);
+            if (std::fread(ix->block_word_h.data(), sizeof(uint32_t), B, f) != B ||
+                std::fread(ix->block_off_h.data(), sizeof(int32_t), B + 1, f) != B + 1) {
+                rc = fail(NHQ_EIO, "index file is truncated");
+                break;
+            }
+            bool ok = ix->block_off_h[0] == hd.n_entry && ix->block_off_h[B] == hd.n_entry_total;
+            for (size_t b = 0; b < B && ok; ++b)
+                ok = ix->block_off_h[b] < ix->block_off_h[b + 1] &&
+                     ix->block_off_h[b + 1] - ix->block_off_h[b] <= hd.per_pattern &&
+                     (b == 0 || ix->block_word_h[b - 1] < ix->block_word_h[b]);
+            if (!ok) {
+                rc = fail(NHQ_EIO, "index file block table is inconsistent");
+                break;
+            }
+            if (hipMalloc(&ix->block_word, sizeof(uint32_t) * B) != hipSuccess ||
+                hipMalloc(&ix->block_off, sizeof(int32_t) * (B + 1)) != hipSuccess ||
+                hipMemcpy(ix->block_word, ix->block_word_h.data(), sizeof(uint32_t) * B, hipMemcpyHostToDevice) !=
+                    hipSuccess ||
+                hipMemcpy(ix->block_off, ix->block_off_h.data(), sizeof(int32_t) * (B + 1), hipMemcpyHostToDevice) !=
+                    hipSuccess) {
+                rc = fail(NHQ_ENOMEM, "index allocation failed");
+                break;
+            }
+        }
         const size_t lp = sizeof(float) * NHQ_MAX_ATTRS * 256;
         if ((rc = read_dev(f, (void **)&ix->logp, lp, lp, buf)) != NHQ_OK)
             break;

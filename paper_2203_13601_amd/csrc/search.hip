@@ -117,7 +117,7 @@ int launch_search(const SearchLaunch &s)
     a.m = ix->m;
     a.R = ix->degree;
     a.n_seed = s.n_seed_cand;
-    a.n_entry = s.entry_override ? s.n_entry_override : ix->n_entry;
+    a.n_entry = s.entry_override ? s.n_entry_override : ix->n_entry_total;
     a.k = s.k;
     a.L = s.L;
     a.n_init = s.n_init;

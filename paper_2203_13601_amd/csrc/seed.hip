@@ -67,6 +67,13 @@ struct KeyArgs {
     Weights w;            // weight setting of Gamma
     int abits;            // attribute field width
     uint32_t hmask;       // high bit of every attribute field
+    // stratified sample (seg non-null): workgroup x ranks its 64 query rows
+    // against entry block seg[x] (n_blocks: the n_global global members;
+    // < 0: no rows), whose members are entries block_off[b] ..
+    // block_off[b + 1] - 1
+    const int32_t *seg = nullptr;
+    const int32_t *block_off = nullptr;
+    int n_blocks = 0, n_global = 0;
 };
 
 // the wave's group minima (16 rows, ng groups from group gbeg) to HBM, each
@@ -205,10 +212,25 @@ __device__ __forceinline__ bool group_exact(const KeyArgs &a, int64_t rowc)
 // Float32 products (v_mfma_f32_16x16x4f32); workgroups whose queries are
 // all exact in bf16 are left to k_entry_keys_b16.
 template <int DP, bool DEF, int TL>
-__global__ __launch_bounds__(256) void k_entry_keys(const KeyArgs a)
+__global__ __launch_bounds__(256) void k_entry_keys(const KeyArgs a0)
 {
     using K = KShape<DP>;
     constexpr int kKeyTiles = TL, kGmStride = GmStride<TL>::v;
+    KeyArgs a = a0;
+    if (a0.seg) {  // stratified: this workgroup's entry block (uniform per workgroup)
+        const int b = a0.seg[blockIdx.x];
+        if (b < 0)
+            return;
+        int e0 = 0, cnt = a0.n_global;
+        if (b < a0.n_blocks) {
+            e0 = a0.block_off[b];
+            cnt = a0.block_off[b + 1] - e0;
+        }
+        a.ev += (int64_t)e0 * DP;
+        a.en += e0;
+        a.ea += e0;
+        a.ne = cnt;
+    }
     // entry tile; afterwards the key staging of the four waves
     __shared__ __align__(16) float tile[64 * K::LDSW > 4 * 16 * 68 ? 64 * K::LDSW : 4 * 16 * 68];
     __shared__ float gms[4 * 16 * kGmStride];
@@ -392,11 +414,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
 // One wave per query, K > 64: the row in registers, a radix select over it.
 template <int NJ>
 __global__ __launch_bounds__(64) void k_entry_select(const float *__restrict__ keys, int64_t nq,
-                                                     int ne, int ne_pad, int K, int32_t *__restrict__ cand)
+                                                     int ne, int ne_pad, int K, int32_t *__restrict__ cand,
+                                                     const int32_t *__restrict__ live)
 {
     const int lane = threadIdx.x;
     const int64_t qi = blockIdx.x;
-    if (qi >= nq)
+    if (qi >= nq || (live && live[qi] < 0))
         return;
     const float *row = keys + qi * ne_pad;
     int32_t *out = cand + qi * K;
@@ -415,7 +438,8 @@ __global__ __launch_bounds__(64) void k_entry_select(const float *__restrict__ k
 template <int GPL>
 __global__ __launch_bounds__(64) void k_entry_select_g(const float *__restrict__ keys,
                                                        const float *__restrict__ gmin, int64_t nq, int ne,
-                                                       int ne_pad, int K, int32_t *__restrict__ cand)
+                                                       int ne_pad, int K, int32_t *__restrict__ cand,
+                                                       const int32_t *__restrict__ live)
 {
     constexpr int kRounds = 16;  // 64 groups of 16 keys
     constexpr int kCap = 128;    // kept keys
@@ -424,7 +448,7 @@ __global__ __launch_bounds__(64) void k_entry_select_g(const float *__restrict__
     __shared__ int32_t cp[256];
     const int lane = threadIdx.x;
     const int64_t qi = blockIdx.x;
-    if (qi >= nq)
+    if (qi >= nq || (live && live[qi] < 0))
         return;
     const int ng = ne_pad / 16;
     const uint32_t *row = reinterpret_cast<const uint32_t *>(keys + qi * ne_pad);
@@ -501,19 +525,15 @@ __global__ __launch_bounds__(64) void k_entry_select_g(const float *__restrict__
 }  // namespace
 
 // positions of the n_cand best entry-sample members per query (unordered)
-int launch_seed_rank(const Index *ix, const float *qpad, const float *qnorm, const uint32_t *qword,
-                     const uint32_t *qmask, const uint32_t *qexact, int64_t nq, int K, float *keys,
-                     int32_t *cand, hipStream_t st)
+namespace {
+
+// the key kernels over rows 0 .. a.nq - 1 (query groups of 64) and entry
+// tiles of a.ne_pad columns
+int launch_keys(const Index *ix, const KeyArgs &a, hipStream_t st)
 {
-    const int ne = ix->n_entry;
-    const int ne_pad = (ne + 63) / 64 * 64;
-    const int nj = ne_pad / 64;
-    if (nj > 128)
-        return fail(NHQ_EINVAL, "entry sample larger than 8192");
-    KeyArgs a{qpad, qnorm, qword, qmask, ix->entry_vec, ix->entry_norm, ix->entry_attr, ix->entry_bf16,
-              qexact, keys, keys + (size_t)nq * ne_pad, nq, ne, ne_pad, ix->w, ix->abits, ix->hmask};
+    const int nj = a.ne_pad / 64;
     // tiles per workgroup: the most (up to 8) that still give >= 1024 workgroups
-    const int64_t qgroups = (nq + 63) / 64;
+    const int64_t qgroups = (a.nq + 63) / 64;
     int tl = 1;
     for (int t : {kMaxKeyTiles, 2})
         if (qgroups * ((nj + t - 1) / t) >= 1024) {
@@ -565,29 +585,271 @@ int launch_seed_rank(const Index *ix, const float *qpad, const float *qnorm, con
     }
     if (rc == NHQ_OK && hipGetLastError() != hipSuccess)
         rc = fail(NHQ_EHIP, "entry key launch failed");
-    if (rc == NHQ_OK) {
-        const dim3 g2((unsigned)nq);
-        const int gpl = (ne_pad / 16 + 63) / 64;
-        if (K <= 64) {
-            if (gpl <= 1)
-                hipLaunchKernelGGL(k_entry_select_g<1>, g2, dim3(64), 0, st, keys, a.gmin, nq, ne, ne_pad, K, cand);
-            else if (gpl <= 2)
-                hipLaunchKernelGGL(k_entry_select_g<2>, g2, dim3(64), 0, st, keys, a.gmin, nq, ne, ne_pad, K, cand);
-            else if (gpl <= 4)
-                hipLaunchKernelGGL(k_entry_select_g<4>, g2, dim3(64), 0, st, keys, a.gmin, nq, ne, ne_pad, K, cand);
-            else
-                hipLaunchKernelGGL(k_entry_select_g<8>, g2, dim3(64), 0, st, keys, a.gmin, nq, ne, ne_pad, K, cand);
-        } else if (nj <= 16)
-            hipLaunchKernelGGL(k_entry_select<16>, g2, dim3(64), 0, st, keys, nq, ne, ne_pad, K, cand);
-        else if (nj <= 32)
-            hipLaunchKernelGGL(k_entry_select<32>, g2, dim3(64), 0, st, keys, nq, ne, ne_pad, K, cand);
-        else if (nj <= 64)
-            hipLaunchKernelGGL(k_entry_select<64>, g2, dim3(64), 0, st, keys, nq, ne, ne_pad, K, cand);
+    return rc;
+}
+
+// positions of the K best keys of each row (rows with live[row] < 0 skipped)
+int launch_select(const float *keys, const float *gmin, int64_t rows, int ne, int ne_pad, int K, int32_t *cand,
+                  const int32_t *live, hipStream_t st)
+{
+    const int nj = ne_pad / 64;
+    const dim3 g2((unsigned)rows);
+    const int gpl = (ne_pad / 16 + 63) / 64;
+    if (K <= 64) {
+        if (gpl <= 1)
+            hipLaunchKernelGGL(k_entry_select_g<1>, g2, dim3(64), 0, st, keys, gmin, rows, ne, ne_pad, K, cand, live);
+        else if (gpl <= 2)
+            hipLaunchKernelGGL(k_entry_select_g<2>, g2, dim3(64), 0, st, keys, gmin, rows, ne, ne_pad, K, cand, live);
+        else if (gpl <= 4)
+            hipLaunchKernelGGL(k_entry_select_g<4>, g2, dim3(64), 0, st, keys, gmin, rows, ne, ne_pad, K, cand, live);
         else
-            hipLaunchKernelGGL(k_entry_select<128>, g2, dim3(64), 0, st, keys, nq, ne, ne_pad, K, cand);
-        if (hipGetLastError() != hipSuccess)
-            rc = fail(NHQ_EHIP, "entry select launch failed");
+            hipLaunchKernelGGL(k_entry_select_g<8>, g2, dim3(64), 0, st, keys, gmin, rows, ne, ne_pad, K, cand, live);
+    } else if (nj <= 16)
+        hipLaunchKernelGGL(k_entry_select<16>, g2, dim3(64), 0, st, keys, rows, ne, ne_pad, K, cand, live);
+    else if (nj <= 32)
+        hipLaunchKernelGGL(k_entry_select<32>, g2, dim3(64), 0, st, keys, rows, ne, ne_pad, K, cand, live);
+    else if (nj <= 64)
+        hipLaunchKernelGGL(k_entry_select<64>, g2, dim3(64), 0, st, keys, rows, ne, ne_pad, K, cand, live);
+    else
+        hipLaunchKernelGGL(k_entry_select<128>, g2, dim3(64), 0, st, keys, rows, ne, ne_pad, K, cand, live);
+    if (hipGetLastError() != hipSuccess)
+        return fail(NHQ_EHIP, "entry select launch failed");
+    return NHQ_OK;
+}
+
+// ---- stratified entry sample: queries grouped by their pattern's block
+
+// zero the block counters and cursors, mark every slot empty
+__global__ void k_strata_clear(int32_t *hist, int32_t *cursor, int nb, int32_t *inv, int64_t slots)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nb) {
+        hist[t] = 0;
+        cursor[t] = 0;
     }
+    if (t < slots)
+        inv[t] = -1;
+}
+
+// each query's block: its pattern's when every attribute is constrained and
+// some object holds the pattern (binary search of the sorted block words),
+// else the global members (n_blocks)
+__global__ void k_strata_assign(const uint32_t *__restrict__ qword, const uint32_t *__restrict__ qmask,
+                                int64_t nq, int full_bits, const uint32_t *__restrict__ block_word, int n_blocks,
+                                int32_t *__restrict__ qblock, int32_t *__restrict__ hist)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq)
+        return;
+    int b = n_blocks;
+    if (__popc(qmask[q]) == full_bits) {
+        const uint32_t w = qword[q];
+        int lo = 0, hi = n_blocks;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (block_word[mid] < w)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        if (lo < n_blocks && block_word[lo] == w)
+            b = lo;
+    }
+    qblock[q] = b;
+    atomicAdd(&hist[b], 1);
+}
+
+// slot ranges: block b owns slots off[b] .. off[b] + hist[b] - 1 (ranges
+// start at multiples of 64); seg[g] = the block of slots 64 g .. 64 g + 63,
+// -1 past the last
+__global__ __launch_bounds__(64) void k_strata_scan(const int32_t *__restrict__ hist, int nb,
+                                                    int32_t *__restrict__ off, int32_t *__restrict__ seg,
+                                                    int64_t nseg)
+{
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int b = 0; b < nb; ++b) {
+            off[b] = run;
+            run += (hist[b] + 63) & ~63;
+        }
+        off[nb] = run;
+    }
+    __syncthreads();
+    for (int64_t g = threadIdx.x; g < nseg; g += 64) {
+        const int32_t s0 = (int32_t)(64 * g);
+        int b = -1;
+        if (s0 < off[nb]) {
+            int lo = 0, hi = nb - 1;  // the last block whose range starts at or before s0
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (off[mid] <= s0)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            b = lo;
+        }
+        seg[g] = b;
+    }
+}
+
+__global__ void k_strata_slot(const int32_t *__restrict__ qblock, int64_t nq, const int32_t *__restrict__ off,
+                              int32_t *__restrict__ cursor, int32_t *__restrict__ perm, int32_t *__restrict__ inv)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq)
+        return;
+    const int b = qblock[q];
+    const int32_t slot = off[b] + atomicAdd(&cursor[b], 1);
+    perm[q] = slot;
+    inv[slot] = (int32_t)q;
+}
+
+// the padded query rows, norms and codes in slot order (empty slots: zeros)
+__global__ void k_strata_permute(const float *__restrict__ qpad, const float *__restrict__ qnorm,
+                                 const uint32_t *__restrict__ qword, const uint32_t *__restrict__ qmask,
+                                 const int32_t *__restrict__ inv, int64_t slots, int dp, float *__restrict__ spad,
+                                 float *__restrict__ snorm, uint32_t *__restrict__ sword, uint32_t *__restrict__ smask)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= slots * dp)
+        return;
+    const int64_t s = t / dp;
+    const int c = (int)(t - s * dp);
+    const int32_t q = inv[s];
+    spad[t] = q >= 0 ? qpad[(int64_t)q * dp + c] : 0.0f;
+    if (c == 0) {
+        snorm[s] = q >= 0 ? qnorm[q] : 0.0f;
+        sword[s] = q >= 0 ? qword[q] : 0u;
+        smask[s] = q >= 0 ? qmask[q] : 0u;
+    }
+}
+
+// block-local positions of each query's slot -> positions in the whole
+// entry sample (-1 past the block's members)
+__global__ void k_strata_gather(const int32_t *__restrict__ cslot, const int32_t *__restrict__ perm,
+                                const int32_t *__restrict__ qblock, const int32_t *__restrict__ block_off,
+                                int n_blocks, int n_global, int64_t nq, int K, int32_t *__restrict__ cand)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nq * K)
+        return;
+    const int64_t q = t / K;
+    const int j = (int)(t - q * K);
+    const int b = qblock[q];
+    const int32_t e0 = b < n_blocks ? block_off[b] : 0;
+    const int32_t cnt = b < n_blocks ? block_off[b + 1] - e0 : n_global;
+    const int32_t loc = cslot[(int64_t)perm[q] * K + j];
+    cand[t] = (loc >= 0 && loc < cnt) ? e0 + loc : -1;
+}
+
+struct StrataLayout {
+    int64_t slots, nseg;
+    int nb, ne_pad;
+    size_t o_spad, o_snorm, o_sword, o_smask, o_keys, o_gmin, o_cslot, o_qblock, o_perm, o_inv, o_hist, o_off,
+        o_cursor, o_seg, words;
+};
+
+StrataLayout strata_layout(const Index *ix, int64_t nq, int K)
+{
+    StrataLayout L{};
+    L.nb = ix->n_blocks + 1;
+    L.slots = (nq + 64 * (int64_t)L.nb + 63) / 64 * 64;
+    L.nseg = L.slots / 64;
+    int emax = ix->n_entry;
+    for (int b = 0; b < ix->n_blocks; ++b)
+        emax = std::max(emax, ix->block_off_h[b + 1] - ix->block_off_h[b]);
+    L.ne_pad = (emax + 63) / 64 * 64;
+    size_t o = 0;
+    auto take = [&](size_t words) {
+        const size_t at = o;
+        o += (words + 63) / 64 * 64;  // 256-byte pieces
+        return at;
+    };
+    L.o_spad = take((size_t)L.slots * ix->dp);
+    L.o_snorm = take((size_t)L.slots);
+    L.o_sword = take((size_t)L.slots);
+    L.o_smask = take((size_t)L.slots);
+    L.o_keys = take((size_t)L.slots * L.ne_pad);
+    L.o_gmin = take((size_t)L.slots * (L.ne_pad / 16));
+    L.o_cslot = take((size_t)L.slots * K);
+    L.o_qblock = take((size_t)nq);
+    L.o_perm = take((size_t)nq);
+    L.o_inv = take((size_t)L.slots);
+    L.o_hist = take((size_t)L.nb + 1);
+    L.o_off = take((size_t)L.nb + 1);
+    L.o_cursor = take((size_t)L.nb + 1);
+    L.o_seg = take((size_t)L.nseg);
+    L.words = o;
+    return L;
+}
+
+}  // namespace
+
+size_t strata_rank_words(const Index *ix, int64_t nq, int K)
+{
+    return strata_layout(ix, nq, K).words;
+}
+
+int launch_strata_rank(const Index *ix, const float *qpad, const float *qnorm, const uint32_t *qword,
+                       const uint32_t *qmask, int64_t nq, int K, uint32_t *blk, int32_t *cand, hipStream_t st)
+{
+    const StrataLayout L = strata_layout(ix, nq, K);
+    float *spad = reinterpret_cast<float *>(blk + L.o_spad);
+    float *snorm = reinterpret_cast<float *>(blk + L.o_snorm);
+    uint32_t *sword = blk + L.o_sword, *smask = blk + L.o_smask;
+    float *keys = reinterpret_cast<float *>(blk + L.o_keys);
+    float *gmin = reinterpret_cast<float *>(blk + L.o_gmin);
+    int32_t *cslot = reinterpret_cast<int32_t *>(blk + L.o_cslot);
+    int32_t *qblock = reinterpret_cast<int32_t *>(blk + L.o_qblock);
+    int32_t *perm = reinterpret_cast<int32_t *>(blk + L.o_perm);
+    int32_t *inv = reinterpret_cast<int32_t *>(blk + L.o_inv);
+    int32_t *hist = reinterpret_cast<int32_t *>(blk + L.o_hist);
+    int32_t *off = reinterpret_cast<int32_t *>(blk + L.o_off);
+    int32_t *cursor = reinterpret_cast<int32_t *>(blk + L.o_cursor);
+    int32_t *seg = reinterpret_cast<int32_t *>(blk + L.o_seg);
+    const int64_t clear = std::max<int64_t>(L.slots, L.nb);
+    hipLaunchKernelGGL(k_strata_clear, dim3((unsigned)((clear + 255) / 256)), dim3(256), 0, st, hist, cursor, L.nb,
+                       inv, L.slots);
+    hipLaunchKernelGGL(k_strata_assign, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, qword, qmask, nq,
+                       ix->m * ix->abits, ix->block_word, ix->n_blocks, qblock, hist);
+    hipLaunchKernelGGL(k_strata_scan, dim3(1), dim3(64), 0, st, hist, L.nb, off, seg, L.nseg);
+    hipLaunchKernelGGL(k_strata_slot, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, qblock, nq, off, cursor,
+                       perm, inv);
+    hipLaunchKernelGGL(k_strata_permute, dim3((unsigned)((L.slots * ix->dp + 255) / 256)), dim3(256), 0, st, qpad,
+                       qnorm, qword, qmask, inv, L.slots, ix->dp, spad, snorm, sword, smask);
+    NHQ_HIP(hipGetLastError());
+    KeyArgs a{spad, snorm, sword, smask, ix->entry_vec, ix->entry_norm, ix->entry_attr, nullptr,
+              nullptr, keys, gmin, L.slots, ix->n_entry, L.ne_pad, ix->w, ix->abits, ix->hmask};
+    a.seg = seg;
+    a.block_off = ix->block_off;
+    a.n_blocks = ix->n_blocks;
+    a.n_global = ix->n_entry;
+    int rc = launch_keys(ix, a, st);
+    if (rc != NHQ_OK)
+        return rc;
+    rc = launch_select(keys, gmin, L.slots, L.ne_pad, L.ne_pad, K, cslot, inv, st);
+    if (rc != NHQ_OK)
+        return rc;
+    hipLaunchKernelGGL(k_strata_gather, dim3((unsigned)((nq * K + 255) / 256)), dim3(256), 0, st, cslot, perm,
+                       qblock, ix->block_off, ix->n_blocks, ix->n_entry, nq, K, cand);
+    NHQ_HIP(hipGetLastError());
+    return NHQ_OK;
+}
+
+int launch_seed_rank(const Index *ix, const float *qpad, const float *qnorm, const uint32_t *qword,
+                     const uint32_t *qmask, const uint32_t *qexact, int64_t nq, int K, float *keys,
+                     int32_t *cand, hipStream_t st)
+{
+    const int ne = ix->n_entry;
+    const int ne_pad = (ne + 63) / 64 * 64;
+    if (ne_pad / 64 > 128)
+        return fail(NHQ_EINVAL, "entry sample larger than 8192");
+    KeyArgs a{qpad, qnorm, qword, qmask, ix->entry_vec, ix->entry_norm, ix->entry_attr, ix->entry_bf16,
+              qexact, keys, keys + (size_t)nq * ne_pad, nq, ne, ne_pad, ix->w, ix->abits, ix->hmask};
+    int rc = launch_keys(ix, a, st);
+    if (rc == NHQ_OK)
+        rc = launch_select(keys, a.gmin, nq, ne, ne_pad, K, cand, nullptr, st);
     return rc;
 }
 
