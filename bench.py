@@ -354,7 +354,11 @@ def headline(args):
         mixed, mixed_net = mixed_selectivity(args, w, ix, ixb, tq)
     serving = None
     if not args.no_serve:
-        serving = serve_config5(args, w, ixb, ix, h, tq, x.device, mixed_net)
+        fixed_beam = None
+        if mixed is not None:
+            ok = [p["beam"] for p in mixed["fixed_sweep"] if p["recall"] >= target]
+            fixed_beam = ok[0] if ok else None
+        serving = serve_config5(args, w, ixb, ix, h, tq, x.device, mixed_net, fixed_beam)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args, w, ix, h, forms["fp32_fixed"]["beam"], rerank_n=0)
@@ -452,7 +456,7 @@ def mixed_selectivity(args, w, ix, ixb, tq):
     return _r(out), params
 
 
-def serve_config5(args, w, ixb, ix32, h, tq, dev, params=None):
+def serve_config5(args, w, ixb, ix32, h, tq, dev, params=None, fixed_beam=None):
     """The serving form: Poisson stream through the continuous-batching
     server on the BF16 index (float32 re-score), then a saturation run."""
     import torch
@@ -496,12 +500,19 @@ def serve_config5(args, w, ixb, ix32, h, tq, dev, params=None):
     sp = dict(n_init=args.n_init, expand=args.expand, rerank=4, auto_beam=beam_auto, beam_small=beam_auto,
               beam_large=-1, max_k=100, ring=16384, learned_mode=2, cap_factor=s_cf, stop_threshold=0.9,
               check_every=ce, lifetime_s=180.0)
+    sat_n = min(ns, args.serve_saturation_requests)
+    rf = rfs = None
     with nhq.Server(ixb, **sp) as srv:
         r = srv.run(s_q, s_qa, s_k, s_beam, s_arr, timeout_s=120.0)
         slots, hz = srv.slots, srv.tick_hz
         # saturation: the same requests offered all at once
-        sat_n = min(ns, args.serve_saturation_requests)
         rs = srv.run(s_q[:sat_n], s_qa[:sat_n], s_k[:sat_n], s_beam[:sat_n], np.zeros(sat_n), timeout_s=120.0)
+        if fixed_beam is not None:
+            # the method without the network: every request at the fixed beam
+            # that reaches the target on the mixed batch (stream, then saturation)
+            fb = np.full(ns, fixed_beam, dtype=np.int32)
+            rf = srv.run(s_q, s_qa, s_k, fb, s_arr, timeout_s=120.0)
+            rfs = srv.run(s_q[:sat_n], s_qa[:sat_n], s_k[:sat_n], fb[:sat_n], np.zeros(sat_n), timeout_s=120.0)
     lat_ms = r["latency_s"] * 1000.0
     svc_ms = (r["ticks"][:, 1].astype(np.float64) - r["ticks"][:, 0]) / hz * 1000.0
     rec = recall_at_k(r["ids"][samp, :10], w.x, s_q[samp], w.attrs, s_qa[samp], gsi, w.k)
@@ -527,6 +538,25 @@ def serve_config5(args, w, ixb, ix32, h, tq, dev, params=None):
     log("serving: %d requests at %.0f/s: p50 %.3f ms, p99 %.3f ms, recall@10 %.4f; saturation %.0f QPS" % (
         ns, args.serve_rate, out["p50_ms"], out["p99_ms"], out["recall_at_10_k_ge_10"],
         out["saturation"]["sustained_qps"]))
+    if rf is not None:
+        sat = samp[samp < sat_n]
+        lf = rf["latency_s"] * 1000.0
+        out["fixed_beam_form"] = {
+            "beam": int(fixed_beam), "p50_ms": round(float(np.percentile(lf, 50)), 4),
+            "p99_ms": round(float(np.percentile(lf, 99)), 4),
+            "recall_at_10_k_ge_10": round(float(recall_at_k(rf["ids"][samp, :10], w.x, s_q[samp], w.attrs,
+                                                            s_qa[samp], gsi, w.k).mean()), 5),
+            "hops_mean": round(float(rf["counters"][:, 1].mean()), 2),
+            "saturation_qps": round(sat_n / rfs["elapsed_s"], 1),
+            "saturation_recall": round(float(recall_at_k(rfs["ids"][sat, :10], w.x, s_q[sat], w.attrs,
+                                                         s_qa[sat], gsi[np.isin(samp, sat)], w.k).mean()), 5)}
+        out["saturation"]["recall_at_10_k_ge_10"] = round(float(recall_at_k(
+            rs["ids"][sat, :10], w.x, s_q[sat], w.attrs, s_qa[sat], gsi[np.isin(samp, sat)], w.k).mean()), 5)
+        out["learned_saturation_speedup_vs_fixed"] = round(out["saturation"]["sustained_qps"]
+                                                           / out["fixed_beam_form"]["saturation_qps"], 4)
+        log("serving, fixed beam %d: p50 %.3f ms, p99 %.3f ms, recall@10 %.4f, saturation %.0f QPS" % (
+            fixed_beam, out["fixed_beam_form"]["p50_ms"], out["fixed_beam_form"]["p99_ms"],
+            out["fixed_beam_form"]["recall_at_10_k_ge_10"], out["fixed_beam_form"]["saturation_qps"]))
     return out
 
 
@@ -648,14 +678,108 @@ def plain(args):
                       "forms": _r(forms), "roofline": roof, "cpu_baseline": cpu}), flush=True)
 
 
+def learned10m(args):
+    """The learned-stop form at full size: 10,000,000 Gaussian-mixture
+    vectors of d = 96 (1,024 centres), 3 attributes of cardinality 3/4/5
+    with Zipf(1.1) codes, fully constrained queries whose code tuples follow
+    the data (|P|/|S| from 1/681 to 1/7.5).  The composite index (NN-descent
+    candidate lists) with a stratified entry sample (--entry-per-pattern per
+    attribute pattern).  The stop network is trained on the GPU from traces
+    of 200,000 training queries and evaluated on 10,000 held-out queries:
+    the fixed-beam sweep against the learned hop budget, QPS at
+    Recall@10 = 0.95 interpolated for each, and the hops at equal recall."""
+    import torch
+    import synth
+    import paper_2203_13601_amd as nhq
+    from paper_2203_13601_amd.learned import train_stop_network
+    from paper_2203_13601_amd.metrics import qps_at_recall
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    w = synth.config4(n=args.n, nq=args.nq)
+    tq_np, tqa_np = synth.config4_train_queries(args.train_queries)
+    log("generated %s in %.1fs" % (w.name, time.time() - t0))
+    x = torch.from_numpy(w.x).to(dev)
+    a = torch.from_numpy(w.attrs).to(dev)
+    tq, tqa = torch.from_numpy(tq_np).to(dev), torch.from_numpy(tqa_np).to(dev)
+    h = Harness(w, args, dev)
+    t0 = time.time()
+    ix = nhq.nhq_build_index(x, a, degree=w.degree, cand=w.cand, n_entry=args.n_entry, seed=w.build_seed,
+                             builder="nndescent", entry_per_pattern=args.entry_per_pattern)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    log("built (NN-descent, %d rounds, stratified entry sample %d per pattern) in %.1fs" % (
+        nhq.nhq_index_build_report(ix)["nnd_rounds_run"], args.entry_per_pattern, build_s))
+    gi, _ = nhq.nhq_bruteforce_hybrid_knn(ix, h.q, h.qa, w.k)
+    h.gt = gi.cpu().numpy()
+    target, ce = args.target, args.check_every
+    fixed = _sweep(h, ix, "fixed", [10, 12, 16, 20, 24, 32, 40, 48, 64, 96, 128], target)
+    runs = []
+    for l_train in args.learned_beams:
+        t0 = time.time()
+        params, info = train_stop_network(ix, tq, tqa, w.k, l_train, epochs=args.epochs, check_every=ce,
+                                          n_init=args.n_init, expand=args.expand, seed=1)
+        nhq.nhq_mlp_load(ix, params)
+        torch.cuda.synchronize()
+        train_s = time.time() - t0
+        log("stop network at beam %d: %d samples from %d training queries, trained in %.1fs (loss %.4f)" % (
+            l_train, info["samples"], tq.shape[0], train_s, info["losses"][-1]))
+        pts = []
+        for cf in (0.5, 0.75, 1.0, 1.25, 1.5, 2.0, 2.5, 3.0):
+            p = h.point(ix, l_train, learned=2, stop_threshold=0.9, check_every=ce, cap_factor=cf)
+            p["cap_factor"] = cf
+            pts.append(p)
+            log("learned beam %d cap %.2f recall %.4f hops %.1f (p99 %.0f) %.0f QPS" % (
+                l_train, cf, p["recall"], p["hops"], p["hops_p99"], p["qps"]))
+            if p["recall"] >= target + 0.01 and len([q for q in pts if q["recall"] >= target]) >= 2:
+                break
+        runs.append({"beam": l_train, "train_samples": info["samples"], "train_s": train_s,
+                     "positive_rate": info["positive_rate"], "sweep": pts,
+                     "qps_at_target_interp": qps_at_recall([p["cap_factor"] for p in pts],
+                                                           [p["recall"] for p in pts], [p["qps"] for p in pts],
+                                                           target),
+                     "hops_at_target": _interp_at(pts, target, "hops")})
+    fa = qps_at_recall([p["beam"] for p in fixed], [p["recall"] for p in fixed], [p["qps"] for p in fixed], target)
+    best = max(runs, key=lambda r: r["qps_at_target_interp"] or 0.0)
+    out = {"metric": "hybrid QPS at Recall@10=0.95 on 1 GPU, learned stop vs fixed beam (10M x 96, Zipf)",
+           "value": None if best["qps_at_target_interp"] is None else round(best["qps_at_target_interp"], 1),
+           "unit": "queries/s", "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": w.name, "n": w.n, "d": w.d, "cards": list(w.cards), "queries": w.nq,
+                      "train_queries": int(tq.shape[0]), "k": w.k, "n_entry": args.n_entry,
+                      "entry_per_pattern": args.entry_per_pattern, "n_init": args.n_init, "expand": args.expand,
+                      "builder": "nndescent", "build_s": round(build_s, 2), "storage": "fp32"},
+           "fixed_qps_at_target_interp": fa, "fixed_hops_at_target": _interp_at(fixed, target, "hops"),
+           "learned_qps_at_target_interp": best["qps_at_target_interp"],
+           "learned_hops_at_target": best["hops_at_target"],
+           "learned_speedup_vs_fixed": None if not (fa and best["qps_at_target_interp"]) else
+           best["qps_at_target_interp"] / fa,
+           "fixed_sweep": fixed, "learned": runs}
+    print(json.dumps(_r(out)), flush=True)
+
+
+def _interp_at(pts, target, key):
+    """`key` interpolated linearly in recall at the target (None if never reached)"""
+    prev = None
+    for p in pts:
+        if p["recall"] >= target:
+            if prev is None or prev["recall"] >= p["recall"]:
+                return p[key]
+            t = (target - prev["recall"]) / (p["recall"] - prev["recall"])
+            return prev[key] + t * (p[key] - prev[key])
+        prev = p
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="headline", choices=["headline", "plain", "ablation", "build"],
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "plain", "learned10m", "ablation", "build"],
                     help="headline: 1M x 960 FP32 / BF16 / BF16 + learned stop and serving (default); "
-                         "plain: 1M x 128 integer workload; ablation: weight settings, selectivity and "
+                         "plain: 1M x 128 integer workload; learned10m: 10M x 96 Zipf, learned stop vs fixed "
+                         "beam; ablation: weight settings, selectivity and "
                          "post-filtering sweeps; build: exact vs NN-descent vs NSW candidate lists")
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--nq", type=int, default=10_000)
@@ -668,7 +792,10 @@ def main():
     ap.add_argument("--builder", default="exact", choices=["exact", "nndescent"])
     ap.add_argument("--check-every", type=int, default=1)
     ap.add_argument("--learned-beams", type=int, nargs="+", default=[20, 24, 32])
-    ap.add_argument("--train-queries", type=int, default=20_000)
+    ap.add_argument("--train-queries", type=int, default=None,
+                    help="training queries of the stop network (20,000; 200,000 for learned10m)")
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--entry-per-pattern", type=int, default=8192)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=50_000.0)
     ap.add_argument("--serve-requests", type=int, default=500_000)
@@ -684,6 +811,10 @@ def main():
     args = ap.parse_args()
     if args.n_entry is None:
         args.n_entry = 1024 if args.workload == "headline" else 4096
+    if args.train_queries is None:
+        args.train_queries = 200_000 if args.workload == "learned10m" else 20_000
+    if args.workload == "learned10m" and args.n == 1_000_000:
+        args.n = 10_000_000
     if args.expand is None:
         args.expand = 2 if args.workload == "headline" else 6
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -691,7 +822,8 @@ def main():
         print("bench.py: this build measures one GPU only (--gpus 1); multi-GPU runs are not "
               "part of it", file=sys.stderr)
         sys.exit(2)
-    {"headline": headline, "plain": plain, "ablation": ablation, "build": build_study}[args.workload](args)
+    {"headline": headline, "plain": plain, "learned10m": learned10m, "ablation": ablation,
+     "build": build_study}[args.workload](args)
 
 def build_study(args):
     """Composite-index builds (Alg. 1 / Sec. 4.3): the exact all-pairs

@@ -260,6 +260,14 @@ def config4(n: int = 10_000_000, nq: int = 10_000, train: bool = False) -> Workl
                     build_seed=405, integer=False)
 
 
+def config4_train_queries(nq: int = 200_000):
+    """Training queries of the learned-stop form (same mixture and Zipf
+    attribute law as its base set, the training seeds 403 / 1403)."""
+    q = gaussian_mixture(nq, 96, 1024, seed=403, centre_seed=1401)
+    qa = zipf_attrs(nq, (3, 4, 5), 1403)
+    return q, qa
+
+
 def config5_stream(nq: int, cards: Sequence[int] = (2, 3, 5, 10), d: int = 960,
                    rate_per_s: float = 50_000.0):
     """Serving stream: query vectors from the precision-form mixture,

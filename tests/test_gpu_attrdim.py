@@ -52,7 +52,7 @@ def test_build_and_seeds(m):
     ix = nhq.nhq_build_index(_dev(w.x), _dev(w.attrs), degree=16, cand=32, n_entry=256, seed=5)
     adj = nhq.nhq_index_get_graph(ix).cpu().numpy()
     want = oracle.build_graph(w.x, w.attrs, l=32, R=16)
-    assert (adj == want).all(axis=1).mean() >= 0.999
+    assert (adj == want).all(), np.nonzero(~(adj == want).all(axis=1))[0][:10]
     cand = nhq.nhq_seed_rank(ix, _dev(w.q), _dev(w.qattrs), 24).cpu().numpy()
     entry = oracle.entry_points(5, w.n, 256)
     noedge = np.full((256, 1), -1, np.int32)

@@ -6,6 +6,7 @@ import pytest
 import torch
 
 import oracle
+from parity import assert_float_parity
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -60,9 +61,7 @@ def test_reduced_storage_search_matches_oracle_on_decoded_vectors(gmm, storage):
     ids, dist = ids.cpu().numpy(), dist.cpu().numpy()
     oi, og, _, _, _ = oracle.search(adj, xs, w.attrs, w.q, w.qattrs, 10, 64, entry,
                                     rerank_n=40, xr=w.x)
-    overlap = np.mean([len(set(a[a >= 0]) & set(b[b >= 0])) / max(1, (b >= 0).sum())
-                       for a, b in zip(ids, oi)])
-    assert overlap >= 0.98, overlap
+    assert_float_parity(ids, oi, w.x, w.attrs, w.q, w.qattrs)
     # every returned distance is the exact delta of the returned object (the
     # re-score reads the float32 copy): error against FP64 per result
     rel = []

@@ -13,6 +13,7 @@ import pytest
 import torch
 
 import oracle
+from parity import assert_float_parity
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -122,9 +123,7 @@ def test_float_data_matches_fp64_oracle(float_set):
     for L in (32, 64, 160):
         ids, dist, cnt = _gpu(ix, w, 10, L)
         oi, og, ondc, _, _ = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, L, entry)
-        overlap = np.mean([len(set(a[a >= 0]) & set(b[b >= 0])) / max(1, (b >= 0).sum())
-                           for a, b in zip(ids, oi)])
-        assert overlap >= 0.99, overlap
+        assert_float_parity(ids, oi, w.x, w.attrs, w.q, w.qattrs)
         _check_gamma(w, ids, dist)
         assert abs(cnt[:, 0].mean() - ondc.mean()) <= 0.02 * ondc.mean()
 

@@ -34,7 +34,14 @@ def test_build_matches_oracle(int_set, mode, p):
     with oracle.weights(mode, p):
         want = oracle.build_graph(w.x, w.attrs, l=32, R=16)
     same = (adj == want).all(axis=1)
-    assert same.mean() >= 0.999, same.mean()
+    if mode == "default":
+        # integer data: every default key is exact in the tiles and the re-score
+        assert same.all(), np.nonzero(~same)[0][:10]
+    else:
+        # the other settings' keys pass through float32 square roots and
+        # divisions in the candidate tiles; a near-tie there can push a
+        # candidate past the 16-entry re-score margin (design reading R6/R14)
+        assert same.mean() >= 0.999, same.mean()
 
 
 @pytest.mark.parametrize("mode,p", SETTINGS)

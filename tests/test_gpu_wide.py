@@ -10,6 +10,7 @@ import pytest
 import torch
 
 import oracle
+from parity import assert_float_parity
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -51,9 +52,7 @@ def test_search_matches_oracle_wide(d, storage):
     ids, dist = ids.cpu().numpy(), dist.cpu().numpy()
     oi, og, _, _, _ = oracle.search(adj, xs, w.attrs, w.q, w.qattrs, 10, 64, entry, rerank_n=10 * rr,
                                     xr=w.x if rr else None, expand=4)
-    overlap = np.mean([len(set(a[a >= 0]) & set(b[b >= 0])) / max(1, (b >= 0).sum())
-                       for a, b in zip(ids, oi)])
-    assert overlap >= 0.97, overlap
+    assert_float_parity(ids, oi, w.x, w.attrs, w.q, w.qattrs)
     for i in range(w.nq):
         mq = oracle.arity(w.qattrs[i])
         for v, g in zip(ids[i], dist[i]):
