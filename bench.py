@@ -312,7 +312,8 @@ def headline(args):
     kernel = "k_search_ck" if value_form == "bf16_learned" else "k_search"
     traffic = None
     if args.n == 1_000_000 and args.nq == 10_000:
-        traffic = _profiled_traffic(kernel, SEARCH_SOURCES, "_config3")
+        traffic = _profiled_traffic(kernel, SEARCH_SOURCES, "_n1M_d960_bf16_%s" % (
+            "learned" if value_form == "bf16_learned" else "fixed"))
     step_bytes = bq * h.nq + h.nq * (4.0 * w.d + 8.0 * h.n_cand)  # + the seed stage's query reads and candidates
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
@@ -356,8 +357,11 @@ def headline(args):
     if not args.no_serve:
         fixed_beam = None
         if mixed is not None:
-            ok = [p["beam"] for p in mixed["fixed_sweep"] if p["recall"] >= target]
-            fixed_beam = ok[0] if ok else None
+            # the fixed beams that bracket the target on the mixed batch
+            sw = mixed["fixed_sweep"]
+            ok = [i for i, p in enumerate(sw) if p["recall"] >= target]
+            if ok:
+                fixed_beam = [sw[ok[0] - 1]["beam"], sw[ok[0]]["beam"]] if ok[0] > 0 else [sw[ok[0]]["beam"]]
         serving = serve_config5(args, w, ixb, ix, h, tq, x.device, mixed_net, fixed_beam)
     cpu = None
     if not args.no_cpu_baseline:
@@ -508,11 +512,13 @@ def serve_config5(args, w, ixb, ix32, h, tq, dev, params=None, fixed_beam=None):
         # saturation: the same requests offered all at once
         rs = srv.run(s_q[:sat_n], s_qa[:sat_n], s_k[:sat_n], s_beam[:sat_n], np.zeros(sat_n), timeout_s=120.0)
         if fixed_beam is not None:
-            # the method without the network: every request at the fixed beam
-            # that reaches the target on the mixed batch (stream, then saturation)
-            fb = np.full(ns, fixed_beam, dtype=np.int32)
+            # the method without the network: every request at a fixed beam,
+            # the two beams that bracket the target on the mixed batch (the
+            # stream at the larger, saturation at both)
+            fb = np.full(ns, fixed_beam[-1], dtype=np.int32)
             rf = srv.run(s_q, s_qa, s_k, fb, s_arr, timeout_s=120.0)
-            rfs = srv.run(s_q[:sat_n], s_qa[:sat_n], s_k[:sat_n], fb[:sat_n], np.zeros(sat_n), timeout_s=120.0)
+            rfs = [(b, srv.run(s_q[:sat_n], s_qa[:sat_n], s_k[:sat_n], np.full(sat_n, b, np.int32),
+                               np.zeros(sat_n), timeout_s=120.0)) for b in fixed_beam]
     lat_ms = r["latency_s"] * 1000.0
     svc_ms = (r["ticks"][:, 1].astype(np.float64) - r["ticks"][:, 0]) / hz * 1000.0
     rec = recall_at_k(r["ids"][samp, :10], w.x, s_q[samp], w.attrs, s_qa[samp], gsi, w.k)
@@ -539,24 +545,36 @@ def serve_config5(args, w, ixb, ix32, h, tq, dev, params=None, fixed_beam=None):
         ns, args.serve_rate, out["p50_ms"], out["p99_ms"], out["recall_at_10_k_ge_10"],
         out["saturation"]["sustained_qps"]))
     if rf is not None:
+        from paper_2203_13601_amd.metrics import qps_at_recall
         sat = samp[samp < sat_n]
+        gsat = gsi[samp < sat_n]
+
+        def srec(ids):
+            return float(recall_at_k(ids[sat, :10], w.x, s_q[sat], w.attrs, s_qa[sat], gsat, w.k).mean())
         lf = rf["latency_s"] * 1000.0
+        sat_pts = [{"beam": int(b), "saturation_qps": round(sat_n / x["elapsed_s"], 1),
+                    "recall_at_10_k_ge_10": round(srec(x["ids"]), 5),
+                    "hops_mean": round(float(x["counters"][:, 1].mean()), 2)} for b, x in rfs]
+        lrec = srec(rs["ids"])
+        out["saturation"]["recall_at_10_k_ge_10"] = round(lrec, 5)
+        out["saturation"]["hops_mean"] = round(float(rs["counters"][:, 1].mean()), 2)
+        at = qps_at_recall([p["beam"] for p in sat_pts], [p["recall_at_10_k_ge_10"] for p in sat_pts],
+                           [p["saturation_qps"] for p in sat_pts], lrec)
         out["fixed_beam_form"] = {
-            "beam": int(fixed_beam), "p50_ms": round(float(np.percentile(lf, 50)), 4),
+            "beam": int(fixed_beam[-1]), "p50_ms": round(float(np.percentile(lf, 50)), 4),
             "p99_ms": round(float(np.percentile(lf, 99)), 4),
             "recall_at_10_k_ge_10": round(float(recall_at_k(rf["ids"][samp, :10], w.x, s_q[samp], w.attrs,
                                                             s_qa[samp], gsi, w.k).mean()), 5),
             "hops_mean": round(float(rf["counters"][:, 1].mean()), 2),
-            "saturation_qps": round(sat_n / rfs["elapsed_s"], 1),
-            "saturation_recall": round(float(recall_at_k(rfs["ids"][sat, :10], w.x, s_q[sat], w.attrs,
-                                                         s_qa[sat], gsi[np.isin(samp, sat)], w.k).mean()), 5)}
-        out["saturation"]["recall_at_10_k_ge_10"] = round(float(recall_at_k(
-            rs["ids"][sat, :10], w.x, s_q[sat], w.attrs, s_qa[sat], gsi[np.isin(samp, sat)], w.k).mean()), 5)
-        out["learned_saturation_speedup_vs_fixed"] = round(out["saturation"]["sustained_qps"]
-                                                           / out["fixed_beam_form"]["saturation_qps"], 4)
-        log("serving, fixed beam %d: p50 %.3f ms, p99 %.3f ms, recall@10 %.4f, saturation %.0f QPS" % (
-            fixed_beam, out["fixed_beam_form"]["p50_ms"], out["fixed_beam_form"]["p99_ms"],
-            out["fixed_beam_form"]["recall_at_10_k_ge_10"], out["fixed_beam_form"]["saturation_qps"]))
+            "saturation": sat_pts,
+            "saturation_qps_at_learned_recall_interp": None if at is None else round(at, 1)}
+        if at:
+            out["learned_saturation_speedup_vs_fixed_at_equal_recall"] = round(
+                out["saturation"]["sustained_qps"] / at, 4)
+        log("serving, fixed beam %d: p50 %.3f ms, p99 %.3f ms, recall@10 %.4f; saturation %s; at the learned "
+            "form's recall %.4f: %s QPS" % (fixed_beam[-1], out["fixed_beam_form"]["p50_ms"],
+                                           out["fixed_beam_form"]["p99_ms"],
+                                           out["fixed_beam_form"]["recall_at_10_k_ge_10"], sat_pts, lrec, at))
     return out
 
 

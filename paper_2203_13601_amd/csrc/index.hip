@@ -80,15 +80,22 @@ __global__ void k_pack_attr(const uint8_t *__restrict__ a, uint32_t *__restrict_
     }
 }
 
+// squared norm of each row: one wavefront per row, lane j summing elements
+// j, j + 64, ... (coalesced 256-byte loads), then a butterfly over the wave
 __global__ void k_row_norm(const float *__restrict__ v, float *__restrict__ norm, int64_t n, int dp)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
+    for (int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; i < n; i += waves) {
         const float *r = v + i * dp;
         float s = 0.0f;
-        for (int c = 0; c < dp; ++c)
+        for (int c = lane; c < dp; c += 64)
             s = fmaf(r[c], r[c], s);
-        norm[i] = s;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+            s += __shfl_xor(s, o, 64);
+        if (lane == 0)
+            norm[i] = s;
     }
 }
 
@@ -520,7 +527,7 @@ int nhq_index_create(const float *vecs, const uint8_t *attrs, int64_t n, int32_t
         } else {
             (void)hipMemsetAsync(ix->attr, 0, (size_t)n * sizeof(uint32_t), st);
         }
-        hipLaunchKernelGGL(k_row_norm, dim3(grid_for(n, 256)), dim3(256), 0, st, ix->vec32, ix->norm,
+        hipLaunchKernelGGL(k_row_norm, dim3(grid_for(n, 4)), dim3(256), 0, st, ix->vec32, ix->norm,
                            n, ix->dp);
         if (ix->storage == NHQ_STORAGE_FP32) {
             ix->vecs = ix->vec32;
@@ -709,7 +716,7 @@ int nhq_index_insert(nhq_index *h, const float *vecs, const uint8_t *attrs, int6
                            nb, m, ix->abits);
     else
         NHQ_HIP(hipMemsetAsync(ix->attr + s0, 0, (size_t)nb * sizeof(uint32_t), st));
-    hipLaunchKernelGGL(k_row_norm, dim3(grid_for(nb, 256)), dim3(256), 0, st, ix->vec32 + s0 * dp,
+    hipLaunchKernelGGL(k_row_norm, dim3(grid_for(nb, 4)), dim3(256), 0, st, ix->vec32 + s0 * dp,
                        ix->norm + s0, nb, dp);
     if (ix->storage == NHQ_STORAGE_BF16)
         hipLaunchKernelGGL(k_to_bf16, dim3(grid_for((int64_t)rows, 256)), dim3(256), 0, st,

@@ -145,6 +145,39 @@ def test_fp16_inference_matches_reference(setup):
     nhq.nhq_mlp_load(ix, None)
 
 
+def _check_learned(ix, w, adj, entry, wh, mode, tau, cf, ce, beam=128):
+    """The learned search against the oracle's.  Both evaluate the network on
+    the same fp16 weights, the kernel in float32 with float32 features, the
+    oracle in FP64, so a stop decision can differ only where the stop logit
+    (or the budget exponent) lies within rounding of its threshold.  Every
+    query must either equal the oracle's run, or stop at a hop count between
+    the oracle's runs with the threshold and the budget moved by that rounding
+    band -- and then return exactly the oracle's search state at that hop."""
+    import math
+    kw = dict(learned=mode, stop_threshold=tau, check_every=ce, counters=True)
+    if cf:
+        kw["cap_factor"] = cf
+    ids, dist, cnt = nhq.nhq_hybrid_search(ix, _dev(w.q), _dev(w.qattrs), 10, beam, **kw)
+    ids, hops = ids.cpu().numpy(), cnt.cpu().numpy()[:, 1].astype(np.int64)
+
+    def orun(t, c):
+        return oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, beam, entry, key_mode=oracle.KEY32,
+                             check_every=ce, mlp=wh, stop_threshold=t, cap_factor=c, learned_mode=mode)
+    o = orun(tau, cf)
+    eps = 1e-3                                   # logit / log2-budget rounding band
+    lg = math.log(tau / (1.0 - tau))
+    sig = lambda z: 1.0 / (1.0 + math.exp(-z))  # noqa: E731
+    early = orun(sig(lg - eps), cf * 2.0 ** -eps if cf else 0.0)
+    late = orun(sig(lg + eps), cf * 2.0 ** eps if cf else 0.0)
+    same = (ids == o[0]).all(axis=1) & (hops == o[3])
+    for q in np.nonzero(~same)[0]:
+        assert early[3][q] <= hops[q] <= late[3][q], (q, hops[q], early[3][q], o[3][q], late[3][q])
+        ref = oracle.search(adj, w.x, w.attrs, w.q[q:q + 1], w.qattrs[q:q + 1], 10, beam, entry,
+                            key_mode=oracle.KEY32, max_hops=int(hops[q]))
+        assert np.array_equal(ref[0][0], ids[q]), q
+    return float(same.mean())
+
+
 def test_learned_search_matches_oracle(setup):
     w, adj, ix, entry = setup
     p = oracle.MLPRef.init(6)
@@ -153,22 +186,10 @@ def test_learned_search_matches_oracle(setup):
     nhq.nhq_mlp_load(ix, _dev(flat))
     wh = flat.astype(np.float16).astype(np.float64)
     for tau in (0.3, 0.6):
-        ids, dist, cnt = nhq.nhq_hybrid_search(ix, _dev(w.q), _dev(w.qattrs), 10, 128, learned=True,
-                                               stop_threshold=tau, check_every=4, counters=True)
-        o = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, 128, entry, key_mode=oracle.KEY32,
-                          check_every=4, mlp=wh, stop_threshold=tau)
-        same = (ids.cpu().numpy() == o[0]).all(axis=1) & (cnt.cpu().numpy()[:, 1] == o[3])
-        # a decision can flip only where the logit sits within rounding of the threshold
-        assert same.mean() >= 0.97, same.mean()
+        _check_learned(ix, w, adj, entry, wh, 1, tau, 0.0, 4)
     # the hop budget (checked before every step) and the one-checkpoint mode
     for mode, tau, cf, ce in ((1, 0.6, 1.5, 4), (2, 0.6, 2.0, 8), (2, 0.99, 1.0, 4)):
-        ids, dist, cnt = nhq.nhq_hybrid_search(ix, _dev(w.q), _dev(w.qattrs), 10, 128, learned=mode,
-                                               stop_threshold=tau, check_every=ce, cap_factor=cf,
-                                               counters=True)
-        o = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, 128, entry, key_mode=oracle.KEY32,
-                          check_every=ce, mlp=wh, stop_threshold=tau, cap_factor=cf, learned_mode=mode)
-        same = (ids.cpu().numpy() == o[0]).all(axis=1) & (cnt.cpu().numpy()[:, 1] == o[3])
-        assert same.mean() >= 0.97, (mode, same.mean())
+        _check_learned(ix, w, adj, entry, wh, mode, tau, cf, ce)
     nhq.nhq_mlp_load(ix, None)
     with pytest.raises(nhq.NHQError):
         nhq.nhq_hybrid_search(ix, _dev(w.q), _dev(w.qattrs), 10, 64, learned=True)
