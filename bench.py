@@ -269,7 +269,7 @@ def headline(args):
         run = h.run_form(index, op["beam"], args.steps, args.warmup, **kw)
         at = qps_at_recall([p["beam"] for p in pts], [p["recall"] for p in pts], [p["qps"] for p in pts], target)
         forms[name] = {**run, "beam": op["beam"], "recall": op["recall"], "ndc": op["ndc"], "hops": op["hops"],
-                       "qps_at_target_interp": at, "rerank": kw.get("rerank", 0),
+                       "returned": op["returned"], "qps_at_target_interp": at, "rerank": kw.get("rerank", 0),
                        "bytes_per_query": _bytes_per_query(w, elem, op, op["returned"] if elem == 2 else 0.0),
                        "sweep": [{kk: vv for kk, vv in p.items()} for p in pts]}
         log("%s: beam %d recall %.4f: %.3f ms/step, %.0f QPS (interpolated at %.2f: %s)" % (
@@ -281,7 +281,7 @@ def headline(args):
         run = h.run_form(ixb, best["beam"], args.steps, args.warmup, **op["kw"])
         forms["bf16_learned"] = {
             **run, "beam": best["beam"], "recall": op["recall"], "ndc": op["ndc"], "hops": op["hops"],
-            "hops_p99": op["hops_p99"], "learned_mode": 2, "check_every": ce, "cap_factor": op["cap_factor"],
+            "returned": op["returned"], "hops_p99": op["hops_p99"], "learned_mode": 2, "check_every": ce, "cap_factor": op["cap_factor"],
             "rerank": rr, "qps_at_target_interp": best["qps_at_target_interp"],
             "train_samples": best["train_samples"], "train_s": best["train_s"],
             "bytes_per_query": _bytes_per_query(w, 2, op, op["returned"]),
@@ -324,6 +324,11 @@ def headline(args):
             "kernel_avg_ms": round(vf["search_kernel_avg_ms"], 4),
             "rank_kernels_avg_ms": round(vf["rank_kernels_avg_ms"], 4),
             "whole_step_frac": round(step_bytes / (vf["ms_per_step"] / 1000.0) / 1e9 / HBM_PEAK_GBS, 5)}
+    from paper_2203_13601_amd.metrics import search_extra_bytes_per_query
+    roof["extra_bytes_per_query"] = {k2: round(v2, 1) for k2, v2 in search_extra_bytes_per_query(
+        d_pad=960, elem_bytes=2, n_cand=h.n_cand, out_rows=k, rerank=True).items()}
+    roof["extra_bytes_per_query"]["rerank_rows_beyond_returned_max"] = round(
+        (min(rr * k, vf["beam"]) - vf.get("returned", k)) * 4.0 * w.d, 1)
     waves, rounds = 65536, 20
     nhq.nhq_gather_probe(ixb, waves, rounds)
     pe = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
@@ -347,6 +352,22 @@ def headline(args):
         del src, dst
         log("copy calibration: 3 copies of 1 GiB")
 
+    # ---- the seed set of Alg. 2 drawn at random (Sec. 3.2: n_init random
+    # vertices, no ranking) against the ranked entry sample, fp32, same graph
+    seed_policy = None
+    if not args.no_seed_study:
+        ixr = nhq.nhq_index_create(x, a, n_entry=args.n_init, seed=w.build_seed, degree=w.degree)
+        nhq.nhq_index_set_graph(ixr, adj)
+        hr = Harness(w, argparse.Namespace(**{**vars(args), "n_entry": args.n_init}), dev)
+        hr.gt = h.gt
+        rs = _sweep(hr, ixr, "fp32 random seeds", beams, target)
+        seed_policy = {"random_seeds": {"n_init": args.n_init, "sweep": rs,
+                                        "qps_at_target_interp": qps_at_recall(
+                                            [p["beam"] for p in rs], [p["recall"] for p in rs],
+                                            [p["qps"] for p in rs], target)},
+                       "ranked_entry_sample": {"n_entry": args.n_entry,
+                                               "qps_at_target_interp": forms["fp32_fixed"]["qps_at_target_interp"]}}
+        ixr.free()
     # ---- 5. where selectivity varies: the serving stream's constraint law
     # (1 to 4 of the 4 attributes constrained) on the same query vectors; the
     # fixed beam against the learned budget at one large beam
@@ -391,6 +412,7 @@ def headline(args):
         "p99_ms": None if serving is None else serving["p99_ms"],
         "forms": _r({kk: {k2: v2 for k2, v2 in f.items()} for kk, f in forms.items()}),
         "mixed_selectivity": mixed,
+        "seed_policy": _r(seed_policy),
         "serving": serving,
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -821,6 +843,7 @@ def main():
     ap.add_argument("--serve-recall-sample", type=int, default=10_000)
     ap.add_argument("--serve-beam", type=int, default=256)
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-seed-study", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cpu-bf-queries", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")

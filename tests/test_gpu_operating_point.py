@@ -60,3 +60,49 @@ def test_bench_launch_matches_oracle(plain, storage, beam):
     assert np.allclose(dist[fin], og[fin], rtol=1e-4)
     assert not oflag.any() and nhq.nhq_index_device_error(ix) == 0
     ix.free()
+
+
+# ---- the headline launch at full size: 1,000,000 x 960 Gaussian mixture,
+# 4 attributes (2/3/5/10) all constrained, entry sample 1,024, 4 seeds, 2
+# expansions per step, beam 20; float32 rows and bf16 rows with the float32
+# re-score.  The graph is a seeded random degree-32 graph (the oracle cannot
+# build the composite index at this size); float data, so the answers must
+# overlap at >= 0.99 with Recall@10 within 0.005 and FP64-exact distances,
+# on a sample of the batch the launch answers.
+@pytest.fixture(scope="module")
+def headline():
+    w = synth.config3(n=1_000_000, nq=10_000)
+    adj = synth.random_graph(w.n, 32, seed=21)
+    return w, adj
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+def test_headline_launch_full_size(headline, storage):
+    from parity import assert_float_parity
+    w, adj = headline
+    ix = nhq.nhq_index_create(_dev(w.x), _dev(w.attrs), storage=storage, n_entry=1024, seed=w.build_seed,
+                              degree=32)
+    nhq.nhq_index_set_graph(ix, _dev(adj))
+    rr = 4 if storage == "bf16" else 0
+    q, qa = _dev(w.q), _dev(w.qattrs)
+    cand = nhq.nhq_seed_rank(ix, q, qa, 4 + SEED_MARGIN)
+    ids, dist = nhq.nhq_search_seeded(ix, q, qa, cand, K, 20, n_init=4, expand=2, rerank=rr)
+    torch.cuda.synchronize()
+    sel = np.arange(0, w.nq, 40)                       # 250 of the 10,000 answers
+    ids, dist = ids.cpu().numpy()[sel], dist.cpu().numpy()[sel]
+    xs = w.x if storage == "fp32" else oracle.from_bf16_bits(oracle.to_bf16_bits(w.x)).astype(np.float32)
+    entry = oracle.entry_points(w.build_seed, w.n, 1024)
+    oi, og, _, _, _ = oracle.search(adj, xs, w.attrs, w.q[sel], w.qattrs[sel], K, 20, entry, n_init=4,
+                                    expand=2, rerank_n=min(4 * K, 20) if rr else 0, xr=w.x if rr else None)
+    assert_float_parity(ids, oi, w.x, w.attrs, w.q[sel], w.qattrs[sel])
+    # every returned distance is the FP64 Gamma of the returned object (all
+    # four attributes constrained and matched: Gamma = delta)
+    for i, qi in enumerate(sel):
+        for v, g in zip(ids[i], dist[i]):
+            if v < 0:
+                assert np.isinf(g)
+                continue
+            assert oracle.chi(w.qattrs[qi], w.attrs[v]) == 0
+            want = oracle.delta(w.q[qi], w.x[v])
+            assert abs(g - want) <= 1e-4 * want, (qi, v, g, want)
+    ix.free()
