@@ -82,9 +82,10 @@ def _profiled_traffic(kernel: str, source: str, tag: str):
     return None
 
 
-def _r(v, n=5):
+def _r(v, n=6):
+    """floats to n significant digits (nested)"""
     if isinstance(v, float):
-        return round(v, n)
+        return float("%.*g" % (n, v))
     if isinstance(v, dict):
         return {k: _r(x, n) for k, x in v.items()}
     if isinstance(v, list):
@@ -183,6 +184,44 @@ def _sweep(h, index, label, beams, target, **kw):
     return pts
 
 
+def _form_errors(h, w, index, beam, storage, **kw):
+    """Per returned result of the form's step: |Gamma - Gamma FP64| / Gamma FP64
+    (every distance recomputed from the vectors); for bf16 / fp8 also the
+    error of Gamma computed from the decoded stored row of each returned
+    object (the approximation the loop orders by before the float32
+    re-score), over the first 1,000 queries."""
+    import paper_2203_13601_amd as nhq
+    from paper_2203_13601_amd.metrics import gamma_rel_error
+    h.step(index, beam, **kw)
+    h.torch.cuda.synchronize()
+    ids, dists = h.ids.cpu().numpy(), h.dists.cpu().numpy()
+    e = gamma_rel_error(ids, dists, w.x, w.q, w.attrs, w.qattrs)
+    out = {"results": int(e.size), "max": float(e.max()), "p99": float(np.percentile(e, 99)),
+           "mean": float(e.mean())}
+    if storage in ("bf16", "fp8"):
+        ns = min(1000, h.nq)
+        rows, scales = nhq.nhq_index_get_storage(index)
+        sel = h.torch.from_numpy(ids[:ns].clip(min=0).astype(np.int64)).to(rows.device).reshape(-1)
+        r_np = rows[sel].cpu().numpy()
+        if storage == "bf16":
+            dec = (r_np.view(np.uint16).astype(np.uint32) << 16).view(np.float32)
+        else:
+            c = r_np.astype(np.int64)
+            sgn = np.where(c >> 7, -1.0, 1.0)
+            ex, mn = (c >> 3) & 15, c & 7
+            val = np.where(ex == 0, mn / 8.0 * 2.0 ** -6, (1.0 + mn / 8.0) * 2.0 ** (ex - 7.0))
+            dec = sgn * val * scales[sel].cpu().numpy().astype(np.float64)[:, None]
+        dec = dec.reshape(ns, ids.shape[1], -1)[:, :, :w.d].astype(np.float64)
+        dl_dec = np.sqrt(((dec - w.q[:ns, None, :].astype(np.float64)) ** 2).sum(-1))
+        from paper_2203_13601_amd.metrics import true_delta
+        dl = true_delta(ids[:ns], w.x, w.q[:ns])
+        ok = ids[:ns] >= 0
+        es = np.abs(dl_dec - dl)[ok] / np.maximum(dl[ok], 1e-30)  # every returned object matches: Gamma = delta
+        out["stored_form"] = {"results": int(es.size), "max": float(es.max()), "mean": float(es.mean())}
+        del rows, scales
+    return out
+
+
 def _first_at(pts, target):
     ok = [p for p in pts if p["recall"] >= target]
     return ok[0] if ok else None
@@ -228,9 +267,12 @@ def headline(args):
     target, k, rr = args.target, w.k, 4
     beams = [10, 12, 14, 16, 18, 20, 24, 28, 32, 40, 48, 64, 96, 128]
 
-    # ---- 1 and 2: fixed-beam sweeps (fp32; bf16 + float32 re-score)
+    # ---- 1 and 2: fixed-beam sweeps (fp32; bf16 and fp8 e4m3 + float32 re-score)
     s32 = _sweep(h, ix, "fp32", beams, target)
     s16 = _sweep(h, ixb, "bf16", beams, target, rerank=rr)
+    ix8 = nhq.nhq_index_create(x, a, storage="fp8", n_entry=args.n_entry, seed=w.build_seed, degree=w.degree)
+    nhq.nhq_index_set_graph(ix8, adj)
+    s8 = _sweep(h, ix8, "fp8", beams, target, rerank=rr)
     # ---- 3: bf16 + learned stop, per training beam a sweep of the budget factor
     ce = args.check_every
     learned_runs = []
@@ -263,22 +305,26 @@ def headline(args):
 
     # ---- timed steps at each form's first setting reaching the target
     forms = {}
-    for name, index, pts, elem in (("fp32_fixed", ix, s32, 4), ("bf16_fixed", ixb, s16, 2)):
+    for name, index, pts, elem in (("fp32_fixed", ix, s32, 4), ("bf16_fixed", ixb, s16, 2),
+                                   ("fp8_fixed", ix8, s8, 1)):
         op = _first_at(pts, target) or pts[-1]
-        kw = {"rerank": rr} if name == "bf16_fixed" else {}
+        kw = {"rerank": rr} if name != "fp32_fixed" else {}
         run = h.run_form(index, op["beam"], args.steps, args.warmup, **kw)
+        run["gamma_rel_err_vs_fp64"] = _form_errors(h, w, index, op["beam"], name.split("_")[0], **kw)
         at = qps_at_recall([p["beam"] for p in pts], [p["recall"] for p in pts], [p["qps"] for p in pts], target)
         forms[name] = {**run, "beam": op["beam"], "recall": op["recall"], "ndc": op["ndc"], "hops": op["hops"],
                        "returned": op["returned"], "qps_at_target_interp": at, "rerank": kw.get("rerank", 0),
-                       "bytes_per_query": _bytes_per_query(w, elem, op, op["returned"] if elem == 2 else 0.0),
+                       "bytes_per_query": _bytes_per_query(w, elem, op, op["returned"] if elem != 4 else 0.0),
                        "sweep": [{kk: vv for kk, vv in p.items()} for p in pts]}
         log("%s: beam %d recall %.4f: %.3f ms/step, %.0f QPS (interpolated at %.2f: %s)" % (
             name, op["beam"], op["recall"], run["ms_per_step"], run["qps"], target, at))
+    ix8.free()
     value_form = "bf16_fixed"
     if best is not None:
         nhq.nhq_mlp_load(ixb, best["params"])
         op = _first_at(best["sweep"], target)
         run = h.run_form(ixb, best["beam"], args.steps, args.warmup, **op["kw"])
+        run["gamma_rel_err_vs_fp64"] = _form_errors(h, w, ixb, best["beam"], "bf16", **op["kw"])
         forms["bf16_learned"] = {
             **run, "beam": best["beam"], "recall": op["recall"], "ndc": op["ndc"], "hops": op["hops"],
             "returned": op["returned"], "hops_p99": op["hops_p99"], "learned_mode": 2, "check_every": ce, "cap_factor": op["cap_factor"],
@@ -293,7 +339,7 @@ def headline(args):
         log("bf16+learned: beam %d cap %.2f recall %.4f: %.3f ms/step, %.0f QPS" % (
             best["beam"], op["cap_factor"], op["recall"], run["ms_per_step"], run["qps"]))
     vf = forms[value_form]
-    for name in ("bf16_fixed", "bf16_learned"):
+    for name in ("bf16_fixed", "fp8_fixed", "bf16_learned"):
         if name in forms:
             f = forms[name]
             f["speedup_vs_fp32_fixed"] = f["qps"] / forms["fp32_fixed"]["qps"]
