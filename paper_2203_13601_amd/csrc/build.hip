@@ -116,7 +116,7 @@ int nhq_bruteforce_hybrid_knn(const nhq_index *h, const float *queries, const ui
     NHQ_HIP(hipMallocAsync((void **)&qm, sizeof(uint32_t) * (size_t)nq, st));
     NHQ_HIP(hipMallocAsync((void **)&cand, sizeof(int32_t) * (size_t)nq * K, st));
     int rc = launch_pad_queries(queries, qattrs, nq, ix->d, ix->dp, ix->m, ix->abits, qpad, qnorm, qw, qm,
-                                nullptr, st);
+                                nullptr, nullptr, st);
     if (rc == NHQ_OK)
         rc = launch_dense_topk(qpad, qnorm, qw, qm, nq, ix->vec32, ix->norm, ix->attr, ix->n, ix->dp,
                                ix->m, ix->abits, 1, 0, K, cand, nullptr, st);

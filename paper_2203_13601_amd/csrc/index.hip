@@ -99,13 +99,41 @@ __global__ void k_row_norm(const float *__restrict__ v, float *__restrict__ norm
     }
 }
 
-// float32 -> bfloat16, round to nearest even (finite inputs)
+// float32 -> bfloat16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ uint32_t bf16_rne(float v)
+{
+    const uint32_t u = __float_as_uint(v);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
 __global__ void k_to_bf16(const float *__restrict__ v, uint16_t *__restrict__ out, int64_t total)
 {
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x)
+        out[t] = (uint16_t)bf16_rne(v[t]);
+}
+
+// The split of one value for the bf16 matrix cores: hi = bf16(v), lo =
+// bf16(v - hi) (v - hi is exact in float32), so hi + lo equals v to within
+// 2^-17 |v|, and hi * hi' + hi * lo' + lo * hi' equals v v' to within about
+// 3 * 2^-17 |v v'|; values exact in bf16 have lo = 0.  Element c of a row
+// goes to chunk c / 32: hi at 64 (c / 32) + c % 32, lo 32 further on.
+__device__ __forceinline__ void put_split(uint16_t *row, int c, float v)
+{
+    const uint32_t hi = bf16_rne(v);
+    const uint32_t lo = bf16_rne(v - __uint_as_float(hi << 16));
+    const int at = 64 * (c >> 5) + (c & 31);
+    row[at] = (uint16_t)hi;
+    row[at + 32] = (uint16_t)lo;
+}
+
+__global__ void k_split_rows(const float *__restrict__ src, int64_t rows, int dp, uint16_t *__restrict__ dst)
+{
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < rows * dp;
          t += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t u = __float_as_uint(v[t]);
-        out[t] = (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+        const int64_t r = t / dp;
+        const int c = (int)(t - r * dp);
+        put_split(dst + r * 2 * dp, c, src[t]);
     }
 }
 
@@ -165,15 +193,16 @@ __device__ __forceinline__ float row_mov(float v)
 }
 
 // 16 lanes per query (4 queries per wave): zero-padded float32 row,
-// squared norm, packed codes and constraint mask, and whether every value
-// is an integer of magnitude <= 256
+// squared norm, packed codes and constraint mask, whether every value is an
+// integer of magnitude <= 256, and (qsplit non-null) the row's hi/lo split
 __global__ __launch_bounds__(64) void k_pad_queries(const float *__restrict__ q,
                                                     const uint8_t *__restrict__ qa, int64_t nq, int d,
                                                     int dp, int m, int abits, float *__restrict__ qpad,
                                                     float *__restrict__ qnorm,
                                                     uint32_t *__restrict__ qword,
                                                     uint32_t *__restrict__ qmask,
-                                                    uint32_t *__restrict__ qexact)
+                                                    uint32_t *__restrict__ qexact,
+                                                    uint16_t *__restrict__ qsplit)
 {
     const int lane = threadIdx.x, sub = lane & 15, grp = lane >> 4;
     const uint32_t fm = (abits >= 32) ? 0xFFFFFFFFu : ((1u << abits) - 1u);
@@ -199,6 +228,8 @@ __global__ __launch_bounds__(64) void k_pad_queries(const float *__restrict__ q,
                     const int c = c0 + 16 * u + sub;
                     if (c < dp) {
                         qpad[i * dp + c] = v[u];
+                        if (qsplit)
+                            put_split(qsplit + i * 2 * dp, c, v[u]);
                         s = fmaf(v[u], v[u], s);
                         exact = exact && v[u] == rintf(v[u]) && fabsf(v[u]) <= 256.0f;
                     }
@@ -313,8 +344,8 @@ void free_index(Index *ix)
     if (ix->vecs && ix->vecs != ix->vec32)
         (void)hipFree(ix->vecs);
     void *ptrs[] = {ix->vec32, ix->scale, ix->attr, ix->norm, ix->adj, ix->entry, ix->entry_vec,
-                    ix->entry_norm, ix->entry_attr, ix->entry_bf16, ix->err, ix->ws, ix->mlp, ix->logp,
-                    ix->block_word, ix->block_off};
+                    ix->entry_norm, ix->entry_attr, ix->entry_bf16, ix->entry_split, ix->err, ix->ws, ix->mlp,
+                    ix->logp, ix->block_word, ix->block_off};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -322,12 +353,21 @@ void free_index(Index *ix)
 
 int launch_pad_queries(const float *q, const uint8_t *qa, int64_t nq, int d, int dp, int m,
                        int abits, float *qpad, float *qnorm, uint32_t *qword, uint32_t *qmask,
-                       uint32_t *qexact, hipStream_t st)
+                       uint32_t *qexact, uint16_t *qsplit, hipStream_t st)
 {
     if (nq == 0)
         return NHQ_OK;
     hipLaunchKernelGGL(k_pad_queries, dim3(grid_for(nq, 4)), dim3(64), 0, st, q, qa, nq, d, dp, m,
-                       abits, qpad, qnorm, qword, qmask, qexact);
+                       abits, qpad, qnorm, qword, qmask, qexact, qsplit);
+    NHQ_HIP(hipGetLastError());
+    return NHQ_OK;
+}
+
+int launch_split_rows(const float *src, int64_t rows, int dp, uint16_t *dst, hipStream_t st)
+{
+    if (rows == 0)
+        return NHQ_OK;
+    hipLaunchKernelGGL(k_split_rows, dim3(grid_for(rows * dp, 256)), dim3(256), 0, st, src, rows, dp, dst);
     NHQ_HIP(hipGetLastError());
     return NHQ_OK;
 }
@@ -609,6 +649,12 @@ int nhq_index_create(const float *vecs, const uint8_t *attrs, int64_t n, int32_t
         hipLaunchKernelGGL(k_gather_entry, dim3(grid_for(ne_all * ix->dp, 256)), dim3(256), 0, st, ix->entry,
                            (int)ne_all, ix->vec32, ix->norm, ix->attr, ix->dp, ix->entry_vec,
                            ix->entry_norm, ix->entry_attr);
+        if (hipMalloc(&ix->entry_split, (size_t)ne_all * ix->dp * 2 * sizeof(uint16_t)) != hipSuccess) {
+            rc = fail(NHQ_ENOMEM, "entry sample allocation failed");
+            break;
+        }
+        if ((rc = launch_split_rows(ix->entry_vec, ne_all, ix->dp, ix->entry_split, st)) != NHQ_OK)
+            break;
         if (hipMalloc(&ix->logp, sizeof(float) * hh.size()) != hipSuccess) {
             rc = fail(NHQ_ENOMEM, "histogram allocation failed");
             break;
@@ -841,13 +887,14 @@ void nhq_index_free(nhq_index *h)
 namespace {
 
 // 32-bit words of the seed ranking's scratch: padded rows, norms, codes,
-// masks, exactness flags and (for the matrix-core ranking) the key matrix and
-// its group minima
+// masks, exactness flags, split rows (each 2 dp bf16 halves, 256-byte
+// aligned) and (for the matrix-core ranking) the key matrix and its group
+// minima
 size_t seed_rank_words(const Index *ix, int64_t nq, int K)
 {
     const size_t ne_pad = (size_t)(ix->n_entry + 63) / 64 * 64;
     const bool dense = ix->n_entry <= 8192;
-    const size_t pad = (size_t)nq * ix->dp + 5 * (size_t)nq + 64;
+    const size_t pad = 2 * (size_t)nq * ix->dp + 5 * (size_t)nq + 128;
     if (ix->n_blocks > 0)
         return pad + strata_rank_words(ix, nq, K);
     return pad + (dense ? (size_t)nq * ne_pad / 16 * 17 : 0);
@@ -876,14 +923,19 @@ int seed_rank_at(const Index *cix, const float *queries, const uint8_t *qattrs, 
     uint32_t *qw = reinterpret_cast<uint32_t *>(qnorm + f_small);
     uint32_t *qm = qw + f_small;
     uint32_t *qx = qm + f_small;
-    float *keys = reinterpret_cast<float *>((reinterpret_cast<uintptr_t>(qx + f_small) + 255) & ~uintptr_t(255));
-    int rc = launch_pad_queries(queries, qattrs, nq, ix->d, ix->dp, ix->m, ix->abits, qpad, qnorm, qw, qm, qx, st);
+    uint16_t *qs =
+        reinterpret_cast<uint16_t *>((reinterpret_cast<uintptr_t>(qx + f_small) + 255) & ~uintptr_t(255));
+    float *keys = reinterpret_cast<float *>(
+        (reinterpret_cast<uintptr_t>(qs + 2 * f_rows) + 255) & ~uintptr_t(255));
+    // split rows only where the matrix-core ranking reads them
+    int rc = launch_pad_queries(queries, qattrs, nq, ix->d, ix->dp, ix->m, ix->abits, qpad, qnorm, qw, qm, qx,
+                                (ix->n_blocks > 0 || dense) ? qs : nullptr, st);
     if (rc == NHQ_OK) {
         if (ix->n_blocks > 0)
-            rc = launch_strata_rank(ix, qpad, qnorm, qw, qm, nq, n_cand, reinterpret_cast<uint32_t *>(keys),
+            rc = launch_strata_rank(ix, qs, qnorm, qw, qm, nq, n_cand, reinterpret_cast<uint32_t *>(keys),
                                     cand, st);
         else if (dense)
-            rc = launch_seed_rank(ix, qpad, qnorm, qw, qm, qx, nq, n_cand, keys, cand, st);
+            rc = launch_seed_rank(ix, qpad, qs, qnorm, qw, qm, qx, nq, n_cand, keys, cand, st);
         else
             rc = launch_dense_topk(qpad, qnorm, qw, qm, nq, ix->entry_vec, ix->entry_norm, ix->entry_attr,
                                    ix->n_entry, ix->dp, ix->m, ix->abits, 0, 0, n_cand, cand, nullptr, st,

@@ -77,6 +77,10 @@ struct Index {
     // <= 256 and dp <= 128: then bf16 products summed in float32 are exact,
     // and the ranking uses the bf16 matrix-core instructions (else null)
     uint16_t *entry_bf16 = nullptr;
+    // entry_vec split for the bf16 matrix cores: every float32 value v as
+    // hi = bf16(v) and lo = bf16(v - hi); row r holds, per 32-element chunk
+    // c, the 32 hi halves then the 32 lo halves ([n_entry_total][2 dp])
+    uint16_t *entry_split = nullptr;
     // stratified entry sample (entry_per_pattern > 0): after the n_entry
     // global members, one block per attribute pattern the objects hold, in
     // increasing packed-word order; block b holds entry positions
@@ -160,25 +164,32 @@ int launch_dense_topk(const float *A, const float *A_norm, const uint32_t *A_att
 
 // seed ranking of a stratified entry sample (see seed.hip): each query
 // ranked against its pattern's block, or the global members; scratch of
-// strata_rank_words(ix, nq, K) 32-bit words at blk
+// strata_rank_words(ix, nq, K) 32-bit words at blk; qsplit: the query rows
+// split like Index::entry_split
 size_t strata_rank_words(const Index *ix, int64_t nq, int K);
-int launch_strata_rank(const Index *ix, const float *qpad, const float *qnorm, const uint32_t *qword,
+int launch_strata_rank(const Index *ix, const uint16_t *qsplit, const float *qnorm, const uint32_t *qword,
                        const uint32_t *qmask, int64_t nq, int K, uint32_t *blk, int32_t *cand,
                        hipStream_t st);
 
 // seed ranking of the entry sample (see seed.hip): positions of the K best
 // keys: scratch of nq * ((n_entry + 63) / 64 * 64) * 17 / 16 floats (the key
 // matrix, then its 16-entry group minima); qexact (nullable):
-// per query, nonzero when every value is an integer of magnitude <= 256
-int launch_seed_rank(const Index *ix, const float *qpad, const float *qnorm, const uint32_t *qword,
-                     const uint32_t *qmask, const uint32_t *qexact, int64_t nq, int K, float *keys,
-                     int32_t *cand, hipStream_t st);
+// per query, nonzero when every value is an integer of magnitude <= 256;
+// qsplit: the query rows split like Index::entry_split
+int launch_seed_rank(const Index *ix, const float *qpad, const uint16_t *qsplit, const float *qnorm,
+                     const uint32_t *qword, const uint32_t *qmask, const uint32_t *qexact, int64_t nq, int K,
+                     float *keys, int32_t *cand, hipStream_t st);
 
 // queries -> zero-padded float32 rows, squared norms, packed codes and masks,
-// and (qexact nullable) whether every value is an integer of magnitude <= 256
+// (qexact nullable) whether every value is an integer of magnitude <= 256,
+// and (qsplit nullable) the rows split like Index::entry_split
 int launch_pad_queries(const float *q, const uint8_t *qa, int64_t nq, int d, int dp, int m,
                        int abits, float *qpad, float *qnorm, uint32_t *qword, uint32_t *qmask, uint32_t *qexact,
-                       hipStream_t st);
+                       uint16_t *qsplit, hipStream_t st);
+
+// float32 rows [rows][dp] -> their hi/lo bf16 split [rows][2 dp] (the layout
+// of Index::entry_split)
+int launch_split_rows(const float *src, int64_t rows, int dp, uint16_t *dst, hipStream_t st);
 
 }  // namespace nhq
 

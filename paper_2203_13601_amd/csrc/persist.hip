@@ -322,6 +322,18 @@ int nhq_index_load(const char *path, void *stream, nhq_index **out)
         if ((rc = read_dev(f, (void **)&ix->entry_vec, sizeof(float) * ne * dp, sizeof(float) * ne * dp, buf)) !=
             NHQ_OK)
             break;
+        // the matrix-core split of the entry rows is derived, not stored
+        if (hipMalloc(&ix->entry_split, sizeof(uint16_t) * 2 * ne * dp) != hipSuccess) {
+            rc = fail(NHQ_ENOMEM, "entry sample allocation failed");
+            break;
+        }
+        if ((rc = launch_split_rows(ix->entry_vec, (int64_t)ne, (int)dp, ix->entry_split, (hipStream_t)stream)) !=
+            NHQ_OK)
+            break;
+        if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) {
+            rc = fail(NHQ_EHIP, "entry split failed");
+            break;
+        }
         if ((rc = read_dev(f, (void **)&ix->entry_norm, sizeof(float) * ne, sizeof(float) * ne, buf)) != NHQ_OK)
             break;
         if ((rc = read_dev(f, (void **)&ix->entry_attr, sizeof(uint32_t) * ne, sizeof(uint32_t) * ne, buf)) !=

@@ -26,11 +26,12 @@ __global__ __launch_bounds__(256) void k_gather_probe(const void *__restrict__ v
     const int g = lane % S::G, gi = lane / S::G;
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     float acc = 0.0f;
-    for (int r0 = 0; r0 < rounds; r0 += S::RB) {
-        T buf[S::RB][S::NCH];
-        float sc[S::RB];
+    constexpr int RB = Lay<DP, ST>::RB;
+    for (int r0 = 0; r0 < rounds; r0 += RB) {
+        T buf[RB][S::NCH];
+        float sc[RB];
 #pragma unroll
-        for (int rr = 0; rr < S::RB; ++rr) {
+        for (int rr = 0; rr < RB; ++rr) {
             const uint64_t j = (wave * (uint64_t)rounds + (uint64_t)(r0 + rr)) * S::NG + gi;
             const int64_t id = (int64_t)(mix64(seed + 0x9E3779B97F4A7C15ull * (j + 1)) % (uint64_t)n);
             const T *row = reinterpret_cast<const T *>(vbase) + id * (DP / 4);
@@ -40,7 +41,7 @@ __global__ __launch_bounds__(256) void k_gather_probe(const void *__restrict__ v
             sc[rr] = ST == NHQ_STORAGE_FP8 ? scale[id] : 1.0f;
         }
 #pragma unroll
-        for (int rr = 0; rr < S::RB; ++rr)
+        for (int rr = 0; rr < RB; ++rr)
 #pragma unroll
             for (int c = 0; c < S::NCH; ++c) {
                 const float4 x = decode<ST>(buf[rr][c], sc[rr]);
@@ -91,7 +92,9 @@ extern "C" int nhq_gather_probe(const nhq_index *h, int64_t waves, int32_t round
     switch (ix->dp) {
 #define NHQ_P(DPV)                                                       \
     case DPV:                                                            \
-        rb = Shape<DPV>::RB;                                             \
+        rb = ix->storage == NHQ_STORAGE_FP32 ? Lay<DPV, NHQ_STORAGE_FP32>::RB \
+             : ix->storage == NHQ_STORAGE_BF16 ? Lay<DPV, NHQ_STORAGE_BF16>::RB \
+                                               : Lay<DPV, NHQ_STORAGE_FP8>::RB; \
         ng = Shape<DPV>::NG;                                             \
         if (rounds % rb != 0)                                            \
             return fail(NHQ_EINVAL, "rounds must be a multiple of the rounds in flight"); \

@@ -91,6 +91,13 @@ struct Lay {
                               : NCH % 3 == 0       ? 3
                               : NCH % 2 == 0       ? 2
                                                    : 1;
+    // rounds of rows in flight per wave: two when a lane's share of a round
+    // is at most 120 bytes (wide bf16 / fp8 rows fit the float32 row's
+    // register budget with two rounds), else the width's default.  The
+    // checkpointed search keeps the width's default: the stop network's
+    // registers plus a second round would cost it a wave per SIMD.
+    static constexpr int CHB = ST == NHQ_STORAGE_FP32 ? 16 : ST == NHQ_STORAGE_BF16 ? 8 : 4;
+    static constexpr int RB = Shape<DP>::RB > 1 ? Shape<DP>::RB : (NCH * CHB <= 120 ? 2 : 1);
 };
 
 template <int DP, int K4>
@@ -174,8 +181,9 @@ __device__ __forceinline__ float group_sum(float v)
 // row (storage ST), written to out[j] as the ordering key or as delta^2.
 // mode 0: key, chi taken from the staged word; mode 1: key, chi computed
 // from the attribute word (fetched together with the row) and written into
-// the staged word; mode 2: delta^2.
-template <int DP, int ST, int K4 = Lay<DP, ST>::K4>
+// the staged word; mode 2: delta^2.  RB rounds of rows are loaded before
+// any of them is scored.
+template <int DP, int ST, int K4 = Lay<DP, ST>::K4, int RB = Lay<DP, ST>::RB>
 __device__ __forceinline__ void score_batch(const void *vbase, const float *scale,
                                             const float4 (&qv)[Shape<DP>::NCH],
                                             uint32_t *sid, float *out, int nf, int mq,
@@ -189,12 +197,12 @@ __device__ __forceinline__ void score_batch(const void *vbase, const float *scal
     const int lane = threadIdx.x & 63;
     const int g = lane % S::G, gi = lane / S::G;
     const int rounds = (nf + S::NG - 1) / S::NG;
-    for (int r0 = 0; r0 < rounds; r0 += S::RB) {
-        T buf[S::RB][S::NCH];
-        float sc[S::RB];
-        uint32_t w[S::RB], aw[S::RB];
+    for (int r0 = 0; r0 < rounds; r0 += RB) {
+        T buf[RB][S::NCH];
+        float sc[RB];
+        uint32_t w[RB], aw[RB];
 #pragma unroll
-        for (int rr = 0; rr < S::RB; ++rr) {
+        for (int rr = 0; rr < RB; ++rr) {
             const int j = (r0 + rr) * S::NG + gi;
             w[rr] = 0;
             aw[rr] = 0;
@@ -213,7 +221,7 @@ __device__ __forceinline__ void score_batch(const void *vbase, const float *scal
             }
         }
 #pragma unroll
-        for (int rr = 0; rr < S::RB; ++rr) {
+        for (int rr = 0; rr < RB; ++rr) {
             const int j = (r0 + rr) * S::NG + gi;
             float a0 = 0.0f, a1 = 0.0f;
             if (j < nf) {
@@ -479,6 +487,7 @@ template <int DP, int ST, bool CK>
 __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *smem)
 {
     using S = Shape<DP>;
+    constexpr int RBS = CK ? S::RB : Lay<DP, ST>::RB;
     const int lane = threadIdx.x & 63;
     const int L = a.L;
     float *pkey = reinterpret_cast<float *>(smem);
@@ -539,7 +548,8 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
         if (ok)
             sid[lanes_below(vb)] = (uint32_t)v;
         wsync();
-        score_batch<DP, ST>(a.vecs, a.scale, qv, sid, skey, ne, mq, 1, a.w, a.attr, qword, qmask, a.hmask);
+        score_batch<DP, ST, Lay<DP, ST>::K4, RBS>(a.vecs, a.scale, qv, sid, skey, ne, mq, 1, a.w, a.attr, qword,
+                                                 qmask, a.hmask);
         wsync();
         if (a.w.mode != NHQ_WEIGHTS_DEFAULT)
             weigh_keys(skey, sid, ne, mq, a.w);
@@ -784,7 +794,8 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
         }
         wsync();
         ndc += nf;
-        score_batch<DP, ST>(a.vecs, a.scale, qv, sid, skey, nf, mq, 1, a.w, a.attr, qword, qmask, a.hmask);
+        score_batch<DP, ST, Lay<DP, ST>::K4, RBS>(a.vecs, a.scale, qv, sid, skey, nf, mq, 1, a.w, a.attr, qword,
+                                                 qmask, a.hmask);
         wsync();
         if (a.w.mode != NHQ_WEIGHTS_DEFAULT)
             weigh_keys(skey, sid, nf, mq, a.w);

@@ -1,16 +1,26 @@
 // Seed ranking: every query against the index's random entry sample (the
 // seed set B of Alg. 2 is drawn from it): a key kernel, then a selection.
 //
-// k_entry_keys (matrix cores): the full key matrix [nq][n_entry_pad] with
+// k_entry_keys_x3 (matrix cores): the full key matrix [nq][n_entry_pad] with
 //   key = delta^2 (m_q + chi)^2 (delta^2 when m_q = 0),
-//   delta^2 = |q|^2 + |e|^2 - 2 q.e   (q.e from v_mfma_f32_16x16x4f32, or
-//   from v_mfma_f32_16x16x32_bf16 in k_entry_keys_b16 where both sides are
-//   exact in bf16),
-// chi over the query's constrained codes; padding columns hold +inf.  A
-// workgroup of 4 waves takes 64 queries (16 per wave) against TL
-// tiles of 64 entries.  Each tile's entry rows, norms and attribute words
-// are staged in LDS with all of the tile's loads in flight at once, and the
-// weight setting is a template argument chosen once per launch.
+//   delta^2 = |q|^2 + |e|^2 - 2 q.e,
+// chi over the query's constrained codes; padding columns hold +inf.  q.e
+// comes from the bf16 matrix cores (v_mfma_f32_16x16x32_bf16) on split
+// rows: every float32 value v as hi = bf16(v) plus lo = bf16(v - hi), and
+// q.e as hi.hi' + hi.lo' + lo.hi' accumulated in float32 -- the split-bf16
+// product of Henry, Tang and Heinecke (ARITH 2019), about 2^-17 relative
+// error per term against 2^-24 for float32.  The ranking only prefilters:
+// the search re-scores its candidates exactly in float32 and keeps the
+// n_init best, and the candidates carry a margin of 8 beyond n_init, so an
+// error of this size changes which entries seed a search only when keys
+// tie to within it.  Values exact in bf16 have lo = 0, and integer rows of
+// at most 128 elements keep every partial sum exact (k_entry_keys_b16 takes
+// those workgroups with one product per chunk).  A workgroup of 4 waves
+// takes 64 queries (16 per wave) against TL tiles of 64 entries; a tile's
+// split entry rows are staged in LDS a pass of 64 (or 32) elements at a
+// time, the next pass's loads in flight during the current pass's
+// products, and the weight setting is a template argument chosen once per
+// launch.
 //
 // The key kernels also write, per query, the minimum of every 16-entry group
 // of keys.  The K-th smallest group minimum bounds the K-th smallest key
@@ -38,6 +48,7 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 
 // 64-entry tiles per key workgroup, TL: 8 where the grid already has enough
@@ -52,10 +63,11 @@ struct GmStride {
 };
 
 struct KeyArgs {
-    const float *qpad;    // [nq][DP]
+    const float *qpad;    // [nq][DP] (read by the exact bf16 kernel only)
+    const uint16_t *qs;   // [nq][2 DP] split query rows (see the top)
     const float *qnorm;   // [nq]
     const uint32_t *qword, *qmask;  // [nq]
-    const float *ev;      // [ne][DP]
+    const uint16_t *es;   // [ne][2 DP] split entry rows
     const float *en;      // [ne]
     const uint32_t *ea;   // [ne]
     const uint16_t *eb;   // [ne][DP] exact bf16 copy of ev, or null
@@ -116,13 +128,21 @@ __device__ __forceinline__ void put_entry_meta(const EntryMeta &m, float *ten, u
     }
 }
 
+// Passes over a split row: KC elements per pass (64, or 32 where 64 does
+// not divide DP: wider passes need more registers than three waves per
+// SIMD leave), NCK 32-element chunks per pass, NP passes; an entry row's
+// pass sits in LDS at a stride of ROW bf16 halves (hi and lo of its NCK
+// chunks, 16 bytes of padding against bank conflicts).  The staged values
+// are native vectors (u32x4): held across the pass loop, HIP's uint4 class
+// is not kept in registers.
 template <int DP>
-struct KShape {
-    // dims staged per pass: the whole row up to 128, else 64 (or 32)
-    static constexpr int KC = DP <= 128 ? DP : (DP % 64 == 0 ? 64 : 32);
-    static constexpr int NK = DP / KC;
-    static constexpr int NT = KC / 16;   // float4 per lane per point per pass
-    static constexpr int LDSW = KC + 4;  // padded row stride (floats): no bank conflicts
+struct XShape {
+    static constexpr int KC = DP % 64 == 0 ? 64 : 32;
+    static constexpr int NCK = KC / 32;
+    static constexpr int NP = DP / KC;
+    static constexpr int ROW = 2 * KC + 8;
+    static constexpr int NV = 64 * (KC / 4) / 256;  // 16-byte staging loads per thread per pass
+    static_assert(DP % KC == 0 && KC % 32 == 0 && NV * 256 == 64 * (KC / 4), "whole passes and loads");
 };
 
 // a lane's value from another lane of its quad (DPP quad_perm)
@@ -207,15 +227,38 @@ __device__ __forceinline__ bool group_exact(const KeyArgs &a, int64_t rowc)
     return __syncthreads_and(a.qx[rowc] != 0u) != 0;
 }
 
-// A workgroup of 4 waves: 64 queries (16 per wave) against 256 entries; the
-// entries' rows are staged through LDS 64 at a time and shared by the waves.
-// Float32 products (v_mfma_f32_16x16x4f32); workgroups whose queries are
-// all exact in bf16 are left to k_entry_keys_b16.
-template <int DP, bool DEF, int TL>
-__global__ __launch_bounds__(256) void k_entry_keys(const KeyArgs a0)
+// One pass's loads: this thread's share of the 64 split entry rows from
+// column c0 (columns past the sample's end repeat its last entry), and the
+// lane's query chunks of the pass (16-byte units of the split row: chunk
+// t's hi halves 8 lq .. 8 lq + 7 at 8 t + lq, its lo halves at 8 t + 4 + lq).
+template <int DP>
+__device__ __forceinline__ void x3_load(const u32x4 *es4, const u32x4 *qrow, int c0, int kc, int ne, int lq,
+                                        u32x4 (&v)[XShape<DP>::NV], u32x4 (&q)[XShape<DP>::NCK][2])
 {
-    using K = KShape<DP>;
-    constexpr int kKeyTiles = TL, kGmStride = GmStride<TL>::v;
+    using X = XShape<DP>;
+#pragma unroll
+    for (int it = 0; it < X::NV; ++it) {
+        const int i = (int)threadIdx.x + 256 * it, r = i / (X::KC / 4), c4 = i - r * (X::KC / 4);
+        const int col = min(c0 + r, ne - 1);
+        v[it] = es4[(int64_t)col * (DP / 4) + kc * (X::KC / 4) + c4];
+    }
+#pragma unroll
+    for (int j = 0; j < X::NCK; ++j) {
+        q[j][0] = qrow[8 * (kc * X::NCK + j) + lq];
+        q[j][1] = qrow[8 * (kc * X::NCK + j) + 4 + lq];
+    }
+}
+
+// A workgroup of 4 waves: 64 queries (16 per wave) against TL tiles of 64
+// entries, split-bf16 products (see the top).  Each pass writes its staged
+// entry rows to LDS, issues the next pass's loads (the next tile's first
+// after a tile's last pass), then runs its products.  Workgroups whose
+// queries are all exact in bf16 are left to k_entry_keys_b16.
+template <int DP, bool DEF, int TL>
+__global__ __launch_bounds__(256) void k_entry_keys_x3(const KeyArgs a0)
+{
+    using X = XShape<DP>;
+    constexpr int kGmStride = GmStride<TL>::v;
     KeyArgs a = a0;
     if (a0.seg) {  // stratified: this workgroup's entry block (uniform per workgroup)
         const int b = a0.seg[blockIdx.x];
@@ -226,99 +269,107 @@ __global__ __launch_bounds__(256) void k_entry_keys(const KeyArgs a0)
             e0 = a0.block_off[b];
             cnt = a0.block_off[b + 1] - e0;
         }
-        a.ev += (int64_t)e0 * DP;
+        a.es += (int64_t)e0 * 2 * DP;
         a.en += e0;
         a.ea += e0;
         a.ne = cnt;
     }
-    // entry tile; afterwards the key staging of the four waves
-    __shared__ __align__(16) float tile[64 * K::LDSW > 4 * 16 * 68 ? 64 * K::LDSW : 4 * 16 * 68];
+    // one pass of the tile's split rows; afterwards the key staging of the
+    // four waves (16 rows of 68 floats each)
+    constexpr int kTile = 64 * X::ROW, kStage = 2 * 4 * 16 * 68;
+    __shared__ __align__(16) uint16_t tile[kTile > kStage ? kTile : kStage];
     __shared__ float gms[4 * 16 * kGmStride];
     __shared__ __align__(16) float ten[64];
     __shared__ __align__(16) uint32_t tea[64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int rl = lane & 15, lq = lane >> 4;
-    const int64_t row = (int64_t)blockIdx.x * 64 + wave * 16 + rl;
-    const bool row_ok = row < a.nq;
-    const int64_t rowc = row_ok ? row : a.nq - 1;
-    const float4 *qrow = reinterpret_cast<const float4 *>(a.qpad + rowc * DP);
+    const int64_t row0 = (int64_t)blockIdx.x * 64 + wave * 16;
+    const int64_t row = row0 + rl;
+    const int64_t rowc = row < a.nq ? row : a.nq - 1;
+    // the query's split row in 16-byte units
+    const u32x4 *qrow = reinterpret_cast<const u32x4 *>(a.qs + rowc * 2 * DP);
     const float rn = a.qnorm[rowc];
     const uint32_t qw = a.qword[rowc], qm = a.qmask[rowc];
     const float mq = (float)(__popc(qm) / a.abits);
     if (group_exact<DP>(a, rowc))
         return;  // done by k_entry_keys_b16
-    float4 ra[K::NT];
-    if constexpr (K::NK == 1) {
-#pragma unroll
-        for (int t = 0; t < K::NT; ++t)
-            ra[t] = qrow[4 * t + lq];
+    const int cbeg = blockIdx.y * (64 * TL);
+    const int cend = min(cbeg + 64 * TL, a.ne_pad);
+    const int ntiles = (cend - cbeg) / 64;
+    const u32x4 *es4 = reinterpret_cast<const u32x4 *>(a.es);
+
+    u32x4 v[X::NV];            // the next pass's entry rows (this thread's share)
+    u32x4 qb[2][X::NCK][2];    // query chunks (hi, lo): this pass's and the next's
+    EntryMeta em{0.0f, 0u};
+    if (ntiles > 0) {
+        x3_load<DP>(es4, qrow, cbeg, 0, a.ne, lq, v, qb[0]);
+        em = load_entry_meta(a, cbeg);
     }
-    const int cbeg = blockIdx.y * (64 * kKeyTiles);
-    for (int c0 = cbeg; c0 < cbeg + 64 * kKeyTiles && c0 < a.ne_pad; c0 += 64) {
+    for (int t = 0; t < ntiles; ++t) {
+        const int c0 = cbeg + 64 * t;
         f32x4 acc[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s)
             acc[s] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        {
-            for (int kc = 0; kc < K::NK; ++kc) {
-                // stage 64 entry rows (dims kc*KC .. +KC) into LDS, every
-                // load issued before the first write
-                constexpr int kIt = 64 * (K::KC / 4) / 256;
-                static_assert(kIt * 256 == 64 * (K::KC / 4), "whole staging rounds");
-                __syncthreads();
-                float4 v[kIt];
 #pragma unroll
-                for (int it = 0; it < kIt; ++it) {
-                    const int i = (int)threadIdx.x + 256 * it, r = i / (K::KC / 4), c4 = i - r * (K::KC / 4);
-                    const int col = min(c0 + r, a.ne - 1);
-                    v[it] = reinterpret_cast<const float4 *>(a.ev + (int64_t)col * DP + kc * K::KC)[c4];
+        for (int kc = 0; kc < X::NP; ++kc) {
+            __syncthreads();  // the previous pass's readers of the LDS are done
+#pragma unroll
+            for (int it = 0; it < X::NV; ++it) {
+                const int i = (int)threadIdx.x + 256 * it, r = i / (X::KC / 4), c4 = i - r * (X::KC / 4);
+                *reinterpret_cast<u32x4 *>(tile + r * X::ROW + 8 * c4) = v[it];
+            }
+            if (kc == 0)
+                put_entry_meta(em, ten, tea);
+            __syncthreads();
+            // the next pass's loads (the next tile's first pass after the
+            // last), in flight during this pass's products; one call with a
+            // fixed target buffer, so the buffers stay in registers
+            if (kc + 1 < X::NP || t + 1 < ntiles) {
+                const bool last = kc + 1 == X::NP;
+                x3_load<DP>(es4, qrow, last ? c0 + 64 : c0, last ? 0 : kc + 1, a.ne, lq, v, qb[(kc + 1) & 1]);
+                if (last)
+                    em = load_entry_meta(a, c0 + 64);
+            }
+            const int cur = kc & 1;
+#pragma unroll
+            for (int j = 0; j < X::NCK; ++j) {
+                bf16x8 ah[4], al[4];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const uint16_t *er = tile + (16 * s + rl) * X::ROW + 64 * j + 8 * lq;
+                    ah[s] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(er));
+                    al[s] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(er + 32));
                 }
-                EntryMeta em{0.0f, 0u};
-                if (kc == 0)
-                    em = load_entry_meta(a, c0);
+                const bf16x8 bh = __builtin_bit_cast(bf16x8, qb[cur][j][0]);
+                const bf16x8 bl = __builtin_bit_cast(bf16x8, qb[cur][j][1]);
 #pragma unroll
-                for (int it = 0; it < kIt; ++it) {
-                    const int i = (int)threadIdx.x + 256 * it, r = i / (K::KC / 4), c4 = i - r * (K::KC / 4);
-                    *reinterpret_cast<float4 *>(tile + r * K::LDSW + 4 * c4) = v[it];
-                }
-                if (kc == 0)
-                    put_entry_meta(em, ten, tea);
-                __syncthreads();
-                if constexpr (K::NK > 1) {
+                for (int s = 0; s < 4; ++s)
+                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], bh, acc[s], 0, 0, 0);
 #pragma unroll
-                    for (int t = 0; t < K::NT; ++t)
-                        ra[t] = qrow[kc * (K::KC / 4) + 4 * t + lq];
-                }
+                for (int s = 0; s < 4; ++s)
+                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], bl, acc[s], 0, 0, 0);
 #pragma unroll
-                for (int t = 0; t < K::NT; ++t) {
-                    float4 cb[4];
+                for (int s = 0; s < 4; ++s)
+                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[s], bh, acc[s], 0, 0, 0);
+            }
+        }
+        // an odd pass count leaves the next tile's first chunks in buffer 1
+        if constexpr (X::NP % 2 == 1) {
 #pragma unroll
-                    for (int s = 0; s < 4; ++s)
-                        cb[s] = *reinterpret_cast<const float4 *>(tile + (16 * s + rl) * K::LDSW + 16 * t + 4 * lq);
-                    const float4 rv = ra[t];
-#pragma unroll
-                    for (int s = 0; s < 4; ++s)
-                        acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[s].x, rv.x, acc[s], 0, 0, 0);
-#pragma unroll
-                    for (int s = 0; s < 4; ++s)
-                        acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[s].y, rv.y, acc[s], 0, 0, 0);
-#pragma unroll
-                    for (int s = 0; s < 4; ++s)
-                        acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[s].z, rv.z, acc[s], 0, 0, 0);
-#pragma unroll
-                    for (int s = 0; s < 4; ++s)
-                        acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[s].w, rv.w, acc[s], 0, 0, 0);
-                }
+            for (int j = 0; j < X::NCK; ++j) {
+                qb[0][j][0] = qb[1][j][0];
+                qb[0][j][1] = qb[1][j][1];
             }
         }
         __syncthreads();  // the tile's products are done: its LDS stages the keys
-        store_keys<DEF, TL>(a, acc, c0, (int64_t)blockIdx.x * 64 + wave * 16, rl, lq, rn, qw, qm, mq, ten, tea,
-                        tile + wave * 16 * 68, gms + wave * 16 * kGmStride, (c0 - cbeg) / 16);
+        store_keys<DEF, TL>(a, acc, c0, row0, rl, lq, rn, qw, qm, mq, ten, tea,
+                            reinterpret_cast<float *>(tile) + wave * 16 * 68, gms + wave * 16 * kGmStride,
+                            (c0 - cbeg) / 16);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    flush_gmin<TL>(a, gms + wave * 16 * kGmStride, (int64_t)blockIdx.x * 64 + wave * 16, cbeg / 16,
-               (min(cbeg + 64 * kKeyTiles, a.ne_pad) - cbeg) / 16);
+    flush_gmin<TL>(a, gms + wave * 16 * kGmStride, row0, cbeg / 16, (cend - cbeg) / 16);
 }
 
 // The same product on the bf16 matrix cores (v_mfma_f32_16x16x32_bf16) for
@@ -531,6 +582,8 @@ namespace {
 // tiles of a.ne_pad columns
 int launch_keys(const Index *ix, const KeyArgs &a, hipStream_t st)
 {
+    if (!a.qs || !a.es)
+        return fail(NHQ_EINVAL, "seed ranking without split rows");
     const int nj = a.ne_pad / 64;
     // tiles per workgroup: the most (up to 8) that still give >= 1024 workgroups
     const int64_t qgroups = (a.nq + 63) / 64;
@@ -559,14 +612,14 @@ int launch_keys(const Index *ix, const KeyArgs &a, hipStream_t st)
     switch (ix->dp) {
 #define NHQ_K(DPV)                                                                       \
     case DPV:                                                                            \
-        NHQ_KTL(k_entry_keys, DPV)                                                       \
+        NHQ_KTL(k_entry_keys_x3, DPV)                                                    \
         break;
 #define NHQ_KB(DPV)                                                                      \
     case DPV:                                                                            \
         if (a.eb && a.qx) {                                                              \
             NHQ_KTL(k_entry_keys_b16, DPV)                                               \
         }                                                                                \
-        NHQ_KTL(k_entry_keys, DPV)                                                       \
+        NHQ_KTL(k_entry_keys_x3, DPV)                                                    \
         break;
         NHQ_KB(32)
         NHQ_KB(64)
@@ -705,10 +758,11 @@ __global__ void k_strata_slot(const int32_t *__restrict__ qblock, int64_t nq, co
     inv[slot] = (int32_t)q;
 }
 
-// the padded query rows, norms and codes in slot order (empty slots: zeros)
-__global__ void k_strata_permute(const float *__restrict__ qpad, const float *__restrict__ qnorm,
+// the split query rows (dp 32-bit words each: two bf16 halves per word),
+// norms and codes in slot order (empty slots: zeros)
+__global__ void k_strata_permute(const uint32_t *__restrict__ qsw, const float *__restrict__ qnorm,
                                  const uint32_t *__restrict__ qword, const uint32_t *__restrict__ qmask,
-                                 const int32_t *__restrict__ inv, int64_t slots, int dp, float *__restrict__ spad,
+                                 const int32_t *__restrict__ inv, int64_t slots, int dp, uint32_t *__restrict__ ssw,
                                  float *__restrict__ snorm, uint32_t *__restrict__ sword, uint32_t *__restrict__ smask)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -717,7 +771,7 @@ __global__ void k_strata_permute(const float *__restrict__ qpad, const float *__
     const int64_t s = t / dp;
     const int c = (int)(t - s * dp);
     const int32_t q = inv[s];
-    spad[t] = q >= 0 ? qpad[(int64_t)q * dp + c] : 0.0f;
+    ssw[t] = q >= 0 ? qsw[(int64_t)q * dp + c] : 0u;
     if (c == 0) {
         snorm[s] = q >= 0 ? qnorm[q] : 0.0f;
         sword[s] = q >= 0 ? qword[q] : 0u;
@@ -746,7 +800,7 @@ __global__ void k_strata_gather(const int32_t *__restrict__ cslot, const int32_t
 struct StrataLayout {
     int64_t slots, nseg;
     int nb, ne_pad;
-    size_t o_spad, o_snorm, o_sword, o_smask, o_keys, o_gmin, o_cslot, o_qblock, o_perm, o_inv, o_hist, o_off,
+    size_t o_ssplit, o_snorm, o_sword, o_smask, o_keys, o_gmin, o_cslot, o_qblock, o_perm, o_inv, o_hist, o_off,
         o_cursor, o_seg, words;
 };
 
@@ -766,7 +820,7 @@ StrataLayout strata_layout(const Index *ix, int64_t nq, int K)
         o += (words + 63) / 64 * 64;  // 256-byte pieces
         return at;
     };
-    L.o_spad = take((size_t)L.slots * ix->dp);
+    L.o_ssplit = take((size_t)L.slots * ix->dp);
     L.o_snorm = take((size_t)L.slots);
     L.o_sword = take((size_t)L.slots);
     L.o_smask = take((size_t)L.slots);
@@ -791,11 +845,11 @@ size_t strata_rank_words(const Index *ix, int64_t nq, int K)
     return strata_layout(ix, nq, K).words;
 }
 
-int launch_strata_rank(const Index *ix, const float *qpad, const float *qnorm, const uint32_t *qword,
+int launch_strata_rank(const Index *ix, const uint16_t *qsplit, const float *qnorm, const uint32_t *qword,
                        const uint32_t *qmask, int64_t nq, int K, uint32_t *blk, int32_t *cand, hipStream_t st)
 {
     const StrataLayout L = strata_layout(ix, nq, K);
-    float *spad = reinterpret_cast<float *>(blk + L.o_spad);
+    uint32_t *ssw = blk + L.o_ssplit;
     float *snorm = reinterpret_cast<float *>(blk + L.o_snorm);
     uint32_t *sword = blk + L.o_sword, *smask = blk + L.o_smask;
     float *keys = reinterpret_cast<float *>(blk + L.o_keys);
@@ -816,11 +870,13 @@ int launch_strata_rank(const Index *ix, const float *qpad, const float *qnorm, c
     hipLaunchKernelGGL(k_strata_scan, dim3(1), dim3(64), 0, st, hist, L.nb, off, seg, L.nseg);
     hipLaunchKernelGGL(k_strata_slot, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, qblock, nq, off, cursor,
                        perm, inv);
-    hipLaunchKernelGGL(k_strata_permute, dim3((unsigned)((L.slots * ix->dp + 255) / 256)), dim3(256), 0, st, qpad,
-                       qnorm, qword, qmask, inv, L.slots, ix->dp, spad, snorm, sword, smask);
+    hipLaunchKernelGGL(k_strata_permute, dim3((unsigned)((L.slots * ix->dp + 255) / 256)), dim3(256), 0, st,
+                       reinterpret_cast<const uint32_t *>(qsplit), qnorm, qword, qmask, inv, L.slots, ix->dp, ssw,
+                       snorm, sword, smask);
     NHQ_HIP(hipGetLastError());
-    KeyArgs a{spad, snorm, sword, smask, ix->entry_vec, ix->entry_norm, ix->entry_attr, nullptr,
-              nullptr, keys, gmin, L.slots, ix->n_entry, L.ne_pad, ix->w, ix->abits, ix->hmask};
+    KeyArgs a{nullptr, reinterpret_cast<const uint16_t *>(ssw), snorm, sword, smask, ix->entry_split,
+              ix->entry_norm, ix->entry_attr, nullptr, nullptr, keys, gmin, L.slots, ix->n_entry, L.ne_pad, ix->w,
+              ix->abits, ix->hmask};
     a.seg = seg;
     a.block_off = ix->block_off;
     a.n_blocks = ix->n_blocks;
@@ -837,15 +893,15 @@ int launch_strata_rank(const Index *ix, const float *qpad, const float *qnorm, c
     return NHQ_OK;
 }
 
-int launch_seed_rank(const Index *ix, const float *qpad, const float *qnorm, const uint32_t *qword,
-                     const uint32_t *qmask, const uint32_t *qexact, int64_t nq, int K, float *keys,
-                     int32_t *cand, hipStream_t st)
+int launch_seed_rank(const Index *ix, const float *qpad, const uint16_t *qsplit, const float *qnorm,
+                     const uint32_t *qword, const uint32_t *qmask, const uint32_t *qexact, int64_t nq, int K,
+                     float *keys, int32_t *cand, hipStream_t st)
 {
     const int ne = ix->n_entry;
     const int ne_pad = (ne + 63) / 64 * 64;
     if (ne_pad / 64 > 128)
         return fail(NHQ_EINVAL, "entry sample larger than 8192");
-    KeyArgs a{qpad, qnorm, qword, qmask, ix->entry_vec, ix->entry_norm, ix->entry_attr, ix->entry_bf16,
+    KeyArgs a{qpad, qsplit, qnorm, qword, qmask, ix->entry_split, ix->entry_norm, ix->entry_attr, ix->entry_bf16,
               qexact, keys, keys + (size_t)nq * ne_pad, nq, ne, ne_pad, ix->w, ix->abits, ix->hmask};
     int rc = launch_keys(ix, a, st);
     if (rc == NHQ_OK)

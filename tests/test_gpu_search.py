@@ -247,14 +247,17 @@ def test_seed_rank_ties_break_by_position(distinct, n_cand, n_entry):
         assert sorted(cand[i].tolist()) == sorted(want[i].tolist())
 
 
-@pytest.mark.parametrize("d", [20, 64, 90, 128])
-@pytest.mark.parametrize("integer", [True, False])
+@pytest.mark.parametrize("d,integer", [(20, True), (64, True), (90, True), (128, True), (20, False), (64, False),
+                                       (90, False), (128, False), (200, False), (500, False), (960, False),
+                                       (1000, False)])
 def test_seed_rank_exact_at_every_padded_width(d, integer):
-    # the key kernels stage a tile's entry rows in 1 to 8 rounds of loads
-    # depending on the padded width (32, 64, 96, 128) and the path (bf16 for
-    # integer data, float32 otherwise); a ragged sample (1,000 entries: the
-    # last tile holds 40) checks the clamped columns and their +inf keys.
-    # Data on a 1/8 grid keeps every float32 product and sum exact, so both
+    # the key kernels stage a tile's entry rows in passes of 32 or 64
+    # elements depending on the padded width (32 .. 1024) and take the
+    # exact bf16 path for integer data up to 128 wide, the split-bf16 path
+    # otherwise; a ragged sample (1,000 entries: the last tile holds 40)
+    # checks the clamped columns and their +inf keys.  Data on a 1/8 grid
+    # below 8 is exact in bf16 (its lo halves are zero) and keeps every
+    # product and partial sum exact in float32 at every width here, so both
     # paths must return exactly the oracle's best entries.
     rng = np.random.default_rng(d + 1000 * integer)
     n, nq, ne, K = 6000, 80, 1000, 24
@@ -275,13 +278,15 @@ def test_seed_rank_exact_at_every_padded_width(d, integer):
         assert sorted(cand[i].tolist()) == sorted(want[i].tolist()), i
 
 
-@pytest.mark.parametrize("n_entry,n_cand", [(4096, 32), (1000, 64), (8192, 17)])
-def test_seed_rank_float_data_is_the_best_up_to_rounding(n_entry, n_cand):
-    # float vectors (the float32 matrix-core path): the keys differ from the
-    # FP64 ones by rounding only, so every returned entry's FP64 key is
-    # within a relative 1e-4 of the n_cand-th best FP64 key, and the count is
-    # exact
-    w = synth.config1(n=30000, nq=96)
+@pytest.mark.parametrize("n_entry,n_cand,wide", [(4096, 32, False), (1000, 64, False), (8192, 17, False),
+                                                  (1024, 12, True), (2000, 40, True)])
+def test_seed_rank_float_data_is_the_best_up_to_rounding(n_entry, n_cand, wide):
+    # float vectors (the split-bf16 matrix-core path, 128 and 960 wide): the
+    # keys differ from the FP64 ones by the split's error only (about 2^-17
+    # relative per product, 1.8e-5 of a key at most on these data), so every
+    # returned entry's FP64 key is within a relative 1e-4 of the n_cand-th
+    # best FP64 key, and the count is exact
+    w = synth.config3(n=30000, nq=64) if wide else synth.config1(n=30000, nq=96)
     ix = nhq.nhq_index_create(_dev(w.x), _dev(w.attrs), n_entry=n_entry, seed=13)
     cand = nhq.nhq_seed_rank(ix, _dev(w.q), _dev(w.qattrs), n_cand).cpu().numpy()
     entry = oracle.entry_points(13, w.n, n_entry)
