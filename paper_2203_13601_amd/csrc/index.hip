@@ -118,10 +118,15 @@ __global__ void k_to_bf16(const float *__restrict__ v, uint16_t *__restrict__ ou
 // 2^-17 |v|, and hi * hi' + hi * lo' + lo * hi' equals v v' to within about
 // 3 * 2^-17 |v v'|; values exact in bf16 have lo = 0.  Element c of a row
 // goes to chunk c / 32: hi at 64 (c / 32) + c % 32, lo 32 further on.
+__device__ __forceinline__ void split_bf16(float v, uint32_t &hi, uint32_t &lo)
+{
+    hi = bf16_rne(v);
+    lo = bf16_rne(v - __uint_as_float(hi << 16));
+}
 __device__ __forceinline__ void put_split(uint16_t *row, int c, float v)
 {
-    const uint32_t hi = bf16_rne(v);
-    const uint32_t lo = bf16_rne(v - __uint_as_float(hi << 16));
+    uint32_t hi, lo;
+    split_bf16(v, hi, lo);
     const int at = 64 * (c >> 5) + (c & 31);
     row[at] = (uint16_t)hi;
     row[at + 32] = (uint16_t)lo;
@@ -214,25 +219,47 @@ __global__ __launch_bounds__(64) void k_pad_queries(const float *__restrict__ q,
         float s = 0.0f;
         bool exact = true;
         if (live) {
-            // 128 elements per round: every load of a round before its stores;
-            // each lane sums its elements in increasing order
-            for (int c0 = 0; c0 < dp; c0 += 128) {
+            // 128 elements per round, 8 consecutive ones per lane (dp is a
+            // multiple of 32, so a lane's 8 lie all inside the row or all
+            // past it): 16-byte loads where the row allows them, 16-byte
+            // stores of the padded row and of the split halves; each lane
+            // sums its elements in increasing order
+            const bool vec = (d & 3) == 0;
+            for (int c0 = 8 * sub; c0 < dp; c0 += 128) {
                 float v[8];
+                if (vec && c0 + 8 <= d) {
+                    const float4 *src = reinterpret_cast<const float4 *>(q + i * d + c0);
+                    const float4 lo4 = src[0], hi4 = src[1];
+                    v[0] = lo4.x, v[1] = lo4.y, v[2] = lo4.z, v[3] = lo4.w;
+                    v[4] = hi4.x, v[5] = hi4.y, v[6] = hi4.z, v[7] = hi4.w;
+                } else {
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int c = c0 + 16 * u + sub;
-                    v[u] = c < d ? q[i * d + c] : 0.0f;
+                    for (int u = 0; u < 8; ++u)
+                        v[u] = c0 + u < d ? q[i * d + c0 + u] : 0.0f;
+                }
+                float4 *dst = reinterpret_cast<float4 *>(qpad + i * dp + c0);
+                dst[0] = make_float4(v[0], v[1], v[2], v[3]);
+                dst[1] = make_float4(v[4], v[5], v[6], v[7]);
+                if (qsplit) {
+                    uint32_t hw[4], lw[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        uint32_t h2[2], l2[2];
+#pragma unroll
+                        for (int e = 0; e < 2; ++e) {
+                            split_bf16(v[2 * u + e], h2[e], l2[e]);
+                        }
+                        hw[u] = h2[0] | (h2[1] << 16);
+                        lw[u] = l2[0] | (l2[1] << 16);
+                    }
+                    uint16_t *row = qsplit + i * 2 * dp + 64 * (c0 >> 5) + (c0 & 31);
+                    *reinterpret_cast<uint4 *>(row) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+                    *reinterpret_cast<uint4 *>(row + 32) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
-                    const int c = c0 + 16 * u + sub;
-                    if (c < dp) {
-                        qpad[i * dp + c] = v[u];
-                        if (qsplit)
-                            put_split(qsplit + i * 2 * dp, c, v[u]);
-                        s = fmaf(v[u], v[u], s);
-                        exact = exact && v[u] == rintf(v[u]) && fabsf(v[u]) <= 256.0f;
-                    }
+                    s = fmaf(v[u], v[u], s);
+                    exact = exact && v[u] == rintf(v[u]) && fabsf(v[u]) <= 256.0f;
                 }
             }
         }

@@ -128,16 +128,18 @@ __device__ __forceinline__ void put_entry_meta(const EntryMeta &m, float *ten, u
     }
 }
 
-// Passes over a split row: KC elements per pass (64, or 32 where 64 does
-// not divide DP: wider passes need more registers than three waves per
-// SIMD leave), NCK 32-element chunks per pass, NP passes; an entry row's
+// Passes over a split row: KC elements per pass (the whole row up to 128
+// wide, else 64, or 32 where 64 does not divide DP: wider passes need more
+// registers than three waves per SIMD leave), NCK 32-element chunks per
+// pass, NP passes (with one pass, a wave loads its query chunks once for
+// every tile); an entry row's
 // pass sits in LDS at a stride of ROW bf16 halves (hi and lo of its NCK
 // chunks, 16 bytes of padding against bank conflicts).  The staged values
 // are native vectors (u32x4): held across the pass loop, HIP's uint4 class
 // is not kept in registers.
 template <int DP>
 struct XShape {
-    static constexpr int KC = DP % 64 == 0 ? 64 : 32;
+    static constexpr int KC = DP <= 128 ? DP : DP % 64 == 0 ? 64 : 32;
     static constexpr int NCK = KC / 32;
     static constexpr int NP = DP / KC;
     static constexpr int ROW = 2 * KC + 8;
@@ -227,13 +229,26 @@ __device__ __forceinline__ bool group_exact(const KeyArgs &a, int64_t rowc)
     return __syncthreads_and(a.qx[rowc] != 0u) != 0;
 }
 
+// Workgroups go to the 8 XCDs (each with its own L2) round-robin in
+// dispatch order.  The logical workgroup: XCD x takes the x-th contiguous
+// run of (query group, column tile) pairs, column tile fastest, so the
+// tiles of one query group (and the stratified block its neighbours share)
+// meet in one L2.  A bijection of 0 .. total - 1.
+__device__ __forceinline__ int xcd_logical(int flat, int total)
+{
+    constexpr int kXcd = 8;
+    const int x = flat % kXcd, pos = flat / kXcd;
+    return x * (total / kXcd) + min(x, total % kXcd) + pos;
+}
+
 // One pass's loads: this thread's share of the 64 split entry rows from
 // column c0 (columns past the sample's end repeat its last entry), and the
-// lane's query chunks of the pass (16-byte units of the split row: chunk
-// t's hi halves 8 lq .. 8 lq + 7 at 8 t + lq, its lo halves at 8 t + 4 + lq).
-template <int DP>
-__device__ __forceinline__ void x3_load(const u32x4 *es4, const u32x4 *qrow, int c0, int kc, int ne, int lq,
-                                        u32x4 (&v)[XShape<DP>::NV], u32x4 (&q)[XShape<DP>::NCK][2])
+// lane's query chunks of the pass for each of its QS query rows (16-byte
+// units of a split row: chunk t's hi halves 8 lq .. 8 lq + 7 at 8 t + lq,
+// its lo halves at 8 t + 4 + lq).
+template <int DP, int QS, bool LOADQ>
+__device__ __forceinline__ void x3_load(const u32x4 *es4, const u32x4 *const (&qrow)[QS], int c0, int kc, int ne,
+                                        int lq, u32x4 (&v)[XShape<DP>::NV], u32x4 (&q)[QS][XShape<DP>::NCK][2])
 {
     using X = XShape<DP>;
 #pragma unroll
@@ -242,75 +257,111 @@ __device__ __forceinline__ void x3_load(const u32x4 *es4, const u32x4 *qrow, int
         const int col = min(c0 + r, ne - 1);
         v[it] = es4[(int64_t)col * (DP / 4) + kc * (X::KC / 4) + c4];
     }
+    if constexpr (LOADQ) {
 #pragma unroll
-    for (int j = 0; j < X::NCK; ++j) {
-        q[j][0] = qrow[8 * (kc * X::NCK + j) + lq];
-        q[j][1] = qrow[8 * (kc * X::NCK + j) + 4 + lq];
+        for (int h = 0; h < QS; ++h)
+#pragma unroll
+            for (int j = 0; j < X::NCK; ++j) {
+                q[h][j][0] = qrow[h][8 * (kc * X::NCK + j) + lq];
+                q[h][j][1] = qrow[h][8 * (kc * X::NCK + j) + 4 + lq];
+            }
     }
 }
 
-// A workgroup of 4 waves: 64 queries (16 per wave) against TL tiles of 64
-// entries, split-bf16 products (see the top).  Each pass writes its staged
-// entry rows to LDS, issues the next pass's loads (the next tile's first
-// after a tile's last pass), then runs its products.  Workgroups whose
-// queries are all exact in bf16 are left to k_entry_keys_b16.
-template <int DP, bool DEF, int TL>
+// A workgroup of 4 waves: 64 QS queries (QS sets of 16 per wave) against
+// TL tiles of 64 entries, split-bf16 products (see the top); every entry
+// fragment read from LDS feeds the products of all QS sets.  Each pass
+// writes its staged entry rows to LDS, issues the next pass's loads (the
+// next tile's first after a tile's last pass), then runs its products.
+// QS = 1 where workgroups may be left to k_entry_keys_b16 (all 64 queries
+// exact in bf16) or rank against a stratified block (one per 64 rows).
+template <int DP, bool DEF, int TL, int QS>
 __global__ __launch_bounds__(256) void k_entry_keys_x3(const KeyArgs a0)
 {
     using X = XShape<DP>;
     constexpr int kGmStride = GmStride<TL>::v;
+    // a one-dimensional grid of query groups x column tiles: XCD-grouped
+    // (see xcd_logical) where every group ranks against the whole sample;
+    // query group fastest in dispatch order for a stratified sample, whose
+    // groups read disjoint column tiles of a block but share each tile with
+    // the block's other groups
+    const int nct = (a0.ne_pad / 64 + TL - 1) / TL;
+    int qgroup, ctile;
+    if (a0.seg) {
+        const int groups = (int)gridDim.x / nct;
+        ctile = (int)blockIdx.x / groups;
+        qgroup = (int)blockIdx.x - ctile * groups;
+    } else {
+        const int logical = xcd_logical((int)blockIdx.x, (int)gridDim.x);
+        qgroup = logical / nct;
+        ctile = logical - qgroup * nct;
+    }
     KeyArgs a = a0;
-    if (a0.seg) {  // stratified: this workgroup's entry block (uniform per workgroup)
-        const int b = a0.seg[blockIdx.x];
-        if (b < 0)
-            return;
-        int e0 = 0, cnt = a0.n_global;
-        if (b < a0.n_blocks) {
-            e0 = a0.block_off[b];
-            cnt = a0.block_off[b + 1] - e0;
+    if constexpr (QS == 1) {
+        if (a0.seg) {  // stratified: this workgroup's entry block (uniform per workgroup)
+            const int b = a0.seg[qgroup];
+            if (b < 0)
+                return;
+            int e0 = 0, cnt = a0.n_global;
+            if (b < a0.n_blocks) {
+                e0 = a0.block_off[b];
+                cnt = a0.block_off[b + 1] - e0;
+            }
+            a.es += (int64_t)e0 * 2 * DP;
+            a.en += e0;
+            a.ea += e0;
+            a.ne = cnt;
         }
-        a.es += (int64_t)e0 * 2 * DP;
-        a.en += e0;
-        a.ea += e0;
-        a.ne = cnt;
     }
     // one pass of the tile's split rows; afterwards the key staging of the
-    // four waves (16 rows of 68 floats each)
+    // four waves (16 rows of 68 floats each, one query set at a time)
     constexpr int kTile = 64 * X::ROW, kStage = 2 * 4 * 16 * 68;
     __shared__ __align__(16) uint16_t tile[kTile > kStage ? kTile : kStage];
-    __shared__ float gms[4 * 16 * kGmStride];
+    __shared__ float gms[4 * QS * 16 * kGmStride];
     __shared__ __align__(16) float ten[64];
     __shared__ __align__(16) uint32_t tea[64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int rl = lane & 15, lq = lane >> 4;
-    const int64_t row0 = (int64_t)blockIdx.x * 64 + wave * 16;
-    const int64_t row = row0 + rl;
-    const int64_t rowc = row < a.nq ? row : a.nq - 1;
-    // the query's split row in 16-byte units
-    const u32x4 *qrow = reinterpret_cast<const u32x4 *>(a.qs + rowc * 2 * DP);
-    const float rn = a.qnorm[rowc];
-    const uint32_t qw = a.qword[rowc], qm = a.qmask[rowc];
-    const float mq = (float)(__popc(qm) / a.abits);
-    if (group_exact<DP>(a, rowc))
-        return;  // done by k_entry_keys_b16
-    const int cbeg = blockIdx.y * (64 * TL);
+    const int64_t row0 = (int64_t)qgroup * 64 * QS + wave * 16 * QS;  // the wave's first row
+    const u32x4 *qrow[QS];  // the lane's query rows, split, in 16-byte units
+    float rn[QS], mq[QS];
+    uint32_t qw[QS], qm[QS];
+#pragma unroll
+    for (int h = 0; h < QS; ++h) {
+        const int64_t row = row0 + 16 * h + rl;
+        const int64_t rowc = row < a.nq ? row : a.nq - 1;
+        qrow[h] = reinterpret_cast<const u32x4 *>(a.qs + rowc * 2 * DP);
+        rn[h] = a.qnorm[rowc];
+        qw[h] = a.qword[rowc];
+        qm[h] = a.qmask[rowc];
+        mq[h] = (float)(__popc(qm[h]) / a.abits);
+    }
+    if constexpr (QS == 1) {
+        const int64_t row = row0 + rl;
+        if (group_exact<DP>(a, row < a.nq ? row : a.nq - 1))
+            return;  // done by k_entry_keys_b16
+    }
+    const int cbeg = ctile * (64 * TL);
     const int cend = min(cbeg + 64 * TL, a.ne_pad);
     const int ntiles = (cend - cbeg) / 64;
     const u32x4 *es4 = reinterpret_cast<const u32x4 *>(a.es);
 
-    u32x4 v[X::NV];            // the next pass's entry rows (this thread's share)
-    u32x4 qb[2][X::NCK][2];    // query chunks (hi, lo): this pass's and the next's
+    u32x4 v[X::NV];                // the next pass's entry rows (this thread's share)
+    u32x4 qb[2][QS][X::NCK][2];    // query chunks (hi, lo): this pass's and the next's
     EntryMeta em{0.0f, 0u};
+    constexpr bool kQOnce = X::NP == 1;  // the same query chunks for every tile
     if (ntiles > 0) {
-        x3_load<DP>(es4, qrow, cbeg, 0, a.ne, lq, v, qb[0]);
+        x3_load<DP, QS, true>(es4, qrow, cbeg, 0, a.ne, lq, v, qb[0]);
         em = load_entry_meta(a, cbeg);
     }
     for (int t = 0; t < ntiles; ++t) {
         const int c0 = cbeg + 64 * t;
-        f32x4 acc[4];
+        f32x4 acc[QS][4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
-            acc[s] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int h = 0; h < QS; ++h)
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                acc[h][s] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int kc = 0; kc < X::NP; ++kc) {
             __syncthreads();  // the previous pass's readers of the LDS are done
@@ -327,7 +378,8 @@ __global__ __launch_bounds__(256) void k_entry_keys_x3(const KeyArgs a0)
             // fixed target buffer, so the buffers stay in registers
             if (kc + 1 < X::NP || t + 1 < ntiles) {
                 const bool last = kc + 1 == X::NP;
-                x3_load<DP>(es4, qrow, last ? c0 + 64 : c0, last ? 0 : kc + 1, a.ne, lq, v, qb[(kc + 1) & 1]);
+                x3_load<DP, QS, !kQOnce>(es4, qrow, last ? c0 + 64 : c0, last ? 0 : kc + 1, a.ne, lq, v,
+                                         qb[(kc + 1) & 1]);
                 if (last)
                     em = load_entry_meta(a, c0 + 64);
             }
@@ -341,35 +393,44 @@ __global__ __launch_bounds__(256) void k_entry_keys_x3(const KeyArgs a0)
                     ah[s] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(er));
                     al[s] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(er + 32));
                 }
-                const bf16x8 bh = __builtin_bit_cast(bf16x8, qb[cur][j][0]);
-                const bf16x8 bl = __builtin_bit_cast(bf16x8, qb[cur][j][1]);
 #pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], bh, acc[s], 0, 0, 0);
+                for (int h = 0; h < QS; ++h) {
+                    const bf16x8 bh = __builtin_bit_cast(bf16x8, qb[cur][h][j][0]);
+                    const bf16x8 bl = __builtin_bit_cast(bf16x8, qb[cur][h][j][1]);
 #pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], bl, acc[s], 0, 0, 0);
+                    for (int s = 0; s < 4; ++s)
+                        acc[h][s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], bh, acc[h][s], 0, 0, 0);
 #pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[s], bh, acc[s], 0, 0, 0);
+                    for (int s = 0; s < 4; ++s)
+                        acc[h][s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], bl, acc[h][s], 0, 0, 0);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        acc[h][s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[s], bh, acc[h][s], 0, 0, 0);
+                }
             }
         }
         // an odd pass count leaves the next tile's first chunks in buffer 1
-        if constexpr (X::NP % 2 == 1) {
+        if constexpr (X::NP % 2 == 1 && !kQOnce) {
 #pragma unroll
-            for (int j = 0; j < X::NCK; ++j) {
-                qb[0][j][0] = qb[1][j][0];
-                qb[0][j][1] = qb[1][j][1];
-            }
+            for (int h = 0; h < QS; ++h)
+#pragma unroll
+                for (int j = 0; j < X::NCK; ++j) {
+                    qb[0][h][j][0] = qb[1][h][j][0];
+                    qb[0][h][j][1] = qb[1][h][j][1];
+                }
         }
         __syncthreads();  // the tile's products are done: its LDS stages the keys
-        store_keys<DEF, TL>(a, acc, c0, row0, rl, lq, rn, qw, qm, mq, ten, tea,
-                            reinterpret_cast<float *>(tile) + wave * 16 * 68, gms + wave * 16 * kGmStride,
-                            (c0 - cbeg) / 16);
+#pragma unroll
+        for (int h = 0; h < QS; ++h)
+            store_keys<DEF, TL>(a, acc[h], c0, row0 + 16 * h, rl, lq, rn[h], qw[h], qm[h], mq[h], ten, tea,
+                                reinterpret_cast<float *>(tile) + wave * 16 * 68,
+                                gms + (wave * QS + h) * 16 * kGmStride, (c0 - cbeg) / 16);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    flush_gmin<TL>(a, gms + wave * 16 * kGmStride, row0, cbeg / 16, (cend - cbeg) / 16);
+#pragma unroll
+    for (int h = 0; h < QS; ++h)
+        flush_gmin<TL>(a, gms + (wave * QS + h) * 16 * kGmStride, row0 + 16 * h, cbeg / 16, (cend - cbeg) / 16);
 }
 
 // The same product on the bf16 matrix cores (v_mfma_f32_16x16x32_bf16) for
@@ -578,67 +639,97 @@ __global__ __launch_bounds__(64) void k_entry_select_g(const float *__restrict__
 // positions of the n_cand best entry-sample members per query (unordered)
 namespace {
 
-// the key kernels over rows 0 .. a.nq - 1 (query groups of 64) and entry
-// tiles of a.ne_pad columns
+// tiles per workgroup: the most of (8, 2) that still gives min_wg
+// workgroups, else 1
+int pick_tiles(int64_t groups, int nj, int64_t min_wg)
+{
+    for (int t : {kMaxKeyTiles, 2})
+        if (groups * ((nj + t - 1) / t) >= min_wg)
+            return t;
+    return 1;
+}
+
+template <template <int, bool, int> class L, int DP>
+void launch_tiles(int tl, bool def, dim3 grid, const KeyArgs &a, hipStream_t st)
+{
+    if (tl == kMaxKeyTiles)
+        def ? L<DP, true, kMaxKeyTiles>::go(grid, a, st) : L<DP, false, kMaxKeyTiles>::go(grid, a, st);
+    else if (tl == 2)
+        def ? L<DP, true, 2>::go(grid, a, st) : L<DP, false, 2>::go(grid, a, st);
+    else
+        def ? L<DP, true, 1>::go(grid, a, st) : L<DP, false, 1>::go(grid, a, st);
+}
+template <int DP, bool DEF, int TL>
+struct LaunchB16 {
+    static void go(dim3 g, const KeyArgs &a, hipStream_t st)
+    {
+        if constexpr (DP <= 128 && DP % 32 == 0)
+            hipLaunchKernelGGL((k_entry_keys_b16<DP, DEF, TL>), g, dim3(256), 0, st, a);
+    }
+};
+template <int DP, bool DEF, int TL>
+struct LaunchX3Q1 {
+    static void go(dim3 g, const KeyArgs &a, hipStream_t st)
+    {
+        hipLaunchKernelGGL((k_entry_keys_x3<DP, DEF, TL, 1>), g, dim3(256), 0, st, a);
+    }
+};
+template <int DP, bool DEF, int TL>
+struct LaunchX3Q2 {
+    static void go(dim3 g, const KeyArgs &a, hipStream_t st)
+    {
+        hipLaunchKernelGGL((k_entry_keys_x3<DP, DEF, TL, 2>), g, dim3(256), 0, st, a);
+    }
+};
+
+// workgroups the split kernel aims for (about 2.5 per resident slot on 256
+// compute units, so the last round of workgroups is a small share)
+constexpr int64_t kX3MinWorkgroups = 2048;
+
+// The key kernels over rows 0 .. a.nq - 1 and entry tiles of a.ne_pad
+// columns: the exact bf16 kernel for the workgroups it takes (rows <= 128
+// wide, exact bf16 copies present: groups of 64 queries), and the split
+// kernel, two query sets per wave where neither that nor a stratified
+// sample fixes the groups at 64 queries.
+template <int DP>
+void launch_keys_dp(bool def, const KeyArgs &a, hipStream_t st)
+{
+    const int nj = a.ne_pad / 64;
+    const bool b16 = DP <= 128 && DP % 32 == 0 && a.eb && a.qx;
+    if (b16) {
+        const int64_t groups = (a.nq + 63) / 64;
+        const int tl = pick_tiles(groups, nj, 1024);
+        launch_tiles<LaunchB16, DP>(tl, def, dim3((unsigned)groups, (unsigned)((nj + tl - 1) / tl)), a, st);
+    }
+    const int qs = (b16 || a.seg) ? 1 : 2;
+    const int64_t groups = (a.nq + 64 * qs - 1) / (64 * qs);
+    const int tl = pick_tiles(groups, nj, kX3MinWorkgroups);
+    const dim3 grid((unsigned)(groups * ((nj + tl - 1) / tl)));
+    if (qs == 1)
+        launch_tiles<LaunchX3Q1, DP>(tl, def, grid, a, st);
+    else
+        launch_tiles<LaunchX3Q2, DP>(tl, def, grid, a, st);
+}
+
 int launch_keys(const Index *ix, const KeyArgs &a, hipStream_t st)
 {
     if (!a.qs || !a.es)
         return fail(NHQ_EINVAL, "seed ranking without split rows");
-    const int nj = a.ne_pad / 64;
-    // tiles per workgroup: the most (up to 8) that still give >= 1024 workgroups
-    const int64_t qgroups = (a.nq + 63) / 64;
-    int tl = 1;
-    for (int t : {kMaxKeyTiles, 2})
-        if (qgroups * ((nj + t - 1) / t) >= 1024) {
-            tl = t;
-            break;
-        }
-    const dim3 grid((unsigned)qgroups, (unsigned)((nj + tl - 1) / tl));
-    int rc = NHQ_OK;
     const bool def = ix->w.mode == NHQ_WEIGHTS_DEFAULT;
-#define NHQ_KT(KER, DPV, TLV)                                                               \
-    if (def)                                                                                \
-        hipLaunchKernelGGL((KER<DPV, true, TLV>), grid, dim3(256), 0, st, a);               \
-    else                                                                                    \
-        hipLaunchKernelGGL((KER<DPV, false, TLV>), grid, dim3(256), 0, st, a);
-#define NHQ_KTL(KER, DPV)                                                                   \
-    if (tl == kMaxKeyTiles) {                                                               \
-        NHQ_KT(KER, DPV, kMaxKeyTiles)                                                      \
-    } else if (tl == 2) {                                                                   \
-        NHQ_KT(KER, DPV, 2)                                                                 \
-    } else {                                                                                \
-        NHQ_KT(KER, DPV, 1)                                                                 \
-    }
     switch (ix->dp) {
-#define NHQ_K(DPV)                                                                       \
-    case DPV:                                                                            \
-        NHQ_KTL(k_entry_keys_x3, DPV)                                                    \
-        break;
-#define NHQ_KB(DPV)                                                                      \
-    case DPV:                                                                            \
-        if (a.eb && a.qx) {                                                              \
-            NHQ_KTL(k_entry_keys_b16, DPV)                                               \
-        }                                                                                \
-        NHQ_KTL(k_entry_keys_x3, DPV)                                                    \
-        break;
-        NHQ_KB(32)
-        NHQ_KB(64)
-        NHQ_KB(96)
-        NHQ_KB(128)
-        NHQ_K(256)
-        NHQ_K(512)
-        NHQ_K(960)
-        NHQ_K(1024)
-#undef NHQ_KB
-#undef NHQ_K
-#undef NHQ_KTL
-#undef NHQ_KT
-    default:
-        rc = fail(NHQ_EINVAL, "unsupported padded dimension");
+    case 32: launch_keys_dp<32>(def, a, st); break;
+    case 64: launch_keys_dp<64>(def, a, st); break;
+    case 96: launch_keys_dp<96>(def, a, st); break;
+    case 128: launch_keys_dp<128>(def, a, st); break;
+    case 256: launch_keys_dp<256>(def, a, st); break;
+    case 512: launch_keys_dp<512>(def, a, st); break;
+    case 960: launch_keys_dp<960>(def, a, st); break;
+    case 1024: launch_keys_dp<1024>(def, a, st); break;
+    default: return fail(NHQ_EINVAL, "unsupported padded dimension");
     }
-    if (rc == NHQ_OK && hipGetLastError() != hipSuccess)
-        rc = fail(NHQ_EHIP, "entry key launch failed");
-    return rc;
+    if (hipGetLastError() != hipSuccess)
+        return fail(NHQ_EHIP, "entry key launch failed");
+    return NHQ_OK;
 }
 
 // positions of the K best keys of each row (rows with live[row] < 0 skipped)
@@ -672,44 +763,61 @@ int launch_select(const float *keys, const float *gmin, int64_t rows, int ne, in
 
 // ---- stratified entry sample: queries grouped by their pattern's block
 
-// zero the block counters and cursors, mark every slot empty
-__global__ void k_strata_clear(int32_t *hist, int32_t *cursor, int nb, int32_t *inv, int64_t slots)
+// zero the block counters, mark every slot empty
+__global__ void k_strata_clear(int32_t *hist, int nb, int32_t *inv, int64_t slots)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < nb) {
+    if (t < nb)
         hist[t] = 0;
-        cursor[t] = 0;
-    }
     if (t < slots)
         inv[t] = -1;
 }
 
 // each query's block: its pattern's when every attribute is constrained and
 // some object holds the pattern (binary search of the sorted block words),
-// else the global members (n_blocks)
-__global__ void k_strata_assign(const uint32_t *__restrict__ qword, const uint32_t *__restrict__ qmask,
-                                int64_t nq, int full_bits, const uint32_t *__restrict__ block_word, int n_blocks,
-                                int32_t *__restrict__ qblock, int32_t *__restrict__ hist)
+// else the global members (n_blocks); and its position among the block's
+// queries (pos).  Counts go through a histogram in LDS, then one global
+// atomic per (workgroup, block) reserves the workgroup's run of positions.
+constexpr int kStrataMaxBlocks = 4096 + 1;  // patterns plus the global members
+__global__ __launch_bounds__(256) void k_strata_assign(const uint32_t *__restrict__ qword,
+                                                       const uint32_t *__restrict__ qmask, int64_t nq, int full_bits,
+                                                       const uint32_t *__restrict__ block_word, int n_blocks,
+                                                       int32_t *__restrict__ qblock, int32_t *__restrict__ pos,
+                                                       int32_t *__restrict__ hist)
 {
+    __shared__ int32_t lh[kStrataMaxBlocks];
+    const int nb = n_blocks + 1;
+    for (int t = threadIdx.x; t < nb; t += blockDim.x)
+        lh[t] = 0;
+    __syncthreads();
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nq)
-        return;
-    int b = n_blocks;
-    if (__popc(qmask[q]) == full_bits) {
-        const uint32_t w = qword[q];
-        int lo = 0, hi = n_blocks;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (block_word[mid] < w)
-                lo = mid + 1;
-            else
-                hi = mid;
+    const bool live = q < nq;
+    int b = n_blocks, r = 0;
+    if (live) {
+        if (__popc(qmask[q]) == full_bits) {
+            const uint32_t w = qword[q];
+            int lo = 0, hi = n_blocks;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (block_word[mid] < w)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            if (lo < n_blocks && block_word[lo] == w)
+                b = lo;
         }
-        if (lo < n_blocks && block_word[lo] == w)
-            b = lo;
+        r = atomicAdd(&lh[b], 1);
     }
-    qblock[q] = b;
-    atomicAdd(&hist[b], 1);
+    __syncthreads();
+    for (int t = threadIdx.x; t < nb; t += blockDim.x)
+        if (lh[t] > 0)
+            lh[t] = atomicAdd(&hist[t], lh[t]);
+    __syncthreads();
+    if (live) {
+        qblock[q] = b;
+        pos[q] = lh[b] + r;
+    }
 }
 
 // slot ranges: block b owns slots off[b] .. off[b] + hist[b] - 1 (ranges
@@ -746,14 +854,14 @@ __global__ __launch_bounds__(64) void k_strata_scan(const int32_t *__restrict__ 
     }
 }
 
+// each query's slot: its block's range start plus its position in the block
 __global__ void k_strata_slot(const int32_t *__restrict__ qblock, int64_t nq, const int32_t *__restrict__ off,
-                              int32_t *__restrict__ cursor, int32_t *__restrict__ perm, int32_t *__restrict__ inv)
+                              int32_t *__restrict__ perm, int32_t *__restrict__ inv)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nq)
         return;
-    const int b = qblock[q];
-    const int32_t slot = off[b] + atomicAdd(&cursor[b], 1);
+    const int32_t slot = off[qblock[q]] + perm[q];
     perm[q] = slot;
     inv[slot] = (int32_t)q;
 }
@@ -801,7 +909,7 @@ struct StrataLayout {
     int64_t slots, nseg;
     int nb, ne_pad;
     size_t o_ssplit, o_snorm, o_sword, o_smask, o_keys, o_gmin, o_cslot, o_qblock, o_perm, o_inv, o_hist, o_off,
-        o_cursor, o_seg, words;
+        o_seg, words;
 };
 
 StrataLayout strata_layout(const Index *ix, int64_t nq, int K)
@@ -832,7 +940,6 @@ StrataLayout strata_layout(const Index *ix, int64_t nq, int K)
     L.o_inv = take((size_t)L.slots);
     L.o_hist = take((size_t)L.nb + 1);
     L.o_off = take((size_t)L.nb + 1);
-    L.o_cursor = take((size_t)L.nb + 1);
     L.o_seg = take((size_t)L.nseg);
     L.words = o;
     return L;
@@ -849,6 +956,8 @@ int launch_strata_rank(const Index *ix, const uint16_t *qsplit, const float *qno
                        const uint32_t *qmask, int64_t nq, int K, uint32_t *blk, int32_t *cand, hipStream_t st)
 {
     const StrataLayout L = strata_layout(ix, nq, K);
+    if (L.nb > kStrataMaxBlocks)
+        return fail(NHQ_EINVAL, "a stratified entry sample holds at most 4096 attribute patterns");
     uint32_t *ssw = blk + L.o_ssplit;
     float *snorm = reinterpret_cast<float *>(blk + L.o_snorm);
     uint32_t *sword = blk + L.o_sword, *smask = blk + L.o_smask;
@@ -860,16 +969,15 @@ int launch_strata_rank(const Index *ix, const uint16_t *qsplit, const float *qno
     int32_t *inv = reinterpret_cast<int32_t *>(blk + L.o_inv);
     int32_t *hist = reinterpret_cast<int32_t *>(blk + L.o_hist);
     int32_t *off = reinterpret_cast<int32_t *>(blk + L.o_off);
-    int32_t *cursor = reinterpret_cast<int32_t *>(blk + L.o_cursor);
     int32_t *seg = reinterpret_cast<int32_t *>(blk + L.o_seg);
     const int64_t clear = std::max<int64_t>(L.slots, L.nb);
-    hipLaunchKernelGGL(k_strata_clear, dim3((unsigned)((clear + 255) / 256)), dim3(256), 0, st, hist, cursor, L.nb,
+    hipLaunchKernelGGL(k_strata_clear, dim3((unsigned)((clear + 255) / 256)), dim3(256), 0, st, hist, L.nb,
                        inv, L.slots);
     hipLaunchKernelGGL(k_strata_assign, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, qword, qmask, nq,
-                       ix->m * ix->abits, ix->block_word, ix->n_blocks, qblock, hist);
+                       ix->m * ix->abits, ix->block_word, ix->n_blocks, qblock, perm, hist);
     hipLaunchKernelGGL(k_strata_scan, dim3(1), dim3(64), 0, st, hist, L.nb, off, seg, L.nseg);
-    hipLaunchKernelGGL(k_strata_slot, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, qblock, nq, off, cursor,
-                       perm, inv);
+    hipLaunchKernelGGL(k_strata_slot, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, qblock, nq, off, perm,
+                       inv);
     hipLaunchKernelGGL(k_strata_permute, dim3((unsigned)((L.slots * ix->dp + 255) / 256)), dim3(256), 0, st,
                        reinterpret_cast<const uint32_t *>(qsplit), qnorm, qword, qmask, inv, L.slots, ix->dp, ssw,
                        snorm, sword, smask);
