@@ -82,6 +82,18 @@ def _profiled_traffic(kernel: str, source: str, tag: str):
     return None
 
 
+def _copy_calibration(torch, dev):
+    """Three device-to-device copies of 1 GiB, the last copies of the run: a
+    counter pass divides them out of FETCH_SIZE / WRITE_SIZE to get bytes."""
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    log("copy calibration: 3 copies of 1 GiB")
+
+
 def _r(v, n=6):
     """floats to n significant digits (nested)"""
     if isinstance(v, float):
@@ -264,7 +276,7 @@ def headline(args):
     adj = nhq.nhq_index_get_graph(ix)
     ixb = nhq.nhq_index_create(x, a, storage="bf16", n_entry=args.n_entry, seed=w.build_seed, degree=w.degree)
     nhq.nhq_index_set_graph(ixb, adj)
-    target, k, rr = args.target, w.k, 4
+    target, k, rr = args.target, w.k, args.rerank
     beams = [10, 12, 14, 16, 18, 20, 24, 28, 32, 40, 48, 64, 96, 128]
 
     # ---- 1 and 2: fixed-beam sweeps (fp32; bf16 and fp8 e4m3 + float32 re-score)
@@ -390,13 +402,7 @@ def headline(args):
     log("roofline: %s %.0f GB/s = %.1f%% of 8 TB/s (random %d-byte row gathers: %.0f GB/s)" % (
         kernel, achieved, 100 * achieved / HBM_PEAK_GBS, w.d * 2, gather_gbs))
     if args.copy_calibration:
-        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-        log("copy calibration: 3 copies of 1 GiB")
+        _copy_calibration(torch, dev)
 
     # ---- the seed set of Alg. 2 drawn at random (Sec. 3.2: n_init random
     # vertices, no ranking) against the ranked entry sample, fp32, same graph
@@ -753,6 +759,8 @@ def plain(args):
             "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": "k_search",
             "bytes_per_query": round(bq, 1), "queries_per_launch": h.nq,
             "kernel_avg_ms": round(vf["search_kernel_avg_ms"], 4)}
+    if args.copy_calibration:
+        _copy_calibration(torch, dev)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args, w, ix, h, vf["beam"])
     print(json.dumps({"metric": "hybrid QPS at Recall@10=0.95 on 1 GPU, 1M x 128 integer workload",
                       "value": round(vf["qps"], 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
@@ -877,6 +885,8 @@ def main():
     ap.add_argument("--expand", type=int, default=None, help="vertices expanded per step (headline 2, else 6)")
     ap.add_argument("--builder", default="exact", choices=["exact", "nndescent"])
     ap.add_argument("--check-every", type=int, default=1)
+    ap.add_argument("--rerank", type=int, default=4,
+                    help="headline reduced forms: re-score the first min(rerank * k, beam) eligible entries in FP32")
     ap.add_argument("--learned-beams", type=int, nargs="+", default=[20, 24, 32])
     ap.add_argument("--train-queries", type=int, default=None,
                     help="training queries of the stop network (20,000; 200,000 for learned10m)")
