@@ -220,14 +220,21 @@ typedef struct {
                             evaluated every check_every hops; 2: evaluated
                             once, at hop check_every, where it may stop the
                             search and otherwise sets the hop budget
-                            cap_factor * 2^(beam output) (cap_factor > 0) */
+                            cap_factor * 2^(beam output) (cap_factor > 0);
+                            3: the beam-width predictor, evaluated once, at
+                            hop check_every: the pool size becomes
+                            ceil(cap_factor * 2^(beam output)), clamped to
+                            [k, beam], for the rest of the search (the pool
+                            keeps its best entries; the stop logit is not
+                            read; cap_factor > 0)                          [0] */
     float stop_threshold;/* stop when sigmoid(stop logit) exceeds it    [0.5] */
     int32_t check_every; /* network evaluated every this many hops        [4] */
     uint32_t *counters;  /* nullable DEVICE uint32 [nq][2]: NDC (neighbour
                             distance evaluations) and H (expansions)          */
-    float cap_factor;    /* learned, > 0: stop at cap_factor * 2^(beam output
-                            at the first checkpoint) hops, checked before
-                            every step                                     [0] */
+    float cap_factor;    /* learned 1 or 2, > 0: stop at cap_factor * 2^(beam
+                            output at the first checkpoint) hops, checked
+                            before every step; learned 3: the pool size
+                            factor                                         [0] */
     const nhq_trace *trace; /* nullable: record checkpoint traces           */
     int32_t expand;      /* vertices expanded per step: the `expand` best
                             unexpanded pool entries are expanded together and
@@ -485,9 +492,10 @@ typedef struct {
                             the learned stop (needs nhq_mlp_load)   [beam_small] */
     int32_t max_hops;    /* expansion cap                               [100000] */
     float stop_threshold;/* learned stop threshold                          [0.5] */
-    float cap_factor;    /* learned hop budget factor (0 = none)              [0] */
-    int32_t learned_mode;/* learned requests: 1 or 2 (as nhq_search_params
-                            .learned)                                        [1] */
+    float cap_factor;    /* learned hop budget factor (0 = none), or the
+                            pool size factor of learned mode 3               [0] */
+    int32_t learned_mode;/* learned requests: 1, 2 or 3 (as
+                            nhq_search_params.learned)                       [1] */
     int32_t reserved1;
     double lifetime_s;   /* the kernels end by themselves after this long  [600] */
 } nhq_server_params;

@@ -379,7 +379,10 @@ def search(adj, xs, attrs, q, qa, k: int, L: int, seeds, n_init: int = 32, key_m
     hash, count, final_hash).  ``mlp`` (float64 [4866], weights as the GPU
     holds them) turns on the learned stop with threshold stop_threshold;
     learned_mode 2 evaluates it at the first checkpoint only, whose beam
-    output (times cap_factor) then bounds the hops.
+    output (times cap_factor) then bounds the hops; learned_mode 3 (the
+    beam-width predictor) evaluates it at the first checkpoint only and takes
+    ceil(cap_factor * 2^z1), clamped to [k, L], as the pool size from there
+    on (the pool keeps its best entries).
     ``expand`` E > 1 expands the E best unexpanded entries per step (a
     batched form of the algorithm's expansion loop; E = 1 is Alg. 2 itself).
     ``route_h`` h >= 2 runs two-stage routing (Sec. 4.2): a first stage that

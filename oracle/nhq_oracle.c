@@ -846,7 +846,10 @@ static void mlp_forward(const double *w, const double *f, double *z)
  *            reaches stop_logit; with cap_factor > 0 the beam output of the
  *            first checkpoint sets a hop budget cap_factor * 2^z1, checked
  *            before every step; learned_mode 2 takes the first checkpoint
- *            only (its budget then bounds the search);
+ *            only (its budget then bounds the search); learned_mode 3 is the
+ *            beam-width predictor: the first checkpoint's beam output sets
+ *            the pool size ceil(cap_factor * 2^z1), clamped to [k, L], for
+ *            the rest of the search (no stop logit, no budget);
  *   route_h  >= 2: two-stage routing (Sec. 4.2): stage S1 expands with a
  *            random 1-in-route_h subset of each vertex's slots until a step
  *            adds nothing to the pool, then S2 re-expands the whole pool with
@@ -903,6 +906,7 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
             const uint8_t *qav = qa + iq * (int64_t)m;
             int mq = or_arity(qav, m);
             int size = 0;
+            int Lq = L; /* pool capacity; learned mode 3 lowers it */
             int64_t ndc = 0, hops = 0, step_stamp = 0;
             int flag = 0;
 
@@ -914,9 +918,9 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
         int c_ = or_chi(qav, attrs + v_ * (int64_t)m, m);                               \
         double k_ = or_order_key(d2_, c_, mq, key_mode);                                \
         ndc += 1;                                                                        \
-        if (size == L && !lt(k_, v_, pool[L - 1].key, pool[L - 1].id))                  \
+        if (size == Lq && !lt(k_, v_, pool[Lq - 1].key, pool[Lq - 1].id))               \
             break;                                                                       \
-        int pos_ = (size < L) ? size : L - 1;                                            \
+        int pos_ = (size < Lq) ? size : Lq - 1;                                          \
         while (pos_ > 0 && lt(k_, v_, pool[pos_ - 1].key, pool[pos_ - 1].id)) {         \
             pool[pos_] = pool[pos_ - 1];                                                 \
             pos_ -= 1;                                                                   \
@@ -927,7 +931,7 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
         pool[pos_].chi = c_;                                                             \
         pool[pos_].expanded = 0;                                                         \
         pool[pos_].born = step_stamp;                                                    \
-        if (size < L)                                                                    \
+        if (size < Lq)                                                                   \
             size += 1;                                                                   \
     } while (0)
 
@@ -1041,7 +1045,27 @@ void or_search(const int32_t *adj, int R, const float *xs, const float *xr,
                         tr_hash[tt] = h;
                         ntrace += 1;
                     }
-                    if (mlp) {
+                    if (mlp && learned_mode == 3) {
+                        /* the beam-width predictor: the first checkpoint's
+                         * beam output sets the pool size for the rest of the
+                         * search, ceil(cap_factor * 2^z1) clamped to [k, L];
+                         * the pool keeps its best entries and the step's
+                         * selection is made again from what is left */
+                        double z[2];
+                        mlp_forward(mlp, f, z);
+                        next_ckpt = INT64_MAX;
+                        if (first_ckpt) {
+                            first_ckpt = 0;
+                            double want = ceil(cap_factor * pow(2.0, z[1]));
+                            int lp = !(want < (double)Lq) ? Lq : (want < (double)k ? k : (int)want);
+                            if (lp < Lq) {
+                                Lq = lp;
+                                if (size > Lq)
+                                    size = Lq;
+                                continue;
+                            }
+                        }
+                    } else if (mlp) {
                         double z[2];
                         mlp_forward(mlp, f, z);
                         if (cap_factor > 0 && first_ckpt)

@@ -1082,12 +1082,14 @@ int nhq_search_seeded(const nhq_index *h, const float *queries, const uint8_t *q
         return fail(NHQ_EINVAL, "visited_log2 must be 0 or in [10, 13]");
     if (p.route_h < 0 || p.route_h > NHQ_MAX_DEGREE)
         return fail(NHQ_EINVAL, "route_h must be in [0, 64]");
-    if (p.learned < 0 || p.learned > 2)
-        return fail(NHQ_EINVAL, "learned must be 0, 1 or 2");
+    if (p.learned < 0 || p.learned > 3)
+        return fail(NHQ_EINVAL, "learned must be 0, 1, 2 or 3");
     if (p.learned && !ix->mlp)
         return fail(NHQ_EINVAL, "learned stop requested but no network is loaded");
     if (p.learned == 2 && !(p.cap_factor > 0.0f))
         return fail(NHQ_EINVAL, "learned mode 2 needs cap_factor > 0 (its hop budget)");
+    if (p.learned == 3 && !(p.cap_factor > 0.0f))
+        return fail(NHQ_EINVAL, "learned mode 3 needs cap_factor > 0 (its pool size factor)");
     SearchLaunch s{};
     s.ix = ix;
     s.seed_cand = cand;

@@ -570,6 +570,7 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
     // checkpoint state (the rest is in LDS)
     int ins_window = 0;
     float budget = 3.0e38f;  // learned hop budget
+    int Lq = L;              // pool capacity (learned mode 3 lowers it)
     // E = 1: the adjacency row of the runner-up is fetched one hop ahead (it
     // is the next vertex to expand unless this hop inserts a better one)
     const int E = a.expand;
@@ -678,7 +679,25 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
                     cks->ntrace = ntrace + 1;
             }
             wsync();
-            if (a.learned) {
+            if (a.learned == 3) {
+                // the beam-width predictor: the first checkpoint's beam
+                // output sets the pool size ceil(cap_factor 2^z1), clamped to
+                // [k, L], for the rest of the search; the pool keeps its best
+                // entries and the step's selection is made again
+                float z0, z1;
+                mlp_infer(io.mlp, cks->f, cks->h1, z0, z1);
+                next_ckpt = 0xFFFFFFFFu;
+                if (first_ckpt) {
+                    const float want = ceilf(a.cap_factor * exp2f(z1));
+                    const int lp = !(want < (float)Lq) ? Lq : (want < (float)a.k ? a.k : (int)want);
+                    if (lp < Lq) {
+                        Lq = lp;
+                        size = min(size, Lq);
+                        lo = min(lo, size);
+                        continue;
+                    }
+                }
+            } else if (a.learned) {
                 float z0, z1;
                 mlp_infer(io.mlp, cks->f, cks->h1, z0, z1);
                 if (a.cap_factor > 0.0f && first_ckpt)
@@ -807,7 +826,7 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
             const uint32_t cw = v ? sid[j] : 0u;
             int ins = 0;
             bool mine = false;
-            size = pool_merge(pkey, pid, size, L, ck, cw, v, lo, &ins, &mine);
+            size = pool_merge(pkey, pid, size, Lq, ck, cw, v, lo, &ins, &mine);
             // several chunks: mark the staged entries that entered the pool
             // (bit 31 of a staged word is free) for the count below
             if (CK && nf > 64 && mine)
@@ -824,7 +843,7 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
             int joined = step_ins;
             if (nf > 64) {
                 wsync();
-                const bool full = size >= L;
+                const bool full = size >= Lq;
                 const float wk = pkey[size - 1];
                 const uint32_t wm = pid[size - 1] & kIdMask;
                 int cnt = 0;

@@ -484,8 +484,8 @@ int nhq_server_create(nhq_index *h, const nhq_server_params *pp, nhq_server **ou
         p.lifetime_s = 600.0;
     if (p.learned_mode == 0)
         p.learned_mode = 1;
-    if (p.learned_mode < 1 || p.learned_mode > 2 || (p.learned_mode == 2 && !(p.cap_factor > 0.0f)))
-        return fail(NHQ_EINVAL, "learned_mode must be 1, or 2 with cap_factor > 0");
+    if (p.learned_mode < 1 || p.learned_mode > 3 || (p.learned_mode >= 2 && !(p.cap_factor > 0.0f)))
+        return fail(NHQ_EINVAL, "learned_mode must be 1, or 2 or 3 with cap_factor > 0");
     if (p.beam_small < 1 || p.beam_small > NHQ_MAX_BEAM || (p.beam_large > 0 && p.beam_large <= p.beam_small) ||
         p.beam_large > NHQ_MAX_BEAM)
         return fail(NHQ_EINVAL, "need 1 <= beam_small < beam_large <= 1024 (beam_large < 0: no large class)");

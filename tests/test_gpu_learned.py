@@ -296,3 +296,93 @@ def test_trace_features_on_hand_walks(walk):
     assert [int(h) for h in hs] == [hand_walks.fingerprint(t) for t in walk["topk"]]
     assert int(tr.final_hash.cpu().numpy().view(np.uint32)[0]) == hand_walks.fingerprint(walk["ids"])
     ix.free()
+
+
+# ---- learned mode 3: the beam-width predictor
+
+def _check_pool(ix, w, adj, entry, wh, cf, ce, beam=128):
+    """Mode 3 against the oracle.  The pool size ceil(cf * 2^z1) is an integer
+    taken from a float: the kernel's float32 network can land on the other
+    side of an integer than the oracle's FP64 one only where cf * 2^z1 lies
+    within rounding of it.  Every query must equal the oracle's run, or its
+    run with cf moved by that rounding band either way."""
+    ids, dist, cnt = nhq.nhq_hybrid_search(ix, _dev(w.q), _dev(w.qattrs), 10, beam, learned=3, check_every=ce,
+                                           cap_factor=cf, counters=True)
+    ids, cnt = ids.cpu().numpy(), cnt.cpu().numpy().astype(np.int64)
+
+    def orun(c):
+        return oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, beam, entry, key_mode=oracle.KEY32,
+                             check_every=ce, mlp=wh, cap_factor=c, learned_mode=3)
+    o = orun(cf)
+    eps = 1e-3
+    lo, hi = orun(cf * 2.0 ** -eps), orun(cf * 2.0 ** eps)
+
+    def eq(r, q):
+        return np.array_equal(ids[q], r[0][q]) and cnt[q, 0] == r[2][q] and cnt[q, 1] == r[3][q]
+    same = np.array([eq(o, q) for q in range(w.nq)])
+    for q in np.nonzero(~same)[0]:
+        assert eq(lo, q) or eq(hi, q), q
+    return float(same.mean()), o
+
+
+def test_pool_size_predictor_matches_oracle(setup):
+    w, adj, ix, entry = setup
+    p = oracle.MLPRef.init(11)
+    flat = _flat(p).astype(np.float32)
+    flat[4865] = 5.0               # beam output about log2(32) plus the network's spread
+    nhq.nhq_mlp_load(ix, _dev(flat))
+    wh = flat.astype(np.float16).astype(np.float64)
+    fixed = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, 10, 128, entry, key_mode=oracle.KEY32)
+    for cf, ce in ((1.0, 2), (0.5, 4), (2.0, 1)):
+        frac, o = _check_pool(ix, w, adj, entry, wh, cf, ce)
+        assert frac >= 0.95, (cf, ce, frac)
+        # the predictor did cut pools: some searches end earlier than at beam 128
+        assert (o[3] < fixed[3]).mean() > 0.2, (cf, ce)
+    with pytest.raises(nhq.NHQError):  # mode 3 needs its pool size factor
+        nhq.nhq_hybrid_search(ix, _dev(w.q), _dev(w.qattrs), 10, 64, learned=3, check_every=2)
+    nhq.nhq_mlp_load(ix, None)
+
+
+def test_trained_pool_predictor_on_held_out_queries():
+    # train the beam-width predictor on traces of training queries; on
+    # held-out queries the predicted pool sizes follow the sizes the queries
+    # need, and some factor reaches the fixed-beam recall with fewer
+    # distance evaluations than the fixed-beam curve at that recall
+    from scipy.stats import spearmanr
+    from paper_2203_13601_amd import learned
+    from paper_2203_13601_amd.metrics import recall_at_k
+    w = synth.small(30000, 64, 2400, seed=93, integer=True, n_centres=16, zipf=True, wildcard_arity=True)
+    ix = nhq.nhq_build_index(_dev(w.x), _dev(w.attrs), degree=32, cand=64, n_entry=1024, seed=7)
+    qtr, qatr = _dev(w.q[:1600]), _dev(w.qattrs[:1600])
+    qte, qate = _dev(w.q[1600:]), _dev(w.qattrs[1600:])
+    params, info = learned.train_pool_network(ix, qtr, qatr, k=10, beam=256, epochs=60, seed=1,
+                                              check_every=1, n_init=8)
+    nhq.nhq_mlp_load(ix, params)
+    # the prediction at the first checkpoint against the held-out targets
+    need = learned.pool_labels(ix, qte, qate, 10, 256, (10, 12, 16, 20, 24, 32, 40, 48, 64, 96, 128, 192),
+                               n_init=8).cpu().numpy()
+    tr = nhq.TraceBuffers(qte.shape[0], 1)
+    nhq.nhq_hybrid_search(ix, qte, qate, 10, 256, n_init=8, check_every=1, trace=tr)
+    has = tr.count.cpu().numpy() > 0
+    Z = nhq.nhq_mlp_eval(ix, tr.feat[:, 0, :][torch.from_numpy(has).cuda()].contiguous())
+    rho = spearmanr(Z[:, 1].cpu().numpy(), need[has]).correlation
+    assert rho > 0.3, rho
+    gi, gd = oracle.bruteforce(w.x, w.attrs, w.q[1600:], w.qattrs[1600:], 10)[:2]
+
+    def run(**kw):
+        ids, _, cnt = nhq.nhq_hybrid_search(ix, qte, qate, 10, kw.pop("beam"), n_init=8, counters=True, **kw)
+        r = recall_at_k(ids.cpu().numpy(), w.x, w.q[1600:], w.attrs, w.qattrs[1600:], gi, 10).mean()
+        return r, cnt.cpu().numpy()[:, 0].mean()
+    fixed = [run(beam=b) for b in (12, 16, 24, 32, 48, 64, 96, 128, 192, 256)]
+    fr = np.array([f[0] for f in fixed])
+    fn = np.array([f[1] for f in fixed])
+    gain = False
+    for cf in (1.0, 1.5, 2.0, 3.0):
+        r, ndc = run(beam=256, learned=3, check_every=1, cap_factor=cf)
+        if r <= fr[0] or r > fr[-1]:
+            continue
+        j = int(np.searchsorted(fr, r))             # fixed beams bracketing r
+        t = (r - fr[j - 1]) / max(fr[j] - fr[j - 1], 1e-12)
+        gain = gain or ndc < fn[j - 1] + t * (fn[j] - fn[j - 1])
+    nhq.nhq_mlp_load(ix, None)
+    assert gain

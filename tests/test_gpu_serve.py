@@ -141,14 +141,19 @@ def test_serve_alone_equals_mix(float_index, storage):
         ix.free()
 
 
-def test_serve_learned_requests_equal_batch_learned_search(int_index):
+@pytest.mark.parametrize("mode,cf", [(1, 0.0), (3, 32.0)])
+def test_serve_learned_requests_equal_batch_learned_search(int_index, mode, cf):
+    # mode 1: the stop network at every checkpoint; mode 3: the beam-width
+    # predictor (pool size cf * 2^(beam output) from the first checkpoint)
     w, ix = int_index
     nhq.nhq_mlp_load(ix, init_params(3))
     torch.cuda.synchronize()
-    wi, wd, wc = _batch(ix, w, 10, 128, n_init=32, learned=True, stop_threshold=0.7, check_every=4)
+    wi, wd, wc = _batch(ix, w, 10, 128, n_init=32, learned=mode, stop_threshold=0.7, check_every=4,
+                        cap_factor=cf)
     n = w.nq
     with nhq.Server(ix, n_init=32, lifetime_s=LIFE, ring=256, slots_small=64, beam_large=-1,
-                    auto_beam=128, stop_threshold=0.7, check_every=4) as srv:
+                    auto_beam=128, stop_threshold=0.7, check_every=4, learned_mode=mode,
+                    cap_factor=cf) as srv:
         r = srv.run(w.q, w.qattrs, np.full(n, 10, np.int32), np.zeros(n, np.int32), np.zeros(n),
                     timeout_s=30.0)
     nhq.nhq_mlp_load(ix, None)

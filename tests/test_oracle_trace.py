@@ -153,3 +153,96 @@ def test_joined_counts_survivors_of_the_whole_step():
     walk = hand_walks.wide_step(1)
     _, _, _, _, _, tr = _run_hand(walk, oracle.KEY32)
     assert tr["feat"][0, 0, 6] == 1.0
+
+
+# ---- learned mode 3: the beam output chooses the pool size
+
+def _bias_net(stop_bias, beam_bias):
+    """A network whose outputs are its output biases (all weights zero)."""
+    net = np.zeros(4866)
+    net[4864] = stop_bias
+    net[4865] = beam_bias
+    return net
+
+
+def test_pool_size_predictor_on_the_chain_walk():
+    # chain (tests/hand_walks.py): k = 2, L = 3, one checkpoint per hop.  With
+    # beam output 0 and factor 2 the pool size is ceil(2 * 2^0) = 2 from the
+    # checkpoint at H = 1: the pool v2 v0* v1 is cut to v2 v0*; expanding v2
+    # offers v4(36) and v3(49), leaving v4 v3; v4 offers v5(16, mismatch)
+    # -> v5 v4*; v5 offers v6(9) (v2 was visited) -> v6 v5*; v6 has no
+    # neighbours.  H = 5, NDC = 6, and the only eligible entry is v6 (the
+    # fixed search also returns v4, which the cut pushed out at step 3).
+    walk = hand_walks.chain()
+    x = np.asarray(walk["x"], np.float32)[:, None]
+    attrs = np.asarray(walk["attrs"], np.uint8)[:, None]
+    adj = np.asarray(walk["adj"], np.int32)
+    q = np.zeros((1, 1), np.float32)
+    qa = np.zeros((1, 1), np.uint8)
+    seeds = np.asarray(walk["seeds"], np.int32)
+    kw = dict(n_init=1, key_mode=oracle.KEY64, expand=1, check_every=1, learned_mode=3)
+    ids, gam, ndc, hops, flag = oracle.search(adj, x, attrs, q, qa, 2, 3, seeds, mlp=_bias_net(-1e6, 0.0),
+                                              cap_factor=2.0, **kw)
+    assert ids[0].tolist() == [6, -1] and ndc[0] == 6 and hops[0] == 5
+    assert gam[0][0] == pytest.approx(3.0) and np.isinf(gam[0][1])
+    # a pool size of at least L leaves the search as it was
+    ids, gam, ndc, hops, flag = oracle.search(adj, x, attrs, q, qa, 2, 3, seeds, mlp=_bias_net(-1e6, 0.0),
+                                              cap_factor=3.0, **kw)
+    assert ids[0].tolist() == walk["ids"] and ndc[0] == walk["ndc"] and hops[0] == walk["hops"]
+    # the size is clamped below at k
+    low = oracle.search(adj, x, attrs, q, qa, 2, 3, seeds, mlp=_bias_net(-1e6, -10.0), cap_factor=1.0, **kw)
+    assert low[0][0].tolist() == [6, -1] and low[2][0] == 6 and low[3][0] == 5
+
+
+def _beam_with_cut(adj, keys, seeds, L, ckpt, Lp):
+    """Beam search with E = 1 written out plainly: the pool holds the L best
+    (key, id) seen, the best unexpanded entry is expanded next, each vertex is
+    scored once; before the step that follows hop `ckpt` the pool is cut to
+    its Lp best entries and holds Lp from then on.  Returns the final pool
+    (ids), NDC and H."""
+    pool = sorted(set(int(s) for s in seeds), key=lambda v: (keys[v], v))[:L]
+    seen = set(pool)
+    expanded = set()
+    cap, ndc, hops, cut = L, 0, 0, False
+    while True:
+        if not cut and hops >= ckpt:
+            cut = True
+            cap = min(cap, Lp)
+            pool = pool[:cap]
+        nxt = [v for v in pool if v not in expanded]
+        if not nxt:
+            break
+        u = nxt[0]
+        expanded.add(u)
+        hops += 1
+        for v in adj[u]:
+            if v < 0 or v in seen:
+                continue
+            seen.add(v)
+            ndc += 1
+            pool.append(int(v))
+            pool.sort(key=lambda t: (keys[t], t))
+            pool = pool[:cap]
+    return pool, ndc, hops
+
+
+@pytest.mark.parametrize("Lp", [10, 13, 24, 40])
+def test_pool_size_predictor_matches_a_plain_beam_search_with_a_cut(Lp):
+    # integer data (every key exact in FP64), E = 1, one checkpoint at H = 3
+    w = synth.small(1500, 8, 25, seed=202, integer=True, n_centres=5)
+    adj = oracle.build_graph(w.x, w.attrs, l=24, R=12)
+    entry = oracle.entry_points(5, w.n, 64)
+    L, k, ce = 40, 10, 3
+    beam_bias = math.log2(Lp)          # pool size ceil(2^log2(Lp)) = Lp
+    ids, gam, ndc, hops, flag = oracle.search(adj, w.x, w.attrs, w.q, w.qattrs, k, L, entry, n_init=4,
+                                              key_mode=oracle.KEY64, out_mode=1, check_every=ce,
+                                              mlp=_bias_net(-1e6, beam_bias), cap_factor=1.0, learned_mode=3)
+    for i in range(w.nq):
+        con = w.qattrs[i] != 255
+        mq = int(con.sum())
+        d2 = ((w.x.astype(np.float64) - w.q[i].astype(np.float64)) ** 2).sum(1)
+        chi = (w.attrs[:, con] != w.qattrs[i][con]).sum(1)
+        keys = d2 * (mq + chi) ** 2 if mq else d2
+        seeds = sorted(entry.tolist(), key=lambda v: (keys[v], v))[:4]
+        pool, rndc, rhops = _beam_with_cut(adj, keys, seeds, L, ce, max(Lp, k))
+        assert ids[i].tolist() == pool[:k] and ndc[i] == rndc and hops[i] == rhops, i
