@@ -314,6 +314,33 @@ def headline(args):
                              "positive_rate": info["positive_rate"]})
     best = max((r for r in learned_runs if _first_at(r["sweep"], target) is not None),
                key=lambda r: r["qps_at_target_interp"] or 0.0, default=None)
+    # ---- 3b: bf16 + the beam-width predictor (learned mode 3) at one beam
+    pool_run = None
+    if args.pool_beam:
+        from paper_2203_13601_amd.learned import train_pool_network
+        t0 = time.time()
+        pparams, pinfo = train_pool_network(ixb, tq, tqa, k, args.pool_beam, epochs=60, check_every=ce,
+                                            n_init=args.n_init, expand=args.expand, seed=3, rerank=rr)
+        nhq.nhq_mlp_load(ixb, pparams)
+        torch.cuda.synchronize()
+        ptrain_s = time.time() - t0
+        log("pool-size network at beam %d: %d samples in %.2fs (median target %.0f)" % (
+            args.pool_beam, pinfo["samples"], ptrain_s, pinfo["pool_label_median"]))
+        pts = []
+        for cf in (1.0, 1.25, 1.5, 2.0, 2.5, 3.0, 4.0):
+            kw = dict(rerank=rr, learned=3, check_every=ce, cap_factor=cf)
+            p = h.point(ixb, args.pool_beam, **kw)
+            p.update({"cap_factor": cf, "kw": kw})
+            pts.append(p)
+            log("bf16+pool predictor beam %d factor %.2f recall %.4f hops %.1f ndc %.0f search %.3fms %.0f QPS" % (
+                args.pool_beam, cf, p["recall"], p["hops"], p["ndc"], p["search_ms"], p["qps"]))
+            if p["recall"] >= target + 0.01 and len([x for x in pts if x["recall"] >= target]) >= 2:
+                break
+        pool_run = {"beam": args.pool_beam, "params": pparams, "sweep": pts, "train_s": ptrain_s,
+                    "train_samples": pinfo["samples"], "median_pool_target": pinfo["pool_label_median"],
+                    "qps_at_target_interp": qps_at_recall([p["cap_factor"] for p in pts],
+                                                          [p["recall"] for p in pts], [p["qps"] for p in pts],
+                                                          target)}
 
     # ---- timed steps at each form's first setting reaching the target
     forms = {}
@@ -350,8 +377,24 @@ def headline(args):
         value_form = "bf16_learned"
         log("bf16+learned: beam %d cap %.2f recall %.4f: %.3f ms/step, %.0f QPS" % (
             best["beam"], op["cap_factor"], op["recall"], run["ms_per_step"], run["qps"]))
+    if pool_run is not None and _first_at(pool_run["sweep"], target) is not None:
+        nhq.nhq_mlp_load(ixb, pool_run["params"])
+        pop = _first_at(pool_run["sweep"], target)
+        prun = h.run_form(ixb, pool_run["beam"], args.steps, args.warmup, **pop["kw"])
+        forms["bf16_pool_predictor"] = {
+            **prun, "beam": pool_run["beam"], "recall": pop["recall"], "ndc": pop["ndc"], "hops": pop["hops"],
+            "returned": pop["returned"], "learned_mode": 3, "check_every": ce, "pool_factor": pop["cap_factor"],
+            "rerank": rr, "qps_at_target_interp": pool_run["qps_at_target_interp"],
+            "train_samples": pool_run["train_samples"], "train_s": pool_run["train_s"],
+            "median_pool_target": pool_run["median_pool_target"],
+            "bytes_per_query": _bytes_per_query(w, 2, pop, pop["returned"]),
+            "sweep": [{kk: vv for kk, vv in p.items() if kk != "kw"} for p in pool_run["sweep"]]}
+        log("bf16_pool_predictor: beam %d factor %.2f recall %.4f: %.3f ms/step, %.0f QPS" % (
+            pool_run["beam"], pop["cap_factor"], pop["recall"], prun["ms_per_step"], prun["qps"]))
+        if best is not None:
+            nhq.nhq_mlp_load(ixb, best["params"])
     vf = forms[value_form]
-    for name in ("bf16_fixed", "fp8_fixed", "bf16_learned"):
+    for name in ("bf16_fixed", "fp8_fixed", "bf16_learned", "bf16_pool_predictor"):
         if name in forms:
             f = forms[name]
             f["speedup_vs_fp32_fixed"] = f["qps"] / forms["fp32_fixed"]["qps"]
@@ -423,9 +466,9 @@ def headline(args):
     # ---- 5. where selectivity varies: the serving stream's constraint law
     # (1 to 4 of the 4 attributes constrained) on the same query vectors; the
     # fixed beam against the learned budget at one large beam
-    mixed, mixed_net = None, None
+    mixed, mixed_net, pool_net = None, None, None
     if not args.no_mixed:
-        mixed, mixed_net = mixed_selectivity(args, w, ix, ixb, tq)
+        mixed, mixed_net, pool_net = mixed_selectivity(args, w, ix, ixb, tq)
     serving = None
     if not args.no_serve:
         fixed_beam = None
@@ -435,7 +478,7 @@ def headline(args):
             ok = [i for i, p in enumerate(sw) if p["recall"] >= target]
             if ok:
                 fixed_beam = [sw[ok[0] - 1]["beam"], sw[ok[0]]["beam"]] if ok[0] > 0 else [sw[ok[0]]["beam"]]
-        serving = serve_config5(args, w, ixb, ix, h, tq, x.device, mixed_net, fixed_beam)
+        serving = serve_config5(args, w, ixb, ix, h, tq, x.device, mixed_net, fixed_beam, pool_net)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args, w, ix, h, forms["fp32_fixed"]["beam"], rerank_n=0)
@@ -483,7 +526,7 @@ def mixed_selectivity(args, w, ix, ixb, tq):
     import torch
     import synth
     import paper_2203_13601_amd as nhq
-    from paper_2203_13601_amd.learned import train_stop_network
+    from paper_2203_13601_amd.learned import train_pool_network, train_stop_network
     from paper_2203_13601_amd.metrics import qps_at_recall
     dev = torch.device("cuda:0")
     wm = dataclasses.replace(w, qattrs=synth.partial_constraints(w.nq, w.cards, 508))
@@ -512,6 +555,27 @@ def mixed_selectivity(args, w, ix, ixb, tq):
     fa = qps_at_recall([p["beam"] for p in fixed], [p["recall"] for p in fixed], [p["qps"] for p in fixed], target)
     la = qps_at_recall([p["cap_factor"] for p in learned], [p["recall"] for p in learned],
                        [p["qps"] for p in learned], target)
+    # the beam-width predictor (learned mode 3): the network trained on pool
+    # size targets chooses each query's pool size at its first checkpoint
+    t0 = time.time()
+    pool_params, pinfo = train_pool_network(ixb, tq, tqa_p, w.k, big, epochs=60, check_every=ce,
+                                            n_init=args.n_init, expand=args.expand, seed=3, rerank=rr)
+    pool_s = time.time() - t0
+    log("mixed: pool-size network at beam %d: %d samples in %.2fs (median target %.0f)" % (
+        big, pinfo["samples"], pool_s, pinfo["pool_label_median"]))
+    nhq.nhq_mlp_load(ixb, pool_params)
+    pooled = []
+    for cf in (0.75, 1.0, 1.25, 1.5, 2.0, 2.5, 3.0, 4.0, 6.0):
+        p = hm.point(ixb, big, rerank=rr, learned=3, check_every=ce, cap_factor=cf)
+        p["cap_factor"] = cf
+        pooled.append(p)
+        log("mixed bf16+pool predictor beam %d factor %.2f recall %.4f hops %.1f (p99 %.0f) ndc %.0f %.0f QPS" % (
+            big, cf, p["recall"], p["hops"], p["hops_p99"], p["ndc"], p["qps"]))
+        if p["recall"] >= target + 0.01 and len([x for x in pooled if x["recall"] >= target]) >= 2:
+            break
+    pa = qps_at_recall([p["cap_factor"] for p in pooled], [p["recall"] for p in pooled],
+                       [p["qps"] for p in pooled], target)
+    nhq.nhq_mlp_load(ixb, params)
 
     def hops_at(pts, key):
         prev = None
@@ -528,13 +592,19 @@ def mixed_selectivity(args, w, ix, ixb, tq):
            "learned_speedup_vs_fixed": None if not (fa and la) else la / fa,
            "fixed_hops_at_target": hops_at(fixed, "beam"), "learned_hops_at_target": hops_at(learned, "cap_factor"),
            "learned_beam": big, "learned_mode": 2, "train_samples": info["samples"], "train_s": train_s,
+           "pool_predictor": {"learned_mode": 3, "qps_at_target_interp": pa,
+                              "speedup_vs_fixed": None if not (fa and pa) else pa / fa,
+                              "hops_at_target": hops_at(pooled, "cap_factor"), "train_samples": pinfo["samples"],
+                              "train_s": pool_s, "median_pool_target": pinfo["pool_label_median"],
+                              "sweep": pooled},
            "fixed_sweep": fixed, "learned_sweep": learned}
-    log("mixed selectivity: fixed %s QPS, learned %s QPS at Recall@10 %.2f (hops %s vs %s)" % (
-        fa, la, target, out["fixed_hops_at_target"], out["learned_hops_at_target"]))
-    return _r(out), params
+    log("mixed selectivity: fixed %s QPS, learned stop %s QPS, pool predictor %s QPS at Recall@10 %.2f "
+        "(hops %s / %s / %s)" % (fa, la, pa, target, out["fixed_hops_at_target"], out["learned_hops_at_target"],
+                                 out["pool_predictor"]["hops_at_target"]))
+    return _r(out), params, pool_params
 
 
-def serve_config5(args, w, ixb, ix32, h, tq, dev, params=None, fixed_beam=None):
+def serve_config5(args, w, ixb, ix32, h, tq, dev, params=None, fixed_beam=None, pool_params=None):
     """The serving form: Poisson stream through the continuous-batching
     server on the BF16 index (float32 re-score), then a saturation run."""
     import torch
@@ -649,6 +719,44 @@ def serve_config5(args, w, ixb, ix32, h, tq, dev, params=None, fixed_beam=None):
             "form's recall %.4f: %s QPS" % (fixed_beam[-1], out["fixed_beam_form"]["p50_ms"],
                                            out["fixed_beam_form"]["p99_ms"],
                                            out["fixed_beam_form"]["recall_at_10_k_ge_10"], sat_pts, lrec, at))
+    if pool_params is not None:
+        # the beam-width predictor (learned mode 3): the same stream and
+        # saturation run with each request's pool size chosen by the network
+        nhq.nhq_mlp_load(ixb, pool_params)
+        sq_d = torch.from_numpy(np.ascontiguousarray(s_q[samp])).to(dev)
+        sqa_d = torch.from_numpy(np.ascontiguousarray(s_qa[samp])).to(dev)
+        p_cf = None
+        for cf in (0.75, 1.0, 1.25, 1.5, 2.0, 2.5, 3.0, 4.0, 6.0, 8.0):
+            vi, _ = nhq.nhq_hybrid_search(ixb, sq_d, sqa_d, w.k, beam_auto, n_init=args.n_init,
+                                          expand=args.expand, rerank=4, learned=3, check_every=ce, cap_factor=cf)
+            vr = recall_at_k(vi.cpu().numpy(), w.x, s_q[samp], w.attrs, s_qa[samp], gsi, w.k).mean()
+            log("serving pool-size network: factor %.2f recall %.4f on the sample" % (cf, vr))
+            p_cf = cf
+            if vr >= args.target + 0.005:
+                break
+        del sq_d, sqa_d
+        torch.cuda.synchronize()
+        with nhq.Server(ixb, **{**sp, "learned_mode": 3, "cap_factor": p_cf}) as srv:
+            rp = srv.run(s_q, s_qa, s_k, s_beam, s_arr, timeout_s=120.0)
+            rps = srv.run(s_q[:sat_n], s_qa[:sat_n], s_k[:sat_n], s_beam[:sat_n], np.zeros(sat_n),
+                          timeout_s=120.0)
+        lp = rp["latency_s"] * 1000.0
+        sat = samp[samp < sat_n]
+        out["pool_predictor_form"] = {
+            "learned_mode": 3, "pool_factor": p_cf,
+            "p50_ms": round(float(np.percentile(lp, 50)), 4), "p99_ms": round(float(np.percentile(lp, 99)), 4),
+            "recall_at_10_k_ge_10": round(float(recall_at_k(rp["ids"][samp, :10], w.x, s_q[samp], w.attrs,
+                                                            s_qa[samp], gsi, w.k).mean()), 5),
+            "hops_mean": round(float(rp["counters"][:, 1].mean()), 2),
+            "saturation_qps": round(sat_n / rps["elapsed_s"], 1),
+            "saturation_recall_at_10_k_ge_10": round(float(recall_at_k(
+                rps["ids"][sat, :10], w.x, s_q[sat], w.attrs, s_qa[sat], gsi[samp < sat_n], w.k).mean()), 5)}
+        pf = out["pool_predictor_form"]
+        log("serving, pool-size predictor (factor %.2f): p50 %.3f ms, p99 %.3f ms, recall@10 %.4f, hops %.1f; "
+            "saturation %.0f QPS at recall %.4f" % (p_cf, pf["p50_ms"], pf["p99_ms"], pf["recall_at_10_k_ge_10"],
+                                                    pf["hops_mean"], pf["saturation_qps"],
+                                                    pf["saturation_recall_at_10_k_ge_10"]))
+        nhq.nhq_mlp_load(ixb, params)
     return out
 
 
@@ -834,6 +942,33 @@ def learned10m(args):
                      "hops_at_target": _interp_at(pts, target, "hops")})
     fa = qps_at_recall([p["beam"] for p in fixed], [p["recall"] for p in fixed], [p["qps"] for p in fixed], target)
     best = max(runs, key=lambda r: r["qps_at_target_interp"] or 0.0)
+    # the beam-width predictor (learned mode 3) at the largest training beam
+    pool = None
+    if args.pool_beam:
+        from paper_2203_13601_amd.learned import train_pool_network
+        pb = max(args.learned_beams)
+        t0 = time.time()
+        pparams, pinfo = train_pool_network(ix, tq, tqa, w.k, pb, epochs=max(args.epochs, 30), check_every=ce,
+                                            n_init=args.n_init, expand=args.expand, seed=3)
+        nhq.nhq_mlp_load(ix, pparams)
+        torch.cuda.synchronize()
+        ptrain_s = time.time() - t0
+        log("pool-size network at beam %d: %d samples in %.1fs (median target %.0f)" % (
+            pb, pinfo["samples"], ptrain_s, pinfo["pool_label_median"]))
+        pts = []
+        for cf in (0.75, 1.0, 1.25, 1.5, 2.0, 2.5, 3.0, 4.0):
+            p = h.point(ix, pb, learned=3, check_every=ce, cap_factor=cf)
+            p["cap_factor"] = cf
+            pts.append(p)
+            log("pool predictor beam %d factor %.2f recall %.4f hops %.1f ndc %.0f %.0f QPS" % (
+                pb, cf, p["recall"], p["hops"], p["ndc"], p["qps"]))
+            if p["recall"] >= target + 0.01 and len([q for q in pts if q["recall"] >= target]) >= 2:
+                break
+        pool = {"learned_mode": 3, "beam": pb, "train_samples": pinfo["samples"], "train_s": ptrain_s,
+                "median_pool_target": pinfo["pool_label_median"], "sweep": pts,
+                "qps_at_target_interp": qps_at_recall([p["cap_factor"] for p in pts], [p["recall"] for p in pts],
+                                                      [p["qps"] for p in pts], target),
+                "hops_at_target": _interp_at(pts, target, "hops"), "ndc_at_target": _interp_at(pts, target, "ndc")}
     out = {"metric": "hybrid QPS at Recall@10=0.95 on 1 GPU, learned stop vs fixed beam (10M x 96, Zipf)",
            "value": None if best["qps_at_target_interp"] is None else round(best["qps_at_target_interp"], 1),
            "unit": "queries/s", "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f32",
@@ -847,6 +982,7 @@ def learned10m(args):
            "learned_hops_at_target": best["hops_at_target"],
            "learned_speedup_vs_fixed": None if not (fa and best["qps_at_target_interp"]) else
            best["qps_at_target_interp"] / fa,
+           "fixed_ndc_at_target": _interp_at(fixed, target, "ndc"), "pool_predictor": pool,
            "fixed_sweep": fixed, "learned": runs}
     print(json.dumps(_r(out)), flush=True)
 
@@ -888,6 +1024,8 @@ def main():
     ap.add_argument("--rerank", type=int, default=4,
                     help="headline reduced forms: re-score the first min(rerank * k, beam) eligible entries in FP32")
     ap.add_argument("--learned-beams", type=int, nargs="+", default=[20, 24, 32])
+    ap.add_argument("--pool-beam", type=int, default=32,
+                    help="headline: beam of the beam-width predictor form (learned mode 3; 0 = skip)")
     ap.add_argument("--train-queries", type=int, default=None,
                     help="training queries of the stop network (20,000; 200,000 for learned10m)")
     ap.add_argument("--epochs", type=int, default=30)
