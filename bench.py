@@ -555,6 +555,24 @@ def mixed_selectivity(args, w, ix, ixb, tq):
     fa = qps_at_recall([p["beam"] for p in fixed], [p["recall"] for p in fixed], [p["qps"] for p in fixed], target)
     la = qps_at_recall([p["cap_factor"] for p in learned], [p["recall"] for p in learned],
                        [p["qps"] for p in learned], target)
+    # the same forms launched least selective first (nhq_query_order): the
+    # queries that need the most hops start first, so the batch's tail shrinks
+    order = nhq.nhq_query_order(ixb, hm.qa)
+    fixed_o = _sweep(hm, ixb, "mixed bf16 ordered", [16, 32, 48, 64, 96, 128, 160, 192, 256, 320, 384, 512], target,
+                     rerank=rr, order=order)
+    learned_o = []
+    for cf in (0.5, 0.75, 1.0, 1.25, 1.5, 2.0, 2.5, 3.0, 4.0):
+        p = hm.point(ixb, big, rerank=rr, learned=2, stop_threshold=0.9, check_every=ce, cap_factor=cf, order=order)
+        p["cap_factor"] = cf
+        learned_o.append(p)
+        log("mixed bf16+learned ordered beam %d cap %.2f recall %.4f hops %.1f %.0f QPS" % (
+            big, cf, p["recall"], p["hops"], p["qps"]))
+        if p["recall"] >= target + 0.01 and len([x for x in learned_o if x["recall"] >= target]) >= 2:
+            break
+    fao = qps_at_recall([p["beam"] for p in fixed_o], [p["recall"] for p in fixed_o], [p["qps"] for p in fixed_o],
+                        target)
+    lao = qps_at_recall([p["cap_factor"] for p in learned_o], [p["recall"] for p in learned_o],
+                        [p["qps"] for p in learned_o], target)
     # the beam-width predictor (learned mode 3): the network trained on pool
     # size targets chooses each query's pool size at its first checkpoint
     t0 = time.time()
@@ -575,6 +593,17 @@ def mixed_selectivity(args, w, ix, ixb, tq):
             break
     pa = qps_at_recall([p["cap_factor"] for p in pooled], [p["recall"] for p in pooled],
                        [p["qps"] for p in pooled], target)
+    pooled_o = []
+    for cf in (0.75, 1.0, 1.25, 1.5, 2.0, 2.5, 3.0, 4.0, 6.0):
+        p = hm.point(ixb, big, rerank=rr, learned=3, check_every=ce, cap_factor=cf, order=order)
+        p["cap_factor"] = cf
+        pooled_o.append(p)
+        log("mixed bf16+pool predictor ordered beam %d factor %.2f recall %.4f hops %.1f %.0f QPS" % (
+            big, cf, p["recall"], p["hops"], p["qps"]))
+        if p["recall"] >= target + 0.01 and len([x for x in pooled_o if x["recall"] >= target]) >= 2:
+            break
+    pao = qps_at_recall([p["cap_factor"] for p in pooled_o], [p["recall"] for p in pooled_o],
+                        [p["qps"] for p in pooled_o], target)
     nhq.nhq_mlp_load(ixb, params)
 
     def hops_at(pts, key):
@@ -597,7 +626,16 @@ def mixed_selectivity(args, w, ix, ixb, tq):
                               "hops_at_target": hops_at(pooled, "cap_factor"), "train_samples": pinfo["samples"],
                               "train_s": pool_s, "median_pool_target": pinfo["pool_label_median"],
                               "sweep": pooled},
+           "launched_least_selective_first": {
+               "order": "nhq_query_order: sum of ln(count / n) over the constrained codes, largest first",
+               "fixed_qps_at_target_interp": fao, "learned_qps_at_target_interp": lao,
+               "pool_predictor_qps_at_target_interp": pao,
+               "learned_speedup_vs_fixed": None if not (fao and lao) else lao / fao,
+               "pool_predictor_speedup_vs_fixed": None if not (fao and pao) else pao / fao,
+               "fixed_sweep": fixed_o, "learned_sweep": learned_o, "pool_predictor_sweep": pooled_o},
            "fixed_sweep": fixed, "learned_sweep": learned}
+    log("mixed selectivity, least selective first: fixed %s QPS, learned stop %s QPS, pool predictor %s QPS" % (
+        fao, lao, pao))
     log("mixed selectivity: fixed %s QPS, learned stop %s QPS, pool predictor %s QPS at Recall@10 %.2f "
         "(hops %s / %s / %s)" % (fa, la, pa, target, out["fixed_hops_at_target"], out["learned_hops_at_target"],
                                  out["pool_predictor"]["hops_at_target"]))

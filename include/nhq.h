@@ -248,6 +248,14 @@ typedef struct {
                             entry becomes unexpanded again and stage S2 (all
                             neighbours, Alg. 2) runs to the end.  0 or 1: off
                                                                           [0] */
+    const int32_t *order;/* nullable DEVICE int32 [nq]: launch order, the
+                            i-th wavefront searching query order[i] (results
+                            stay in query order and do not depend on it);
+                            nhq_query_order writes one that launches the
+                            least selective queries first.  An entry outside
+                            [0, nq) is skipped and sets NHQ_DEVERR_BADID;
+                            it must be a permutation for every query to be
+                            searched                                       [0] */
 } nhq_search_params;
 
 /* Device error word bits (accumulated per index; nhq_index_device_error). */
@@ -351,7 +359,7 @@ int nhq_hybrid_search(const nhq_index *ix, const float *queries, const uint8_t *
  * whole sample for every query by Gamma on the matrix cores and writes the
  * positions (in the entry sample) of the n_cand best, -1 padded, to cand:
  * device int32 [nq][n_cand], 1 <= n_cand <= 144.  Its scratch (about
- * nq * (4 d + 4.25 n_entry) bytes) lives in the index's workspace, which a
+ * nq * (8 d + 4.25 n_entry) bytes) lives in the index's workspace, which a
  * call that needs more than any call before it grows (that call synchronises
  * the device); nhq_hybrid_search keeps the candidates there too.
  *
@@ -359,15 +367,29 @@ int nhq_hybrid_search(const nhq_index *ix, const float *queries, const uint8_t *
  * re-scores them exactly, starts the pool with the best n_init of them and
  * runs the expansion loop.  nhq_hybrid_search passes n_cand = min(n_entry,
  * n_init + 8); the result then equals a search started from the best n_init
- * members of the whole entry sample unless the dense ranking (float32 GEMM
- * form of delta^2) misplaces one past the 8-entry margin (never when the
- * queries and the entry sample hold integers of magnitude <= 256 and rows
- * have at most 128 elements: then the ranking is exact). */
+ * members of the whole entry sample unless the dense ranking (the GEMM form
+ * of delta^2 on split-bf16 products, about 2^-17 relative error per term)
+ * misplaces one past the 8-entry margin (never when the queries and the
+ * entry sample hold values exact in bf16 whose partial sums stay exact in
+ * float32, such as integers of magnitude <= 256 in rows of at most 128
+ * elements: then the ranking is exact). */
 int nhq_seed_rank(const nhq_index *ix, const float *queries, const uint8_t *qattrs, int64_t nq,
                   int32_t n_cand, int32_t *cand, void *stream);
 int nhq_search_seeded(const nhq_index *ix, const float *queries, const uint8_t *qattrs, int64_t nq,
                       const int32_t *cand, int32_t n_cand, int32_t k, int32_t beam,
                       const nhq_search_params *sp, int32_t *ids, float *dists, void *stream);
+
+/* A launch order for nhq_search_params.order: the queries by decreasing
+ * selectivity fraction, least selective first, estimated from the object
+ * set's code frequencies as sum over the constrained attributes of
+ * ln(count(code) / n) (count 0 read as 0.5), in buckets of 1/16.  Queries
+ * that match more objects need more hops (fewer constrained attributes,
+ * frequent codes), so launching them first shortens the batch's tail, and
+ * queries of one attribute pattern run side by side.  The order is a
+ * scheduling choice only: results do not depend on it.  qattrs: device
+ * uint8 [nq][m]; order: device int32 [nq], a permutation of 0 .. nq - 1 on
+ * return.  Uses the index's workspace (see nhq_seed_rank). */
+int nhq_query_order(const nhq_index *ix, const uint8_t *qattrs, int64_t nq, int32_t *order, void *stream);
 
 /* Allocation-free nhq_hybrid_search, for callers that cannot allocate
  * device memory: code under HIP graph capture, tight serving loops,
@@ -379,7 +401,7 @@ int nhq_search_seeded(const nhq_index *ix, const float *queries, const uint8_t *
  * itself allocates and frees nothing (its first call on a device looks the
  * array's address up once).  The batch must fit: with ks = min(n_entry,
  * n_init + 8), dp the padded width and E = n_entry rounded up to 64, it
- * needs roundup256(4 nq ks) + 4 (nq dp + 5 nq + nq E 17 / 16 + 64) bytes;
+ * needs roundup256(4 nq ks) + 4 (2 nq dp + 5 nq + nq E 17 / 16 + 128) bytes;
  * larger batches fail with NHQ_EINVAL (split them), and an entry sample of
  * more than 8192 with NHQ_ENOTSUP.  Every call on a device shares that
  * device's array and leaves its contents behind (nothing in it needs to start

@@ -51,7 +51,7 @@ class SearchParams(ctypes.Structure):
                 ("stop_threshold", ctypes.c_float), ("check_every", ctypes.c_int32),
                 ("counters", ctypes.c_void_p), ("cap_factor", ctypes.c_float),
                 ("trace", ctypes.c_void_p), ("expand", ctypes.c_int32),
-                ("route_h", ctypes.c_int32)]
+                ("route_h", ctypes.c_int32), ("order", ctypes.c_void_p)]
 
 
 MLP_PARAMS = 4866
@@ -106,6 +106,7 @@ def lib() -> ctypes.CDLL:
         "nhq_hybrid_search_noalloc": ([P, P, P, i64, i32, i32, P, P, P, P], i32),
         "nhq_seed_rank": ([P, P, P, i64, i32, P, P], i32),
         "nhq_search_seeded": ([P, P, P, i64, P, i32, i32, i32, P, P, P, P], i32),
+        "nhq_query_order": ([P, P, i64, P, P], i32),
         "nhq_trace_samples": ([P, i64, P, P, P, P, P, P], i32),
         "nhq_mlp_grad": ([P, P, P, P, i64, ctypes.c_float, P, P, P, P], i32),
         "nhq_mlp_train": ([P, P, P, P, P, P, i64, i32, i32, ctypes.c_float, ctypes.c_float,
@@ -414,10 +415,11 @@ def nhq_hybrid_search(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, k:
                       check_every: int = 0, counters: bool = False, stream=None,
                       out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None,
                       cap_factor: float = 0.0, trace: Optional["TraceBuffers"] = None,
-                      expand: int = 1, route_h: int = 0):
+                      expand: int = 1, route_h: int = 0, order: Optional[torch.Tensor] = None):
     """Returns (ids int32 [nq,k], dists float32 [nq,k]) and, with
     counters=True, a uint32-valued int32 tensor [nq,2] of (NDC, H).
-    route_h >= 2 turns on two-stage routing (Sec. 4.2)."""
+    route_h >= 2 turns on two-stage routing (Sec. 4.2); order (int32 [nq]
+    permutation, see nhq_query_order) sets the launch order."""
     queries, qattrs = _query_inputs(ix, queries, qattrs)
     nq = queries.shape[0]
     ids, dists = _out_pair(ix, out, nq, int(k))
@@ -428,7 +430,7 @@ def nhq_hybrid_search(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, k:
                       int(learned), float(stop_threshold), int(check_every),
                       cnt.data_ptr() if cnt is not None else None, float(cap_factor),
                       ctypes.cast(ctypes.byref(trace.c), ctypes.c_void_p) if trace is not None else None,
-                      int(expand), int(route_h))
+                      int(expand), int(route_h), _order(ix, order, nq))
     _check(lib().nhq_hybrid_search(ix.handle, queries.data_ptr(), qattrs.data_ptr(), nq, int(k),
                                    int(beam), ctypes.byref(sp), ids.data_ptr(), dists.data_ptr(),
                                    _stream(stream)), "nhq_hybrid_search")
@@ -454,11 +456,39 @@ def nhq_hybrid_search_noalloc(ix: Index, queries: torch.Tensor, qattrs: torch.Te
     sp = SearchParams(int(n_init), int(kw.get("rerank", 0)), int(kw.get("output_mode", 0)),
                       int(kw.get("max_hops", 0)), int(kw.get("visited_log2", 0)), 0, 0.0, 0,
                       counters.data_ptr() if counters is not None else None, 0.0, None,
-                      int(kw.get("expand", 1)), int(kw.get("route_h", 0)))
+                      int(kw.get("expand", 1)), int(kw.get("route_h", 0)), _order(ix, kw.get("order"), nq))
     _check(lib().nhq_hybrid_search_noalloc(ix.handle, queries.data_ptr(), qattrs.data_ptr(), nq, int(k),
                                            int(beam), ctypes.byref(sp), ids.data_ptr(), dists.data_ptr(),
                                            _stream(stream)), "nhq_hybrid_search_noalloc")
     return ids, dists
+
+
+def _order(ix: Index, order: Optional[torch.Tensor], nq: int):
+    """The launch-order pointer for SearchParams (None: natural order)."""
+    if order is None:
+        return None
+    if (not isinstance(order, torch.Tensor) or order.dtype != torch.int32 or tuple(order.shape) != (nq,)
+            or not order.is_contiguous() or order.device != ix.device):
+        raise ValueError("order must be a contiguous int32 [%d] tensor on %s" % (nq, ix.device))
+    return order.data_ptr()
+
+
+def nhq_query_order(ix: Index, qattrs: torch.Tensor, stream=None) -> torch.Tensor:
+    """Launch order by decreasing selectivity fraction (least selective
+    queries first): an int32 [nq] permutation for the searches' `order`."""
+    if not isinstance(qattrs, torch.Tensor) or qattrs.dtype != torch.uint8 or qattrs.dim() != 2:
+        raise ValueError("qattrs must be a uint8 [nq][m] tensor")
+    _, m = ix.dims()
+    if qattrs.shape[1] != m:
+        raise ValueError("qattrs has %d attributes, the index %d" % (qattrs.shape[1], m))
+    if qattrs.device != ix.device:
+        raise ValueError("qattrs must be on the index's device %s" % ix.device)
+    qattrs = qattrs.contiguous()
+    nq = qattrs.shape[0]
+    order = torch.empty((nq,), dtype=torch.int32, device=ix.device)
+    _check(lib().nhq_query_order(ix.handle, qattrs.data_ptr(), nq, order.data_ptr(), _stream(stream)),
+           "nhq_query_order")
+    return order
 
 
 def nhq_seed_rank(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, n_cand: int,
@@ -484,7 +514,7 @@ def nhq_search_seeded(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, ca
                       stop_threshold: float = 0.0, check_every: int = 0, counters: bool = False,
                       stream=None, out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None,
                       cap_factor: float = 0.0, trace: Optional["TraceBuffers"] = None,
-                      expand: int = 1, route_h: int = 0):
+                      expand: int = 1, route_h: int = 0, order: Optional[torch.Tensor] = None):
     queries, qattrs = _query_inputs(ix, queries, qattrs)
     nq = queries.shape[0]
     if (not isinstance(cand, torch.Tensor) or cand.dtype != torch.int32 or cand.dim() != 2
@@ -501,7 +531,7 @@ def nhq_search_seeded(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, ca
                       int(learned), float(stop_threshold), int(check_every),
                       cnt.data_ptr() if cnt is not None else None, float(cap_factor),
                       ctypes.cast(ctypes.byref(trace.c), ctypes.c_void_p) if trace is not None else None,
-                      int(expand), int(route_h))
+                      int(expand), int(route_h), _order(ix, order, nq))
     _check(lib().nhq_search_seeded(ix.handle, queries.data_ptr(), qattrs.data_ptr(), nq,
                                    cand.data_ptr(), cand.shape[1], int(k), int(beam), ctypes.byref(sp),
                                    ids.data_ptr(), dists.data_ptr(), _stream(stream)),

@@ -913,6 +913,73 @@ void nhq_index_free(nhq_index *h)
 
 namespace {
 
+// ---- launch order by selectivity (nhq_query_order)
+constexpr int kOrderBuckets = 1024;  // buckets of 1/16 of -sum ln(count / n)
+
+__global__ void k_order_clear(int32_t *hist)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < kOrderBuckets)
+        hist[t] = 0;
+}
+
+// each query's bucket, and its position among the bucket's queries: counts
+// in an LDS histogram, then one global atomic per (workgroup, bucket)
+// reserves the workgroup's run of positions
+__global__ __launch_bounds__(256) void k_order_assign(const uint8_t *__restrict__ qa, int64_t nq, int m,
+                                                      const float *__restrict__ logp,
+                                                      int32_t *__restrict__ bucket, int32_t *__restrict__ pos,
+                                                      int32_t *__restrict__ hist)
+{
+    __shared__ int32_t lh[kOrderBuckets];
+    for (int t = threadIdx.x; t < kOrderBuckets; t += blockDim.x)
+        lh[t] = 0;
+    __syncthreads();
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = q < nq;
+    int b = 0, r = 0;
+    if (live) {
+        float ls = 0.0f;
+        for (int i = 0; i < m; ++i) {
+            const uint32_t c = qa[q * m + i];
+            if (c != 0xFFu)
+                ls += logp[i * 256 + c];
+        }
+        b = (int)fminf(fmaxf(-ls * 16.0f, 0.0f), (float)(kOrderBuckets - 1));
+        r = atomicAdd(&lh[b], 1);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kOrderBuckets; t += blockDim.x)
+        if (lh[t] > 0)
+            lh[t] = atomicAdd(&hist[t], lh[t]);
+    __syncthreads();
+    if (live) {
+        bucket[q] = b;
+        pos[q] = lh[b] + r;
+    }
+}
+
+// bucket starts (exclusive scan, one thread: 1,024 buckets)
+__global__ void k_order_scan(int32_t *hist)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        int32_t run = 0;
+        for (int b = 0; b < kOrderBuckets; ++b) {
+            const int32_t c = hist[b];
+            hist[b] = run;
+            run += c;
+        }
+    }
+}
+
+__global__ void k_order_place(const int32_t *__restrict__ bucket, const int32_t *__restrict__ pos,
+                              const int32_t *__restrict__ start, int64_t nq, int32_t *__restrict__ order)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nq)
+        order[start[bucket[q]] + pos[q]] = (int32_t)q;
+}
+
 // 32-bit words of the seed ranking's scratch: padded rows, norms, codes,
 // masks, exactness flags, split rows (each 2 dp bf16 halves, 256-byte
 // aligned) and (for the matrix-core ranking) the key matrix and its group
@@ -1114,8 +1181,37 @@ int nhq_search_seeded(const nhq_index *h, const float *queries, const uint8_t *q
     s.ids = ids;
     s.dists = dists;
     s.counters = p.counters;
+    s.order = p.order;
     s.stream = (hipStream_t)stream;
     return launch_search(s);
+}
+
+int nhq_query_order(const nhq_index *h, const uint8_t *qattrs, int64_t nq, int32_t *order, void *stream)
+{
+    if (!h)
+        return fail(NHQ_EINVAL, "null index");
+    Index *ix = const_cast<Index *>(&h->impl);
+    if (nq < 0 || nq > 0x7FFFFFFF)
+        return fail(NHQ_EINVAL, "need 0 <= nq < 2^31");
+    if (nq == 0)
+        return NHQ_OK;
+    if (!order || (ix->m > 0 && !qattrs))
+        return fail(NHQ_EINVAL, "null array argument");
+    // workspace: bucket counts (then starts) [1024], bucket [nq], position [nq]
+    int rc = ensure_workspace(ix, sizeof(int32_t) * ((size_t)kOrderBuckets + 2 * (size_t)nq));
+    if (rc != NHQ_OK)
+        return rc;
+    int32_t *hist = static_cast<int32_t *>(ix->ws);
+    int32_t *bucket = hist + kOrderBuckets;
+    int32_t *pos = bucket + nq;
+    hipStream_t st = (hipStream_t)stream;
+    const unsigned g = (unsigned)((nq + 255) / 256);
+    hipLaunchKernelGGL(k_order_clear, dim3(kOrderBuckets / 256), dim3(256), 0, st, hist);
+    hipLaunchKernelGGL(k_order_assign, dim3(g), dim3(256), 0, st, qattrs, nq, ix->m, ix->logp, bucket, pos, hist);
+    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, st, hist);
+    hipLaunchKernelGGL(k_order_place, dim3(g), dim3(256), 0, st, bucket, pos, hist, nq, order);
+    NHQ_HIP(hipGetLastError());
+    return NHQ_OK;
 }
 
 int nhq_hybrid_search(const nhq_index *h, const float *queries, const uint8_t *qattrs, int64_t nq,

@@ -144,6 +144,7 @@ struct SearchLaunch {
     int32_t *ids;
     float *dists;
     uint32_t *counters;
+    const int32_t *order;  // nullable launch order (wave i searches query order[i])
     hipStream_t stream;
 };
 int launch_search(const SearchLaunch &s);

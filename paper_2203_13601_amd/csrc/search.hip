@@ -24,9 +24,12 @@ template <int DP, int ST, bool CK>
 __device__ __forceinline__ void search_block(const SearchArgs &a)
 {
     extern __shared__ __align__(16) uint32_t smem[];
-    const int64_t qi = blockIdx.x;
-    if (qi >= a.nq)
+    const int64_t qi = a.order ? (int64_t)a.order[blockIdx.x] : (int64_t)blockIdx.x;
+    if (qi < 0 || qi >= a.nq) {
+        if (threadIdx.x == 0)
+            atomicOr(a.err, NHQ_DEVERR_BADID);
         return;
+    }
     QueryIO io;
     io.q = a.q + qi * (int64_t)a.d;
     pack_query_attrs(a.qa + qi * a.m, a.m, a.abits, io.qword, io.qmask);
@@ -110,6 +113,7 @@ int launch_search(const SearchLaunch &s)
     a.out_ids = s.ids;
     a.out_dist = s.dists;
     a.counters = s.counters;
+    a.order = s.order;
     a.err = ix->err;
     a.n = ix->n;
     a.nq = s.nq;

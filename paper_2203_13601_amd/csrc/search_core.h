@@ -53,6 +53,7 @@ struct SearchArgs {
     int32_t *trace_count; // [nq]
     uint32_t *final_hash; // [nq]
     int trace_cap;
+    const int32_t *order;  // nullable: wave i searches query order[i]
 };
 
 template <int DP>

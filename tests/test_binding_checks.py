@@ -77,3 +77,20 @@ def test_caller_outputs_are_checked(ix):
 def test_mlp_inputs_are_checked():
     with pytest.raises(ValueError):
         b._samples(torch.zeros((5, 7)), torch.zeros(5), torch.zeros(5), torch.device("cpu"))
+
+
+@pytest.mark.parametrize("bad", ["dtype", "length", "device", "strided"])
+def test_launch_order_is_checked(ix, bad):
+    # the launch order must be an int32 [nq] tensor on the index's device
+    order = {"dtype": torch.zeros(4, dtype=torch.int64), "length": torch.zeros(3, dtype=torch.int32),
+             "device": torch.zeros(4, dtype=torch.int32),
+             "strided": torch.zeros(8, dtype=torch.int32)[::2]}[bad]
+    with pytest.raises(ValueError):
+        b._order(ix, order, 4)
+
+
+def test_query_order_checks_its_codes(ix):
+    with pytest.raises(ValueError):
+        b.nhq_query_order(ix, torch.zeros((4, 2), dtype=torch.uint8))
+    with pytest.raises(ValueError):
+        b.nhq_query_order(ix, torch.zeros((4, 3), dtype=torch.float32))
