@@ -16,11 +16,12 @@
 // tie to within it.  Values exact in bf16 have lo = 0, and integer rows of
 // at most 128 elements keep every partial sum exact (k_entry_keys_b16 takes
 // those workgroups with one product per chunk).  A workgroup of 4 waves
-// takes 64 queries (16 per wave) against TL tiles of 64 entries; a tile's
-// split entry rows are staged in LDS a pass of 64 (or 32) elements at a
-// time, the next pass's loads in flight during the current pass's
-// products, and the weight setting is a template argument chosen once per
-// launch.
+// takes 64 or 128 queries (one or two sets of 16 per wave) against TL tiles
+// of 64 entries, on a grid remapped so that a query group's tiles share one
+// XCD's L2; a tile's split entry rows are staged in LDS a pass of 64 (or
+// 32, or the whole row up to 128) elements at a time, the next pass's loads
+// in flight during the current pass's products, and the weight setting is a
+// template argument chosen once per launch.
 //
 // The key kernels also write, per query, the minimum of every 16-entry group
 // of keys.  The K-th smallest group minimum bounds the K-th smallest key
@@ -51,10 +52,11 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 
-// 64-entry tiles per key workgroup, TL: 8 where the grid already has enough
-// workgroups (measured at d = 128 with 4,096 entries: 8 beats 1, 2, 4 and
-// 16); fewer for small grids (wide rows with a small entry sample), where
-// more workgroups in flight hide the staging latency of each tile
+// 64-entry tiles per key workgroup, TL: up to 8 where the grid already has
+// enough workgroups (the exact bf16 kernel at d = 128 with 4,096 entries: 8
+// beats 1, 2, 4 and 16); fewer for small grids (wide rows with a small entry
+// sample), where more workgroups in flight hide the staging latency of each
+// tile
 constexpr int kMaxKeyTiles = 8;
 // a wave's group minima of its chunk, 16 rows in LDS (padded row stride)
 template <int TL>
@@ -86,19 +88,32 @@ struct KeyArgs {
     const int32_t *seg = nullptr;
     const int32_t *block_off = nullptr;
     int n_blocks = 0, n_global = 0;
+    // nullable [nq]: rows with live[row] < 0 hold no query (a stratified
+    // block's padding slots); their keys and group minima are not written
+    const int32_t *live = nullptr;
 };
+
+// Bit r: row row0 + r of a wave's 16 rows holds a query (and is below nq).
+__device__ __forceinline__ uint32_t live_rows16(const KeyArgs &a, int64_t row0)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t row = row0 + (lane & 15);
+    const bool on = row < a.nq && (!a.live || a.live[row] >= 0);
+    return (uint32_t)(__ballot(on && lane < 16) & 0xFFFFull);
+}
 
 // the wave's group minima (16 rows, ng groups from group gbeg) to HBM, each
 // row's run of groups contiguous
 template <int TL>
-__device__ __forceinline__ void flush_gmin(const KeyArgs &a, const float *gm, int64_t row0, int gbeg, int ng)
+__device__ __forceinline__ void flush_gmin(const KeyArgs &a, const float *gm, int64_t row0, int gbeg, int ng,
+                                           uint32_t live16)
 {
     constexpr int kGmStride = GmStride<TL>::v;
     const int lane = threadIdx.x & 63;
     for (int i = lane; i < 16 * ng; i += 64) {
         const int r = i / ng, g = i - r * ng;
         const int64_t row = row0 + r;
-        if (row < a.nq)
+        if ((live16 >> r) & 1u)
             a.gmin[row * (a.ne_pad / 16) + gbeg + g] = gm[r * kGmStride + g];
     }
 }
@@ -178,7 +193,8 @@ __device__ __forceinline__ float pair_key(float d2, int c, int mq, float m1, con
 template <bool DEF, int TL>
 __device__ __forceinline__ void store_keys(const KeyArgs &a, const f32x4 (&acc)[4], int c0, int64_t row0, int rl,
                                            int lq, float rn, uint32_t qw, uint32_t qm, float mq, const float *ten,
-                                           const uint32_t *tea, float *stage, float *gm, int g0)
+                                           const uint32_t *tea, float *stage, float *gm, int g0,
+                                           uint32_t live16)
 {
     constexpr int kGmStride = GmStride<TL>::v;
     const int lane = threadIdx.x & 63;
@@ -210,7 +226,7 @@ __device__ __forceinline__ void store_keys(const KeyArgs &a, const f32x4 (&acc)[
         float mn = fminf(fminf(x.x, x.y), fminf(x.z, x.w));
         mn = fminf(mn, quad_mov<0xB1>(mn));  // quad_perm(1, 0, 3, 2)
         mn = fminf(mn, quad_mov<0x4E>(mn));  // quad_perm(2, 3, 0, 1)
-        if (row < a.nq)
+        if ((live16 >> r) & 1u)
             *reinterpret_cast<float4 *>(a.keys + row * a.ne_pad + c0 + 4 * c4) = x;
         if ((lane & 3) == 0)
             gm[r * kGmStride + g0 + (c4 >> 2)] = mn;
@@ -325,9 +341,10 @@ __global__ __launch_bounds__(256) void k_entry_keys_x3(const KeyArgs a0)
     const int64_t row0 = (int64_t)qgroup * 64 * QS + wave * 16 * QS;  // the wave's first row
     const u32x4 *qrow[QS];  // the lane's query rows, split, in 16-byte units
     float rn[QS], mq[QS];
-    uint32_t qw[QS], qm[QS];
+    uint32_t qw[QS], qm[QS], live16[QS];
 #pragma unroll
     for (int h = 0; h < QS; ++h) {
+        live16[h] = live_rows16(a, row0 + 16 * h);
         const int64_t row = row0 + 16 * h + rl;
         const int64_t rowc = row < a.nq ? row : a.nq - 1;
         qrow[h] = reinterpret_cast<const u32x4 *>(a.qs + rowc * 2 * DP);
@@ -424,20 +441,22 @@ __global__ __launch_bounds__(256) void k_entry_keys_x3(const KeyArgs a0)
         for (int h = 0; h < QS; ++h)
             store_keys<DEF, TL>(a, acc[h], c0, row0 + 16 * h, rl, lq, rn[h], qw[h], qm[h], mq[h], ten, tea,
                                 reinterpret_cast<float *>(tile) + wave * 16 * 68,
-                                gms + (wave * QS + h) * 16 * kGmStride, (c0 - cbeg) / 16);
+                                gms + (wave * QS + h) * 16 * kGmStride, (c0 - cbeg) / 16, live16[h]);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int h = 0; h < QS; ++h)
-        flush_gmin<TL>(a, gms + (wave * QS + h) * 16 * kGmStride, row0 + 16 * h, cbeg / 16, (cend - cbeg) / 16);
+        flush_gmin<TL>(a, gms + (wave * QS + h) * 16 * kGmStride, row0 + 16 * h, cbeg / 16, (cend - cbeg) / 16,
+                       live16[h]);
 }
 
 // The same product on the bf16 matrix cores (v_mfma_f32_16x16x32_bf16) for
 // workgroups whose queries are all integers of magnitude <= 256 against the
 // exact bf16 copy of the entry sample: every product is exact in float32 and
 // every partial sum is an integer below 2^24 (rows of at most 128
-// elements), so the keys are bit-identical to the float32 kernel's.
+// elements), so the keys are bit-identical to the split kernel's (whose lo
+// halves are zero on such data) and to the float32 definition.
 template <int DP, bool DEF, int TL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_entry_keys_b16(const KeyArgs a)
 {
@@ -458,7 +477,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     constexpr int NB = DP / 32;   // 32-element chunks
     constexpr int LDSB = DP + 8;  // row stride in LDS (elements)
     if (!group_exact<DP>(a, rowc))
-        return;  // left to the float32 kernel
+        return;  // left to the split kernel
+    const uint32_t live16 = live_rows16(a, (int64_t)blockIdx.x * 64 + wave * 16);
     bf16x8 qb[NB];
     {
         // query elements 32 t + 8 lq + 0..7, exact in bf16 (the top half of the float)
@@ -515,12 +535,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         __syncthreads();  // the tile's products are done: its LDS stages the keys
         store_keys<DEF, TL>(a, acc, c0, (int64_t)blockIdx.x * 64 + wave * 16, rl, lq, rn, qw, qm, mq, ten, tea,
                         reinterpret_cast<float *>(t16) + wave * 16 * 68, gms + wave * 16 * kGmStride,
-                        (c0 - cbeg) / 16);
+                        (c0 - cbeg) / 16, live16);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     flush_gmin<TL>(a, gms + wave * 16 * kGmStride, (int64_t)blockIdx.x * 64 + wave * 16, cbeg / 16,
-               (min(cbeg + 64 * kKeyTiles, a.ne_pad) - cbeg) / 16);
+               (min(cbeg + 64 * kKeyTiles, a.ne_pad) - cbeg) / 16, live16);
 }
 
 // One wave per query, K > 64: the row in registers, a radix select over it.
@@ -989,6 +1009,7 @@ int launch_strata_rank(const Index *ix, const uint16_t *qsplit, const float *qno
     a.block_off = ix->block_off;
     a.n_blocks = ix->n_blocks;
     a.n_global = ix->n_entry;
+    a.live = inv;
     int rc = launch_keys(ix, a, st);
     if (rc != NHQ_OK)
         return rc;
