@@ -70,6 +70,7 @@ __global__ __launch_bounds__(64) void k_nnd_round(const NndArgs a)
 #pragma unroll
     for (int c = 0; c < S::NCH; ++c)
         qv[c] = *reinterpret_cast<const float4 *>(qp + 4 * (g + S::G * c));
+    const QSrc<DP, 1, false> qsrc{qv, nullptr};
     const uint32_t qword = a.attr[i];
     const uint32_t qmask = attr_full_mask(a.m, a.abits);
     const int mq = a.m;
@@ -85,8 +86,8 @@ __global__ __launch_bounds__(64) void k_nnd_round(const NndArgs a)
     // score staged ids sid[0..nf) and merge them into the pool
     auto score_merge = [&](int nf) {
         wsync();
-        score_batch<DP, NHQ_STORAGE_FP32>(a.vec32, nullptr, qv, sid, skey, nf, mq, 1, a.w, a.attr,
-                                          qword, qmask, a.hmask);
+        score_batch<DP, NHQ_STORAGE_FP32, 1, Lay<DP, NHQ_STORAGE_FP32>::RB>(a.vec32, nullptr, qsrc, sid, skey, nf, mq,
+                                                                            1, a.w, a.attr, qword, qmask, a.hmask);
         wsync();
         if (a.w.mode != NHQ_WEIGHTS_DEFAULT)
             weigh_keys(skey, sid, nf, mq, a.w);

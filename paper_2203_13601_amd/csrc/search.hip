@@ -10,7 +10,8 @@
 // 16 above): lane g of a group holds 4-element chunks g, g+G, g+2G, ... so a
 // group's loads for one row are contiguous 16-, 8- or 4-byte pieces (fp32,
 // bf16, fp8 storage) and 64/G rows are scored per round.  Partial sums are
-// reduced inside the group with xor-shuffles.
+// reduced inside the group with DPP lane moves.  Rows of 512 elements and
+// more read the query from the wave's LDS copy instead of registers.
 //
 // Ordering key: Gamma = delta * (m_q + chi) / m_q is ordered through
 // key = delta^2 * (m_q + chi)^2 (delta^2 when m_q = 0), one float multiply of
@@ -32,6 +33,7 @@ __device__ __forceinline__ void search_block(const SearchArgs &a)
     }
     QueryIO io;
     io.q = a.q + qi * (int64_t)a.d;
+    io.qlds = nullptr;
     pack_query_attrs(a.qa + qi * a.m, a.m, a.abits, io.qword, io.qmask);
     io.seeds = a.seed_cand + (a.seeds_shared ? 0 : qi * a.n_seed);
     io.n_seed = a.n_seed;
@@ -52,8 +54,11 @@ __device__ __forceinline__ void search_block(const SearchArgs &a)
 #endif
 #define NHQ_CK_ATTR __attribute__((amdgpu_waves_per_eu(DP <= 128 ? NHQ_CK_WAVES : 1)))
 
+#ifndef NHQ_QL_WAVES
+#define NHQ_QL_WAVES 4
+#endif
 template <int DP, int ST>
-__global__ __launch_bounds__(64) void k_search(const SearchArgs a)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(Shape<DP>::QL ? NHQ_QL_WAVES : 1))) void k_search(const SearchArgs a)
 {
     search_block<DP, ST, false>(a);
 }
@@ -169,9 +174,10 @@ int launch_search(const SearchLaunch &s)
         a.vis_words = 1 << hb;
         a.hash_log2 = hb;
     }
-    // the checkpoint state exists only in the checkpointing kernel
+    // the checkpoint state exists only in the checkpointing kernel; wide
+    // rows keep the query row in LDS after it
     const size_t lds = sizeof(uint32_t) *
-                       ((size_t)ck_offset(a.L, a.scap, a.vis_words) + (a.ckpt > 0 ? kCkWords : 0));
+                       ((size_t)q_offset(a.L, a.scap, a.vis_words, a.ckpt > 0) + query_lds_words(ix->dp));
     if (s.nq > 0x7FFFFFFF)
         return fail(NHQ_EINVAL, "too many queries in one call");
     switch (ix->dp) {

@@ -62,6 +62,10 @@ struct Shape {
     static constexpr int NG = 64 / G;                      // rows per round
     static constexpr int NCH = DP / (4 * G);               // 4-element chunks per lane
     static constexpr int RB = NCH <= 4 ? 2 : 1;  // rounds in flight
+    // the query row is read from the wave's LDS copy rather than held in
+    // registers (4 NCH of them per lane) when rows are this wide: the freed
+    // registers hold more waves, and so more row gathers in flight
+    static constexpr bool QL = DP >= 512;
     static_assert(DP % (4 * G) == 0, "padded width must split into lane chunks");
 };
 
@@ -106,6 +110,28 @@ __device__ __forceinline__ int lane_chunk(int g, int c)
 {
     return K4 * (g + Shape<DP>::G * (c / K4)) + c % K4;
 }
+
+// The query slice a lane scores with, its c-th chunk at a time (lane g of a
+// row group, chunks in the order of lane_chunk<DP, K4>): held in registers
+// (v[c]) or, when QL, read from a zero-padded copy of the query row in LDS
+// (the row groups of a wave read the same addresses, which LDS broadcasts).
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) const f32x4v lds_f32x4;
+
+template <int DP, int K4, bool QL>
+struct QSrc {
+    const float4 *v;        // registers (QL false)
+    const lds_f32x4 *row;   // LDS, DP / 4 chunks (QL true)
+    __device__ __forceinline__ float4 at(int c, int g) const
+    {
+        if constexpr (QL) {
+            const f32x4v x = row[lane_chunk<DP, K4>(g, c)];
+            return make_float4(x.x, x.y, x.z, x.w);
+        } else {
+            return v[c];
+        }
+    }
+};
 
 __device__ __forceinline__ void wsync()
 {
@@ -184,9 +210,8 @@ __device__ __forceinline__ float group_sum(float v)
 // from the attribute word (fetched together with the row) and written into
 // the staged word; mode 2: delta^2.  RB rounds of rows are loaded before
 // any of them is scored.
-template <int DP, int ST, int K4 = Lay<DP, ST>::K4, int RB = Lay<DP, ST>::RB>
-__device__ __forceinline__ void score_batch(const void *vbase, const float *scale,
-                                            const float4 (&qv)[Shape<DP>::NCH],
+template <int DP, int ST, int K4, int RB, class Q>
+__device__ __forceinline__ void score_batch(const void *vbase, const float *scale, const Q &qv,
                                             uint32_t *sid, float *out, int nf, int mq,
                                             int mode, const Weights &wt,
                                             const uint32_t *attr = nullptr,
@@ -229,8 +254,9 @@ __device__ __forceinline__ void score_batch(const void *vbase, const float *scal
 #pragma unroll
                 for (int c = 0; c < S::NCH; ++c) {
                     const float4 x = decode<ST>(buf[rr][c], sc[rr]);
-                    const float t0 = qv[c].x - x.x, t1 = qv[c].y - x.y;
-                    const float t2 = qv[c].z - x.z, t3 = qv[c].w - x.w;
+                    const float4 qc = qv.at(c, g);
+                    const float t0 = qc.x - x.x, t1 = qc.y - x.y;
+                    const float t2 = qc.z - x.z, t3 = qc.w - x.w;
                     a0 = fmaf(t0, t0, a0);
                     a1 = fmaf(t1, t1, a1);
                     a0 = fmaf(t2, t2, a0);
@@ -461,10 +487,26 @@ __host__ __device__ inline int ck_offset(int L, int scap, int vis_words)
     return (2 * L + 2 * scap + vis_words + 3) & ~3;
 }
 
+// LDS word offset of the query row copy (widths with Shape<DP>::QL): after
+// the checkpoint state when there is one; DP words
+__host__ __device__ inline int q_offset(int L, int scap, int vis_words, bool ck)
+{
+    return ck_offset(L, scap, vis_words) + (ck ? kCkWords : 0);
+}
+
+// LDS words a search of padded width dp needs beyond the checkpoint state
+__host__ __device__ inline int query_lds_words(int dp)
+{
+    return dp >= 512 ? dp : 0;
+}
+
 // One query's inputs and outputs.  The query vector has d floats; `seeds`
 // holds n_seed entry-sample positions (-1 padded) in global memory or LDS.
 struct QueryIO {
     const float *q;
+    // nullable: the query row already in this wave's LDS, zero-padded to the
+    // padded width (else it is copied there when the width reads it from LDS)
+    const float *qlds;
     uint32_t qword, qmask;
     const int32_t *seeds;
     int n_seed;
@@ -483,7 +525,9 @@ __device__ __forceinline__ void pack_query_attrs(const uint8_t *qa, int m, int b
 
 // The search of one query by one wave (Alg. 2 in beam form), LDS at smem:
 // pool keys [L], pool words [L], staged keys [scap], staged words [scap],
-// visited set [vis_words], checkpoint state [kCkWords] at ck_offset.
+// visited set [vis_words], checkpoint state [kCkWords] at ck_offset (CK),
+// then for widths of 512 and more the query row [DP] at q_offset unless
+// io.qlds already holds it.
 template <int DP, int ST, bool CK>
 __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *smem)
 {
@@ -501,17 +545,32 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
     const bool bitset = a.use_bitset != 0;
     const int g = lane % S::G;
 
-    // query slice in registers, query attributes packed like the objects'
-    float4 qv[S::NCH];
-    const float *qp = io.q;
+    // query slice in registers, or the query row in LDS (wide rows);
+    // query attributes packed like the objects'
+    constexpr int K4 = Lay<DP, ST>::K4;
+    float4 qreg[S::QL ? 1 : S::NCH];
+    const lds_f32x4 *qrow = nullptr;
+    if constexpr (S::QL) {
+        const float *src = io.qlds;
+        if (src == nullptr) {
+            float *dst = reinterpret_cast<float *>(smem + q_offset(L, a.scap, a.vis_words, CK));
+            for (int c = lane; c < DP; c += 64)
+                dst[c] = c < a.d ? io.q[c] : 0.0f;
+            src = dst;
+        }
+        qrow = (const lds_f32x4 *)src;
+    } else {
+        const float *qp = io.q;
 #pragma unroll
-    for (int c = 0; c < S::NCH; ++c) {
-        const int e = 4 * lane_chunk<DP, Lay<DP, ST>::K4>(g, c);
-        qv[c].x = e + 0 < a.d ? qp[e + 0] : 0.0f;
-        qv[c].y = e + 1 < a.d ? qp[e + 1] : 0.0f;
-        qv[c].z = e + 2 < a.d ? qp[e + 2] : 0.0f;
-        qv[c].w = e + 3 < a.d ? qp[e + 3] : 0.0f;
+        for (int c = 0; c < S::NCH; ++c) {
+            const int e = 4 * lane_chunk<DP, K4>(g, c);
+            qreg[c].x = e + 0 < a.d ? qp[e + 0] : 0.0f;
+            qreg[c].y = e + 1 < a.d ? qp[e + 1] : 0.0f;
+            qreg[c].z = e + 2 < a.d ? qp[e + 2] : 0.0f;
+            qreg[c].w = e + 3 < a.d ? qp[e + 3] : 0.0f;
+        }
     }
+    const QSrc<DP, K4, S::QL> qv{qreg, qrow};
     const uint32_t qword = io.qword, qmask = io.qmask;
     const int mq = __popc(qmask) / a.abits;
     if (CK && a.ckpt > 0) {
@@ -549,7 +608,7 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
         if (ok)
             sid[lanes_below(vb)] = (uint32_t)v;
         wsync();
-        score_batch<DP, ST, Lay<DP, ST>::K4, RBS>(a.vecs, a.scale, qv, sid, skey, ne, mq, 1, a.w, a.attr, qword,
+        score_batch<DP, ST, K4, RBS>(a.vecs, a.scale, qv, sid, skey, ne, mq, 1, a.w, a.attr, qword,
                                                  qmask, a.hmask);
         wsync();
         if (a.w.mode != NHQ_WEIGHTS_DEFAULT)
@@ -814,7 +873,7 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
         }
         wsync();
         ndc += nf;
-        score_batch<DP, ST, Lay<DP, ST>::K4, RBS>(a.vecs, a.scale, qv, sid, skey, nf, mq, 1, a.w, a.attr, qword,
+        score_batch<DP, ST, K4, RBS>(a.vecs, a.scale, qv, sid, skey, nf, mq, 1, a.w, a.attr, qword,
                                                  qmask, a.hmask);
         wsync();
         if (a.w.mode != NHQ_WEIGHTS_DEFAULT)
@@ -893,7 +952,8 @@ __device__ void search_one(const SearchArgs &a, const QueryIO &io, uint32_t *sme
     got = min(got, want);
     wsync();
     // delta^2 from the float32 copy (identical to the loop's for fp32 storage)
-    score_batch<DP, NHQ_STORAGE_FP32, Lay<DP, ST>::K4>(a.vec32, nullptr, qv, sid, skey, got, mq, 2, a.w);
+    score_batch<DP, NHQ_STORAGE_FP32, K4, Lay<DP, NHQ_STORAGE_FP32>::RB>(a.vec32, nullptr, qv, sid, skey, got, mq,
+                                                                        2, a.w);
     wsync();
     // final order into LDS (the pool is no longer needed), then one store
     // per output slot

@@ -250,6 +250,7 @@ __global__ __launch_bounds__(64) void k_serve(const SearchArgs base, const Serve
         OutHead *o = reinterpret_cast<OutHead *>(s.outs + (size_t)slot * s.out_bytes);
         QueryIO io;
         io.q = qlds;
+        io.qlds = qlds;
         io.qword = qword;
         io.qmask = qmask;
         io.seeds = seedpos;
