@@ -197,9 +197,10 @@ __device__ __forceinline__ float row_mov(float v)
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
-// 16 lanes per query (4 queries per wave): zero-padded float32 row,
-// squared norm, packed codes and constraint mask, whether every value is an
-// integer of magnitude <= 256, and (qsplit non-null) the row's hi/lo split
+// 16 lanes per query (4 queries per wave): (qpad non-null) zero-padded
+// float32 row, squared norm, packed codes and constraint mask, whether every
+// value is an integer of magnitude <= 256, and (qsplit non-null) the row's
+// hi/lo split
 __global__ __launch_bounds__(64) void k_pad_queries(const float *__restrict__ q,
                                                     const uint8_t *__restrict__ qa, int64_t nq, int d,
                                                     int dp, int m, int abits, float *__restrict__ qpad,
@@ -237,9 +238,11 @@ __global__ __launch_bounds__(64) void k_pad_queries(const float *__restrict__ q,
                     for (int u = 0; u < 8; ++u)
                         v[u] = c0 + u < d ? q[i * d + c0 + u] : 0.0f;
                 }
-                float4 *dst = reinterpret_cast<float4 *>(qpad + i * dp + c0);
-                dst[0] = make_float4(v[0], v[1], v[2], v[3]);
-                dst[1] = make_float4(v[4], v[5], v[6], v[7]);
+                if (qpad) {
+                    float4 *dst = reinterpret_cast<float4 *>(qpad + i * dp + c0);
+                    dst[0] = make_float4(v[0], v[1], v[2], v[3]);
+                    dst[1] = make_float4(v[4], v[5], v[6], v[7]);
+                }
                 if (qsplit) {
                     uint32_t hw[4], lw[4];
 #pragma unroll
@@ -1021,9 +1024,11 @@ int seed_rank_at(const Index *cix, const float *queries, const uint8_t *qattrs, 
         reinterpret_cast<uint16_t *>((reinterpret_cast<uintptr_t>(qx + f_small) + 255) & ~uintptr_t(255));
     float *keys = reinterpret_cast<float *>(
         (reinterpret_cast<uintptr_t>(qs + 2 * f_rows) + 255) & ~uintptr_t(255));
-    // split rows only where the matrix-core ranking reads them
-    int rc = launch_pad_queries(queries, qattrs, nq, ix->d, ix->dp, ix->m, ix->abits, qpad, qnorm, qw, qm, qx,
-                                (ix->n_blocks > 0 || dense) ? qs : nullptr, st);
+    // split rows only where the matrix-core ranking reads them; padded
+    // float32 rows only for the exact bf16 kernel and the float32 tiles
+    const bool need_pad = ix->n_blocks == 0 && (!dense || (ix->entry_bf16 != nullptr && ix->dp <= 128));
+    int rc = launch_pad_queries(queries, qattrs, nq, ix->d, ix->dp, ix->m, ix->abits, need_pad ? qpad : nullptr,
+                                qnorm, qw, qm, qx, (ix->n_blocks > 0 || dense) ? qs : nullptr, st);
     if (rc == NHQ_OK) {
         if (ix->n_blocks > 0)
             rc = launch_strata_rank(ix, qs, qnorm, qw, qm, nq, n_cand, reinterpret_cast<uint32_t *>(keys),

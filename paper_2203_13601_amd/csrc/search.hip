@@ -54,11 +54,8 @@ __device__ __forceinline__ void search_block(const SearchArgs &a)
 #endif
 #define NHQ_CK_ATTR __attribute__((amdgpu_waves_per_eu(DP <= 128 ? NHQ_CK_WAVES : 1)))
 
-#ifndef NHQ_QL_WAVES
-#define NHQ_QL_WAVES 4
-#endif
 template <int DP, int ST>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(Shape<DP>::QL ? NHQ_QL_WAVES : 1))) void k_search(const SearchArgs a)
+__global__ __launch_bounds__(64) void k_search(const SearchArgs a)
 {
     search_block<DP, ST, false>(a);
 }
