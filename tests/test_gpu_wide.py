@@ -1,6 +1,8 @@
-"""Wide rows (the precision form's d = 960, and d = 1000 padded to 1024):
-the kernels' 16-lane row groups, the one-round-in-flight scoring and the
-wide matrix-core tiles, against the CPU oracle.
+"""Wide rows (the precision form's d = 960, d = 1000 padded to 1024, and
+d = 500 padded to 512, the narrowest width whose searches read the query row
+from LDS): the kernels' 16-lane row groups, the one-round-in-flight scoring,
+the LDS query row and the wide matrix-core tiles, in the batch search and the
+serving loop, against the CPU oracle.
 
 Float vectors: orders can differ from the FP64 oracle only at near-ties, so
 results must overlap and every returned distance must be Gamma of the
@@ -31,7 +33,7 @@ def test_graph_matches_oracle_d960():
     assert same.mean() >= 0.995, same.mean()
 
 
-@pytest.mark.parametrize("d", [960, 1000])
+@pytest.mark.parametrize("d", [500, 960, 1000])
 @pytest.mark.parametrize("storage", ["fp32", "bf16", "fp8"])
 def test_search_matches_oracle_wide(d, storage):
     w = synth.small(4000, d, 48, seed=92, n_centres=8, cards=(2, 3, 5))
@@ -77,3 +79,38 @@ def test_bruteforce_knn_d960():
         assert ok.all(), i
         fin = np.isfinite(og[i])
         assert np.allclose(gd[i][fin], og[i][fin], rtol=1e-5)
+
+
+@pytest.mark.parametrize("d,storage", [(500, "fp32"), (960, "bf16")])
+def test_serve_matches_oracle_wide(d, storage):
+    # the serving loop at widths that keep the query row in LDS: its own
+    # entry ranking, then the shared per-query search, against the oracle's
+    # search on the stored rows (FP32 re-score for bf16)
+    w = synth.small(4000, d, 48, seed=94, n_centres=8, cards=(2, 3, 5), wildcard_arity=True)
+    adj = synth.random_graph(w.n, 32, seed=6)
+    rr = 0 if storage == "fp32" else 4
+    xs = w.x if storage == "fp32" else oracle.from_bf16_bits(oracle.to_bf16_bits(w.x)).astype(np.float32)
+    ix = nhq.nhq_index_create(_dev(w.x), _dev(w.attrs), storage=storage, n_entry=256, seed=w.build_seed,
+                              degree=32)
+    nhq.nhq_index_set_graph(ix, _dev(adj))
+    n = w.nq
+    k = np.full(n, 10, np.int32)
+    beam = np.full(n, 64, np.int32)
+    with nhq.Server(ix, n_init=16, expand=4, rerank=rr, lifetime_s=60.0, ring=128, slots_small=32,
+                    beam_large=-1) as srv:
+        r = srv.run(w.q, w.qattrs, k, beam, synth.poisson_arrivals(n, 50_000.0, 7), timeout_s=30.0)
+    ids, dist = r["ids"][:, :10], r["dists"][:, :10]
+    entry = oracle.entry_points(w.build_seed, w.n, 256)
+    oi, og, _, _, _ = oracle.search(adj, xs, w.attrs, w.q, w.qattrs, 10, 64, entry, n_init=16,
+                                    rerank_n=10 * rr, xr=w.x if rr else None, expand=4)
+    assert_float_parity(ids, oi, w.x, w.attrs, w.q, w.qattrs)
+    for i in range(n):
+        mq = oracle.arity(w.qattrs[i])
+        for v, g in zip(ids[i], dist[i]):
+            if v < 0:
+                assert np.isinf(g)
+                continue
+            assert oracle.chi(w.qattrs[i], w.attrs[v]) == 0
+            want = oracle.gamma(oracle.delta(w.q[i], w.x[v]), 0, mq)
+            assert abs(g - want) <= 1e-4 * max(want, 1e-30), (i, v, g, want)
+    ix.free()
