@@ -412,6 +412,8 @@ __global__ __launch_bounds__(256) void k_entry_keys_x3(const KeyArgs a0)
                 }
 #pragma unroll
                 for (int h = 0; h < QS; ++h) {
+                    if (live16[h] == 0u)
+                        continue;  // a set of padding slots (wave-uniform)
                     const bf16x8 bh = __builtin_bit_cast(bf16x8, qb[cur][h][j][0]);
                     const bf16x8 bl = __builtin_bit_cast(bf16x8, qb[cur][h][j][1]);
 #pragma unroll
@@ -439,7 +441,8 @@ __global__ __launch_bounds__(256) void k_entry_keys_x3(const KeyArgs a0)
         __syncthreads();  // the tile's products are done: its LDS stages the keys
 #pragma unroll
         for (int h = 0; h < QS; ++h)
-            store_keys<DEF, TL>(a, acc[h], c0, row0 + 16 * h, rl, lq, rn[h], qw[h], qm[h], mq[h], ten, tea,
+            if (live16[h] != 0u)
+                store_keys<DEF, TL>(a, acc[h], c0, row0 + 16 * h, rl, lq, rn[h], qw[h], qm[h], mq[h], ten, tea,
                                 reinterpret_cast<float *>(tile) + wave * 16 * 68,
                                 gms + (wave * QS + h) * 16 * kGmStride, (c0 - cbeg) / 16, live16[h]);
     }
