@@ -21,7 +21,10 @@
 // supplies point (l % 16) at dims 16 t + 4 (l / 16) + j for k-step 4 t + j:
 // both operands use the same dimension order, so the contraction covers every
 // dimension once.  Survivors of the per-row threshold (the current K-th best)
-// are appended to a per-row LDS buffer that is re-ranked when it fills.
+// are appended to a per-row LDS buffer of K + 64 entries, which is re-ranked
+// after any 16-column sub-tile that could overflow it.  The buffers bound the
+// waves per CU: 64 entries of slack measured faster than 16 (more re-ranking)
+// and than 128 (fewer waves).
 #include "nhq_internal.h"
 
 namespace nhq {
@@ -220,11 +223,12 @@ __global__ __launch_bounds__(128) void k_dense_topk(const TopkArgs a)
             for (int s = 0; s < 4; ++s)
                 acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[s].w, rv.w, acc[s], 0, 0, 0);
         }
-        // epilogue: keys of this lane's 16 columns for its row
-        const float tk = thk[rl];
-        const uint32_t ti = thi[rl];
+        // epilogue: keys of this lane's 16 columns for its row, one 16-column
+        // sub-tile at a time (at most 16 appends per row each)
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
+            const float tk = thk[rl];
+            const uint32_t ti = thi[rl];
             const int64_t cb0 = c0 + 16 * s + 4 * lq;  // this lane's 4 columns
             const float nb4[4] = {nrm[s].x, nrm[s].y, nrm[s].z, nrm[s].w};
             const uint32_t at4[4] = {atr[s].x, atr[s].y, atr[s].z, atr[s].w};
@@ -247,15 +251,15 @@ __global__ __launch_bounds__(128) void k_dense_topk(const TopkArgs a)
                     bi[rl * cap + slot] = (uint32_t)col;
                 }
             }
-        }
-        wsync();
-        // re-rank the rows whose buffers could overflow on the next tile
-        const bool full_row = lane < kRowsPerWave && cnt[lane] > cap - 64;
-        uint64_t fb = __ballot(full_row);
-        while (fb) {
-            const int r = __ffsll((unsigned long long)fb) - 1;
-            fb &= fb - 1;
-            compact_row(bk, bi, cnt, thk, thi, r, cap, a.K);
+            wsync();
+            // re-rank the rows whose buffers could overflow on the next sub-tile
+            const bool full_row = lane < kRowsPerWave && cnt[lane] > cap - 16;
+            uint64_t fb = __ballot(full_row);
+            while (fb) {
+                const int r = __ffsll((unsigned long long)fb) - 1;
+                fb &= fb - 1;
+                compact_row(bk, bi, cnt, thk, thi, r, cap, a.K);
+            }
         }
     }
     // final ranking of every row and output
@@ -354,9 +358,9 @@ int launch_dense_topk(const float *A, const float *A_norm, const uint32_t *A_att
     a.nb = nb;
     a.m = m;
     a.K = K;
-    // a full tile (64 appends per row) of slack above the kept K, so a row is
-    // re-ranked only after at least 64 new survivors
-    a.cap = ((K + 128 + 15) / 16) * 16;
+    // slack above the kept K: at least one 16-column sub-tile (16 appends
+    // per row); a row is re-ranked once fewer than 16 free entries remain
+    a.cap = ((K + 64 + 15) / 16) * 16;
     a.mode = mode;
     a.abits = abits;
     a.hmask = attr_hmask(abits);
