@@ -56,6 +56,9 @@ struct SearchArgs {
     const int32_t *order;  // nullable: wave i searches query order[i]
 };
 
+// padded widths from which a search reads the query row from LDS
+constexpr int kQueryLdsMinDp = 512;
+
 template <int DP>
 struct Shape {
     static constexpr int G = DP <= 512 ? 8 : 16;           // lanes per row
@@ -65,7 +68,7 @@ struct Shape {
     // the query row is read from the wave's LDS copy rather than held in
     // registers (4 NCH of them per lane) when rows are this wide: the freed
     // registers hold more waves, and so more row gathers in flight
-    static constexpr bool QL = DP >= 512;
+    static constexpr bool QL = DP >= kQueryLdsMinDp;
     static_assert(DP % (4 * G) == 0, "padded width must split into lane chunks");
 };
 
@@ -497,7 +500,7 @@ __host__ __device__ inline int q_offset(int L, int scap, int vis_words, bool ck)
 // LDS words a search of padded width dp needs beyond the checkpoint state
 __host__ __device__ inline int query_lds_words(int dp)
 {
-    return dp >= 512 ? dp : 0;
+    return dp >= kQueryLdsMinDp ? dp : 0;
 }
 
 // One query's inputs and outputs.  The query vector has d floats; `seeds`
