@@ -12,7 +12,13 @@ computed from FP64 distances recomputed from the vectors.
 One timed "step" is one full pass of the hot path over the 10,000 queries:
 seed ranking of the entry sample (matrix cores) plus the joint-pruning
 search (one wavefront per query), with the exact float32 re-score of the
-final candidates in the precision forms.
+final candidates in the precision forms.  Two batches are kept in flight:
+step i runs on stream i % 2 with its own candidates, outputs and ranking
+scratch (nhq_seed_rank_ws), so one batch's ranking and search use the
+compute units that the other batch's last queries leave idle.  QPS is the
+wall clock over the timed steps; the kernels' own durations (for the
+roofline) come from a second pass of the same steps one after another on
+one stream with HIP events around each stage.
 
 1. FP32, fixed beam: a beam sweep; QPS at Recall@10 = 0.95 is interpolated
    (log QPS linear in recall between the bracketing beams).
@@ -120,10 +126,37 @@ class Harness:
         self.cand = torch.empty((self.nq, self.n_cand), dtype=torch.int32, device=dev)
         self.ids = torch.empty((self.nq, self.k), dtype=torch.int32, device=dev)
         self.dists = torch.empty((self.nq, self.k), dtype=torch.float32, device=dev)
+        # two batches in flight: step i runs on stream i % 2 with its own
+        # candidates, outputs and seed-ranking scratch (stream 1 brings its
+        # own workspace, stream 0 uses the index's), so one batch's ranking
+        # and search fill the device while the other's last queries finish
+        self.streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+        self.cand1 = torch.empty_like(self.cand)
+        self.ids1 = torch.empty_like(self.ids)
+        self.dists1 = torch.empty_like(self.dists)
+        self._ws = {}
         self.gt = None
 
-    def step(self, index, beam, counters=False, ev=None, **kw):
-        nhq = self.nhq
+    def _workspace(self, index):
+        key = id(index)
+        if key not in self._ws:
+            b = self.nhq.nhq_seed_rank_workspace_size(index, self.nq, self.n_cand)
+            self._ws[key] = (index, self.torch.empty(b, dtype=self.torch.uint8, device=self.dev))
+        return self._ws[key][1]
+
+    def step(self, index, beam, counters=False, ev=None, j=None, **kw):
+        """one batch: seed ranking, then the search; j None on the current
+        stream, else on stream j of the two kept in flight"""
+        nhq, torch = self.nhq, self.torch
+        if j is not None:
+            s = self.streams[j]
+            cand, out = (self.cand, (self.ids, self.dists)) if j == 0 else (self.cand1, (self.ids1, self.dists1))
+            ws = None if j == 0 else self._workspace(index)
+            with torch.cuda.stream(s):
+                nhq.nhq_seed_rank(index, self.q, self.qa, self.n_cand, out=cand, stream=s, workspace=ws)
+                nhq.nhq_search_seeded(index, self.q, self.qa, cand, self.k, beam, n_init=self.args.n_init,
+                                      out=out, expand=self.args.expand, stream=s, **kw)
+            return None
         if ev is not None:
             ev[0].record()
         nhq.nhq_seed_rank(index, self.q, self.qa, self.n_cand, out=self.cand)
@@ -136,15 +169,17 @@ class Harness:
         return r
 
     def timed(self, index, beam, reps, **kw):
-        """wall clock over `reps` steps with nothing else on the stream, then
-        the same number of steps with HIP events around each stage (event
-        records are stream packets of their own, so they stay out of the
-        wall-clock loop)"""
+        """wall clock over `reps` steps, two batches in flight (steps
+        alternate between two streams), then the same number of steps one
+        after another on one stream with HIP events around each stage, which
+        give the kernels' own durations (event records are stream packets of
+        their own, so they stay out of the wall-clock loop)"""
         torch = self.torch
+        self._workspace(index)
         torch.cuda.synchronize()
         t = time.time()
-        for _ in range(reps):
-            self.step(index, beam, **kw)
+        for i in range(reps):
+            self.step(index, beam, j=i % 2, **kw)
         torch.cuda.synchronize()
         wall = time.time() - t
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
@@ -174,8 +209,8 @@ class Harness:
                 "rank_ms": float(np.median(rk)), "search_ms": float(np.median(se))}
 
     def run_form(self, index, beam, steps, warmup, **kw):
-        for _ in range(warmup):
-            self.step(index, beam, **kw)
+        for i in range(max(warmup, 2)):
+            self.step(index, beam, j=i % 2, **kw)
         wall, rank_ms, search_ms = self.timed(index, beam, steps, **kw)
         return {"qps": self.nq * steps / wall, "ms_per_step": wall * 1000.0 / steps,
                 "rank_kernels_avg_ms": float(np.mean(rank_ms)), "search_kernel_avg_ms": float(np.mean(search_ms)),
@@ -503,7 +538,7 @@ def headline(args):
                    "degree": w.degree, "cand": w.cand, "builder": args.builder, "n_entry": args.n_entry,
                    "n_init": args.n_init, "expand": args.expand, "build_s": round(build_s, 3),
                    "exact_knn_s": round(gt_s, 3), "recall": "FP64 distances recomputed from the vectors",
-                   "parallelism": "single GPU"},
+                   "batches_in_flight": 2, "parallelism": "single GPU"},
         "p99_ms": None if serving is None else serving["p99_ms"],
         "forms": _r({kk: {k2: v2 for k2, v2 in f.items()} for kk, f in forms.items()}),
         "mixed_selectivity": mixed,
@@ -914,7 +949,8 @@ def plain(args):
                       "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
                       "config": {"workload": w.name, "n": w.n, "d": w.d, "queries_per_step": h.nq, "k": w.k,
                                  "beam": vf["beam"], "n_entry": args.n_entry, "n_init": args.n_init,
-                                 "expand": args.expand, "build_s": round(build_s, 3), "parallelism": "single GPU"},
+                                 "expand": args.expand, "build_s": round(build_s, 3), "batches_in_flight": 2,
+                                 "parallelism": "single GPU"},
                       "forms": _r(forms), "roofline": roof, "cpu_baseline": cpu}), flush=True)
 
 
@@ -1037,7 +1073,8 @@ def learned10m(args):
            "config": {"workload": w.name, "n": w.n, "d": w.d, "cards": list(w.cards), "queries": w.nq,
                       "train_queries": int(tq.shape[0]), "k": w.k, "n_entry": args.n_entry,
                       "entry_per_pattern": args.entry_per_pattern, "n_init": args.n_init, "expand": args.expand,
-                      "builder": "nndescent", "build_s": round(build_s, 2), "storage": "fp32"},
+                      "builder": "nndescent", "build_s": round(build_s, 2), "storage": "fp32",
+                      "batches_in_flight": 2},
            "fixed_qps_at_target_interp": fa, "fixed_hops_at_target": _interp_at(fixed, target, "hops"),
            "learned_qps_at_target_interp": best["qps_at_target_interp"],
            "learned_hops_at_target": best["hops_at_target"],

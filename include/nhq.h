@@ -375,6 +375,20 @@ int nhq_hybrid_search(const nhq_index *ix, const float *queries, const uint8_t *
  * elements: then the ranking is exact). */
 int nhq_seed_rank(const nhq_index *ix, const float *queries, const uint8_t *qattrs, int64_t nq,
                   int32_t n_cand, int32_t *cand, void *stream);
+
+/* nhq_seed_rank with the caller's scratch in place of the index's
+ * workspace (same ranking, bit-identical candidates): workspace is device
+ * memory on the index's device, 256-byte aligned, of at least the
+ * workspace_size bytes for the same nq and n_cand (host size_t *bytes; the
+ * size depends on the index's padded width and entry sample), owned by the
+ * caller.  The call only reads the index, so calls with different
+ * workspaces may run at the same time on different streams: that keeps
+ * several batches in flight, and each batch's seed ranking and search fill
+ * the device while another batch's last queries finish.  NHQ_EINVAL for a
+ * null, misaligned or short workspace, else as nhq_seed_rank. */
+int nhq_seed_rank_workspace_size(const nhq_index *ix, int64_t nq, int32_t n_cand, size_t *bytes);
+int nhq_seed_rank_ws(const nhq_index *ix, const float *queries, const uint8_t *qattrs, int64_t nq,
+                     int32_t n_cand, int32_t *cand, void *workspace, size_t workspace_bytes, void *stream);
 int nhq_search_seeded(const nhq_index *ix, const float *queries, const uint8_t *qattrs, int64_t nq,
                       const int32_t *cand, int32_t n_cand, int32_t k, int32_t beam,
                       const nhq_search_params *sp, int32_t *ids, float *dists, void *stream);

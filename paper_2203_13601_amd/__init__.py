@@ -9,7 +9,8 @@ from ._binding import (BuildParams, Index, NHQError, SearchParams, lib,  # noqa:
                        nhq_bruteforce_hybrid_knn, nhq_build_index, nhq_hybrid_search,
                        nhq_index_build_graph, nhq_index_create, nhq_index_device_error,
                        nhq_index_get_entry, nhq_index_get_graph, nhq_index_get_storage, nhq_index_info,
-                       nhq_index_set_graph, nhq_search_seeded, nhq_seed_rank, DEVERR_BADID, DEVERR_HOPCAP, STORAGE,
+                       nhq_index_set_graph, nhq_search_seeded, nhq_seed_rank, nhq_seed_rank_workspace_size,
+                       DEVERR_BADID, DEVERR_HOPCAP, STORAGE,
                        MLP_PARAMS, TraceBuffers, nhq_mlp_eval, nhq_mlp_grad, nhq_mlp_load, nhq_mlp_train,
                        nhq_trace_samples, Server, ServerParams, nhq_server_create, SERVE_RAW, nhq_gather_probe,
                        nhq_nndescent_lists, nhq_index_build_report, WEIGHTS, BUILDERS,

@@ -105,6 +105,8 @@ def lib() -> ctypes.CDLL:
         "nhq_bruteforce_hybrid_knn": ([P, P, P, i64, i32, P, P, P], i32),
         "nhq_hybrid_search_noalloc": ([P, P, P, i64, i32, i32, P, P, P, P], i32),
         "nhq_seed_rank": ([P, P, P, i64, i32, P, P], i32),
+        "nhq_seed_rank_workspace_size": ([P, i64, i32, P], i32),
+        "nhq_seed_rank_ws": ([P, P, P, i64, i32, P, P, ctypes.c_size_t, P], i32),
         "nhq_search_seeded": ([P, P, P, i64, P, i32, i32, i32, P, P, P, P], i32),
         "nhq_query_order": ([P, P, i64, P, P], i32),
         "nhq_trace_samples": ([P, i64, P, P, P, P, P, P], i32),
@@ -491,8 +493,21 @@ def nhq_query_order(ix: Index, qattrs: torch.Tensor, stream=None) -> torch.Tenso
     return order
 
 
+def nhq_seed_rank_workspace_size(ix: Index, nq: int, n_cand: int) -> int:
+    """Bytes of device scratch nhq_seed_rank(..., workspace=) needs."""
+    b = ctypes.c_size_t()
+    _check(lib().nhq_seed_rank_workspace_size(ix.handle, int(nq), int(n_cand), ctypes.byref(b)),
+           "nhq_seed_rank_workspace_size")
+    return int(b.value)
+
+
 def nhq_seed_rank(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, n_cand: int,
-                  stream=None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+                  stream=None, out: Optional[torch.Tensor] = None,
+                  workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Seed candidates [nq][n_cand]; with `workspace` (a contiguous uint8
+    device tensor of at least nhq_seed_rank_workspace_size bytes, 256-byte
+    aligned) the ranking's scratch is the caller's, so calls with different
+    workspaces may run concurrently on different streams."""
     queries, qattrs = _query_inputs(ix, queries, qattrs)
     nq = queries.shape[0]
     if out is None:
@@ -503,8 +518,16 @@ def nhq_seed_rank(ix: Index, queries: torch.Tensor, qattrs: torch.Tensor, n_cand
                 or tuple(cand.shape) != (nq, int(n_cand)) or not cand.is_contiguous()
                 or cand.device != ix.device):
             raise ValueError("out must be a contiguous int32 [%d][%d] tensor on %s" % (nq, n_cand, ix.device))
-    _check(lib().nhq_seed_rank(ix.handle, queries.data_ptr(), qattrs.data_ptr(), nq, int(n_cand),
-                               cand.data_ptr(), _stream(stream)), "nhq_seed_rank")
+    if workspace is None:
+        _check(lib().nhq_seed_rank(ix.handle, queries.data_ptr(), qattrs.data_ptr(), nq, int(n_cand),
+                                   cand.data_ptr(), _stream(stream)), "nhq_seed_rank")
+        return cand
+    if (not isinstance(workspace, torch.Tensor) or workspace.dtype != torch.uint8
+            or not workspace.is_contiguous() or workspace.device != ix.device):
+        raise ValueError("workspace must be a contiguous uint8 tensor on %s" % ix.device)
+    _check(lib().nhq_seed_rank_ws(ix.handle, queries.data_ptr(), qattrs.data_ptr(), nq, int(n_cand),
+                                  cand.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream(stream)),
+           "nhq_seed_rank_ws")
     return cand
 
 

@@ -1105,6 +1105,33 @@ int nhq_seed_rank(const nhq_index *h, const float *queries, const uint8_t *qattr
     return seed_rank_ws(h, queries, qattrs, nq, n_cand, cand, stream, 0);
 }
 
+int nhq_seed_rank_workspace_size(const nhq_index *h, int64_t nq, int32_t n_cand, size_t *bytes)
+{
+    if (!h || !bytes)
+        return fail(NHQ_EINVAL, "null argument");
+    if (nq < 0 || n_cand < 1 || n_cand > 144)
+        return fail(NHQ_EINVAL, "need nq >= 0 and 1 <= n_cand <= 144");
+    *bytes = sizeof(uint32_t) * seed_rank_words(&h->impl, nq, n_cand);
+    return NHQ_OK;
+}
+
+int nhq_seed_rank_ws(const nhq_index *h, const float *queries, const uint8_t *qattrs, int64_t nq,
+                     int32_t n_cand, int32_t *cand, void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (!h)
+        return fail(NHQ_EINVAL, "null index");
+    const Index *ix = &h->impl;
+    int rc = check_seed_rank_args(ix, queries, qattrs, nq, n_cand, cand);
+    if (rc != NHQ_OK || nq == 0)
+        return rc;
+    const size_t need = sizeof(uint32_t) * seed_rank_words(ix, nq, n_cand);
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255u) != 0 || workspace_bytes < need)
+        return fail(NHQ_EINVAL, "workspace: need 256-byte aligned device memory of " + std::to_string(need) +
+                                    " bytes (nhq_seed_rank_workspace_size)");
+    return seed_rank_at(ix, queries, qattrs, nq, n_cand, cand, (hipStream_t)stream,
+                        static_cast<uint32_t *>(workspace));
+}
+
 int nhq_search_seeded(const nhq_index *h, const float *queries, const uint8_t *qattrs, int64_t nq,
                       const int32_t *cand, int32_t n_cand, int32_t k, int32_t beam,
                       const nhq_search_params *sp, int32_t *ids, float *dists, void *stream)
