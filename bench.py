@@ -1122,7 +1122,7 @@ def main():
     ap.add_argument("--check-every", type=int, default=1)
     ap.add_argument("--rerank", type=int, default=4,
                     help="headline reduced forms: re-score the first min(rerank * k, beam) eligible entries in FP32")
-    ap.add_argument("--learned-beams", type=int, nargs="+", default=[20, 24, 32])
+    ap.add_argument("--learned-beams", type=int, nargs="+", default=[18, 20, 24, 32])
     ap.add_argument("--pool-beam", type=int, default=32,
                     help="headline: beam of the beam-width predictor form (learned mode 3; 0 = skip)")
     ap.add_argument("--train-queries", type=int, default=None,
