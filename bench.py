@@ -200,7 +200,8 @@ class Harness:
         ids = self.ids.cpu().numpy()
         rec = self.recall(ids)
         cnt = cnt.cpu().numpy().astype(np.float64)
-        self.step(index, beam, **kw)
+        for j in (0, 1):
+            self.step(index, beam, j=j, **kw)
         wall, rk, se = self.timed(index, beam, 3, **kw)
         return {"beam": beam, "recall": float(rec.mean()), "qps": self.nq * 3 / wall,
                 "ndc": float(cnt[:, 0].mean()), "hops": float(cnt[:, 1].mean()),
