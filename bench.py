@@ -449,8 +449,9 @@ def headline(args):
     kernel = "k_search_ck" if value_form == "bf16_learned" else "k_search"
     traffic = None
     if args.n == 1_000_000 and args.nq == 10_000:
-        traffic = _profiled_traffic(kernel, SEARCH_SOURCES, "_n1M_d960_bf16_%s" % (
-            "learned" if value_form == "bf16_learned" else "fixed"))
+        # the summary of the same launch: form and beam in its name
+        traffic = _profiled_traffic(kernel, SEARCH_SOURCES, "_n1M_d960_bf16_%s_beam%d" % (
+            "learned" if value_form == "bf16_learned" else "fixed", vf["beam"]))
     step_bytes = bq * h.nq + h.nq * (4.0 * w.d + 8.0 * h.n_cand)  # + the seed stage's query reads and candidates
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
