@@ -443,8 +443,8 @@ __global__ __launch_bounds__(256) void k_entry_keys_x3(const KeyArgs a0)
         for (int h = 0; h < QS; ++h)
             if (live16[h] != 0u)
                 store_keys<DEF, TL>(a, acc[h], c0, row0 + 16 * h, rl, lq, rn[h], qw[h], qm[h], mq[h], ten, tea,
-                                reinterpret_cast<float *>(tile) + wave * 16 * 68,
-                                gms + (wave * QS + h) * 16 * kGmStride, (c0 - cbeg) / 16, live16[h]);
+                                    reinterpret_cast<float *>(tile) + wave * 16 * 68,
+                                    gms + (wave * QS + h) * 16 * kGmStride, (c0 - cbeg) / 16, live16[h]);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
