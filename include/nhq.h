@@ -484,10 +484,14 @@ int nhq_mlp_eval(const nhq_index *ix, const float *X, int64_t n, float *Z, void 
 /* ---------------------------------------------------------------- serving
  *
  * Continuous batching of hybrid queries (Def. 4, answered as by
- * nhq_hybrid_search): a server keeps one persistent kernel per memory class
- * resident on the device.  A class is the largest beam its slots hold and
- * fixes each slot's LDS (pool, staging, visited set, entry-sample keys); a
- * slot is one wavefront serving one request at a time.  Requests go to the
+ * nhq_hybrid_search): a server keeps one persistent kernel resident on the
+ * device, whose slots belong to one or two memory classes.  A class is the
+ * largest beam its slots hold and fixes the LDS its requests use (pool,
+ * staging, visited set, entry-sample keys); every slot of the launch holds
+ * the largest class's LDS.  A slot is one wavefront serving one request at a
+ * time.  (One launch keeps the classes running side by side: persistent
+ * launches on separate streams may share a hardware queue and then run one
+ * after the other.)  Requests go to the
  * smallest class whose beam covers theirs ("admission by memory") and are
  * taken by the next free slot of that class as soon as they are published,
  * while the other slots keep working: requests that arrive while others run
@@ -501,11 +505,11 @@ int nhq_mlp_eval(const nhq_index *ix, const float *X, int64_t n, float *Z, void 
  * bit-identical ids, distances and counters alone or in any mix.
  *
  * The server reads the index (which must outlive it and stay unchanged) and
- * the kernels hold their slots until nhq_server_free.  While a server runs,
+ * the kernel holds its slots until nhq_server_free.  While a server runs,
  * do not synchronise the whole device (hipDeviceSynchronize waits for the
- * persistent kernels); synchronise streams instead.  Every kernel wait is
- * bounded by the stop flag and by lifetime_s, after which the kernels end
- * by themselves and later submits fail with NHQ_EDEVICE.  The server calls
+ * persistent kernel); synchronise streams instead.  Every kernel wait is
+ * bounded by the stop flag and by lifetime_s, after which the kernel ends
+ * by itself and later submits fail with NHQ_EDEVICE.  The server calls
  * are not thread-safe: one host thread drives a server. */
 typedef struct nhq_server nhq_server;
 
@@ -533,19 +537,19 @@ typedef struct {
     int32_t learned_mode;/* learned requests: 1, 2 or 3 (as
                             nhq_search_params.learned)                       [1] */
     int32_t reserved1;
-    double lifetime_s;   /* the kernels end by themselves after this long  [600] */
+    double lifetime_s;   /* the kernel ends by itself after this long      [600] */
 } nhq_server_params;
 
 #define NHQ_SERVE_RAW 1 /* request flag: output_mode 1 (first k by Gamma) */
 #define NHQ_PENDING 1   /* nhq_server_poll: the request has not finished */
 
-/* Start a server on the index's device (launches the kernels; synchronises
+/* Start a server on the index's device (launches the kernel; synchronises
  * the device once before launching). */
 int nhq_server_create(nhq_index *ix, const nhq_server_params *params, nhq_server **out);
 
 /* Per class (host arrays of 2; class 1 reads 0 slots when absent): slots,
- * LDS bytes per slot, largest beam; tick_hz: rate of the device wall clock
- * that nhq_server_poll's ticks count. */
+ * LDS bytes a request of the class uses, largest beam; tick_hz: rate of the
+ * device wall clock that nhq_server_poll's ticks count. */
 int nhq_server_info(const nhq_server *s, int32_t *slots, int32_t *lds_bytes, int32_t *beam_max,
                     double *tick_hz);
 

@@ -2,11 +2,13 @@
 // joint pruning (Alg. 2) from a stream of requests, each with its own k,
 // beam and constrained attributes.
 //
-// One persistent kernel per memory class (a class is the largest beam its
-// slots hold; its LDS per slot is sized for that beam).  Workgroup 0 is the
-// doorbell: it reads the host ring's tail (pinned host memory) and marks the
+// One persistent launch serves every memory class (a class is the largest
+// beam its slots hold; a request goes to the smallest class that holds its
+// beam, and each class has its own ring).  Workgroup c < ncls is class c's
+// doorbell: it reads the class ring's tail (pinned host memory) and marks the
 // newly published ring entries ready in device memory.  Every other
-// workgroup is one wavefront, one slot: it takes the next request index
+// workgroup is one wavefront, one slot of a class: it takes the next request
+// index
 // (device atomic), waits until that entry is ready, reads the request from
 // the host ring, ranks the entry sample for the query itself, runs the same
 // per-query search as the batch kernel, writes the results into the host
@@ -151,16 +153,30 @@ __device__ void entry_keys_wave(const float *ev, const uint32_t *ea, int ne, con
     }
 }
 
+// The classes of one server in one launch: workgroups 0 .. ncls - 1 are
+// their doorbells, then come class 0's slots0 slots and class 1's.  Two
+// persistent launches on two streams could share a hardware queue, and then
+// the second would wait for the first to end; one launch keeps every class
+// running side by side.  The launch's LDS per workgroup is the largest
+// class's.
+struct ServeLaunch {
+    ServeArgs c[2];
+    int ncls, slots0;
+};
+
 template <int DP, int ST>
-__global__ __launch_bounds__(64) void k_serve(const SearchArgs base, const ServeArgs s)
+__global__ __launch_bounds__(64) void k_serve(const SearchArgs base, const ServeLaunch L)
 {
     extern __shared__ __align__(16) uint32_t smem[];
     const int lane = threadIdx.x & 63;
-    const unsigned long long t_end = wall_clock64() + s.life_ticks;
-    if (blockIdx.x == 0) {
-        doorbell(s, t_end);
+    const int b = (int)blockIdx.x;
+    if (b < L.ncls) {
+        const ServeArgs &d = b == 0 ? L.c[0] : L.c[1];
+        doorbell(d, wall_clock64() + d.life_ticks);
         return;
     }
+    const ServeArgs s = b - L.ncls < L.slots0 ? L.c[0] : L.c[1];
+    const unsigned long long t_end = wall_clock64() + s.life_ticks;
     float *qlds = reinterpret_cast<float *>(smem + s.seed_off);
     int32_t *seedpos = reinterpret_cast<int32_t *>(smem + s.seed_off + DP);
     uint32_t *kb = smem + s.seed_off + DP + 160;
@@ -312,8 +328,6 @@ const void *pick_kernel(int dp, int storage)
 struct ServeClass {
     int lmax = 0, slots = 0, scap = 0, vis = 0;
     size_t lds = 0;
-    bool running = false;
-    hipStream_t st = nullptr;
     uint8_t *ring = nullptr, *outs = nullptr;  // host pinned, coherent
     unsigned long long *ctl = nullptr;         // host pinned: [0] tail, [1] stop, [2] status
     unsigned long long *dev = nullptr;         // device: [0] next, [1] stop_dev, [2..] ready
@@ -342,6 +356,8 @@ struct Server {
     double tick_hz = 1.0e8;
     double started = 0.0;
     ServeClass cls[2];
+    hipStream_t st = nullptr;  // the one launch of every class
+    bool running = false;
 };
 
 }  // namespace nhq
@@ -356,8 +372,6 @@ namespace {
 
 void release_class(ServeClass &c)
 {
-    if (c.st)
-        (void)hipStreamDestroy(c.st);
     if (c.ring)
         (void)hipHostFree(c.ring);
     if (c.outs)
@@ -369,7 +383,7 @@ void release_class(ServeClass &c)
     c = ServeClass{};
 }
 
-// stop the kernels and wait (bounded) for them to end
+// stop the kernel and wait (bounded) for it to end
 int stop_server(Server &s)
 {
     for (auto &c : s.cls)
@@ -377,11 +391,9 @@ int stop_server(Server &s)
             __atomic_store_n(&c.ctl[1], 1ull, __ATOMIC_RELEASE);
     const double limit = now_s() + 30.0;
     int rc = NHQ_OK;
-    for (auto &c : s.cls) {
-        if (!c.running)
-            continue;
+    if (s.running) {
         for (;;) {
-            const hipError_t e = hipStreamQuery(c.st);
+            const hipError_t e = hipStreamQuery(s.st);
             if (e == hipSuccess)
                 break;
             if (e != hipErrorNotReady) {
@@ -394,15 +406,14 @@ int stop_server(Server &s)
             }
             std::this_thread::sleep_for(std::chrono::microseconds(200));
         }
-        c.running = false;
+        s.running = false;
     }
     return rc;
 }
 
-int launch_class(Server &s, ServeClass &c, const void *kern, const SearchArgs &base)
+// a class's ring, outputs and control words, and its kernel arguments
+int prepare_class(Server &s, ServeClass &c, ServeArgs &a)
 {
-    const Index *ix = s.ix;
-    NHQ_HIP(hipStreamCreateWithFlags(&c.st, hipStreamNonBlocking));
     const size_t ring_bytes = (size_t)s.p.ring * s.rec_bytes, out_bytes = (size_t)s.p.ring * s.out_bytes;
     NHQ_HIP(hipHostMalloc((void **)&c.ring, ring_bytes, hipHostMallocCoherent | hipHostMallocMapped));
     NHQ_HIP(hipHostMalloc((void **)&c.outs, out_bytes, hipHostMallocCoherent | hipHostMallocMapped));
@@ -411,14 +422,14 @@ int launch_class(Server &s, ServeClass &c, const void *kern, const SearchArgs &b
     memset(c.outs, 0, out_bytes);
     memset(c.ctl, 0, 64);
     NHQ_HIP(hipMalloc((void **)&c.dev, sizeof(unsigned long long) * (2 + (size_t)s.p.ring)));
-    NHQ_HIP(hipMemsetAsync(c.dev, 0, sizeof(unsigned long long) * (2 + (size_t)s.p.ring), c.st));
+    NHQ_HIP(hipMemsetAsync(c.dev, 0, sizeof(unsigned long long) * (2 + (size_t)s.p.ring), s.st));
     c.owner.assign((size_t)s.p.ring, 0);
     uint8_t *ring_d = nullptr, *outs_d = nullptr;
     unsigned long long *ctl_d = nullptr;
     NHQ_HIP(hipHostGetDevicePointer((void **)&ring_d, c.ring, 0));
     NHQ_HIP(hipHostGetDevicePointer((void **)&outs_d, c.outs, 0));
     NHQ_HIP(hipHostGetDevicePointer((void **)&ctl_d, c.ctl, 0));
-    ServeArgs a{};
+    a = ServeArgs{};
     a.ring = ring_d;
     a.outs = outs_d;
     a.tail = ctl_d;
@@ -437,12 +448,27 @@ int launch_class(Server &s, ServeClass &c, const void *kern, const SearchArgs &b
     a.check_every = s.p.check_every;
     a.learned_mode = s.p.learned_mode;
     a.life_ticks = (unsigned long long)(s.p.lifetime_s * s.tick_hz);
-    if (c.lds > 64 * 1024)
-        NHQ_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds));
-    void *args[] = {const_cast<SearchArgs *>(&base), &a};
-    NHQ_HIP(hipLaunchKernel(kern, dim3((unsigned)c.slots + 1), dim3(64), args, c.lds, c.st));
-    c.running = true;
-    (void)ix;
+    return NHQ_OK;
+}
+
+// one launch of every class: its doorbells, then class 0's slots, then class 1's
+int launch_server(Server &s, int ncls, const void *kern, const SearchArgs &base, size_t lds)
+{
+    NHQ_HIP(hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking));
+    ServeLaunch L{};
+    L.ncls = ncls;
+    L.slots0 = s.cls[0].slots;
+    for (int ci = 0; ci < ncls; ++ci) {
+        const int rc = prepare_class(s, s.cls[ci], L.c[ci]);
+        if (rc != NHQ_OK)
+            return rc;
+    }
+    if (lds > 64 * 1024)
+        NHQ_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const unsigned grid = (unsigned)(ncls + s.cls[0].slots + (ncls > 1 ? s.cls[1].slots : 0));
+    void *args[] = {const_cast<SearchArgs *>(&base), &L};
+    NHQ_HIP(hipLaunchKernel(kern, dim3(grid), dim3(64), args, lds, s.st));
+    s.running = true;
     return NHQ_OK;
 }
 
@@ -566,19 +592,23 @@ int nhq_server_create(nhq_index *h, const nhq_server_params *pp, nhq_server **ou
             rc = fail(NHQ_EINVAL, "a serving slot's LDS exceeds 160 KiB (beam or entry sample too large)");
             break;
         }
-        if (c.lds > 64 * 1024 && hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                     (int)c.lds) != hipSuccess) {
-            rc = fail(NHQ_EHIP, "hipFuncSetAttribute failed");
-            break;
-        }
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, c.lds) != hipSuccess || per_cu < 1) {
-            rc = fail(NHQ_EHIP, "occupancy query failed for the serving kernel");
-            break;
-        }
-        // both classes stay resident together: each gets part of the chip
+    }
+    // one launch: every workgroup gets the largest class's LDS, and every
+    // class stays resident together, each with its part of the chip
+    size_t lds = 0;
+    for (int ci = 0; ci < ncls; ++ci)
+        lds = std::max(lds, s.cls[ci].lds);
+    if (rc == NHQ_OK && lds > 64 * 1024 &&
+        hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        rc = fail(NHQ_EHIP, "hipFuncSetAttribute failed");
+    int per_cu = 0;
+    if (rc == NHQ_OK &&
+        (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, lds) != hipSuccess || per_cu < 1))
+        rc = fail(NHQ_EHIP, "occupancy query failed for the serving kernel");
+    for (int ci = 0; ci < ncls && rc == NHQ_OK; ++ci) {
+        ServeClass &c = s.cls[ci];
         const double share = ncls == 1 ? 0.9 : (ci == 0 ? 0.6 : 0.3);
-        const int fit = std::max(1, (int)(share * per_cu * n_cu) - 1);
+        const int fit = std::max(1, (int)(share * per_cu * n_cu) - ncls);
         const int asked = ci == 0 ? p.slots_small : p.slots_large;
         c.slots = asked > 0 ? std::min(asked, fit) : fit;
     }
@@ -591,12 +621,14 @@ int nhq_server_create(nhq_index *h, const nhq_server_params *pp, nhq_server **ou
         if (hipDeviceSynchronize() != hipSuccess)
             rc = fail(NHQ_EHIP, "device synchronisation before serving failed");
     }
-    for (int ci = 0; ci < ncls && rc == NHQ_OK; ++ci)
-        rc = launch_class(s, s.cls[ci], kern, base);
+    if (rc == NHQ_OK)
+        rc = launch_server(s, ncls, kern, base, lds);
     if (rc != NHQ_OK) {
         (void)stop_server(s);
         for (auto &c : s.cls)
             release_class(c);
+        if (s.st)
+            (void)hipStreamDestroy(s.st);
         delete hs;
         return rc;
     }
@@ -652,7 +684,7 @@ int nhq_server_submit(nhq_server *h, const float *q, const uint8_t *qattr, int32
         return fail(NHQ_EINVAL, "beam exceeds every memory class of the server");
     ServeClass &c = s.cls[ci];
     const uint32_t st = (uint32_t)__atomic_load_n(&c.ctl[2], __ATOMIC_ACQUIRE);
-    if (st != 0 || !c.running)
+    if (st != 0 || !s.running)
         return fail(NHQ_EDEVICE, st == 2 ? "serving kernel reached its lifetime" : "serving kernel has ended");
     const size_t slot = (size_t)(c.tail % (unsigned long long)s.p.ring);
     if (c.owner[slot] != 0)
@@ -792,9 +824,11 @@ int nhq_server_free(nhq_server *h)
     Server &s = h->impl;
     const int rc = stop_server(s);
     if (rc != NHQ_OK)
-        return rc;  // the kernels may still run: keep their memory
+        return rc;  // the kernel may still run: keep its memory
     for (auto &c : s.cls)
         release_class(c);
+    if (s.st)
+        (void)hipStreamDestroy(s.st);
     delete h;
     return NHQ_OK;
 }

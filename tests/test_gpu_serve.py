@@ -163,6 +163,30 @@ def test_serve_learned_requests_equal_batch_learned_search(int_index, mode, cf):
     assert np.array_equal(r["counters"], wc)
 
 
+def test_two_classes_run_side_by_side_after_many_streams(int_index):
+    # Both memory classes live in one persistent launch.  Streams made busy
+    # beforehand (the process's streams share a few hardware queues) must
+    # not keep either class from running: every request of both classes
+    # finishes and equals the batch search.
+    w, ix = int_index
+    streams = [torch.cuda.Stream() for _ in range(12)]
+    for st in streams:
+        with torch.cuda.stream(st):
+            torch.ones(4096, device="cuda").cumsum(0)
+    torch.cuda.synchronize()
+    n = w.nq
+    k = np.full(n, 10, np.int32)
+    beam = np.where(np.arange(n) % 2 == 0, 64, 300).astype(np.int32)   # small class, large class
+    want = {b: _batch(ix, w, 10, b, n_init=32) for b in (64, 300)}
+    with nhq.Server(ix, n_init=32, lifetime_s=LIFE, ring=256, slots_small=64, slots_large=16) as srv:
+        assert srv.slots[0] > 0 and srv.slots[1] > 0 and srv.beam_max[1] >= 300
+        r = srv.run(w.q, w.qattrs, k, beam, np.zeros(n), timeout_s=30.0)
+    for b in (64, 300):
+        sel = beam == b
+        assert np.array_equal(r["ids"][sel, :10], want[b][0][sel])
+        assert np.array_equal(r["counters"][sel], want[b][2][sel])
+
+
 def test_serve_full_ring_refuses_then_recovers(int_index):
     w, ix = int_index
     with nhq.Server(ix, lifetime_s=LIFE, ring=4, slots_small=8, beam_large=-1) as srv:
