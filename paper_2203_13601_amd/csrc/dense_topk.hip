@@ -126,8 +126,10 @@ __device__ void compact_row(float *bk, uint32_t *bi, int *cnt, float *thk, uint3
     wsync();
 }
 
+// Row block rb (kWaves x kRowsPerWave rows) against the workgroup's column
+// range, its K best per row written out.
 template <int DP>
-__global__ __launch_bounds__(128) void k_dense_topk(const TopkArgs a)
+__device__ __forceinline__ void topk_row_block(const TopkArgs &a, int64_t rb, uint32_t *smem)
 {
     constexpr int NT = DP / 16;             // float4 chunks per lane per point
     constexpr bool ROWS_IN_REGS = NT <= 16;  // rows stay in registers up to 256 dims
@@ -136,7 +138,6 @@ __global__ __launch_bounds__(128) void k_dense_topk(const TopkArgs a)
     const int rl = lane & 15, lq = lane >> 4;
     const int cap = a.cap;
 
-    extern __shared__ __align__(16) uint32_t smem[];
     float *bk = reinterpret_cast<float *>(smem) + (size_t)wave * kRowsPerWave * cap;
     uint32_t *bi = smem + (size_t)kWaves * kRowsPerWave * cap + (size_t)wave * kRowsPerWave * cap;
     uint32_t *tail = smem + (size_t)2 * kWaves * kRowsPerWave * cap + wave * 3 * kRowsPerWave;
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(128) void k_dense_topk(const TopkArgs a)
     float *thk = reinterpret_cast<float *>(tail + kRowsPerWave);
     uint32_t *thi = tail + 2 * kRowsPerWave;
 
-    const int64_t row0 = (int64_t)blockIdx.x * (kWaves * kRowsPerWave) + wave * kRowsPerWave;
+    const int64_t row0 = rb * (kWaves * kRowsPerWave) + wave * kRowsPerWave;
     const int64_t row = row0 + rl;
     const bool row_ok = row < a.na;
     const int64_t rowc = row_ok ? row : a.na - 1;
@@ -277,6 +278,21 @@ __global__ __launch_bounds__(128) void k_dense_topk(const TopkArgs a)
                 a.out_keys[base + e] = e < n ? bk[r * cap + e] : __int_as_float(0x7F800000);
         }
     }
+    wsync();  // the buffers are read out before the next row block resets them
+}
+
+// The grid holds about as many workgroups as the device keeps resident, and
+// each takes row blocks blockIdx.x, + gridDim.x, ... in turn: the workgroups
+// in flight then sweep the columns side by side and share the column rows in
+// L2 (a workgroup started whenever another ends would sweep from the first
+// column while the others are far along, and read every column row again).
+template <int DP>
+__global__ __launch_bounds__(128) void k_dense_topk(const TopkArgs a)
+{
+    extern __shared__ __align__(16) uint32_t smem[];
+    const int64_t row_blocks = (a.na + kWaves * kRowsPerWave - 1) / (kWaves * kRowsPerWave);
+    for (int64_t rb = blockIdx.x; rb < row_blocks; rb += gridDim.x)
+        topk_row_block<DP>(a, rb, smem);
 }
 
 // join the per-range sorted lists of one row: K steps of a k-way merge, the
@@ -330,7 +346,15 @@ int launch_dp(const TopkArgs &a, hipStream_t st)
     if (lds > 64 * 1024)
         NHQ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    const int64_t blocks = (a.na + kWaves * kRowsPerWave - 1) / (kWaves * kRowsPerWave);
+    // as many workgroups as stay resident (the kernel loops over row blocks)
+    const int64_t row_blocks = (a.na + kWaves * kRowsPerWave - 1) / (kWaves * kRowsPerWave);
+    int dev = 0, n_cu = 0, per_cu = 0;
+    NHQ_HIP(hipGetDevice(&dev));
+    NHQ_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    NHQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kern),
+                                                         64 * kWaves, lds));
+    const int64_t resident = std::max<int64_t>(1, (int64_t)std::max(per_cu, 1) * n_cu / a.splits);
+    const int64_t blocks = std::min(row_blocks, resident);
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks, (unsigned)a.splits), dim3(64 * kWaves), lds, st, a);
     NHQ_HIP(hipGetLastError());
     return NHQ_OK;
