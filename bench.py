@@ -10,9 +10,10 @@ brute force, checked against the CPU oracle on a sample; every Recall@10 is
 computed from FP64 distances recomputed from the vectors.
 
 One timed "step" is one full pass of the hot path over the 10,000 queries:
-seed ranking of the entry sample (matrix cores) plus the joint-pruning
-search (one wavefront per query), with the exact float32 re-score of the
-final candidates in the precision forms.  Two batches are kept in flight:
+seed ranking of the entry sample (matrix cores), the launch order that
+groups the queries by their best seed (nhq_seed_order), and the
+joint-pruning search (one wavefront per query), with the exact float32
+re-score of the final candidates in the precision forms.  Two batches are kept in flight:
 step i runs on stream i % 2 with its own candidates, outputs and ranking
 scratch (nhq_seed_rank_ws), so one batch's ranking and search use the
 compute units that the other batch's last queries leave idle.  QPS is the
@@ -134,6 +135,9 @@ class Harness:
         self.cand1 = torch.empty_like(self.cand)
         self.ids1 = torch.empty_like(self.ids)
         self.dists1 = torch.empty_like(self.dists)
+        # launch orders (queries grouped by their best seed, each group on one
+        # XCD), one per batch in flight
+        self.order = [torch.empty(self.nq, dtype=torch.int32, device=dev) for _ in range(2)]
         self._ws = {}
         self.gt = None
 
@@ -148,18 +152,25 @@ class Harness:
         """one batch: seed ranking, then the search; j None on the current
         stream, else on stream j of the two kept in flight"""
         nhq, torch = self.nhq, self.torch
+        seed_order = "order" not in kw  # else the caller's launch order
         if j is not None:
             s = self.streams[j]
             cand, out = (self.cand, (self.ids, self.dists)) if j == 0 else (self.cand1, (self.ids1, self.dists1))
             ws = None if j == 0 else self._workspace(index)
             with torch.cuda.stream(s):
                 nhq.nhq_seed_rank(index, self.q, self.qa, self.n_cand, out=cand, stream=s, workspace=ws)
+                okw = kw
+                if seed_order:
+                    okw = dict(kw, order=nhq.nhq_seed_order(index, cand, stream=s, out=self.order[j],
+                                                            workspace=ws))
                 nhq.nhq_search_seeded(index, self.q, self.qa, cand, self.k, beam, n_init=self.args.n_init,
-                                      out=out, expand=self.args.expand, stream=s, **kw)
+                                      out=out, expand=self.args.expand, stream=s, **okw)
             return None
         if ev is not None:
             ev[0].record()
         nhq.nhq_seed_rank(index, self.q, self.qa, self.n_cand, out=self.cand)
+        if seed_order:
+            kw = dict(kw, order=nhq.nhq_seed_order(index, self.cand, out=self.order[0]))
         if ev is not None:
             ev[1].record()
         r = nhq.nhq_search_seeded(index, self.q, self.qa, self.cand, self.k, beam, n_init=self.args.n_init,

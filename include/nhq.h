@@ -347,7 +347,9 @@ int nhq_index_load(const char *path, void *stream, nhq_index **out);
  * and stops when every pool entry is expanded.  Output per output_mode.
  * queries: device float32 [nq][d]; qattrs: device uint8 [nq][m];
  * 1 <= k <= beam <= 1024; ids: device int32 [nq][k]; dists: device float32
- * [nq][k].  nq = 0 is a no-op. */
+ * [nq][k].  nq = 0 is a no-op.  Batches of 2,048 queries and more whose
+ * parameters name no launch order are launched in nhq_seed_order's order
+ * (results do not depend on it). */
 int nhq_hybrid_search(const nhq_index *ix, const float *queries, const uint8_t *qattrs,
                       int64_t nq, int32_t k, int32_t beam, const nhq_search_params *sp,
                       int32_t *ids, float *dists, void *stream);
@@ -404,6 +406,23 @@ int nhq_search_seeded(const nhq_index *ix, const float *queries, const uint8_t *
  * uint8 [nq][m]; order: device int32 [nq], a permutation of 0 .. nq - 1 on
  * return.  Uses the index's workspace (see nhq_seed_rank). */
 int nhq_query_order(const nhq_index *ix, const uint8_t *qattrs, int64_t nq, int32_t *order, void *stream);
+
+/* A launch order for nhq_search_params.order from the batch's seed
+ * candidates (nhq_seed_rank's cand, [nq][n_cand]): the queries grouped by
+ * their best candidate, each group's wavefronts kept on one XCD.  Queries
+ * that start from one member of the entry sample search one part of the
+ * graph and read many of the same rows; workgroups go to the device's 8 XCDs
+ * round-robin, so XCD x is given the x-th of 8 contiguous runs of the
+ * grouped queries, and their rows meet in that XCD's L2.  A scheduling
+ * choice only: results do not depend on it.  order: device int32 [nq], a
+ * permutation of 0 .. nq - 1 (wave i searches query order[i]).  workspace:
+ * null for the index's workspace (calls on one index then go on one
+ * stream), else 256-byte aligned device memory of at least 4 (1024 + 2 nq)
+ * bytes -- the workspace of nhq_seed_rank_ws for the same batch is large
+ * enough.  nhq_hybrid_search applies this order itself to batches of 2,048
+ * queries and more when its parameters name no order. */
+int nhq_seed_order(const nhq_index *ix, const int32_t *cand, int32_t n_cand, int64_t nq, int32_t *order,
+                   void *workspace, size_t workspace_bytes, void *stream);
 
 /* Allocation-free nhq_hybrid_search, for callers that cannot allocate
  * device memory: code under HIP graph capture, tight serving loops,

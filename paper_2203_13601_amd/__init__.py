@@ -16,4 +16,4 @@ from ._binding import (BuildParams, Index, NHQError, SearchParams, lib,  # noqa:
                        nhq_nndescent_lists, nhq_index_build_report, WEIGHTS, BUILDERS,
                        nhq_index_insert, nhq_index_save, nhq_index_load,
                        nhq_hybrid_search_noalloc, NOALLOC_SCRATCH_BYTES,
-                       nhq_index_entry_blocks, nhq_query_order)
+                       nhq_index_entry_blocks, nhq_query_order, nhq_seed_order)

@@ -109,6 +109,7 @@ def lib() -> ctypes.CDLL:
         "nhq_seed_rank_ws": ([P, P, P, i64, i32, P, P, ctypes.c_size_t, P], i32),
         "nhq_search_seeded": ([P, P, P, i64, P, i32, i32, i32, P, P, P, P], i32),
         "nhq_query_order": ([P, P, i64, P, P], i32),
+        "nhq_seed_order": ([P, P, i32, i64, P, P, ctypes.c_size_t, P], i32),
         "nhq_trace_samples": ([P, i64, P, P, P, P, P, P], i32),
         "nhq_mlp_grad": ([P, P, P, P, i64, ctypes.c_float, P, P, P, P], i32),
         "nhq_mlp_train": ([P, P, P, P, P, P, i64, i32, i32, ctypes.c_float, ctypes.c_float,
@@ -490,6 +491,30 @@ def nhq_query_order(ix: Index, qattrs: torch.Tensor, stream=None) -> torch.Tenso
     order = torch.empty((nq,), dtype=torch.int32, device=ix.device)
     _check(lib().nhq_query_order(ix.handle, qattrs.data_ptr(), nq, order.data_ptr(), _stream(stream)),
            "nhq_query_order")
+    return order
+
+
+def nhq_seed_order(ix: Index, cand: torch.Tensor, stream=None, out: Optional[torch.Tensor] = None,
+                   workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Launch order grouping a batch by its best seed candidate (cand from
+    nhq_seed_rank), each group on one XCD; int32 [nq] on the index's device.
+    workspace: as for nhq_seed_rank (the same tensor serves both calls)."""
+    if (not isinstance(cand, torch.Tensor) or cand.dtype != torch.int32 or cand.dim() != 2
+            or cand.device != ix.device):
+        raise ValueError("cand must be an int32 [nq][n_cand] tensor on %s" % ix.device)
+    cand = cand.contiguous()
+    nq = cand.shape[0]
+    order = out if out is not None else torch.empty(nq, dtype=torch.int32, device=cand.device)
+    if (order.dtype != torch.int32 or tuple(order.shape) != (nq,) or not order.is_contiguous()
+            or order.device != ix.device):
+        raise ValueError("out must be a contiguous int32 [%d] tensor on %s" % (nq, ix.device))
+    if workspace is not None and (not isinstance(workspace, torch.Tensor) or workspace.dtype != torch.uint8
+                                  or not workspace.is_contiguous() or workspace.device != ix.device):
+        raise ValueError("workspace must be a contiguous uint8 tensor on %s" % ix.device)
+    _check(lib().nhq_seed_order(ix.handle, cand.data_ptr(), cand.shape[1], nq, order.data_ptr(),
+                                None if workspace is None else workspace.data_ptr(),
+                                0 if workspace is None else workspace.numel(), _stream(stream)),
+           "nhq_seed_order")
     return order
 
 

@@ -916,8 +916,41 @@ void nhq_index_free(nhq_index *h)
 
 namespace {
 
-// ---- launch order by selectivity (nhq_query_order)
-constexpr int kOrderBuckets = 1024;  // buckets of 1/16 of -sum ln(count / n)
+// ---- launch orders: by selectivity (nhq_query_order) and by seed
+// (nhq_seed_order), a counting sort over kOrderBuckets buckets
+constexpr int kOrderBuckets = 1024;
+
+// selectivity: buckets of 1/16 of -sum ln(count / n) over the constrained codes
+struct SelectivityBucket {
+    const uint8_t *qa;
+    int m;
+    const float *logp;
+    __device__ int operator()(int64_t q) const
+    {
+        float ls = 0.0f;
+        for (int i = 0; i < m; ++i) {
+            const uint32_t c = qa[q * m + i];
+            if (c != 0xFFu)
+                ls += logp[i * 256 + c];
+        }
+        return (int)fminf(fmaxf(-ls * 16.0f, 0.0f), (float)(kOrderBuckets - 1));
+    }
+};
+
+// seed: the query's best candidate (its position in the entry sample),
+// n_total positions spread over the buckets; no candidate: the last bucket
+struct SeedBucket {
+    const int32_t *cand;
+    int n_cand;
+    int64_t n_total;
+    __device__ int operator()(int64_t q) const
+    {
+        const int32_t p = cand[q * n_cand];
+        if (p < 0 || p >= n_total)
+            return kOrderBuckets - 1;
+        return (int)((int64_t)p * kOrderBuckets / n_total);
+    }
+};
 
 __global__ void k_order_clear(int32_t *hist)
 {
@@ -929,8 +962,8 @@ __global__ void k_order_clear(int32_t *hist)
 // each query's bucket, and its position among the bucket's queries: counts
 // in an LDS histogram, then one global atomic per (workgroup, bucket)
 // reserves the workgroup's run of positions
-__global__ __launch_bounds__(256) void k_order_assign(const uint8_t *__restrict__ qa, int64_t nq, int m,
-                                                      const float *__restrict__ logp,
+template <class BucketOf>
+__global__ __launch_bounds__(256) void k_order_assign(const BucketOf bucket_of, int64_t nq,
                                                       int32_t *__restrict__ bucket, int32_t *__restrict__ pos,
                                                       int32_t *__restrict__ hist)
 {
@@ -942,13 +975,7 @@ __global__ __launch_bounds__(256) void k_order_assign(const uint8_t *__restrict_
     const bool live = q < nq;
     int b = 0, r = 0;
     if (live) {
-        float ls = 0.0f;
-        for (int i = 0; i < m; ++i) {
-            const uint32_t c = qa[q * m + i];
-            if (c != 0xFFu)
-                ls += logp[i * 256 + c];
-        }
-        b = (int)fminf(fmaxf(-ls * 16.0f, 0.0f), (float)(kOrderBuckets - 1));
+        b = bucket_of(q);
         r = atomicAdd(&lh[b], 1);
     }
     __syncthreads();
@@ -975,12 +1002,72 @@ __global__ void k_order_scan(int32_t *hist)
     }
 }
 
+// The wavefront that runs sorted position p when a batch of n one-wave
+// workgroups keeps each XCD on a contiguous run of the sorted queries:
+// workgroups go to the 8 XCDs round-robin (workgroup i to XCD i mod 8), and
+// XCD x takes the x-th of 8 contiguous runs (the first n mod 8 runs one
+// longer).  A bijection of 0 .. n - 1.
+__device__ __forceinline__ int64_t xcd_wave(int64_t p, int64_t n)
+{
+    constexpr int kXcd = 8;
+    const int64_t base = n / kXcd, r = n % kXcd;
+    int64_t x, j;
+    if (p < r * (base + 1)) {
+        x = p / (base + 1);
+        j = p - x * (base + 1);
+    } else {
+        const int64_t pp = p - r * (base + 1);
+        x = r + pp / base;
+        j = pp - (x - r) * base;
+    }
+    return x + kXcd * j;
+}
+
+// order[wave] = q for each query's sorted position (xcd: the wave that
+// runs that position on its XCD's run, else the position itself)
 __global__ void k_order_place(const int32_t *__restrict__ bucket, const int32_t *__restrict__ pos,
-                              const int32_t *__restrict__ start, int64_t nq, int32_t *__restrict__ order)
+                              const int32_t *__restrict__ start, int64_t nq, int xcd,
+                              int32_t *__restrict__ order)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < nq)
-        order[start[bucket[q]] + pos[q]] = (int32_t)q;
+    if (q < nq) {
+        const int64_t p = start[bucket[q]] + pos[q];
+        order[xcd ? xcd_wave(p, nq) : p] = (int32_t)q;
+    }
+}
+
+// a launch order by counting sort: scratch of kOrderBuckets + 2 nq words
+template <class BucketOf>
+int launch_order(const BucketOf &bucket_of, int64_t nq, int xcd, int32_t *scratch, int32_t *order, hipStream_t st)
+{
+    int32_t *hist = scratch, *bucket = scratch + kOrderBuckets, *pos = bucket + nq;
+    const unsigned g = (unsigned)((nq + 255) / 256);
+    hipLaunchKernelGGL(k_order_clear, dim3(kOrderBuckets / 256), dim3(256), 0, st, hist);
+    hipLaunchKernelGGL(k_order_assign<BucketOf>, dim3(g), dim3(256), 0, st, bucket_of, nq, bucket, pos, hist);
+    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, st, hist);
+    hipLaunchKernelGGL(k_order_place, dim3(g), dim3(256), 0, st, bucket, pos, hist, nq, xcd, order);
+    NHQ_HIP(hipGetLastError());
+    return NHQ_OK;
+}
+
+// batches from this size on are launched grouped by their best seed when the
+// caller gives no order (smaller ones gain less than the order costs)
+constexpr int64_t kSeedOrderMinQueries = 2048;
+
+// 32-bit words of a launch order's scratch
+size_t order_words(int64_t nq)
+{
+    return (size_t)kOrderBuckets + 2 * (size_t)nq;
+}
+
+// the order grouping queries by their best seed candidate, each group's
+// waves on one XCD (queries that start from one entry search one part of the
+// graph, so their row gathers share that XCD's L2)
+int seed_order_at(const Index *ix, const int32_t *cand, int n_cand, int64_t nq, int32_t *order,
+                  int32_t *scratch, hipStream_t st)
+{
+    const int64_t n_total = std::max(ix->n_entry_total, ix->n_entry);
+    return launch_order(SeedBucket{cand, n_cand, n_total}, nq, 1, scratch, order, st);
 }
 
 // 32-bit words of the seed ranking's scratch: padded rows, norms, codes,
@@ -992,9 +1079,10 @@ size_t seed_rank_words(const Index *ix, int64_t nq, int K)
     const size_t ne_pad = (size_t)(ix->n_entry + 63) / 64 * 64;
     const bool dense = ix->n_entry <= 8192;
     const size_t pad = 2 * (size_t)nq * ix->dp + 5 * (size_t)nq + 128;
+    // the same scratch serves the seed order afterwards (nhq_seed_order)
     if (ix->n_blocks > 0)
-        return pad + strata_rank_words(ix, nq, K);
-    return pad + (dense ? (size_t)nq * ne_pad / 16 * 17 : 0);
+        return std::max(order_words(nq), pad + strata_rank_words(ix, nq, K));
+    return std::max(order_words(nq), pad + (dense ? (size_t)nq * ne_pad / 16 * 17 : 0));
 }
 
 int check_seed_rank_args(const Index *ix, const float *queries, const uint8_t *qattrs, int64_t nq,
@@ -1230,20 +1318,37 @@ int nhq_query_order(const nhq_index *h, const uint8_t *qattrs, int64_t nq, int32
     if (!order || (ix->m > 0 && !qattrs))
         return fail(NHQ_EINVAL, "null array argument");
     // workspace: bucket counts (then starts) [1024], bucket [nq], position [nq]
-    int rc = ensure_workspace(ix, sizeof(int32_t) * ((size_t)kOrderBuckets + 2 * (size_t)nq));
+    int rc = ensure_workspace(ix, sizeof(int32_t) * order_words(nq));
     if (rc != NHQ_OK)
         return rc;
-    int32_t *hist = static_cast<int32_t *>(ix->ws);
-    int32_t *bucket = hist + kOrderBuckets;
-    int32_t *pos = bucket + nq;
-    hipStream_t st = (hipStream_t)stream;
-    const unsigned g = (unsigned)((nq + 255) / 256);
-    hipLaunchKernelGGL(k_order_clear, dim3(kOrderBuckets / 256), dim3(256), 0, st, hist);
-    hipLaunchKernelGGL(k_order_assign, dim3(g), dim3(256), 0, st, qattrs, nq, ix->m, ix->logp, bucket, pos, hist);
-    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, st, hist);
-    hipLaunchKernelGGL(k_order_place, dim3(g), dim3(256), 0, st, bucket, pos, hist, nq, order);
-    NHQ_HIP(hipGetLastError());
-    return NHQ_OK;
+    return launch_order(SelectivityBucket{qattrs, ix->m, ix->logp}, nq, 0, static_cast<int32_t *>(ix->ws), order,
+                        (hipStream_t)stream);
+}
+
+int nhq_seed_order(const nhq_index *h, const int32_t *cand, int32_t n_cand, int64_t nq, int32_t *order,
+                   void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (!h)
+        return fail(NHQ_EINVAL, "null index");
+    Index *ix = const_cast<Index *>(&h->impl);
+    if (nq < 0 || nq > 0x7FFFFFFF || n_cand < 1)
+        return fail(NHQ_EINVAL, "need 0 <= nq < 2^31 and n_cand >= 1");
+    if (nq == 0)
+        return NHQ_OK;
+    if (!order || !cand)
+        return fail(NHQ_EINVAL, "null array argument");
+    int32_t *scratch = static_cast<int32_t *>(workspace);
+    if (!scratch) {
+        const int rc = ensure_workspace(ix, sizeof(int32_t) * order_words(nq));
+        if (rc != NHQ_OK)
+            return rc;
+        scratch = static_cast<int32_t *>(ix->ws);
+    } else if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0 ||
+               workspace_bytes < sizeof(int32_t) * order_words(nq)) {
+        return fail(NHQ_EINVAL, "workspace: need 256-byte aligned device memory of " +
+                                    std::to_string(sizeof(int32_t) * order_words(nq)) + " bytes");
+    }
+    return seed_order_at(ix, cand, n_cand, nq, order, scratch, (hipStream_t)stream);
 }
 
 int nhq_hybrid_search(const nhq_index *h, const float *queries, const uint8_t *qattrs, int64_t nq,
@@ -1261,17 +1366,29 @@ int nhq_hybrid_search(const nhq_index *h, const float *queries, const uint8_t *q
     if (n_init > 128)
         return fail(NHQ_EINVAL, "need 1 <= n_init <= 128");
     const int ks = std::min(std::max(ix->n_entry, ix->n_blocks > 0 ? ix->per_pattern : 0), n_init + kSeedMargin);
-    // the candidates at the start of the index's workspace, the ranking's
-    // scratch after them
+    // the candidates and the launch order at the start of the index's
+    // workspace, the ranking's scratch (then the order's) after them
+    nhq_search_params p{};
+    if (sp)
+        p = *sp;
+    const bool order = p.order == nullptr && nq >= kSeedOrderMinQueries;
     const size_t cbytes = (sizeof(int32_t) * (size_t)nq * ks + 255) & ~size_t(255);
+    const size_t obytes = order ? (sizeof(int32_t) * (size_t)nq + 255) & ~size_t(255) : 0;
     Index *mix = const_cast<Index *>(ix);
-    int rc = ensure_workspace(mix, cbytes + sizeof(uint32_t) * seed_rank_words(ix, nq, ks));
+    int rc = ensure_workspace(mix, cbytes + obytes + sizeof(uint32_t) * seed_rank_words(ix, nq, ks));
     if (rc != NHQ_OK)
         return rc;
     int32_t *cand = static_cast<int32_t *>(mix->ws);
-    rc = seed_rank_ws(h, queries, qattrs, nq, ks, cand, stream, cbytes);
+    rc = seed_rank_ws(h, queries, qattrs, nq, ks, cand, stream, cbytes + obytes);
+    if (rc == NHQ_OK && order) {
+        int32_t *ord = reinterpret_cast<int32_t *>(static_cast<char *>(mix->ws) + cbytes);
+        rc = seed_order_at(ix, cand, ks, nq, ord,
+                           reinterpret_cast<int32_t *>(static_cast<char *>(mix->ws) + cbytes + obytes),
+                           (hipStream_t)stream);
+        p.order = ord;
+    }
     if (rc == NHQ_OK)
-        rc = nhq_search_seeded(h, queries, qattrs, nq, cand, ks, k, beam, sp, ids, dists, stream);
+        rc = nhq_search_seeded(h, queries, qattrs, nq, cand, ks, k, beam, &p, ids, dists, stream);
     return rc;
 }
 

@@ -87,3 +87,48 @@ def test_order_entry_out_of_range_is_skipped_and_reported(mixed):
     assert nhq.nhq_index_device_error(ix) & nhq.DEVERR_BADID
     # every listed query was searched as in the natural order
     assert torch.equal(ids[:63], ref[:63])
+
+
+# ---- the launch order by best seed (nhq_seed_order), and the one-call
+# search that applies it to large batches by itself
+def _xcd_wave(p, n):
+    """the wavefront running sorted position p: workgroup i goes to XCD i % 8,
+    XCD x takes the x-th of 8 contiguous runs (the first n % 8 one longer)"""
+    base, r = divmod(n, 8)
+    if p < r * (base + 1):
+        x, j = divmod(p, base + 1)
+    else:
+        pp = p - r * (base + 1)
+        x, j = r + pp // base, pp % base
+    return x + 8 * j
+
+
+@pytest.mark.parametrize("nq", [600, 4099])
+def test_seed_order_groups_by_best_seed_per_xcd(nq):
+    w = synth.small(20000, 64, nq, seed=132, integer=True, n_centres=8, wildcard_arity=True)
+    ix = nhq.nhq_build_index(_dev(w.x), _dev(w.attrs), degree=32, cand=64, n_entry=512, seed=w.build_seed)
+    q, qa = _dev(w.q), _dev(w.qattrs)
+    cand = nhq.nhq_seed_rank(ix, q, qa, 12)
+    order = nhq.nhq_seed_order(ix, cand).cpu().numpy()
+    assert np.array_equal(np.sort(order), np.arange(nq))
+    waves = np.array([_xcd_wave(p, nq) for p in range(nq)])
+    assert np.array_equal(np.sort(waves), np.arange(nq))          # a bijection
+    best = cand.cpu().numpy()[:, 0].astype(np.int64)
+    bucket = np.where(best >= 0, best * 1024 // 512, 1023)
+    assert (np.diff(bucket[order[waves]]) >= 0).all()             # sorted along each XCD's run
+    # same order from a caller workspace, results independent of the order
+    ws = torch.empty(nhq.nhq_seed_rank_workspace_size(ix, nq, 12), dtype=torch.uint8, device="cuda")
+    order2 = nhq.nhq_seed_order(ix, cand, workspace=ws).cpu().numpy()
+    assert (np.diff(bucket[order2[waves]]) >= 0).all()
+    a = nhq.nhq_search_seeded(ix, q, qa, cand, 10, 64, n_init=4, expand=2, counters=True)
+    b = nhq.nhq_search_seeded(ix, q, qa, cand, 10, 64, n_init=4, expand=2, counters=True,
+                              order=torch.from_numpy(order).cuda())
+    # the one-call search orders batches of 2,048 and more by itself
+    c = nhq.nhq_hybrid_search(ix, q, qa, 10, 64, n_init=4, expand=2, counters=True)
+    torch.cuda.synchronize()
+    for x in (b, c):
+        assert torch.equal(a[0], x[0])
+        assert torch.equal(a[1].view(torch.int32), x[1].view(torch.int32))
+        assert torch.equal(a[2], x[2])
+    assert nhq.nhq_index_device_error(ix) == 0
+    ix.free()
