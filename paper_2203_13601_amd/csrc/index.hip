@@ -989,16 +989,33 @@ __global__ __launch_bounds__(256) void k_order_assign(const BucketOf bucket_of, 
     }
 }
 
-// bucket starts (exclusive scan, one thread: 1,024 buckets)
-__global__ void k_order_scan(int32_t *hist)
+// bucket starts (exclusive scan by one wavefront: each lane sums a run of
+// kOrderBuckets / 64 buckets, a wave prefix sum of the runs gives their
+// starts, and each lane writes its run's starts)
+__global__ __launch_bounds__(64) void k_order_scan(int32_t *hist)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        int32_t run = 0;
-        for (int b = 0; b < kOrderBuckets; ++b) {
-            const int32_t c = hist[b];
-            hist[b] = run;
-            run += c;
-        }
+    constexpr int kRun = kOrderBuckets / 64;
+    static_assert(kRun * 64 == kOrderBuckets, "whole runs");
+    const int lane = threadIdx.x;
+    int32_t c[kRun];
+    int32_t sum = 0;
+#pragma unroll
+    for (int u = 0; u < kRun; ++u) {
+        c[u] = hist[lane * kRun + u];
+        sum += c[u];
+    }
+    int32_t incl = sum;  // inclusive prefix over lanes
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t v = __shfl_up(incl, o, 64);
+        if (lane >= o)
+            incl += v;
+    }
+    int32_t run = incl - sum;
+#pragma unroll
+    for (int u = 0; u < kRun; ++u) {
+        hist[lane * kRun + u] = run;
+        run += c[u];
     }
 }
 
