@@ -413,7 +413,10 @@ int nhq_query_order(const nhq_index *ix, const uint8_t *qattrs, int64_t nq, int3
  * that start from one member of the entry sample search one part of the
  * graph and read many of the same rows; workgroups go to the device's 8 XCDs
  * round-robin, so XCD x is given the x-th of 8 contiguous runs of the
- * grouped queries, and their rows meet in that XCD's L2.  A scheduling
+ * grouped queries, and their rows meet in that XCD's L2.  The groups are
+ * taken in a scrambled order of their entry positions, so each XCD's run
+ * mixes many groups and the runs cost about the same (the blocks of a
+ * stratified sample sit at neighbouring positions).  A scheduling
  * choice only: results do not depend on it.  order: device int32 [nq], a
  * permutation of 0 .. nq - 1 (wave i searches query order[i]).  workspace:
  * null for the index's workspace (calls on one index then go on one

@@ -938,17 +938,22 @@ struct SelectivityBucket {
 };
 
 // seed: the query's best candidate (its position in the entry sample),
-// n_total positions spread over the buckets; no candidate: the last bucket
+// n_total positions spread over the buckets (no candidate: the last
+// position's bucket), the buckets then permuted by an odd multiplier mod
+// 1,024.  Neighbouring positions (one attribute pattern's block of a
+// stratified sample) land far apart, so each XCD's run of the sorted queries
+// mixes many buckets of every kind, and their cost evens out across XCDs;
+// the queries of one bucket stay together.
 struct SeedBucket {
     const int32_t *cand;
     int n_cand;
     int64_t n_total;
     __device__ int operator()(int64_t q) const
     {
+        static_assert(kOrderBuckets == 1024, "the permutation is mod 1024");
         const int32_t p = cand[q * n_cand];
-        if (p < 0 || p >= n_total)
-            return kOrderBuckets - 1;
-        return (int)((int64_t)p * kOrderBuckets / n_total);
+        const int b = (p < 0 || p >= n_total) ? kOrderBuckets - 1 : (int)((int64_t)p * kOrderBuckets / n_total);
+        return (b * 757 + 419) & (kOrderBuckets - 1);
     }
 };
 
