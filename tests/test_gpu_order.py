@@ -103,7 +103,7 @@ def _xcd_wave(p, n):
     return x + 8 * j
 
 
-@pytest.mark.parametrize("nq", [600, 4099])
+@pytest.mark.parametrize("nq", [600, 4099, 70000])
 def test_seed_order_groups_by_best_seed_per_xcd(nq):
     w = synth.small(20000, 64, nq, seed=132, integer=True, n_centres=8, wildcard_arity=True)
     ix = nhq.nhq_build_index(_dev(w.x), _dev(w.attrs), degree=32, cand=64, n_entry=512, seed=w.build_seed)
