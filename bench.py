@@ -11,7 +11,7 @@ computed from FP64 distances recomputed from the vectors.
 
 One timed "step" is one full pass of the hot path over the 10,000 queries:
 seed ranking of the entry sample (matrix cores), the launch order that
-groups the queries by their best seed (nhq_seed_order), and the
+groups the queries by seed candidate (nhq_seed_order), and the
 joint-pruning search (one wavefront per query), with the exact float32
 re-score of the final candidates in the precision forms.  Two batches are kept in flight:
 step i runs on stream i % 2 with its own candidates, outputs and ranking
@@ -135,7 +135,7 @@ class Harness:
         self.cand1 = torch.empty_like(self.cand)
         self.ids1 = torch.empty_like(self.ids)
         self.dists1 = torch.empty_like(self.dists)
-        # launch orders (queries grouped by their best seed, each group on one
+        # launch orders (queries grouped by seed candidate, each group on one
         # XCD), one per batch in flight
         self.order = [torch.empty(self.nq, dtype=torch.int32, device=dev) for _ in range(2)]
         self._ws = {}

@@ -409,9 +409,10 @@ int nhq_query_order(const nhq_index *ix, const uint8_t *qattrs, int64_t nq, int3
 
 /* A launch order for nhq_search_params.order from the batch's seed
  * candidates (nhq_seed_rank's cand, [nq][n_cand]): the queries grouped by
- * their best candidate, each group's wavefronts kept on one XCD.  Queries
- * that start from one member of the entry sample search one part of the
- * graph and read many of the same rows; workgroups go to the device's 8 XCDs
+ * the lowest entry-sample position among their candidates, each group's
+ * wavefronts kept on one XCD.  Queries that share a member of the entry
+ * sample among their seed candidates search one part of the graph and read
+ * many of the same rows; workgroups go to the device's 8 XCDs
  * round-robin, so XCD x is given the x-th of 8 contiguous runs of the
  * grouped queries, and their rows meet in that XCD's L2.  The groups are
  * taken in a scrambled order of their entry positions, so each XCD's run

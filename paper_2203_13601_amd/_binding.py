@@ -496,9 +496,10 @@ def nhq_query_order(ix: Index, qattrs: torch.Tensor, stream=None) -> torch.Tenso
 
 def nhq_seed_order(ix: Index, cand: torch.Tensor, stream=None, out: Optional[torch.Tensor] = None,
                    workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """Launch order grouping a batch by its best seed candidate (cand from
-    nhq_seed_rank), each group on one XCD; int32 [nq] on the index's device.
-    workspace: as for nhq_seed_rank (the same tensor serves both calls)."""
+    """Launch order grouping a batch by the lowest entry position among each
+    query's seed candidates (cand from nhq_seed_rank), each group on one XCD;
+    int32 [nq] on the index's device.  workspace: as for nhq_seed_rank (the
+    same tensor serves both calls)."""
     if (not isinstance(cand, torch.Tensor) or cand.dtype != torch.int32 or cand.dim() != 2
             or cand.device != ix.device):
         raise ValueError("cand must be an int32 [nq][n_cand] tensor on %s" % ix.device)

@@ -937,13 +937,16 @@ struct SelectivityBucket {
     }
 };
 
-// seed: the query's best candidate (its position in the entry sample),
-// n_total positions spread over the buckets (no candidate: the last
-// position's bucket), the buckets then permuted by an odd multiplier mod
-// 1,024.  Neighbouring positions (one attribute pattern's block of a
-// stratified sample) land far apart, so each XCD's run of the sorted queries
-// mixes many buckets of every kind, and their cost evens out across XCDs;
-// the queries of one bucket stay together.
+// seed: the lowest entry-sample position among the query's candidates (a
+// member of its seed neighbourhood that many queries of one region share:
+// measured, grouping by it keeps more of a batch's row reads in L2 than
+// grouping by the best candidate), n_total positions spread over the
+// buckets (no candidate: the last position's bucket), the buckets then
+// permuted by an odd multiplier mod 1,024.  Neighbouring positions (one
+// attribute pattern's block of a stratified sample) land far apart, so each
+// XCD's run of the sorted queries mixes many buckets of every kind, and
+// their cost evens out across XCDs; the queries of one bucket stay
+// together.
 struct SeedBucket {
     const int32_t *cand;
     int n_cand;
@@ -951,8 +954,13 @@ struct SeedBucket {
     __device__ int operator()(int64_t q) const
     {
         static_assert(kOrderBuckets == 1024, "the permutation is mod 1024");
-        const int32_t p = cand[q * n_cand];
-        const int b = (p < 0 || p >= n_total) ? kOrderBuckets - 1 : (int)((int64_t)p * kOrderBuckets / n_total);
+        int64_t lo = n_total;
+        for (int j = 0; j < n_cand; ++j) {
+            const int32_t p = cand[q * n_cand + j];
+            if (p >= 0 && p < lo)
+                lo = p;
+        }
+        const int b = lo >= n_total ? kOrderBuckets - 1 : (int)(lo * kOrderBuckets / n_total);
         return (b * 757 + 419) & (kOrderBuckets - 1);
     }
 };
@@ -1072,7 +1080,7 @@ int launch_order(const BucketOf &bucket_of, int64_t nq, int xcd, int32_t *scratc
     return NHQ_OK;
 }
 
-// batches from this size on are launched grouped by their best seed when the
+// batches from this size on are launched grouped by seed candidate when the
 // caller gives no order (smaller ones gain less than the order costs)
 constexpr int64_t kSeedOrderMinQueries = 2048;
 
@@ -1082,9 +1090,10 @@ size_t order_words(int64_t nq)
     return (size_t)kOrderBuckets + 2 * (size_t)nq;
 }
 
-// the order grouping queries by their best seed candidate, each group's
-// waves on one XCD (queries that start from one entry search one part of the
-// graph, so their row gathers share that XCD's L2)
+// the order grouping queries by the lowest entry position among their seed
+// candidates, each group's waves on one XCD (queries that share a seed
+// candidate search one part of the graph, so their row gathers share that
+// XCD's L2)
 int seed_order_at(const Index *ix, const int32_t *cand, int n_cand, int64_t nq, int32_t *order,
                   int32_t *scratch, hipStream_t st)
 {
