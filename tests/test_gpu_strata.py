@@ -77,6 +77,36 @@ def test_stratified_search_matches_oracle(zipf_set, storage, expand, n_init, bea
     ix.free()
 
 
+def test_stratified_search_in_seed_order(zipf_set):
+    # 2,700 queries (the 300 nine times over): the one-call search launches
+    # batches this large in the seed order, whose candidates here are
+    # positions inside the pattern blocks; results equal the natural order's
+    # bit for bit and the oracle's copy for copy
+    w, adj = zipf_set
+    per, ne, reps = 128, 256, 9
+    ix = nhq.nhq_index_create(_dev(w.x), _dev(w.attrs), n_entry=ne, seed=w.build_seed, degree=24,
+                              entry_per_pattern=per)
+    nhq.nhq_index_set_graph(ix, _dev(adj))
+    q, qa = _dev(np.tile(w.q, (reps, 1))), _dev(np.tile(w.qattrs, (reps, 1)))
+    kw = dict(n_init=4, expand=2, counters=True)
+    a = nhq.nhq_hybrid_search(ix, q, qa, 10, 32, **kw)
+    nat = torch.arange(q.shape[0], dtype=torch.int32, device="cuda")
+    b = nhq.nhq_hybrid_search(ix, q, qa, 10, 32, order=nat, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0])
+    assert torch.equal(a[1].view(torch.int32), b[1].view(torch.int32))
+    assert torch.equal(a[2], b[2])
+    strata = oracle.entry_strata(w.build_seed, w.attrs, per)
+    glob = oracle.entry_points(w.build_seed, w.n, ne)
+    oi, _, ondc, ohops, _ = oracle.search_strata(adj, w.x, w.attrs, w.q, w.qattrs, 10, 32, glob, strata,
+                                                 n_init=4, expand=2, key_mode=oracle.KEY32)
+    assert np.array_equal(a[0].cpu().numpy(), np.tile(oi, (reps, 1)))
+    cnt = a[2].cpu().numpy()
+    assert np.array_equal(cnt[:, 0], np.tile(ondc, reps)) and np.array_equal(cnt[:, 1], np.tile(ohops, reps))
+    assert nhq.nhq_index_device_error(ix) == 0
+    ix.free()
+
+
 def test_stratified_index_file_round_trip(zipf_set, tmp_path):
     w, adj = zipf_set
     ix = nhq.nhq_index_create(_dev(w.x), _dev(w.attrs), n_entry=256, seed=w.build_seed, degree=24,
