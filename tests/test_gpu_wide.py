@@ -33,6 +33,20 @@ def test_graph_matches_oracle_d960():
     assert same.mean() >= 0.995, same.mean()
 
 
+@pytest.mark.parametrize("d,cand", [(500, 64), (1000, 100)])
+def test_graph_matches_oracle_wide_tiles(d, cand):
+    # the LDS-staged tiles of 512+ element rows: 8 waves per workgroup with
+    # 48 entries of survivor slack (cand 64, 80 kept), and 4 waves (cand 100,
+    # 116 kept); 1,300 rows leave a ragged row block
+    w = synth.small(1300, d, 1, seed=96, n_centres=6, cards=(2, 3, 5, 10))
+    ix = nhq.nhq_build_index(_dev(w.x), _dev(w.attrs), degree=32, cand=cand, n_entry=64, seed=1)
+    adj = nhq.nhq_index_get_graph(ix).cpu().numpy()
+    want = oracle.build_graph(w.x, w.attrs, l=cand, R=32)
+    same = (adj == want).all(axis=1)
+    assert same.mean() >= 0.995, same.mean()
+    ix.free()
+
+
 @pytest.mark.parametrize("d", [500, 960, 1000])
 @pytest.mark.parametrize("storage", ["fp32", "bf16", "fp8"])
 def test_search_matches_oracle_wide(d, storage):
@@ -79,6 +93,25 @@ def test_bruteforce_knn_d960():
         assert ok.all(), i
         fin = np.isfinite(og[i])
         assert np.allclose(gd[i][fin], og[i][fin], rtol=1e-5)
+
+
+@pytest.mark.parametrize("d,k,nq", [(500, 10, 150), (960, 100, 70), (1000, 40, 130)])
+def test_bruteforce_knn_wide_tiles(d, k, nq):
+    # exact kNN through the LDS-staged tiles: two row blocks of 8 waves (one
+    # ragged), the 4-wave form (k = 100), and four column ranges of which
+    # the last ends inside a 128-column tile
+    w = synth.small(2900, d, nq, seed=95 + d, n_centres=8, cards=(2, 3, 5), wildcard_arity=True)
+    ix = nhq.nhq_index_create(_dev(w.x), _dev(w.attrs), n_entry=64)
+    gi, gd = nhq.nhq_bruteforce_hybrid_knn(ix, _dev(w.q), _dev(w.qattrs), k)
+    gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
+    oi, og, _ = oracle.bruteforce(w.x, w.attrs, w.q, w.qattrs, k)
+    for i in range(w.nq):
+        ok = (gi[i] == oi[i]) | np.isclose(gd[i], og[i], rtol=1e-6)
+        assert ok.all(), i
+        fin = np.isfinite(og[i])
+        assert np.array_equal(np.isfinite(gd[i]), fin), i
+        assert np.allclose(gd[i][fin], og[i][fin], rtol=1e-5)
+    ix.free()
 
 
 @pytest.mark.parametrize("d,storage", [(500, "fp32"), (960, "bf16")])
