@@ -308,7 +308,7 @@ __global__ __launch_bounds__(128) void k_dense_topk(const TopkArgs a)
 
 constexpr int kWideCols = 128;                // columns per tile (8 sub-tiles)
 constexpr int kSlice = 32;                    // elements per staged slice
-constexpr int kSliceStride = kSlice + 4;      // padded LDS row: conflict-free 16-byte reads
+constexpr int kSliceStride = kSlice + 4;      // padded LDS row: the 16 rows a read touches start in distinct banks
 constexpr size_t kMaxLds = 160 * 1024;
 
 __host__ __device__ constexpr size_t wide_lds_bytes(int waves, int cap)
