@@ -13,10 +13,10 @@ One timed "step" is one full pass of the hot path over the 10,000 queries:
 seed ranking of the entry sample (matrix cores), the launch order that
 groups the queries by seed candidate (nhq_seed_order), and the
 joint-pruning search (one wavefront per query), with the exact float32
-re-score of the final candidates in the precision forms.  Two batches are kept in flight:
-step i runs on stream i % 2 with its own candidates, outputs and ranking
-scratch (nhq_seed_rank_ws), so one batch's ranking and search use the
-compute units that the other batch's last queries leave idle.  QPS is the
+re-score of the final candidates in the precision forms.  Three batches are kept in flight
+(--in-flight): step i runs on stream i % 3 with its own candidates, outputs
+and ranking scratch (nhq_seed_rank_ws), so one batch's ranking and search
+use the compute units that another batch's last queries leave idle.  QPS is the
 wall clock over the timed steps; the kernels' own durations (for the
 roofline) come from a second pass of the same steps one after another on
 one stream with HIP events around each stage.
@@ -127,22 +127,24 @@ class Harness:
         self.cand = torch.empty((self.nq, self.n_cand), dtype=torch.int32, device=dev)
         self.ids = torch.empty((self.nq, self.k), dtype=torch.int32, device=dev)
         self.dists = torch.empty((self.nq, self.k), dtype=torch.float32, device=dev)
-        # two batches in flight: step i runs on stream i % 2 with its own
-        # candidates, outputs and seed-ranking scratch (stream 1 brings its
-        # own workspace, stream 0 uses the index's), so one batch's ranking
-        # and search fill the device while the other's last queries finish
-        self.streams = [torch.cuda.Stream(), torch.cuda.Stream()]
-        self.cand1 = torch.empty_like(self.cand)
-        self.ids1 = torch.empty_like(self.ids)
-        self.dists1 = torch.empty_like(self.dists)
+        # batches in flight (--in-flight, 3 by default): step i runs on stream
+        # i % nf with its own candidates, outputs and seed-ranking scratch
+        # (streams 1.. bring their own workspaces, stream 0 uses the
+        # index's), so one batch's ranking and search fill the device while
+        # another's last queries finish
+        self.nf = max(1, getattr(args, "in_flight", 3))
+        self.streams = [torch.cuda.Stream() for _ in range(self.nf)]
+        self.cands = [self.cand] + [torch.empty_like(self.cand) for _ in range(self.nf - 1)]
+        self.outs = [(self.ids, self.dists)] + [(torch.empty_like(self.ids), torch.empty_like(self.dists))
+                                                for _ in range(self.nf - 1)]
         # launch orders (queries grouped by seed candidate, each group on one
         # XCD), one per batch in flight
-        self.order = [torch.empty(self.nq, dtype=torch.int32, device=dev) for _ in range(2)]
+        self.order = [torch.empty(self.nq, dtype=torch.int32, device=dev) for _ in range(self.nf)]
         self._ws = {}
         self.gt = None
 
-    def _workspace(self, index):
-        key = id(index)
+    def _workspace(self, index, j=1):
+        key = (id(index), j)
         if key not in self._ws:
             b = self.nhq.nhq_seed_rank_workspace_size(index, self.nq, self.n_cand)
             self._ws[key] = (index, self.torch.empty(b, dtype=self.torch.uint8, device=self.dev))
@@ -150,13 +152,13 @@ class Harness:
 
     def step(self, index, beam, counters=False, ev=None, j=None, **kw):
         """one batch: seed ranking, then the search; j None on the current
-        stream, else on stream j of the two kept in flight"""
+        stream, else on stream j of those kept in flight"""
         nhq, torch = self.nhq, self.torch
         seed_order = "order" not in kw  # else the caller's launch order
         if j is not None:
             s = self.streams[j]
-            cand, out = (self.cand, (self.ids, self.dists)) if j == 0 else (self.cand1, (self.ids1, self.dists1))
-            ws = None if j == 0 else self._workspace(index)
+            cand, out = self.cands[j], self.outs[j]
+            ws = None if j == 0 else self._workspace(index, j)
             with torch.cuda.stream(s):
                 nhq.nhq_seed_rank(index, self.q, self.qa, self.n_cand, out=cand, stream=s, workspace=ws)
                 okw = kw
@@ -180,17 +182,18 @@ class Harness:
         return r
 
     def timed(self, index, beam, reps, **kw):
-        """wall clock over `reps` steps, two batches in flight (steps
-        alternate between two streams), then the same number of steps one
+        """wall clock over `reps` steps, nf batches in flight (step i on
+        stream i % nf), then the same number of steps one
         after another on one stream with HIP events around each stage, which
         give the kernels' own durations (event records are stream packets of
         their own, so they stay out of the wall-clock loop)"""
         torch = self.torch
-        self._workspace(index)
+        for j in range(1, self.nf):
+            self._workspace(index, j)
         torch.cuda.synchronize()
         t = time.time()
         for i in range(reps):
-            self.step(index, beam, j=i % 2, **kw)
+            self.step(index, beam, j=i % self.nf, **kw)
         torch.cuda.synchronize()
         wall = time.time() - t
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
@@ -205,24 +208,26 @@ class Harness:
         return recall_at_k(ids, w.x, w.q, w.attrs, w.qattrs, self.gt, self.k)
 
     def point(self, index, beam, **kw):
-        """one setting: Recall@10 (FP64), NDC, hops, QPS over 3 steps, stage times"""
+        """one setting: Recall@10 (FP64), NDC, hops, QPS over 3 steps per
+        stream in flight, stage times"""
         _, _, cnt = self.step(index, beam, counters=True, **kw)
         self.torch.cuda.synchronize()
         ids = self.ids.cpu().numpy()
         rec = self.recall(ids)
         cnt = cnt.cpu().numpy().astype(np.float64)
-        for j in (0, 1):
+        for j in range(self.nf):
             self.step(index, beam, j=j, **kw)
-        wall, rk, se = self.timed(index, beam, 3, **kw)
-        return {"beam": beam, "recall": float(rec.mean()), "qps": self.nq * 3 / wall,
+        reps = 3 * self.nf
+        wall, rk, se = self.timed(index, beam, reps, **kw)
+        return {"beam": beam, "recall": float(rec.mean()), "qps": self.nq * reps / wall,
                 "ndc": float(cnt[:, 0].mean()), "hops": float(cnt[:, 1].mean()),
                 "hops_p99": float(np.percentile(cnt[:, 1], 99)),
                 "returned": float((ids >= 0).sum(axis=1).mean()),
                 "rank_ms": float(np.median(rk)), "search_ms": float(np.median(se))}
 
     def run_form(self, index, beam, steps, warmup, **kw):
-        for i in range(max(warmup, 2)):
-            self.step(index, beam, j=i % 2, **kw)
+        for i in range(max(warmup, self.nf)):
+            self.step(index, beam, j=i % self.nf, **kw)
         wall, rank_ms, search_ms = self.timed(index, beam, steps, **kw)
         return {"qps": self.nq * steps / wall, "ms_per_step": wall * 1000.0 / steps,
                 "rank_kernels_avg_ms": float(np.mean(rank_ms)), "search_kernel_avg_ms": float(np.mean(search_ms)),
@@ -551,7 +556,7 @@ def headline(args):
                    "degree": w.degree, "cand": w.cand, "builder": args.builder, "n_entry": args.n_entry,
                    "n_init": args.n_init, "expand": args.expand, "build_s": round(build_s, 3),
                    "exact_knn_s": round(gt_s, 3), "recall": "FP64 distances recomputed from the vectors",
-                   "batches_in_flight": 2, "parallelism": "single GPU"},
+                   "batches_in_flight": args.in_flight, "parallelism": "single GPU"},
         "p99_ms": None if serving is None else serving["p99_ms"],
         "forms": _r({kk: {k2: v2 for k2, v2 in f.items()} for kk, f in forms.items()}),
         "mixed_selectivity": mixed,
@@ -962,7 +967,7 @@ def plain(args):
                       "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
                       "config": {"workload": w.name, "n": w.n, "d": w.d, "queries_per_step": h.nq, "k": w.k,
                                  "beam": vf["beam"], "n_entry": args.n_entry, "n_init": args.n_init,
-                                 "expand": args.expand, "build_s": round(build_s, 3), "batches_in_flight": 2,
+                                 "expand": args.expand, "build_s": round(build_s, 3), "batches_in_flight": args.in_flight,
                                  "parallelism": "single GPU"},
                       "forms": _r(forms), "roofline": roof, "cpu_baseline": cpu}), flush=True)
 
@@ -1087,7 +1092,7 @@ def learned10m(args):
                       "train_queries": int(tq.shape[0]), "k": w.k, "n_entry": args.n_entry,
                       "entry_per_pattern": args.entry_per_pattern, "n_init": args.n_init, "expand": args.expand,
                       "builder": "nndescent", "build_s": round(build_s, 2), "storage": "fp32",
-                      "batches_in_flight": 2},
+                      "batches_in_flight": args.in_flight},
            "fixed_qps_at_target_interp": fa, "fixed_hops_at_target": _interp_at(fixed, target, "hops"),
            "learned_qps_at_target_interp": best["qps_at_target_interp"],
            "learned_hops_at_target": best["hops_at_target"],
@@ -1143,6 +1148,9 @@ def main():
                     help="training queries of the stop network (20,000; 200,000 for learned10m)")
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--entry-per-pattern", type=int, default=8192)
+    ap.add_argument("--in-flight", type=int, default=3,
+                    help="batches kept in flight on their own streams in the timed loops (4 streams "
+                         "with the default one exceed the 4 hardware queues)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=50_000.0)
     ap.add_argument("--serve-requests", type=int, default=500_000)
